@@ -41,6 +41,31 @@ def _omega(info, n):
     return om
 
 
+def _mat2(A, B):
+    """Batched A @ B for A (n,2,2), B (n,2,k)."""
+    return np.matmul(A, B)
+
+
+def _tmul(A, B):
+    """Batched A^T B for A (n,m,i), B (n,m,j) -> (n,i,j), summing over m."""
+    return np.matmul(A.transpose(0, 2, 1), B)
+
+
+def _tvec(A, v):
+    """Batched A^T v for A (n,m,i), v (n,m) -> (n,i)."""
+    return np.matmul(A.transpose(0, 2, 1), v[:, :, None])[:, :, 0]
+
+
+def _scatter_sum(index, values, n):
+    """out[k] = sum of values[e] over e with index[e] == k."""
+    shape = values.shape[1:]
+    flat = values.reshape(len(values), -1)
+    out = np.empty((n, flat.shape[1]))
+    for c in range(flat.shape[1]):
+        out[:, c] = np.bincount(index, weights=flat[:, c], minlength=n)
+    return out.reshape((n,) + shape)
+
+
 class Linearization:
     pass
 
@@ -50,7 +75,7 @@ class BAProblem:
 
     def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs, info=None,
                  cam_fixed=None, pt_fixed=None, edge_active=None,
-                 loss=robust.SQUARED, delta=1.0, pair_chunk=400_000):
+                 loss=robust.SQUARED, delta=1.0, pair_chunk=500_000):
         self.n_cams = int(n_cams)
         self.n_pts = int(n_pts)
         cam_idx = np.asarray(cam_idx, dtype=np.int64)
@@ -106,26 +131,21 @@ class BAProblem:
         Jc = Jc * (~self.cam_fixed[self.cam_idx])[:, None, None]
         Jp = Jp * (~self.pt_fixed[self.pt_idx])[:, None, None]
         WOm = self.omega * w[:, None, None]                  # w Omega  (n,2,2)
-        OJc = np.einsum("nab,nbk->nak", WOm, Jc)             # (n,2,9)
-        OJp = np.einsum("nab,nbk->nak", WOm, Jp)             # (n,2,3)
-        Or = np.einsum("nab,nb->na", WOm, r)                 # (n,2)
+        OJc = _mat2(WOm, Jc)                                 # (n,2,9)
+        OJp = _mat2(WOm, Jp)                                 # (n,2,3)
+        Or = np.matmul(WOm, r[:, :, None])[:, :, 0]
         L = Linearization()
         L.r, L.Jc, L.Jp, L.w = r, Jc, Jp, w
-        L.Hcc = np.zeros((self.n_cams, 9, 9))
-        np.add.at(L.Hcc, self.cam_idx, np.einsum("nai,naj->nij", Jc, OJc))
-        L.bc = np.zeros((self.n_cams, 9))
-        np.add.at(L.bc, self.cam_idx, np.einsum("nai,na->ni", Jc, Or))
-        L.Hpp = np.zeros((self.n_pts, 3, 3))
-        np.add.at(L.Hpp, self.pt_idx, np.einsum("nai,naj->nij", Jp, OJp))
-        L.bp = np.zeros((self.n_pts, 3))
-        np.add.at(L.bp, self.pt_idx, np.einsum("nai,na->ni", Jp, Or))
+        L.Hcc = _scatter_sum(self.cam_idx, _tmul(Jc, OJc), self.n_cams)
+        L.bc = _scatter_sum(self.cam_idx, _tvec(Jc, Or), self.n_cams)
+        L.Hpp = _scatter_sum(self.pt_idx, _tmul(Jp, OJp), self.n_pts)
+        L.bp = _scatter_sum(self.pt_idx, _tvec(Jp, Or), self.n_pts)
         # camera-point coupling blocks, summed over repeated (i, j) pairs
         key = self.cam_idx * self.n_pts + self.pt_idx
         uk, inv = np.unique(key, return_inverse=True)
         L.pair_cam = uk // self.n_pts
         L.pair_pt = uk % self.n_pts
-        L.Hcp = np.zeros((len(uk), 9, 3))
-        np.add.at(L.Hcp, inv, np.einsum("nai,naj->nij", Jc, OJp))
+        L.Hcp = _scatter_sum(inv, _tmul(Jc, OJp), len(uk))
         return L
 
     def damped_diagonal(self, lin, min_diag, max_diag):
@@ -172,29 +192,37 @@ class BAProblem:
         sq = counts * counts
         total = int(sq.sum())
         if total:
+            # every ordered pair (a, b) of coupling blocks of one point adds
+            # Lcp_a Lcp_b^T at camera block (cam_a, cam_b); the pairs with
+            # a > b give the transposes of those with a < b
             pts_rep = np.repeat(np.arange(npf), sq)
             base = np.repeat(np.cumsum(sq) - sq, sq)
             loc = np.arange(total) - base
             m = counts[pts_rep]
             a = starts[pts_rep] + loc // m
             b = starts[pts_rep] + loc % m
+            keep = a <= b
+            a, b = a[keep], b[keep]
             rr = np.arange(9)
+            off81 = (rr[:, None] * N + rr[None, :]).ravel()
             accum = np.zeros(N * N)
-            for s0 in range(0, total, self.pair_chunk):
+            for s0 in range(0, len(a), self.pair_chunk):
                 aa = a[s0:s0 + self.pair_chunk]
                 bb = b[s0:s0 + self.pair_chunk]
-                prod = np.einsum("nki,nkj->nij", LcpT_s[aa], LcpT_s[bb])
-                rows = 9 * pc_s[aa][:, None] + rr[None, :]          # (n,9)
-                cols = 9 * pc_s[bb][:, None] + rr[None, :]
-                flat = rows[:, :, None] * N + cols[:, None, :]
-                accum += np.bincount(flat.ravel(), weights=prod.ravel(),
+                prod = _tmul(LcpT_s[aa], LcpT_s[bb])               # (n,9,9)
+                prod[aa == bb] *= 0.5
+                base = 9 * pc_s[aa] * N + 9 * pc_s[bb]
+                flat = base[:, None] + off81[None, :]
+                accum += np.bincount(flat.ravel(), weights=prod.reshape(-1),
                                      minlength=N * N)
-            Acc -= accum.reshape(N, N)
+            accum = accum.reshape(N, N)
+            accum += accum.T.copy()
+            Acc -= accum
 
         # forward: Lcc y_c = -b_c - Lcp y_p
         rhs_c = -lin.bc[fc].reshape(-1) if nc else np.zeros(0)
         if len(pp):
-            contrib = np.einsum("nki,nk->ni", LcpT, yp[pp])           # (P,9)
+            contrib = _tvec(LcpT, yp[pp])                           # (P,9)
             idx = (9 * pc[:, None] + np.arange(9)[None, :]).ravel()
             rhs_c = rhs_c - np.bincount(idx, weights=contrib.ravel(),
                                         minlength=N)
@@ -208,7 +236,7 @@ class BAProblem:
         # back: Lpp^T dp = y_p - Lcp^T dc
         t = yp.copy()
         if len(pp):
-            back = np.einsum("nki,ni->nk", LcpT, dcf[pc])             # (P,3)
+            back = np.matmul(LcpT, dcf[pc][:, :, None])[:, :, 0]     # (P,3)
             for k in range(3):
                 t[:, k] -= np.bincount(pp, weights=back[:, k], minlength=npf)
         dpf = (np.linalg.solve(Lpp.transpose(0, 2, 1), t[:, :, None])[:, :, 0]
@@ -223,9 +251,9 @@ class BAProblem:
     def model_decrease(self, lin, dx):
         dcam, dpt = dx
         b_dx = float(np.sum(lin.bc * dcam) + np.sum(lin.bp * dpt))
-        jd = (np.einsum("nak,nk->na", lin.Jc, dcam[self.cam_idx]) +
-              np.einsum("nak,nk->na", lin.Jp, dpt[self.pt_idx]))
-        quad = float(np.sum(lin.w * np.einsum("na,nab,nb->n", jd, self.omega, jd)))
+        jd = (np.matmul(lin.Jc, dcam[self.cam_idx][:, :, None]) +
+              np.matmul(lin.Jp, dpt[self.pt_idx][:, :, None]))[:, :, 0]
+        quad = float(np.sum(lin.w * self._s(jd)))
         return -(b_dx + 0.5 * quad)
 
     def step(self, x, dx):
