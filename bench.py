@@ -1,0 +1,156 @@
+"""Benchmark: LM iterations/s of bundle adjustment at 1M observations on one
+MI355X, plus the PCG matvec roofline and the CPU oracle as a baseline.
+
+Workload (synthetic, seeded): 1,000 cameras, 200,000 points, ~1.0M
+observations (track length 2 + Geometric(1/4)), Huber delta = 1 px, 20 LM
+trials per solve, PCG tolerance 1e-6 relative, at most 100 iterations.
+One step = one 20-trial solve from the perturbed start (device-side reset of
+the parameters, then gba_solve).  Inputs are resident on the device before the
+timed region.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
+                  [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LM iter/s + PCG HBM GB/s at 1M obs; p50/p99 latency for local-BA stream"
+HBM_PEAK_GBS = 8000.0
+PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf16", 2)}
+
+
+def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes):
+    """Bytes the fused Schur product must move per launch: the two Jacobian
+    blocks (24 entries per edge), the edge's camera index, and per point its
+    CSR offset and the 6 unique entries of the FP64 inverse point block."""
+    return n_obs * (24 * jac_bytes + 4) + n_pts_active * (4 + 6 * 8)
+
+
+def cpu_baseline(sc):
+    """The oracle as it stands on a bounded sample: one LM trial (cost,
+    linearisation, exact damped solve, candidate cost) of the same workload."""
+    from oracle import ba
+    threads = os.cpu_count()
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas = [i.get("num_threads") for i in info if i.get("user_api") == "blas"]
+        if blas:
+            threads = max(blas)
+    except Exception:
+        pass
+    prob = ba.BAProblem(sc.n_cams, sc.n_pts, sc.cam_idx, sc.pt_idx, sc.obs,
+                        loss=sc.loss, delta=sc.delta)
+    t0 = time.perf_counter()
+    res = ba.solve(prob, sc.cams0, sc.pts0, 1)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "LM iter/s", "cores": int(threads), "kind": "oracle",
+            "sample": "1 LM trial (initial cost, dual-number linearisation, exact block-"
+                      "Cholesky damped solve, candidate cost) of the same 1M-observation "
+                      "workload, seed 0; %.1f s" % dt,
+            "trial_cost": res.log[0]["candidate_cost"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=list(PRECISIONS))
+    ap.add_argument("--workload", default="bal1m")
+    ap.add_argument("--trials", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this "
+              "build (see DESIGN.md, 'How the path would shard')", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_26581_amd import gba, synth
+
+    if not os.path.exists(gba.LIB_PATH):
+        from __graft_entry__ import build
+        build()
+    torch.cuda.set_device(0)
+    prec_id, dtype_name, jac_bytes = PRECISIONS[args.precision]
+    t0 = time.perf_counter()
+    sc = synth.make_scene(args.workload, seed=0)
+    trials = args.trials or sc.trials
+    print(f"[bench] workload {args.workload}: {sc.n_cams} cams, {sc.n_pts} pts, {sc.n_obs} obs "
+          f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
+    opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
+                       timing=0 if args.no_timing else 1)
+    g = gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
+                              loss=sc.loss, delta=sc.delta, precision=prec_id, options=opts,
+                              use_torch=True)
+    t0 = time.perf_counter()
+    gba.gba_prepare(g.h)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    print(f"[bench] graph build + upload {build_s:.2f} s", flush=True)
+
+    reports = []
+    for w in range(args.warmup):
+        gba.gba_reset(g.h)
+        rep = g.solve(trials)
+        print(f"[bench] warmup {w}: {rep.trials} trials, {rep.ms_total:.1f} ms, "
+              f"cost {rep.initial_cost:.6e} -> {rep.final_cost:.6e}", flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        gba.gba_reset(g.h)
+        reports.append(g.solve(trials))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_trials = sum(r.trials for r in reports)
+    lm_iters_s = total_trials / elapsed
+    last = reports[-1]
+    mv_ms = sum(r.ms_matvec for r in reports)
+    mv_n = sum(r.matvec_count for r in reports)
+    n_pts_active = int(np.unique(sc.pt_idx).size)
+    alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes)
+    roofline = None
+    if mv_n:
+        avg_s = mv_ms / mv_n / 1e3
+        achieved = alg_bytes / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "kernel": "k_point_pass<kMatvec> (fused Schur product)",
+                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": int(alg_bytes)}
+    line = {
+        "metric": METRIC, "value": round(lm_iters_s, 3), "unit": "LM iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype_name, "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {sc.n_cams} cameras, {sc.n_pts} points, "
+                               f"{sc.n_obs} observations, Huber 1px, {trials} LM trials/step, "
+                               f"PCG tol {sc.pcg_tol} max {sc.pcg_max_iters}",
+                   "precision": args.precision, "seed": 0},
+        "obs_per_s": round(sc.n_obs * lm_iters_s, 1),
+        "pcg_iters_per_trial": round(sum(r.pcg_iters_total for r in reports) / max(total_trials, 1), 2),
+        "final_cost": last.final_cost, "initial_cost": last.initial_cost,
+        "phase_ms_per_solve": {k: round(getattr(last, k), 3) for k in
+                               ("ms_linearize", "ms_precond", "ms_pcg", "ms_other", "ms_matvec")},
+        "graph_build_s": round(build_s, 3), "workspace_bytes": int(last.workspace_bytes),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a one-trial sample ...", flush=True)
+        line["cpu_baseline"] = cpu_baseline(sc)
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * gba.h -- C ABI of the MI355X (gfx950) Levenberg-Marquardt bundle-adjustment
+ * solver.
+ *
+ * The method is the LM graph optimiser of Graphite (arXiv 2509.26581) applied
+ * to bundle adjustment: minimise half the sum of robustified squared
+ * Mahalanobis reprojection errors (Background, Eq. 1-2, Huber kernel Eq. 7) by
+ * repeatedly solving the damped normal equations
+ *     (J^T W J + lambda D^T D) dx = -J^T W r            (Background, Eq. 4-6)
+ * with D^T D the clamped Hessian diagonal (Sec. IV-D).  On the GPU the point
+ * blocks are eliminated (Schur complement) and the reduced camera system is
+ * solved by block-Jacobi preconditioned conjugate gradients with implicit,
+ * matrix-free products built from the stored Jacobian blocks (Sec. IV-D:
+ * implicit PCG over the graph structure, block-Jacobi preconditioner).
+ *
+ * Camera model (the BAL camera; the paper benchmarks BAL but does not write
+ * the model out): 9 parameters per camera (w[3] angle-axis, t[3], f, k1, k2),
+ *     P = R(w) X + t,  p = -P_xy / P_z,  pixel = f (1 + k1|p|^2 + k2|p|^4) p,
+ *     residual r = pixel - observation.
+ *
+ * Conventions common to every call:
+ *   - Every function returns gba_status: GBA_OK (0) or a negative GBA_ERR_*.
+ *     No exception crosses the ABI.  After an error, gba_last_error(g) returns
+ *     a message for that handle.
+ *   - Host pointers are read (or written) before the call returns; the caller
+ *     keeps ownership of every array it passes.  Arrays are row-major,
+ *     contiguous, in the units stated.
+ *   - Device memory is obtained from the allocator callbacks given to
+ *     gba_create (or hipMalloc/hipFree when both are NULL) and released by
+ *     gba_destroy.  All work is issued on the stream given to gba_set_stream
+ *     (default: the null stream of the chosen device).
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Vertex ids are arbitrary int64 values, unique per kind (Sec. IV-A:
+ *     vertices are added with a user identifier).  Results are returned in
+ *     the order the vertices were added.
+ */
+#ifndef GBA_H
+#define GBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int gba_status;
+
+#define GBA_OK 0
+#define GBA_ERR_INVALID_ARG (-1)  /* bad size, NULL pointer, bad enum        */
+#define GBA_ERR_UNKNOWN_ID (-2)   /* an edge or set_fixed names no vertex    */
+#define GBA_ERR_DUPLICATE_ID (-3) /* a vertex id added twice                 */
+#define GBA_ERR_NONFINITE (-4)    /* NaN/Inf in parameters or observations   */
+#define GBA_ERR_OOM (-5)          /* the allocator returned NULL             */
+#define GBA_ERR_HIP (-6)          /* a HIP runtime call failed               */
+#define GBA_ERR_STATE (-7)        /* call not valid in the current state     */
+#define GBA_ERR_UNSUPPORTED (-8)  /* configuration this build cannot run     */
+
+typedef struct gba_graph gba_graph;
+
+/* Precision policy (Sec. IV-D: vertex precision and linear-system precision
+ * chosen separately; Table I runs FP64, FP32 and FP32 with BF16 storage). */
+typedef enum {
+    GBA_FP64 = 0,        /* everything in FP64                               */
+    GBA_MIXED_FP32 = 1,  /* FP32 Jacobians, Hessian blocks and PCG vectors;
+                            FP64 cost, gain ratio, PCG dot products, step
+                            acceptance and 3x3 point-block inversion          */
+    GBA_MIXED_BF16 = 2   /* as MIXED_FP32, plus BF16 storage of the Jacobian
+                            copy read by the PCG products                     */
+} gba_precision;
+
+/* Robust kernel on s = r^T Omega r (Background, Eq. 7). */
+typedef enum {
+    GBA_LOSS_SQUARED = 0, /* rho(s) = s                                        */
+    GBA_LOSS_HUBER = 1    /* rho(s) = s if s <= delta^2, else 2 delta sqrt(s) - delta^2 */
+} gba_loss;
+
+/* Preconditioner of the reduced camera system (Sec. IV-D). */
+typedef enum {
+    GBA_PRECOND_IDENTITY = 0,
+    GBA_PRECOND_BLOCK_JACOBI = 1  /* exact 9x9 diagonal blocks of the Schur complement */
+} gba_precond;
+
+/* Why gba_solve stopped (report.termination). */
+typedef enum {
+    GBA_TERM_NONE = 0,
+    GBA_TERM_MAX_ITERS = 1,        /* max_iters trials were run               */
+    GBA_TERM_COST_TOL = 2,         /* accepted step with (F - F')/F < tol     */
+    GBA_TERM_STEP_TOL = 3,         /* |dx| <= tol (|x| + tol)                 */
+    GBA_TERM_LAMBDA_OVERFLOW = 4,  /* damping exceeded 1e32                   */
+    GBA_TERM_NUMERICAL_FAILURE = 5,/* initial cost not finite                 */
+    GBA_TERM_NO_WORK = 6           /* no active edge or no free vertex        */
+} gba_termination;
+
+/* Device allocator supplied by the caller (e.g. PyTorch's caching
+ * allocator).  alloc returns NULL on failure; free accepts what alloc gave. */
+typedef void* (*gba_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*gba_free_fn)(void* ptr, void* ctx);
+
+/* Solver options.  Defaults from gba_default_options().  The PCG knobs follow
+ * the paper's PCG solver (maximum iterations, tolerance, rejection ratio;
+ * Sec. IV-A listing and Sec. V-C settings). */
+typedef struct gba_options {
+    double initial_lambda;     /* initial damping (default 1e-4)             */
+    double min_diag;           /* clamp of diag(H) used for damping (1e-6)   */
+    double max_diag;           /* (1e32)                                     */
+    int pcg_max_iters;         /* (100)                                      */
+    double pcg_tol;            /* (1e-6)                                     */
+    int pcg_tol_relative;      /* 1: |r_k| <= tol |r_0|; 0: |r_k| <= tol (1) */
+    double pcg_rejection_ratio;/* stop PCG and keep the best iterate when
+                                  |r_k| > ratio * min_m<=k |r_m|; <= 0 or Inf
+                                  disables (default: disabled)               */
+    int precond;               /* gba_precond (BLOCK_JACOBI)                 */
+    int timing;                /* 1: time phases with HIP events (0)         */
+    int reserved[7];
+} gba_options;
+
+/* Summary of one gba_solve call. */
+typedef struct gba_report {
+    double initial_cost;       /* F at the start: 1/2 sum rho(s_e)           */
+    double final_cost;
+    double final_lambda;
+    int trials;                /* linear solves run (accepted or not)        */
+    int accepted;
+    int pcg_iters_total;
+    int termination;           /* gba_termination                            */
+    double ms_total;           /* wall time of the call (host clock)         */
+    double ms_linearize;       /* HIP-event times, when options.timing = 1   */
+    double ms_precond;
+    double ms_pcg;
+    double ms_other;
+    double ms_matvec;          /* summed duration of the matvec kernels      */
+    int matvec_count;
+    int reserved_i;
+    size_t workspace_bytes;    /* device bytes held by the graph             */
+} gba_report;
+
+/* One LM trial (for comparisons and diagnostics). */
+typedef struct gba_trial {
+    double cost;               /* F before the trial                         */
+    double candidate_cost;     /* F(x + dx)                                  */
+    double lambda;             /* damping used                               */
+    double model_decrease;     /* L = -(b^T dx + 1/2 dx^T H dx)              */
+    double step_norm;          /* |dx|                                       */
+    int accepted;
+    int pcg_iters;
+} gba_trial;
+
+void gba_default_options(gba_options* out);
+
+/* Create an empty graph on `device` with the given precision policy.
+ * alloc/free may both be NULL (hipMalloc/hipFree are then used). */
+gba_status gba_create(gba_precision precision, int device, gba_alloc_fn alloc,
+                      gba_free_fn free_fn, void* ctx, gba_graph** out);
+
+/* Issue all device work on this hipStream_t (e.g. torch's current stream). */
+gba_status gba_set_stream(gba_graph* g, void* hip_stream);
+
+/* Pre-size host staging for the given counts (Sec. IV-A: descriptors reserve
+ * memory before vertices and constraints are added).  Optional. */
+gba_status gba_reserve(gba_graph* g, int64_t n_cams, int64_t n_pts, int64_t n_edges);
+
+/* Add n cameras: ids[n], params[n x 9] = (w0 w1 w2 t0 t1 t2 f k1 k2). */
+gba_status gba_add_cameras(gba_graph* g, int64_t n, const int64_t* ids,
+                           const double* params);
+
+/* Add n points: ids[n], xyz[n x 3]. */
+gba_status gba_add_points(gba_graph* g, int64_t n, const int64_t* ids,
+                          const double* xyz);
+
+/* Add n reprojection edges (binary constraints, Sec. IV-A): camera and point
+ * ids, uv[n x 2] observed pixel, info[n x 3] = (O00, O01, O11) of the 2x2
+ * information matrix Omega (symmetric positive definite), or NULL for the
+ * identity (the paper's nullptr-means-identity precision matrix).  Edges are
+ * numbered in insertion order starting at 0. */
+gba_status gba_add_edges(gba_graph* g, int64_t n, const int64_t* cam_ids,
+                         const int64_t* pt_ids, const double* uv,
+                         const double* info);
+
+/* Hold a vertex constant (kind 0 = camera, 1 = point; Sec. IV-A set_fixed). */
+gba_status gba_set_fixed(gba_graph* g, int kind, int64_t id, int fixed);
+
+/* Include (1) or exclude (0) an edge (Sec. IV-A set_active / optimisation
+ * level).  Excluded edges contribute neither cost nor linear terms. */
+gba_status gba_set_edge_active(gba_graph* g, int64_t edge_index, int active);
+
+/* Robust kernel for every edge (Background, Eq. 7); delta > 0 for Huber. */
+gba_status gba_set_robust_kernel(gba_graph* g, gba_loss loss, double delta);
+
+gba_status gba_set_options(gba_graph* g, const gba_options* opts);
+
+/* Build the device graph (id maps, point-major and camera-major edge orders,
+ * workspace) and upload it.  gba_solve calls it when the graph changed. */
+gba_status gba_prepare(gba_graph* g);
+
+/* Run up to max_iters LM trials from the current parameters (tol as in
+ * gba_termination).  Synchronous: returns after the results are on device and
+ * the report is filled (report may be NULL).  Returns GBA_OK whenever the
+ * solver ran, including on early termination. */
+gba_status gba_solve(gba_graph* g, int max_iters, double tol, gba_report* report);
+
+/* Restore the parameters given at insertion time (device-side copy). */
+gba_status gba_reset(gba_graph* g);
+
+/* Current cost F = 1/2 sum rho(s_e) over active edges (FP64). */
+gba_status gba_get_cost(gba_graph* g, double* cost);
+
+/* Current parameters, insertion order: out[n_cams x 9] / out[n_pts x 3]. */
+gba_status gba_get_cameras(gba_graph* g, double* out);
+gba_status gba_get_points(gba_graph* g, double* out);
+
+/* Per-trial log of the last gba_solve: writes min(max_entries, trials)
+ * entries and the count to *n_out. */
+gba_status gba_get_trials(gba_graph* g, int max_entries, gba_trial* out, int* n_out);
+
+/* Step-level entry points of the hot path, for verification.  All outputs
+ * are host arrays in insertion order; entries of inactive edges are zero.
+ *
+ * gba_eval_edges: residual r[n_edges x 2] (pixel - observation), unweighted
+ * Jacobians jc[n_edges x 2 x 9] (d r / d camera) and jp[n_edges x 2 x 3]
+ * (d r / d point) at the current parameters, and the IRLS weight w[n_edges] =
+ * rho'(r^T Omega r).  Jacobian columns of fixed vertices are zero.  Any
+ * output pointer may be NULL. */
+gba_status gba_eval_edges(gba_graph* g, double* r, double* jc, double* jp, double* w);
+
+/* gba_eval_normal_equations: the blocks of H = sum J^T w Omega J and
+ * b = sum J^T w Omega r (Eq. 5) at the current parameters: hcc[n_cams x 81],
+ * bc[n_cams x 9], hpp[n_pts x 9], bp[n_pts x 3] (row-major 9x9 / 3x3). */
+gba_status gba_eval_normal_equations(gba_graph* g, double* hcc, double* bc,
+                                     double* hpp, double* bp);
+
+/* gba_eval_step: one damped step at the current parameters and damping
+ * lambda, computed as the hot path does (point elimination, PCG on the
+ * reduced camera system with the options' settings, back-substitution):
+ * dcam[n_cams x 9], dpt[n_pts x 3]; *pcg_iters receives the PCG count. */
+gba_status gba_eval_step(gba_graph* g, double lambda, double* dcam, double* dpt,
+                         int* pcg_iters);
+
+const char* gba_last_error(const gba_graph* g);
+
+/* Release all device and host memory of the graph.  NULL is ignored. */
+void gba_destroy(gba_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBA_H */

@@ -1,0 +1,321 @@
+// Device helpers of the gfx950 bundle-adjustment kernels: wavefront
+// segmented reductions, the closed-form BAL residual and Jacobian, robust
+// weighting, BF16 storage and small symmetric-block algebra.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gba_internal.h"
+
+namespace gba {
+
+// ------------------------------------------------------------ bf16 storage
+struct bf16 {
+    uint16_t v;
+};
+
+__device__ __forceinline__ float to_float(bf16 x) {
+    return __uint_as_float(((uint32_t)x.v) << 16);
+}
+__device__ __forceinline__ float to_float(float x) { return x; }
+__device__ __forceinline__ double to_float(double x) { return x; }
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__device__ __forceinline__ bf16 to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return bf16{(uint16_t)(u >> 16)};
+}
+
+template <typename S, typename T>
+__device__ __forceinline__ S store_as(T x) { return (S)x; }
+template <>
+__device__ __forceinline__ bf16 store_as<bf16, float>(float x) { return to_bf16(x); }
+
+template <typename T, typename S>
+__device__ __forceinline__ T load_as(S x) { return (T)to_float(x); }
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// For a 64-bit mask of segment starts, the first lane (head) and the last
+// lane (end) of the segment holding lane l.
+__device__ __forceinline__ void segment_of(uint64_t starts, int l, int& head, int& end) {
+    const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
+    const uint64_t le = starts & upto;
+    head = 63 - __clzll((long long)le);
+    const uint64_t after = starts & ~upto;
+    end = after ? (__ffsll((long long)after) - 2) : 63;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_down64(T v, int off) {
+    return __shfl_down(v, off, kWave);
+}
+template <typename T>
+__device__ __forceinline__ T shfl64(T v, int src) {
+    return __shfl(v, src, kWave);
+}
+
+// Inclusive suffix sum inside contiguous segments: after the call the head
+// lane of each segment holds the segment total.
+template <typename T>
+__device__ __forceinline__ T segment_sum(T v, int l, int end) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        T o = shfl_down64(v, off);
+        if (l + off <= end) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Block-wide sum; every thread gets the result.  `red` holds >= 16 values.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + kWave - 1) >> 6;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    T s = 0;
+    for (int k = 0; k < nw; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------ BAL camera model
+// r = f (1 + k1 |p|^2 + k2 |p|^4) p - obs with p = -(P_x, P_y) / P_z and
+// P = R(w) X + t; jc = dr/d(w, t, f, k1, k2), jp = dr/dX.
+// Rotation: R = I + a W + b W^2 with W = [w]x, a = sin(th)/th,
+// b = (1 - cos th)/th^2 (Rodrigues); derivative w.r.t. the angle-axis vector
+// dP/dw = -R [X]x Jr(w) with the right Jacobian Jr = I - b W + c W^2,
+// c = (th - sin th)/th^3.  For th^2 <= 1e-16 the rotation is taken to first
+// order, R X = X + w x X, whose derivative is dP/dw = -[X]x.
+template <typename T>
+struct EdgeEval {
+    T r[2];
+    T jc[2][9];
+    T jp[2][3];
+};
+
+template <typename T, bool kJac>
+__device__ __forceinline__ void bal_eval(const double* __restrict__ cam,
+                                         const double* __restrict__ X, double ou, double ov,
+                                         EdgeEval<T>& e) {
+    const T w0 = (T)cam[0], w1 = (T)cam[1], w2 = (T)cam[2];
+    const T x0 = (T)X[0], x1 = (T)X[1], x2 = (T)X[2];
+    const T th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    T R[3][3], M[3][3];
+    if (th2 > (T)1e-16) {
+        const T th = sqrt(th2);
+        const T s = sin(th);
+        const T hs = sin((T)0.5 * th);
+        const T a = s / th;
+        const T b = (T)2 * hs * hs / th2;
+        R[0][0] = (T)1 + b * (w0 * w0 - th2);
+        R[0][1] = -a * w2 + b * w0 * w1;
+        R[0][2] = a * w1 + b * w0 * w2;
+        R[1][0] = a * w2 + b * w1 * w0;
+        R[1][1] = (T)1 + b * (w1 * w1 - th2);
+        R[1][2] = -a * w0 + b * w1 * w2;
+        R[2][0] = -a * w1 + b * w2 * w0;
+        R[2][1] = a * w0 + b * w2 * w1;
+        R[2][2] = (T)1 + b * (w2 * w2 - th2);
+        if (kJac) {
+            const T c = th < (T)1e-2
+                            ? ((T)1 / (T)6 - th2 * ((T)1 / (T)120 - th2 * ((T)1 / (T)5040)))
+                            : (th - s) / (th2 * th);
+            T Jr[3][3];
+            Jr[0][0] = (T)1 + c * (w0 * w0 - th2);
+            Jr[0][1] = b * w2 + c * w0 * w1;
+            Jr[0][2] = -b * w1 + c * w0 * w2;
+            Jr[1][0] = -b * w2 + c * w1 * w0;
+            Jr[1][1] = (T)1 + c * (w1 * w1 - th2);
+            Jr[1][2] = b * w0 + c * w1 * w2;
+            Jr[2][0] = b * w1 + c * w2 * w0;
+            Jr[2][1] = -b * w0 + c * w2 * w1;
+            Jr[2][2] = (T)1 + c * (w2 * w2 - th2);
+            // K = R [X]x,  [X]x = [[0,-x2,x1],[x2,0,-x0],[-x1,x0,0]]
+            T K[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                K[i][0] = R[i][1] * x2 - R[i][2] * x1;
+                K[i][1] = -R[i][0] * x2 + R[i][2] * x0;
+                K[i][2] = R[i][0] * x1 - R[i][1] * x0;
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    M[i][j] = -(K[i][0] * Jr[0][j] + K[i][1] * Jr[1][j] + K[i][2] * Jr[2][j]);
+        }
+    } else {
+        R[0][0] = (T)1;
+        R[0][1] = -w2;
+        R[0][2] = w1;
+        R[1][0] = w2;
+        R[1][1] = (T)1;
+        R[1][2] = -w0;
+        R[2][0] = -w1;
+        R[2][1] = w0;
+        R[2][2] = (T)1;
+        if (kJac) {
+            M[0][0] = 0;
+            M[0][1] = x2;
+            M[0][2] = -x1;
+            M[1][0] = -x2;
+            M[1][1] = 0;
+            M[1][2] = x0;
+            M[2][0] = x1;
+            M[2][1] = -x0;
+            M[2][2] = 0;
+        }
+    }
+    const T P0 = R[0][0] * x0 + R[0][1] * x1 + R[0][2] * x2 + (T)cam[3];
+    const T P1 = R[1][0] * x0 + R[1][1] * x1 + R[1][2] * x2 + (T)cam[4];
+    const T P2 = R[2][0] * x0 + R[2][1] * x1 + R[2][2] * x2 + (T)cam[5];
+    const T f = (T)cam[6], k1 = (T)cam[7], k2 = (T)cam[8];
+    const T inv = (T)1 / P2;
+    const T px = -P0 * inv, py = -P1 * inv;
+    const T n = px * px + py * py;
+    const T d = (T)1 + k1 * n + k2 * n * n;
+    const T fd = f * d;
+    e.r[0] = fd * px - (T)ou;
+    e.r[1] = fd * py - (T)ov;
+    if (!kJac) return;
+    const T g = (T)2 * f * (k1 + (T)2 * k2 * n);
+    const T A00 = fd + g * px * px, A01 = g * px * py, A11 = fd + g * py * py;
+    T G[2][3];
+    G[0][0] = -inv * A00;
+    G[0][1] = -inv * A01;
+    G[0][2] = -inv * (A00 * px + A01 * py);
+    G[1][0] = -inv * A01;
+    G[1][1] = -inv * A11;
+    G[1][2] = -inv * (A01 * px + A11 * py);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            e.jp[a][j] = G[a][0] * R[0][j] + G[a][1] * R[1][j] + G[a][2] * R[2][j];
+            e.jc[a][j] = G[a][0] * M[0][j] + G[a][1] * M[1][j] + G[a][2] * M[2][j];
+            e.jc[a][3 + j] = G[a][j];
+        }
+    }
+    e.jc[0][6] = d * px;
+    e.jc[1][6] = d * py;
+    e.jc[0][7] = f * n * px;
+    e.jc[1][7] = f * n * py;
+    e.jc[0][8] = f * n * n * px;
+    e.jc[1][8] = f * n * n * py;
+}
+
+// Robust kernel on s (squared Mahalanobis norm): rho(s) and the IRLS weight
+// rho'(s).  Huber: rho = s (s <= d^2), 2 d sqrt(s) - d^2 otherwise.
+template <typename T>
+__device__ __forceinline__ void robust(int loss, double delta, T s, T& rho, T& w) {
+    const T d = (T)delta;
+    if (loss == 1 && s > d * d) {
+        const T q = sqrt(s);
+        rho = (T)2 * d * q - d * d;
+        w = d / q;
+    } else {
+        rho = s;
+        w = (T)1;
+    }
+}
+
+// Whiten one edge: with Omega = A^T A (A upper triangular, rows (a00 a01),
+// (0 a11)), r~ = sqrt(w) A r and J~ = sqrt(w) A J.  Returns s = |A r|^2 and
+// rho(s).  Jacobian blocks of fixed vertices are zeroed.
+template <typename T, bool kJac>
+__device__ __forceinline__ void whiten(EdgeEval<T>& e, const double* sinfo, int stride, int idx,
+                                       int loss, double delta, bool cam_fixed, bool pt_fixed,
+                                       T& s_out, T& rho_out, T& w_out) {
+    T a00 = 1, a01 = 0, a11 = 1;
+    if (sinfo) {
+        a00 = (T)sinfo[idx];
+        a01 = (T)sinfo[stride + idx];
+        a11 = (T)sinfo[2 * stride + idx];
+    }
+    const T ar0 = a00 * e.r[0] + a01 * e.r[1];
+    const T ar1 = a11 * e.r[1];
+    const T s = ar0 * ar0 + ar1 * ar1;
+    T rho, w;
+    robust<T>(loss, delta, s, rho, w);
+    const T sw = sqrt(w);
+    e.r[0] = sw * ar0;
+    e.r[1] = sw * ar1;
+    s_out = s;
+    rho_out = rho;
+    w_out = w;
+    if (!kJac) return;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const T j0 = e.jc[0][k], j1 = e.jc[1][k];
+        e.jc[0][k] = cam_fixed ? (T)0 : sw * (a00 * j0 + a01 * j1);
+        e.jc[1][k] = cam_fixed ? (T)0 : sw * (a11 * j1);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T j0 = e.jp[0][k], j1 = e.jp[1][k];
+        e.jp[0][k] = pt_fixed ? (T)0 : sw * (a00 * j0 + a01 * j1);
+        e.jp[1][k] = pt_fixed ? (T)0 : sw * (a11 * j1);
+    }
+}
+
+// ------------------------------------------------ small symmetric algebra
+// In-place inverse of a symmetric positive definite n x n matrix given as a
+// full row-major array, via Cholesky.  Returns false if not positive definite.
+template <int N>
+__device__ inline bool spd_inverse(double (&A)[N][N]) {
+    double L[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) L[i][j] = 0.0;
+    for (int j = 0; j < N; ++j) {
+        double s = A[j][j];
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0.0)) return false;
+        const double ljj = sqrt(s);
+        L[j][j] = ljj;
+        const double il = 1.0 / ljj;
+        for (int i = j + 1; i < N; ++i) {
+            double t = A[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t * il;
+        }
+    }
+    // Linv lower triangular
+    double Li[N][N];
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Li[i][j] = 0.0;
+    for (int i = 0; i < N; ++i) {
+        Li[i][i] = 1.0 / L[i][i];
+        for (int j = 0; j < i; ++j) {
+            double t = 0.0;
+            for (int k = j; k < i; ++k) t -= L[i][k] * Li[k][j];
+            Li[i][j] = t / L[i][i];
+        }
+    }
+    // A^{-1} = Linv^T Linv
+    for (int i = 0; i < N; ++i)
+        for (int j = i; j < N; ++j) {
+            double t = 0.0;
+            for (int k = j; k < N; ++k) t += Li[k][i] * Li[k][j];
+            A[i][j] = t;
+            A[j][i] = t;
+        }
+    return true;
+}
+
+}  // namespace gba

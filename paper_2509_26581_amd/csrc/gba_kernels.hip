@@ -1,0 +1,1016 @@
+// gfx950 kernels of one Levenberg-Marquardt iteration of bundle adjustment:
+// edge linearisation, block assembly, point-block damping and inversion,
+// Schur right-hand side, block-Jacobi preconditioner of the reduced camera
+// system, preconditioned conjugate gradients with fused implicit Schur
+// products, back-substitution, candidate cost and model decrease.
+//
+// Layout conventions (see gba_internal.h): edge arrays are structure-of-
+// arrays in point-major order, so a wavefront reads the Jacobian entries of 64
+// consecutive edges with one coalesced load per entry; camera vectors are
+// [n_cams][9]; per-point blocks are [6][n_pts] / [3][n_pts].
+#include <hip/hip_runtime.h>
+
+#include "gba_device.h"
+#include "gba_internal.h"
+
+namespace gba {
+
+// ==========================================================================
+// Linearisation: per edge residual and closed-form Jacobian, robust
+// whitening (Eq. 7 kernel on s = r^T Omega r, IRLS weight), storage of the
+// weighted blocks, and point-side sums Hpp_j = sum J_p^T J_p, bp_j =
+// sum J_p^T r (Eq. 5) by segmented wavefront reductions over the point's
+// contiguous edges.  One wavefront per tile of whole points.
+// ==========================================================================
+template <typename T, typename JS>
+__global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
+    const int l = lane_id();
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    T* Jc = (T*)g.jc;
+    T* Jp = (T*)g.jp;
+    JS* Jc16 = (JS*)g.jc16;
+    JS* Jp16 = (JS*)g.jp16;
+    T* rw = (T*)g.rw;
+    T* Hpp = (T*)g.hpp;
+    T* bp = (T*)g.bp;
+    const int ne = g.ne;
+    for (int t = wave; t < g.n_tiles; t += nwaves) {
+        const int e0 = g.tile_off[t], e1 = g.tile_off[t + 1];
+        const int n = e1 - e0;
+        T acc[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] = 0;
+        int j_first = g.e_pt[e0];
+        uint64_t starts = 0;
+        int head = 0, end = 63;
+        for (int c0 = 0; c0 < n; c0 += kWave) {
+            const int idx = c0 + l;
+            const bool valid = idx < n;
+            const int e = e0 + (valid ? idx : 0);
+            const int j = g.e_pt[e];
+            const int i = g.e_cam[e];
+            EdgeEval<T> ev;
+            bal_eval<T, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
+            T s, rho, w;
+            whiten<T, true>(ev, g.sinfo, ne, e, g.loss, g.delta, g.cam_fixed[i] != 0,
+                            g.pt_fixed[j] != 0, s, rho, w);
+            if (valid) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    Jc[k * ne + e] = ev.jc[0][k];
+                    Jc[(9 + k) * ne + e] = ev.jc[1][k];
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Jp[k * ne + e] = ev.jp[0][k];
+                    Jp[(3 + k) * ne + e] = ev.jp[1][k];
+                }
+                if (Jc16) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        Jc16[k * ne + e] = store_as<JS>(ev.jc[0][k]);
+                        Jc16[(9 + k) * ne + e] = store_as<JS>(ev.jc[1][k]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        Jp16[k * ne + e] = store_as<JS>(ev.jp[0][k]);
+                        Jp16[(3 + k) * ne + e] = store_as<JS>(ev.jp[1][k]);
+                    }
+                }
+                rw[e] = ev.r[0];
+                rw[ne + e] = ev.r[1];
+                if (raw.r) {
+                    // unweighted values for verification
+                    EdgeEval<double> ed;
+                    bal_eval<double, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ed);
+                    raw.r[e] = ed.r[0];
+                    raw.r[ne + e] = ed.r[1];
+                    const bool cf = g.cam_fixed[i] != 0, pf = g.pt_fixed[j] != 0;
+                    for (int k = 0; k < 9; ++k) {
+                        raw.jc[k * ne + e] = cf ? 0.0 : ed.jc[0][k];
+                        raw.jc[(9 + k) * ne + e] = cf ? 0.0 : ed.jc[1][k];
+                    }
+                    for (int k = 0; k < 3; ++k) {
+                        raw.jp[k * ne + e] = pf ? 0.0 : ed.jp[0][k];
+                        raw.jp[(3 + k) * ne + e] = pf ? 0.0 : ed.jp[1][k];
+                    }
+                    raw.w[e] = (double)w;
+                }
+            }
+            // point-side contributions of this edge
+            T h[9];
+            h[0] = ev.jp[0][0] * ev.jp[0][0] + ev.jp[1][0] * ev.jp[1][0];
+            h[1] = ev.jp[0][0] * ev.jp[0][1] + ev.jp[1][0] * ev.jp[1][1];
+            h[2] = ev.jp[0][0] * ev.jp[0][2] + ev.jp[1][0] * ev.jp[1][2];
+            h[3] = ev.jp[0][1] * ev.jp[0][1] + ev.jp[1][1] * ev.jp[1][1];
+            h[4] = ev.jp[0][1] * ev.jp[0][2] + ev.jp[1][1] * ev.jp[1][2];
+            h[5] = ev.jp[0][2] * ev.jp[0][2] + ev.jp[1][2] * ev.jp[1][2];
+            h[6] = ev.jp[0][0] * ev.r[0] + ev.jp[1][0] * ev.r[1];
+            h[7] = ev.jp[0][1] * ev.r[0] + ev.jp[1][1] * ev.r[1];
+            h[8] = ev.jp[0][2] * ev.r[0] + ev.jp[1][2] * ev.r[1];
+            if (n <= kWave) {
+                const bool st = !valid || idx == 0 || g.e_pt[e - 1] != j;
+                starts = __ballot(st);
+                segment_of(starts, l, head, end);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) acc[k] = segment_sum(valid ? h[k] : (T)0, l, end);
+                if (valid && head == l) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) Hpp[k * g.np + j] = acc[k];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) bp[k * g.np + j] = acc[6 + k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) acc[k] += valid ? h[k] : (T)0;
+            }
+        }
+        if (n > kWave) {
+            // one long point: full-wavefront sums
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[k] = wave_sum(acc[k]);
+            if (l == 0) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Hpp[k * g.np + j_first] = acc[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) bp[k * g.np + j_first] = acc[6 + k];
+            }
+        }
+    }
+}
+
+// ==========================================================================
+// Cost F = 1/2 sum_e rho(s_e) (Eq. 1 with the Eq. 7 kernel) in FP64 at the
+// given parameters; per-workgroup partial sums.
+// ==========================================================================
+__global__ __launch_bounds__(256) void k_cost(DeviceGraph g, const double* __restrict__ cam,
+                                              const double* __restrict__ pt) {
+    __shared__ double red[16];
+    double acc = 0.0;
+    const int ne = g.ne;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        const int i = g.e_cam[e], j = g.e_pt[e];
+        EdgeEval<double> ev;
+        bal_eval<double, false>(cam + 9 * i, pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
+        double s, rho, w;
+        whiten<double, false>(ev, g.sinfo, ne, e, g.loss, g.delta, false, false, s, rho, w);
+        acc += 0.5 * rho;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) g.cost_partial[blockIdx.x] = acc;
+}
+
+// ==========================================================================
+// Point blocks: Hpp_lambda = Hpp + lambda diag(clamp(diag Hpp)) (Eq. 4-6 with
+// the clamped diagonal), inverted in FP64 by Cholesky; fixed points get a
+// zero inverse (no unknowns).  Also initialises the candidate points and
+// the |x|^2 partial sums over free points.
+// ==========================================================================
+template <typename T>
+__global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double lambda, double min_diag,
+                                                     double max_diag) {
+    __shared__ double red[16];
+    const T* Hpp = (const T*)g.hpp;
+    double x2 = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.np; j += gridDim.x * blockDim.x) {
+        const bool fixed = g.pt_fixed[j] != 0;
+        double A[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) A[r][c] = (double)Hpp[sym3(r, c) * g.np + j];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) A[r][r] += lambda * fmin(fmax(A[r][r], min_diag), max_diag);
+        bool ok = !fixed && spd_inverse<3>(A);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = r; c < 3; ++c) g.hpp_inv[sym3(r, c) * g.np + j] = ok ? A[r][c] : 0.0;
+        const double p0 = g.pt[3 * j], p1 = g.pt[3 * j + 1], p2 = g.pt[3 * j + 2];
+        g.pt_c[3 * j] = p0;
+        g.pt_c[3 * j + 1] = p1;
+        g.pt_c[3 * j + 2] = p2;
+        g.dpt[3 * j] = 0.0;
+        g.dpt[3 * j + 1] = 0.0;
+        g.dpt[3 * j + 2] = 0.0;
+        if (!fixed) x2 += p0 * p0 + p1 * p1 + p2 * p2;
+    }
+    x2 = block_sum(x2, red);
+    if (threadIdx.x == 0) g.damp_partial[blockIdx.x] = x2;
+}
+
+// ==========================================================================
+// Camera-major accumulation over runs of equal (camera, point), recomputing
+// the edge Jacobians from the parameters (no gathers of stored Jacobians):
+//   kAssemble: Hcc_i = sum J_c^T J_c (45 unique), bc_i = sum J_c^T r (9)
+//   kPrecond:  sum over runs of W Hpp_lambda^{-1} W^T with W = sum_run J_c^T J_p
+//              (the point-elimination term of the 9x9 diagonal block of the
+//              Schur complement)
+// One workgroup per chunk of one camera's runs; partials per chunk.
+// ==========================================================================
+enum { kAssemble = 0, kPrecond = 1 };
+
+template <typename T, int kMode>
+__global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
+    constexpr int K = kMode == kAssemble ? 54 : 45;
+    __shared__ double red[4][K];
+    const int chunk = blockIdx.x;
+    const int cam = g.chunk_cam[chunk];
+    const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
+    const bool cfix = g.cam_fixed[cam] != 0;
+    T acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0;
+    const int ne = g.ne;
+    for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
+        const int q0 = g.cm_run_off[run], q1 = g.cm_run_off[run + 1];
+        const int j = g.cm_pt[q0];
+        const bool pfix = g.pt_fixed[j] != 0;
+        T W[9][3];
+#pragma unroll
+        for (int a = 0; a < 9; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) W[a][b] = 0;
+        for (int q = q0; q < q1; ++q) {
+            EdgeEval<T> ev;
+            bal_eval<T, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
+            T s, rho, w;
+            whiten<T, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
+            if (kMode == kAssemble) {
+                int k = 0;
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int b = a; b < 9; ++b, ++k)
+                        acc[k] += ev.jc[0][a] * ev.jc[0][b] + ev.jc[1][a] * ev.jc[1][b];
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+                    acc[45 + a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
+            } else {
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        W[a][b] += ev.jc[0][a] * ev.jp[0][b] + ev.jc[1][a] * ev.jp[1][b];
+            }
+        }
+        if (kMode == kPrecond) {
+            T Hi[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Hi[r][c] = (T)g.hpp_inv[sym3(r, c) * g.np + j];
+            T WH[9][3];
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    WH[a][c] = W[a][0] * Hi[0][c] + W[a][1] * Hi[1][c] + W[a][2] * Hi[2][c];
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int b = a; b < 9; ++b, ++k)
+                    acc[k] += WH[a][0] * W[b][0] + WH[a][1] * W[b][1] + WH[a][2] * W[b][2];
+        }
+    }
+    // workgroup reduction of the K accumulators
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double v = wave_sum((double)acc[k]);
+        if (lane_id() == 0) red[w][k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const int nw = blockDim.x >> 6;
+        double s = 0.0;
+        for (int q = 0; q < nw; ++q) s += red[q][k];
+        g.chunk_partial[chunk * 54 + k] = s;
+    }
+}
+
+// Per camera: sum the chunk partials.  kAssemble stores Hcc and bc.
+// kPrecond forms M_i = Hcc_lambda,i - sum W Hpp^-1 W^T and stores M_i^{-1}
+// (FP64 Cholesky); identity preconditioner stores I.  Fixed cameras: 0.
+template <typename T, int kMode>
+__global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double lambda, double min_diag,
+                                                     double max_diag, int block_jacobi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nc) return;
+    const int c0 = g.cam_chunk_off[i], c1 = g.cam_chunk_off[i + 1];
+    T* Hcc = (T*)g.hcc;
+    if (kMode == kAssemble) {
+        T* bc = (T*)g.bc;
+        for (int k = 0; k < 54; ++k) {
+            double s = 0.0;
+            for (int c = c0; c < c1; ++c) s += g.chunk_partial[c * 54 + k];
+            if (k < 45)
+                Hcc[i * 45 + k] = (T)s;
+            else
+                bc[i * 9 + (k - 45)] = (T)s;
+        }
+        return;
+    }
+    T* Minv = (T*)g.minv;
+    const bool fixed = g.cam_fixed[i] != 0;
+    if (fixed) {
+        for (int k = 0; k < 45; ++k) Minv[i * 45 + k] = 0;
+        return;
+    }
+    double M[9][9];
+    for (int r = 0; r < 9; ++r)
+        for (int c = r; c < 9; ++c) {
+            double h = (double)Hcc[i * 45 + sym9(r, c)];
+            if (r == c) h += lambda * fmin(fmax(h, min_diag), max_diag);
+            if (block_jacobi) {
+                double s = 0.0;
+                for (int q = c0; q < c1; ++q) s += g.chunk_partial[q * 54 + sym9(r, c)];
+                h -= s;
+            }
+            M[r][c] = h;
+            M[c][r] = h;
+        }
+    if (!block_jacobi) {
+        for (int r = 0; r < 9; ++r)
+            for (int c = r; c < 9; ++c) Minv[i * 45 + sym9(r, c)] = (T)(r == c ? 1.0 : 0.0);
+        return;
+    }
+    if (!spd_inverse<9>(M)) {
+        // rounding left the block indefinite: fall back to the damped diagonal
+        for (int r = 0; r < 9; ++r)
+            for (int c = r; c < 9; ++c) {
+                double h = (double)Hcc[i * 45 + sym9(r, r)];
+                h += lambda * fmin(fmax(h, min_diag), max_diag);
+                Minv[i * 45 + sym9(r, c)] = (T)(r == c ? 1.0 / h : 0.0);
+            }
+        return;
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = r; c < 9; ++c) Minv[i * 45 + sym9(r, c)] = (T)M[r][c];
+}
+
+// ==========================================================================
+// Point passes over the stored weighted Jacobians, one wavefront per tile of
+// whole points, camera-side sums privatised in LDS per workgroup and flushed
+// as one partial camera vector per workgroup (no global atomics):
+//   kRhs:     sum_e J_c^T J_p (Hpp^-1 bp_j)                       (reduced RHS)
+//   kMatvec:  sum_e J_c^T J_p Hpp^-1 sum_e' J_p^T J_c' p_i'       (Schur product)
+//   kBacksub: dp_j = -Hpp^-1 (bp_j + sum_e J_p^T J_c dc_i), candidate points,
+//             model terms sum |J_e dx_e|^2, bp^T dp, |dp|^2
+// ==========================================================================
+enum { kRhs = 0, kMatvec = 1, kBacksub = 2 };
+
+template <typename T, typename JS, typename AT, int kMode>
+__global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __restrict__ Jc,
+                                                     const JS* __restrict__ Jp,
+                                                     const T* __restrict__ vin, AT* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    AT* acc_lds = (AT*)smem_raw;
+    __shared__ double red[16];
+    const int l = lane_id();
+    const int nc9 = 9 * g.nc;
+    if (kMode != kBacksub) {
+        for (int k = threadIdx.x; k < nc9; k += blockDim.x) acc_lds[k] = 0;
+        __syncthreads();
+    }
+    // contiguous tile range of this workgroup, wavefronts interleaved
+    const int tb = (int)(((long long)g.n_tiles * blockIdx.x) / gridDim.x);
+    const int te = (int)(((long long)g.n_tiles * (blockIdx.x + 1)) / gridDim.x);
+    const int nw = blockDim.x >> 6;
+    const int ne = g.ne;
+    const T* bp = (const T*)g.bp;
+    const T* rw = (const T*)g.rw;
+    double red_m = 0.0, red_b = 0.0, red_s = 0.0;
+    for (int t = tb + (int)(threadIdx.x >> 6); t < te; t += nw) {
+        const int e0 = g.tile_off[t], e1 = g.tile_off[t + 1];
+        const int n = e1 - e0;
+        if (n <= kWave) {
+            const bool valid = l < n;
+            const int e = e0 + (valid ? l : 0);
+            const int j = g.e_pt[e];
+            const int i = g.e_cam[e];
+            const bool st = !valid || l == 0 || g.e_pt[e - 1] != j;
+            const uint64_t starts = __ballot(st);
+            int head, end;
+            segment_of(starts, l, head, end);
+            T jc[2][9], jp[2][3];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                jc[0][k] = load_as<T>(Jc[k * ne + e]);
+                jc[1][k] = load_as<T>(Jc[(9 + k) * ne + e]);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                jp[0][k] = load_as<T>(Jp[k * ne + e]);
+                jp[1][k] = load_as<T>(Jp[(3 + k) * ne + e]);
+            }
+            T z[3];
+            T pc[9];
+            if (kMode == kRhs) {
+                const T b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
+                const double* H = g.hpp_inv;
+                const T h00 = (T)H[j], h01 = (T)H[g.np + j], h02 = (T)H[2 * g.np + j];
+                const T h11 = (T)H[3 * g.np + j], h12 = (T)H[4 * g.np + j], h22 = (T)H[5 * g.np + j];
+                z[0] = h00 * b0 + h01 * b1 + h02 * b2;
+                z[1] = h01 * b0 + h11 * b1 + h12 * b2;
+                z[2] = h02 * b0 + h12 * b1 + h22 * b2;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) pc[k] = vin[9 * i + k];
+                T a0 = 0, a1 = 0;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    a0 += jc[0][k] * pc[k];
+                    a1 += jc[1][k] * pc[k];
+                }
+                T tt[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    tt[k] = valid ? jp[0][k] * a0 + jp[1][k] * a1 : (T)0;
+                    tt[k] = segment_sum(tt[k], l, end);
+                }
+                // head lane applies the point block
+                const double* H = g.hpp_inv;
+                T zz[3] = {0, 0, 0};
+                if (valid && head == l) {
+                    const T h00 = (T)H[j], h01 = (T)H[g.np + j], h02 = (T)H[2 * g.np + j];
+                    const T h11 = (T)H[3 * g.np + j], h12 = (T)H[4 * g.np + j];
+                    const T h22 = (T)H[5 * g.np + j];
+                    T v0 = tt[0], v1 = tt[1], v2 = tt[2];
+                    if (kMode == kBacksub) {
+                        v0 += bp[j];
+                        v1 += bp[g.np + j];
+                        v2 += bp[2 * g.np + j];
+                    }
+                    zz[0] = h00 * v0 + h01 * v1 + h02 * v2;
+                    zz[1] = h01 * v0 + h11 * v1 + h12 * v2;
+                    zz[2] = h02 * v0 + h12 * v1 + h22 * v2;
+                    if (kMode == kBacksub) {
+                        zz[0] = -zz[0];
+                        zz[1] = -zz[1];
+                        zz[2] = -zz[2];
+                        const double d0 = zz[0], d1 = zz[1], d2 = zz[2];
+                        g.dpt[3 * j] = d0;
+                        g.dpt[3 * j + 1] = d1;
+                        g.dpt[3 * j + 2] = d2;
+                        g.pt_c[3 * j] = g.pt[3 * j] + d0;
+                        g.pt_c[3 * j + 1] = g.pt[3 * j + 1] + d1;
+                        g.pt_c[3 * j + 2] = g.pt[3 * j + 2] + d2;
+                        red_b += (double)bp[j] * d0 + (double)bp[g.np + j] * d1 +
+                                 (double)bp[2 * g.np + j] * d2;
+                        red_s += d0 * d0 + d1 * d1 + d2 * d2;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) z[k] = shfl64(zz[k], head);
+            }
+            if (kMode == kBacksub) {
+                if (valid) {
+                    T y0 = jp[0][0] * z[0] + jp[0][1] * z[1] + jp[0][2] * z[2];
+                    T y1 = jp[1][0] * z[0] + jp[1][1] * z[1] + jp[1][2] * z[2];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        y0 += jc[0][k] * pc[k];
+                        y1 += jc[1][k] * pc[k];
+                    }
+                    red_m += (double)y0 * (double)y0 + (double)y1 * (double)y1;
+                }
+            } else if (valid) {
+                const T u0 = jp[0][0] * z[0] + jp[0][1] * z[1] + jp[0][2] * z[2];
+                const T u1 = jp[1][0] * z[0] + jp[1][1] * z[1] + jp[1][2] * z[2];
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    atomicAdd(&acc_lds[9 * i + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
+            }
+        } else {
+            // a single point with more than 64 edges: two sweeps over chunks
+            const int j = g.e_pt[e0];
+            T z[3];
+            if (kMode == kRhs) {
+                const T b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
+                const double* H = g.hpp_inv;
+                z[0] = (T)H[j] * b0 + (T)H[g.np + j] * b1 + (T)H[2 * g.np + j] * b2;
+                z[1] = (T)H[g.np + j] * b0 + (T)H[3 * g.np + j] * b1 + (T)H[4 * g.np + j] * b2;
+                z[2] = (T)H[2 * g.np + j] * b0 + (T)H[4 * g.np + j] * b1 + (T)H[5 * g.np + j] * b2;
+            } else {
+                T tt[3] = {0, 0, 0};
+                for (int c0 = 0; c0 < n; c0 += kWave) {
+                    if (c0 + l < n) {
+                        const int e = e0 + c0 + l;
+                        const int i = g.e_cam[e];
+                        T a0 = 0, a1 = 0;
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) {
+                            const T pk = vin[9 * i + k];
+                            a0 += load_as<T>(Jc[k * ne + e]) * pk;
+                            a1 += load_as<T>(Jc[(9 + k) * ne + e]) * pk;
+                        }
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            tt[k] += load_as<T>(Jp[k * ne + e]) * a0 +
+                                     load_as<T>(Jp[(3 + k) * ne + e]) * a1;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) tt[k] = wave_sum(tt[k]);
+                if (kMode == kBacksub) {
+                    tt[0] += bp[j];
+                    tt[1] += bp[g.np + j];
+                    tt[2] += bp[2 * g.np + j];
+                }
+                const double* H = g.hpp_inv;
+                z[0] = (T)H[j] * tt[0] + (T)H[g.np + j] * tt[1] + (T)H[2 * g.np + j] * tt[2];
+                z[1] = (T)H[g.np + j] * tt[0] + (T)H[3 * g.np + j] * tt[1] + (T)H[4 * g.np + j] * tt[2];
+                z[2] = (T)H[2 * g.np + j] * tt[0] + (T)H[4 * g.np + j] * tt[1] + (T)H[5 * g.np + j] * tt[2];
+                if (kMode == kBacksub) {
+                    z[0] = -z[0];
+                    z[1] = -z[1];
+                    z[2] = -z[2];
+                    if (l == 0) {
+                        const double d0 = z[0], d1 = z[1], d2 = z[2];
+                        g.dpt[3 * j] = d0;
+                        g.dpt[3 * j + 1] = d1;
+                        g.dpt[3 * j + 2] = d2;
+                        g.pt_c[3 * j] = g.pt[3 * j] + d0;
+                        g.pt_c[3 * j + 1] = g.pt[3 * j + 1] + d1;
+                        g.pt_c[3 * j + 2] = g.pt[3 * j + 2] + d2;
+                        red_b += (double)bp[j] * d0 + (double)bp[g.np + j] * d1 +
+                                 (double)bp[2 * g.np + j] * d2;
+                        red_s += d0 * d0 + d1 * d1 + d2 * d2;
+                    }
+                }
+            }
+            for (int c0 = 0; c0 < n; c0 += kWave) {
+                if (c0 + l < n) {
+                    const int e = e0 + c0 + l;
+                    const int i = g.e_cam[e];
+                    T u0 = 0, u1 = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        u0 += load_as<T>(Jp[k * ne + e]) * z[k];
+                        u1 += load_as<T>(Jp[(3 + k) * ne + e]) * z[k];
+                    }
+                    if (kMode == kBacksub) {
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) {
+                            const T pk = vin[9 * i + k];
+                            u0 += load_as<T>(Jc[k * ne + e]) * pk;
+                            u1 += load_as<T>(Jc[(9 + k) * ne + e]) * pk;
+                        }
+                        red_m += (double)u0 * (double)u0 + (double)u1 * (double)u1;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 9; ++k)
+                            atomicAdd(&acc_lds[9 * i + k],
+                                      (AT)(load_as<T>(Jc[k * ne + e]) * u0 +
+                                           load_as<T>(Jc[(9 + k) * ne + e]) * u1));
+                    }
+                }
+            }
+        }
+    }
+    if (kMode == kBacksub) {
+        red_m = block_sum(red_m, red);
+        red_b = block_sum(red_b, red);
+        red_s = block_sum(red_s, red);
+        if (threadIdx.x == 0) {
+            g.red_partial[4 * blockIdx.x + 0] = red_m;
+            g.red_partial[4 * blockIdx.x + 1] = red_b;
+            g.red_partial[4 * blockIdx.x + 2] = red_s;
+            g.red_partial[4 * blockIdx.x + 3] = 0.0;
+        }
+        return;
+    }
+    __syncthreads();
+    AT* dst = out + (size_t)blockIdx.x * nc9;
+    for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = acc_lds[k];
+}
+
+// ==========================================================================
+// Sum of the per-workgroup camera partials.
+//   kRhs:    r = -bc + sum                              (reduced RHS)
+//   kMatvec: q = Hcc_lambda p - sum, and partial dots p^T q (FP64)
+// Workgroup: 64 components x 16 partial groups.
+// ==========================================================================
+template <typename T, typename AT, int kMode>
+__global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __restrict__ part,
+                                                 double lambda, double min_diag, double max_diag) {
+    __shared__ double red[16][64];
+    __shared__ double dred[16];
+    const int cl = threadIdx.x & 63;
+    const int grp = threadIdx.x >> 6;
+    const int nc9 = 9 * g.nc;
+    const int k = blockIdx.x * 64 + cl;
+    double s = 0.0;
+    if (k < nc9)
+        for (int b = grp; b < g.grid_pp; b += 16) s += (double)part[(size_t)b * nc9 + k];
+    red[grp][cl] = s;
+    __syncthreads();
+    double dot = 0.0;
+    if (grp == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < 16; ++q) tot += red[q][cl];
+        if (k < nc9) {
+            const int i = k / 9, r = k % 9;
+            if (kMode == kRhs) {
+                const T* bc = (const T*)g.bc;
+                ((T*)g.v_r)[k] = (T)(-(double)bc[k] + tot);
+            } else {
+                const T* Hcc = (const T*)g.hcc;
+                const T* p = (const T*)g.v_p;
+                double hp = 0.0;
+                for (int c = 0; c < 9; ++c) {
+                    double h = (double)Hcc[i * 45 + sym9(r, c)];
+                    if (c == r) h += lambda * fmin(fmax(h, min_diag), max_diag);
+                    hp += h * (double)p[9 * i + c];
+                }
+                const double q = hp - tot;
+                ((T*)g.v_q)[k] = (T)q;
+                dot = (double)p[k] * (double)(T)q;
+            }
+        }
+    }
+    if (kMode == kMatvec) {
+        dot = block_sum(dot, dred);
+        if (threadIdx.x == 0) g.pq_partial[blockIdx.x] = dot;
+    }
+}
+
+// ==========================================================================
+// PCG on the reduced camera system (single workgroup: the camera vectors are
+// small).  Dots in FP64.  State in PcgState.
+// ==========================================================================
+template <typename T>
+__device__ __forceinline__ void apply_minv(const T* __restrict__ Minv, const T* __restrict__ r,
+                                           T* __restrict__ z, int i) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        T s = 0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) s += Minv[i * 45 + sym9(a, b)] * r[9 * i + b];
+        z[9 * i + a] = s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pcg_init(DeviceGraph g, double tol, int relative) {
+    __shared__ double red[16];
+    T* x = (T*)g.v_x;
+    T* r = (T*)g.v_r;
+    T* z = (T*)g.v_z;
+    T* p = (T*)g.v_p;
+    const T* Minv = (const T*)g.minv;
+    double rz = 0.0, rr = 0.0;
+    for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
+        apply_minv(Minv, r, z, i);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const int k = 9 * i + a;
+            x[k] = 0;
+            p[k] = z[k];
+            rz += (double)r[k] * (double)z[k];
+            rr += (double)r[k] * (double)r[k];
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        PcgState* st = g.pcg;
+        st->rz = rz;
+        st->rr = rr;
+        st->rr0 = rr;
+        st->min_rr = rr;
+        st->thresh = relative ? tol * tol * rr : tol * tol;
+        st->iters = 0;
+        st->use_best = 0;
+        st->done = (rr <= st->thresh || !(rz > 0.0)) ? 1 : 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pcg_update(DeviceGraph g, int max_iters, double ratio) {
+    __shared__ double red[16];
+    __shared__ int s_done, s_copy_best;
+    PcgState* st = g.pcg;
+    if (st->done) return;
+    double pq = 0.0;
+    for (int b = threadIdx.x; b < g.grid_red; b += blockDim.x) pq += g.pq_partial[b];
+    pq = block_sum(pq, red);
+    const double rz_old = st->rz;
+    const bool breakdown = !(pq > 0.0) || !isfinite(pq);
+    const double alpha = breakdown ? 0.0 : rz_old / pq;
+    T* x = (T*)g.v_x;
+    T* r = (T*)g.v_r;
+    T* z = (T*)g.v_z;
+    T* p = (T*)g.v_p;
+    const T* q = (const T*)g.v_q;
+    const T* Minv = (const T*)g.minv;
+    double rz = 0.0, rr = 0.0;
+    if (!breakdown) {
+        for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const int k = 9 * i + a;
+                x[k] = (T)((double)x[k] + alpha * (double)p[k]);
+                r[k] = (T)((double)r[k] - alpha * (double)q[k]);
+            }
+            apply_minv(Minv, r, z, i);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                const int k = 9 * i + a;
+                rz += (double)r[k] * (double)z[k];
+                rr += (double)r[k] * (double)r[k];
+            }
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        int done = 0, copy_best = 0;
+        if (breakdown) {
+            done = 3;
+        } else {
+            st->iters += 1;
+            st->rr = rr;
+            const bool track = ratio > 0.0 && isfinite(ratio);
+            if (track && rr < st->min_rr) {
+                st->min_rr = rr;
+                copy_best = 1;
+            } else if (track && rr > ratio * ratio * st->min_rr) {
+                done = 4;
+            }
+            if (!done && rr <= st->thresh) done = 1;
+            if (!done && st->iters >= max_iters) done = 2;
+        }
+        s_done = done;
+        s_copy_best = copy_best;
+    }
+    __syncthreads();
+    const int done = s_done;
+    const int copy_best = s_copy_best;
+    const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
+    T* best = (T*)g.v_best;
+    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
+        if (done == 0) p[k] = (T)((double)z[k] + beta * (double)p[k]);
+        if (copy_best) best[k] = x[k];
+        if (done == 4) x[k] = best[k];
+    }
+    if (threadIdx.x == 0) {
+        if (copy_best) st->use_best = 1;
+        st->rz = rz;
+        st->done = done;
+    }
+}
+
+// ==========================================================================
+// Cameras after PCG: dc = x, candidate cameras, bc^T dc, |dc|^2, |c|^2 over
+// free cameras (single workgroup).
+// ==========================================================================
+template <typename T>
+__global__ __launch_bounds__(1024) void k_cam_update(DeviceGraph g) {
+    __shared__ double red[16];
+    const T* x = (const T*)g.v_x;
+    const T* bc = (const T*)g.bc;
+    double bdx = 0.0, s2 = 0.0, x2 = 0.0;
+    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
+        const int i = k / 9;
+        const bool fixed = g.cam_fixed[i] != 0;
+        const double d = fixed ? 0.0 : (double)x[k];
+        const double c = g.cam[k];
+        g.cam_c[k] = c + d;
+        bdx += (double)bc[k] * d;
+        s2 += d * d;
+        if (!fixed) x2 += c * c;
+    }
+    bdx = block_sum(bdx, red);
+    s2 = block_sum(s2, red);
+    x2 = block_sum(x2, red);
+    if (threadIdx.x == 0) {
+        g.scal->b_dot_dx = bdx;
+        g.scal->step2 = s2;
+        g.scal->x2 = x2;
+    }
+}
+
+// Combine the per-workgroup partial sums of the trial (single workgroup).
+__global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
+    __shared__ double red[16];
+    double c = 0.0, m = 0.0, b = 0.0, s = 0.0, x = 0.0;
+    for (int k = threadIdx.x; k < g.grid_edges; k += blockDim.x) c += g.cost_partial[k];
+    for (int k = threadIdx.x; k < g.grid_pp; k += blockDim.x) {
+        m += g.red_partial[4 * k + 0];
+        b += g.red_partial[4 * k + 1];
+        s += g.red_partial[4 * k + 2];
+    }
+    for (int k = threadIdx.x; k < g.grid_pts; k += blockDim.x) x += g.damp_partial[k];
+    c = block_sum(c, red);
+    m = block_sum(m, red);
+    b = block_sum(b, red);
+    s = block_sum(s, red);
+    x = block_sum(x, red);
+    if (threadIdx.x == 0) {
+        TrialScalars* t = g.scal;
+        t->cost = c;
+        t->quad = m;
+        t->b_dot_dx += b;
+        t->step2 += s;
+        t->x2 += x;
+        t->pcg_iters = g.pcg->iters;
+        t->pcg_reason = g.pcg->done;
+    }
+}
+
+// cost only (no trial): combine cost partials into scal->cost
+__global__ __launch_bounds__(1024) void k_cost_finish(DeviceGraph g) {
+    __shared__ double red[16];
+    double c = 0.0;
+    for (int k = threadIdx.x; k < g.grid_edges; k += blockDim.x) c += g.cost_partial[k];
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) g.scal->cost = c;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, size_t n) {
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+// ==========================================================================
+// launchers
+// ==========================================================================
+template <typename F>
+static hipError_t dispatch(const DeviceGraph& g, F&& f) {
+    return f(g.mode);
+}
+
+#define GBA_CHECK_LAUNCH() \
+    do {                   \
+        hipError_t e_ = hipGetLastError(); \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
+hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw) {
+    RawOut r = raw ? *raw : RawOut{nullptr, nullptr, nullptr, nullptr};
+    const int blocks = (g.n_tiles * kWave + 255) / 256;
+    const int grid = blocks < 1 ? 1 : blocks;
+    if (g.mode == kModeFP64) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.hpp, 0.0, (size_t)6 * g.np);
+        hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.bp, 0.0, (size_t)3 * g.np);
+        hipLaunchKernelGGL((k_linearize<double, double>), dim3(grid), dim3(256), 0, s, g, r);
+    } else if (g.mode == kModeFP32) {
+        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
+        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
+        hipLaunchKernelGGL((k_linearize<float, float>), dim3(grid), dim3(256), 0, s, g, r);
+    } else {
+        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
+        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
+        hipLaunchKernelGGL((k_linearize<float, bf16>), dim3(grid), dim3(256), 0, s, g, r);
+    }
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
+    if (g.n_chunks > 0) {
+        if (g.mode == kModeFP64)
+            hipLaunchKernelGGL((k_cam_accumulate<double, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        else
+            hipLaunchKernelGGL((k_cam_accumulate<float, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        GBA_CHECK_LAUNCH();
+    }
+    const int grid = (g.nc + 63) / 64;
+    if (g.mode == kModeFP64)
+        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(grid), dim3(64), 0, s, g, 0.0, 0.0, 0.0, 0);
+    else
+        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(grid), dim3(64), 0, s, g, 0.0, 0.0, 0.0, 0);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_cost(const DeviceGraph& g, hipStream_t s, const double* cam, const double* pt) {
+    hipLaunchKernelGGL(k_cost, dim3(g.grid_edges), dim3(256), 0, s, g, cam, pt);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
+                       double max_diag) {
+    if (g.mode == kModeFP64)
+        hipLaunchKernelGGL(k_damp_points<double>, dim3(g.grid_pts), dim3(256), 0, s, g, lambda, min_diag, max_diag);
+    else
+        hipLaunchKernelGGL(k_damp_points<float>, dim3(g.grid_pts), dim3(256), 0, s, g, lambda, min_diag, max_diag);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
+                          double max_diag, int block_jacobi) {
+    if (block_jacobi && g.n_chunks > 0) {
+        if (g.mode == kModeFP64)
+            hipLaunchKernelGGL((k_cam_accumulate<double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        else
+            hipLaunchKernelGGL((k_cam_accumulate<float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        GBA_CHECK_LAUNCH();
+    }
+    const int grid = (g.nc + 63) / 64;
+    if (g.mode == kModeFP64)
+        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(grid), dim3(64), 0, s, g, lambda, min_diag, max_diag, block_jacobi);
+    else
+        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(grid), dim3(64), 0, s, g, lambda, min_diag, max_diag, block_jacobi);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename T, typename JS, typename AT, int kMode>
+static void point_pass(const DeviceGraph& g, hipStream_t s, const void* jc, const void* jp,
+                       const void* vin, void* out) {
+    // allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per CU)
+    static int lds_set = -1;
+    if (kMode != kBacksub && g.lds_pp > 0 && lds_set < g.lds_pp) {
+        (void)hipFuncSetAttribute((const void*)k_point_pass<T, JS, AT, kMode>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_pp);
+        lds_set = g.lds_pp;
+    }
+    hipLaunchKernelGGL((k_point_pass<T, JS, AT, kMode>), dim3(g.grid_pp), dim3(g.block_pp),
+                       kMode == kBacksub ? 0 : g.lds_pp, s, g, (const JS*)jc, (const JS*)jp,
+                       (const T*)vin, (AT*)out);
+}
+
+hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
+    const int grid_red = (9 * g.nc + 63) / 64;
+    if (g.mode == kModeFP64) {
+        point_pass<double, double, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+        hipLaunchKernelGGL((k_reduce<double, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
+                           (const double*)g.cam_partial, 0.0, 0.0, 0.0);
+    } else {
+        point_pass<float, float, float, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+        hipLaunchKernelGGL((k_reduce<float, float, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
+                           (const float*)g.cam_partial, 0.0, 0.0, 0.0);
+    }
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int relative) {
+    if (g.mode == kModeFP64)
+        hipLaunchKernelGGL(k_pcg_init<double>, dim3(1), dim3(1024), 0, s, g, tol, relative);
+    else
+        hipLaunchKernelGGL(k_pcg_init<float>, dim3(1), dim3(1024), 0, s, g, tol, relative);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
+                           double max_diag, int max_iters, double ratio, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+    const int grid_red = (9 * g.nc + 63) / 64;
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (g.mode == kModeFP64) {
+        point_pass<double, double, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
+    } else if (g.mode == kModeFP32) {
+        point_pass<float, float, float, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
+    } else {
+        point_pass<float, bf16, float, kMatvec>(g, s, g.jc16, g.jp16, g.v_p, g.cam_partial);
+    }
+    if (ev1) (void)hipEventRecord(ev1, s);
+    if (g.mode == kModeFP64) {
+        hipLaunchKernelGGL((k_reduce<double, double, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
+                           (const double*)g.cam_partial, lambda, min_diag, max_diag);
+        hipLaunchKernelGGL(k_pcg_update<double>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+    } else {
+        hipLaunchKernelGGL((k_reduce<float, float, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
+                           (const float*)g.cam_partial, lambda, min_diag, max_diag);
+        hipLaunchKernelGGL(k_pcg_update<float>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+    }
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s) {
+    if (g.mode == kModeFP64) {
+        hipLaunchKernelGGL(k_cam_update<double>, dim3(1), dim3(1024), 0, s, g);
+        point_pass<double, double, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+    } else {
+        hipLaunchKernelGGL(k_cam_update<float>, dim3(1), dim3(1024), 0, s, g);
+        point_pass<float, float, float, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+    }
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_finish(const DeviceGraph& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, g);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_cost_finish(const DeviceGraph& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_cost_finish, dim3(1), dim3(1024), 0, s, g);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+}  // namespace gba

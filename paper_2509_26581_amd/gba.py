@@ -1,0 +1,380 @@
+"""Python binding of the gfx950 bundle-adjustment library (libgba.so).
+
+Argument marshalling only: every function forwards to the C ABI of the same
+name declared in include/gba.h; all arithmetic runs in the HIP kernels.  The
+library is required: importing a function that needs it raises GbaError when
+libgba.so has not been built (python -m paper_2509_26581_amd.build).
+
+PyTorch is used only as plumbing: `torch_allocator()` hands the library
+PyTorch's caching allocator and `torch_stream()` the current HIP stream.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgba.so")
+
+GBA_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "UNKNOWN_ID", -3: "DUPLICATE_ID", -4: "NONFINITE",
+          -5: "OOM", -6: "HIP", -7: "STATE", -8: "UNSUPPORTED"}
+
+GBA_FP64, GBA_MIXED_FP32, GBA_MIXED_BF16 = 0, 1, 2
+GBA_LOSS_SQUARED, GBA_LOSS_HUBER = 0, 1
+GBA_PRECOND_IDENTITY, GBA_PRECOND_BLOCK_JACOBI = 0, 1
+TERMINATION = {0: "NONE", 1: "MAX_ITERS", 2: "COST_TOL", 3: "STEP_TOL",
+               4: "LAMBDA_OVERFLOW", 5: "NUMERICAL_FAILURE", 6: "NO_WORK"}
+
+
+class GbaError(RuntimeError):
+    def __init__(self, status, message=""):
+        super().__init__(f"gba error {status} ({ERRORS.get(status, '?')}): {message}")
+        self.status = status
+
+
+class gba_options(ctypes.Structure):
+    _fields_ = [("initial_lambda", ctypes.c_double), ("min_diag", ctypes.c_double),
+                ("max_diag", ctypes.c_double), ("pcg_max_iters", ctypes.c_int),
+                ("pcg_tol", ctypes.c_double), ("pcg_tol_relative", ctypes.c_int),
+                ("pcg_rejection_ratio", ctypes.c_double), ("precond", ctypes.c_int),
+                ("timing", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+
+
+class gba_report(ctypes.Structure):
+    _fields_ = [("initial_cost", ctypes.c_double), ("final_cost", ctypes.c_double),
+                ("final_lambda", ctypes.c_double), ("trials", ctypes.c_int),
+                ("accepted", ctypes.c_int), ("pcg_iters_total", ctypes.c_int),
+                ("termination", ctypes.c_int), ("ms_total", ctypes.c_double),
+                ("ms_linearize", ctypes.c_double), ("ms_precond", ctypes.c_double),
+                ("ms_pcg", ctypes.c_double), ("ms_other", ctypes.c_double),
+                ("ms_matvec", ctypes.c_double), ("matvec_count", ctypes.c_int),
+                ("reserved_i", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved_i"}
+        d["termination_name"] = TERMINATION.get(self.termination, "?")
+        return d
+
+
+class gba_trial(ctypes.Structure):
+    _fields_ = [("cost", ctypes.c_double), ("candidate_cost", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("model_decrease", ctypes.c_double),
+                ("step_norm", ctypes.c_double), ("accepted", ctypes.c_int),
+                ("pcg_iters", ctypes.c_int)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+_SIGS = {
+    "gba_default_options": (None, [ctypes.POINTER(gba_options)]),
+    "gba_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ALLOC_FN, FREE_FN, _P,
+                                  ctypes.POINTER(_P)]),
+    "gba_set_stream": (ctypes.c_int, [_P, _P]),
+    "gba_reserve": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]),
+    "gba_add_cameras": (ctypes.c_int, [_P, ctypes.c_int64, _I64, _D]),
+    "gba_add_points": (ctypes.c_int, [_P, ctypes.c_int64, _I64, _D]),
+    "gba_add_edges": (ctypes.c_int, [_P, ctypes.c_int64, _I64, _I64, _D, _D]),
+    "gba_set_fixed": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int]),
+    "gba_set_edge_active": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int]),
+    "gba_set_robust_kernel": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double]),
+    "gba_set_options": (ctypes.c_int, [_P, ctypes.POINTER(gba_options)]),
+    "gba_prepare": (ctypes.c_int, [_P]),
+    "gba_solve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.POINTER(gba_report)]),
+    "gba_reset": (ctypes.c_int, [_P]),
+    "gba_get_cost": (ctypes.c_int, [_P, _D]),
+    "gba_get_cameras": (ctypes.c_int, [_P, _D]),
+    "gba_get_points": (ctypes.c_int, [_P, _D]),
+    "gba_get_trials": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(gba_trial),
+                                      ctypes.POINTER(ctypes.c_int)]),
+    "gba_eval_edges": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "gba_eval_normal_equations": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "gba_eval_step": (ctypes.c_int, [_P, ctypes.c_double, _D, _D, ctypes.POINTER(ctypes.c_int)]),
+    "gba_last_error": (ctypes.c_char_p, [_P]),
+    "gba_destroy": (None, [_P]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load libgba.so; raise GbaError if it is absent (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise GbaError(-8, f"{path} is not built; run python -m paper_2509_26581_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _ptr(a, dtype=np.float64):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(np.ctypeslib.as_ctypes_type(dtype)))
+
+
+def _arr(a, dtype, shape_tail=None):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape_tail is not None:
+        a = a.reshape((-1,) + tuple(shape_tail))
+    return a
+
+
+def _check(h, status):
+    if status != GBA_OK:
+        msg = load().gba_last_error(h)
+        raise GbaError(status, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------- C names
+def gba_default_options():
+    o = gba_options()
+    load().gba_default_options(ctypes.byref(o))
+    return o
+
+
+class _Allocator:
+    """Keeps ctypes callbacks alive for the lifetime of a graph."""
+
+    def __init__(self, alloc_fn, free_fn):
+        self.alloc = ALLOC_FN(alloc_fn)
+        self.free = FREE_FN(free_fn)
+
+
+def torch_allocator(device=0):
+    """PyTorch caching-allocator callbacks (device memory plumbing only)."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        stream = torch.cuda.current_stream(device).cuda_stream
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return _Allocator(_alloc, _free)
+
+
+def torch_stream(device=0):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def gba_create(precision=GBA_FP64, device=0, allocator=None):
+    lib = load()
+    h = _P()
+    a = allocator.alloc if allocator else ALLOC_FN(0)
+    f = allocator.free if allocator else FREE_FN(0)
+    st = lib.gba_create(int(precision), int(device), a, f, None, ctypes.byref(h))
+    if st != GBA_OK:
+        raise GbaError(st, "gba_create failed")
+    return h
+
+
+def gba_set_stream(h, stream):
+    _check(h, load().gba_set_stream(h, _P(stream)))
+
+
+def gba_reserve(h, n_cams, n_pts, n_edges):
+    _check(h, load().gba_reserve(h, int(n_cams), int(n_pts), int(n_edges)))
+
+
+def gba_add_cameras(h, ids, params):
+    ids = _arr(ids, np.int64)
+    params = _arr(params, np.float64, (9,))
+    _check(h, load().gba_add_cameras(h, len(ids), _ptr(ids, np.int64), _ptr(params)))
+
+
+def gba_add_points(h, ids, xyz):
+    ids = _arr(ids, np.int64)
+    xyz = _arr(xyz, np.float64, (3,))
+    _check(h, load().gba_add_points(h, len(ids), _ptr(ids, np.int64), _ptr(xyz)))
+
+
+def gba_add_edges(h, cam_ids, pt_ids, uv, info=None):
+    c = _arr(cam_ids, np.int64)
+    p = _arr(pt_ids, np.int64)
+    uv = _arr(uv, np.float64, (2,))
+    inf = None if info is None else _arr(info, np.float64, (3,))
+    _check(h, load().gba_add_edges(h, len(c), _ptr(c, np.int64), _ptr(p, np.int64), _ptr(uv),
+                                   _ptr(inf)))
+
+
+def gba_set_fixed(h, kind, vid, fixed=True):
+    _check(h, load().gba_set_fixed(h, int(kind), int(vid), 1 if fixed else 0))
+
+
+def gba_set_edge_active(h, edge_index, active=True):
+    _check(h, load().gba_set_edge_active(h, int(edge_index), 1 if active else 0))
+
+
+def gba_set_robust_kernel(h, loss, delta=1.0):
+    _check(h, load().gba_set_robust_kernel(h, int(loss), float(delta)))
+
+
+def gba_set_options(h, opts):
+    _check(h, load().gba_set_options(h, ctypes.byref(opts)))
+
+
+def gba_prepare(h):
+    _check(h, load().gba_prepare(h))
+
+
+def gba_solve(h, max_iters, tol=0.0):
+    rep = gba_report()
+    _check(h, load().gba_solve(h, int(max_iters), float(tol), ctypes.byref(rep)))
+    return rep
+
+
+def gba_reset(h):
+    _check(h, load().gba_reset(h))
+
+
+def gba_get_cost(h):
+    c = ctypes.c_double()
+    _check(h, load().gba_get_cost(h, ctypes.byref(c)))
+    return c.value
+
+
+def gba_get_cameras(h, n_cams):
+    out = np.empty((n_cams, 9))
+    _check(h, load().gba_get_cameras(h, _ptr(out)))
+    return out
+
+
+def gba_get_points(h, n_pts):
+    out = np.empty((n_pts, 3))
+    _check(h, load().gba_get_points(h, _ptr(out)))
+    return out
+
+
+def gba_get_trials(h, max_entries=100000):
+    buf = (gba_trial * max_entries)()
+    n = ctypes.c_int()
+    _check(h, load().gba_get_trials(h, max_entries, buf, ctypes.byref(n)))
+    return [dict(cost=t.cost, candidate_cost=t.candidate_cost, lam=t.lambda_,
+                 model_decrease=t.model_decrease, step_norm=t.step_norm,
+                 accepted=bool(t.accepted), pcg_iters=t.pcg_iters)
+            for t in buf[:min(n.value, max_entries)]]
+
+
+def gba_eval_edges(h, n_edges):
+    r = np.empty((n_edges, 2))
+    jc = np.empty((n_edges, 2, 9))
+    jp = np.empty((n_edges, 2, 3))
+    w = np.empty(n_edges)
+    _check(h, load().gba_eval_edges(h, _ptr(r), _ptr(jc), _ptr(jp), _ptr(w)))
+    return r, jc, jp, w
+
+
+def gba_eval_normal_equations(h, n_cams, n_pts):
+    hcc = np.empty((n_cams, 9, 9))
+    bc = np.empty((n_cams, 9))
+    hpp = np.empty((n_pts, 3, 3))
+    bp = np.empty((n_pts, 3))
+    _check(h, load().gba_eval_normal_equations(h, _ptr(hcc), _ptr(bc), _ptr(hpp), _ptr(bp)))
+    return hcc, bc, hpp, bp
+
+
+def gba_eval_step(h, lam, n_cams, n_pts):
+    dc = np.empty((n_cams, 9))
+    dp = np.empty((n_pts, 3))
+    it = ctypes.c_int()
+    _check(h, load().gba_eval_step(h, float(lam), _ptr(dc), _ptr(dp), ctypes.byref(it)))
+    return dc, dp, it.value
+
+
+def gba_last_error(h):
+    m = load().gba_last_error(h)
+    return m.decode() if m else ""
+
+
+def gba_destroy(h):
+    if h:
+        load().gba_destroy(h)
+
+
+# ------------------------------------------------------ convenience wrapper
+class Graph:
+    """Owns one gba_graph handle; builds it from arrays (marshalling only)."""
+
+    def __init__(self, precision=GBA_FP64, device=0, use_torch=False):
+        self.allocator = torch_allocator(device) if use_torch else None
+        self.h = gba_create(precision, device, self.allocator)
+        if use_torch:
+            gba_set_stream(self.h, torch_stream(device))
+        self.n_cams = self.n_pts = self.n_edges = 0
+
+    @classmethod
+    def from_arrays(cls, cams, pts, cam_idx, pt_idx, obs, info=None, loss=GBA_LOSS_SQUARED,
+                    delta=1.0, precision=GBA_FP64, options=None, cam_fixed=None,
+                    pt_fixed=None, edge_active=None, device=0, use_torch=False):
+        g = cls(precision, device, use_torch)
+        cams = np.asarray(cams, np.float64)
+        pts = np.asarray(pts, np.float64)
+        gba_reserve(g.h, len(cams), len(pts), len(cam_idx))
+        gba_add_cameras(g.h, np.arange(len(cams)), cams)
+        gba_add_points(g.h, np.arange(len(pts)), pts)
+        gba_add_edges(g.h, cam_idx, pt_idx, obs, info)
+        g.n_cams, g.n_pts, g.n_edges = len(cams), len(pts), len(cam_idx)
+        gba_set_robust_kernel(g.h, loss, delta)
+        if options is not None:
+            gba_set_options(g.h, options)
+        if cam_fixed is not None:
+            for i in np.flatnonzero(cam_fixed):
+                gba_set_fixed(g.h, 0, int(i), True)
+        if pt_fixed is not None:
+            for j in np.flatnonzero(pt_fixed):
+                gba_set_fixed(g.h, 1, int(j), True)
+        if edge_active is not None:
+            for e in np.flatnonzero(~np.asarray(edge_active, bool)):
+                gba_set_edge_active(g.h, int(e), False)
+        return g
+
+    def solve(self, max_iters, tol=0.0):
+        return gba_solve(self.h, max_iters, tol)
+
+    def cameras(self):
+        return gba_get_cameras(self.h, self.n_cams)
+
+    def points(self):
+        return gba_get_points(self.h, self.n_pts)
+
+    def cost(self):
+        return gba_get_cost(self.h)
+
+    def trials(self):
+        return gba_get_trials(self.h)
+
+    def close(self):
+        if self.h:
+            gba_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def options(**kw):
+    o = gba_default_options()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
