@@ -42,8 +42,12 @@ def transform_scene(cams, pts, s, Q, tau):
 
 
 def aligned_errors(cams, pts, ref_cams, ref_pts):
-    """Align (cams, pts) onto (ref_cams, ref_pts); return relative parameter
-    error over the stacked (w, t, f, k1, k2, X) vector plus per-block figures."""
+    """Align (cams, pts) onto (ref_cams, ref_pts); return the relative
+    parameter error over the stacked (rotation, t, f, k1, k2, X) vector plus
+    per-block figures.  An angle-axis vector is not unique (theta about n and
+    2 pi - theta about -n give the same rotation), so the rotation part of the
+    difference is the angle of R R_ref^{-1} rather than a difference of
+    angle-axis vectors."""
     s, Q, tau = umeyama(pts, ref_pts)
     c2, p2 = transform_scene(cams, pts, s, Q, tau)
     ref_cams = np.asarray(ref_cams, np.float64)
@@ -51,13 +55,10 @@ def aligned_errors(cams, pts, ref_cams, ref_pts):
     Ra = Rotation.from_rotvec(c2[:, 0:3])
     Rb = Rotation.from_rotvec(ref_cams[:, 0:3])
     rot_err = (Ra * Rb.inv()).magnitude()
-    # compare angle-axis through the aligned rotation (branch-safe)
-    w_a = (Ra * Rb.inv() * Rb).as_rotvec()
-    va = np.concatenate([w_a.ravel(), c2[:, 3:].ravel(), p2.ravel()])
-    vb = np.concatenate([ref_cams[:, 0:3].ravel(), ref_cams[:, 3:].ravel(),
-                         ref_pts.ravel()])
-    rel = float(np.linalg.norm(va - vb) / np.linalg.norm(vb))
-    return dict(rel=rel, scale=s, max_rot=float(rot_err.max()),
+    num = np.sqrt(np.sum(rot_err ** 2) + np.sum((c2[:, 3:] - ref_cams[:, 3:]) ** 2) +
+                  np.sum((p2 - ref_pts) ** 2))
+    den = np.sqrt(np.sum(ref_cams ** 2) + np.sum(ref_pts ** 2))
+    return dict(rel=float(num / den), scale=s, max_rot=float(rot_err.max()),
                 pts_rel=float(np.linalg.norm(p2 - ref_pts) / np.linalg.norm(ref_pts)),
                 cams_rel=float(np.linalg.norm(c2[:, 3:] - ref_cams[:, 3:]) /
                                np.linalg.norm(ref_cams[:, 3:])))

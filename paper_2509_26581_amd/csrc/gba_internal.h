@@ -96,6 +96,7 @@ struct DeviceGraph {
     void* hpp;                // [6][np]
     void* bp;                 // [3][np]
     void* hcc;                // [45][nc] stored as [nc][45]
+    void* wrun;               // [27][n_runs] W = sum_run J_c^T J_p per camera-major run
     void* bc;                 // [nc][9]
     double* hpp_inv;          // [6][np] damped inverse (FP64)
     void* minv;               // [nc][45] preconditioner inverse blocks

@@ -201,13 +201,14 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double lambd
 }
 
 // ==========================================================================
-// Camera-major accumulation over runs of equal (camera, point), recomputing
-// the edge Jacobians from the parameters (no gathers of stored Jacobians):
-//   kAssemble: Hcc_i = sum J_c^T J_c (45 unique), bc_i = sum J_c^T r (9)
-//   kPrecond:  sum over runs of W Hpp_lambda^{-1} W^T with W = sum_run J_c^T J_p
-//              (the point-elimination term of the 9x9 diagonal block of the
-//              Schur complement)
-// One workgroup per chunk of one camera's runs; partials per chunk.
+// Camera-major accumulation over runs of equal (camera, point), one
+// workgroup per chunk of one camera's runs; partial sums per chunk.
+//   kAssemble: recompute the run's edge Jacobians from the parameters (no
+//              gathers of stored Jacobians) and sum Hcc_i = sum J_c^T J_c
+//              (45 unique), bc_i = sum J_c^T r (9); store the run's coupling
+//              block W = sum_run J_c^T J_p (9x3) for the preconditioner.
+//   kPrecond:  sum over runs of W Hpp_lambda^{-1} W^T: the point-elimination
+//              term of the 9x9 diagonal block of the Schur complement.
 // ==========================================================================
 enum { kAssemble = 0, kPrecond = 1 };
 
@@ -223,21 +224,24 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0;
     const int ne = g.ne;
+    const int nr = g.n_runs;
+    T* __restrict__ wrun = (T*)g.wrun;
     for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
-        const int q0 = g.cm_run_off[run], q1 = g.cm_run_off[run + 1];
+        const int q0 = g.cm_run_off[run];
         const int j = g.cm_pt[q0];
-        const bool pfix = g.pt_fixed[j] != 0;
         T W[9][3];
+        if (kMode == kAssemble) {
+            const int q1 = g.cm_run_off[run + 1];
+            const bool pfix = g.pt_fixed[j] != 0;
 #pragma unroll
-        for (int a = 0; a < 9; ++a)
+            for (int a = 0; a < 9; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) W[a][b] = 0;
-        for (int q = q0; q < q1; ++q) {
-            EdgeEval<T> ev;
-            bal_eval<T, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
-            T s, rho, w;
-            whiten<T, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
-            if (kMode == kAssemble) {
+                for (int b = 0; b < 3; ++b) W[a][b] = 0;
+            for (int q = q0; q < q1; ++q) {
+                EdgeEval<T> ev;
+                bal_eval<T, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
+                T s, rho, w;
+                whiten<T, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
@@ -245,17 +249,22 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     for (int b = a; b < 9; ++b, ++k)
                         acc[k] += ev.jc[0][a] * ev.jc[0][b] + ev.jc[1][a] * ev.jc[1][b];
 #pragma unroll
-                for (int a = 0; a < 9; ++a)
+                for (int a = 0; a < 9; ++a) {
                     acc[45 + a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
-            } else {
-#pragma unroll
-                for (int a = 0; a < 9; ++a)
 #pragma unroll
                     for (int b = 0; b < 3; ++b)
                         W[a][b] += ev.jc[0][a] * ev.jp[0][b] + ev.jc[1][a] * ev.jp[1][b];
+                }
             }
-        }
-        if (kMode == kPrecond) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) wrun[(3 * a + b) * nr + run] = W[a][b];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) W[a][b] = wrun[(3 * a + b) * nr + run];
             T Hi[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
@@ -291,52 +300,58 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     }
 }
 
-// Per camera: sum the chunk partials.  kAssemble stores Hcc and bc.
-// kPrecond forms M_i = Hcc_lambda,i - sum W Hpp^-1 W^T and stores M_i^{-1}
-// (FP64 Cholesky); identity preconditioner stores I.  Fixed cameras: 0.
+// One workgroup per camera: sum the chunk partials of the camera.
+// kAssemble stores Hcc and bc.  kPrecond forms M_i = Hcc_lambda,i -
+// sum W Hpp^-1 W^T and stores M_i^{-1} (FP64 Cholesky); the identity
+// preconditioner stores I; fixed cameras store 0.
 template <typename T, int kMode>
 __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double lambda, double min_diag,
                                                      double max_diag, int block_jacobi) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.nc) return;
+    __shared__ double Ms[54];
+    const int i = blockIdx.x;
+    const int k = threadIdx.x;
     const int c0 = g.cam_chunk_off[i], c1 = g.cam_chunk_off[i + 1];
     T* Hcc = (T*)g.hcc;
     if (kMode == kAssemble) {
-        T* bc = (T*)g.bc;
-        for (int k = 0; k < 54; ++k) {
+        if (k < 54) {
             double s = 0.0;
             for (int c = c0; c < c1; ++c) s += g.chunk_partial[c * 54 + k];
             if (k < 45)
                 Hcc[i * 45 + k] = (T)s;
             else
-                bc[i * 9 + (k - 45)] = (T)s;
+                ((T*)g.bc)[i * 9 + (k - 45)] = (T)s;
         }
         return;
     }
     T* Minv = (T*)g.minv;
     const bool fixed = g.cam_fixed[i] != 0;
-    if (fixed) {
-        for (int k = 0; k < 45; ++k) Minv[i * 45 + k] = 0;
+    if (fixed || !block_jacobi) {
+        if (k < 45) {
+            int r = 0;
+            while (k >= sym9(r, 8) + 1) ++r;
+            const int c = k - sym9(r, r) + r;
+            Minv[i * 45 + k] = (T)((!fixed && r == c) ? 1.0 : 0.0);
+        }
         return;
     }
+    if (k < 45) {
+        int r = 0;
+        while (k >= sym9(r, 8) + 1) ++r;
+        const int c = k - sym9(r, r) + r;
+        double h = (double)Hcc[i * 45 + k];
+        if (r == c) h += lambda * fmin(fmax(h, min_diag), max_diag);
+        double s = 0.0;
+        for (int q = c0; q < c1; ++q) s += g.chunk_partial[q * 54 + k];
+        Ms[k] = h - s;
+    }
+    __syncthreads();
+    if (k != 0) return;
     double M[9][9];
     for (int r = 0; r < 9; ++r)
         for (int c = r; c < 9; ++c) {
-            double h = (double)Hcc[i * 45 + sym9(r, c)];
-            if (r == c) h += lambda * fmin(fmax(h, min_diag), max_diag);
-            if (block_jacobi) {
-                double s = 0.0;
-                for (int q = c0; q < c1; ++q) s += g.chunk_partial[q * 54 + sym9(r, c)];
-                h -= s;
-            }
-            M[r][c] = h;
-            M[c][r] = h;
+            M[r][c] = Ms[sym9(r, c)];
+            M[c][r] = M[r][c];
         }
-    if (!block_jacobi) {
-        for (int r = 0; r < 9; ++r)
-            for (int c = r; c < 9; ++c) Minv[i * 45 + sym9(r, c)] = (T)(r == c ? 1.0 : 0.0);
-        return;
-    }
     if (!spd_inverse<9>(M)) {
         // rounding left the block indefinite: fall back to the damped diagonal
         for (int r = 0; r < 9; ++r)
@@ -369,6 +384,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
     extern __shared__ __align__(16) unsigned char smem_raw[];
     AT* acc_lds = (AT*)smem_raw;
     __shared__ double red[16];
+    if (kMode == kMatvec && g.pcg->done) return;   // PCG already converged
     const int l = lane_id();
     const int nc9 = 9 * g.nc;
     if (kMode != kBacksub) {
@@ -599,6 +615,7 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __rest
                                                  double lambda, double min_diag, double max_diag) {
     __shared__ double red[16][64];
     __shared__ double dred[16];
+    if (kMode == kMatvec && g.pcg->done) return;   // PCG already converged
     const int cl = threadIdx.x & 63;
     const int grp = threadIdx.x >> 6;
     const int nc9 = 9 * g.nc;
@@ -640,39 +657,56 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __rest
 
 // ==========================================================================
 // PCG on the reduced camera system (single workgroup: the camera vectors are
-// small).  Dots in FP64.  State in PcgState.
+// small).  Dots in FP64.  State in PcgState.  Each thread owns whole cameras
+// and keeps their 9-vectors in registers between the load and the store.
 // ==========================================================================
 template <typename T>
-__device__ __forceinline__ void apply_minv(const T* __restrict__ Minv, const T* __restrict__ r,
-                                           T* __restrict__ z, int i) {
+__device__ __forceinline__ void load9(const T* __restrict__ v, int i, T (&o)[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o[a] = v[9 * i + a];
+}
+template <typename T>
+__device__ __forceinline__ void store9(T* __restrict__ v, int i, const T (&o)[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) v[9 * i + a] = o[a];
+}
+template <typename T>
+__device__ __forceinline__ void minv_apply(const T* __restrict__ Minv, int i, const T (&r)[9],
+                                           T (&z)[9]) {
+    T m[45];
+#pragma unroll
+    for (int k = 0; k < 45; ++k) m[k] = Minv[i * 45 + k];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         T s = 0;
 #pragma unroll
-        for (int b = 0; b < 9; ++b) s += Minv[i * 45 + sym9(a, b)] * r[9 * i + b];
-        z[9 * i + a] = s;
+        for (int b = 0; b < 9; ++b) s += m[sym9(a, b)] * r[b];
+        z[a] = s;
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_pcg_init(DeviceGraph g, double tol, int relative) {
     __shared__ double red[16];
-    T* x = (T*)g.v_x;
-    T* r = (T*)g.v_r;
-    T* z = (T*)g.v_z;
-    T* p = (T*)g.v_p;
-    const T* Minv = (const T*)g.minv;
+    T* __restrict__ x = (T*)g.v_x;
+    const T* __restrict__ r = (const T*)g.v_r;
+    T* __restrict__ z = (T*)g.v_z;
+    T* __restrict__ p = (T*)g.v_p;
+    const T* __restrict__ Minv = (const T*)g.minv;
     double rz = 0.0, rr = 0.0;
     for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
-        apply_minv(Minv, r, z, i);
+        T rv[9], zv[9], zero[9];
+        load9(r, i, rv);
+        minv_apply(Minv, i, rv, zv);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const int k = 9 * i + a;
-            x[k] = 0;
-            p[k] = z[k];
-            rz += (double)r[k] * (double)z[k];
-            rr += (double)r[k] * (double)r[k];
+            zero[a] = 0;
+            rz += (double)rv[a] * (double)zv[a];
+            rr += (double)rv[a] * (double)rv[a];
         }
+        store9(x, i, zero);
+        store9(z, i, zv);
+        store9(p, i, zv);
     }
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
@@ -701,28 +735,34 @@ __global__ __launch_bounds__(1024) void k_pcg_update(DeviceGraph g, int max_iter
     const double rz_old = st->rz;
     const bool breakdown = !(pq > 0.0) || !isfinite(pq);
     const double alpha = breakdown ? 0.0 : rz_old / pq;
-    T* x = (T*)g.v_x;
-    T* r = (T*)g.v_r;
-    T* z = (T*)g.v_z;
-    T* p = (T*)g.v_p;
-    const T* q = (const T*)g.v_q;
-    const T* Minv = (const T*)g.minv;
+    T* __restrict__ x = (T*)g.v_x;
+    T* __restrict__ r = (T*)g.v_r;
+    T* __restrict__ z = (T*)g.v_z;
+    T* __restrict__ p = (T*)g.v_p;
+    const T* __restrict__ q = (const T*)g.v_q;
+    const T* __restrict__ Minv = (const T*)g.minv;
     double rz = 0.0, rr = 0.0;
     if (!breakdown) {
         for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
+            T xv[9], rv[9], pv[9], qv[9], zv[9];
+            load9(x, i, xv);
+            load9(r, i, rv);
+            load9(p, i, pv);
+            load9(q, i, qv);
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                const int k = 9 * i + a;
-                x[k] = (T)((double)x[k] + alpha * (double)p[k]);
-                r[k] = (T)((double)r[k] - alpha * (double)q[k]);
+                xv[a] = (T)((double)xv[a] + alpha * (double)pv[a]);
+                rv[a] = (T)((double)rv[a] - alpha * (double)qv[a]);
             }
-            apply_minv(Minv, r, z, i);
+            minv_apply(Minv, i, rv, zv);
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
-                const int k = 9 * i + a;
-                rz += (double)r[k] * (double)z[k];
-                rr += (double)r[k] * (double)r[k];
+                rz += (double)rv[a] * (double)zv[a];
+                rr += (double)rv[a] * (double)rv[a];
             }
+            store9(x, i, xv);
+            store9(r, i, rv);
+            store9(z, i, zv);
         }
     }
     rz = block_sum(rz, red);
@@ -751,11 +791,28 @@ __global__ __launch_bounds__(1024) void k_pcg_update(DeviceGraph g, int max_iter
     const int done = s_done;
     const int copy_best = s_copy_best;
     const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
-    T* best = (T*)g.v_best;
-    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
-        if (done == 0) p[k] = (T)((double)z[k] + beta * (double)p[k]);
-        if (copy_best) best[k] = x[k];
-        if (done == 4) x[k] = best[k];
+    T* __restrict__ best = (T*)g.v_best;
+    if (done == 0 || copy_best || done == 4) {
+        for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
+            if (done == 0) {
+                T zv[9], pv[9];
+                load9(z, i, zv);
+                load9(p, i, pv);
+#pragma unroll
+                for (int a = 0; a < 9; ++a) pv[a] = (T)((double)zv[a] + beta * (double)pv[a]);
+                store9(p, i, pv);
+            }
+            if (copy_best) {
+                T xv[9];
+                load9(x, i, xv);
+                store9(best, i, xv);
+            }
+            if (done == 4) {
+                T bv[9];
+                load9(best, i, bv);
+                store9(x, i, bv);
+            }
+        }
     }
     if (threadIdx.x == 0) {
         if (copy_best) st->use_best = 1;
@@ -881,7 +938,7 @@ hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
             hipLaunchKernelGGL((k_cam_accumulate<float, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
-    const int grid = (g.nc + 63) / 64;
+    const int grid = g.nc;
     if (g.mode == kModeFP64)
         hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(grid), dim3(64), 0, s, g, 0.0, 0.0, 0.0, 0);
     else
@@ -915,7 +972,7 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, do
             hipLaunchKernelGGL((k_cam_accumulate<float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
-    const int grid = (g.nc + 63) / 64;
+    const int grid = g.nc;
     if (g.mode == kModeFP64)
         hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(grid), dim3(64), 0, s, g, lambda, min_diag, max_diag, block_jacobi);
     else

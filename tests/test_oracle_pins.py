@@ -479,3 +479,20 @@ def test_generator_is_deterministic_and_has_stated_statistics():
     sm = synth.make_scene("small", seed=0)
     c = np.bincount(sm.pt_idx)
     assert c.min() >= 3 and c.max() <= 8
+
+
+def test_aligned_errors_are_gauge_and_branch_invariant():
+    sc = synth.make_scene("small", seed=16, n_pts=50)
+    Q = Rotation.from_rotvec([0.2, 0.4, -1.1]).as_matrix()
+    c2, p2 = align.transform_scene(sc.cams_true, sc.pts_true, 0.7, Q, np.array([2.0, 0.0, -1.0]))
+    # same rotation, other angle-axis representative (2 pi - theta about -n)
+    w = c2[:, 0:3]
+    th = np.linalg.norm(w, axis=1, keepdims=True)
+    c2[::2, 0:3] = -(w / th * (2 * np.pi - th))[::2]
+    err = align.aligned_errors(c2, p2, sc.cams_true, sc.pts_true)
+    assert err["rel"] < 1e-12 and abs(err["scale"] - 1 / 0.7) < 1e-12
+    # a known perturbation of one point shows up at its size
+    p3 = sc.pts_true.copy()
+    p3[0] += 1e-3
+    e3 = align.aligned_errors(sc.cams_true, p3, sc.cams_true, sc.pts_true)
+    assert 1e-6 < e3["rel"] < 1e-4
