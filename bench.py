@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--trials", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before the run, one device-to-device copy of this many MiB "
+                         "(calibrates HBM byte counters; not timed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path in this "
@@ -82,6 +85,14 @@ def main():
         from __graft_entry__ import build
         build()
     torch.cuda.set_device(0)
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {args.copy_probe_mb} MiB device-to-device", flush=True)
+        del src, dst
     prec_id, dtype_name, jac_bytes = PRECISIONS[args.precision]
     t0 = time.perf_counter()
     sc = synth.make_scene(args.workload, seed=0)

@@ -311,6 +311,7 @@ gba_status build(gba_graph* g) {
     P.add(&d.v_best, tsz * 9 * NC);
     P.add(&d.cam_partial, tsz * 9 * NC * (size_t)d.grid_pp);
     P.add((void**)&d.pq_partial, sizeof(double) * d.grid_red);
+    P.add((void**)&d.dot_partial, sizeof(double) * 2 * ((nc + 27) / 28 + 1));
     P.add((void**)&d.chunk_partial, sizeof(double) * 54 * std::max(1, n_chunks));
     P.add((void**)&d.red_partial, sizeof(double) * 4 * d.grid_pp);
     P.add((void**)&d.cost_partial, sizeof(double) * d.grid_edges);

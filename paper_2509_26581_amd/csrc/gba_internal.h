@@ -112,6 +112,7 @@ struct DeviceGraph {
     // partial sums
     void* cam_partial;        // [grid_pp][9 nc]
     double* pq_partial;       // [grid_red]
+    double* dot_partial;      // [2][pcg workgroups] r^T z, r^T r
     double* chunk_partial;    // [n_chunks][54]
     double* red_partial;      // [grid_edges][4] misc per-block sums
     double* cost_partial;     // [grid_edges]

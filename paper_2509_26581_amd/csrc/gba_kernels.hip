@@ -621,8 +621,18 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __rest
     const int nc9 = 9 * g.nc;
     const int k = blockIdx.x * 64 + cl;
     double s = 0.0;
-    if (k < nc9)
-        for (int b = grp; b < g.grid_pp; b += 16) s += (double)part[(size_t)b * nc9 + k];
+    if (k < nc9) {
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = grp;
+        for (; b + 48 < g.grid_pp; b += 64) {
+            s += (double)part[(size_t)b * nc9 + k];
+            s1 += (double)part[(size_t)(b + 16) * nc9 + k];
+            s2 += (double)part[(size_t)(b + 32) * nc9 + k];
+            s3 += (double)part[(size_t)(b + 48) * nc9 + k];
+        }
+        for (; b < g.grid_pp; b += 16) s += (double)part[(size_t)b * nc9 + k];
+        s += (s1 + s2) + s3;
+    }
     red[grp][cl] = s;
     __syncthreads();
     double dot = 0.0;
@@ -656,60 +666,68 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __rest
 }
 
 // ==========================================================================
-// PCG on the reduced camera system (single workgroup: the camera vectors are
-// small).  Dots in FP64.  State in PcgState.  Each thread owns whole cameras
-// and keeps their 9-vectors in registers between the load and the store.
+// PCG on the reduced camera system, dots in FP64, scalar state in PcgState.
 // ==========================================================================
+// Camera-aligned PCG vector kernels: a workgroup owns kCamsPerBlock whole
+// cameras (9 consecutive components each), so every global access is
+// coalesced and the 9x9 preconditioner block is applied from LDS.
+constexpr int kCamsPerBlock = 28;                 // 252 components per workgroup
+constexpr int kPcgBlock = 256;
+
+// z = M^{-1} r for this workgroup's cameras; r_lds holds r of those cameras.
 template <typename T>
-__device__ __forceinline__ void load9(const T* __restrict__ v, int i, T (&o)[9]) {
+__device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds, int i, int a,
+                                      int base) {
+    T s = 0;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) o[a] = v[9 * i + a];
-}
-template <typename T>
-__device__ __forceinline__ void store9(T* __restrict__ v, int i, const T (&o)[9]) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) v[9 * i + a] = o[a];
-}
-template <typename T>
-__device__ __forceinline__ void minv_apply(const T* __restrict__ Minv, int i, const T (&r)[9],
-                                           T (&z)[9]) {
-    T m[45];
-#pragma unroll
-    for (int k = 0; k < 45; ++k) m[k] = Minv[i * 45 + k];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        T s = 0;
-#pragma unroll
-        for (int b = 0; b < 9; ++b) s += m[sym9(a, b)] * r[b];
-        z[a] = s;
-    }
+    for (int b = 0; b < 9; ++b) s += Minv[i * 45 + sym9(a, b)] * r_lds[base + b];
+    return s;
 }
 
+// PCG start: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_pcg_init(DeviceGraph g, double tol, int relative) {
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
+    __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
-    T* __restrict__ x = (T*)g.v_x;
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x * (9 * kCamsPerBlock) + tid;
+    const bool valid = tid < 9 * kCamsPerBlock && k < 9 * g.nc;
     const T* __restrict__ r = (const T*)g.v_r;
-    T* __restrict__ z = (T*)g.v_z;
-    T* __restrict__ p = (T*)g.v_p;
-    const T* __restrict__ Minv = (const T*)g.minv;
+    T rv = valid ? r[k] : (T)0;
+    r_lds[tid] = rv;
+    __syncthreads();
     double rz = 0.0, rr = 0.0;
-    for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
-        T rv[9], zv[9], zero[9];
-        load9(r, i, rv);
-        minv_apply(Minv, i, rv, zv);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            zero[a] = 0;
-            rz += (double)rv[a] * (double)zv[a];
-            rr += (double)rv[a] * (double)rv[a];
-        }
-        store9(x, i, zero);
-        store9(z, i, zv);
-        store9(p, i, zv);
+    if (valid) {
+        const int i = k / 9, a = k % 9;
+        const T zv = minv_row((const T*)g.minv, r_lds, i, a, tid - a);
+        ((T*)g.v_z)[k] = zv;
+        ((T*)g.v_x)[k] = 0;
+        rz = (double)rv * (double)zv;
+        rr = (double)rv * (double)rv;
     }
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
+    if (tid == 0) {
+        g.dot_partial[2 * blockIdx.x] = rz;
+        g.dot_partial[2 * blockIdx.x + 1] = rr;
+    }
+}
+
+// PCG start, scalars (single workgroup): rz0, rr0, threshold; p = z.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, int nblk, double tol,
+                                                           int relative) {
+    __shared__ double red[16];
+    double rz = 0.0, rr = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        rz += g.dot_partial[2 * b];
+        rr += g.dot_partial[2 * b + 1];
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    const T* __restrict__ z = (const T*)g.v_z;
+    T* __restrict__ p = (T*)g.v_p;
+    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) p[k] = z[k];
     if (threadIdx.x == 0) {
         PcgState* st = g.pcg;
         st->rz = rz;
@@ -723,53 +741,73 @@ __global__ __launch_bounds__(1024) void k_pcg_init(DeviceGraph g, double tol, in
     }
 }
 
+// PCG step, vectors: alpha = r^T z / p^T q; x += alpha p; r -= alpha q;
+// z = M^{-1} r; partial (r^T z, r^T r) per workgroup.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_pcg_update(DeviceGraph g, int max_iters, double ratio) {
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
+    __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
-    __shared__ int s_done, s_copy_best;
-    PcgState* st = g.pcg;
+    const PcgState* st = g.pcg;
     if (st->done) return;
     double pq = 0.0;
     for (int b = threadIdx.x; b < g.grid_red; b += blockDim.x) pq += g.pq_partial[b];
     pq = block_sum(pq, red);
-    const double rz_old = st->rz;
-    const bool breakdown = !(pq > 0.0) || !isfinite(pq);
-    const double alpha = breakdown ? 0.0 : rz_old / pq;
+    if (!(pq > 0.0) || !isfinite(pq)) return;   // breakdown: the finisher stops PCG
+    const double alpha = st->rz / pq;
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x * (9 * kCamsPerBlock) + tid;
+    const bool valid = tid < 9 * kCamsPerBlock && k < 9 * g.nc;
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ r = (T*)g.v_r;
-    T* __restrict__ z = (T*)g.v_z;
-    T* __restrict__ p = (T*)g.v_p;
-    const T* __restrict__ q = (const T*)g.v_q;
-    const T* __restrict__ Minv = (const T*)g.minv;
+    T rv = 0;
+    if (valid) {
+        const double pk = (double)((const T*)g.v_p)[k];
+        const double qk = (double)((const T*)g.v_q)[k];
+        x[k] = (T)((double)x[k] + alpha * pk);
+        rv = (T)((double)r[k] - alpha * qk);
+        r[k] = rv;
+    }
+    r_lds[tid] = rv;
+    __syncthreads();
     double rz = 0.0, rr = 0.0;
-    if (!breakdown) {
-        for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
-            T xv[9], rv[9], pv[9], qv[9], zv[9];
-            load9(x, i, xv);
-            load9(r, i, rv);
-            load9(p, i, pv);
-            load9(q, i, qv);
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                xv[a] = (T)((double)xv[a] + alpha * (double)pv[a]);
-                rv[a] = (T)((double)rv[a] - alpha * (double)qv[a]);
-            }
-            minv_apply(Minv, i, rv, zv);
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                rz += (double)rv[a] * (double)zv[a];
-                rr += (double)rv[a] * (double)rv[a];
-            }
-            store9(x, i, xv);
-            store9(r, i, rv);
-            store9(z, i, zv);
-        }
+    if (valid) {
+        const int i = k / 9, a = k % 9;
+        const T zv = minv_row((const T*)g.minv, r_lds, i, a, tid - a);
+        ((T*)g.v_z)[k] = zv;
+        rz = (double)rv * (double)zv;
+        rr = (double)rv * (double)rv;
     }
     rz = block_sum(rz, red);
     rr = block_sum(rr, red);
+    if (tid == 0) {
+        g.dot_partial[2 * blockIdx.x] = rz;
+        g.dot_partial[2 * blockIdx.x + 1] = rr;
+    }
+}
+
+// PCG step, scalars (single workgroup): convergence / iteration limit /
+// rejection ratio / breakdown, beta = r^T z / (r^T z)_old, p = z + beta p,
+// and the best-iterate copy when the rejection ratio is enabled.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int nblk, int max_iters,
+                                                     double ratio) {
+    __shared__ double red[16];
+    __shared__ int s_done, s_copy_best;
+    PcgState* st = g.pcg;
+    if (st->done) return;
+    double pq = 0.0, rz = 0.0, rr = 0.0;
+    for (int b = threadIdx.x; b < g.grid_red; b += blockDim.x) pq += g.pq_partial[b];
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        rz += g.dot_partial[2 * b];
+        rr += g.dot_partial[2 * b + 1];
+    }
+    pq = block_sum(pq, red);
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    const double rz_old = st->rz;
     if (threadIdx.x == 0) {
         int done = 0, copy_best = 0;
-        if (breakdown) {
+        if (!(pq > 0.0) || !isfinite(pq)) {
             done = 3;
         } else {
             st->iters += 1;
@@ -791,32 +829,18 @@ __global__ __launch_bounds__(1024) void k_pcg_update(DeviceGraph g, int max_iter
     const int done = s_done;
     const int copy_best = s_copy_best;
     const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
+    T* __restrict__ x = (T*)g.v_x;
+    T* __restrict__ p = (T*)g.v_p;
+    const T* __restrict__ z = (const T*)g.v_z;
     T* __restrict__ best = (T*)g.v_best;
-    if (done == 0 || copy_best || done == 4) {
-        for (int i = threadIdx.x; i < g.nc; i += blockDim.x) {
-            if (done == 0) {
-                T zv[9], pv[9];
-                load9(z, i, zv);
-                load9(p, i, pv);
-#pragma unroll
-                for (int a = 0; a < 9; ++a) pv[a] = (T)((double)zv[a] + beta * (double)pv[a]);
-                store9(p, i, pv);
-            }
-            if (copy_best) {
-                T xv[9];
-                load9(x, i, xv);
-                store9(best, i, xv);
-            }
-            if (done == 4) {
-                T bv[9];
-                load9(best, i, bv);
-                store9(x, i, bv);
-            }
-        }
+    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
+        if (done == 0) p[k] = (T)((double)z[k] + beta * (double)p[k]);
+        if (copy_best) best[k] = x[k];
+        if (done == 4) x[k] = best[k];
     }
     if (threadIdx.x == 0) {
         if (copy_best) st->use_best = 1;
-        st->rz = rz;
+        if (done != 3) st->rz = rz;
         st->done = done;
     }
 }
@@ -1011,11 +1035,17 @@ hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
     return hipSuccess;
 }
 
+static int pcg_blocks(const DeviceGraph& g) { return (g.nc + kCamsPerBlock - 1) / kCamsPerBlock; }
+
 hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int relative) {
-    if (g.mode == kModeFP64)
-        hipLaunchKernelGGL(k_pcg_init<double>, dim3(1), dim3(1024), 0, s, g, tol, relative);
-    else
-        hipLaunchKernelGGL(k_pcg_init<float>, dim3(1), dim3(1024), 0, s, g, tol, relative);
+    const int nb = pcg_blocks(g);
+    if (g.mode == kModeFP64) {
+        hipLaunchKernelGGL(k_pcg_start<double>, dim3(nb), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_start_finish<double>, dim3(1), dim3(1024), 0, s, g, nb, tol, relative);
+    } else {
+        hipLaunchKernelGGL(k_pcg_start<float>, dim3(nb), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_start_finish<float>, dim3(1), dim3(1024), 0, s, g, nb, tol, relative);
+    }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1036,11 +1066,13 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, d
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, double, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
                            (const double*)g.cam_partial, lambda, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_update<double>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        hipLaunchKernelGGL(k_pcg_apply<double>, dim3(pcg_blocks(g)), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_finish<double>, dim3(1), dim3(1024), 0, s, g, pcg_blocks(g), max_iters, ratio);
     } else {
         hipLaunchKernelGGL((k_reduce<float, float, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
                            (const float*)g.cam_partial, lambda, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_update<float>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        hipLaunchKernelGGL(k_pcg_apply<float>, dim3(pcg_blocks(g)), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_finish<float>, dim3(1), dim3(1024), 0, s, g, pcg_blocks(g), max_iters, ratio);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;

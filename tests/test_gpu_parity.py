@@ -317,3 +317,47 @@ def test_bal1m_fp64_final_cost_and_solution():
     pts = g.points()[gold["point_sample"]]
     err = align.aligned_errors(cams, pts, np.array(gold["cams"]), np.array(gold["points"]))
     assert err["rel"] <= 1e-6, err
+
+
+# ------------------------------------------------------ mixed precision --
+MIXED = [gba.GBA_MIXED_FP32, gba.GBA_MIXED_BF16]
+
+
+@pytest.mark.parametrize("precision", MIXED)
+def test_mixed_normal_equation_blocks(precision):
+    sc = synth.make_scene("small", seed=31, n_cams=9, n_pts=500, noise_px=2.0)
+    g = _graph(sc, precision=precision, loss=robust.HUBER, delta=1.0)
+    hcc, bc, hpp, bp = gba.gba_eval_normal_equations(g.h, 9, 500)
+    lin = _oracle(sc, loss=robust.HUBER, delta=1.0).linearize((sc.cams0, sc.pts0))
+    # FP32 Jacobians and FP32 accumulation (BF16 only affects the PCG copy)
+    _close(hcc, lin.Hcc, 2e-5, "Hcc")
+    _close(bc, lin.bc, 2e-4, "bc")
+    _close(hpp, lin.Hpp, 2e-5, "Hpp")
+    _close(bp, lin.bp, 2e-4, "bp")
+
+
+@pytest.mark.parametrize("precision", MIXED)
+def test_mixed_small_workload_final_cost(precision):
+    sc = synth.make_scene("small", seed=0)
+    g = _graph(sc, precision=precision, pcg_max_iters=sc.pcg_max_iters, pcg_tol=1e-8)
+    rep = g.solve(sc.trials)
+    res = ba.solve(_oracle(sc), sc.cams0, sc.pts0, sc.trials)
+    assert abs(rep.final_cost - res.cost) <= 1e-4 * res.cost, (rep.final_cost, res.cost)
+    err = align.aligned_errors(g.cameras(), g.points(), res.x[0], res.x[1])
+    assert err["rel"] <= 1e-3, err
+    acc = [t["candidate_cost"] for t in g.trials() if t["accepted"]]
+    assert all(b < a for a, b in zip(acc, acc[1:]))          # FP64 acceptance
+
+
+@pytest.mark.parametrize("precision", MIXED)
+def test_bal1m_mixed_final_cost_and_solution(precision):
+    gold = _bal1m_golden()
+    sc = synth.make_scene("bal1m", seed=0)
+    g = _graph(sc, precision=precision, pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol)
+    rep = g.solve(gold["trials"])
+    assert abs(rep.initial_cost - gold["initial_cost"]) <= 1e-12 * gold["initial_cost"]
+    rel = abs(rep.final_cost - gold["final_cost"]) / gold["final_cost"]
+    assert rel <= 1e-4, (rep.final_cost, gold["final_cost"], rel)
+    pts = g.points()[gold["point_sample"]]
+    err = align.aligned_errors(g.cameras(), pts, np.array(gold["cams"]), np.array(gold["points"]))
+    assert err["rel"] <= 1e-3, err
