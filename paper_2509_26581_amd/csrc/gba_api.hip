@@ -257,7 +257,9 @@ gba_status build(gba_graph* g) {
     const int waves_pp = d.block_pp / 64;
     int gpp = (n_tiles + waves_pp - 1) / waves_pp;
     d.grid_pp = std::max(1, std::min(g->n_cu, gpp));
-    d.lds_pp = (int)(9 * (size_t)nc * tsz);
+    // camera partial sums are FP64 in every mode: the Schur product subtracts
+    // the point-elimination term from Hcc p, so summation noise is amplified
+    d.lds_pp = (int)(9 * (size_t)nc * sizeof(double));
     if ((size_t)d.lds_pp + 1024 > g->max_lds)
         return fail(g, GBA_ERR_UNSUPPORTED,
                     "camera vector does not fit in LDS (" + std::to_string(nc) + " cameras)");
@@ -309,7 +311,7 @@ gba_status build(gba_graph* g) {
     P.add(&d.v_p, tsz * 9 * NC);
     P.add(&d.v_q, tsz * 9 * NC);
     P.add(&d.v_best, tsz * 9 * NC);
-    P.add(&d.cam_partial, tsz * 9 * NC * (size_t)d.grid_pp);
+    P.add(&d.cam_partial, sizeof(double) * 9 * NC * (size_t)d.grid_pp);
     P.add((void**)&d.pq_partial, sizeof(double) * d.grid_red);
     P.add((void**)&d.dot_partial, sizeof(double) * 2 * ((nc + 27) / 28 + 1));
     P.add((void**)&d.chunk_partial, sizeof(double) * 54 * std::max(1, n_chunks));

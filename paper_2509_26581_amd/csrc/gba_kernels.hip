@@ -20,7 +20,8 @@ namespace gba {
 // whitening (Eq. 7 kernel on s = r^T Omega r, IRLS weight), storage of the
 // weighted blocks, and point-side sums Hpp_j = sum J_p^T J_p, bp_j =
 // sum J_p^T r (Eq. 5) by segmented wavefront reductions over the point's
-// contiguous edges.  One wavefront per tile of whole points.
+// contiguous edges.  One wavefront per tile of whole points.  Arithmetic is
+// FP64 in every precision mode; T / JS are only the storage types.
 // ==========================================================================
 template <typename T, typename JS>
 __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
@@ -38,9 +39,9 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
     for (int t = wave; t < g.n_tiles; t += nwaves) {
         const int e0 = g.tile_off[t], e1 = g.tile_off[t + 1];
         const int n = e1 - e0;
-        T acc[9];
+        double acc[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] = 0;
+        for (int k = 0; k < 9; ++k) acc[k] = 0.0;
         int j_first = g.e_pt[e0];
         uint64_t starts = 0;
         int head = 0, end = 63;
@@ -50,36 +51,36 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
             const int e = e0 + (valid ? idx : 0);
             const int j = g.e_pt[e];
             const int i = g.e_cam[e];
-            EdgeEval<T> ev;
-            bal_eval<T, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
-            T s, rho, w;
-            whiten<T, true>(ev, g.sinfo, ne, e, g.loss, g.delta, g.cam_fixed[i] != 0,
+            EdgeEval<double> ev;
+            bal_eval<double, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
+            double s, rho, w;
+            whiten<double, true>(ev, g.sinfo, ne, e, g.loss, g.delta, g.cam_fixed[i] != 0,
                             g.pt_fixed[j] != 0, s, rho, w);
             if (valid) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    Jc[k * ne + e] = ev.jc[0][k];
-                    Jc[(9 + k) * ne + e] = ev.jc[1][k];
+                    Jc[k * ne + e] = (T)ev.jc[0][k];
+                    Jc[(9 + k) * ne + e] = (T)ev.jc[1][k];
                 }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    Jp[k * ne + e] = ev.jp[0][k];
-                    Jp[(3 + k) * ne + e] = ev.jp[1][k];
+                    Jp[k * ne + e] = (T)ev.jp[0][k];
+                    Jp[(3 + k) * ne + e] = (T)ev.jp[1][k];
                 }
                 if (Jc16) {
 #pragma unroll
                     for (int k = 0; k < 9; ++k) {
-                        Jc16[k * ne + e] = store_as<JS>(ev.jc[0][k]);
-                        Jc16[(9 + k) * ne + e] = store_as<JS>(ev.jc[1][k]);
+                        Jc16[k * ne + e] = store_as<JS>((T)ev.jc[0][k]);
+                        Jc16[(9 + k) * ne + e] = store_as<JS>((T)ev.jc[1][k]);
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        Jp16[k * ne + e] = store_as<JS>(ev.jp[0][k]);
-                        Jp16[(3 + k) * ne + e] = store_as<JS>(ev.jp[1][k]);
+                        Jp16[k * ne + e] = store_as<JS>((T)ev.jp[0][k]);
+                        Jp16[(3 + k) * ne + e] = store_as<JS>((T)ev.jp[1][k]);
                     }
                 }
-                rw[e] = ev.r[0];
-                rw[ne + e] = ev.r[1];
+                rw[e] = (T)ev.r[0];
+                rw[ne + e] = (T)ev.r[1];
                 if (raw.r) {
                     // unweighted values for verification
                     EdgeEval<double> ed;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
                 }
             }
             // point-side contributions of this edge
-            T h[9];
+            double h[9];
             h[0] = ev.jp[0][0] * ev.jp[0][0] + ev.jp[1][0] * ev.jp[1][0];
             h[1] = ev.jp[0][0] * ev.jp[0][1] + ev.jp[1][0] * ev.jp[1][1];
             h[2] = ev.jp[0][0] * ev.jp[0][2] + ev.jp[1][0] * ev.jp[1][2];
@@ -114,16 +115,16 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
                 starts = __ballot(st);
                 segment_of(starts, l, head, end);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) acc[k] = segment_sum(valid ? h[k] : (T)0, l, end);
+                for (int k = 0; k < 9; ++k) acc[k] = segment_sum(valid ? h[k] : 0.0, l, end);
                 if (valid && head == l) {
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) Hpp[k * g.np + j] = acc[k];
+                    for (int k = 0; k < 6; ++k) Hpp[k * g.np + j] = (T)acc[k];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) bp[k * g.np + j] = acc[6 + k];
+                    for (int k = 0; k < 3; ++k) bp[k * g.np + j] = (T)acc[6 + k];
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) acc[k] += valid ? h[k] : (T)0;
+                for (int k = 0; k < 9; ++k) acc[k] += valid ? h[k] : 0.0;
             }
         }
         if (n > kWave) {
@@ -132,9 +133,9 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
             for (int k = 0; k < 9; ++k) acc[k] = wave_sum(acc[k]);
             if (l == 0) {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) Hpp[k * g.np + j_first] = acc[k];
+                for (int k = 0; k < 6; ++k) Hpp[k * g.np + j_first] = (T)acc[k];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) bp[k * g.np + j_first] = acc[6 + k];
+                for (int k = 0; k < 3; ++k) bp[k * g.np + j_first] = (T)acc[6 + k];
             }
         }
     }
@@ -220,16 +221,16 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     const int cam = g.chunk_cam[chunk];
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
     const bool cfix = g.cam_fixed[cam] != 0;
-    T acc[K];
+    double acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0;
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
     const int ne = g.ne;
     const int nr = g.n_runs;
     T* __restrict__ wrun = (T*)g.wrun;
     for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
         const int q0 = g.cm_run_off[run];
         const int j = g.cm_pt[q0];
-        T W[9][3];
+        double W[9][3];
         if (kMode == kAssemble) {
             const int q1 = g.cm_run_off[run + 1];
             const bool pfix = g.pt_fixed[j] != 0;
@@ -238,10 +239,10 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
                 for (int b = 0; b < 3; ++b) W[a][b] = 0;
             for (int q = q0; q < q1; ++q) {
-                EdgeEval<T> ev;
-                bal_eval<T, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
-                T s, rho, w;
-                whiten<T, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
+                EdgeEval<double> ev;
+                bal_eval<double, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
+                double s, rho, w;
+                whiten<double, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
@@ -259,18 +260,18 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
             for (int a = 0; a < 9; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) wrun[(3 * a + b) * nr + run] = W[a][b];
+                for (int b = 0; b < 3; ++b) wrun[(3 * a + b) * nr + run] = (T)W[a][b];
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) W[a][b] = wrun[(3 * a + b) * nr + run];
-            T Hi[3][3];
+                for (int b = 0; b < 3; ++b) W[a][b] = (double)wrun[(3 * a + b) * nr + run];
+            double Hi[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Hi[r][c] = (T)g.hpp_inv[sym3(r, c) * g.np + j];
-            T WH[9][3];
+                for (int c = 0; c < 3; ++c) Hi[r][c] = g.hpp_inv[sym3(r, c) * g.np + j];
+            double WH[9][3];
 #pragma unroll
             for (int a = 0; a < 9; ++a)
 #pragma unroll
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double v = wave_sum((double)acc[k]);
+        const double v = wave_sum(acc[k]);
         if (lane_id() == 0) red[w][k] = v;
     }
     __syncthreads();
@@ -377,10 +378,15 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double lambd
 // ==========================================================================
 enum { kRhs = 0, kMatvec = 1, kBacksub = 2 };
 
-template <typename T, typename JS, typename AT, int kMode>
+template <typename VT, typename JS, typename AT, int kMode>
 __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __restrict__ Jc,
                                                      const JS* __restrict__ Jp,
-                                                     const T* __restrict__ vin, AT* __restrict__ out) {
+                                                     const VT* __restrict__ vin, AT* __restrict__ out) {
+    // Arithmetic in FP64 whatever the storage type: the product chain
+    // J_c p -> J_p^T -> Hpp^-1 -> J_p -> J_c^T and the final cancellation
+    // against Hcc p amplify rounding, and FP64 costs nothing in this
+    // memory-bound pass.
+    using T = double;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     AT* acc_lds = (AT*)smem_raw;
     __shared__ double red[16];
@@ -396,8 +402,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
     const int te = (int)(((long long)g.n_tiles * (blockIdx.x + 1)) / gridDim.x);
     const int nw = blockDim.x >> 6;
     const int ne = g.ne;
-    const T* bp = (const T*)g.bp;
-    const T* rw = (const T*)g.rw;
+    const VT* bp = (const VT*)g.bp;
     double red_m = 0.0, red_b = 0.0, red_s = 0.0;
     for (int t = tb + (int)(threadIdx.x >> 6); t < te; t += nw) {
         const int e0 = g.tile_off[t], e1 = g.tile_off[t + 1];
@@ -425,7 +430,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
             T z[3];
             T pc[9];
             if (kMode == kRhs) {
-                const T b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
+                const T b0 = (T)bp[j], b1 = (T)bp[g.np + j], b2 = (T)bp[2 * g.np + j];
                 const double* H = g.hpp_inv;
                 const T h00 = (T)H[j], h01 = (T)H[g.np + j], h02 = (T)H[2 * g.np + j];
                 const T h11 = (T)H[3 * g.np + j], h12 = (T)H[4 * g.np + j], h22 = (T)H[5 * g.np + j];
@@ -434,7 +439,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                 z[2] = h02 * b0 + h12 * b1 + h22 * b2;
             } else {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) pc[k] = vin[9 * i + k];
+                for (int k = 0; k < 9; ++k) pc[k] = (T)vin[9 * i + k];
                 T a0 = 0, a1 = 0;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
@@ -505,7 +510,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
             const int j = g.e_pt[e0];
             T z[3];
             if (kMode == kRhs) {
-                const T b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
+                const T b0 = (T)bp[j], b1 = (T)bp[g.np + j], b2 = (T)bp[2 * g.np + j];
                 const double* H = g.hpp_inv;
                 z[0] = (T)H[j] * b0 + (T)H[g.np + j] * b1 + (T)H[2 * g.np + j] * b2;
                 z[1] = (T)H[g.np + j] * b0 + (T)H[3 * g.np + j] * b1 + (T)H[4 * g.np + j] * b2;
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                         T a0 = 0, a1 = 0;
 #pragma unroll
                         for (int k = 0; k < 9; ++k) {
-                            const T pk = vin[9 * i + k];
+                            const T pk = (T)vin[9 * i + k];
                             a0 += load_as<T>(Jc[k * ne + e]) * pk;
                             a1 += load_as<T>(Jc[(9 + k) * ne + e]) * pk;
                         }
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                     if (kMode == kBacksub) {
 #pragma unroll
                         for (int k = 0; k < 9; ++k) {
-                            const T pk = vin[9 * i + k];
+                            const T pk = (T)vin[9 * i + k];
                             u0 += load_as<T>(Jc[k * ne + e]) * pk;
                             u1 += load_as<T>(Jc[(9 + k) * ne + e]) * pk;
                         }
@@ -678,10 +683,10 @@ constexpr int kPcgBlock = 256;
 template <typename T>
 __device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds, int i, int a,
                                       int base) {
-    T s = 0;
+    double s = 0.0;
 #pragma unroll
-    for (int b = 0; b < 9; ++b) s += Minv[i * 45 + sym9(a, b)] * r_lds[base + b];
-    return s;
+    for (int b = 0; b < 9; ++b) s += (double)Minv[i * 45 + sym9(a, b)] * (double)r_lds[base + b];
+    return (T)s;
 }
 
 // PCG start: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
@@ -1005,19 +1010,19 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, do
     return hipSuccess;
 }
 
-template <typename T, typename JS, typename AT, int kMode>
+template <typename VT, typename JS, typename AT, int kMode>
 static void point_pass(const DeviceGraph& g, hipStream_t s, const void* jc, const void* jp,
                        const void* vin, void* out) {
     // allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per CU)
     static int lds_set = -1;
     if (kMode != kBacksub && g.lds_pp > 0 && lds_set < g.lds_pp) {
-        (void)hipFuncSetAttribute((const void*)k_point_pass<T, JS, AT, kMode>,
+        (void)hipFuncSetAttribute((const void*)k_point_pass<VT, JS, AT, kMode>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_pp);
         lds_set = g.lds_pp;
     }
-    hipLaunchKernelGGL((k_point_pass<T, JS, AT, kMode>), dim3(g.grid_pp), dim3(g.block_pp),
+    hipLaunchKernelGGL((k_point_pass<VT, JS, AT, kMode>), dim3(g.grid_pp), dim3(g.block_pp),
                        kMode == kBacksub ? 0 : g.lds_pp, s, g, (const JS*)jc, (const JS*)jp,
-                       (const T*)vin, (AT*)out);
+                       (const VT*)vin, (AT*)out);
 }
 
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
@@ -1027,9 +1032,9 @@ hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
         hipLaunchKernelGGL((k_reduce<double, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
                            (const double*)g.cam_partial, 0.0, 0.0, 0.0);
     } else {
-        point_pass<float, float, float, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
-        hipLaunchKernelGGL((k_reduce<float, float, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
-                           (const float*)g.cam_partial, 0.0, 0.0, 0.0);
+        point_pass<float, float, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+        hipLaunchKernelGGL((k_reduce<float, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
+                           (const double*)g.cam_partial, 0.0, 0.0, 0.0);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
@@ -1058,9 +1063,9 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, d
     if (g.mode == kModeFP64) {
         point_pass<double, double, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     } else if (g.mode == kModeFP32) {
-        point_pass<float, float, float, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
+        point_pass<float, float, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     } else {
-        point_pass<float, bf16, float, kMatvec>(g, s, g.jc16, g.jp16, g.v_p, g.cam_partial);
+        point_pass<float, bf16, double, kMatvec>(g, s, g.jc16, g.jp16, g.v_p, g.cam_partial);
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     if (g.mode == kModeFP64) {
@@ -1069,8 +1074,8 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, d
         hipLaunchKernelGGL(k_pcg_apply<double>, dim3(pcg_blocks(g)), dim3(kPcgBlock), 0, s, g);
         hipLaunchKernelGGL(k_pcg_finish<double>, dim3(1), dim3(1024), 0, s, g, pcg_blocks(g), max_iters, ratio);
     } else {
-        hipLaunchKernelGGL((k_reduce<float, float, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
-                           (const float*)g.cam_partial, lambda, min_diag, max_diag);
+        hipLaunchKernelGGL((k_reduce<float, double, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
+                           (const double*)g.cam_partial, lambda, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<float>, dim3(pcg_blocks(g)), dim3(kPcgBlock), 0, s, g);
         hipLaunchKernelGGL(k_pcg_finish<float>, dim3(1), dim3(1024), 0, s, g, pcg_blocks(g), max_iters, ratio);
     }
@@ -1084,7 +1089,7 @@ hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s) {
         point_pass<double, double, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
     } else {
         hipLaunchKernelGGL(k_cam_update<float>, dim3(1), dim3(1024), 0, s, g);
-        point_pass<float, float, float, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+        point_pass<float, float, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
