@@ -291,12 +291,10 @@ gba_status build(gba_graph* g) {
     P.add((void**)&d.pt_c, sizeof(double) * 3 * NP);
     P.add((void**)&d.pt_init, sizeof(double) * 3 * NP);
     P.add((void**)&d.dpt, sizeof(double) * 3 * NP);
-    P.add(&d.jc, tsz * 18 * NE);
-    P.add(&d.jp, tsz * 6 * NE);
-    if (g->precision == GBA_MIXED_BF16) {
-        P.add(&d.jc16, 2 * 18 * NE);
-        P.add(&d.jp16, 2 * 6 * NE);
-    }
+    const size_t jsz = g->precision == GBA_FP64 ? 8 : (g->precision == GBA_MIXED_FP32 ? 4 : 2);
+    d.jac_bytes = (int)jsz;
+    P.add(&d.jc, jsz * 18 * NE);
+    P.add(&d.jp, jsz * 6 * NE);
     P.add(&d.rw, tsz * 2 * NE);
     P.add(&d.hpp, tsz * 6 * NP);
     P.add(&d.bp, tsz * 3 * NP);

@@ -36,6 +36,15 @@ __device__ __forceinline__ bf16 store_as<bf16, float>(float x) { return to_bf16(
 template <typename T, typename S>
 __device__ __forceinline__ T load_as(S x) { return (T)to_float(x); }
 
+// Storage of a Jacobian entry computed in FP64, and the value the stored
+// entry represents (the linear system is built from what is stored).
+template <typename JS>
+__device__ __forceinline__ JS jac_store(double x) { return (JS)x; }
+template <>
+__device__ __forceinline__ bf16 jac_store<bf16>(double x) { return to_bf16((float)x); }
+template <typename JS>
+__device__ __forceinline__ double jac_round(double x) { return (double)to_float(jac_store<JS>(x)); }
+
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 

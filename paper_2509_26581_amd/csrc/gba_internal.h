@@ -88,10 +88,8 @@ struct DeviceGraph {
     const double* pt_init;
 
     // linearisation (T = double or float; J copy may be bf16)
-    void* jc;                 // [18][ne] weighted Jacobian w.r.t. camera
+    void* jc;                 // [18][ne] weighted Jacobian w.r.t. camera (FP64/FP32/BF16)
     void* jp;                 // [6][ne]  weighted Jacobian w.r.t. point
-    void* jc16;               // [18][ne] bf16 copy for the PCG products (mode 2)
-    void* jp16;
     void* rw;                 // [2][ne]  weighted residual
     void* hpp;                // [6][np]
     void* bp;                 // [3][np]

@@ -21,17 +21,17 @@ namespace gba {
 // weighted blocks, and point-side sums Hpp_j = sum J_p^T J_p, bp_j =
 // sum J_p^T r (Eq. 5) by segmented wavefront reductions over the point's
 // contiguous edges.  One wavefront per tile of whole points.  Arithmetic is
-// FP64 in every precision mode; T / JS are only the storage types.
+// FP64 in every precision mode; T (blocks) and JS (Jacobian) are storage
+// types.  The linear system is built from the stored Jacobian, the gradient
+// b from the FP64 one, so the LM fixed point is that of the FP64 problem.
 // ==========================================================================
 template <typename T, typename JS>
 __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
     const int l = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    T* Jc = (T*)g.jc;
-    T* Jp = (T*)g.jp;
-    JS* Jc16 = (JS*)g.jc16;
-    JS* Jp16 = (JS*)g.jp16;
+    JS* Jc = (JS*)g.jc;
+    JS* Jp = (JS*)g.jp;
     T* rw = (T*)g.rw;
     T* Hpp = (T*)g.hpp;
     T* bp = (T*)g.bp;
@@ -59,25 +59,13 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
             if (valid) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    Jc[k * ne + e] = (T)ev.jc[0][k];
-                    Jc[(9 + k) * ne + e] = (T)ev.jc[1][k];
+                    Jc[k * ne + e] = jac_store<JS>(ev.jc[0][k]);
+                    Jc[(9 + k) * ne + e] = jac_store<JS>(ev.jc[1][k]);
                 }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    Jp[k * ne + e] = (T)ev.jp[0][k];
-                    Jp[(3 + k) * ne + e] = (T)ev.jp[1][k];
-                }
-                if (Jc16) {
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) {
-                        Jc16[k * ne + e] = store_as<JS>((T)ev.jc[0][k]);
-                        Jc16[(9 + k) * ne + e] = store_as<JS>((T)ev.jc[1][k]);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        Jp16[k * ne + e] = store_as<JS>((T)ev.jp[0][k]);
-                        Jp16[(3 + k) * ne + e] = store_as<JS>((T)ev.jp[1][k]);
-                    }
+                    Jp[k * ne + e] = jac_store<JS>(ev.jp[0][k]);
+                    Jp[(3 + k) * ne + e] = jac_store<JS>(ev.jp[1][k]);
                 }
                 rw[e] = (T)ev.r[0];
                 rw[ne + e] = (T)ev.r[1];
@@ -99,14 +87,21 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
                     raw.w[e] = (double)w;
                 }
             }
-            // point-side contributions of this edge
+            // point-side contributions of this edge: the Hessian block from the
+            // stored (rounded) Jacobian, the gradient from the FP64 one
+            double jr[2][3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                jr[0][k] = jac_round<JS>(ev.jp[0][k]);
+                jr[1][k] = jac_round<JS>(ev.jp[1][k]);
+            }
             double h[9];
-            h[0] = ev.jp[0][0] * ev.jp[0][0] + ev.jp[1][0] * ev.jp[1][0];
-            h[1] = ev.jp[0][0] * ev.jp[0][1] + ev.jp[1][0] * ev.jp[1][1];
-            h[2] = ev.jp[0][0] * ev.jp[0][2] + ev.jp[1][0] * ev.jp[1][2];
-            h[3] = ev.jp[0][1] * ev.jp[0][1] + ev.jp[1][1] * ev.jp[1][1];
-            h[4] = ev.jp[0][1] * ev.jp[0][2] + ev.jp[1][1] * ev.jp[1][2];
-            h[5] = ev.jp[0][2] * ev.jp[0][2] + ev.jp[1][2] * ev.jp[1][2];
+            h[0] = jr[0][0] * jr[0][0] + jr[1][0] * jr[1][0];
+            h[1] = jr[0][0] * jr[0][1] + jr[1][0] * jr[1][1];
+            h[2] = jr[0][0] * jr[0][2] + jr[1][0] * jr[1][2];
+            h[3] = jr[0][1] * jr[0][1] + jr[1][1] * jr[1][1];
+            h[4] = jr[0][1] * jr[0][2] + jr[1][1] * jr[1][2];
+            h[5] = jr[0][2] * jr[0][2] + jr[1][2] * jr[1][2];
             h[6] = ev.jp[0][0] * ev.r[0] + ev.jp[1][0] * ev.r[1];
             h[7] = ev.jp[0][1] * ev.r[0] + ev.jp[1][1] * ev.r[1];
             h[8] = ev.jp[0][2] * ev.r[0] + ev.jp[1][2] * ev.r[1];
@@ -213,7 +208,7 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double lambd
 // ==========================================================================
 enum { kAssemble = 0, kPrecond = 1 };
 
-template <typename T, int kMode>
+template <typename T, typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     constexpr int K = kMode == kAssemble ? 54 : 45;
     __shared__ double red[4][K];
@@ -243,18 +238,29 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                 bal_eval<double, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
                 double s, rho, w;
                 whiten<double, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
+                double jc[2][9], jp[2][3];
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    jc[0][a] = jac_round<JS>(ev.jc[0][a]);
+                    jc[1][a] = jac_round<JS>(ev.jc[1][a]);
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    jp[0][a] = jac_round<JS>(ev.jp[0][a]);
+                    jp[1][a] = jac_round<JS>(ev.jp[1][a]);
+                }
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
 #pragma unroll
                     for (int b = a; b < 9; ++b, ++k)
-                        acc[k] += ev.jc[0][a] * ev.jc[0][b] + ev.jc[1][a] * ev.jc[1][b];
+                        acc[k] += jc[0][a] * jc[0][b] + jc[1][a] * jc[1][b];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
                     acc[45 + a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
 #pragma unroll
                     for (int b = 0; b < 3; ++b)
-                        W[a][b] += ev.jc[0][a] * ev.jp[0][b] + ev.jc[1][a] * ev.jp[1][b];
+                        W[a][b] += jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
                 }
             }
 #pragma unroll
@@ -950,7 +956,7 @@ hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* r
         hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
         hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
         hipLaunchKernelGGL((k_linearize<float, float>), dim3(grid), dim3(256), 0, s, g, r);
-    } else {
+    } else {  // FP32 blocks, BF16 Jacobian
         hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
         hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
         hipLaunchKernelGGL((k_linearize<float, bf16>), dim3(grid), dim3(256), 0, s, g, r);
@@ -962,9 +968,11 @@ hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* r
 hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
     if (g.n_chunks > 0) {
         if (g.mode == kModeFP64)
-            hipLaunchKernelGGL((k_cam_accumulate<double, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            hipLaunchKernelGGL((k_cam_accumulate<double, double, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        else if (g.mode == kModeFP32)
+            hipLaunchKernelGGL((k_cam_accumulate<float, float, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
         else
-            hipLaunchKernelGGL((k_cam_accumulate<float, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
     const int grid = g.nc;
@@ -996,9 +1004,9 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, do
                           double max_diag, int block_jacobi) {
     if (block_jacobi && g.n_chunks > 0) {
         if (g.mode == kModeFP64)
-            hipLaunchKernelGGL((k_cam_accumulate<double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            hipLaunchKernelGGL((k_cam_accumulate<double, double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
         else
-            hipLaunchKernelGGL((k_cam_accumulate<float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            hipLaunchKernelGGL((k_cam_accumulate<float, float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
     const int grid = g.nc;
@@ -1032,7 +1040,10 @@ hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
         hipLaunchKernelGGL((k_reduce<double, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
                            (const double*)g.cam_partial, 0.0, 0.0, 0.0);
     } else {
-        point_pass<float, float, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+        if (g.mode == kModeFP32)
+            point_pass<float, float, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+        else
+            point_pass<float, bf16, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
         hipLaunchKernelGGL((k_reduce<float, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
                            (const double*)g.cam_partial, 0.0, 0.0, 0.0);
     }
@@ -1065,7 +1076,7 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, d
     } else if (g.mode == kModeFP32) {
         point_pass<float, float, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     } else {
-        point_pass<float, bf16, double, kMatvec>(g, s, g.jc16, g.jp16, g.v_p, g.cam_partial);
+        point_pass<float, bf16, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     if (g.mode == kModeFP64) {
@@ -1089,7 +1100,10 @@ hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s) {
         point_pass<double, double, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
     } else {
         hipLaunchKernelGGL(k_cam_update<float>, dim3(1), dim3(1024), 0, s, g);
-        point_pass<float, float, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+        if (g.mode == kModeFP32)
+            point_pass<float, float, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+        else
+            point_pass<float, bf16, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
