@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 METRIC = "LM iter/s + PCG HBM GB/s at 1M obs; p50/p99 latency for local-BA stream"
 HBM_PEAK_GBS = 8000.0
 PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf16", 2)}
+# HBM bytes per matvec launch measured with rocprofv3 counters on the 1M-observation
+# workload (FETCH_SIZE x 2 + WRITE_SIZE, the factor 2 from a 256 MiB copy probe whose
+# FETCH_SIZE reads half its size); see profiles/.  None until measured for the
+# current kernel.
+MEASURED_TRAFFIC = {}
 
 
 def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes):
@@ -62,7 +67,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=list(PRECISIONS))
+    ap.add_argument("--precision", default="fp32", choices=list(PRECISIONS))
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain-FP64 comparison run")
     ap.add_argument("--workload", default="bal1m")
     ap.add_argument("--trials", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -99,30 +106,35 @@ def main():
     trials = args.trials or sc.trials
     print(f"[bench] workload {args.workload}: {sc.n_cams} cams, {sc.n_pts} pts, {sc.n_obs} obs "
           f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
-    opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
-                       timing=0 if args.no_timing else 1)
-    g = gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
-                              loss=sc.loss, delta=sc.delta, precision=prec_id, options=opts,
-                              use_torch=True)
-    t0 = time.perf_counter()
-    gba.gba_prepare(g.h)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    print(f"[bench] graph build + upload {build_s:.2f} s", flush=True)
+    def timed_run(prec_id, timing):
+        opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
+                           timing=1 if timing else 0)
+        g = gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
+                                  loss=sc.loss, delta=sc.delta, precision=prec_id,
+                                  options=opts, use_torch=True)
+        t0 = time.perf_counter()
+        gba.gba_prepare(g.h)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        for w in range(args.warmup):
+            gba.gba_reset(g.h)
+            rep = g.solve(trials)
+            print(f"[bench] precision {prec_id} warmup {w}: {rep.trials} trials, "
+                  f"{rep.ms_total:.1f} ms, cost {rep.initial_cost:.6e} -> {rep.final_cost:.6e}",
+                  flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reports = []
+        for k in range(args.steps):
+            gba.gba_reset(g.h)
+            reports.append(g.solve(trials))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        g.close()
+        return reports, elapsed, build_s
 
-    reports = []
-    for w in range(args.warmup):
-        gba.gba_reset(g.h)
-        rep = g.solve(trials)
-        print(f"[bench] warmup {w}: {rep.trials} trials, {rep.ms_total:.1f} ms, "
-              f"cost {rep.initial_cost:.6e} -> {rep.final_cost:.6e}", flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        gba.gba_reset(g.h)
-        reports.append(g.solve(trials))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    reports, elapsed, build_s = timed_run(prec_id, not args.no_timing)
+    print(f"[bench] graph build + upload {build_s:.2f} s", flush=True)
     total_trials = sum(r.trials for r in reports)
     lm_iters_s = total_trials / elapsed
     last = reports[-1]
@@ -134,10 +146,19 @@ def main():
     if mv_n:
         avg_s = mv_ms / mv_n / 1e3
         achieved = alg_bytes / avg_s / 1e9
+        traffic = MEASURED_TRAFFIC.get(args.precision) if args.workload == "bal1m" else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "kernel": "k_point_pass<kMatvec> (fused Schur product)",
+                    "traffic": traffic, "kernel": "k_point_pass<kMatvec> (fused Schur product)",
                     "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": int(alg_bytes)}
+    compare = None
+    if not args.no_compare and prec_id != 0:
+        r64, e64, _ = timed_run(0, False)
+        v64 = sum(r.trials for r in r64) / e64
+        compare = {"fp64_lm_iter_per_s": round(v64, 3), "mixed_over_fp64": round(lm_iters_s / v64, 3),
+                   "fp64_final_cost": r64[-1].final_cost,
+                   "mixed_vs_fp64_final_cost_rel": abs(last.final_cost - r64[-1].final_cost) /
+                   r64[-1].final_cost}
     line = {
         "metric": METRIC, "value": round(lm_iters_s, 3), "unit": "LM iter/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -155,11 +176,13 @@ def main():
                                ("ms_linearize", "ms_precond", "ms_pcg", "ms_other", "ms_matvec")},
         "graph_build_s": round(build_s, 3), "workspace_bytes": int(last.workspace_bytes),
         "roofline": roofline,
+        "fp64_comparison": compare,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a one-trial sample ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(sc)
-    g.close()
+    else:
+        line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
 
 

@@ -16,24 +16,25 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc")]
 
 
-def build(verbose=False):
-    out_dir = os.path.join(ROOT, "_build")
+def build(verbose=False, lib=LIB, defines=()):
+    out_dir = os.path.join(ROOT, "_build", os.path.basename(lib).replace(".so", ""))
     os.makedirs(out_dir, exist_ok=True)
     objs = []
     for src in SRC:
         obj = os.path.join(out_dir, src.replace(".hip", ".o"))
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + [
+            "-c", os.path.join(HERE, "csrc", src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

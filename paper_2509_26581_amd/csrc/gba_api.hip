@@ -301,7 +301,7 @@ gba_status build(gba_graph* g) {
     P.add(&d.hcc, tsz * 45 * NC);
     P.add(&d.wrun, tsz * 27 * (size_t)std::max(1, n_runs));
     P.add(&d.bc, tsz * 9 * NC);
-    P.add((void**)&d.hpp_inv, sizeof(double) * 6 * NP);
+    P.add((void**)&d.hpp_inv, sizeof(double) * gba::kHinvStride * NP);
     P.add(&d.minv, tsz * 45 * NC);
     P.add(&d.v_x, tsz * 9 * NC);
     P.add(&d.v_r, tsz * 9 * NC);

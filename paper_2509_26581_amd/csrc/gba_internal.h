@@ -12,6 +12,7 @@ constexpr int kTileEdges = 64;        // edges per point tile (one wavefront)
 constexpr int kChunkRuns = 1024;      // camera-major runs per workgroup chunk
 constexpr int kHccN = 45;             // unique entries of a symmetric 9x9
 constexpr int kHppN = 6;              // unique entries of a symmetric 3x3
+constexpr int kHinvStride = 8;        // padded row of the damped inverse point blocks
 
 // symmetric 9x9 packed upper triangle, row-major: index of (r, c), r <= c
 __host__ __device__ constexpr int sym9(int r, int c) {
@@ -96,7 +97,7 @@ struct DeviceGraph {
     void* hcc;                // [45][nc] stored as [nc][45]
     void* wrun;               // [27][n_runs] W = sum_run J_c^T J_p per camera-major run
     void* bc;                 // [nc][9]
-    double* hpp_inv;          // [6][np] damped inverse (FP64)
+    double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per 64-byte row
     void* minv;               // [nc][45] preconditioner inverse blocks
 
     // Schur / PCG vectors, [nc][9]

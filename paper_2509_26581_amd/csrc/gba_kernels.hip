@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double lambd
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int c = r; c < 3; ++c) g.hpp_inv[sym3(r, c) * g.np + j] = ok ? A[r][c] : 0.0;
+            for (int c = r; c < 3; ++c) g.hpp_inv[kHinvStride * j + sym3(r, c)] = ok ? A[r][c] : 0.0;
         const double p0 = g.pt[3 * j], p1 = g.pt[3 * j + 1], p2 = g.pt[3 * j + 2];
         g.pt_c[3 * j] = p0;
         g.pt_c[3 * j + 1] = p1;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Hi[r][c] = g.hpp_inv[sym3(r, c) * g.np + j];
+                for (int c = 0; c < 3; ++c) Hi[r][c] = g.hpp_inv[kHinvStride * j + sym3(r, c)];
             double WH[9][3];
 #pragma unroll
             for (int a = 0; a < 9; ++a)
@@ -437,9 +437,8 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
             T pc[9];
             if (kMode == kRhs) {
                 const T b0 = (T)bp[j], b1 = (T)bp[g.np + j], b2 = (T)bp[2 * g.np + j];
-                const double* H = g.hpp_inv;
-                const T h00 = (T)H[j], h01 = (T)H[g.np + j], h02 = (T)H[2 * g.np + j];
-                const T h11 = (T)H[3 * g.np + j], h12 = (T)H[4 * g.np + j], h22 = (T)H[5 * g.np + j];
+                const double* H = g.hpp_inv + kHinvStride * j;
+                const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
                 z[0] = h00 * b0 + h01 * b1 + h02 * b2;
                 z[1] = h01 * b0 + h11 * b1 + h12 * b2;
                 z[2] = h02 * b0 + h12 * b1 + h22 * b2;
@@ -459,12 +458,10 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                     tt[k] = segment_sum(tt[k], l, end);
                 }
                 // head lane applies the point block
-                const double* H = g.hpp_inv;
                 T zz[3] = {0, 0, 0};
                 if (valid && head == l) {
-                    const T h00 = (T)H[j], h01 = (T)H[g.np + j], h02 = (T)H[2 * g.np + j];
-                    const T h11 = (T)H[3 * g.np + j], h12 = (T)H[4 * g.np + j];
-                    const T h22 = (T)H[5 * g.np + j];
+                    const double* H = g.hpp_inv + kHinvStride * j;
+                    const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
                     T v0 = tt[0], v1 = tt[1], v2 = tt[2];
                     if (kMode == kBacksub) {
                         v0 += bp[j];
@@ -517,10 +514,10 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
             T z[3];
             if (kMode == kRhs) {
                 const T b0 = (T)bp[j], b1 = (T)bp[g.np + j], b2 = (T)bp[2 * g.np + j];
-                const double* H = g.hpp_inv;
-                z[0] = (T)H[j] * b0 + (T)H[g.np + j] * b1 + (T)H[2 * g.np + j] * b2;
-                z[1] = (T)H[g.np + j] * b0 + (T)H[3 * g.np + j] * b1 + (T)H[4 * g.np + j] * b2;
-                z[2] = (T)H[2 * g.np + j] * b0 + (T)H[4 * g.np + j] * b1 + (T)H[5 * g.np + j] * b2;
+                const double* H = g.hpp_inv + kHinvStride * j;
+                z[0] = H[0] * b0 + H[1] * b1 + H[2] * b2;
+                z[1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
+                z[2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
             } else {
                 T tt[3] = {0, 0, 0};
                 for (int c0 = 0; c0 < n; c0 += kWave) {
@@ -547,10 +544,10 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                     tt[1] += bp[g.np + j];
                     tt[2] += bp[2 * g.np + j];
                 }
-                const double* H = g.hpp_inv;
-                z[0] = (T)H[j] * tt[0] + (T)H[g.np + j] * tt[1] + (T)H[2 * g.np + j] * tt[2];
-                z[1] = (T)H[g.np + j] * tt[0] + (T)H[3 * g.np + j] * tt[1] + (T)H[4 * g.np + j] * tt[2];
-                z[2] = (T)H[2 * g.np + j] * tt[0] + (T)H[4 * g.np + j] * tt[1] + (T)H[5 * g.np + j] * tt[2];
+                const double* H = g.hpp_inv + kHinvStride * j;
+                z[0] = H[0] * tt[0] + H[1] * tt[1] + H[2] * tt[2];
+                z[1] = H[1] * tt[0] + H[3] * tt[1] + H[4] * tt[2];
+                z[2] = H[2] * tt[0] + H[4] * tt[1] + H[5] * tt[2];
                 if (kMode == kBacksub) {
                     z[0] = -z[0];
                     z[1] = -z[1];

@@ -13,7 +13,8 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgba.so")
+LIB_PATH = os.environ.get("GBA_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libgba.so")
 
 GBA_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "UNKNOWN_ID", -3: "DUPLICATE_ID", -4: "NONFINITE",
