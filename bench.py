@@ -62,6 +62,82 @@ def cpu_baseline(sc):
             "trial_cost": res.log[0]["candidate_cost"]}
 
 
+def serving_measurement(gba, synth, n_req, precision, budget, slots, tune_db, seed=0):
+    """Local-BA stream on the server: (1) the same requests one at a time,
+    (2) all submitted at once (saturated throughput), (3) a Poisson stream at
+    0.8 x the saturated rate; latency = submission to result."""
+    t0 = time.perf_counter()
+    reqs = [synth.make_local_request(10_000 * seed + k) for k in range(n_req)]
+    n_obs = [len(r["cam_idx"]) for r in reqs]
+    print(f"[bench] serving: {n_req} local-BA requests generated in "
+          f"{time.perf_counter() - t0:.1f} s (obs {min(n_obs)}..{max(n_obs)}, "
+          f"mean {sum(n_obs) / n_req:.0f})", flush=True)
+
+    def server():
+        return gba.Server(precision=precision, budget_bytes=budget, max_slots=slots,
+                          tune_db=tune_db)
+
+    # (1) one at a time, on a prefix
+    n_single = min(n_req, 64)
+    s = server()
+    lat = []
+    t0 = time.perf_counter()
+    for r in reqs[:n_single]:
+        lat.append(s.poll(s.submit(r))["latency_ms"])
+    single_s = time.perf_counter() - t0
+    s.close()
+    single = {"requests": n_single, "solves_per_s": round(n_single / single_s, 2),
+              "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+              "p99_latency_ms": round(float(np.percentile(lat, 99)), 3)}
+    print(f"[bench] serving one at a time: {single}", flush=True)
+    # (2) saturated
+    s = server()
+    t0 = time.perf_counter()
+    tickets = [s.submit(r) for r in reqs]
+    for t in tickets:
+        s.poll(t)
+    sat_s = time.perf_counter() - t0
+    sat_stats = s.stats()
+    s.close()
+    sat = n_req / sat_s
+    print(f"[bench] serving saturated: {sat:.1f} solves/s, mean batch "
+          f"{sat_stats['mean_batch']:.1f}", flush=True)
+    # (3) Poisson stream at 0.8 x saturated
+    rate = 0.8 * sat
+    arrivals = synth.poisson_arrivals(n_req, rate, seed + 1)
+    s = server()
+    tickets = []
+    t0 = time.perf_counter()
+    for r, ta in zip(reqs, arrivals):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(s.submit(r))
+    results = [s.poll(t) for t in tickets]
+    st = s.stats()
+    s.close()
+    lat = [x["latency_ms"] for x in results]
+    svc = [x["report"]["ms_total"] for x in results]
+    out = {"requests": n_req, "precision": {0: "fp64", 1: "fp32", 2: "bf16"}[precision],
+           "arrival_rate_per_s": round(rate, 2),
+           "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_latency_ms": round(float(np.percentile(lat, 99)), 3),
+           "p50_service_ms": round(float(np.percentile(svc, 50)), 3),
+           "p99_service_ms": round(float(np.percentile(svc, 99)), 3),
+           "solves_per_s": round(st["solves_per_s"], 2),
+           "saturated_solves_per_s": round(sat, 2),
+           "one_at_a_time": single,
+           "admitted": st["admitted"], "rejected": st["rejected"],
+           "mean_batch": round(st["mean_batch"], 2), "repacks": st["repacks"],
+           "budget_bytes": int(budget), "bytes_peak": int(st["bytes_peak"]), "max_slots": slots,
+           "tiles_per_block": st["tiles_per_block"], "edges_per_block": st["edges_per_block"],
+           "pts_per_block": st["pts_per_block"], "pcg_sync_every": st["pcg_sync_every"],
+           "trials_per_request": reqs[0]["max_iters"]}
+    print(f"[bench] serving stream: p50 {out['p50_latency_ms']} ms, p99 "
+          f"{out['p99_latency_ms']} ms at {rate:.1f} req/s", flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +150,11 @@ def main():
     ap.add_argument("--trials", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the local-BA stream")
+    ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-budget-mb", type=int, default=4096)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the run, one device-to-device copy of this many MiB "
                          "(calibrates HBM byte counters; not timed)")
@@ -101,6 +182,13 @@ def main():
         print(f"[bench] copy probe: {args.copy_probe_mb} MiB device-to-device", flush=True)
         del src, dst
     prec_id, dtype_name, jac_bytes = PRECISIONS[args.precision]
+    tune_db = os.path.join(ROOT, "paper_2509_26581_amd", "tune_db.txt")
+    tune_db = tune_db if os.path.exists(tune_db) else None
+    if args.serve_only:
+        out = serving_measurement(gba, synth, args.serve_requests, prec_id,
+                                  args.serve_budget_mb << 20, args.serve_slots, tune_db)
+        print(json.dumps({"serving": out}), flush=True)
+        return
     t0 = time.perf_counter()
     sc = synth.make_scene(args.workload, seed=0)
     trials = args.trials or sc.trials
@@ -178,6 +266,11 @@ def main():
         "roofline": roofline,
         "fp64_comparison": compare,
     }
+    line["serving"] = None
+    if not args.no_serve:
+        line["serving"] = serving_measurement(gba, synth, args.serve_requests, prec_id,
+                                              args.serve_budget_mb << 20, args.serve_slots,
+                                              tune_db)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a one-trial sample ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(sc)

@@ -55,6 +55,8 @@ typedef int gba_status;
 #define GBA_ERR_HIP (-6)          /* a HIP runtime call failed               */
 #define GBA_ERR_STATE (-7)        /* call not valid in the current state     */
 #define GBA_ERR_UNSUPPORTED (-8)  /* configuration this build cannot run     */
+#define GBA_ERR_BUDGET (-9)       /* serving: request larger than the budget */
+#define GBA_PENDING 1             /* serving: result not ready (not an error) */
 
 typedef struct gba_graph gba_graph;
 
@@ -112,8 +114,19 @@ typedef struct gba_options {
                                   disables (default: disabled)               */
     int precond;               /* gba_precond (BLOCK_JACOBI)                 */
     int timing;                /* 1: time phases with HIP events (0)         */
-    int reserved[7];
+    int accumulation;          /* camera-side sums of the point passes:
+                                  GBA_ACC_AUTO (default): per-workgroup LDS
+                                  partials when one problem's 9 x n_cams FP64
+                                  vector fits in LDS, else global atomics;
+                                  GBA_ACC_LDS / GBA_ACC_GLOBAL force one
+                                  (LDS fails with UNSUPPORTED when it does not
+                                  fit).  Read when the device graph is built. */
+    int reserved[6];
 } gba_options;
+
+#define GBA_ACC_AUTO 0
+#define GBA_ACC_LDS 1
+#define GBA_ACC_GLOBAL 2
 
 /* Summary of one gba_solve call. */
 typedef struct gba_report {
@@ -240,6 +253,117 @@ const char* gba_last_error(const gba_graph* g);
 
 /* Release all device and host memory of the graph.  NULL is ignored. */
 void gba_destroy(gba_graph* g);
+
+/* ====================================================================
+ * Serving: many small (local) bundle-adjustment problems solved
+ * concurrently on one GPU.
+ *
+ * Requests are admitted while both a slot and device memory are free (the
+ * memory budget bounds the device bytes of every resident request: its
+ * uploaded image plus its share of the batch workspace).  Resident problems
+ * are packed into one batch whose kernels work on problem-aligned
+ * decompositions: each workgroup serves one problem, so every problem keeps
+ * its own damping, PCG state, scalars and accept / reject decisions, and the
+ * LM iterations of all resident problems advance together (one batched trial
+ * at a time).  A request that arrives while others run is uploaded
+ * asynchronously and joins the batch at the next trial boundary; a finished
+ * problem leaves it.  With fixed decomposition sizes (always the case in the
+ * server) a problem's arithmetic does not depend on its batch mates: its
+ * result is the same alone and in any mix.
+ *
+ * The paper batches constraints and vertices of one graph for its kernels
+ * (Sec. IV-B); serving several graphs at once is this library's production
+ * form of the same method, not a construct of the paper.
+ *
+ * Threading: gba_server_submit / poll / stats may be called from any thread;
+ * one internal thread drives the device.
+ * ==================================================================== */
+typedef struct gba_server gba_server;
+
+/* One request: a complete problem with dense, request-local indices. */
+typedef struct gba_problem {
+    int32_t n_cams;
+    int32_t n_pts;
+    int64_t n_edges;
+    const double* cams;          /* [n_cams x 9] as in gba_add_cameras          */
+    const double* pts;           /* [n_pts x 3]                                 */
+    const int32_t* cam_idx;      /* [n_edges] in [0, n_cams)                    */
+    const int32_t* pt_idx;       /* [n_edges] in [0, n_pts)                     */
+    const double* uv;            /* [n_edges x 2] observed pixels               */
+    const double* info;          /* [n_edges x 3] or NULL (identity)            */
+    const uint8_t* cam_fixed;    /* [n_cams] nonzero = constant, or NULL        */
+    const uint8_t* pt_fixed;     /* [n_pts] or NULL                             */
+    int32_t max_iters;           /* LM trials (as gba_solve)                    */
+    int32_t reserved;
+    double tol;                  /* as gba_solve                                */
+} gba_problem;
+
+/* Result of one request.  cams / pts are caller buffers sized for the
+ * request (or NULL to skip); the rest is filled by gba_server_poll. */
+typedef struct gba_result {
+    double* cams;                /* [n_cams x 9]                                */
+    double* pts;                 /* [n_pts x 3]                                 */
+    gba_report report;           /* ms_total = service time (admission to result) */
+    double latency_ms;           /* submission to result                        */
+    double queue_ms;             /* submission to admission                     */
+    int32_t batch_peak;          /* most problems resident with it in one trial */
+    int32_t reserved;
+} gba_result;
+
+typedef struct gba_server_config {
+    gba_precision precision;     /* (GBA_MIXED_FP32)                            */
+    int device;                  /* (0)                                         */
+    size_t hbm_budget_bytes;     /* device bytes for all resident requests (4 GiB) */
+    int max_slots;               /* resident requests at most (64; <= 4096)     */
+    gba_loss loss;               /* (GBA_LOSS_HUBER)                            */
+    double delta;                /* (1.0)                                       */
+    gba_options options;         /* as gba_set_options (defaults)               */
+    const char* tune_db;         /* tuning database written by the autotuner, or
+                                    NULL for built-in sizes; read at creation   */
+    int tiles_per_block;         /* > 0 overrides the database                  */
+    int edges_per_block;
+    int pts_per_block;
+    int pcg_sync_every;
+    int reserved[8];
+} gba_server_config;
+
+typedef struct gba_serving_stats {
+    int64_t submitted, admitted, rejected, completed, collected;
+    int64_t in_flight;           /* resident now                                */
+    int64_t queued;              /* waiting for admission                       */
+    int64_t trials_run;          /* batched LM trials issued                    */
+    int64_t repacks;             /* batch rebuilds on membership change         */
+    double mean_batch;           /* mean resident problems per batched trial   */
+    double p50_latency_ms, p99_latency_ms;  /* over completed requests          */
+    double p50_service_ms, p99_service_ms;
+    double solves_per_s;         /* completed / (last completion - first submission) */
+    size_t bytes_in_use, bytes_peak, budget;
+    int tiles_per_block, edges_per_block, pts_per_block, pcg_sync_every;  /* in use */
+} gba_serving_stats;
+
+void gba_server_default_config(gba_server_config* out);
+
+/* Create a server: reserves the budget on the device (one allocation from
+ * alloc / free, or hipMalloc when both are NULL) and starts its thread. */
+gba_status gba_server_create(const gba_server_config* cfg, gba_alloc_fn alloc,
+                             gba_free_fn free_fn, void* ctx, gba_server** out);
+
+/* Copy a request (all arrays are read before return), validate it and
+ * queue it.  GBA_ERR_BUDGET when it can never fit the budget. */
+gba_status gba_server_submit(gba_server* s, const gba_problem* req, uint64_t* ticket);
+
+/* Collect a result: GBA_PENDING while the request runs (wait = 0), or block
+ * until it is done (wait != 0).  A collected ticket is forgotten. */
+gba_status gba_server_poll(gba_server* s, uint64_t ticket, int wait, gba_result* out);
+
+gba_status gba_server_stats(gba_server* s, gba_serving_stats* out);
+
+/* Message of the last failed server call or of a failure of its thread. */
+const char* gba_server_last_error(gba_server* s);
+
+/* Stop the thread (finishing resident requests is not waited for) and
+ * release everything.  NULL is ignored. */
+void gba_server_destroy(gba_server* s);
 
 #ifdef __cplusplus
 }

@@ -1,5 +1,13 @@
-// Internal interface between the host driver (gba_api.hip) and the gfx950
-// kernels (gba_kernels.hip).  Not part of the public ABI.
+// Internal interface between the host drivers (gba_api.hip, gba_serve.hip)
+// and the gfx950 kernels (gba_kernels.hip).  Not part of the public ABI.
+//
+// A device graph holds P >= 1 independent bundle-adjustment problems laid out
+// one after the other (cameras, points, point-major edges and tiles of a
+// problem are contiguous).  A single solve is P = 1; the serving loop packs
+// many resident problems into one graph.  Every kernel works on a
+// problem-aligned decomposition: each workgroup handles items of exactly one
+// problem, so per-workgroup partial sums add up per problem without atomics,
+// and each problem carries its own damping, PCG state and trial scalars.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,9 +18,15 @@ namespace gba {
 constexpr int kWave = 64;
 constexpr int kTileEdges = 64;        // edges per point tile (one wavefront)
 constexpr int kChunkRuns = 1024;      // camera-major runs per workgroup chunk
-constexpr int kHccN = 45;             // unique entries of a symmetric 9x9
-constexpr int kHppN = 6;              // unique entries of a symmetric 3x3
 constexpr int kHinvStride = 8;        // padded row of the damped inverse point blocks
+constexpr int kCamsPerBlock = 28;     // cameras per PCG-vector workgroup (252 components)
+constexpr int kPcgBlock = 256;        // threads of the PCG-vector workgroups
+constexpr int kRedComps = 64;         // components per partial-reduction workgroup
+constexpr int kMaxProblems = 4096;    // problems per device graph
+#ifndef GBA_PP_BLOCK
+#define GBA_PP_BLOCK 1024
+#endif
+constexpr int kPointPassBlock = GBA_PP_BLOCK;  // threads per point-pass workgroup
 
 // symmetric 9x9 packed upper triangle, row-major: index of (r, c), r <= c
 __host__ __device__ constexpr int sym9(int r, int c) {
@@ -25,7 +39,7 @@ __host__ __device__ constexpr int sym3(int r, int c) {
 
 enum Mode { kModeFP64 = 0, kModeFP32 = 1, kModeBF16 = 2 };
 
-// Per-trial scalars read back by the host after each LM trial.
+// Per-problem scalars of one LM trial, read back by the host.
 struct TrialScalars {
     double cost;         // F at the candidate (or at x for the initial eval)
     double b_dot_dx;     // b^T dx
@@ -36,7 +50,7 @@ struct TrialScalars {
     int pcg_reason;
 };
 
-// PCG scalar state, written by the single-workgroup update kernels.
+// Per-problem PCG state.
 struct PcgState {
     double rz;           // r^T z of the current iterate
     double rr;           // r^T r
@@ -44,24 +58,40 @@ struct PcgState {
     double min_rr;
     double thresh;       // stop when rr <= thresh
     int iters;
-    int done;            // 0 running, 1 converged, 2 max iters, 3 breakdown, 4 rejected
+    int done;            // 0 running, 1 converged, 2 max iters, 3 breakdown, 4 rejected, 5 idle problem
     int use_best;
     int pad;
 };
 
+// Problem-aligned work decomposition: workgroup b handles items
+// [blk[3b], blk[3b+1]) of problem blk[3b+2]; the workgroups of problem p are
+// prob_blk[p] .. prob_blk[p+1]-1.
+struct Decomp {
+    const int* blk;
+    const int* prob_blk;
+    int nblk;
+};
+
+__device__ __forceinline__ int decomp_block(const Decomp& d, int b, int& begin, int& end) {
+    begin = d.blk[3 * b];
+    end = d.blk[3 * b + 1];
+    return d.blk[3 * b + 2];
+}
+
 // Device view of one graph.  All arrays are device pointers.  Edge arrays are
-// in point-major order (sorted by point, then camera) unless prefixed cm_
+// in point-major order (sorted by problem, point, camera) unless prefixed cm_
 // (camera-major order, sorted by camera, then point).
 struct DeviceGraph {
     int nc, np, ne;
-    int n_tiles;         // point tiles (whole points, <= 64 edges, or one long point)
+    int n_tiles;         // point tiles (whole points of one problem, <= 64 edges, or one long point)
     int n_runs;          // camera-major runs of equal (camera, point)
     int n_chunks;        // camera-major workgroup chunks
+    int n_probs;         // P
     int has_info;
     int loss;            // 0 squared, 1 huber
     double delta;
     int mode;            // Mode
-    int jac_bytes;       // bytes per stored Jacobian entry for the PCG copy
+    int jac_bytes;       // bytes per stored Jacobian entry
 
     // topology
     const int* tile_off;      // [n_tiles + 1] edge offsets
@@ -79,25 +109,34 @@ struct DeviceGraph {
     const unsigned char* cam_fixed;  // [nc]
     const unsigned char* pt_fixed;   // [np]
 
-    // parameters (FP64 master copies; candidate buffers swap with these)
+    // problems
+    const int* cam_prob;      // [nc] problem of each camera
+    const int* pt_prob;       // [np]
+    const int* prob_cam_off;  // [P + 1] camera range of each problem
+    double* lam;              // [P] damping of the current trial; negative: problem idle (no PCG)
+    int* accept;              // [P] 1: commit the candidate of this problem
+    PcgState* pcg;            // [P]
+    TrialScalars* scal;       // [P]
+
+    // parameters (FP64 master copies and candidates)
     double* cam;              // [nc][9]
     double* pt;               // [np][3]
     double* cam_c;            // candidates
     double* pt_c;
     double* dpt;              // [np][3] point step of the last damped solve
-    const double* cam_init;   // as inserted, for reset
-    const double* pt_init;
+    double* cam_init;         // as inserted, for reset
+    double* pt_init;
 
-    // linearisation (T = double or float; J copy may be bf16)
-    void* jc;                 // [18][ne] weighted Jacobian w.r.t. camera (FP64/FP32/BF16)
+    // linearisation (T = double or float blocks; Jacobian FP64 / FP32 / BF16)
+    void* jc;                 // [18][ne] weighted Jacobian w.r.t. camera
     void* jp;                 // [6][ne]  weighted Jacobian w.r.t. point
     void* rw;                 // [2][ne]  weighted residual
     void* hpp;                // [6][np]
     void* bp;                 // [3][np]
-    void* hcc;                // [45][nc] stored as [nc][45]
+    void* hcc;                // [nc][45]
     void* wrun;               // [27][n_runs] W = sum_run J_c^T J_p per camera-major run
     void* bc;                 // [nc][9]
-    double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per 64-byte row
+    double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per row
     void* minv;               // [nc][45] preconditioner inverse blocks
 
     // Schur / PCG vectors, [nc][9]
@@ -108,28 +147,27 @@ struct DeviceGraph {
     void* v_q;
     void* v_best;
 
-    // partial sums
-    void* cam_partial;        // [grid_pp][9 nc]
-    double* pq_partial;       // [grid_red]
-    double* dot_partial;      // [2][pcg workgroups] r^T z, r^T r
+    // decompositions and partial sums
+    Decomp dc_pp;             // point tiles (RHS, matvec, back-substitution)
+    Decomp dc_red;            // camera components, <= kRedComps per workgroup
+    Decomp dc_cam;            // cameras, <= kCamsPerBlock per workgroup
+    Decomp dc_edges;          // edges (cost)
+    Decomp dc_pts;            // points (damping)
+    const int* pp_part_off;   // [dc_pp.nblk] offset of each point-pass partial vector
+    double* cam_partial;      // point-pass camera partials
+    double* pq_partial;       // [dc_red.nblk]
+    double* dot_partial;      // [2][dc_cam.nblk] r^T z, r^T r
+    double* camupd_partial;   // [3][dc_cam.nblk] b^T dc, |dc|^2, |c|^2
     double* chunk_partial;    // [n_chunks][54]
-    double* red_partial;      // [grid_edges][4] misc per-block sums
-    double* cost_partial;     // [grid_edges]
-    double* damp_partial;     // [grid_pts]
-    PcgState* pcg;
-    TrialScalars* scal;
+    double* red_partial;      // [4][dc_pp.nblk] back-substitution sums
+    double* cost_partial;     // [dc_edges.nblk]
+    double* damp_partial;     // [dc_pts.nblk]
 
     // launch geometry
-    int grid_pp;              // workgroups of the point passes (one partial each)
     int block_pp;             // threads per point-pass workgroup
-    int lds_pp;               // dynamic LDS bytes of the point passes
-    int grid_red;             // workgroups of the partial reduction
-    int grid_edges;           // workgroups of the per-edge passes
-    int grid_pts;             // workgroups of the per-point kernels
-};
-
-struct LaunchCtx {
-    hipStream_t stream;
+    int lds_pp;               // dynamic LDS bytes of the point passes (9 x max cameras of a problem)
+    int global_acc;           // 1: a problem's camera vector exceeds LDS; the point passes add
+                              // their camera sums into one global vector (FP64 atomics)
 };
 
 // ---- launchers (gba_kernels.hip) --------------------------------------
@@ -141,19 +179,38 @@ struct RawOut {
     double* w;   // [ne]
 };
 
+// Batch assembly on the device: copy (or fill) element ranges, adding a
+// constant to 32-bit indices.  One workgroup per PackChunk.
+enum PackKind { kPackI32 = 0, kPackF64 = 1, kPackU8 = 2, kPackFillI32 = 3, kPackFillF64 = 4 };
+struct PackDesc {
+    const void* src;   // unused by the fill kinds
+    void* dst;
+    long long n;       // elements
+    int add;           // kPackI32: added to every element; kPackFillI32: the value
+    int kind;          // PackKind
+    double fval;       // kPackFillF64: the value
+};
+constexpr int kPackChunk = 4096;  // elements per workgroup
+struct PackChunk {
+    int desc;
+    int begin;         // first element of this chunk
+};
+hipError_t launch_pack(const PackDesc* desc, const PackChunk* chunks, int n_chunks, hipStream_t s);
+
 hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw);
+hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_cost(const DeviceGraph& g, hipStream_t s, const double* cam, const double* pt);
-hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
-                       double max_diag);
-hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
-                          double max_diag, int block_jacobi);
+hipError_t launch_cost_finish(const DeviceGraph& g, hipStream_t s);
+hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag);
+hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
+                          int block_jacobi);
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int relative);
-hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
-                           double max_diag, int max_iters, double reject_ratio,
-                           hipEvent_t ev_mv0, hipEvent_t ev_mv1);
+hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
+                           int max_iters, double reject_ratio, hipEvent_t ev_mv0,
+                           hipEvent_t ev_mv1);
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_finish(const DeviceGraph& g, hipStream_t s);
-hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s);
+hipError_t launch_commit(const DeviceGraph& g, hipStream_t s);
 
 }  // namespace gba

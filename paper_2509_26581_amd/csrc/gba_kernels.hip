@@ -143,9 +143,11 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
 __global__ __launch_bounds__(256) void k_cost(DeviceGraph g, const double* __restrict__ cam,
                                               const double* __restrict__ pt) {
     __shared__ double red[16];
+    int eb, ee;
+    decomp_block(g.dc_edges, blockIdx.x, eb, ee);
     double acc = 0.0;
     const int ne = g.ne;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+    for (int e = eb + (int)threadIdx.x; e < ee; e += blockDim.x) {
         const int i = g.e_cam[e], j = g.e_pt[e];
         EdgeEval<double> ev;
         bal_eval<double, false>(cam + 9 * i, pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
@@ -159,17 +161,19 @@ __global__ __launch_bounds__(256) void k_cost(DeviceGraph g, const double* __res
 
 // ==========================================================================
 // Point blocks: Hpp_lambda = Hpp + lambda diag(clamp(diag Hpp)) (Eq. 4-6 with
-// the clamped diagonal), inverted in FP64 by Cholesky; fixed points get a
-// zero inverse (no unknowns).  Also initialises the candidate points and
+// the clamped diagonal, lambda of the point's problem), inverted in FP64 by
+// Cholesky; fixed points get a zero inverse (no unknowns).  Also initialises the candidate points and
 // the |x|^2 partial sums over free points.
 // ==========================================================================
 template <typename T>
-__global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double lambda, double min_diag,
-                                                     double max_diag) {
+__global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_diag, double max_diag) {
     __shared__ double red[16];
+    int pb, pe;
+    const int prob = decomp_block(g.dc_pts, blockIdx.x, pb, pe);
+    const double lambda = fabs(g.lam[prob]);   // negative: problem idle this trial
     const T* Hpp = (const T*)g.hpp;
     double x2 = 0.0;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.np; j += gridDim.x * blockDim.x) {
+    for (int j = pb + (int)threadIdx.x; j < pe; j += blockDim.x) {
         const bool fixed = g.pt_fixed[j] != 0;
         double A[3][3];
 #pragma unroll
@@ -312,10 +316,11 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 // sum W Hpp^-1 W^T and stores M_i^{-1} (FP64 Cholesky); the identity
 // preconditioner stores I; fixed cameras store 0.
 template <typename T, int kMode>
-__global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double lambda, double min_diag,
-                                                     double max_diag, int block_jacobi) {
+__global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_diag, double max_diag,
+                                                     int block_jacobi) {
     __shared__ double Ms[54];
     const int i = blockIdx.x;
+    const double lambda = kMode == kPrecond ? fabs(g.lam[g.cam_prob[i]]) : 0.0;
     const int k = threadIdx.x;
     const int c0 = g.cam_chunk_off[i], c1 = g.cam_chunk_off[i + 1];
     T* Hcc = (T*)g.hcc;
@@ -385,7 +390,7 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double lambd
 enum { kRhs = 0, kMatvec = 1, kBacksub = 2 };
 
 template <typename VT, typename JS, typename AT, int kMode>
-__global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __restrict__ Jc,
+__global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const JS* __restrict__ Jc,
                                                      const JS* __restrict__ Jp,
                                                      const VT* __restrict__ vin, AT* __restrict__ out) {
     // Arithmetic in FP64 whatever the storage type: the product chain
@@ -396,16 +401,17 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
     extern __shared__ __align__(16) unsigned char smem_raw[];
     AT* acc_lds = (AT*)smem_raw;
     __shared__ double red[16];
-    if (kMode == kMatvec && g.pcg->done) return;   // PCG already converged
+    int tb, te;
+    const int prob = decomp_block(g.dc_pp, blockIdx.x, tb, te);
+    if (kMode == kMatvec && g.pcg[prob].done) return;   // PCG of this problem converged
     const int l = lane_id();
-    const int nc9 = 9 * g.nc;
-    if (kMode != kBacksub) {
+    const int c0 = g.prob_cam_off[prob];
+    const int nc9 = 9 * (g.prob_cam_off[prob + 1] - c0);   // this problem's camera components
+    const bool gacc = g.global_acc != 0;   // camera sums straight to the global vector
+    if (kMode != kBacksub && !gacc) {
         for (int k = threadIdx.x; k < nc9; k += blockDim.x) acc_lds[k] = 0;
         __syncthreads();
     }
-    // contiguous tile range of this workgroup, wavefronts interleaved
-    const int tb = (int)(((long long)g.n_tiles * blockIdx.x) / gridDim.x);
-    const int te = (int)(((long long)g.n_tiles * (blockIdx.x + 1)) / gridDim.x);
     const int nw = blockDim.x >> 6;
     const int ne = g.ne;
     const VT* bp = (const VT*)g.bp;
@@ -504,9 +510,15 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
             } else if (valid) {
                 const T u0 = jp[0][0] * z[0] + jp[0][1] * z[1] + jp[0][2] * z[2];
                 const T u1 = jp[1][0] * z[0] + jp[1][1] * z[1] + jp[1][2] * z[2];
+                if (gacc) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    atomicAdd(&acc_lds[9 * i + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
+                    for (int k = 0; k < 9; ++k)
+                        unsafeAtomicAdd(&out[9 * i + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k)
+                        atomicAdd(&acc_lds[9 * (i - c0) + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
+                }
             }
         } else {
             // a single point with more than 64 edges: two sweeps over chunks
@@ -520,9 +532,9 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                 z[2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
             } else {
                 T tt[3] = {0, 0, 0};
-                for (int c0 = 0; c0 < n; c0 += kWave) {
-                    if (c0 + l < n) {
-                        const int e = e0 + c0 + l;
+                for (int ch = 0; ch < n; ch += kWave) {
+                    if (ch + l < n) {
+                        const int e = e0 + ch + l;
                         const int i = g.e_cam[e];
                         T a0 = 0, a1 = 0;
 #pragma unroll
@@ -566,9 +578,9 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                     }
                 }
             }
-            for (int c0 = 0; c0 < n; c0 += kWave) {
-                if (c0 + l < n) {
-                    const int e = e0 + c0 + l;
+            for (int ch = 0; ch < n; ch += kWave) {
+                if (ch + l < n) {
+                    const int e = e0 + ch + l;
                     const int i = g.e_cam[e];
                     T u0 = 0, u1 = 0;
 #pragma unroll
@@ -586,10 +598,14 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
                         red_m += (double)u0 * (double)u0 + (double)u1 * (double)u1;
                     } else {
 #pragma unroll
-                        for (int k = 0; k < 9; ++k)
-                            atomicAdd(&acc_lds[9 * i + k],
-                                      (AT)(load_as<T>(Jc[k * ne + e]) * u0 +
-                                           load_as<T>(Jc[(9 + k) * ne + e]) * u1));
+                        for (int k = 0; k < 9; ++k) {
+                            const AT v = (AT)(load_as<T>(Jc[k * ne + e]) * u0 +
+                                              load_as<T>(Jc[(9 + k) * ne + e]) * u1);
+                            if (gacc)
+                                unsafeAtomicAdd(&out[9 * i + k], v);
+                            else
+                                atomicAdd(&acc_lds[9 * (i - c0) + k], v);
+                        }
                     }
                 }
             }
@@ -607,64 +623,69 @@ __global__ __launch_bounds__(1024) void k_point_pass(DeviceGraph g, const JS* __
         }
         return;
     }
+    if (gacc) return;
     __syncthreads();
-    AT* dst = out + (size_t)blockIdx.x * nc9;
+    AT* dst = out + g.pp_part_off[blockIdx.x];
     for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = acc_lds[k];
 }
 
 // ==========================================================================
-// Sum of the per-workgroup camera partials.
+// Sum of the per-workgroup camera partials of each problem.
 //   kRhs:    r = -bc + sum                              (reduced RHS)
 //   kMatvec: q = Hcc_lambda p - sum, and partial dots p^T q (FP64)
-// Workgroup: 64 components x 16 partial groups.
+// Workgroup: up to 64 components of one problem x 16 partial groups.
 // ==========================================================================
-template <typename T, typename AT, int kMode>
-__global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __restrict__ part,
-                                                 double lambda, double min_diag, double max_diag) {
+template <typename T, int kMode>
+__global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag, double max_diag) {
     __shared__ double red[16][64];
     __shared__ double dred[16];
-    if (kMode == kMatvec && g.pcg->done) return;   // PCG already converged
+    int kb, ke;
+    const int prob = decomp_block(g.dc_red, blockIdx.x, kb, ke);
+    if (kMode == kMatvec && g.pcg[prob].done) return;   // PCG of this problem converged
     const int cl = threadIdx.x & 63;
     const int grp = threadIdx.x >> 6;
-    const int nc9 = 9 * g.nc;
-    const int k = blockIdx.x * 64 + cl;
+    const int k = kb + cl;
+    const int kl = k - 9 * g.prob_cam_off[prob];          // component within the problem
+    const int q0 = g.dc_pp.prob_blk[prob];
+    // global accumulation: all workgroups of the problem share one vector
+    const int q1 = g.global_acc ? min(q0 + 1, g.dc_pp.prob_blk[prob + 1]) : g.dc_pp.prob_blk[prob + 1];
+    const double* part = g.cam_partial;
     double s = 0.0;
-    if (k < nc9) {
+    if (k < ke) {
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int b = grp;
-        for (; b + 48 < g.grid_pp; b += 64) {
-            s += (double)part[(size_t)b * nc9 + k];
-            s1 += (double)part[(size_t)(b + 16) * nc9 + k];
-            s2 += (double)part[(size_t)(b + 32) * nc9 + k];
-            s3 += (double)part[(size_t)(b + 48) * nc9 + k];
+        int q = q0 + grp;
+        for (; q + 48 < q1; q += 64) {
+            s += part[g.pp_part_off[q] + kl];
+            s1 += part[g.pp_part_off[q + 16] + kl];
+            s2 += part[g.pp_part_off[q + 32] + kl];
+            s3 += part[g.pp_part_off[q + 48] + kl];
         }
-        for (; b < g.grid_pp; b += 16) s += (double)part[(size_t)b * nc9 + k];
+        for (; q < q1; q += 16) s += part[g.pp_part_off[q] + kl];
         s += (s1 + s2) + s3;
     }
     red[grp][cl] = s;
     __syncthreads();
     double dot = 0.0;
-    if (grp == 0) {
+    if (grp == 0 && k < ke) {
         double tot = 0.0;
         for (int q = 0; q < 16; ++q) tot += red[q][cl];
-        if (k < nc9) {
-            const int i = k / 9, r = k % 9;
-            if (kMode == kRhs) {
-                const T* bc = (const T*)g.bc;
-                ((T*)g.v_r)[k] = (T)(-(double)bc[k] + tot);
-            } else {
-                const T* Hcc = (const T*)g.hcc;
-                const T* p = (const T*)g.v_p;
-                double hp = 0.0;
-                for (int c = 0; c < 9; ++c) {
-                    double h = (double)Hcc[i * 45 + sym9(r, c)];
-                    if (c == r) h += lambda * fmin(fmax(h, min_diag), max_diag);
-                    hp += h * (double)p[9 * i + c];
-                }
-                const double q = hp - tot;
-                ((T*)g.v_q)[k] = (T)q;
-                dot = (double)p[k] * (double)(T)q;
+        const int i = k / 9, r = k % 9;
+        if (kMode == kRhs) {
+            const T* bc = (const T*)g.bc;
+            ((T*)g.v_r)[k] = (T)(-(double)bc[k] + tot);
+        } else {
+            const double lambda = fabs(g.lam[prob]);   // negative: problem idle this trial
+            const T* Hcc = (const T*)g.hcc;
+            const T* p = (const T*)g.v_p;
+            double hp = 0.0;
+            for (int c = 0; c < 9; ++c) {
+                double h = (double)Hcc[i * 45 + sym9(r, c)];
+                if (c == r) h += lambda * fmin(fmax(h, min_diag), max_diag);
+                hp += h * (double)p[9 * i + c];
             }
+            const double q = hp - tot;
+            ((T*)g.v_q)[k] = (T)q;
+            dot = (double)p[k] * (double)(T)q;
         }
     }
     if (kMode == kMatvec) {
@@ -674,13 +695,12 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, const AT* __rest
 }
 
 // ==========================================================================
-// PCG on the reduced camera system, dots in FP64, scalar state in PcgState.
+// PCG on the reduced camera system of every problem, dots in FP64, scalar
+// state per problem in PcgState.  The vector kernels use camera-aligned
+// workgroups inside one problem (coalesced accesses; the 9x9 preconditioner
+// block is applied from LDS); the scalar kernels are single-workgroup, one
+// wavefront per problem at a time.
 // ==========================================================================
-// Camera-aligned PCG vector kernels: a workgroup owns kCamsPerBlock whole
-// cameras (9 consecutive components each), so every global access is
-// coalesced and the 9x9 preconditioner block is applied from LDS.
-constexpr int kCamsPerBlock = 28;                 // 252 components per workgroup
-constexpr int kPcgBlock = 256;
 
 // z = M^{-1} r for this workgroup's cameras; r_lds holds r of those cameras.
 template <typename T>
@@ -692,14 +712,25 @@ __device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds
     return (T)s;
 }
 
-// PCG start: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
+// Sum of part[stride * q + off] over the workgroups q of a problem, by one
+// wavefront (every lane gets the result).
+__device__ __forceinline__ double wave_sum_blocks(const double* part, int stride, int off, int q0,
+                                                  int q1) {
+    double s = 0.0;
+    for (int q = q0 + lane_id(); q < q1; q += kWave) s += part[stride * q + off];
+    return wave_sum(s);
+}
+
+// PCG start, vectors: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
     __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
+    int cb, ce;
+    decomp_block(g.dc_cam, blockIdx.x, cb, ce);
     const int tid = threadIdx.x;
-    const int k = blockIdx.x * (9 * kCamsPerBlock) + tid;
-    const bool valid = tid < 9 * kCamsPerBlock && k < 9 * g.nc;
+    const int k = 9 * cb + tid;
+    const bool valid = tid < 9 * (ce - cb);
     const T* __restrict__ r = (const T*)g.v_r;
     T rv = valid ? r[k] : (T)0;
     r_lds[tid] = rv;
@@ -721,32 +752,29 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
     }
 }
 
-// PCG start, scalars (single workgroup): rz0, rr0, threshold; p = z.
+// PCG start, scalars: rz0, rr0, threshold per problem; p = z.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, int nblk, double tol,
-                                                           int relative) {
-    __shared__ double red[16];
-    double rz = 0.0, rr = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        rz += g.dot_partial[2 * b];
-        rr += g.dot_partial[2 * b + 1];
+__global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double tol, int relative) {
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int prob = w; prob < g.n_probs; prob += nw) {
+        const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
+        const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
+        const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+        if (lane_id() == 0) {
+            PcgState* st = g.pcg + prob;
+            st->rz = rz;
+            st->rr = rr;
+            st->rr0 = rr;
+            st->min_rr = rr;
+            st->thresh = relative ? tol * tol * rr : tol * tol;
+            st->iters = 0;
+            st->use_best = 0;
+            st->done = g.lam[prob] < 0.0 ? 5 : ((rr <= st->thresh || !(rz > 0.0)) ? 1 : 0);
+        }
     }
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
     const T* __restrict__ z = (const T*)g.v_z;
     T* __restrict__ p = (T*)g.v_p;
     for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) p[k] = z[k];
-    if (threadIdx.x == 0) {
-        PcgState* st = g.pcg;
-        st->rz = rz;
-        st->rr = rr;
-        st->rr0 = rr;
-        st->min_rr = rr;
-        st->thresh = relative ? tol * tol * rr : tol * tol;
-        st->iters = 0;
-        st->use_best = 0;
-        st->done = (rr <= st->thresh || !(rz > 0.0)) ? 1 : 0;
-    }
 }
 
 // PCG step, vectors: alpha = r^T z / p^T q; x += alpha p; r -= alpha q;
@@ -755,16 +783,20 @@ template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
-    const PcgState* st = g.pcg;
+    int cb, ce;
+    const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
+    const PcgState* st = g.pcg + prob;
     if (st->done) return;
     double pq = 0.0;
-    for (int b = threadIdx.x; b < g.grid_red; b += blockDim.x) pq += g.pq_partial[b];
+    for (int b = g.dc_red.prob_blk[prob] + threadIdx.x; b < g.dc_red.prob_blk[prob + 1];
+         b += blockDim.x)
+        pq += g.pq_partial[b];
     pq = block_sum(pq, red);
-    if (!(pq > 0.0) || !isfinite(pq)) return;   // breakdown: the finisher stops PCG
+    if (!(pq > 0.0) || !isfinite(pq)) return;   // breakdown: the finisher stops this PCG
     const double alpha = st->rz / pq;
     const int tid = threadIdx.x;
-    const int k = blockIdx.x * (9 * kCamsPerBlock) + tid;
-    const bool valid = tid < 9 * kCamsPerBlock && k < 9 * g.nc;
+    const int k = 9 * cb + tid;
+    const bool valid = tid < 9 * (ce - cb);
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ r = (T*)g.v_r;
     T rv = 0;
@@ -793,131 +825,164 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     }
 }
 
-// PCG step, scalars (single workgroup): convergence / iteration limit /
-// rejection ratio / breakdown, beta = r^T z / (r^T z)_old, p = z + beta p,
-// and the best-iterate copy when the rejection ratio is enabled.
+// PCG step, scalars (single workgroup): per running problem convergence /
+// iteration limit / rejection ratio / breakdown, beta = r^T z / (r^T z)_old;
+// then p = z + beta p, and the best-iterate copy when the rejection ratio is
+// enabled, for the cameras of problems still running.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int nblk, int max_iters,
-                                                     double ratio) {
-    __shared__ double red[16];
-    __shared__ int s_done, s_copy_best;
-    PcgState* st = g.pcg;
-    if (st->done) return;
-    double pq = 0.0, rz = 0.0, rr = 0.0;
-    for (int b = threadIdx.x; b < g.grid_red; b += blockDim.x) pq += g.pq_partial[b];
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        rz += g.dot_partial[2 * b];
-        rr += g.dot_partial[2 * b + 1];
-    }
-    pq = block_sum(pq, red);
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
-    const double rz_old = st->rz;
-    if (threadIdx.x == 0) {
-        int done = 0, copy_best = 0;
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            done = 3;
-        } else {
-            st->iters += 1;
-            st->rr = rr;
-            const bool track = ratio > 0.0 && isfinite(ratio);
-            if (track && rr < st->min_rr) {
-                st->min_rr = rr;
-                copy_best = 1;
-            } else if (track && rr > ratio * ratio * st->min_rr) {
-                done = 4;
-            }
-            if (!done && rr <= st->thresh) done = 1;
-            if (!done && st->iters >= max_iters) done = 2;
+__global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iters, double ratio) {
+    __shared__ double s_beta[kMaxProblems];
+    __shared__ unsigned char s_act[kMaxProblems];   // bit0 update p, bit1 copy best, bit2 restore best
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int prob = w; prob < g.n_probs; prob += nw) {
+        PcgState* st = g.pcg + prob;
+        if (st->done) {
+            if (lane_id() == 0) s_act[prob] = 0;
+            continue;
         }
-        s_done = done;
-        s_copy_best = copy_best;
+        const double pq = wave_sum_blocks(g.pq_partial, 1, 0, g.dc_red.prob_blk[prob],
+                                          g.dc_red.prob_blk[prob + 1]);
+        const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
+        const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
+        const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+        if (lane_id() == 0) {
+            int done = 0, copy_best = 0;
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                done = 3;
+            } else {
+                st->iters += 1;
+                st->rr = rr;
+                const bool track = ratio > 0.0 && isfinite(ratio);
+                if (track && rr < st->min_rr) {
+                    st->min_rr = rr;
+                    copy_best = 1;
+                } else if (track && rr > ratio * ratio * st->min_rr) {
+                    done = 4;
+                }
+                if (!done && rr <= st->thresh) done = 1;
+                if (!done && st->iters >= max_iters) done = 2;
+            }
+            const double rz_old = st->rz;
+            s_beta[prob] = (rz_old > 0.0) ? rz / rz_old : 0.0;
+            s_act[prob] = (unsigned char)((done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0));
+            if (copy_best) st->use_best = 1;
+            if (done != 3) st->rz = rz;
+            st->done = done;
+        }
     }
     __syncthreads();
-    const int done = s_done;
-    const int copy_best = s_copy_best;
-    const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ p = (T*)g.v_p;
     const T* __restrict__ z = (const T*)g.v_z;
     T* __restrict__ best = (T*)g.v_best;
     for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
-        if (done == 0) p[k] = (T)((double)z[k] + beta * (double)p[k]);
-        if (copy_best) best[k] = x[k];
-        if (done == 4) x[k] = best[k];
-    }
-    if (threadIdx.x == 0) {
-        if (copy_best) st->use_best = 1;
-        if (done != 3) st->rz = rz;
-        st->done = done;
+        const int prob = g.cam_prob[k / 9];
+        const int act = s_act[prob];
+        if (!act) continue;
+        if (act & 1) p[k] = (T)((double)z[k] + s_beta[prob] * (double)p[k]);
+        if (act & 2) best[k] = x[k];
+        if (act & 4) x[k] = best[k];
     }
 }
 
 // ==========================================================================
-// Cameras after PCG: dc = x, candidate cameras, bc^T dc, |dc|^2, |c|^2 over
-// free cameras (single workgroup).
+// Cameras after PCG: dc = x, candidate cameras; partial b^T dc, |dc|^2 and
+// |c|^2 over free cameras per camera-aligned workgroup.
 // ==========================================================================
 template <typename T>
-__global__ __launch_bounds__(1024) void k_cam_update(DeviceGraph g) {
+__global__ __launch_bounds__(kPcgBlock) void k_cam_update(DeviceGraph g) {
     __shared__ double red[16];
+    int cb, ce;
+    decomp_block(g.dc_cam, blockIdx.x, cb, ce);
     const T* x = (const T*)g.v_x;
     const T* bc = (const T*)g.bc;
     double bdx = 0.0, s2 = 0.0, x2 = 0.0;
-    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
+    const int tid = threadIdx.x;
+    if (tid < 9 * (ce - cb)) {
+        const int k = 9 * cb + tid;
         const int i = k / 9;
         const bool fixed = g.cam_fixed[i] != 0;
         const double d = fixed ? 0.0 : (double)x[k];
         const double c = g.cam[k];
         g.cam_c[k] = c + d;
-        bdx += (double)bc[k] * d;
-        s2 += d * d;
-        if (!fixed) x2 += c * c;
+        bdx = (double)bc[k] * d;
+        s2 = d * d;
+        if (!fixed) x2 = c * c;
     }
     bdx = block_sum(bdx, red);
     s2 = block_sum(s2, red);
     x2 = block_sum(x2, red);
-    if (threadIdx.x == 0) {
-        g.scal->b_dot_dx = bdx;
-        g.scal->step2 = s2;
-        g.scal->x2 = x2;
+    if (tid == 0) {
+        g.camupd_partial[3 * blockIdx.x] = bdx;
+        g.camupd_partial[3 * blockIdx.x + 1] = s2;
+        g.camupd_partial[3 * blockIdx.x + 2] = x2;
     }
 }
 
-// Combine the per-workgroup partial sums of the trial (single workgroup).
+// Combine the per-workgroup partial sums of the trial, per problem (single
+// workgroup, one wavefront per problem at a time).
 __global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
-    __shared__ double red[16];
-    double c = 0.0, m = 0.0, b = 0.0, s = 0.0, x = 0.0;
-    for (int k = threadIdx.x; k < g.grid_edges; k += blockDim.x) c += g.cost_partial[k];
-    for (int k = threadIdx.x; k < g.grid_pp; k += blockDim.x) {
-        m += g.red_partial[4 * k + 0];
-        b += g.red_partial[4 * k + 1];
-        s += g.red_partial[4 * k + 2];
-    }
-    for (int k = threadIdx.x; k < g.grid_pts; k += blockDim.x) x += g.damp_partial[k];
-    c = block_sum(c, red);
-    m = block_sum(m, red);
-    b = block_sum(b, red);
-    s = block_sum(s, red);
-    x = block_sum(x, red);
-    if (threadIdx.x == 0) {
-        TrialScalars* t = g.scal;
-        t->cost = c;
-        t->quad = m;
-        t->b_dot_dx += b;
-        t->step2 += s;
-        t->x2 += x;
-        t->pcg_iters = g.pcg->iters;
-        t->pcg_reason = g.pcg->done;
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int prob = w; prob < g.n_probs; prob += nw) {
+        const int e0 = g.dc_edges.prob_blk[prob], e1 = g.dc_edges.prob_blk[prob + 1];
+        const int p0 = g.dc_pp.prob_blk[prob], p1 = g.dc_pp.prob_blk[prob + 1];
+        const int t0 = g.dc_pts.prob_blk[prob], t1 = g.dc_pts.prob_blk[prob + 1];
+        const int c0 = g.dc_cam.prob_blk[prob], c1 = g.dc_cam.prob_blk[prob + 1];
+        const double cost = wave_sum_blocks(g.cost_partial, 1, 0, e0, e1);
+        const double quad = wave_sum_blocks(g.red_partial, 4, 0, p0, p1);
+        const double bdp = wave_sum_blocks(g.red_partial, 4, 1, p0, p1);
+        const double sp = wave_sum_blocks(g.red_partial, 4, 2, p0, p1);
+        const double xp = wave_sum_blocks(g.damp_partial, 1, 0, t0, t1);
+        const double bdc = wave_sum_blocks(g.camupd_partial, 3, 0, c0, c1);
+        const double sc = wave_sum_blocks(g.camupd_partial, 3, 1, c0, c1);
+        const double xc = wave_sum_blocks(g.camupd_partial, 3, 2, c0, c1);
+        if (lane_id() == 0) {
+            TrialScalars* t = g.scal + prob;
+            t->cost = cost;
+            t->quad = quad;
+            t->b_dot_dx = bdc + bdp;
+            t->step2 = sc + sp;
+            t->x2 = xc + xp;
+            t->pcg_iters = g.pcg[prob].iters;
+            t->pcg_reason = g.pcg[prob].done;
+        }
     }
 }
 
-// cost only (no trial): combine cost partials into scal->cost
+// Cost only: combine the cost partials per problem.
 __global__ __launch_bounds__(1024) void k_cost_finish(DeviceGraph g) {
-    __shared__ double red[16];
-    double c = 0.0;
-    for (int k = threadIdx.x; k < g.grid_edges; k += blockDim.x) c += g.cost_partial[k];
-    c = block_sum(c, red);
-    if (threadIdx.x == 0) g.scal->cost = c;
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int prob = w; prob < g.n_probs; prob += nw) {
+        const double cost = wave_sum_blocks(g.cost_partial, 1, 0, g.dc_edges.prob_blk[prob],
+                                            g.dc_edges.prob_blk[prob + 1]);
+        if (lane_id() == 0) g.scal[prob].cost = cost;
+    }
+}
+
+// Accepted problems: the candidate parameters become the current ones.
+__global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < 9 * (size_t)g.nc; k += stride)
+        if (g.accept[g.cam_prob[k / 9]]) g.cam[k] = g.cam_c[k];
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < 3 * (size_t)g.np; k += stride)
+        if (g.accept[g.pt_prob[k / 3]]) g.pt[k] = g.pt_c[k];
+}
+
+// Batch assembly: one workgroup per chunk of one descriptor.
+__global__ __launch_bounds__(256) void k_pack(const PackDesc* __restrict__ desc,
+                                              const PackChunk* __restrict__ chunks) {
+    const PackChunk c = chunks[blockIdx.x];
+    const PackDesc d = desc[c.desc];
+    const long long end = d.n < (long long)c.begin + kPackChunk ? d.n : (long long)c.begin + kPackChunk;
+    for (long long k = c.begin + threadIdx.x; k < end; k += blockDim.x) {
+        switch (d.kind) {
+            case kPackI32: ((int*)d.dst)[k] = ((const int*)d.src)[k] + d.add; break;
+            case kPackF64: ((double*)d.dst)[k] = ((const double*)d.src)[k]; break;
+            case kPackU8: ((unsigned char*)d.dst)[k] = ((const unsigned char*)d.src)[k]; break;
+            case kPackFillI32: ((int*)d.dst)[k] = d.add; break;
+            default: ((double*)d.dst)[k] = d.fval; break;
+        }
+    }
 }
 
 template <typename T>
@@ -930,13 +995,8 @@ __global__ void k_fill(T* p, T v, size_t n) {
 // ==========================================================================
 // launchers
 // ==========================================================================
-template <typename F>
-static hipError_t dispatch(const DeviceGraph& g, F&& f) {
-    return f(g.mode);
-}
-
-#define GBA_CHECK_LAUNCH() \
-    do {                   \
+#define GBA_CHECK_LAUNCH()                 \
+    do {                                   \
         hipError_t e_ = hipGetLastError(); \
         if (e_ != hipSuccess) return e_;   \
     } while (0)
@@ -963,6 +1023,7 @@ hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* r
 }
 
 hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
+    if (g.nc == 0) return hipSuccess;
     if (g.n_chunks > 0) {
         if (g.mode == kModeFP64)
             hipLaunchKernelGGL((k_cam_accumulate<double, double, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
@@ -972,33 +1033,40 @@ hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
             hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
-    const int grid = g.nc;
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(grid), dim3(64), 0, s, g, 0.0, 0.0, 0.0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(grid), dim3(64), 0, s, g, 0.0, 0.0, 0.0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_cost(const DeviceGraph& g, hipStream_t s, const double* cam, const double* pt) {
-    hipLaunchKernelGGL(k_cost, dim3(g.grid_edges), dim3(256), 0, s, g, cam, pt);
+    if (g.dc_edges.nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cost, dim3(g.dc_edges.nblk), dim3(256), 0, s, g, cam, pt);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
-                       double max_diag) {
+hipError_t launch_cost_finish(const DeviceGraph& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_cost_finish, dim3(1), dim3(1024), 0, s, g);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag) {
+    if (g.dc_pts.nblk == 0) return hipSuccess;
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL(k_damp_points<double>, dim3(g.grid_pts), dim3(256), 0, s, g, lambda, min_diag, max_diag);
+        hipLaunchKernelGGL(k_damp_points<double>, dim3(g.dc_pts.nblk), dim3(256), 0, s, g, min_diag, max_diag);
     else
-        hipLaunchKernelGGL(k_damp_points<float>, dim3(g.grid_pts), dim3(256), 0, s, g, lambda, min_diag, max_diag);
+        hipLaunchKernelGGL(k_damp_points<float>, dim3(g.dc_pts.nblk), dim3(256), 0, s, g, min_diag, max_diag);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
-                          double max_diag, int block_jacobi) {
+hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
+                          int block_jacobi) {
+    if (g.nc == 0) return hipSuccess;
     if (block_jacobi && g.n_chunks > 0) {
         if (g.mode == kModeFP64)
             hipLaunchKernelGGL((k_cam_accumulate<double, double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
@@ -1006,11 +1074,10 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, do
             hipLaunchKernelGGL((k_cam_accumulate<float, float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
-    const int grid = g.nc;
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(grid), dim3(64), 0, s, g, lambda, min_diag, max_diag, block_jacobi);
+        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(grid), dim3(64), 0, s, g, lambda, min_diag, max_diag, block_jacobi);
+        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1018,6 +1085,7 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double lambda, do
 template <typename VT, typename JS, typename AT, int kMode>
 static void point_pass(const DeviceGraph& g, hipStream_t s, const void* jc, const void* jp,
                        const void* vin, void* out) {
+    if (g.dc_pp.nblk == 0) return;
     // allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per CU)
     static int lds_set = -1;
     if (kMode != kBacksub && g.lds_pp > 0 && lds_set < g.lds_pp) {
@@ -1025,49 +1093,53 @@ static void point_pass(const DeviceGraph& g, hipStream_t s, const void* jc, cons
                                   hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_pp);
         lds_set = g.lds_pp;
     }
-    hipLaunchKernelGGL((k_point_pass<VT, JS, AT, kMode>), dim3(g.grid_pp), dim3(g.block_pp),
+    hipLaunchKernelGGL((k_point_pass<VT, JS, AT, kMode>), dim3(g.dc_pp.nblk), dim3(g.block_pp),
                        kMode == kBacksub ? 0 : g.lds_pp, s, g, (const JS*)jc, (const JS*)jp,
                        (const VT*)vin, (AT*)out);
 }
 
+// Global accumulation: clear the shared camera vectors before a point pass.
+static void clear_global_acc(const DeviceGraph& g, hipStream_t s) {
+    if (g.global_acc)
+        hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, g.cam_partial, 0.0,
+                           (size_t)9 * g.nc);
+}
+
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
-    const int grid_red = (9 * g.nc + 63) / 64;
+    if (g.nc == 0) return hipSuccess;   // no cameras, hence no edges
+    clear_global_acc(g, s);
     if (g.mode == kModeFP64) {
         point_pass<double, double, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
-        hipLaunchKernelGGL((k_reduce<double, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
-                           (const double*)g.cam_partial, 0.0, 0.0, 0.0);
+        hipLaunchKernelGGL((k_reduce<double, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
     } else {
         if (g.mode == kModeFP32)
             point_pass<float, float, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
         else
             point_pass<float, bf16, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
-        hipLaunchKernelGGL((k_reduce<float, double, kRhs>), dim3(grid_red), dim3(1024), 0, s, g,
-                           (const double*)g.cam_partial, 0.0, 0.0, 0.0);
+        hipLaunchKernelGGL((k_reduce<float, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
-
-static int pcg_blocks(const DeviceGraph& g) { return (g.nc + kCamsPerBlock - 1) / kCamsPerBlock; }
 
 hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int relative) {
-    const int nb = pcg_blocks(g);
+    if (g.nc == 0) return hipSuccess;
     if (g.mode == kModeFP64) {
-        hipLaunchKernelGGL(k_pcg_start<double>, dim3(nb), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_start_finish<double>, dim3(1), dim3(1024), 0, s, g, nb, tol, relative);
+        hipLaunchKernelGGL(k_pcg_start<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_start_finish<double>, dim3(1), dim3(1024), 0, s, g, tol, relative);
     } else {
-        hipLaunchKernelGGL(k_pcg_start<float>, dim3(nb), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_start_finish<float>, dim3(1), dim3(1024), 0, s, g, nb, tol, relative);
+        hipLaunchKernelGGL(k_pcg_start<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_start_finish<float>, dim3(1), dim3(1024), 0, s, g, tol, relative);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, double min_diag,
-                           double max_diag, int max_iters, double ratio, hipEvent_t ev0,
-                           hipEvent_t ev1) {
-    const int grid_red = (9 * g.nc + 63) / 64;
+hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
+                           int max_iters, double ratio, hipEvent_t ev0, hipEvent_t ev1) {
+    if (g.nc == 0) return hipSuccess;
     if (ev0) (void)hipEventRecord(ev0, s);
+    clear_global_acc(g, s);
     if (g.mode == kModeFP64) {
         point_pass<double, double, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     } else if (g.mode == kModeFP32) {
@@ -1077,26 +1149,25 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double lambda, d
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     if (g.mode == kModeFP64) {
-        hipLaunchKernelGGL((k_reduce<double, double, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
-                           (const double*)g.cam_partial, lambda, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_apply<double>, dim3(pcg_blocks(g)), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_finish<double>, dim3(1), dim3(1024), 0, s, g, pcg_blocks(g), max_iters, ratio);
+        hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
+        hipLaunchKernelGGL(k_pcg_apply<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_finish<double>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
     } else {
-        hipLaunchKernelGGL((k_reduce<float, double, kMatvec>), dim3(grid_red), dim3(1024), 0, s, g,
-                           (const double*)g.cam_partial, lambda, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_apply<float>, dim3(pcg_blocks(g)), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_finish<float>, dim3(1), dim3(1024), 0, s, g, pcg_blocks(g), max_iters, ratio);
+        hipLaunchKernelGGL((k_reduce<float, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
+        hipLaunchKernelGGL(k_pcg_apply<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_finish<float>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s) {
+    if (g.nc == 0) return hipSuccess;
     if (g.mode == kModeFP64) {
-        hipLaunchKernelGGL(k_cam_update<double>, dim3(1), dim3(1024), 0, s, g);
+        hipLaunchKernelGGL(k_cam_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
         point_pass<double, double, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
     } else {
-        hipLaunchKernelGGL(k_cam_update<float>, dim3(1), dim3(1024), 0, s, g);
+        hipLaunchKernelGGL(k_cam_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
         if (g.mode == kModeFP32)
             point_pass<float, float, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
         else
@@ -1112,8 +1183,18 @@ hipError_t launch_finish(const DeviceGraph& g, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t launch_cost_finish(const DeviceGraph& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_cost_finish, dim3(1), dim3(1024), 0, s, g);
+hipError_t launch_pack(const PackDesc* desc, const PackChunk* chunks, int n_chunks, hipStream_t s) {
+    if (n_chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack, dim3(n_chunks), dim3(256), 0, s, desc, chunks);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_commit(const DeviceGraph& g, hipStream_t s) {
+    size_t n = 9 * (size_t)g.nc > 3 * (size_t)g.np ? 9 * (size_t)g.nc : 3 * (size_t)g.np;
+    int grid = (int)((n + 255) / 256);
+    grid = grid < 1 ? 1 : (grid > 2048 ? 2048 : grid);
+    hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, s, g);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }

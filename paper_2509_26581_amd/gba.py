@@ -18,11 +18,13 @@ LIB_PATH = os.environ.get("GBA_LIBRARY") or os.path.join(
 
 GBA_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "UNKNOWN_ID", -3: "DUPLICATE_ID", -4: "NONFINITE",
-          -5: "OOM", -6: "HIP", -7: "STATE", -8: "UNSUPPORTED"}
+          -5: "OOM", -6: "HIP", -7: "STATE", -8: "UNSUPPORTED", -9: "BUDGET"}
+GBA_PENDING = 1
 
 GBA_FP64, GBA_MIXED_FP32, GBA_MIXED_BF16 = 0, 1, 2
 GBA_LOSS_SQUARED, GBA_LOSS_HUBER = 0, 1
 GBA_PRECOND_IDENTITY, GBA_PRECOND_BLOCK_JACOBI = 0, 1
+GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_GLOBAL = 0, 1, 2
 TERMINATION = {0: "NONE", 1: "MAX_ITERS", 2: "COST_TOL", 3: "STEP_TOL",
                4: "LAMBDA_OVERFLOW", 5: "NUMERICAL_FAILURE", 6: "NO_WORK"}
 
@@ -38,7 +40,8 @@ class gba_options(ctypes.Structure):
                 ("max_diag", ctypes.c_double), ("pcg_max_iters", ctypes.c_int),
                 ("pcg_tol", ctypes.c_double), ("pcg_tol_relative", ctypes.c_int),
                 ("pcg_rejection_ratio", ctypes.c_double), ("precond", ctypes.c_int),
-                ("timing", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+                ("timing", ctypes.c_int), ("accumulation", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
 
 
 class gba_report(ctypes.Structure):
@@ -62,6 +65,46 @@ class gba_trial(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("model_decrease", ctypes.c_double),
                 ("step_norm", ctypes.c_double), ("accepted", ctypes.c_int),
                 ("pcg_iters", ctypes.c_int)]
+
+
+class gba_problem(ctypes.Structure):
+    _fields_ = [("n_cams", ctypes.c_int32), ("n_pts", ctypes.c_int32), ("n_edges", ctypes.c_int64),
+                ("cams", ctypes.c_void_p), ("pts", ctypes.c_void_p), ("cam_idx", ctypes.c_void_p),
+                ("pt_idx", ctypes.c_void_p), ("uv", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("cam_fixed", ctypes.c_void_p), ("pt_fixed", ctypes.c_void_p),
+                ("max_iters", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class gba_result(ctypes.Structure):
+    _fields_ = [("cams", ctypes.c_void_p), ("pts", ctypes.c_void_p), ("report", gba_report),
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("batch_peak", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class gba_server_config(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("device", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("loss", ctypes.c_int), ("delta", ctypes.c_double), ("options", gba_options),
+                ("tune_db", ctypes.c_char_p), ("tiles_per_block", ctypes.c_int),
+                ("edges_per_block", ctypes.c_int), ("pts_per_block", ctypes.c_int),
+                ("pcg_sync_every", ctypes.c_int), ("reserved", ctypes.c_int * 8)]
+
+
+class gba_serving_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("collected", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("trials_run", ctypes.c_int64),
+                ("repacks", ctypes.c_int64), ("mean_batch", ctypes.c_double),
+                ("p50_latency_ms", ctypes.c_double), ("p99_latency_ms", ctypes.c_double),
+                ("p50_service_ms", ctypes.c_double), ("p99_service_ms", ctypes.c_double),
+                ("solves_per_s", ctypes.c_double), ("bytes_in_use", ctypes.c_size_t),
+                ("bytes_peak", ctypes.c_size_t), ("budget", ctypes.c_size_t),
+                ("tiles_per_block", ctypes.c_int), ("edges_per_block", ctypes.c_int),
+                ("pts_per_block", ctypes.c_int), ("pcg_sync_every", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -98,6 +141,15 @@ _SIGS = {
     "gba_eval_step": (ctypes.c_int, [_P, ctypes.c_double, _D, _D, ctypes.POINTER(ctypes.c_int)]),
     "gba_last_error": (ctypes.c_char_p, [_P]),
     "gba_destroy": (None, [_P]),
+    "gba_server_default_config": (None, [ctypes.POINTER(gba_server_config)]),
+    "gba_server_create": (ctypes.c_int, [ctypes.POINTER(gba_server_config), ALLOC_FN, FREE_FN, _P,
+                                         ctypes.POINTER(_P)]),
+    "gba_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(gba_problem),
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "gba_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(gba_result)]),
+    "gba_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(gba_serving_stats)]),
+    "gba_server_last_error": (ctypes.c_char_p, [_P]),
+    "gba_server_destroy": (None, [_P]),
 }
 
 
@@ -379,3 +431,135 @@ def options(**kw):
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+# ------------------------------------------------------------------ serving
+def gba_server_default_config():
+    c = gba_server_config()
+    load().gba_server_default_config(ctypes.byref(c))
+    return c
+
+
+def _check_s(s, status):
+    if status != GBA_OK:
+        msg = load().gba_server_last_error(s)
+        raise GbaError(status, msg.decode() if msg else "")
+
+
+def gba_server_create(cfg, allocator=None):
+    lib = load()
+    h = _P()
+    a = allocator.alloc if allocator else ALLOC_FN(0)
+    f = allocator.free if allocator else FREE_FN(0)
+    st = lib.gba_server_create(ctypes.byref(cfg), a, f, None, ctypes.byref(h))
+    if st != GBA_OK:
+        raise GbaError(st, "gba_server_create failed")
+    return h
+
+
+def gba_server_submit(s, req):
+    """req: dict with cams [nc,9], pts [np,3], cam_idx, pt_idx, uv [ne,2] and
+    optional info [ne,3], cam_fixed, pt_fixed, max_iters, tol."""
+    keep = {
+        "cams": _arr(req["cams"], np.float64, (9,)),
+        "pts": _arr(req["pts"], np.float64, (3,)),
+        "cam_idx": _arr(req["cam_idx"], np.int32),
+        "pt_idx": _arr(req["pt_idx"], np.int32),
+        "uv": _arr(req["uv"], np.float64, (2,)),
+    }
+    if req.get("info") is not None:
+        keep["info"] = _arr(req["info"], np.float64, (3,))
+    for k in ("cam_fixed", "pt_fixed"):
+        if req.get(k) is not None:
+            keep[k] = _arr(np.asarray(req[k]).astype(bool), np.uint8)
+    p = gba_problem()
+    p.n_cams, p.n_pts, p.n_edges = len(keep["cams"]), len(keep["pts"]), len(keep["cam_idx"])
+    for k, v in keep.items():
+        setattr(p, k, v.ctypes.data)
+    p.max_iters = int(req.get("max_iters", 10))
+    p.tol = float(req.get("tol", 0.0))
+    t = ctypes.c_uint64()
+    _check_s(s, load().gba_server_submit(s, ctypes.byref(p), ctypes.byref(t)))
+    return t.value
+
+
+def gba_server_poll(s, ticket, n_cams, n_pts, wait=True):
+    """Returns None while pending (wait=False), else a dict with the result."""
+    cams = np.empty((n_cams, 9))
+    pts = np.empty((n_pts, 3))
+    r = gba_result()
+    r.cams = cams.ctypes.data
+    r.pts = pts.ctypes.data
+    st = load().gba_server_poll(s, ctypes.c_uint64(ticket), 1 if wait else 0, ctypes.byref(r))
+    if st == GBA_PENDING:
+        return None
+    _check_s(s, st)
+    return {"cams": cams, "pts": pts, "report": r.report.as_dict(), "latency_ms": r.latency_ms,
+            "queue_ms": r.queue_ms, "batch_peak": r.batch_peak}
+
+
+def gba_server_stats(s):
+    st = gba_serving_stats()
+    _check_s(s, load().gba_server_stats(s, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def gba_server_last_error(s):
+    m = load().gba_server_last_error(s)
+    return m.decode() if m else ""
+
+
+def gba_server_destroy(s):
+    if s:
+        load().gba_server_destroy(s)
+
+
+class Server:
+    """Owns one gba_server handle (marshalling only)."""
+
+    def __init__(self, precision=GBA_MIXED_FP32, budget_bytes=4 << 30, max_slots=64,
+                 loss=GBA_LOSS_HUBER, delta=1.0, tune_db=None, device=0, **overrides):
+        cfg = gba_server_default_config()
+        cfg.precision = precision
+        cfg.device = device
+        cfg.hbm_budget_bytes = int(budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.loss = loss
+        cfg.delta = float(delta)
+        self._db = tune_db.encode() if tune_db else None
+        cfg.tune_db = self._db
+        for k, v in overrides.items():
+            if hasattr(cfg.options, k):
+                setattr(cfg.options, k, v)
+            elif hasattr(cfg, k):
+                setattr(cfg, k, v)
+            else:
+                raise KeyError(k)
+        self.h = gba_server_create(cfg)
+        self.sizes = {}
+
+    def submit(self, req):
+        t = gba_server_submit(self.h, req)
+        self.sizes[t] = (len(req["cams"]), len(req["pts"]))
+        return t
+
+    def poll(self, ticket, wait=True):
+        nc, np_ = self.sizes[ticket]
+        r = gba_server_poll(self.h, ticket, nc, np_, wait)
+        if r is not None:
+            del self.sizes[ticket]
+        return r
+
+    def stats(self):
+        return gba_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            gba_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,6 +15,7 @@ Workloads (sizes as in the benchmark configurations):
   small   10 cameras on a ring, 500 points, tracks U{3..8}      (~2.75k obs)
   bal1m   1,000 cameras on a sphere, 200k points, tracks 2+Geom(1/4)  (~1.0M)
   bal8m   10,000 cameras, 1M points, tracks 2+Geom(1/7)          (~8M obs)
+  bal8m_proxy  1,000 cameras, 100k points, tracks 2+Geom(1/7)    (~0.8M obs)
 Points are uniform in the box [-5, 5]^3; cameras sit at distance 20-30
 (sphere) or 25 (ring) looking at the origin, so every point is in front of
 every camera at depth >= 10 and random visibility is geometrically valid.
@@ -37,6 +38,11 @@ WORKLOADS = {
     "bal8m": dict(n_cams=10_000, n_pts=1_000_000, layout="sphere",
                   track=("geometric", 1.0 / 7.0), loss=HUBER, delta=1.0,
                   trials=15, pcg_max_iters=100, pcg_tol=1e-6),
+    # one tenth of bal8m in cameras and points (same track law): the size at
+    # which the CPU checker can still solve the at-scale configuration
+    "bal8m_proxy": dict(n_cams=1_000, n_pts=100_000, layout="sphere",
+                        track=("geometric", 1.0 / 7.0), loss=HUBER, delta=1.0,
+                        trials=15, pcg_max_iters=100, pcg_tol=1e-6),
 }
 
 
@@ -167,3 +173,71 @@ def make_scene(workload="small", seed=0, noise_px=1.0, perturb=True, **over):
                  dict(workload=workload if isinstance(workload, str) else "custom",
                       seed=seed, min_depth=float(-depth.max()) if len(depth) else 0.0,
                       noise_px=noise_px))
+
+
+# ------------------------------------------------------------ local-BA stream
+LOCAL = dict(k_range=(5, 40), np_range=(500, 20_000), track_max=10, window_extra=4,
+             arc_per_keyframe=0.03, trials=10)
+
+
+def make_local_request(seed, noise_px=1.0, perturb=True, **over):
+    """One local bundle-adjustment request (a sliding-window problem):
+    K = round(logU[5, 40]) keyframes along an arc of radius 25 around the
+    point box, Np = round(logU[500, 20k]) points, each seen by
+    L ~ U{2..min(10, K)} distinct keyframes inside a window of L + 4
+    consecutive keyframes; the first two keyframes are fixed (gauge).
+    Returns a dict of request arrays (dense indices, shuffled edges)."""
+    cfg = dict(LOCAL)
+    cfg.update(over)
+    rng = np.random.default_rng(seed)
+    lo, hi = cfg["k_range"]
+    K = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+    lo, hi = cfg["np_range"]
+    npt = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+    pts = rng.uniform(-5.0, 5.0, size=(npt, 3))
+    ang0 = rng.uniform(0, 2 * np.pi)
+    ang = ang0 + cfg["arc_per_keyframe"] * np.arange(K) + rng.uniform(-0.005, 0.005, K)
+    centers = np.stack([25 * np.cos(ang), 25 * np.sin(ang), rng.uniform(-2, 2, K)], axis=1)
+    R = _look_at(centers, rng.uniform(-0.1, 0.1, K))
+    t = -np.einsum("nij,nj->ni", R, centers)
+    f = rng.uniform(400.0, 600.0, K)
+    k1 = rng.uniform(-0.05, 0.05, K)
+    k2 = rng.uniform(-0.005, 0.005, K)
+    cams = np.concatenate([Rotation.from_matrix(R).as_rotvec(), t,
+                           f[:, None], k1[:, None], k2[:, None]], axis=1)
+    lengths = rng.integers(2, min(cfg["track_max"], K) + 1, size=npt)
+    width = np.minimum(lengths + cfg["window_extra"], K)
+    start = (rng.uniform(size=npt) * (K - width + 1)).astype(np.int64)
+    # L distinct window positions per point: the L smallest of random keys
+    # over the point's window
+    wmax = int(width.max())
+    keys = rng.uniform(size=(npt, wmax))
+    keys[np.arange(wmax)[None, :] >= width[:, None]] = np.inf
+    sel = np.argsort(keys, axis=1)[:, :int(lengths.max())]
+    mask = np.arange(sel.shape[1])[None, :] < lengths[:, None]
+    pt_idx = np.repeat(np.arange(npt), lengths)
+    cam_idx = (sel + start[:, None])[mask]
+    obs, _ = _measure(R[cam_idx], t[cam_idx], f[cam_idx], k1[cam_idx], k2[cam_idx],
+                      pts[pt_idx])
+    if noise_px:
+        obs = obs + rng.normal(0.0, noise_px, size=obs.shape)
+    perm = rng.permutation(len(cam_idx))
+    cam_idx, pt_idx, obs = cam_idx[perm], pt_idx[perm], obs[perm]
+    cams0, pts0 = cams.copy(), pts.copy()
+    fixed = np.zeros(K, bool)
+    fixed[:2] = True
+    if perturb:
+        free = ~fixed
+        cams0[free, 0:3] += rng.normal(0.0, 0.05, size=(int(free.sum()), 3))
+        cams0[free, 3:6] += rng.normal(0.0, 0.1, size=(int(free.sum()), 3))
+        pts0 += rng.normal(0.0, 0.1, size=pts.shape)
+    return {"cams": cams0, "pts": pts0, "cam_idx": cam_idx.astype(np.int32),
+            "pt_idx": pt_idx.astype(np.int32), "uv": obs, "cam_fixed": fixed,
+            "max_iters": int(cfg["trials"]), "tol": 0.0,
+            "cams_true": cams, "pts_true": pts, "seed": seed}
+
+
+def poisson_arrivals(n, rate_per_s, seed):
+    """Arrival times (s) of a Poisson stream: cumulative Exp(rate) gaps."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))

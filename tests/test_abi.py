@@ -58,7 +58,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"gba_options": gba.gba_options, "gba_report": gba.gba_report,
-               "gba_trial": gba.gba_trial}
+               "gba_trial": gba.gba_trial, "gba_problem": gba.gba_problem,
+               "gba_result": gba.gba_result, "gba_server_config": gba.gba_server_config,
+               "gba_serving_stats": gba.gba_serving_stats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gba.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -95,4 +97,19 @@ def test_create_without_a_gpu_returns_an_error_code():
     _ensure_built()
     with pytest.raises(gba.GbaError) as ei:
         gba.gba_create(gba.GBA_FP64, 0)
+    assert ei.value.status == -6
+
+
+def test_server_default_config_and_create_without_a_gpu():
+    _ensure_built()
+    c = gba.gba_server_default_config()
+    assert c.precision == gba.GBA_MIXED_FP32
+    assert c.max_slots == 64 and c.hbm_budget_bytes == 4 << 30
+    assert c.loss == gba.GBA_LOSS_HUBER and c.delta == 1.0
+    assert c.options.pcg_max_iters == 100
+    import torch
+    if torch.cuda.is_available():
+        return
+    with pytest.raises(gba.GbaError) as ei:
+        gba.gba_server_create(c)
     assert ei.value.status == -6
