@@ -150,6 +150,10 @@ def main():
     ap.add_argument("--trials", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--accumulation", type=int, default=0,
+                    help="camera sums of the point passes: 0 auto, 1 LDS partials, 2 global atomics")
+    ap.add_argument("--tiles-per-block", type=int, default=0,
+                    help="point tiles per point-pass workgroup (0: automatic)")
     ap.add_argument("--no-serve", action="store_true", help="skip the local-BA stream")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -196,7 +200,8 @@ def main():
           f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
     def timed_run(prec_id, timing):
         opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
-                           timing=1 if timing else 0)
+                           timing=1 if timing else 0, accumulation=args.accumulation,
+                           tiles_per_block=args.tiles_per_block)
         g = gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
                                   loss=sc.loss, delta=sc.delta, precision=prec_id,
                                   options=opts, use_torch=True)
@@ -256,7 +261,9 @@ def main():
         "config": {"workload": f"{args.workload}: {sc.n_cams} cameras, {sc.n_pts} points, "
                                f"{sc.n_obs} observations, Huber 1px, {trials} LM trials/step, "
                                f"PCG tol {sc.pcg_tol} max {sc.pcg_max_iters}",
-                   "precision": args.precision, "seed": 0},
+                   "precision": args.precision, "seed": 0,
+                   "accumulation": {0: "auto", 1: "lds", 2: "global"}[args.accumulation],
+                   "tiles_per_block": args.tiles_per_block or "auto"},
         "obs_per_s": round(sc.n_obs * lm_iters_s, 1),
         "pcg_iters_per_trial": round(sum(r.pcg_iters_total for r in reports) / max(total_trials, 1), 2),
         "final_cost": last.final_cost, "initial_cost": last.initial_cost,

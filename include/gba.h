@@ -121,7 +121,12 @@ typedef struct gba_options {
                                   GBA_ACC_LDS / GBA_ACC_GLOBAL force one
                                   (LDS fails with UNSUPPORTED when it does not
                                   fit).  Read when the device graph is built. */
-    int reserved[6];
+    int tiles_per_block;       /* point tiles (whole points, <= 64 edges) per
+                                  workgroup of the point passes; 0 (default):
+                                  max(16, n_tiles / n_CU).  Read when the device
+                                  graph is built; the server takes its sizes
+                                  from gba_server_config instead.             */
+    int reserved[5];
 } gba_options;
 
 #define GBA_ACC_AUTO 0

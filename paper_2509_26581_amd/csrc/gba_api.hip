@@ -334,13 +334,14 @@ gba_status gba_set_options(gba_graph* g, const gba_options* o) {
     if (!(o->initial_lambda > 0.0) || !(o->min_diag > 0.0) || !(o->max_diag >= o->min_diag) ||
         o->pcg_max_iters < 1 || !(o->pcg_tol >= 0.0) ||
         (o->precond != GBA_PRECOND_IDENTITY && o->precond != GBA_PRECOND_BLOCK_JACOBI) ||
-        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_GLOBAL)
+        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_GLOBAL || o->tiles_per_block < 0)
         return fail(g, GBA_ERR_INVALID_ARG, "invalid option value");
-    if (o->accumulation != g->tune.accumulation) {
-        // the accumulation scheme is part of the device graph's plan
+    if (o->accumulation != g->tune.accumulation || o->tiles_per_block != g->tune.tiles_per_block) {
+        // both are part of the device graph's plan
         gba_status st = sync_params_to_host(g);
         if (st != GBA_OK) return st;
         g->tune.accumulation = o->accumulation;
+        g->tune.tiles_per_block = o->tiles_per_block;
         g->dirty = true;
     }
     g->opts = *o;

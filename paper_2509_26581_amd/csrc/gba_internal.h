@@ -60,7 +60,8 @@ struct PcgState {
     int iters;
     int done;            // 0 running, 1 converged, 2 max iters, 3 breakdown, 4 rejected, 5 idle problem
     int use_best;
-    int pad;
+    int act;             // vector work of the last step: bit0 p = z + beta p, bit1 best = x, bit2 x = best
+    double beta;         // of the last step
 };
 
 // Problem-aligned work decomposition: workgroup b handles items

@@ -769,6 +769,8 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
             st->thresh = relative ? tol * tol * rr : tol * tol;
             st->iters = 0;
             st->use_best = 0;
+            st->act = 0;
+            st->beta = 0.0;
             st->done = g.lam[prob] < 0.0 ? 5 : ((rr <= st->thresh || !(rz > 0.0)) ? 1 : 0);
         }
     }
@@ -825,19 +827,16 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     }
 }
 
-// PCG step, scalars (single workgroup): per running problem convergence /
-// iteration limit / rejection ratio / breakdown, beta = r^T z / (r^T z)_old;
-// then p = z + beta p, and the best-iterate copy when the rejection ratio is
-// enabled, for the cameras of problems still running.
-template <typename T>
+// PCG step, scalars (single workgroup, one wavefront per problem): per
+// running problem convergence / iteration limit / rejection ratio /
+// breakdown, beta = r^T z / (r^T z)_old, and the vector work k_pcg_update
+// must do (PcgState::act, ::beta).
 __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iters, double ratio) {
-    __shared__ double s_beta[kMaxProblems];
-    __shared__ unsigned char s_act[kMaxProblems];   // bit0 update p, bit1 copy best, bit2 restore best
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int prob = w; prob < g.n_probs; prob += nw) {
         PcgState* st = g.pcg + prob;
         if (st->done) {
-            if (lane_id() == 0) s_act[prob] = 0;
+            if (lane_id() == 0) st->act = 0;
             continue;
         }
         const double pq = wave_sum_blocks(g.pq_partial, 1, 0, g.dc_red.prob_blk[prob],
@@ -863,26 +862,34 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
                 if (!done && st->iters >= max_iters) done = 2;
             }
             const double rz_old = st->rz;
-            s_beta[prob] = (rz_old > 0.0) ? rz / rz_old : 0.0;
-            s_act[prob] = (unsigned char)((done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0));
+            st->beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
+            st->act = (done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0);
             if (copy_best) st->use_best = 1;
             if (done != 3) st->rz = rz;
             st->done = done;
         }
     }
-    __syncthreads();
+}
+
+// PCG step, vectors (camera-aligned workgroups): p = z + beta p, and the
+// best-iterate copy / restore when the rejection ratio is enabled.
+template <typename T>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(DeviceGraph g) {
+    int cb, ce;
+    const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
+    const PcgState* st = g.pcg + prob;
+    const int act = st->act;
+    if (!act) return;
+    const int tid = threadIdx.x;
+    if (tid >= 9 * (ce - cb)) return;
+    const int k = 9 * cb + tid;
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ p = (T*)g.v_p;
     const T* __restrict__ z = (const T*)g.v_z;
     T* __restrict__ best = (T*)g.v_best;
-    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) {
-        const int prob = g.cam_prob[k / 9];
-        const int act = s_act[prob];
-        if (!act) continue;
-        if (act & 1) p[k] = (T)((double)z[k] + s_beta[prob] * (double)p[k]);
-        if (act & 2) best[k] = x[k];
-        if (act & 4) x[k] = best[k];
-    }
+    if (act & 1) p[k] = (T)((double)z[k] + st->beta * (double)p[k]);
+    if (act & 2) best[k] = x[k];
+    if (act & 4) x[k] = best[k];
 }
 
 // ==========================================================================
@@ -1151,11 +1158,13 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag,
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_finish<double>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        hipLaunchKernelGGL(k_pcg_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
     } else {
         hipLaunchKernelGGL((k_reduce<float, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_finish<float>, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        hipLaunchKernelGGL(k_pcg_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;

@@ -41,7 +41,7 @@ class gba_options(ctypes.Structure):
                 ("pcg_tol", ctypes.c_double), ("pcg_tol_relative", ctypes.c_int),
                 ("pcg_rejection_ratio", ctypes.c_double), ("precond", ctypes.c_int),
                 ("timing", ctypes.c_int), ("accumulation", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("tiles_per_block", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class gba_report(ctypes.Structure):

@@ -378,6 +378,29 @@ def test_bal1m_mixed_final_cost_and_solution(precision, acc):
     assert err["rel"] <= 1e-3, err
 
 
+@pytest.mark.parametrize("acc", ACC)
+def test_bal8m_proxy_bf16_against_oracle(acc):
+    """The at-scale configuration's precision policy (BF16 Jacobian copy, 15
+    trials, tracks 2 + Geometric(1/7)) on its one-tenth proxy, against the
+    oracle's stored solve; also through the global accumulation scheme the
+    full-size workload uses."""
+    path = os.path.join(GOLD, "bal8m_proxy_seed0.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file absent")
+    gold = json.load(open(path))
+    sc = synth.make_scene("bal8m_proxy", seed=0)
+    assert sc.n_obs == gold["n_obs"]
+    g = _graph(sc, precision=gba.GBA_MIXED_BF16, pcg_max_iters=sc.pcg_max_iters,
+               pcg_tol=sc.pcg_tol, accumulation=acc)
+    rep = g.solve(gold["trials"])
+    assert abs(rep.initial_cost - gold["initial_cost"]) <= 1e-12 * gold["initial_cost"]
+    rel = abs(rep.final_cost - gold["final_cost"]) / gold["final_cost"]
+    assert rel <= 1e-4, (rep.final_cost, gold["final_cost"], rel)
+    pts = g.points()[gold["point_sample"]]
+    err = align.aligned_errors(g.cameras(), pts, np.array(gold["cams"]), np.array(gold["points"]))
+    assert err["rel"] <= 1e-3, err
+
+
 # ------------------------------------------------- 10k cameras, 8M obs --
 def test_bal8m_bf16_full_size():
     """The at-scale workload (10,000 cameras: the camera vector exceeds LDS,
