@@ -1,5 +1,6 @@
 """Benchmark: LM iterations/s of bundle adjustment at 1M observations on one
-MI355X, plus the PCG matvec roofline and the CPU oracle as a baseline.
+MI355X, the PCG matvec roofline, the CPU oracle as a baseline, and p50/p99
+latency of a local-BA request stream on the server.
 
 Workload (synthetic, seeded): 1,000 cameras, 200,000 points, ~1.0M
 observations (track length 2 + Geometric(1/4)), Huber delta = 1 px, 20 LM
@@ -8,8 +9,15 @@ One step = one 20-trial solve from the perturbed start (device-side reset of
 the parameters, then gba_solve).  Inputs are resident on the device before the
 timed region.
 
+Serving (in the same JSON line, "serving"): 512 local-BA requests (5-40
+keyframes, 500-20k points, tracks 2-10 inside a local window, first two
+keyframes fixed, 10 trials each, mixed FP32): one at a time, all at once
+(saturated solves/s), and as a Poisson stream at 0.8x the saturated rate
+(p50/p99 latency from submission to result).
+
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
-                  [--no-cpu-baseline]
+                  [--workload bal1m|bal8m|small] [--no-cpu-baseline] [--no-serve]
+                  [--serve-only] [--accumulation 0|1|2] [--tiles-per-block N]
 """
 import argparse
 import json
@@ -66,6 +74,7 @@ def serving_measurement(gba, synth, n_req, precision, budget, slots, tune_db, se
     """Local-BA stream on the server: (1) the same requests one at a time,
     (2) all submitted at once (saturated throughput), (3) a Poisson stream at
     0.8 x the saturated rate; latency = submission to result."""
+    import numpy as np
     t0 = time.perf_counter()
     reqs = [synth.make_local_request(10_000 * seed + k) for k in range(n_req)]
     n_obs = [len(r["cam_idx"]) for r in reqs]
