@@ -36,6 +36,7 @@ PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf1
 # FETCH_SIZE reads half its size); see profiles/.  None until measured for the
 # current kernel.
 MEASURED_TRAFFIC = {"fp32": 136516312, "fp64": 240725298}
+MATVEC_WARMUP, MATVEC_LAUNCHES = 20, 200
 
 
 def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes):
@@ -160,10 +161,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
     ap.add_argument("--accumulation", type=int, default=0,
-                    help="camera sums of the point passes: 0 auto, 1 LDS partials, 2 global atomics")
+                    help="camera sums of the Schur products: 0 auto, 1 LDS partials, 2 camera-major second pass")
     ap.add_argument("--tiles-per-block", type=int, default=0,
                     help="point tiles per point-pass workgroup (0: automatic)")
     ap.add_argument("--no-serve", action="store_true", help="skip the local-BA stream")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the back-to-back Schur-product timing (for kernel traces)")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-mb", type=int, default=4096)
@@ -207,13 +210,40 @@ def main():
     trials = args.trials or sc.trials
     print(f"[bench] workload {args.workload}: {sc.n_cams} cams, {sc.n_pts} pts, {sc.n_obs} obs "
           f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
-    def timed_run(prec_id, timing):
+    n_pts_active = int(np.unique(sc.pt_idx).size)
+    alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes)
+
+    def make_graph(prec_id, timing):
         opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
                            timing=1 if timing else 0, accumulation=args.accumulation,
                            tiles_per_block=args.tiles_per_block)
-        g = gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
-                                  loss=sc.loss, delta=sc.delta, precision=prec_id,
-                                  options=opts, use_torch=True)
+        return gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
+                                     loss=sc.loss, delta=sc.delta, precision=prec_id,
+                                     options=opts, use_torch=True)
+
+    def matvec_roofline(g):
+        """Schur products back to back (MATVEC_WARMUP, then MATVEC_LAUNCHES timed)
+        at the starting parameters and lambda 1e-4: average duration per launch."""
+        gba.gba_time_matvec(g.h, 1e-4, MATVEC_WARMUP)
+        avg_us = gba.gba_time_matvec(g.h, 1e-4, MATVEC_LAUNCHES)
+        achieved = alg_bytes / (avg_us * 1e-6) / 1e9
+        traffic = MEASURED_TRAFFIC.get(args.precision) if args.workload == "bal1m" else None
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_point_pass<kMatvec> (fused Schur product)",
+                "avg_us": round(avg_us, 2), "launches": MATVEC_LAUNCHES,
+                "algorithmic_bytes": int(alg_bytes)}
+
+    if args.matvec_only:
+        g = make_graph(prec_id, False)
+        gba.gba_prepare(g.h)
+        print(json.dumps({"matvec_only": matvec_roofline(g), "precision": args.precision,
+                          "workload": args.workload}), flush=True)
+        g.close()
+        return
+
+    def timed_run(prec_id):
+        g = make_graph(prec_id, False)
         t0 = time.perf_counter()
         gba.gba_prepare(g.h)
         torch.cuda.synchronize()
@@ -232,30 +262,32 @@ def main():
             reports.append(g.solve(trials))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        g.close()
-        return reports, elapsed, build_s
+        return g, reports, elapsed, build_s
 
-    reports, elapsed, build_s = timed_run(prec_id, not args.no_timing)
+    g, reports, elapsed, build_s = timed_run(prec_id)
     print(f"[bench] graph build + upload {build_s:.2f} s", flush=True)
     total_trials = sum(r.trials for r in reports)
     lm_iters_s = total_trials / elapsed
     last = reports[-1]
-    mv_ms = sum(r.ms_matvec for r in reports)
-    mv_n = sum(r.matvec_count for r in reports)
-    n_pts_active = int(np.unique(sc.pt_idx).size)
-    alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes)
-    roofline = None
-    if mv_n:
-        avg_s = mv_ms / mv_n / 1e3
-        achieved = alg_bytes / avg_s / 1e9
-        traffic = MEASURED_TRAFFIC.get(args.precision) if args.workload == "bal1m" else None
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "kernel": "k_point_pass<kMatvec> (fused Schur product)",
-                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": int(alg_bytes)}
+    # outside the timed region: the matvec roofline, then one solve with
+    # per-phase HIP events for the breakdown
+    gba.gba_reset(g.h)
+    roofline = matvec_roofline(g)
+    phases = None
+    if not args.no_timing:
+        gba.gba_reset(g.h)
+        gba.gba_set_options(g.h, gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
+                                             timing=1, accumulation=args.accumulation,
+                                             tiles_per_block=args.tiles_per_block))
+        rt = g.solve(trials)
+        phases = {k: round(getattr(rt, k), 3) for k in
+                  ("ms_total", "ms_linearize", "ms_precond", "ms_pcg", "ms_other", "ms_matvec")}
+        phases["matvec_launches_timed"] = rt.matvec_count
+    g.close()
     compare = None
     if not args.no_compare and prec_id != 0:
-        r64, e64, _ = timed_run(0, False)
+        g64, r64, e64, _ = timed_run(0)
+        g64.close()
         v64 = sum(r.trials for r in r64) / e64
         compare = {"fp64_lm_iter_per_s": round(v64, 3), "mixed_over_fp64": round(lm_iters_s / v64, 3),
                    "fp64_final_cost": r64[-1].final_cost,
@@ -271,13 +303,12 @@ def main():
                                f"{sc.n_obs} observations, Huber 1px, {trials} LM trials/step, "
                                f"PCG tol {sc.pcg_tol} max {sc.pcg_max_iters}",
                    "precision": args.precision, "seed": 0,
-                   "accumulation": {0: "auto", 1: "lds", 2: "global"}[args.accumulation],
+                   "accumulation": {0: "auto", 1: "lds", 2: "camera_pass"}[args.accumulation],
                    "tiles_per_block": args.tiles_per_block or "auto"},
         "obs_per_s": round(sc.n_obs * lm_iters_s, 1),
         "pcg_iters_per_trial": round(sum(r.pcg_iters_total for r in reports) / max(total_trials, 1), 2),
         "final_cost": last.final_cost, "initial_cost": last.initial_cost,
-        "phase_ms_per_solve": {k: round(getattr(last, k), 3) for k in
-                               ("ms_linearize", "ms_precond", "ms_pcg", "ms_other", "ms_matvec")},
+        "phase_ms_per_solve": phases,
         "graph_build_s": round(build_s, 3), "workspace_bytes": int(last.workspace_bytes),
         "roofline": roofline,
         "fp64_comparison": compare,

@@ -114,16 +114,20 @@ typedef struct gba_options {
                                   disables (default: disabled)               */
     int precond;               /* gba_precond (BLOCK_JACOBI)                 */
     int timing;                /* 1: time phases with HIP events (0)         */
-    int accumulation;          /* camera-side sums of the point passes:
-                                  GBA_ACC_AUTO (default): per-workgroup LDS
-                                  partials when one problem's 9 x n_cams FP64
-                                  vector fits in LDS, else global atomics;
-                                  GBA_ACC_LDS / GBA_ACC_GLOBAL force one
-                                  (LDS fails with UNSUPPORTED when it does not
-                                  fit).  Read when the device graph is built. */
+    int accumulation;          /* camera-side sums of the Schur products:
+                                  GBA_ACC_AUTO (default): one point-major pass
+                                  with per-workgroup LDS partials when one
+                                  problem's 9 x n_cams FP64 vector fits in LDS,
+                                  else two passes (point-major, then
+                                  camera-major over a camera-major copy of
+                                  the stored Jacobian); GBA_ACC_LDS /
+                                  GBA_ACC_CAMERA_PASS force one (LDS fails with
+                                  UNSUPPORTED when it does not fit).  Read when
+                                  the device graph is built.                  */
     int tiles_per_block;       /* point tiles (whole points, <= 64 edges) per
                                   workgroup of the point passes; 0 (default):
-                                  max(16, n_tiles / n_CU).  Read when the device
+                                  max(16, n_tiles / n_CU) with LDS partials, 16
+                                  in the two-pass scheme.  Read when the device
                                   graph is built; the server takes its sizes
                                   from gba_server_config instead.             */
     int reserved[5];
@@ -131,7 +135,7 @@ typedef struct gba_options {
 
 #define GBA_ACC_AUTO 0
 #define GBA_ACC_LDS 1
-#define GBA_ACC_GLOBAL 2
+#define GBA_ACC_CAMERA_PASS 2
 
 /* Summary of one gba_solve call. */
 typedef struct gba_report {
@@ -253,6 +257,14 @@ gba_status gba_eval_normal_equations(gba_graph* g, double* hcc, double* bc,
  * dcam[n_cams x 9], dpt[n_pts x 3]; *pcg_iters receives the PCG count. */
 gba_status gba_eval_step(gba_graph* g, double lambda, double* dcam, double* dpt,
                          int* pcg_iters);
+
+/* gba_time_matvec (measurement): linearise at the current parameters, form
+ * the damped reduced camera system at `lambda` as gba_eval_step does, then
+ * run `launches` Schur products S p (the PCG hot loop's dominant kernel) back
+ * to back on the graph's stream between two HIP events; *avg_us receives the
+ * average duration of one product in microseconds.  The parameters are not
+ * changed. */
+gba_status gba_time_matvec(gba_graph* g, double lambda, int launches, double* avg_us);
 
 const char* gba_last_error(const gba_graph* g);
 

@@ -90,6 +90,7 @@ gba_status build(gba_graph* g) {
         release_device(g);
         return st;
     }
+    g->batch.use_graphs = true;
     g->built = true;
     g->dirty = false;
     return GBA_OK;
@@ -171,6 +172,7 @@ gba_status gba_set_stream(gba_graph* g, void* hip_stream) {
     if (g->built) HIP_TRY(g, hipStreamSynchronize(g->stream));
     g->stream = (hipStream_t)hip_stream;
     g->batch.stream = g->stream;
+    g->batch.drop_graphs();   // graphs are replayed on the stream they were made for
     return GBA_OK;
 }
 
@@ -334,7 +336,7 @@ gba_status gba_set_options(gba_graph* g, const gba_options* o) {
     if (!(o->initial_lambda > 0.0) || !(o->min_diag > 0.0) || !(o->max_diag >= o->min_diag) ||
         o->pcg_max_iters < 1 || !(o->pcg_tol >= 0.0) ||
         (o->precond != GBA_PRECOND_IDENTITY && o->precond != GBA_PRECOND_BLOCK_JACOBI) ||
-        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_GLOBAL || o->tiles_per_block < 0)
+        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_CAMERA_PASS || o->tiles_per_block < 0)
         return fail(g, GBA_ERR_INVALID_ARG, "invalid option value");
     if (o->accumulation != g->tune.accumulation || o->tiles_per_block != g->tune.tiles_per_block) {
         // both are part of the device graph's plan
@@ -562,6 +564,22 @@ gba_status gba_eval_step(gba_graph* g, double lambda, double* dcam, double* dpt,
             for (int a = 0; a < 9; ++a)
                 dcam[9 * (size_t)i + a] = g->prob.cam_fixed[i] ? 0.0 : x[9 * (size_t)i + a];
     if (pcg_iters) *pcg_iters = g->batch.h_scal[0].pcg_iters;
+    return GBA_OK;
+}
+
+gba_status gba_time_matvec(gba_graph* g, double lambda, int launches, double* avg_us) {
+    if (!g || !avg_us || !(lambda > 0.0) || launches < 1)
+        return fail(g, GBA_ERR_INVALID_ARG, "lambda must be positive, launches >= 1");
+    HIP_TRY(g, hipSetDevice(g->device));
+    gba_status st = ensure_built(g);
+    if (st != GBA_OK) return st;
+    *avg_us = 0.0;
+    if (g->batch.dg.ne == 0) return GBA_OK;
+    if ((st = gba::batch_linearize(g->batch, nullptr, nullptr, g->err)) != GBA_OK) return st;
+    g->batch.h_lam[0] = lambda;
+    double ms = 0.0;
+    if ((st = gba::batch_time_matvec(g->batch, g->opts, launches, &ms, g->err)) != GBA_OK) return st;
+    *avg_us = ms * 1e3;
     return GBA_OK;
 }
 

@@ -86,7 +86,7 @@ struct UnionPlan {
     std::vector<int> part_off;   // [max(1, pp.nblk())]
     long long part_total = 0;
     int max_cams = 0;
-    bool global_acc = false;   // camera vector of some problem exceeds LDS
+    bool cam_pass = false;     // camera vector of some problem exceeds LDS: two passes
     std::vector<int> cam_prob, pt_prob;   // problem of each union camera / point
 };
 
@@ -134,6 +134,17 @@ struct Batch {
     UnionPlan plan;
     int P = 0;
     std::vector<std::vector<int>> pm_edge; // per problem: point-major position -> insertion index
+    // PCG chunks replayed as HIP graphs (kernel arguments captured by value;
+    // the PCG kernels read no field that changes between rebuilds)
+    bool use_graphs = false;
+    bool pcg_warm = false;          // one eager chunk ran (kernel attributes set)
+    hipStream_t cap_stream = nullptr;   // capture only (the null stream cannot be captured)
+    struct PcgGraph {
+        hipGraphExec_t exec = nullptr;
+        int iters = 0, max_iters = 0;
+        double min_diag = 0, max_diag = 0, ratio = 0;
+    } pcg_graph[2];
+    void drop_graphs();
     // pinned host mirrors of the per-problem device arrays (capacity h_cap)
     int h_cap = 0;
     TrialScalars* h_scal = nullptr;
@@ -190,6 +201,12 @@ gba_status batch_linearize(Batch& b, const RawOut* raw, Timers* tm, std::string&
 // Damped solve of every problem at its damping b.h_lam[p] (negative: idle),
 // back-substitution and candidate cost; trial scalars land in b.h_scal.
 gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune, Timers* tm,
+                             std::string& msg);
+
+// Measurement: set up the damped reduced system at damping b.h_lam[p] (as
+// batch_damped_step does), then run `launches` Schur products back to back
+// between two events; *ms = average per product.
+gba_status batch_time_matvec(Batch& b, const gba_options& o, int launches, double* ms,
                              std::string& msg);
 
 // Current cost of every problem into b.h_scal[p].cost.

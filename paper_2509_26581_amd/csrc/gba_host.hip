@@ -41,7 +41,16 @@ void Allocator::release(void* p) const {
         (void)hipFree(p);
 }
 
+void Batch::drop_graphs() {
+    for (auto& pg : pcg_graph) {
+        if (pg.exec) (void)hipGraphExecDestroy(pg.exec);
+        pg = PcgGraph{};
+    }
+    pcg_warm = false;
+}
+
 void Batch::release() {
+    drop_graphs();
     if (arena && owns_arena) {
         (void)hipStreamSynchronize(stream);
         allocator.release(arena);
@@ -75,6 +84,7 @@ gba_status Batch::ensure_mirrors(int n, std::string& msg) {
 
 Batch::~Batch() {
     release();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (h_scal) (void)hipHostFree(h_scal);
     if (h_pcg) (void)hipHostFree(h_pcg);
     if (h_lam) (void)hipHostFree(h_lam);
@@ -318,10 +328,14 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
               std::to_string(u.max_cams) + " cameras)";
         return GBA_ERR_UNSUPPORTED;
     }
-    u.global_acc = tune.accumulation == GBA_ACC_GLOBAL || !fits;
+    u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits;
+    // automatic: one point-pass workgroup per CU when each flushes an LDS
+    // camera partial (the flush grows with the workgroup count); small
+    // workgroups (more waves resident) in the two-pass scheme, which has none
     const long long tpb = tune.tiles_per_block > 0
                               ? tune.tiles_per_block
-                              : std::max<long long>(16, (st + dev.n_cu - 1) / std::max(1, dev.n_cu));
+                              : u.cam_pass ? 16
+                                           : std::max<long long>(16, (st + dev.n_cu - 1) / std::max(1, dev.n_cu));
     const long long epb = tune.edges_per_block > 0 ? tune.edges_per_block
                                                    : std::max<long long>(256, (se + 2047) / 2048);
     const long long ppb = tune.pts_per_block > 0 ? tune.pts_per_block
@@ -335,18 +349,13 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     u.pts = make_decomp(u.pt_off, ppb);
     u.part_off.assign(std::max(1, u.pp.nblk()), 0);
     long long part = 0;
-    for (int p = 0; p < P; ++p) {
+    for (int p = 0; p < P && !u.cam_pass; ++p) {
         const int ncp = u.cam_off[p + 1] - u.cam_off[p];
         for (int q = u.pp.prob_blk[p]; q < u.pp.prob_blk[p + 1]; ++q) {
-            if (u.global_acc) {
-                u.part_off[q] = 9 * u.cam_off[p];   // one shared vector per problem
-            } else {
-                u.part_off[q] = (int)part;          // one partial vector per workgroup
-                part += 9LL * ncp;
-            }
+            u.part_off[q] = (int)part;          // one partial vector per workgroup
+            part += 9LL * ncp;
         }
     }
-    if (u.global_acc) part = 9LL * sc;
     if (part > std::numeric_limits<int>::max()) {
         msg = "camera partial buffer too large";
         return GBA_ERR_UNSUPPORTED;
@@ -410,6 +419,11 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.wrun, tsz * 27 * (size_t)std::max(1, u.tot.n_runs));
     L.add(d.bc, tsz * 9 * NC);
     L.add(d.hpp_inv, sizeof(double) * kHinvStride * NP);
+    if (u.cam_pass) {
+        L.add(d.jc_cm, jsz * 18 * NE);
+        L.add(d.jp_cm, jsz * 6 * NE);
+        L.add(d.zbuf, sizeof(double) * 4 * NP);
+    }
     L.add(d.minv, tsz * 45 * NC);
     L.add(d.v_x, tsz * 9 * NC);
     L.add(d.v_r, tsz * 9 * NC);
@@ -450,8 +464,8 @@ void set_union_scalars(Batch& b, int precision, int loss, double delta) {
     d.mode = precision;
     d.jac_bytes = precision == GBA_FP64 ? 8 : (precision == GBA_MIXED_FP32 ? 4 : 2);
     d.block_pp = kPointPassBlock;
-    d.global_acc = u.global_acc ? 1 : 0;
-    d.lds_pp = u.global_acc ? 0 : (int)(9 * (size_t)u.max_cams * sizeof(double));
+    d.cam_pass = u.cam_pass ? 1 : 0;
+    d.lds_pp = u.cam_pass ? 0 : (int)(9 * (size_t)u.max_cams * sizeof(double));
     d.dc_pp.nblk = u.pp.nblk();
     d.dc_red.nblk = u.red.nblk();
     d.dc_cam.nblk = u.cam.nblk();
@@ -646,11 +660,47 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     int last_iters = 0;
     while (launched < o.pcg_max_iters) {
         const int c = std::min(chunk, o.pcg_max_iters - launched);
-        for (int k = 0; k < c; ++k) {
-            hipEvent_t e0 = timing ? tm->ev[4 + 2 * k] : nullptr;
-            hipEvent_t e1 = timing ? tm->ev[5 + 2 * k] : nullptr;
-            HIP_OR(msg, launch_pcg_iter(d, s, o.min_diag, o.max_diag, o.pcg_max_iters,
-                                        o.pcg_rejection_ratio, e0, e1));
+        if (b.use_graphs && !timing && b.pcg_warm) {
+            // replay the chunk as one graph (captured on first use)
+            Batch::PcgGraph& pg = b.pcg_graph[c == chunk ? 0 : 1];
+            if (pg.exec && (pg.iters != c || pg.max_iters != o.pcg_max_iters ||
+                            pg.min_diag != o.min_diag || pg.max_diag != o.max_diag ||
+                            pg.ratio != o.pcg_rejection_ratio)) {
+                (void)hipGraphExecDestroy(pg.exec);
+                pg = Batch::PcgGraph{};
+            }
+            if (!pg.exec) {
+                // captured on a private stream, replayed on the batch stream
+                if (!b.cap_stream)
+                    HIP_OR(msg, hipStreamCreateWithFlags(&b.cap_stream, hipStreamNonBlocking));
+                hipStream_t cs = b.cap_stream;
+                hipGraph_t graph = nullptr;
+                HIP_OR(msg, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                hipError_t r = hipSuccess;
+                for (int k = 0; k < c && r == hipSuccess; ++k)
+                    r = launch_pcg_iter(d, cs, o.min_diag, o.max_diag, o.pcg_max_iters,
+                                        o.pcg_rejection_ratio, nullptr, nullptr);
+                hipError_t r2 = hipStreamEndCapture(cs, &graph);
+                HIP_OR(msg, r);
+                HIP_OR(msg, r2);
+                r = hipGraphInstantiate(&pg.exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HIP_OR(msg, r);
+                pg.iters = c;
+                pg.max_iters = o.pcg_max_iters;
+                pg.min_diag = o.min_diag;
+                pg.max_diag = o.max_diag;
+                pg.ratio = o.pcg_rejection_ratio;
+            }
+            HIP_OR(msg, hipGraphLaunch(pg.exec, s));
+        } else {
+            for (int k = 0; k < c; ++k) {
+                hipEvent_t e0 = timing ? tm->ev[4 + 2 * k] : nullptr;
+                hipEvent_t e1 = timing ? tm->ev[5 + 2 * k] : nullptr;
+                HIP_OR(msg, launch_pcg_iter(d, s, o.min_diag, o.max_diag, o.pcg_max_iters,
+                                            o.pcg_rejection_ratio, e0, e1));
+            }
+            b.pcg_warm = true;
         }
         launched += c;
         HIP_OR(msg, hipMemcpyAsync(b.h_pcg, d.pcg, sizeof(PcgState) * b.P, hipMemcpyDeviceToHost, s));
@@ -690,6 +740,33 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
         tm->ms_phase[2] += c;
         tm->ms_phase[3] += e;
     }
+    return GBA_OK;
+}
+
+gba_status batch_time_matvec(Batch& b, const gba_options& o, int launches, double* ms,
+                             std::string& msg) {
+    const DeviceGraph& d = b.dg;
+    hipStream_t s = b.stream;
+    HIP_OR(msg, hipMemcpyAsync(d.lam, b.h_lam, sizeof(double) * b.P, hipMemcpyHostToDevice, s));
+    HIP_OR(msg, launch_damp(d, s, o.min_diag, o.max_diag));
+    HIP_OR(msg, launch_rhs(d, s));
+    HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag,
+                               o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0));
+    // tolerance 0: the products below run for every problem with work
+    HIP_OR(msg, launch_pcg_init(d, s, 0.0, 0));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OR(msg, hipEventCreate(&e0));
+    hipError_t r = hipEventCreate(&e1);
+    if (r == hipSuccess) r = hipEventRecord(e0, s);
+    for (int k = 0; k < launches && r == hipSuccess; ++k) r = launch_matvec(d, s);
+    if (r == hipSuccess) r = hipEventRecord(e1, s);
+    if (r == hipSuccess) r = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    HIP_OR(msg, r);
+    *ms = launches > 0 ? (double)t / launches : 0.0;
     return GBA_OK;
 }
 

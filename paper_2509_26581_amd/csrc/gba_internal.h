@@ -138,6 +138,9 @@ struct DeviceGraph {
     void* wrun;               // [27][n_runs] W = sum_run J_c^T J_p per camera-major run
     void* bc;                 // [nc][9]
     double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per row
+    void* jc_cm;              // [18][ne] camera-major copy of jc (two-pass scheme only)
+    void* jp_cm;              // [6][ne]
+    double* zbuf;             // [np][4] point vectors between the two passes
     void* minv;               // [nc][45] preconditioner inverse blocks
 
     // Schur / PCG vectors, [nc][9]
@@ -167,8 +170,9 @@ struct DeviceGraph {
     // launch geometry
     int block_pp;             // threads per point-pass workgroup
     int lds_pp;               // dynamic LDS bytes of the point passes (9 x max cameras of a problem)
-    int global_acc;           // 1: a problem's camera vector exceeds LDS; the point passes add
-                              // their camera sums into one global vector (FP64 atomics)
+    int cam_pass;             // 1: a problem's camera vector exceeds LDS; the RHS and the
+                              // Schur product take two passes (point-major: z_j into zbuf;
+                              // camera-major over jc_cm / jp_cm: sums per chunk)
 };
 
 // ---- launchers (gba_kernels.hip) --------------------------------------
@@ -210,6 +214,8 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
 hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                            int max_iters, double reject_ratio, hipEvent_t ev_mv0,
                            hipEvent_t ev_mv1);
+// the Schur product S p of the PCG step alone (q partials, no update)
+hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_finish(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_commit(const DeviceGraph& g, hipStream_t s);

@@ -253,6 +253,21 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     jp[0][a] = jac_round<JS>(ev.jp[0][a]);
                     jp[1][a] = jac_round<JS>(ev.jp[1][a]);
                 }
+                if (g.cam_pass) {
+                    // camera-major copy of the stored Jacobian for the two-pass products
+                    JS* jcm = (JS*)g.jc_cm;
+                    JS* jpm = (JS*)g.jp_cm;
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        jcm[a * ne + q] = jac_store<JS>(jc[0][a]);
+                        jcm[(9 + a) * ne + q] = jac_store<JS>(jc[1][a]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        jpm[a * ne + q] = jac_store<JS>(jp[0][a]);
+                        jpm[(3 + a) * ne + q] = jac_store<JS>(jp[1][a]);
+                    }
+                }
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
@@ -407,8 +422,9 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
     const int l = lane_id();
     const int c0 = g.prob_cam_off[prob];
     const int nc9 = 9 * (g.prob_cam_off[prob + 1] - c0);   // this problem's camera components
-    const bool gacc = g.global_acc != 0;   // camera sums straight to the global vector
-    if (kMode != kBacksub && !gacc) {
+    // two-pass scheme: this pass only produces z_j (camera sums in k_cam_pass)
+    const bool cpass = g.cam_pass != 0;
+    if (kMode != kBacksub && !cpass) {
         for (int k = threadIdx.x; k < nc9; k += blockDim.x) acc_lds[k] = 0;
         __syncthreads();
     }
@@ -477,6 +493,11 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                     zz[0] = h00 * v0 + h01 * v1 + h02 * v2;
                     zz[1] = h01 * v0 + h11 * v1 + h12 * v2;
                     zz[2] = h02 * v0 + h12 * v1 + h22 * v2;
+                    if (kMode == kMatvec && cpass) {
+                        g.zbuf[4 * j] = zz[0];
+                        g.zbuf[4 * j + 1] = zz[1];
+                        g.zbuf[4 * j + 2] = zz[2];
+                    }
                     if (kMode == kBacksub) {
                         zz[0] = -zz[0];
                         zz[1] = -zz[1];
@@ -493,6 +514,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                         red_s += d0 * d0 + d1 * d1 + d2 * d2;
                     }
                 }
+                if (kMode == kMatvec && cpass) continue;   // uniform: the whole wave
 #pragma unroll
                 for (int k = 0; k < 3; ++k) z[k] = shfl64(zz[k], head);
             }
@@ -510,15 +532,9 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
             } else if (valid) {
                 const T u0 = jp[0][0] * z[0] + jp[0][1] * z[1] + jp[0][2] * z[2];
                 const T u1 = jp[1][0] * z[0] + jp[1][1] * z[1] + jp[1][2] * z[2];
-                if (gacc) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k)
-                        unsafeAtomicAdd(&out[9 * i + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 9; ++k)
-                        atomicAdd(&acc_lds[9 * (i - c0) + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
-                }
+                for (int k = 0; k < 9; ++k)
+                    atomicAdd(&acc_lds[9 * (i - c0) + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
             }
         } else {
             // a single point with more than 64 edges: two sweeps over chunks
@@ -560,6 +576,14 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                 z[0] = H[0] * tt[0] + H[1] * tt[1] + H[2] * tt[2];
                 z[1] = H[1] * tt[0] + H[3] * tt[1] + H[4] * tt[2];
                 z[2] = H[2] * tt[0] + H[4] * tt[1] + H[5] * tt[2];
+                if (kMode == kMatvec && cpass) {
+                    if (l == 0) {
+                        g.zbuf[4 * j] = z[0];
+                        g.zbuf[4 * j + 1] = z[1];
+                        g.zbuf[4 * j + 2] = z[2];
+                    }
+                    continue;   // uniform: the whole wave
+                }
                 if (kMode == kBacksub) {
                     z[0] = -z[0];
                     z[1] = -z[1];
@@ -598,14 +622,10 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                         red_m += (double)u0 * (double)u0 + (double)u1 * (double)u1;
                     } else {
 #pragma unroll
-                        for (int k = 0; k < 9; ++k) {
-                            const AT v = (AT)(load_as<T>(Jc[k * ne + e]) * u0 +
-                                              load_as<T>(Jc[(9 + k) * ne + e]) * u1);
-                            if (gacc)
-                                unsafeAtomicAdd(&out[9 * i + k], v);
-                            else
-                                atomicAdd(&acc_lds[9 * (i - c0) + k], v);
-                        }
+                        for (int k = 0; k < 9; ++k)
+                            atomicAdd(&acc_lds[9 * (i - c0) + k],
+                                      (AT)(load_as<T>(Jc[k * ne + e]) * u0 +
+                                           load_as<T>(Jc[(9 + k) * ne + e]) * u1));
                     }
                 }
             }
@@ -623,7 +643,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
         }
         return;
     }
-    if (gacc) return;
+    if (cpass) return;
     __syncthreads();
     AT* dst = out + g.pp_part_off[blockIdx.x];
     for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = acc_lds[k];
@@ -646,12 +666,17 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
     const int grp = threadIdx.x >> 6;
     const int k = kb + cl;
     const int kl = k - 9 * g.prob_cam_off[prob];          // component within the problem
-    const int q0 = g.dc_pp.prob_blk[prob];
-    // global accumulation: all workgroups of the problem share one vector
-    const int q1 = g.global_acc ? min(q0 + 1, g.dc_pp.prob_blk[prob + 1]) : g.dc_pp.prob_blk[prob + 1];
+    const int q0 = g.dc_pp.prob_blk[prob], q1 = g.dc_pp.prob_blk[prob + 1];
     const double* part = g.cam_partial;
     double s = 0.0;
-    if (k < ke) {
+    if (g.cam_pass) {
+        // two-pass scheme: the camera's chunk sums from k_cam_pass
+        if (grp == 0 && k < ke) {
+            const int i = k / 9, r = k % 9;
+            for (int c = g.cam_chunk_off[i]; c < g.cam_chunk_off[i + 1]; ++c)
+                s += g.chunk_partial[54 * c + r];
+        }
+    } else if (k < ke) {
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int q = q0 + grp;
         for (; q + 48 < q1; q += 64) {
@@ -715,10 +740,20 @@ __device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds
 // Sum of part[stride * q + off] over the workgroups q of a problem, by one
 // wavefront (every lane gets the result).
 __device__ __forceinline__ double wave_sum_blocks(const double* part, int stride, int off, int q0,
-                                                  int q1) {
-    double s = 0.0;
-    for (int q = q0 + lane_id(); q < q1; q += kWave) s += part[stride * q + off];
-    return wave_sum(s);
+                                                  int q1, int sub = 0, int parts = 1) {
+    // this wavefront is number `sub` of `parts` sharing the range; four
+    // independent partial sums keep four loads in flight per lane
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int step = kWave * parts;
+    int q = q0 + sub * kWave + lane_id();
+    for (; q + 3 * step < q1; q += 4 * step) {
+        s0 += part[stride * q + off];
+        s1 += part[stride * (q + step) + off];
+        s2 += part[stride * (q + 2 * step) + off];
+        s3 += part[stride * (q + 3 * step) + off];
+    }
+    for (; q < q1; q += step) s0 += part[stride * q + off];
+    return wave_sum((s0 + s1) + (s2 + s3));
 }
 
 // PCG start, vectors: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
@@ -927,42 +962,72 @@ __global__ __launch_bounds__(kPcgBlock) void k_cam_update(DeviceGraph g) {
 }
 
 // Combine the per-workgroup partial sums of the trial, per problem (single
-// workgroup, one wavefront per problem at a time).
+// workgroup; with fewer problems than wavefronts several wavefronts share a
+// problem's sums).
 __global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
+    __shared__ double part[16][8];
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int prob = w; prob < g.n_probs; prob += nw) {
-        const int e0 = g.dc_edges.prob_blk[prob], e1 = g.dc_edges.prob_blk[prob + 1];
-        const int p0 = g.dc_pp.prob_blk[prob], p1 = g.dc_pp.prob_blk[prob + 1];
-        const int t0 = g.dc_pts.prob_blk[prob], t1 = g.dc_pts.prob_blk[prob + 1];
-        const int c0 = g.dc_cam.prob_blk[prob], c1 = g.dc_cam.prob_blk[prob + 1];
-        const double cost = wave_sum_blocks(g.cost_partial, 1, 0, e0, e1);
-        const double quad = wave_sum_blocks(g.red_partial, 4, 0, p0, p1);
-        const double bdp = wave_sum_blocks(g.red_partial, 4, 1, p0, p1);
-        const double sp = wave_sum_blocks(g.red_partial, 4, 2, p0, p1);
-        const double xp = wave_sum_blocks(g.damp_partial, 1, 0, t0, t1);
-        const double bdc = wave_sum_blocks(g.camupd_partial, 3, 0, c0, c1);
-        const double sc = wave_sum_blocks(g.camupd_partial, 3, 1, c0, c1);
-        const double xc = wave_sum_blocks(g.camupd_partial, 3, 2, c0, c1);
-        if (lane_id() == 0) {
-            TrialScalars* t = g.scal + prob;
-            t->cost = cost;
-            t->quad = quad;
-            t->b_dot_dx = bdc + bdp;
-            t->step2 = sc + sp;
-            t->x2 = xc + xp;
-            t->pcg_iters = g.pcg[prob].iters;
-            t->pcg_reason = g.pcg[prob].done;
+    const int wpp = g.n_probs >= nw ? 1 : nw / g.n_probs;   // wavefronts per problem
+    const int groups = nw / wpp, gw = w / wpp, sub = w % wpp;
+    for (int base = 0; base < g.n_probs; base += groups) {
+        const int prob = base + gw;
+        const bool mine = gw < groups && prob < g.n_probs;
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (mine) {
+            const int e0 = g.dc_edges.prob_blk[prob], e1 = g.dc_edges.prob_blk[prob + 1];
+            const int p0 = g.dc_pp.prob_blk[prob], p1 = g.dc_pp.prob_blk[prob + 1];
+            const int t0 = g.dc_pts.prob_blk[prob], t1 = g.dc_pts.prob_blk[prob + 1];
+            const int c0 = g.dc_cam.prob_blk[prob], c1 = g.dc_cam.prob_blk[prob + 1];
+            v[0] = wave_sum_blocks(g.cost_partial, 1, 0, e0, e1, sub, wpp);
+            v[1] = wave_sum_blocks(g.red_partial, 4, 0, p0, p1, sub, wpp);
+            v[2] = wave_sum_blocks(g.red_partial, 4, 1, p0, p1, sub, wpp);
+            v[3] = wave_sum_blocks(g.red_partial, 4, 2, p0, p1, sub, wpp);
+            v[4] = wave_sum_blocks(g.damp_partial, 1, 0, t0, t1, sub, wpp);
+            v[5] = wave_sum_blocks(g.camupd_partial, 3, 0, c0, c1, sub, wpp);
+            v[6] = wave_sum_blocks(g.camupd_partial, 3, 1, c0, c1, sub, wpp);
+            v[7] = wave_sum_blocks(g.camupd_partial, 3, 2, c0, c1, sub, wpp);
         }
+        if (lane_id() == 0)
+            for (int k = 0; k < 8; ++k) part[w][k] = v[k];
+        __syncthreads();
+        if (mine && sub == 0 && lane_id() == 0) {
+            double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int s2 = 0; s2 < wpp; ++s2)
+                for (int k = 0; k < 8; ++k) t[k] += part[w + s2][k];
+            TrialScalars* ts = g.scal + prob;
+            ts->cost = t[0];
+            ts->quad = t[1];
+            ts->b_dot_dx = t[5] + t[2];
+            ts->step2 = t[6] + t[3];
+            ts->x2 = t[7] + t[4];
+            ts->pcg_iters = g.pcg[prob].iters;
+            ts->pcg_reason = g.pcg[prob].done;
+        }
+        __syncthreads();
     }
 }
 
-// Cost only: combine the cost partials per problem.
+// Cost only: combine the cost partials per problem (as k_finish).
 __global__ __launch_bounds__(1024) void k_cost_finish(DeviceGraph g) {
+    __shared__ double part[16];
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int prob = w; prob < g.n_probs; prob += nw) {
-        const double cost = wave_sum_blocks(g.cost_partial, 1, 0, g.dc_edges.prob_blk[prob],
-                                            g.dc_edges.prob_blk[prob + 1]);
-        if (lane_id() == 0) g.scal[prob].cost = cost;
+    const int wpp = g.n_probs >= nw ? 1 : nw / g.n_probs;
+    const int groups = nw / wpp, gw = w / wpp, sub = w % wpp;
+    for (int base = 0; base < g.n_probs; base += groups) {
+        const int prob = base + gw;
+        const bool mine = gw < groups && prob < g.n_probs;
+        double v = 0.0;
+        if (mine)
+            v = wave_sum_blocks(g.cost_partial, 1, 0, g.dc_edges.prob_blk[prob],
+                                g.dc_edges.prob_blk[prob + 1], sub, wpp);
+        if (lane_id() == 0) part[w] = v;
+        __syncthreads();
+        if (mine && sub == 0 && lane_id() == 0) {
+            double t = 0.0;
+            for (int s2 = 0; s2 < wpp; ++s2) t += part[w + s2];
+            g.scal[prob].cost = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -973,6 +1038,70 @@ __global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
         if (g.accept[g.cam_prob[k / 9]]) g.cam[k] = g.cam_c[k];
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < 3 * (size_t)g.np; k += stride)
         if (g.accept[g.pt_prob[k / 3]]) g.pt[k] = g.pt_c[k];
+}
+
+// ==========================================================================
+// Two-pass scheme (a problem's camera vector exceeds LDS), second pass:
+// camera-major over the stored Jacobian's camera-major copy, one workgroup
+// per chunk of one camera's runs:
+//   sum_e J_c^T (J_p z_j)   with z_j from the first pass (zbuf)
+// into chunk_partial[chunk][0..8]; k_reduce adds a camera's chunks.
+//   kRhs: z_j = Hpp_lambda^-1 bp_j;  kMatvec: z_j = Hpp_lambda^-1 sum J_p^T J_c p.
+// ==========================================================================
+template <typename JS, int kMode>
+__global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
+    __shared__ double red[4][9];
+    const int chunk = blockIdx.x;
+    const int cam = g.chunk_cam[chunk];
+    if (kMode == kMatvec && g.pcg[g.cam_prob[cam]].done) return;   // converged
+    const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
+    const JS* __restrict__ Jc = (const JS*)g.jc_cm;
+    const JS* __restrict__ Jp = (const JS*)g.jp_cm;
+    const int ne = g.ne;
+    double y[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) y[k] = 0.0;
+    for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
+        const int q0 = g.cm_run_off[run], q1 = g.cm_run_off[run + 1];
+        const int j = g.cm_pt[q0];
+        const double z0 = g.zbuf[4 * j], z1 = g.zbuf[4 * j + 1], z2 = g.zbuf[4 * j + 2];
+        for (int q = q0; q < q1; ++q) {
+            const double u0 = load_as<double>(Jp[q]) * z0 + load_as<double>(Jp[ne + q]) * z1 +
+                              load_as<double>(Jp[2 * ne + q]) * z2;
+            const double u1 = load_as<double>(Jp[3 * ne + q]) * z0 +
+                              load_as<double>(Jp[4 * ne + q]) * z1 +
+                              load_as<double>(Jp[5 * ne + q]) * z2;
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                y[k] += load_as<double>(Jc[k * ne + q]) * u0 + load_as<double>(Jc[(9 + k) * ne + q]) * u1;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double v = wave_sum(y[k]);
+        if (lane_id() == 0) red[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int nw = blockDim.x >> 6;
+        double s = 0.0;
+        for (int q = 0; q < nw; ++q) s += red[q][threadIdx.x];
+        g.chunk_partial[54 * chunk + threadIdx.x] = s;
+    }
+}
+
+// Two-pass scheme, RHS first pass: z_j = Hpp_lambda^-1 bp_j for every point.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
+    const T* bp = (const T*)g.bp;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.np; j += gridDim.x * blockDim.x) {
+        const double b0 = (double)bp[j], b1 = (double)bp[g.np + j], b2 = (double)bp[2 * g.np + j];
+        const double* H = g.hpp_inv + kHinvStride * j;
+        g.zbuf[4 * j] = H[0] * b0 + H[1] * b1 + H[2] * b2;
+        g.zbuf[4 * j + 1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
+        g.zbuf[4 * j + 2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
+    }
 }
 
 // Batch assembly: one workgroup per chunk of one descriptor.
@@ -1105,16 +1234,34 @@ static void point_pass(const DeviceGraph& g, hipStream_t s, const void* jc, cons
                        (const VT*)vin, (AT*)out);
 }
 
-// Global accumulation: clear the shared camera vectors before a point pass.
-static void clear_global_acc(const DeviceGraph& g, hipStream_t s) {
-    if (g.global_acc)
-        hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, g.cam_partial, 0.0,
-                           (size_t)9 * g.nc);
+// Two-pass scheme, camera-major pass of the RHS or of the Schur product.
+template <int kMode>
+static void cam_pass(const DeviceGraph& g, hipStream_t s) {
+    if (g.n_chunks == 0) return;
+    if (g.mode == kModeFP64)
+        hipLaunchKernelGGL((k_cam_pass<double, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+    else if (g.mode == kModeFP32)
+        hipLaunchKernelGGL((k_cam_pass<float, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_cam_pass<bf16, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
 }
 
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;   // no cameras, hence no edges
-    clear_global_acc(g, s);
+    if (g.cam_pass) {
+        const int grid = g.np > 0 ? (g.np + 255) / 256 < 4096 ? (g.np + 255) / 256 : 4096 : 1;
+        if (g.mode == kModeFP64) {
+            hipLaunchKernelGGL(k_rhs_z<double>, dim3(grid), dim3(256), 0, s, g);
+            cam_pass<kRhs>(g, s);
+            hipLaunchKernelGGL((k_reduce<double, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
+        } else {
+            hipLaunchKernelGGL(k_rhs_z<float>, dim3(grid), dim3(256), 0, s, g);
+            cam_pass<kRhs>(g, s);
+            hipLaunchKernelGGL((k_reduce<float, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
+        }
+        GBA_CHECK_LAUNCH();
+        return hipSuccess;
+    }
     if (g.mode == kModeFP64) {
         point_pass<double, double, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
         hipLaunchKernelGGL((k_reduce<double, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
@@ -1142,11 +1289,8 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
     return hipSuccess;
 }
 
-hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
-                           int max_iters, double ratio, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;
-    if (ev0) (void)hipEventRecord(ev0, s);
-    clear_global_acc(g, s);
     if (g.mode == kModeFP64) {
         point_pass<double, double, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     } else if (g.mode == kModeFP32) {
@@ -1154,6 +1298,17 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag,
     } else {
         point_pass<float, bf16, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
     }
+    if (g.cam_pass) cam_pass<kMatvec>(g, s);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
+                           int max_iters, double ratio, hipEvent_t ev0, hipEvent_t ev1) {
+    if (g.nc == 0) return hipSuccess;
+    if (ev0) (void)hipEventRecord(ev0, s);
+    hipError_t e = launch_matvec(g, s);
+    if (e != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);

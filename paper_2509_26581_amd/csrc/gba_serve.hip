@@ -662,7 +662,7 @@ gba_status gba_server_create(const gba_server_config* cfg, gba_alloc_fn alloc, g
     if (!(o.initial_lambda > 0.0) || !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag) ||
         o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) ||
         (o.precond != GBA_PRECOND_IDENTITY && o.precond != GBA_PRECOND_BLOCK_JACOBI) ||
-        o.accumulation < GBA_ACC_AUTO || o.accumulation > GBA_ACC_GLOBAL)
+        o.accumulation < GBA_ACC_AUTO || o.accumulation > GBA_ACC_CAMERA_PASS)
         return GBA_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return GBA_ERR_HIP;

@@ -24,7 +24,7 @@ GBA_PENDING = 1
 GBA_FP64, GBA_MIXED_FP32, GBA_MIXED_BF16 = 0, 1, 2
 GBA_LOSS_SQUARED, GBA_LOSS_HUBER = 0, 1
 GBA_PRECOND_IDENTITY, GBA_PRECOND_BLOCK_JACOBI = 0, 1
-GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_GLOBAL = 0, 1, 2
+GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_CAMERA_PASS = 0, 1, 2
 TERMINATION = {0: "NONE", 1: "MAX_ITERS", 2: "COST_TOL", 3: "STEP_TOL",
                4: "LAMBDA_OVERFLOW", 5: "NUMERICAL_FAILURE", 6: "NO_WORK"}
 
@@ -139,6 +139,7 @@ _SIGS = {
     "gba_eval_edges": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "gba_eval_normal_equations": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "gba_eval_step": (ctypes.c_int, [_P, ctypes.c_double, _D, _D, ctypes.POINTER(ctypes.c_int)]),
+    "gba_time_matvec": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D]),
     "gba_last_error": (ctypes.c_char_p, [_P]),
     "gba_destroy": (None, [_P]),
     "gba_server_default_config": (None, [ctypes.POINTER(gba_server_config)]),
@@ -348,6 +349,12 @@ def gba_eval_step(h, lam, n_cams, n_pts):
     it = ctypes.c_int()
     _check(h, load().gba_eval_step(h, float(lam), _ptr(dc), _ptr(dp), ctypes.byref(it)))
     return dc, dp, it.value
+
+
+def gba_time_matvec(h, lam, launches):
+    t = ctypes.c_double()
+    _check(h, load().gba_time_matvec(h, float(lam), int(launches), ctypes.byref(t)))
+    return t.value
 
 
 def gba_last_error(h):

@@ -117,7 +117,7 @@ def test_normal_equation_blocks():
 
 
 # -------------------------------------------------------- damped step --
-ACC = [gba.GBA_ACC_AUTO, gba.GBA_ACC_GLOBAL]   # LDS partials / global atomics
+ACC = [gba.GBA_ACC_AUTO, gba.GBA_ACC_CAMERA_PASS]   # one pass (LDS) / two passes
 
 
 @pytest.mark.parametrize("acc", ACC)
@@ -223,6 +223,29 @@ def test_mixed_track_lengths_ragged_tiles(acc):
     dco, dpo = prob.solve(prob.linearize((sc.cams0, sc.pts0)), 1e-3, 1e-6, 1e32)
     _close(dc, dco, 1e-8, "camera step")
     _close(dp, dpo, 1e-8, "point step")
+
+
+def test_pcg_graph_replay_matches_eager_launches():
+    # the solver replays each chunk of PCG iterations as a captured HIP graph;
+    # with per-phase timing on it launches every kernel eagerly instead.
+    # Several solves in a row (reset in between) replay the same graphs.
+    # Once the decrease reaches the rounding level of F, accept / reject is
+    # decided by rounding noise (camera partials are combined by LDS atomics
+    # in a varying order), so the comparison stops there (_compare_trajectory).
+    sc = synth.make_scene("small", seed=2, n_cams=12, n_pts=800)
+    ref = _graph(sc, pcg_max_iters=60, pcg_tol=1e-10, timing=1)
+    rep_ref = ref.solve(8)
+    want = ref.trials()
+    g = _graph(sc, pcg_max_iters=60, pcg_tol=1e-10)
+    for _ in range(3):
+        gba.gba_reset(g.h)
+        rep = g.solve(8)
+        got = g.trials()
+        _compare_trajectory(got, want)
+        # the early trials, far above rounding, match step for step
+        assert got[0]["pcg_iters"] == want[0]["pcg_iters"]
+        assert got[0]["accepted"] and want[0]["accepted"]
+        assert abs(rep.final_cost - rep_ref.final_cost) <= 1e-10 * rep_ref.final_cost
 
 
 # ------------------------------------------------------------ edge cases --
@@ -363,7 +386,7 @@ def test_mixed_small_workload_final_cost(precision):
 
 @pytest.mark.parametrize("precision,acc", [(gba.GBA_MIXED_FP32, gba.GBA_ACC_AUTO),
                                            (gba.GBA_MIXED_BF16, gba.GBA_ACC_AUTO),
-                                           (gba.GBA_MIXED_BF16, gba.GBA_ACC_GLOBAL)])
+                                           (gba.GBA_MIXED_BF16, gba.GBA_ACC_CAMERA_PASS)])
 def test_bal1m_mixed_final_cost_and_solution(precision, acc):
     gold = _bal1m_golden()
     sc = synth.make_scene("bal1m", seed=0)
@@ -382,8 +405,8 @@ def test_bal1m_mixed_final_cost_and_solution(precision, acc):
 def test_bal8m_proxy_bf16_against_oracle(acc):
     """The at-scale configuration's precision policy (BF16 Jacobian copy, 15
     trials, tracks 2 + Geometric(1/7)) on its one-tenth proxy, against the
-    oracle's stored solve; also through the global accumulation scheme the
-    full-size workload uses."""
+    oracle's stored solve; also through the two-pass scheme the full-size
+    workload uses."""
     path = os.path.join(GOLD, "bal8m_proxy_seed0.json")
     if not os.path.exists(path):
         pytest.skip("golden file absent")
@@ -404,7 +427,7 @@ def test_bal8m_proxy_bf16_against_oracle(acc):
 # ------------------------------------------------- 10k cameras, 8M obs --
 def test_bal8m_bf16_full_size():
     """The at-scale workload (10,000 cameras: the camera vector exceeds LDS,
-    so the point passes accumulate globally), BF16 Jacobian copy, 15 trials.
+    so the Schur products take two passes), BF16 Jacobian copy, 15 trials.
     The oracle cannot solve it (a 90k x 90k dense camera block), so it checks
     what holds at any size: the reported initial and final costs equal the
     oracle's cost at the start and at the returned parameters, accepted
