@@ -126,8 +126,7 @@ typedef struct gba_options {
                                   the device graph is built.                  */
     int tiles_per_block;       /* point tiles (whole points, <= 64 edges) per
                                   workgroup of the point passes; 0 (default):
-                                  max(16, n_tiles / n_CU) with LDS partials, 16
-                                  in the two-pass scheme.  Read when the device
+                                  max(16, n_tiles / n_CU).  Read when the device
                                   graph is built; the server takes its sizes
                                   from gba_server_config instead.             */
     int reserved[5];

@@ -45,6 +45,91 @@ __device__ __forceinline__ bf16 jac_store<bf16>(double x) { return to_bf16((floa
 template <typename JS>
 __device__ __forceinline__ double jac_round(double x) { return (double)to_float(jac_store<JS>(x)); }
 
+// ------------------------------------------------ stored Jacobian layout
+// 24 entries per edge, in the order jc[0][0..8], jc[1][0..8], jp[0][0..2],
+// jp[1][0..2], packed into 16-byte chunks of 2 (FP64), 4 (FP32) or 8 (BF16)
+// entries.  Chunk c of edge e is 16-byte element ((e / 64) * n + c) * 64 +
+// e % 64 (n chunks per edge): a wavefront reading chunk c of 64 consecutive
+// edges reads one contiguous KiB with one 16-byte load per lane.
+union Chunk16 {
+    uint4 u;
+    double d[2];
+    float f[4];
+    uint16_t h[8];
+};
+
+template <typename JS> struct JacPack;
+template <> struct JacPack<double> { static constexpr int kPer = 2; };
+template <> struct JacPack<float> { static constexpr int kPer = 4; };
+template <> struct JacPack<bf16> { static constexpr int kPer = 8; };
+
+__host__ __device__ __forceinline__ size_t jac_chunk(int e, int c, int n) {
+    return ((size_t)(e >> 6) * n + c) * 64 + (e & 63);
+}
+
+__device__ __forceinline__ double chunk_get(const Chunk16& q, int s, double*) { return q.d[s]; }
+__device__ __forceinline__ double chunk_get(const Chunk16& q, int s, float*) { return (double)q.f[s]; }
+__device__ __forceinline__ double chunk_get(const Chunk16& q, int s, bf16*) {
+    return (double)__uint_as_float(((uint32_t)q.h[s]) << 16);
+}
+__device__ __forceinline__ void chunk_put(Chunk16& q, int s, double x, double*) { q.d[s] = x; }
+__device__ __forceinline__ void chunk_put(Chunk16& q, int s, double x, float*) { q.f[s] = (float)x; }
+__device__ __forceinline__ void chunk_put(Chunk16& q, int s, double x, bf16*) {
+    q.h[s] = to_bf16((float)x).v;
+}
+
+// the 24 stored entries of edge e (as FP64)
+template <typename JS>
+__device__ __forceinline__ void jac_load(const void* __restrict__ J, int e, double (&jc)[2][9],
+                                         double (&jp)[2][3]) {
+    constexpr int kPer = JacPack<JS>::kPer, kCh = 24 / kPer;
+    const uint4* __restrict__ src = (const uint4*)J;
+    double v[24];
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) {
+        Chunk16 q;
+        q.u = src[jac_chunk(e, c, kCh)];
+#pragma unroll
+        for (int s = 0; s < kPer; ++s) v[c * kPer + s] = chunk_get(q, s, (JS*)nullptr);
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        jc[0][a] = v[a];
+        jc[1][a] = v[9 + a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        jp[0][a] = v[18 + a];
+        jp[1][a] = v[21 + a];
+    }
+}
+
+// store the 24 entries of edge e, rounded to JS as jac_store<JS> does
+template <typename JS>
+__device__ __forceinline__ void jac_save(void* __restrict__ J, int e, const double (&jc)[2][9],
+                                         const double (&jp)[2][3]) {
+    constexpr int kPer = JacPack<JS>::kPer, kCh = 24 / kPer;
+    double v[24];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        v[a] = jc[0][a];
+        v[9 + a] = jc[1][a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        v[18 + a] = jp[0][a];
+        v[21 + a] = jp[1][a];
+    }
+    uint4* __restrict__ dst = (uint4*)J;
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) {
+        Chunk16 q;
+#pragma unroll
+        for (int s = 0; s < kPer; ++s) chunk_put(q, s, v[c * kPer + s], (JS*)nullptr);
+        dst[jac_chunk(e, c, kCh)] = q.u;
+    }
+}
+
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 

@@ -329,13 +329,12 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
         return GBA_ERR_UNSUPPORTED;
     }
     u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits;
-    // automatic: one point-pass workgroup per CU when each flushes an LDS
-    // camera partial (the flush grows with the workgroup count); small
-    // workgroups (more waves resident) in the two-pass scheme, which has none
+    // automatic: one point-pass workgroup per CU (each flushes one LDS camera
+    // partial; the flush grows with the workgroup count, and smaller
+    // workgroups measured slower in both schemes)
     const long long tpb = tune.tiles_per_block > 0
                               ? tune.tiles_per_block
-                              : u.cam_pass ? 16
-                                           : std::max<long long>(16, (st + dev.n_cu - 1) / std::max(1, dev.n_cu));
+                              : std::max<long long>(16, (st + dev.n_cu - 1) / std::max(1, dev.n_cu));
     const long long epb = tune.edges_per_block > 0 ? tune.edges_per_block
                                                    : std::max<long long>(256, (se + 2047) / 2048);
     const long long ppb = tune.pts_per_block > 0 ? tune.pts_per_block
@@ -410,8 +409,8 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.pt_c, sizeof(double) * 3 * NP);
     L.add(d.pt_init, sizeof(double) * 3 * NP);
     L.add(d.dpt, sizeof(double) * 3 * NP);
-    L.add(d.jc, jsz * 18 * NE);
-    L.add(d.jp, jsz * 6 * NE);
+    const size_t NE64 = (NE + 63) / 64 * 64;   // the stored Jacobian pads to whole 64-edge groups
+    L.add(d.jst, jsz * 24 * NE64);
     L.add(d.rw, tsz * 2 * NE);
     L.add(d.hpp, tsz * 6 * NP);
     L.add(d.bp, tsz * 3 * NP);
@@ -420,8 +419,7 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.bc, tsz * 9 * NC);
     L.add(d.hpp_inv, sizeof(double) * kHinvStride * NP);
     if (u.cam_pass) {
-        L.add(d.jc_cm, jsz * 18 * NE);
-        L.add(d.jp_cm, jsz * 6 * NE);
+        L.add(d.jst_cm, jsz * 24 * NE64);
         L.add(d.zbuf, sizeof(double) * 4 * NP);
     }
     L.add(d.minv, tsz * 45 * NC);

@@ -129,8 +129,8 @@ struct DeviceGraph {
     double* pt_init;
 
     // linearisation (T = double or float blocks; Jacobian FP64 / FP32 / BF16)
-    void* jc;                 // [18][ne] weighted Jacobian w.r.t. camera
-    void* jp;                 // [6][ne]  weighted Jacobian w.r.t. point
+    void* jst;                // stored weighted Jacobian, 24 entries per edge in 16-byte chunks
+                              // (layout: jac_chunk in gba_device.h), ceil(ne/64)*64 edges
     void* rw;                 // [2][ne]  weighted residual
     void* hpp;                // [6][np]
     void* bp;                 // [3][np]
@@ -138,8 +138,7 @@ struct DeviceGraph {
     void* wrun;               // [27][n_runs] W = sum_run J_c^T J_p per camera-major run
     void* bc;                 // [nc][9]
     double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per row
-    void* jc_cm;              // [18][ne] camera-major copy of jc (two-pass scheme only)
-    void* jp_cm;              // [6][ne]
+    void* jst_cm;             // camera-major copy of jst, same layout (two-pass scheme only)
     double* zbuf;             // [np][4] point vectors between the two passes
     void* minv;               // [nc][45] preconditioner inverse blocks
 
@@ -172,7 +171,7 @@ struct DeviceGraph {
     int lds_pp;               // dynamic LDS bytes of the point passes (9 x max cameras of a problem)
     int cam_pass;             // 1: a problem's camera vector exceeds LDS; the RHS and the
                               // Schur product take two passes (point-major: z_j into zbuf;
-                              // camera-major over jc_cm / jp_cm: sums per chunk)
+                              // camera-major over jst_cm: sums per chunk)
 };
 
 // ---- launchers (gba_kernels.hip) --------------------------------------

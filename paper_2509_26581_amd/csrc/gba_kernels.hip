@@ -30,8 +30,6 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
     const int l = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    JS* Jc = (JS*)g.jc;
-    JS* Jp = (JS*)g.jp;
     T* rw = (T*)g.rw;
     T* Hpp = (T*)g.hpp;
     T* bp = (T*)g.bp;
@@ -57,16 +55,7 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
             whiten<double, true>(ev, g.sinfo, ne, e, g.loss, g.delta, g.cam_fixed[i] != 0,
                             g.pt_fixed[j] != 0, s, rho, w);
             if (valid) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    Jc[k * ne + e] = jac_store<JS>(ev.jc[0][k]);
-                    Jc[(9 + k) * ne + e] = jac_store<JS>(ev.jc[1][k]);
-                }
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    Jp[k * ne + e] = jac_store<JS>(ev.jp[0][k]);
-                    Jp[(3 + k) * ne + e] = jac_store<JS>(ev.jp[1][k]);
-                }
+                jac_save<JS>(g.jst, e, ev.jc, ev.jp);
                 rw[e] = (T)ev.r[0];
                 rw[ne + e] = (T)ev.r[1];
                 if (raw.r) {
@@ -253,21 +242,8 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     jp[0][a] = jac_round<JS>(ev.jp[0][a]);
                     jp[1][a] = jac_round<JS>(ev.jp[1][a]);
                 }
-                if (g.cam_pass) {
-                    // camera-major copy of the stored Jacobian for the two-pass products
-                    JS* jcm = (JS*)g.jc_cm;
-                    JS* jpm = (JS*)g.jp_cm;
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        jcm[a * ne + q] = jac_store<JS>(jc[0][a]);
-                        jcm[(9 + a) * ne + q] = jac_store<JS>(jc[1][a]);
-                    }
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        jpm[a * ne + q] = jac_store<JS>(jp[0][a]);
-                        jpm[(3 + a) * ne + q] = jac_store<JS>(jp[1][a]);
-                    }
-                }
+                if (g.cam_pass)   // camera-major copy of the stored Jacobian (two-pass products)
+                    jac_save<JS>(g.jst_cm, q, jc, jp);
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
@@ -405,8 +381,7 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
 enum { kRhs = 0, kMatvec = 1, kBacksub = 2 };
 
 template <typename VT, typename JS, typename AT, int kMode>
-__global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const JS* __restrict__ Jc,
-                                                     const JS* __restrict__ Jp,
+__global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const void* __restrict__ J,
                                                      const VT* __restrict__ vin, AT* __restrict__ out) {
     // Arithmetic in FP64 whatever the storage type: the product chain
     // J_c p -> J_p^T -> Hpp^-1 -> J_p -> J_c^T and the final cancellation
@@ -429,7 +404,6 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
         __syncthreads();
     }
     const int nw = blockDim.x >> 6;
-    const int ne = g.ne;
     const VT* bp = (const VT*)g.bp;
     double red_m = 0.0, red_b = 0.0, red_s = 0.0;
     for (int t = tb + (int)(threadIdx.x >> 6); t < te; t += nw) {
@@ -445,16 +419,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
             int head, end;
             segment_of(starts, l, head, end);
             T jc[2][9], jp[2][3];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                jc[0][k] = load_as<T>(Jc[k * ne + e]);
-                jc[1][k] = load_as<T>(Jc[(9 + k) * ne + e]);
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                jp[0][k] = load_as<T>(Jp[k * ne + e]);
-                jp[1][k] = load_as<T>(Jp[(3 + k) * ne + e]);
-            }
+            jac_load<JS>(J, e, jc, jp);
             T z[3];
             T pc[9];
             if (kMode == kRhs) {
@@ -552,17 +517,17 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                     if (ch + l < n) {
                         const int e = e0 + ch + l;
                         const int i = g.e_cam[e];
+                        T jc[2][9], jp[2][3];
+                        jac_load<JS>(J, e, jc, jp);
                         T a0 = 0, a1 = 0;
 #pragma unroll
                         for (int k = 0; k < 9; ++k) {
                             const T pk = (T)vin[9 * i + k];
-                            a0 += load_as<T>(Jc[k * ne + e]) * pk;
-                            a1 += load_as<T>(Jc[(9 + k) * ne + e]) * pk;
+                            a0 += jc[0][k] * pk;
+                            a1 += jc[1][k] * pk;
                         }
 #pragma unroll
-                        for (int k = 0; k < 3; ++k)
-                            tt[k] += load_as<T>(Jp[k * ne + e]) * a0 +
-                                     load_as<T>(Jp[(3 + k) * ne + e]) * a1;
+                        for (int k = 0; k < 3; ++k) tt[k] += jp[0][k] * a0 + jp[1][k] * a1;
                     }
                 }
 #pragma unroll
@@ -606,26 +571,26 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                 if (ch + l < n) {
                     const int e = e0 + ch + l;
                     const int i = g.e_cam[e];
+                    T jc[2][9], jp[2][3];
+                    jac_load<JS>(J, e, jc, jp);
                     T u0 = 0, u1 = 0;
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        u0 += load_as<T>(Jp[k * ne + e]) * z[k];
-                        u1 += load_as<T>(Jp[(3 + k) * ne + e]) * z[k];
+                        u0 += jp[0][k] * z[k];
+                        u1 += jp[1][k] * z[k];
                     }
                     if (kMode == kBacksub) {
 #pragma unroll
                         for (int k = 0; k < 9; ++k) {
                             const T pk = (T)vin[9 * i + k];
-                            u0 += load_as<T>(Jc[k * ne + e]) * pk;
-                            u1 += load_as<T>(Jc[(9 + k) * ne + e]) * pk;
+                            u0 += jc[0][k] * pk;
+                            u1 += jc[1][k] * pk;
                         }
                         red_m += (double)u0 * (double)u0 + (double)u1 * (double)u1;
                     } else {
 #pragma unroll
                         for (int k = 0; k < 9; ++k)
-                            atomicAdd(&acc_lds[9 * (i - c0) + k],
-                                      (AT)(load_as<T>(Jc[k * ne + e]) * u0 +
-                                           load_as<T>(Jc[(9 + k) * ne + e]) * u1));
+                            atomicAdd(&acc_lds[9 * (i - c0) + k], (AT)(jc[0][k] * u0 + jc[1][k] * u1));
                     }
                 }
             }
@@ -645,8 +610,11 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
     }
     if (cpass) return;
     __syncthreads();
-    AT* dst = out + g.pp_part_off[blockIdx.x];
-    for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = acc_lds[k];
+    // the flushed partial vector in the storage type of the PCG vectors: the
+    // LDS sums are FP64, each partial is rounded once (FP32 in the mixed
+    // modes halves the flush and the reduction's reads)
+    VT* dst = (VT*)out + g.pp_part_off[blockIdx.x];
+    for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = (VT)acc_lds[k];
 }
 
 // ==========================================================================
@@ -667,7 +635,7 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
     const int k = kb + cl;
     const int kl = k - 9 * g.prob_cam_off[prob];          // component within the problem
     const int q0 = g.dc_pp.prob_blk[prob], q1 = g.dc_pp.prob_blk[prob + 1];
-    const double* part = g.cam_partial;
+    const T* part = (const T*)g.cam_partial;   // flushed in the vector type
     double s = 0.0;
     if (g.cam_pass) {
         // two-pass scheme: the camera's chunk sums from k_cam_pass
@@ -1055,9 +1023,6 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
     const int cam = g.chunk_cam[chunk];
     if (kMode == kMatvec && g.pcg[g.cam_prob[cam]].done) return;   // converged
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
-    const JS* __restrict__ Jc = (const JS*)g.jc_cm;
-    const JS* __restrict__ Jp = (const JS*)g.jp_cm;
-    const int ne = g.ne;
     double y[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) y[k] = 0.0;
@@ -1066,14 +1031,12 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
         const int j = g.cm_pt[q0];
         const double z0 = g.zbuf[4 * j], z1 = g.zbuf[4 * j + 1], z2 = g.zbuf[4 * j + 2];
         for (int q = q0; q < q1; ++q) {
-            const double u0 = load_as<double>(Jp[q]) * z0 + load_as<double>(Jp[ne + q]) * z1 +
-                              load_as<double>(Jp[2 * ne + q]) * z2;
-            const double u1 = load_as<double>(Jp[3 * ne + q]) * z0 +
-                              load_as<double>(Jp[4 * ne + q]) * z1 +
-                              load_as<double>(Jp[5 * ne + q]) * z2;
+            double jc[2][9], jp[2][3];
+            jac_load<JS>(g.jst_cm, q, jc, jp);
+            const double u0 = jp[0][0] * z0 + jp[0][1] * z1 + jp[0][2] * z2;
+            const double u1 = jp[1][0] * z0 + jp[1][1] * z1 + jp[1][2] * z2;
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-                y[k] += load_as<double>(Jc[k * ne + q]) * u0 + load_as<double>(Jc[(9 + k) * ne + q]) * u1;
+            for (int k = 0; k < 9; ++k) y[k] += jc[0][k] * u0 + jc[1][k] * u1;
         }
     }
     const int w = threadIdx.x >> 6;
@@ -1219,19 +1182,19 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, 
 }
 
 template <typename VT, typename JS, typename AT, int kMode>
-static void point_pass(const DeviceGraph& g, hipStream_t s, const void* jc, const void* jp,
-                       const void* vin, void* out) {
+static void point_pass(const DeviceGraph& g, hipStream_t s, const void* vin, void* out) {
     if (g.dc_pp.nblk == 0) return;
-    // allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per CU)
+    // dynamic LDS: the FP64 camera partials of the product and the RHS, beyond
+    // the 64 KiB default (gfx950 has 160 KiB per CU)
+    const int lds = kMode == kBacksub ? 0 : g.lds_pp;
     static int lds_set = -1;
-    if (kMode != kBacksub && g.lds_pp > 0 && lds_set < g.lds_pp) {
+    if (lds > 0 && lds_set < lds) {
         (void)hipFuncSetAttribute((const void*)k_point_pass<VT, JS, AT, kMode>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_pp);
-        lds_set = g.lds_pp;
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        lds_set = lds;
     }
     hipLaunchKernelGGL((k_point_pass<VT, JS, AT, kMode>), dim3(g.dc_pp.nblk), dim3(g.block_pp),
-                       kMode == kBacksub ? 0 : g.lds_pp, s, g, (const JS*)jc, (const JS*)jp,
-                       (const VT*)vin, (AT*)out);
+                       lds, s, g, (const void*)g.jst, (const VT*)vin, (AT*)out);
 }
 
 // Two-pass scheme, camera-major pass of the RHS or of the Schur product.
@@ -1263,13 +1226,13 @@ hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
         return hipSuccess;
     }
     if (g.mode == kModeFP64) {
-        point_pass<double, double, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+        point_pass<double, double, double, kRhs>(g, s, nullptr, g.cam_partial);
         hipLaunchKernelGGL((k_reduce<double, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
     } else {
         if (g.mode == kModeFP32)
-            point_pass<float, float, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+            point_pass<float, float, double, kRhs>(g, s, nullptr, g.cam_partial);
         else
-            point_pass<float, bf16, double, kRhs>(g, s, g.jc, g.jp, nullptr, g.cam_partial);
+            point_pass<float, bf16, double, kRhs>(g, s, nullptr, g.cam_partial);
         hipLaunchKernelGGL((k_reduce<float, kRhs>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, 0.0, 0.0);
     }
     GBA_CHECK_LAUNCH();
@@ -1292,11 +1255,11 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
 hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;
     if (g.mode == kModeFP64) {
-        point_pass<double, double, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
+        point_pass<double, double, double, kMatvec>(g, s, g.v_p, g.cam_partial);
     } else if (g.mode == kModeFP32) {
-        point_pass<float, float, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
+        point_pass<float, float, double, kMatvec>(g, s, g.v_p, g.cam_partial);
     } else {
-        point_pass<float, bf16, double, kMatvec>(g, s, g.jc, g.jp, g.v_p, g.cam_partial);
+        point_pass<float, bf16, double, kMatvec>(g, s, g.v_p, g.cam_partial);
     }
     if (g.cam_pass) cam_pass<kMatvec>(g, s);
     GBA_CHECK_LAUNCH();
@@ -1329,13 +1292,13 @@ hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL(k_cam_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        point_pass<double, double, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+        point_pass<double, double, double, kBacksub>(g, s, g.v_x, nullptr);
     } else {
         hipLaunchKernelGGL(k_cam_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
         if (g.mode == kModeFP32)
-            point_pass<float, float, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+            point_pass<float, float, double, kBacksub>(g, s, g.v_x, nullptr);
         else
-            point_pass<float, bf16, double, kBacksub>(g, s, g.jc, g.jp, g.v_x, nullptr);
+            point_pass<float, bf16, double, kBacksub>(g, s, g.v_x, nullptr);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
