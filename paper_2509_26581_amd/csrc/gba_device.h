@@ -186,6 +186,44 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
     return s;
 }
 
+// ------------------------------------------- camera-vector gathers
+// The 9 entries of camera i of a [nc][9] vector with 16-byte loads: the
+// aligned chunks covering them (3 for FP32, 5 for FP64) and a select of the
+// start.  May read up to 12 (FP32) / 8 (FP64) bytes past the last camera;
+// the vectors are allocated with that slack.
+__device__ __forceinline__ uint32_t pick32(uint32_t a, uint32_t b, uint32_t m) {
+    return (a & ~m) | (b & m);   // m = 0: a, m = ~0: b (bitwise, no memory select)
+}
+
+__device__ __forceinline__ void gather9(const float* __restrict__ v, int i, double (&out)[9]) {
+    const size_t w = 9 * (size_t)i;
+    const uint4* b = (const uint4*)(v + (w & ~(size_t)3));
+    const uint32_t m1 = (w & 1) ? ~0u : 0u, m2 = (w & 2) ? ~0u : 0u;
+    const uint4 c0 = b[0], c1 = b[1], c2 = b[2];
+    const uint32_t q[12] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x, c2.y, c2.z, c2.w};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint32_t lo = pick32(q[k], q[k + 1], m1);
+        const uint32_t hi = pick32(q[k + 2], q[k + 3], m1);
+        out[k] = (double)__uint_as_float(pick32(lo, hi, m2));
+    }
+}
+
+__device__ __forceinline__ void gather9(const double* __restrict__ v, int i, double (&out)[9]) {
+    const size_t w = 9 * (size_t)i;
+    const uint4* b = (const uint4*)(v + (w & ~(size_t)1));
+    const uint32_t m = (w & 1) ? ~0u : 0u;
+    const uint4 c0 = b[0], c1 = b[1], c2 = b[2], c3 = b[3], c4 = b[4];
+    const uint32_t q[20] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x, c2.y,
+                            c2.z, c2.w, c3.x, c3.y, c3.z, c3.w, c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint32_t lo = pick32(q[2 * k], q[2 * k + 2], m);
+        const uint32_t hi = pick32(q[2 * k + 1], q[2 * k + 3], m);
+        out[k] = __hiloint2double((int)hi, (int)lo);
+    }
+}
+
 // ------------------------------------------------------ BAL camera model
 // r = f (1 + k1 |p|^2 + k2 |p|^4) p - obs with p = -(P_x, P_y) / P_z and
 // P = R(w) X + t; jc = dr/d(w, t, f, k1, k2), jp = dr/dX.

@@ -240,7 +240,7 @@ namespace {
 
 // Problem-aligned decomposition of item ranges [off[p], off[p+1]) into
 // workgroups of at most `per_block` items, split evenly inside a problem.
-HostDecomp make_decomp(const std::vector<int>& off, long long per_block) {
+HostDecomp make_decomp(const std::vector<int>& off, long long per_block, bool aligned = false) {
     HostDecomp d;
     const int P = (int)off.size() - 1;
     d.prob_blk.resize(P + 1);
@@ -251,8 +251,11 @@ HostDecomp make_decomp(const std::vector<int>& off, long long per_block) {
         if (n <= 0) continue;
         const long long nb = (n + per_block - 1) / per_block;
         for (long long q = 0; q < nb; ++q) {
-            d.blk.push_back((int)(off[p] + n * q / nb));
-            d.blk.push_back((int)(off[p] + n * (q + 1) / nb));
+            // even split, or full blocks from the problem's start (aligned)
+            const long long b = aligned ? per_block * q : n * q / nb;
+            const long long e = aligned ? std::min(n, per_block * (q + 1)) : n * (q + 1) / nb;
+            d.blk.push_back((int)(off[p] + b));
+            d.blk.push_back((int)(off[p] + e));
             d.blk.push_back(p);
         }
     }
@@ -342,7 +345,7 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     std::vector<int> comp(P + 1);
     for (int p = 0; p <= P; ++p) comp[p] = 9 * u.cam_off[p];
     u.pp = make_decomp(u.tile_off, tpb);
-    u.red = make_decomp(comp, kRedComps);
+    u.red = make_decomp(comp, kRedComps, true);   // 16-byte aligned partial reads
     u.cam = make_decomp(u.cam_off, kCamsPerBlock);
     u.edges = make_decomp(u.edge_off, epb);
     u.pts = make_decomp(u.pt_off, ppb);
@@ -351,8 +354,8 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     for (int p = 0; p < P && !u.cam_pass; ++p) {
         const int ncp = u.cam_off[p + 1] - u.cam_off[p];
         for (int q = u.pp.prob_blk[p]; q < u.pp.prob_blk[p + 1]; ++q) {
-            u.part_off[q] = (int)part;          // one partial vector per workgroup
-            part += 9LL * ncp;
+            u.part_off[q] = (int)part;          // one partial vector per workgroup,
+            part += (9LL * ncp + 3) / 4 * 4;    // 16-byte aligned (read 16 bytes per lane)
         }
     }
     if (part > std::numeric_limits<int>::max()) {
@@ -415,18 +418,15 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.hpp, tsz * 6 * NP);
     L.add(d.bp, tsz * 3 * NP);
     L.add(d.hcc, tsz * 45 * NC);
-    L.add(d.wrun, tsz * 27 * (size_t)std::max(1, u.tot.n_runs));
     L.add(d.bc, tsz * 9 * NC);
     L.add(d.hpp_inv, sizeof(double) * kHinvStride * NP);
-    if (u.cam_pass) {
-        L.add(d.jst_cm, jsz * 24 * NE64);
-        L.add(d.zbuf, sizeof(double) * 4 * NP);
-    }
+    L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
+    if (u.cam_pass) L.add(d.zbuf, sizeof(double) * 4 * NP);
     L.add(d.minv, tsz * 45 * NC);
-    L.add(d.v_x, tsz * 9 * NC);
+    L.add(d.v_x, tsz * 9 * NC + 64);   // slack: 16-byte gathers (gather9)
     L.add(d.v_r, tsz * 9 * NC);
     L.add(d.v_z, tsz * 9 * NC);
-    L.add(d.v_p, tsz * 9 * NC);
+    L.add(d.v_p, tsz * 9 * NC + 64);
     L.add(d.v_q, tsz * 9 * NC);
     L.add(d.v_best, tsz * 9 * NC);
     decomp(d.dc_pp, u.pp);

@@ -21,6 +21,8 @@ constexpr int kChunkRuns = 1024;      // camera-major runs per workgroup chunk
 constexpr int kHinvStride = 8;        // padded row of the damped inverse point blocks
 constexpr int kCamsPerBlock = 28;     // cameras per PCG-vector workgroup (252 components)
 constexpr int kPcgBlock = 256;        // threads of the PCG-vector workgroups
+constexpr int kFusedUpdateProbs = 256;    // PCG finisher updates the vectors itself up to
+constexpr int kFusedUpdateComps = 12288;  // this many problems and reduced-system components
 constexpr int kRedComps = 64;         // components per partial-reduction workgroup
 constexpr int kMaxProblems = 4096;    // problems per device graph
 #ifndef GBA_PP_BLOCK
@@ -135,10 +137,9 @@ struct DeviceGraph {
     void* hpp;                // [6][np]
     void* bp;                 // [3][np]
     void* hcc;                // [nc][45]
-    void* wrun;               // [27][n_runs] W = sum_run J_c^T J_p per camera-major run
     void* bc;                 // [nc][9]
     double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per row
-    void* jst_cm;             // camera-major copy of jst, same layout (two-pass scheme only)
+    void* jst_cm;             // camera-major copy of jst, same layout
     double* zbuf;             // [np][4] point vectors between the two passes
     void* minv;               // [nc][45] preconditioner inverse blocks
 
@@ -173,6 +174,18 @@ struct DeviceGraph {
                               // Schur product take two passes (point-major: z_j into zbuf;
                               // camera-major over jst_cm: sums per chunk)
 };
+
+// The storage types a kernel is instantiated with must be those of the
+// graph's precision mode (another type would address the buffers with the
+// wrong strides, past their ends); kernels check and return at once.
+template <typename VT>
+__device__ __forceinline__ bool vec_type_ok(const DeviceGraph& g) {
+    return (sizeof(VT) == 8) == (g.mode == kModeFP64);
+}
+template <typename JS>
+__device__ __forceinline__ bool jac_type_ok(const DeviceGraph& g) {
+    return sizeof(JS) == (size_t)g.jac_bytes;
+}
 
 // ---- launchers (gba_kernels.hip) --------------------------------------
 // debug outputs of gba_eval_edges, point-major, all may be null

@@ -27,6 +27,7 @@ namespace gba {
 // ==========================================================================
 template <typename T, typename JS>
 __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
+    if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     const int l = lane_id();
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(256) void k_cost(DeviceGraph g, const double* __res
 // ==========================================================================
 template <typename T>
 __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_diag, double max_diag) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ double red[16];
     int pb, pe;
     const int prob = decomp_block(g.dc_pts, blockIdx.x, pb, pe);
@@ -194,15 +196,17 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_d
 // workgroup per chunk of one camera's runs; partial sums per chunk.
 //   kAssemble: recompute the run's edge Jacobians from the parameters (no
 //              gathers of stored Jacobians) and sum Hcc_i = sum J_c^T J_c
-//              (45 unique), bc_i = sum J_c^T r (9); store the run's coupling
-//              block W = sum_run J_c^T J_p (9x3) for the preconditioner.
-//   kPrecond:  sum over runs of W Hpp_lambda^{-1} W^T: the point-elimination
-//              term of the 9x9 diagonal block of the Schur complement.
+//              (45 unique), bc_i = sum J_c^T r (9); store the rounded
+//              Jacobian in camera-major order (jst_cm).
+//   kPrecond:  sum over runs of W Hpp_lambda^{-1} W^T, W = sum over the run's
+//              edges of J_c^T J_p, from jst_cm: the point-elimination term of
+//              the 9x9 diagonal block of the Schur complement.
 // ==========================================================================
 enum { kAssemble = 0, kPrecond = 1 };
 
 template <typename T, typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
+    if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     constexpr int K = kMode == kAssemble ? 54 : 45;
     __shared__ double red[4][K];
     const int chunk = blockIdx.x;
@@ -213,8 +217,6 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     const int ne = g.ne;
-    const int nr = g.n_runs;
-    T* __restrict__ wrun = (T*)g.wrun;
     for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
         const int q0 = g.cm_run_off[run];
         const int j = g.cm_pt[q0];
@@ -222,15 +224,15 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
         if (kMode == kAssemble) {
             const int q1 = g.cm_run_off[run + 1];
             const bool pfix = g.pt_fixed[j] != 0;
-#pragma unroll
-            for (int a = 0; a < 9; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) W[a][b] = 0;
             for (int q = q0; q < q1; ++q) {
                 EdgeEval<double> ev;
                 bal_eval<double, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
                 double s, rho, w;
                 whiten<double, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
+                // gradient from the unrounded Jacobian, before it is rounded
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+                    acc[45 + a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
                 double jc[2][9], jp[2][3];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
@@ -242,48 +244,75 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     jp[0][a] = jac_round<JS>(ev.jp[0][a]);
                     jp[1][a] = jac_round<JS>(ev.jp[1][a]);
                 }
-                if (g.cam_pass)   // camera-major copy of the stored Jacobian (two-pass products)
-                    jac_save<JS>(g.jst_cm, q, jc, jp);
+                // camera-major copy of the stored Jacobian (the preconditioner
+                // pass and the two-pass products read it)
+                jac_save<JS>(g.jst_cm, q, jc, jp);
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
 #pragma unroll
                     for (int b = a; b < 9; ++b, ++k)
                         acc[k] += jc[0][a] * jc[0][b] + jc[1][a] * jc[1][b];
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    acc[45 + a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
-#pragma unroll
-                    for (int b = 0; b < 3; ++b)
-                        W[a][b] += jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
-                }
             }
-#pragma unroll
-            for (int a = 0; a < 9; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) wrun[(3 * a + b) * nr + run] = (T)W[a][b];
         } else {
-#pragma unroll
-            for (int a = 0; a < 9; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) W[a][b] = (double)wrun[(3 * a + b) * nr + run];
+            const int q1 = g.cm_run_off[run + 1];
             double Hi[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Hi[r][c] = g.hpp_inv[kHinvStride * j + sym3(r, c)];
-            double WH[9][3];
+            double jc[2][9], jp[2][3];
+            jac_load<JS>(g.jst_cm, q0, jc, jp);
+            if (q1 - q0 == 1) {
+                // one edge: W Hpp^-1 W^T = J_c^T A J_c with the 2x2
+                // A = J_p Hpp^-1 J_p^T (fewer operations than forming W)
+                double JH[2][3];
 #pragma unroll
-            for (int a = 0; a < 9; ++a)
+                for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    WH[a][c] = W[a][0] * Hi[0][c] + W[a][1] * Hi[1][c] + W[a][2] * Hi[2][c];
-            int k = 0;
+                    for (int c = 0; c < 3; ++c)
+                        JH[r][c] = jp[r][0] * Hi[0][c] + jp[r][1] * Hi[1][c] + jp[r][2] * Hi[2][c];
+                const double A00 = JH[0][0] * jp[0][0] + JH[0][1] * jp[0][1] + JH[0][2] * jp[0][2];
+                const double A01 = JH[0][0] * jp[1][0] + JH[0][1] * jp[1][1] + JH[0][2] * jp[1][2];
+                const double A11 = JH[1][0] * jp[1][0] + JH[1][1] * jp[1][1] + JH[1][2] * jp[1][2];
+                double AJ[2][9];
 #pragma unroll
-            for (int a = 0; a < 9; ++a)
+                for (int b = 0; b < 9; ++b) {
+                    AJ[0][b] = A00 * jc[0][b] + A01 * jc[1][b];
+                    AJ[1][b] = A01 * jc[0][b] + A11 * jc[1][b];
+                }
+                int k = 0;
 #pragma unroll
-                for (int b = a; b < 9; ++b, ++k)
-                    acc[k] += WH[a][0] * W[b][0] + WH[a][1] * W[b][1] + WH[a][2] * W[b][2];
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int b = a; b < 9; ++b, ++k)
+                        acc[k] += jc[0][a] * AJ[0][b] + jc[1][a] * AJ[1][b];
+            } else {
+                // several edges on one (camera, point) pair: W = sum J_c^T J_p
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) W[a][b] = jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
+                for (int q = q0 + 1; q < q1; ++q) {
+                    jac_load<JS>(g.jst_cm, q, jc, jp);
+#pragma unroll
+                    for (int a = 0; a < 9; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) W[a][b] += jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
+                }
+                double WH[9][3];
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        WH[a][c] = W[a][0] * Hi[0][c] + W[a][1] * Hi[1][c] + W[a][2] * Hi[2][c];
+                int k = 0;
+#pragma unroll
+                for (int a = 0; a < 9; ++a)
+#pragma unroll
+                    for (int b = a; b < 9; ++b, ++k)
+                        acc[k] += WH[a][0] * W[b][0] + WH[a][1] * W[b][1] + WH[a][2] * W[b][2];
+            }
         }
     }
     // workgroup reduction of the K accumulators
@@ -309,6 +338,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 template <typename T, int kMode>
 __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_diag, double max_diag,
                                                      int block_jacobi) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ double Ms[54];
     const int i = blockIdx.x;
     const double lambda = kMode == kPrecond ? fabs(g.lam[g.cam_prob[i]]) : 0.0;
@@ -383,6 +413,7 @@ enum { kRhs = 0, kMatvec = 1, kBacksub = 2 };
 template <typename VT, typename JS, typename AT, int kMode>
 __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const void* __restrict__ J,
                                                      const VT* __restrict__ vin, AT* __restrict__ out) {
+    if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     // Arithmetic in FP64 whatever the storage type: the product chain
     // J_c p -> J_p^T -> Hpp^-1 -> J_p -> J_c^T and the final cancellation
     // against Hcc p amplify rounding, and FP64 costs nothing in this
@@ -414,7 +445,8 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
             const int e = e0 + (valid ? l : 0);
             const int j = g.e_pt[e];
             const int i = g.e_cam[e];
-            const bool st = !valid || l == 0 || g.e_pt[e - 1] != j;
+            const int jprev = __shfl_up(j, 1);   // the previous edge of the tile
+            const bool st = !valid || l == 0 || jprev != j;
             const uint64_t starts = __ballot(st);
             int head, end;
             segment_of(starts, l, head, end);
@@ -430,8 +462,16 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                 z[1] = h01 * b0 + h11 * b1 + h12 * b2;
                 z[2] = h02 * b0 + h12 * b1 + h22 * b2;
             } else {
+                // the point block is loaded by every lane of the point at the
+                // start (the head lane applies it), next to the camera gather
+                const double* H = g.hpp_inv + kHinvStride * j;
+                const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
+                if constexpr (sizeof(VT) == 8) {
+                    gather9(vin, i, pc);   // 5 aligned 16-byte loads instead of 9 scalar ones
+                } else {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) pc[k] = (T)vin[9 * i + k];
+                    for (int k = 0; k < 9; ++k) pc[k] = (T)vin[9 * i + k];
+                }
                 T a0 = 0, a1 = 0;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
@@ -447,8 +487,6 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                 // head lane applies the point block
                 T zz[3] = {0, 0, 0};
                 if (valid && head == l) {
-                    const double* H = g.hpp_inv + kHinvStride * j;
-                    const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
                     T v0 = tt[0], v1 = tt[1], v2 = tt[2];
                     if (kMode == kBacksub) {
                         v0 += bp[j];
@@ -625,60 +663,103 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
 // ==========================================================================
 template <typename T, int kMode>
 __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag, double max_diag) {
-    __shared__ double red[16][64];
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
+    // The partial vectors are read with one 16-byte load per lane: a row of
+    // kRedComps components is kCols lanes, and kGroups rows are summed at once
+    // (each partial vector starts on a 16-byte boundary, padded to 4 entries).
+    constexpr int kCpl = 16 / (int)sizeof(T);
+    constexpr int kCols = kRedComps / kCpl;
+    constexpr int kGroups = 1024 / kCols;
+    __shared__ double red[kGroups][kRedComps];
     __shared__ double dred[16];
     int kb, ke;
     const int prob = decomp_block(g.dc_red, blockIdx.x, kb, ke);
     if (kMode == kMatvec && g.pcg[prob].done) return;   // PCG of this problem converged
-    const int cl = threadIdx.x & 63;
-    const int grp = threadIdx.x >> 6;
-    const int k = kb + cl;
-    const int kl = k - 9 * g.prob_cam_off[prob];          // component within the problem
-    const int q0 = g.dc_pp.prob_blk[prob], q1 = g.dc_pp.prob_blk[prob + 1];
-    const T* part = (const T*)g.cam_partial;   // flushed in the vector type
-    double s = 0.0;
-    if (g.cam_pass) {
-        // two-pass scheme: the camera's chunk sums from k_cam_pass
-        if (grp == 0 && k < ke) {
-            const int i = k / 9, r = k % 9;
-            for (int c = g.cam_chunk_off[i]; c < g.cam_chunk_off[i + 1]; ++c)
-                s += g.chunk_partial[54 * c + r];
-        }
-    } else if (k < ke) {
-        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int q = q0 + grp;
-        for (; q + 48 < q1; q += 64) {
-            s += part[g.pp_part_off[q] + kl];
-            s1 += part[g.pp_part_off[q + 16] + kl];
-            s2 += part[g.pp_part_off[q + 32] + kl];
-            s3 += part[g.pp_part_off[q + 48] + kl];
-        }
-        for (; q < q1; q += 16) s += part[g.pp_part_off[q] + kl];
-        s += (s1 + s2) + s3;
-    }
-    red[grp][cl] = s;
-    __syncthreads();
-    double dot = 0.0;
-    if (grp == 0 && k < ke) {
-        double tot = 0.0;
-        for (int q = 0; q < 16; ++q) tot += red[q][cl];
-        const int i = k / 9, r = k % 9;
+    const int tid = threadIdx.x;
+    const int k = kb + tid;                               // component (threads < kRedComps)
+    const bool own = tid < kRedComps && k < ke;
+    // the damped diagonal block row and p (or bc) of this component are
+    // loaded before the partial sums, so their latency overlaps
+    const int i = k / 9, r = k % 9;
+    double h[9], pv[9], lambda = 0.0, bk = 0.0;
+    if (own) {
         if (kMode == kRhs) {
-            const T* bc = (const T*)g.bc;
-            ((T*)g.v_r)[k] = (T)(-(double)bc[k] + tot);
+            bk = (double)((const T*)g.bc)[k];
         } else {
-            const double lambda = fabs(g.lam[prob]);   // negative: problem idle this trial
+            lambda = fabs(g.lam[prob]);   // negative: problem idle this trial
             const T* Hcc = (const T*)g.hcc;
             const T* p = (const T*)g.v_p;
-            double hp = 0.0;
+#pragma unroll
             for (int c = 0; c < 9; ++c) {
-                double h = (double)Hcc[i * 45 + sym9(r, c)];
-                if (c == r) h += lambda * fmin(fmax(h, min_diag), max_diag);
-                hp += h * (double)p[9 * i + c];
+                h[c] = (double)Hcc[i * 45 + sym9(r, c)];
+                pv[c] = (double)p[9 * i + c];
+            }
+        }
+    }
+    double tot = 0.0;
+    if (g.cam_pass) {
+        // two-pass scheme: the camera's chunk sums from k_cam_pass
+        if (own)
+            for (int c = g.cam_chunk_off[i]; c < g.cam_chunk_off[i + 1]; ++c)
+                tot += g.chunk_partial[54 * c + r];
+    } else {
+        const int col = tid % kCols, grp = tid / kCols;
+        const int c0 = kCpl * col;                        // first component of this lane
+        const int kl = kb - 9 * g.prob_cam_off[prob] + c0;   // within the problem
+        const int q0 = g.dc_pp.prob_blk[prob], q1 = g.dc_pp.prob_blk[prob + 1];
+        const T* part = (const T*)g.cam_partial;   // flushed in the vector type
+        double a0[kCpl], a1[kCpl];
+#pragma unroll
+        for (int u = 0; u < kCpl; ++u) a0[u] = a1[u] = 0.0;
+        if (kb + c0 < ke) {
+            int q = q0 + grp;
+            for (; q + kGroups < q1; q += 2 * kGroups) {
+                Chunk16 x, y;
+                x.u = *(const uint4*)(part + g.pp_part_off[q] + kl);
+                y.u = *(const uint4*)(part + g.pp_part_off[q + kGroups] + kl);
+#pragma unroll
+                for (int u = 0; u < kCpl; ++u) {
+                    a0[u] += chunk_get(x, u, (T*)nullptr);
+                    a1[u] += chunk_get(y, u, (T*)nullptr);
+                }
+            }
+            if (q < q1) {
+                Chunk16 x;
+                x.u = *(const uint4*)(part + g.pp_part_off[q] + kl);
+#pragma unroll
+                for (int u = 0; u < kCpl; ++u) a0[u] += chunk_get(x, u, (T*)nullptr);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCpl; ++u) red[grp][c0 + u] = a0[u] + a1[u];
+        __syncthreads();
+        if (own) {
+            double t0 = 0.0, t1 = 0.0;
+            for (int q = 0; q < kGroups; q += 2) {
+                t0 += red[q][tid];
+                t1 += red[q + 1][tid];
+            }
+            tot = t0 + t1;
+        }
+    }
+    double dot = 0.0;
+    if (own) {
+        if (kMode == kRhs) {
+            ((T*)g.v_r)[k] = (T)(-bk + tot);
+        } else {
+            double hp = 0.0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                double hc = h[c];
+                if (c == r) hc += lambda * fmin(fmax(hc, min_diag), max_diag);
+                hp += hc * pv[c];
             }
             const double q = hp - tot;
             ((T*)g.v_q)[k] = (T)q;
-            dot = (double)p[k] * (double)(T)q;
+            double pk = pv[0];
+#pragma unroll
+            for (int c = 1; c < 9; ++c) pk = c == r ? pv[c] : pk;
+            dot = pk * (double)(T)q;
         }
     }
     if (kMode == kMatvec) {
@@ -727,6 +808,7 @@ __device__ __forceinline__ double wave_sum_blocks(const double* part, int stride
 // PCG start, vectors: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
     int cb, ce;
@@ -758,6 +840,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
 // PCG start, scalars: rz0, rr0, threshold per problem; p = z.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double tol, int relative) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int prob = w; prob < g.n_probs; prob += nw) {
         const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
@@ -786,38 +869,54 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
 // z = M^{-1} r; partial (r^T z, r^T r) per workgroup.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
     int cb, ce;
     const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
     const PcgState* st = g.pcg + prob;
-    if (st->done) return;
-    double pq = 0.0;
-    for (int b = g.dc_red.prob_blk[prob] + threadIdx.x; b < g.dc_red.prob_blk[prob + 1];
-         b += blockDim.x)
-        pq += g.pq_partial[b];
-    pq = block_sum(pq, red);
-    if (!(pq > 0.0) || !isfinite(pq)) return;   // breakdown: the finisher stops this PCG
-    const double alpha = st->rz / pq;
     const int tid = threadIdx.x;
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
+    // A finished PCG (the rest of a replayed chunk of iterations) exits
+    // after one load.  Otherwise every load of the step is issued before the
+    // next wait (the dot, alpha): two memory latencies instead of four.
+    if (st->done) return;
+    double pq = 0.0;
+    for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
+        pq += g.pq_partial[b];
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ r = (T*)g.v_r;
+    double xk = 0.0, pk = 0.0, qk = 0.0, rk = 0.0;
+    T m[9];
+    const int i = k / 9, a = k % 9;
+    if (valid) {
+        xk = (double)x[k];
+        pk = (double)((const T*)g.v_p)[k];
+        qk = (double)((const T*)g.v_q)[k];
+        rk = (double)r[k];
+        const T* __restrict__ Minv = (const T*)g.minv;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) m[b] = Minv[i * 45 + sym9(a, b)];
+    }
+    pq = block_sum(pq, red);
+    if (!(pq > 0.0) || !isfinite(pq)) return;   // breakdown: the finisher stops this PCG
+    const double alpha = st->rz / pq;
     T rv = 0;
     if (valid) {
-        const double pk = (double)((const T*)g.v_p)[k];
-        const double qk = (double)((const T*)g.v_q)[k];
-        x[k] = (T)((double)x[k] + alpha * pk);
-        rv = (T)((double)r[k] - alpha * qk);
+        x[k] = (T)(xk + alpha * pk);
+        rv = (T)(rk - alpha * qk);
         r[k] = rv;
     }
     r_lds[tid] = rv;
     __syncthreads();
     double rz = 0.0, rr = 0.0;
     if (valid) {
-        const int i = k / 9, a = k % 9;
-        const T zv = minv_row((const T*)g.minv, r_lds, i, a, tid - a);
+        const int base = tid - a;
+        double sz = 0.0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) sz += (double)m[b] * (double)r_lds[base + b];
+        const T zv = (T)sz;
         ((T*)g.v_z)[k] = zv;
         rz = (double)rv * (double)zv;
         rr = (double)rv * (double)rv;
@@ -832,21 +931,60 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
 
 // PCG step, scalars (single workgroup, one wavefront per problem): per
 // running problem convergence / iteration limit / rejection ratio /
-// breakdown, beta = r^T z / (r^T z)_old, and the vector work k_pcg_update
-// must do (PcgState::act, ::beta).
+// breakdown, beta = r^T z / (r^T z)_old, and the vector work of the step's
+// last phase (PcgState::act, ::beta).  kUpdate: for small reduced systems the
+// same workgroup also does that vector work (k_pcg_update's), which saves a
+// launch and its memory latencies; the decisions reach the threads via LDS.
+template <typename T, bool kUpdate>
 __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iters, double ratio) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
+    __shared__ int s_act[kUpdate ? kFusedUpdateProbs : 1];
+    __shared__ double s_beta[kUpdate ? kFusedUpdateProbs : 1];
+    // kUpdate: this thread's components of z and p are loaded before the
+    // scalar phase, so that their latency hides behind it
+    constexpr int kPer = kUpdate ? kFusedUpdateComps / 1024 : 1;
+    T zv[kPer], pv[kPer];
+    int pr[kPer];
+    const int n = 9 * g.nc;
+    T* __restrict__ x = (T*)g.v_x;
+    T* __restrict__ p = (T*)g.v_p;
+    const T* __restrict__ z = (const T*)g.v_z;
+    T* __restrict__ best = (T*)g.v_best;
+    if (kUpdate) {
+        // an idle replayed iteration (every PCG finished) exits at once; its
+        // PcgState::act stays as the finishing iteration left it, and no
+        // separate update kernel reads it
+        const bool running = (int)threadIdx.x < g.n_probs && !g.pcg[threadIdx.x].done;
+        if (!__syncthreads_or(running)) return;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int k = threadIdx.x + 1024 * u;
+            pr[u] = 0;
+            zv[u] = pv[u] = (T)0;
+            if (k < n) {
+                pr[u] = g.n_probs == 1 ? 0 : g.cam_prob[k / 9];
+                zv[u] = z[k];
+                pv[u] = p[k];
+            }
+        }
+    }
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int prob = w; prob < g.n_probs; prob += nw) {
         PcgState* st = g.pcg + prob;
-        if (st->done) {
-            if (lane_id() == 0) st->act = 0;
-            continue;
-        }
+        // the sums are formed before the state is read (their loads do not
+        // wait for it); a finished problem discards them
         const double pq = wave_sum_blocks(g.pq_partial, 1, 0, g.dc_red.prob_blk[prob],
                                           g.dc_red.prob_blk[prob + 1]);
         const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
         const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
         const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+        if (st->done) {
+            if (lane_id() == 0) {
+                st->act = 0;
+                if (kUpdate) s_act[prob] = 0;
+            }
+            continue;
+        }
         if (lane_id() == 0) {
             int done = 0, copy_best = 0;
             if (!(pq > 0.0) || !isfinite(pq)) {
@@ -865,12 +1003,30 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
                 if (!done && st->iters >= max_iters) done = 2;
             }
             const double rz_old = st->rz;
-            st->beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
-            st->act = (done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0);
+            const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
+            const int act = (done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0);
+            st->beta = beta;
+            st->act = act;
             if (copy_best) st->use_best = 1;
             if (done != 3) st->rz = rz;
             st->done = done;
+            if (kUpdate) {
+                s_act[prob] = act;
+                s_beta[prob] = beta;
+            }
         }
+    }
+    if (!kUpdate) return;
+    __syncthreads();
+    // p = z + beta p, best-iterate copy / restore
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int k = threadIdx.x + 1024 * u;
+        if (k >= n) continue;
+        const int act = s_act[pr[u]];
+        if (act & 1) p[k] = (T)((double)zv[u] + s_beta[pr[u]] * (double)pv[u]);
+        if (act & 2) best[k] = x[k];
+        if (act & 4) x[k] = best[k];
     }
 }
 
@@ -878,11 +1034,10 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
 // best-iterate copy / restore when the rejection ratio is enabled.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(DeviceGraph g) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     int cb, ce;
     const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
     const PcgState* st = g.pcg + prob;
-    const int act = st->act;
-    if (!act) return;
     const int tid = threadIdx.x;
     if (tid >= 9 * (ce - cb)) return;
     const int k = 9 * cb + tid;
@@ -890,7 +1045,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(DeviceGraph g) {
     T* __restrict__ p = (T*)g.v_p;
     const T* __restrict__ z = (const T*)g.v_z;
     T* __restrict__ best = (T*)g.v_best;
-    if (act & 1) p[k] = (T)((double)z[k] + st->beta * (double)p[k]);
+    // p and z are loaded before the state is known (one memory latency)
+    const double zk = (double)z[k], pk = (double)p[k];
+    const int act = st->act;
+    if (!act) return;
+    if (act & 1) p[k] = (T)(zk + st->beta * pk);
     if (act & 2) best[k] = x[k];
     if (act & 4) x[k] = best[k];
 }
@@ -901,6 +1060,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(DeviceGraph g) {
 // ==========================================================================
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_cam_update(DeviceGraph g) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ double red[16];
     int cb, ce;
     decomp_block(g.dc_cam, blockIdx.x, cb, ce);
@@ -1018,6 +1178,7 @@ __global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
 // ==========================================================================
 template <typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
+    if (!jac_type_ok<JS>(g)) return;   // instantiated for another mode
     __shared__ double red[4][9];
     const int chunk = blockIdx.x;
     const int cam = g.chunk_cam[chunk];
@@ -1057,6 +1218,7 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
 // Two-pass scheme, RHS first pass: z_j = Hpp_lambda^-1 bp_j for every point.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     const T* bp = (const T*)g.bp;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.np; j += gridDim.x * blockDim.x) {
         const double b0 = (double)bp[j], b1 = (double)bp[g.np + j], b2 = (double)bp[2 * g.np + j];
@@ -1167,10 +1329,13 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, 
                           int block_jacobi) {
     if (g.nc == 0) return hipSuccess;
     if (block_jacobi && g.n_chunks > 0) {
+        // the pass reads jst_cm: its storage type must be the mode's
         if (g.mode == kModeFP64)
             hipLaunchKernelGGL((k_cam_accumulate<double, double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
-        else
+        else if (g.mode == kModeFP32)
             hipLaunchKernelGGL((k_cam_accumulate<float, float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        else
+            hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
@@ -1266,6 +1431,12 @@ hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s) {
     return hipSuccess;
 }
 
+// the PCG finisher also updates the vectors when the reduced systems are
+// small enough for one workgroup to do it faster than a separate launch
+static bool fused_update(const DeviceGraph& g) {
+    return g.n_probs <= kFusedUpdateProbs && 9 * (long long)g.nc <= kFusedUpdateComps;
+}
+
 hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                            int max_iters, double ratio, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.nc == 0) return hipSuccess;
@@ -1276,13 +1447,21 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag,
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
-        hipLaunchKernelGGL(k_pcg_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        if (fused_update(g)) {
+            hipLaunchKernelGGL((k_pcg_finish<double, true>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        } else {
+            hipLaunchKernelGGL((k_pcg_finish<double, false>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+            hipLaunchKernelGGL(k_pcg_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        }
     } else {
         hipLaunchKernelGGL((k_reduce<float, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
-        hipLaunchKernelGGL(k_pcg_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        if (fused_update(g)) {
+            hipLaunchKernelGGL((k_pcg_finish<float, true>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+        } else {
+            hipLaunchKernelGGL((k_pcg_finish<float, false>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
+            hipLaunchKernelGGL(k_pcg_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        }
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
