@@ -54,7 +54,7 @@ typedef int gba_status;
 #define GBA_ERR_OOM (-5)          /* the allocator returned NULL             */
 #define GBA_ERR_HIP (-6)          /* a HIP runtime call failed               */
 #define GBA_ERR_STATE (-7)        /* call not valid in the current state     */
-#define GBA_ERR_UNSUPPORTED (-8)  /* configuration this build cannot run     */
+#define GBA_ERR_UNSUPPORTED (-8)  /* configuration the library cannot run   */
 #define GBA_ERR_BUDGET (-9)       /* serving: request larger than the budget */
 #define GBA_PENDING 1             /* serving: result not ready (not an error) */
 

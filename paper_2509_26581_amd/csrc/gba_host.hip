@@ -71,13 +71,22 @@ gba_status Batch::ensure_mirrors(int n, std::string& msg) {
     h_lam = nullptr;
     h_accept = nullptr;
     h_cap = 0;
-    if (hipHostMalloc((void**)&h_scal, sizeof(TrialScalars) * n, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h_pcg, sizeof(PcgState) * n, hipHostMallocDefault) != hipSuccess ||
+    d_scal_host = nullptr;
+    d_pcg_host = nullptr;
+    // the per-trial and per-chunk results come back through mapped, coherent
+    // pinned memory that the finishing kernels write (no copy per readback)
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void**)&h_scal, sizeof(TrialScalars) * n, mapped) != hipSuccess ||
+        hipHostMalloc((void**)&h_pcg, sizeof(PcgState) * n, mapped) != hipSuccess ||
         hipHostMalloc((void**)&h_lam, sizeof(double) * n, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h_accept, sizeof(int) * n, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&h_accept, sizeof(int) * n, hipHostMallocDefault) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&d_scal_host, h_scal, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&d_pcg_host, h_pcg, 0) != hipSuccess) {
         msg = "pinned host allocation failed";
         return GBA_ERR_HIP;
     }
+    std::memset(h_scal, 0, sizeof(TrialScalars) * n);
+    std::memset(h_pcg, 0, sizeof(PcgState) * n);
     h_cap = n;
     return GBA_OK;
 }
@@ -460,6 +469,8 @@ void set_union_scalars(Batch& b, int precision, int loss, double delta) {
     d.loss = loss;
     d.delta = delta;
     d.mode = precision;
+    d.pcg_host = b.d_pcg_host;
+    d.scal_host = b.d_scal_host;
     d.jac_bytes = precision == GBA_FP64 ? 8 : (precision == GBA_MIXED_FP32 ? 4 : 2);
     d.block_pp = kPointPassBlock;
     d.cam_pass = u.cam_pass ? 1 : 0;
@@ -616,9 +627,8 @@ gba_status build_batch(const std::vector<const HostProblem*>& probs, int precisi
 // ---------------------------------------------------------------- LM driver
 namespace {
 
+// h_scal is written by k_finish / k_cost_finish through its mapping
 gba_status read_scal(Batch& b, std::string& msg) {
-    HIP_OR(msg, hipMemcpyAsync(b.h_scal, b.dg.scal, sizeof(TrialScalars) * b.P,
-                               hipMemcpyDeviceToHost, b.stream));
     HIP_OR(msg, hipStreamSynchronize(b.stream));
     return GBA_OK;
 }
@@ -701,7 +711,7 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
             b.pcg_warm = true;
         }
         launched += c;
-        HIP_OR(msg, hipMemcpyAsync(b.h_pcg, d.pcg, sizeof(PcgState) * b.P, hipMemcpyDeviceToHost, s));
+        // h_pcg is written by the PCG finishers through its mapping
         HIP_OR(msg, hipStreamSynchronize(s));
         int max_iters_now = 0;
         bool all_done = true;

@@ -120,6 +120,8 @@ struct DeviceGraph {
     int* accept;              // [P] 1: commit the candidate of this problem
     PcgState* pcg;            // [P]
     TrialScalars* scal;       // [P]
+    PcgState* pcg_host;       // [P] mapped host copies written by the finishers, or null
+    TrialScalars* scal_host;  // [P]
 
     // parameters (FP64 master copies and candidates)
     double* cam;              // [nc][9]

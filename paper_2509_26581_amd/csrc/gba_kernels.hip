@@ -858,6 +858,7 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
             st->act = 0;
             st->beta = 0.0;
             st->done = g.lam[prob] < 0.0 ? 5 : ((rr <= st->thresh || !(rz > 0.0)) ? 1 : 0);
+            if (g.pcg_host) g.pcg_host[prob] = *st;
         }
     }
     const T* __restrict__ z = (const T*)g.v_z;
@@ -1010,6 +1011,7 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
             if (copy_best) st->use_best = 1;
             if (done != 3) st->rz = rz;
             st->done = done;
+            if (g.pcg_host) g.pcg_host[prob] = *st;
             if (kUpdate) {
                 s_act[prob] = act;
                 s_beta[prob] = beta;
@@ -1130,6 +1132,7 @@ __global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
             ts->x2 = t[7] + t[4];
             ts->pcg_iters = g.pcg[prob].iters;
             ts->pcg_reason = g.pcg[prob].done;
+            if (g.scal_host) g.scal_host[prob] = *ts;
         }
         __syncthreads();
     }
@@ -1154,6 +1157,7 @@ __global__ __launch_bounds__(1024) void k_cost_finish(DeviceGraph g) {
             double t = 0.0;
             for (int s2 = 0; s2 < wpp; ++s2) t += part[w + s2];
             g.scal[prob].cost = t;
+            if (g.scal_host) g.scal_host[prob].cost = t;
         }
         __syncthreads();
     }
