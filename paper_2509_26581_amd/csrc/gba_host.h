@@ -122,6 +122,8 @@ struct ProblemLM {
     std::vector<gba_trial> log;
 };
 
+constexpr int kMaxPcgChunk = 64;   // PCG iterations per replayed chunk, at most
+
 // One or more problems resident on the device.
 struct Batch {
     int precision = 0;
@@ -143,8 +145,11 @@ struct Batch {
         hipGraphExec_t exec = nullptr;
         int iters = 0, max_iters = 0;
         double min_diag = 0, max_diag = 0, ratio = 0;
-    } pcg_graph[2];
+    } pcg_graph[kMaxPcgChunk + 1];      // by chunk length
     void drop_graphs();
+    // PCG iterations of the last damped step (the largest over the problems):
+    // with graphs, the next step's first chunk is sized from it
+    int last_pcg_iters = 0;
     // pinned host mirrors of the per-problem device arrays (capacity h_cap)
     int h_cap = 0;
     TrialScalars* h_scal = nullptr;

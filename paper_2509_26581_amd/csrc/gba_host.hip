@@ -663,14 +663,23 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
                                o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0));
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[1], s));
     HIP_OR(msg, launch_pcg_init(d, s, o.pcg_tol, o.pcg_tol_relative));
-    const int chunk = std::max(1, std::min(64, tune.pcg_sync_every));
+    const int chunk = std::max(1, std::min(kMaxPcgChunk, tune.pcg_sync_every));
+    // With graphs, the first chunk is the previous step's PCG length less one
+    // (successive LM trials need similar counts) and the rest are chunks of
+    // two: fewer idle iterations replayed past convergence, usually one or
+    // two host checks.  Without a previous count: chunks of pcg_sync_every.
+    int first = chunk, rest = chunk;
+    if (b.use_graphs && b.last_pcg_iters > 1) {
+        first = std::min(kMaxPcgChunk, b.last_pcg_iters - 1);
+        rest = std::min(chunk, 2);
+    }
     int launched = 0;
     int last_iters = 0;
     while (launched < o.pcg_max_iters) {
-        const int c = std::min(chunk, o.pcg_max_iters - launched);
+        const int c = std::min(launched == 0 ? first : rest, o.pcg_max_iters - launched);
         if (b.use_graphs && !timing && b.pcg_warm) {
-            // replay the chunk as one graph (captured on first use)
-            Batch::PcgGraph& pg = b.pcg_graph[c == chunk ? 0 : 1];
+            // replay the chunk as one graph (captured on first use, cached by length)
+            Batch::PcgGraph& pg = b.pcg_graph[c];
             if (pg.exec && (pg.iters != c || pg.max_iters != o.pcg_max_iters ||
                             pg.min_diag != o.min_diag || pg.max_diag != o.max_diag ||
                             pg.ratio != o.pcg_rejection_ratio)) {
@@ -732,6 +741,7 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
         last_iters = max_iters_now;
         if (all_done) break;
     }
+    b.last_pcg_iters = last_iters;
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[2], s));
     HIP_OR(msg, launch_backsub(d, s));
     HIP_OR(msg, launch_cost(d, s, d.cam_c, d.pt_c));
