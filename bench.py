@@ -35,15 +35,16 @@ PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf1
 # workload (FETCH_SIZE x 2 + WRITE_SIZE, the factor 2 from a 256 MiB copy probe whose
 # FETCH_SIZE reads half its size); see profiles/.  None until measured for the
 # current kernel.
-MEASURED_TRAFFIC = {"fp32": 126681127, "fp64": 234954711, "bf16": 78559599}
+MEASURED_TRAFFIC = {"fp64": 234954711}
 MATVEC_WARMUP, MATVEC_LAUNCHES = 20, 200
 
 
-def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes):
+def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes, block_bytes):
     """Bytes the fused Schur product must move per launch: the two Jacobian
     blocks (24 entries per edge), the edge's camera index, and per point its
-    CSR offset and the 6 unique entries of the FP64 inverse point block."""
-    return n_obs * (24 * jac_bytes + 4) + n_pts_active * (4 + 6 * 8)
+    CSR offset and the 6 unique entries of the inverse point block (stored in
+    the block type: FP64, or FP32 in the mixed modes)."""
+    return n_obs * (24 * jac_bytes + 4) + n_pts_active * (4 + 6 * block_bytes)
 
 
 def cpu_baseline(sc):
@@ -211,7 +212,8 @@ def main():
     print(f"[bench] workload {args.workload}: {sc.n_cams} cams, {sc.n_pts} pts, {sc.n_obs} obs "
           f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
     n_pts_active = int(np.unique(sc.pt_idx).size)
-    alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes)
+    alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes,
+                                         8 if args.precision == "fp64" else 4)
 
     def make_graph(prec_id, timing):
         opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,

@@ -428,7 +428,7 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.bp, tsz * 3 * NP);
     L.add(d.hcc, tsz * 45 * NC);
     L.add(d.bc, tsz * 9 * NC);
-    L.add(d.hpp_inv, sizeof(double) * kHinvStride * NP);
+    L.add(d.hpp_inv, tsz * kHinvStride * NP);
     L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
     if (u.cam_pass) L.add(d.zbuf, sizeof(double) * 4 * NP);
     L.add(d.minv, tsz * 45 * NC);

@@ -140,7 +140,8 @@ struct DeviceGraph {
     void* bp;                 // [3][np]
     void* hcc;                // [nc][45]
     void* bc;                 // [nc][9]
-    double* hpp_inv;          // [np][8] damped inverse (FP64), 6 unique entries per row
+    void* hpp_inv;            // [np][8] damped inverse (inverted in FP64, stored in the block
+                              // type), 6 unique entries per row
     void* jst_cm;             // camera-major copy of jst, same layout
     double* zbuf;             // [np][4] point vectors between the two passes
     void* minv;               // [nc][45] preconditioner inverse blocks

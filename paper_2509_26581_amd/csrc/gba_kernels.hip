@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_d
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int c = r; c < 3; ++c) g.hpp_inv[kHinvStride * j + sym3(r, c)] = ok ? A[r][c] : 0.0;
+            for (int c = r; c < 3; ++c) ((T*)g.hpp_inv)[kHinvStride * j + sym3(r, c)] = (T)(ok ? A[r][c] : 0.0);
         const double p0 = g.pt[3 * j], p1 = g.pt[3 * j + 1], p2 = g.pt[3 * j + 2];
         g.pt_c[3 * j] = p0;
         g.pt_c[3 * j + 1] = p1;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Hi[r][c] = g.hpp_inv[kHinvStride * j + sym3(r, c)];
+                for (int c = 0; c < 3; ++c) Hi[r][c] = (double)((const T*)g.hpp_inv)[kHinvStride * j + sym3(r, c)];
             double jc[2][9], jp[2][3];
             jac_load<JS>(g.jst_cm, q0, jc, jp);
             if (q1 - q0 == 1) {
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
             T pc[9];
             if (kMode == kRhs) {
                 const T b0 = (T)bp[j], b1 = (T)bp[g.np + j], b2 = (T)bp[2 * g.np + j];
-                const double* H = g.hpp_inv + kHinvStride * j;
+                const VT* H = (const VT*)g.hpp_inv + kHinvStride * j;
                 const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
                 z[0] = h00 * b0 + h01 * b1 + h02 * b2;
                 z[1] = h01 * b0 + h11 * b1 + h12 * b2;
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
             } else {
                 // the point block is loaded by every lane of the point at the
                 // start (the head lane applies it), next to the camera gather
-                const double* H = g.hpp_inv + kHinvStride * j;
+                const VT* H = (const VT*)g.hpp_inv + kHinvStride * j;
                 const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
                 if constexpr (sizeof(VT) == 8) {
                     gather9(vin, i, pc);   // 5 aligned 16-byte loads instead of 9 scalar ones
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
             T z[3];
             if (kMode == kRhs) {
                 const T b0 = (T)bp[j], b1 = (T)bp[g.np + j], b2 = (T)bp[2 * g.np + j];
-                const double* H = g.hpp_inv + kHinvStride * j;
+                const VT* H = (const VT*)g.hpp_inv + kHinvStride * j;
                 z[0] = H[0] * b0 + H[1] * b1 + H[2] * b2;
                 z[1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
                 z[2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                     tt[1] += bp[g.np + j];
                     tt[2] += bp[2 * g.np + j];
                 }
-                const double* H = g.hpp_inv + kHinvStride * j;
+                const VT* H = (const VT*)g.hpp_inv + kHinvStride * j;
                 z[0] = H[0] * tt[0] + H[1] * tt[1] + H[2] * tt[2];
                 z[1] = H[1] * tt[0] + H[3] * tt[1] + H[4] * tt[2];
                 z[2] = H[2] * tt[0] + H[4] * tt[1] + H[5] * tt[2];
@@ -952,11 +952,6 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
     const T* __restrict__ z = (const T*)g.v_z;
     T* __restrict__ best = (T*)g.v_best;
     if (kUpdate) {
-        // an idle replayed iteration (every PCG finished) exits at once; its
-        // PcgState::act stays as the finishing iteration left it, and no
-        // separate update kernel reads it
-        const bool running = (int)threadIdx.x < g.n_probs && !g.pcg[threadIdx.x].done;
-        if (!__syncthreads_or(running)) return;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int k = threadIdx.x + 1024 * u;
@@ -971,17 +966,18 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
     }
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int prob = w; prob < g.n_probs; prob += nw) {
-        PcgState* st = g.pcg + prob;
-        // the sums are formed before the state is read (their loads do not
-        // wait for it); a finished problem discards them
+        PcgState* stp = g.pcg + prob;
+        // the state, the partial sums' loads and (kUpdate) z and p are all
+        // in flight together; a finished problem discards the sums
+        PcgState st = *stp;
         const double pq = wave_sum_blocks(g.pq_partial, 1, 0, g.dc_red.prob_blk[prob],
                                           g.dc_red.prob_blk[prob + 1]);
         const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
         const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
         const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
-        if (st->done) {
+        if (st.done) {
             if (lane_id() == 0) {
-                st->act = 0;
+                stp->act = 0;
                 if (kUpdate) s_act[prob] = 0;
             }
             continue;
@@ -991,27 +987,28 @@ __global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iter
             if (!(pq > 0.0) || !isfinite(pq)) {
                 done = 3;
             } else {
-                st->iters += 1;
-                st->rr = rr;
+                st.iters += 1;
+                st.rr = rr;
                 const bool track = ratio > 0.0 && isfinite(ratio);
-                if (track && rr < st->min_rr) {
-                    st->min_rr = rr;
+                if (track && rr < st.min_rr) {
+                    st.min_rr = rr;
                     copy_best = 1;
-                } else if (track && rr > ratio * ratio * st->min_rr) {
+                } else if (track && rr > ratio * ratio * st.min_rr) {
                     done = 4;
                 }
-                if (!done && rr <= st->thresh) done = 1;
-                if (!done && st->iters >= max_iters) done = 2;
+                if (!done && rr <= st.thresh) done = 1;
+                if (!done && st.iters >= max_iters) done = 2;
             }
-            const double rz_old = st->rz;
+            const double rz_old = st.rz;
             const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
             const int act = (done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0);
-            st->beta = beta;
-            st->act = act;
-            if (copy_best) st->use_best = 1;
-            if (done != 3) st->rz = rz;
-            st->done = done;
-            if (g.pcg_host) g.pcg_host[prob] = *st;
+            st.beta = beta;
+            st.act = act;
+            if (copy_best) st.use_best = 1;
+            if (done != 3) st.rz = rz;
+            st.done = done;
+            *stp = st;
+            if (g.pcg_host) g.pcg_host[prob] = st;
             if (kUpdate) {
                 s_act[prob] = act;
                 s_beta[prob] = beta;
@@ -1226,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
     const T* bp = (const T*)g.bp;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.np; j += gridDim.x * blockDim.x) {
         const double b0 = (double)bp[j], b1 = (double)bp[g.np + j], b2 = (double)bp[2 * g.np + j];
-        const double* H = g.hpp_inv + kHinvStride * j;
+        const T* H = (const T*)g.hpp_inv + kHinvStride * j;
         g.zbuf[4 * j] = H[0] * b0 + H[1] * b1 + H[2] * b2;
         g.zbuf[4 * j + 1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
         g.zbuf[4 * j + 2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
