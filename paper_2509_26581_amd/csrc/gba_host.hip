@@ -363,8 +363,11 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     for (int p = 0; p < P && !u.cam_pass; ++p) {
         const int ncp = u.cam_off[p + 1] - u.cam_off[p];
         for (int q = u.pp.prob_blk[p]; q < u.pp.prob_blk[p + 1]; ++q) {
-            u.part_off[q] = (int)part;          // one partial vector per workgroup,
-            part += (9LL * ncp + 3) / 4 * 4;    // 16-byte aligned (read 16 bytes per lane)
+            // one partial vector per workgroup, a problem's consecutive and
+            // each padded to 4 entries (k_reduce computes the addresses
+            // from this layout and reads 16 bytes per lane)
+            u.part_off[q] = (int)part;
+            part += (9LL * ncp + 3) / 4 * 4;
         }
     }
     if (part > std::numeric_limits<int>::max()) {

@@ -707,31 +707,33 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
         const int c0 = kCpl * col;                        // first component of this lane
         const int kl = kb - 9 * g.prob_cam_off[prob] + c0;   // within the problem
         const int q0 = g.dc_pp.prob_blk[prob], q1 = g.dc_pp.prob_blk[prob + 1];
-        const T* part = (const T*)g.cam_partial;   // flushed in the vector type
-        double a0[kCpl], a1[kCpl];
+        // a problem's partial vectors are consecutive, each padded to a
+        // multiple of 4 entries (the point-pass decomposition's layout), so
+        // their addresses need no per-vector offset load; four loads per
+        // lane are in flight at once
+        const size_t stride = (size_t)(9 * (g.prob_cam_off[prob + 1] - g.prob_cam_off[prob]) + 3) / 4 * 4;
+        const T* base = (const T*)g.cam_partial + g.pp_part_off[q0] + kl;   // vector type
+        const int nq = q1 - q0;
+        double a[4][kCpl];
 #pragma unroll
-        for (int u = 0; u < kCpl; ++u) a0[u] = a1[u] = 0.0;
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int u = 0; u < kCpl; ++u) a[v][u] = 0.0;
         if (kb + c0 < ke) {
-            int q = q0 + grp;
-            for (; q + kGroups < q1; q += 2 * kGroups) {
-                Chunk16 x, y;
-                x.u = *(const uint4*)(part + g.pp_part_off[q] + kl);
-                y.u = *(const uint4*)(part + g.pp_part_off[q + kGroups] + kl);
+            for (int q = grp; q < nq; q += 4 * kGroups) {
+                Chunk16 x[4];
 #pragma unroll
-                for (int u = 0; u < kCpl; ++u) {
-                    a0[u] += chunk_get(x, u, (T*)nullptr);
-                    a1[u] += chunk_get(y, u, (T*)nullptr);
-                }
-            }
-            if (q < q1) {
-                Chunk16 x;
-                x.u = *(const uint4*)(part + g.pp_part_off[q] + kl);
+                for (int v = 0; v < 4; ++v)
+                    if (q + v * kGroups < nq) x[v].u = *(const uint4*)(base + (size_t)(q + v * kGroups) * stride);
 #pragma unroll
-                for (int u = 0; u < kCpl; ++u) a0[u] += chunk_get(x, u, (T*)nullptr);
+                for (int v = 0; v < 4; ++v)
+                    if (q + v * kGroups < nq)
+#pragma unroll
+                        for (int u = 0; u < kCpl; ++u) a[v][u] += chunk_get(x[v], u, (T*)nullptr);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kCpl; ++u) red[grp][c0 + u] = a0[u] + a1[u];
+        for (int u = 0; u < kCpl; ++u) red[grp][c0 + u] = (a[0][u] + a[1][u]) + (a[2][u] + a[3][u]);
         __syncthreads();
         if (own) {
             double t0 = 0.0, t1 = 0.0;
