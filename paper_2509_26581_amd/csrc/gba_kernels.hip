@@ -217,14 +217,14 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     const int ne = g.ne;
-    for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
-        const int q0 = g.cm_run_off[run];
-        const int j = g.cm_pt[q0];
-        double W[9][3];
-        if (kMode == kAssemble) {
-            const int q1 = g.cm_run_off[run + 1];
+    if (kMode == kAssemble) {
+        // edge-parallel over the chunk's edges (no per-run state here): the
+        // chain of dependent loads per edge is point index -> point
+        const int qb = g.cm_run_off[rb], qe = g.cm_run_off[re];
+        for (int q = qb + (int)threadIdx.x; q < qe; q += blockDim.x) {
+            const int j = g.cm_pt[q];
             const bool pfix = g.pt_fixed[j] != 0;
-            for (int q = q0; q < q1; ++q) {
+            {
                 EdgeEval<double> ev;
                 bal_eval<double, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
                 double s, rho, w;
@@ -254,7 +254,12 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     for (int b = a; b < 9; ++b, ++k)
                         acc[k] += jc[0][a] * jc[0][b] + jc[1][a] * jc[1][b];
             }
-        } else {
+        }
+    } else {
+        for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
+            const int q0 = g.cm_run_off[run];
+            const int j = g.cm_pt[q0];
+            double W[9][3];
             const int q1 = g.cm_run_off[run + 1];
             double Hi[3][3];
 #pragma unroll
