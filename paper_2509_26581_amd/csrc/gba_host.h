@@ -150,6 +150,8 @@ struct Batch {
     // PCG iterations of the last damped step (the largest over the problems):
     // with graphs, the next step's first chunk is sized from it
     int last_pcg_iters = 0;
+    // Hpp / bp of the current layout cleared once (points without edges keep 0)
+    bool blocks_zeroed = false;
     // pinned host mirrors of the per-problem device arrays (capacity h_cap)
     int h_cap = 0;
     TrialScalars* h_scal = nullptr;

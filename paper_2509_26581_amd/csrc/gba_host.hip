@@ -540,6 +540,7 @@ gba_status build_batch(const std::vector<const HostProblem*>& probs, int precisi
     b.arena = arena;
     b.arena_bytes = bytes;
     b.dg = DeviceGraph{};
+    b.blocks_zeroed = false;
     layout_union(u, precision, arena, &b.dg);
     set_union_scalars(b, precision, loss, delta);
     DeviceGraph& d = b.dg;
@@ -641,7 +642,8 @@ gba_status read_scal(Batch& b, std::string& msg) {
 gba_status batch_linearize(Batch& b, const RawOut* raw, Timers* tm, std::string& msg) {
     const bool timing = tm && tm->on;
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[0], b.stream));
-    HIP_OR(msg, launch_linearize(b.dg, b.stream, raw));
+    HIP_OR(msg, launch_linearize(b.dg, b.stream, raw, !b.blocks_zeroed));
+    b.blocks_zeroed = true;
     if (!raw) HIP_OR(msg, launch_assemble(b.dg, b.stream));
     if (timing) {
         HIP_OR(msg, hipEventRecord(tm->ev[1], b.stream));

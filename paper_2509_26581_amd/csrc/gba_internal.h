@@ -217,7 +217,9 @@ struct PackChunk {
 };
 hipError_t launch_pack(const PackDesc* desc, const PackChunk* chunks, int n_chunks, hipStream_t s);
 
-hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw);
+// zero_blocks: clear Hpp and bp first (points without edges are never written;
+// needed once per device-graph layout)
+hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw, bool zero_blocks);
 hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_cost(const DeviceGraph& g, hipStream_t s, const double* cam, const double* pt);
 hipError_t launch_cost_finish(const DeviceGraph& g, hipStream_t s);

@@ -1270,21 +1270,21 @@ __global__ void k_fill(T* p, T v, size_t n) {
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
-hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw) {
+hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw, bool zero_blocks) {
     RawOut r = raw ? *raw : RawOut{nullptr, nullptr, nullptr, nullptr};
     const int blocks = (g.n_tiles * kWave + 255) / 256;
     const int grid = blocks < 1 ? 1 : blocks;
     if (g.mode == kModeFP64) {
-        hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.hpp, 0.0, (size_t)6 * g.np);
-        hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.bp, 0.0, (size_t)3 * g.np);
+        if (zero_blocks) hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.hpp, 0.0, (size_t)6 * g.np);
+        if (zero_blocks) hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.bp, 0.0, (size_t)3 * g.np);
         hipLaunchKernelGGL((k_linearize<double, double>), dim3(grid), dim3(256), 0, s, g, r);
     } else if (g.mode == kModeFP32) {
-        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
-        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
+        if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
+        if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
         hipLaunchKernelGGL((k_linearize<float, float>), dim3(grid), dim3(256), 0, s, g, r);
     } else {  // FP32 blocks, BF16 Jacobian
-        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
-        hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
+        if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
+        if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
         hipLaunchKernelGGL((k_linearize<float, bf16>), dim3(grid), dim3(256), 0, s, g, r);
     }
     GBA_CHECK_LAUNCH();

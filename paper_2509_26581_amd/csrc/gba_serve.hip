@@ -423,6 +423,7 @@ gba_status gba_server::repack() {
     }
     if ((st = batch.ensure_mirrors(std::max<int>(cfg.max_slots, (int)order.size()), err)) != GBA_OK) return st;
     batch.dg = DeviceGraph{};
+    batch.blocks_zeroed = false;
     layout_union(u, cfg.precision, (char*)arena + uo, &batch.dg);
     set_union_scalars(batch, cfg.precision, cfg.loss, cfg.delta);
     batch.arena = (char*)arena + uo;
