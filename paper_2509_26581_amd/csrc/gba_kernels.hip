@@ -10,6 +10,8 @@
 // [n_cams][9]; per-point blocks are [6][n_pts] / [3][n_pts].
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gba_device.h"
 #include "gba_internal.h"
 
@@ -213,9 +215,13 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     const int cam = g.chunk_cam[chunk];
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
     const bool cfix = g.cam_fixed[cam] != 0;
-    double acc[K];
+    // kPrecond accumulates in the block type: FP32 in the mixed modes, where
+    // a thread sums only its few runs before the FP64 workgroup and chunk
+    // sums (the blocks are a preconditioner, computed at >= FP32)
+    using AccT = std::conditional_t<kMode == kPrecond, T, double>;
+    AccT acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int k = 0; k < K; ++k) acc[k] = (AccT)0;
     const int ne = g.ne;
     if (kMode == kAssemble) {
         // edge-parallel over the chunk's edges (no per-run state here): the
@@ -259,28 +265,36 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
         for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
             const int q0 = g.cm_run_off[run];
             const int j = g.cm_pt[q0];
-            double W[9][3];
+            AccT W[9][3];
             const int q1 = g.cm_run_off[run + 1];
-            double Hi[3][3];
+            AccT Hi[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Hi[r][c] = (double)((const T*)g.hpp_inv)[kHinvStride * j + sym3(r, c)];
-            double jc[2][9], jp[2][3];
-            jac_load<JS>(g.jst_cm, q0, jc, jp);
+                for (int c = 0; c < 3; ++c) Hi[r][c] = (AccT)((const T*)g.hpp_inv)[kHinvStride * j + sym3(r, c)];
+            double jcd[2][9], jpd[2][3];
+            jac_load<JS>(g.jst_cm, q0, jcd, jpd);
+            AccT jc[2][9], jp[2][3];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) jc[r][a] = (AccT)jcd[r][a];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) jp[r][a] = (AccT)jpd[r][a];
+            }
             if (q1 - q0 == 1) {
                 // one edge: W Hpp^-1 W^T = J_c^T A J_c with the 2x2
                 // A = J_p Hpp^-1 J_p^T (fewer operations than forming W)
-                double JH[2][3];
+                AccT JH[2][3];
 #pragma unroll
                 for (int r = 0; r < 2; ++r)
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
                         JH[r][c] = jp[r][0] * Hi[0][c] + jp[r][1] * Hi[1][c] + jp[r][2] * Hi[2][c];
-                const double A00 = JH[0][0] * jp[0][0] + JH[0][1] * jp[0][1] + JH[0][2] * jp[0][2];
-                const double A01 = JH[0][0] * jp[1][0] + JH[0][1] * jp[1][1] + JH[0][2] * jp[1][2];
-                const double A11 = JH[1][0] * jp[1][0] + JH[1][1] * jp[1][1] + JH[1][2] * jp[1][2];
-                double AJ[2][9];
+                const AccT A00 = JH[0][0] * jp[0][0] + JH[0][1] * jp[0][1] + JH[0][2] * jp[0][2];
+                const AccT A01 = JH[0][0] * jp[1][0] + JH[0][1] * jp[1][1] + JH[0][2] * jp[1][2];
+                const AccT A11 = JH[1][0] * jp[1][0] + JH[1][1] * jp[1][1] + JH[1][2] * jp[1][2];
+                AccT AJ[2][9];
 #pragma unroll
                 for (int b = 0; b < 9; ++b) {
                     AJ[0][b] = A00 * jc[0][b] + A01 * jc[1][b];
@@ -299,13 +313,20 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
                     for (int b = 0; b < 3; ++b) W[a][b] = jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
                 for (int q = q0 + 1; q < q1; ++q) {
-                    jac_load<JS>(g.jst_cm, q, jc, jp);
+                    jac_load<JS>(g.jst_cm, q, jcd, jpd);
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+                        for (int a = 0; a < 9; ++a) jc[r][a] = (AccT)jcd[r][a];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) jp[r][a] = (AccT)jpd[r][a];
+                    }
 #pragma unroll
                     for (int a = 0; a < 9; ++a)
 #pragma unroll
                         for (int b = 0; b < 3; ++b) W[a][b] += jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
                 }
-                double WH[9][3];
+                AccT WH[9][3];
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
 #pragma unroll
@@ -324,7 +345,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double v = wave_sum(acc[k]);
+        const double v = wave_sum((double)acc[k]);
         if (lane_id() == 0) red[w][k] = v;
     }
     __syncthreads();
