@@ -416,6 +416,7 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.lam, sizeof(double) * P);
     L.add(d.accept, sizeof(int) * P);
     L.add(d.pcg, sizeof(PcgState) * P);
+    L.add(d.pcg_dec, sizeof(PcgState) * P);
     L.add(d.scal, sizeof(TrialScalars) * P);
     L.add(d.cam, sizeof(double) * 9 * NC);
     L.add(d.cam_c, sizeof(double) * 9 * NC);
@@ -435,11 +436,11 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
     if (u.cam_pass) L.add(d.zbuf, sizeof(double) * 4 * NP);
     L.add(d.minv, tsz * 45 * NC);
-    L.add(d.v_x, tsz * 9 * NC + 64);   // slack: 16-byte gathers (gather9)
+    L.add(d.v_x, tsz * 9 * NC + 64);   // slack: 16-byte gathers (gather9); back-substitution
     L.add(d.v_r, tsz * 9 * NC);
-    L.add(d.v_z, tsz * 9 * NC);
-    L.add(d.v_p, tsz * 9 * NC + 64);
-    L.add(d.v_q, tsz * 9 * NC);
+    L.add(d.v_z, tsz * 9 * NC + 64);   // the product gathers z
+    L.add(d.v_p, tsz * 9 * NC);
+    L.add(d.v_q, sizeof(double) * 9 * NC);   // FP64 in every mode (formed by recurrence)
     L.add(d.v_best, tsz * 9 * NC);
     decomp(d.dc_pp, u.pp);
     decomp(d.dc_red, u.red);
@@ -669,19 +670,24 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[1], s));
     HIP_OR(msg, launch_pcg_init(d, s, o.pcg_tol, o.pcg_tol_relative));
     const int chunk = std::max(1, std::min(kMaxPcgChunk, tune.pcg_sync_every));
-    // With graphs, the first chunk is the previous step's PCG length less one
-    // (successive LM trials need similar counts) and the rest are chunks of
-    // two: fewer idle iterations replayed past convergence, usually one or
-    // two host checks.  Without a previous count: chunks of pcg_sync_every.
+    // A PCG of k steps takes k + 1 launched iterations: an iteration decides
+    // at its start whether the previous step ended the PCG.  With graphs, the
+    // first chunk is the previous step's PCG length (one launch short of the
+    // same count; successive LM trials need similar counts) and the rest are
+    // chunks of two: fewer idle iterations replayed past convergence, usually
+    // one or two host checks.  Without a previous count: chunks of
+    // pcg_sync_every.
     int first = chunk, rest = chunk;
-    if (b.use_graphs && b.last_pcg_iters > 1) {
-        first = std::min(kMaxPcgChunk, b.last_pcg_iters - 1);
+    if (b.use_graphs && b.last_pcg_iters > 0) {
+        first = std::min(kMaxPcgChunk, b.last_pcg_iters);
         rest = std::min(chunk, 2);
     }
+    const int max_launch = o.pcg_max_iters + 1;
     int launched = 0;
     int last_iters = 0;
-    while (launched < o.pcg_max_iters) {
-        const int c = std::min(launched == 0 ? first : rest, o.pcg_max_iters - launched);
+    int products = 0;   // timing: launches that ran a product
+    while (launched < max_launch) {
+        const int c = std::min(launched == 0 ? first : rest, max_launch - launched);
         if (b.use_graphs && !timing && b.pcg_warm) {
             // replay the chunk as one graph (captured on first use, cached by length)
             Batch::PcgGraph& pg = b.pcg_graph[c];
@@ -725,7 +731,7 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
             b.pcg_warm = true;
         }
         launched += c;
-        // h_pcg is written by the PCG finishers through its mapping
+        // h_pcg is written by the apply kernels through its mapping
         HIP_OR(msg, hipStreamSynchronize(s));
         int max_iters_now = 0;
         bool all_done = true;
@@ -734,8 +740,11 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
             all_done = all_done && b.h_pcg[p].done != 0;
         }
         if (timing) {
-            // only launches in which some problem still iterated time a product
-            const int ran = std::min(c, max_iters_now - last_iters);
+            // only launches in which some problem still stepped time a
+            // product: every launch until all PCGs have stopped, then as many
+            // as the longest one took steps
+            const int ran = std::min(c, std::max(0, (all_done ? max_iters_now : launched) - products));
+            products += ran;
             for (int k = 0; k < ran; ++k) {
                 float ms = 0.f;
                 HIP_OR(msg, hipEventElapsedTime(&ms, tm->ev[4 + 2 * k], tm->ev[5 + 2 * k]));
@@ -775,13 +784,17 @@ gba_status batch_time_matvec(Batch& b, const gba_options& o, int launches, doubl
     HIP_OR(msg, launch_rhs(d, s));
     HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag,
                                o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0));
-    // tolerance 0: the products below run for every problem with work
+    // tolerance 0 and no iteration limit: the products below run for every
+    // problem with work.  One iteration first, so that they take the decision
+    // of a later iteration, as in the PCG loop.
+    constexpr int kNoLimit = 1 << 30;
     HIP_OR(msg, launch_pcg_init(d, s, 0.0, 0));
+    HIP_OR(msg, launch_pcg_iter(d, s, o.min_diag, o.max_diag, kNoLimit, 0.0, nullptr, nullptr));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR(msg, hipEventCreate(&e0));
     hipError_t r = hipEventCreate(&e1);
     if (r == hipSuccess) r = hipEventRecord(e0, s);
-    for (int k = 0; k < launches && r == hipSuccess; ++k) r = launch_matvec(d, s);
+    for (int k = 0; k < launches && r == hipSuccess; ++k) r = launch_matvec(d, s, kNoLimit, 0.0);
     if (r == hipSuccess) r = hipEventRecord(e1, s);
     if (r == hipSuccess) r = hipEventSynchronize(e1);
     float t = 0.f;

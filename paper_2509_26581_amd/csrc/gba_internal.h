@@ -21,8 +21,6 @@ constexpr int kChunkRuns = 1024;      // camera-major runs per workgroup chunk
 constexpr int kHinvStride = 8;        // padded row of the damped inverse point blocks
 constexpr int kCamsPerBlock = 28;     // cameras per PCG-vector workgroup (252 components)
 constexpr int kPcgBlock = 256;        // threads of the PCG-vector workgroups
-constexpr int kFusedUpdateProbs = 256;    // PCG finisher updates the vectors itself up to
-constexpr int kFusedUpdateComps = 12288;  // this many problems and reduced-system components
 constexpr int kRedComps = 64;         // components per partial-reduction workgroup
 constexpr int kMaxProblems = 4096;    // problems per device graph
 #ifndef GBA_PP_BLOCK
@@ -62,9 +60,20 @@ struct PcgState {
     int iters;
     int done;            // 0 running, 1 converged, 2 max iters, 3 breakdown, 4 rejected, 5 idle problem
     int use_best;
-    int act;             // vector work of the last step: bit0 p = z + beta p, bit1 best = x, bit2 x = best
+    int act;             // decisions only: the work of this iteration (kAct* bits)
     double beta;         // of the last step
+    int fresh;           // no step taken yet (the first direction is p = z)
+    int pad_;
 };
+
+// Work of one PCG iteration, decided at its start from the previous step's
+// dot products (PcgState::act of a decision).
+constexpr int kActRun = 1;        // a step with p = z + beta p
+constexpr int kActFresh = 2;      // the first step, p = z
+constexpr int kActKeepBest = 4;   // best = x before the step (rejection ratio)
+constexpr int kActRestore = 8;    // x = best (stopped by the rejection ratio)
+constexpr int kActState = 16;     // the state changed: the apply kernel stores it
+constexpr int kActStep = kActRun | kActFresh;
 
 // Problem-aligned work decomposition: workgroup b handles items
 // [blk[3b], blk[3b+1]) of problem blk[3b+2]; the workgroups of problem p are
@@ -120,7 +129,8 @@ struct DeviceGraph {
     int* accept;              // [P] 1: commit the candidate of this problem
     PcgState* pcg;            // [P]
     TrialScalars* scal;       // [P]
-    PcgState* pcg_host;       // [P] mapped host copies written by the finishers, or null
+    PcgState* pcg_dec;        // [P] decision of the current PCG iteration (from the product)
+    PcgState* pcg_host;       // [P] mapped host copies of pcg (at the start and once stopped), or null
     TrialScalars* scal_host;  // [P]
 
     // parameters (FP64 master copies and candidates)
@@ -173,6 +183,8 @@ struct DeviceGraph {
     // launch geometry
     int block_pp;             // threads per point-pass workgroup
     int lds_pp;               // dynamic LDS bytes of the point passes (9 x max cameras of a problem)
+    int pcg_max_iters;        // PCG stop rules, set by the PCG launchers
+    double pcg_ratio;
     int cam_pass;             // 1: a problem's camera vector exceeds LDS; the RHS and the
                               // Schur product take two passes (point-major: z_j into zbuf;
                               // camera-major over jst_cm: sums per chunk)
@@ -231,8 +243,9 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
 hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                            int max_iters, double reject_ratio, hipEvent_t ev_mv0,
                            hipEvent_t ev_mv1);
-// the Schur product S p of the PCG step alone (q partials, no update)
-hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s);
+// the Schur product of a PCG iteration alone (its decision and the q
+// partials, no update)
+hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s, int max_iters, double reject_ratio);
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_finish(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_commit(const DeviceGraph& g, hipStream_t s);

@@ -425,6 +425,82 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
         for (int c = r; c < 9; ++c) Minv[i * 45 + sym9(r, c)] = (T)M[r][c];
 }
 
+// Sum of part[stride * q + off] over the workgroups q of a problem, by one
+// wavefront (every lane gets the result).
+__device__ __forceinline__ double wave_sum_blocks(const double* part, int stride, int off, int q0,
+                                                  int q1, int sub = 0, int parts = 1) {
+    // this wavefront is number `sub` of `parts` sharing the range; four
+    // independent partial sums keep four loads in flight per lane
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int step = kWave * parts;
+    int q = q0 + sub * kWave + lane_id();
+    for (; q + 3 * step < q1; q += 4 * step) {
+        s0 += part[stride * q + off];
+        s1 += part[stride * (q + step) + off];
+        s2 += part[stride * (q + 2 * step) + off];
+        s3 += part[stride * (q + 3 * step) + off];
+    }
+    for (; q < q1; q += step) s0 += part[stride * q + off];
+    return wave_sum((s0 + s1) + (s2 + s3));
+}
+
+// ==========================================================================
+// PCG decisions.  The step taken by iteration i of the PCG is decided at its
+// start, from the state (g.pcg) and the dot products r^T z, r^T r left by
+// iteration i-1 (per camera-aligned workgroup in dot_partial): convergence,
+// iteration limit, rejection ratio, beta = r^T z / (r^T z)_old.  The product
+// kernel takes the decision (every workgroup from the same sums, so all agree;
+// the problem's first workgroup stores it in g.pcg_dec for the later kernels
+// of the iteration) and multiplies z, not the direction: by linearity
+// S p = S z + beta S p_old, so the q reduction forms q = S z + beta q_old and
+// p = z + beta p_old itself, and the apply kernel stores the state.  An
+// iteration is three kernels with no separate scalar pass, and the product
+// gathers one vector.
+// ==========================================================================
+__device__ __forceinline__ PcgState pcg_decision(const DeviceGraph& g, int prob) {
+    PcgState st = g.pcg[prob];
+    const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
+    const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
+    const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+    if (st.done) {   // stopped earlier: nothing to do
+        st.act = 0;
+        return st;
+    }
+    if (st.fresh) {  // first step: p = z, r^T z from the start
+        st.fresh = 0;
+        st.beta = 0.0;
+        st.act = kActFresh | kActState;
+        return st;
+    }
+    int done = 0, keep_best = 0;
+    st.iters += 1;
+    st.rr = rr;
+    const double ratio = g.pcg_ratio;
+    const bool track = ratio > 0.0 && isfinite(ratio);
+    if (track && rr < st.min_rr) {
+        st.min_rr = rr;
+        keep_best = 1;
+    } else if (track && rr > ratio * ratio * st.min_rr) {
+        done = 4;
+    }
+    if (!done && rr <= st.thresh) done = 1;
+    if (!done && st.iters >= g.pcg_max_iters) done = 2;
+    st.beta = st.rz > 0.0 ? rz / st.rz : 0.0;
+    st.rz = rz;
+    st.done = done;
+    if (keep_best) st.use_best = 1;
+    st.act = kActState | (done ? 0 : kActRun) | (keep_best ? kActKeepBest : 0) |
+             (done == 4 ? kActRestore : 0);
+    return st;
+}
+
+// One entry of the direction: z + beta p_old rounded to the vector type, or z
+// on the first step.
+template <typename VT>
+__device__ __forceinline__ VT dir_entry(VT z, VT pold, int act, double beta) {
+    return (act & kActRun) ? (VT)fma(beta, (double)pold, (double)z) : z;
+}
+
 // ==========================================================================
 // Point passes over the stored weighted Jacobians, one wavefront per tile of
 // whole points, camera-side sums privatised in LDS per workgroup and flushed
@@ -448,18 +524,27 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
     extern __shared__ __align__(16) unsigned char smem_raw[];
     AT* acc_lds = (AT*)smem_raw;
     __shared__ double red[16];
+    __shared__ int s_act;
     int tb, te;
     const int prob = decomp_block(g.dc_pp, blockIdx.x, tb, te);
-    if (kMode == kMatvec && g.pcg[prob].done) return;   // PCG of this problem converged
     const int l = lane_id();
     const int c0 = g.prob_cam_off[prob];
     const int nc9 = 9 * (g.prob_cam_off[prob + 1] - c0);   // this problem's camera components
     // two-pass scheme: this pass only produces z_j (camera sums in k_cam_pass)
     const bool cpass = g.cam_pass != 0;
-    if (kMode != kBacksub && !cpass) {
-        for (int k = threadIdx.x; k < nc9; k += blockDim.x) acc_lds[k] = 0;
-        __syncthreads();
+    // the product: this PCG iteration's decision, by the first wavefront
+    // while the others clear the partials
+    if (kMode == kMatvec && threadIdx.x < kWave) {
+        const PcgState d = pcg_decision(g, prob);
+        if (threadIdx.x == 0) {
+            s_act = d.act;
+            if (blockIdx.x == g.dc_pp.prob_blk[prob]) g.pcg_dec[prob] = d;
+        }
     }
+    if (kMode != kBacksub && !cpass)
+        for (int k = threadIdx.x; k < nc9; k += blockDim.x) acc_lds[k] = 0;
+    if (kMode == kMatvec || (kMode == kRhs && !cpass)) __syncthreads();
+    if (kMode == kMatvec && !(s_act & kActStep)) return;   // this problem's PCG has stopped
     const int nw = blockDim.x >> 6;
     const VT* bp = (const VT*)g.bp;
     double red_m = 0.0, red_b = 0.0, red_s = 0.0;
@@ -684,7 +769,8 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
 // ==========================================================================
 // Sum of the per-workgroup camera partials of each problem.
 //   kRhs:    r = -bc + sum                              (reduced RHS)
-//   kMatvec: q = Hcc_lambda p - sum, and partial dots p^T q (FP64)
+//   kMatvec: S z = Hcc_lambda z - sum; the direction p = z + beta p and
+//            q = S p = S z + beta q (FP64); partial dots p^T q (FP64)
 // Workgroup: up to 64 components of one problem x 16 partial groups.
 // ==========================================================================
 template <typename T, int kMode>
@@ -700,26 +786,36 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
     __shared__ double dred[16];
     int kb, ke;
     const int prob = decomp_block(g.dc_red, blockIdx.x, kb, ke);
-    if (kMode == kMatvec && g.pcg[prob].done) return;   // PCG of this problem converged
+    int act = 0;
+    double beta = 0.0;
+    if (kMode == kMatvec) {
+        const PcgState* dp = g.pcg_dec + prob;
+        act = dp->act;
+        if (!(act & kActStep)) return;   // this problem's PCG has stopped
+        beta = dp->beta;
+    }
     const int tid = threadIdx.x;
     const int k = kb + tid;                               // component (threads < kRedComps)
     const bool own = tid < kRedComps && k < ke;
-    // the damped diagonal block row and p (or bc) of this component are
+    // the damped diagonal block row, z, p and q (or bc) of this component are
     // loaded before the partial sums, so their latency overlaps
     const int i = k / 9, r = k % 9;
-    double h[9], pv[9], lambda = 0.0, bk = 0.0;
+    double h[9], pv[9], lambda = 0.0, bk = 0.0, qold = 0.0;
+    T pold = 0;
     if (own) {
         if (kMode == kRhs) {
             bk = (double)((const T*)g.bc)[k];
         } else {
             lambda = fabs(g.lam[prob]);   // negative: problem idle this trial
             const T* Hcc = (const T*)g.hcc;
-            const T* p = (const T*)g.v_p;
+            const T* z = (const T*)g.v_z;
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
                 h[c] = (double)Hcc[i * 45 + sym9(r, c)];
-                pv[c] = (double)p[9 * i + c];
+                pv[c] = (double)z[9 * i + c];
             }
+            pold = ((const T*)g.v_p)[k];
+            qold = ((const double*)g.v_q)[k];
         }
     }
     double tot = 0.0;
@@ -782,12 +878,16 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
                 if (c == r) hc += lambda * fmin(fmax(hc, min_diag), max_diag);
                 hp += hc * pv[c];
             }
-            const double q = hp - tot;
-            ((T*)g.v_q)[k] = (T)q;
-            double pk = pv[0];
+            // S z, then q = S p = S z + beta q_old (FP64) and p = z + beta p_old
+            const double sz = hp - tot;
+            const double q = (act & kActRun) ? fma(beta, qold, sz) : sz;
+            double zk = pv[0];
 #pragma unroll
-            for (int c = 1; c < 9; ++c) pk = c == r ? pv[c] : pk;
-            dot = pk * (double)(T)q;
+            for (int c = 1; c < 9; ++c) zk = c == r ? pv[c] : zk;
+            const T pk = dir_entry<T>((T)zk, pold, act, beta);
+            ((double*)g.v_q)[k] = q;
+            ((T*)g.v_p)[k] = pk;
+            dot = (double)pk * q;
         }
     }
     if (kMode == kMatvec) {
@@ -812,25 +912,6 @@ __device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds
 #pragma unroll
     for (int b = 0; b < 9; ++b) s += (double)Minv[i * 45 + sym9(a, b)] * (double)r_lds[base + b];
     return (T)s;
-}
-
-// Sum of part[stride * q + off] over the workgroups q of a problem, by one
-// wavefront (every lane gets the result).
-__device__ __forceinline__ double wave_sum_blocks(const double* part, int stride, int off, int q0,
-                                                  int q1, int sub = 0, int parts = 1) {
-    // this wavefront is number `sub` of `parts` sharing the range; four
-    // independent partial sums keep four loads in flight per lane
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const int step = kWave * parts;
-    int q = q0 + sub * kWave + lane_id();
-    for (; q + 3 * step < q1; q += 4 * step) {
-        s0 += part[stride * q + off];
-        s1 += part[stride * (q + step) + off];
-        s2 += part[stride * (q + 2 * step) + off];
-        s3 += part[stride * (q + 3 * step) + off];
-    }
-    for (; q < q1; q += step) s0 += part[stride * q + off];
-    return wave_sum((s0 + s1) + (s2 + s3));
 }
 
 // PCG start, vectors: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
@@ -865,37 +946,43 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
     }
 }
 
-// PCG start, scalars: rz0, rr0, threshold per problem; p = z.
-template <typename T>
+// PCG start, scalars: rz0, rr0, threshold per problem (the first direction
+// p = z is formed by the first iteration).
 __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double tol, int relative) {
-    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int prob = w; prob < g.n_probs; prob += nw) {
         const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
         const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
         const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
         if (lane_id() == 0) {
-            PcgState* st = g.pcg + prob;
-            st->rz = rz;
-            st->rr = rr;
-            st->rr0 = rr;
-            st->min_rr = rr;
-            st->thresh = relative ? tol * tol * rr : tol * tol;
-            st->iters = 0;
-            st->use_best = 0;
-            st->act = 0;
-            st->beta = 0.0;
-            st->done = g.lam[prob] < 0.0 ? 5 : ((rr <= st->thresh || !(rz > 0.0)) ? 1 : 0);
-            if (g.pcg_host) g.pcg_host[prob] = *st;
+            PcgState st;
+            st.rz = rz;
+            st.rr = rr;
+            st.rr0 = rr;
+            st.min_rr = rr;
+            st.thresh = relative ? tol * tol * rr : tol * tol;
+            st.iters = 0;
+            st.use_best = 0;
+            st.act = 0;
+            st.beta = 0.0;
+            st.fresh = 1;
+            st.pad_ = 0;
+            st.done = g.lam[prob] < 0.0 ? 5 : ((rr <= st.thresh || !(rz > 0.0)) ? 1 : 0);
+            g.pcg[prob] = st;
+            // a problem without point-pass workgroups never takes a decision:
+            // its slot says stopped (such a problem has r = 0 and stops here)
+            g.pcg_dec[prob] = st;
+            if (g.pcg_host) g.pcg_host[prob] = st;
         }
     }
-    const T* __restrict__ z = (const T*)g.v_z;
-    T* __restrict__ p = (T*)g.v_p;
-    for (int k = threadIdx.x; k < 9 * g.nc; k += blockDim.x) p[k] = z[k];
 }
 
-// PCG step, vectors: alpha = r^T z / p^T q; x += alpha p; r -= alpha q;
-// z = M^{-1} r; partial (r^T z, r^T r) per workgroup.
+// PCG step, vectors (camera-aligned workgroups), as decided at the start of
+// the iteration (g.pcg_dec): alpha = r^T z / p^T q; x += alpha p; r -= alpha q;
+// z = M^{-1} r; partial (r^T z, r^T r) per workgroup for the next decision;
+// the best-iterate copy / restore of the rejection ratio.  The problem's first
+// workgroup stores the state (the decision, or a breakdown when p^T q <= 0),
+// and its host mirror once the PCG stops; no other workgroup reads the state.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
@@ -903,182 +990,81 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     __shared__ double red[16];
     int cb, ce;
     const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
-    const PcgState* st = g.pcg + prob;
     const int tid = threadIdx.x;
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
-    // A finished PCG (the rest of a replayed chunk of iterations) exits
-    // after one load.  Otherwise every load of the step is issued before the
-    // next wait (the dot, alpha): two memory latencies instead of four.
-    if (st->done) return;
+    // A PCG stopped before this iteration (the rest of a replayed chunk of
+    // iterations) exits after one load.  Otherwise every load of the step is
+    // issued before the next wait (the dot, alpha).
+    const PcgState* dp = g.pcg_dec + prob;
+    const int act = dp->act;
+    const double rz_dec = dp->rz;
+    if (!(act & kActState)) return;
+    T* __restrict__ x = (T*)g.v_x;
+    T* __restrict__ r = (T*)g.v_r;
     double pq = 0.0;
     for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
         pq += g.pq_partial[b];
-    T* __restrict__ x = (T*)g.v_x;
-    T* __restrict__ r = (T*)g.v_r;
     double xk = 0.0, pk = 0.0, qk = 0.0, rk = 0.0;
     T m[9];
     const int i = k / 9, a = k % 9;
     if (valid) {
         xk = (double)x[k];
         pk = (double)((const T*)g.v_p)[k];
-        qk = (double)((const T*)g.v_q)[k];
+        qk = ((const double*)g.v_q)[k];
         rk = (double)r[k];
         const T* __restrict__ Minv = (const T*)g.minv;
 #pragma unroll
         for (int b = 0; b < 9; ++b) m[b] = Minv[i * 45 + sym9(a, b)];
     }
+    // every workgroup of the problem sums the same partials in the same
+    // order, so all of them take the same branch
     pq = block_sum(pq, red);
-    if (!(pq > 0.0) || !isfinite(pq)) return;   // breakdown: the finisher stops this PCG
-    const double alpha = st->rz / pq;
-    T rv = 0;
-    if (valid) {
-        x[k] = (T)(xk + alpha * pk);
-        rv = (T)(rk - alpha * qk);
-        r[k] = rv;
+    const bool lead = tid == 0 && (int)blockIdx.x == g.dc_cam.prob_blk[prob];
+    if (act & (kActKeepBest | kActRestore)) {   // rejection ratio
+        T* __restrict__ best = (T*)g.v_best;
+        if (valid && (act & kActKeepBest)) best[k] = (T)xk;
+        if (valid && (act & kActRestore)) x[k] = best[k];
     }
-    r_lds[tid] = rv;
-    __syncthreads();
-    double rz = 0.0, rr = 0.0;
-    if (valid) {
-        const int base = tid - a;
-        double sz = 0.0;
+    const bool ok = pq > 0.0 && isfinite(pq);
+    if ((act & kActStep) && ok) {
+        const double alpha = rz_dec / pq;
+        T rv = 0;
+        if (valid) {
+            x[k] = (T)(xk + alpha * pk);
+            rv = (T)(rk - alpha * qk);
+            r[k] = rv;
+        }
+        r_lds[tid] = rv;
+        __syncthreads();
+        double rz = 0.0, rr = 0.0;
+        if (valid) {
+            const int base = tid - a;
+            double sz = 0.0;
 #pragma unroll
-        for (int b = 0; b < 9; ++b) sz += (double)m[b] * (double)r_lds[base + b];
-        const T zv = (T)sz;
-        ((T*)g.v_z)[k] = zv;
-        rz = (double)rv * (double)zv;
-        rr = (double)rv * (double)rv;
-    }
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
-    if (tid == 0) {
-        g.dot_partial[2 * blockIdx.x] = rz;
-        g.dot_partial[2 * blockIdx.x + 1] = rr;
-    }
-}
-
-// PCG step, scalars (single workgroup, one wavefront per problem): per
-// running problem convergence / iteration limit / rejection ratio /
-// breakdown, beta = r^T z / (r^T z)_old, and the vector work of the step's
-// last phase (PcgState::act, ::beta).  kUpdate: for small reduced systems the
-// same workgroup also does that vector work (k_pcg_update's), which saves a
-// launch and its memory latencies; the decisions reach the threads via LDS.
-template <typename T, bool kUpdate>
-__global__ __launch_bounds__(1024) void k_pcg_finish(DeviceGraph g, int max_iters, double ratio) {
-    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
-    __shared__ int s_act[kUpdate ? kFusedUpdateProbs : 1];
-    __shared__ double s_beta[kUpdate ? kFusedUpdateProbs : 1];
-    // kUpdate: this thread's components of z and p are loaded before the
-    // scalar phase, so that their latency hides behind it
-    constexpr int kPer = kUpdate ? kFusedUpdateComps / 1024 : 1;
-    T zv[kPer], pv[kPer];
-    int pr[kPer];
-    const int n = 9 * g.nc;
-    T* __restrict__ x = (T*)g.v_x;
-    T* __restrict__ p = (T*)g.v_p;
-    const T* __restrict__ z = (const T*)g.v_z;
-    T* __restrict__ best = (T*)g.v_best;
-    if (kUpdate) {
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int k = threadIdx.x + 1024 * u;
-            pr[u] = 0;
-            zv[u] = pv[u] = (T)0;
-            if (k < n) {
-                pr[u] = g.n_probs == 1 ? 0 : g.cam_prob[k / 9];
-                zv[u] = z[k];
-                pv[u] = p[k];
-            }
+            for (int b = 0; b < 9; ++b) sz += (double)m[b] * (double)r_lds[base + b];
+            const T zv = (T)sz;
+            ((T*)g.v_z)[k] = zv;
+            rz = (double)rv * (double)zv;
+            rr = (double)rv * (double)rv;
+        }
+        rz = block_sum(rz, red);
+        rr = block_sum(rr, red);
+        if (tid == 0) {
+            g.dot_partial[2 * blockIdx.x] = rz;
+            g.dot_partial[2 * blockIdx.x + 1] = rr;
         }
     }
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int prob = w; prob < g.n_probs; prob += nw) {
-        PcgState* stp = g.pcg + prob;
-        // the state, the partial sums' loads and (kUpdate) z and p are all
-        // in flight together; a finished problem discards the sums
-        PcgState st = *stp;
-        const double pq = wave_sum_blocks(g.pq_partial, 1, 0, g.dc_red.prob_blk[prob],
-                                          g.dc_red.prob_blk[prob + 1]);
-        const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
-        const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
-        const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
-        if (st.done) {
-            if (lane_id() == 0) {
-                stp->act = 0;
-                if (kUpdate) s_act[prob] = 0;
-            }
-            continue;
-        }
-        if (lane_id() == 0) {
-            int done = 0, copy_best = 0;
-            if (!(pq > 0.0) || !isfinite(pq)) {
-                done = 3;
-            } else {
-                st.iters += 1;
-                st.rr = rr;
-                const bool track = ratio > 0.0 && isfinite(ratio);
-                if (track && rr < st.min_rr) {
-                    st.min_rr = rr;
-                    copy_best = 1;
-                } else if (track && rr > ratio * ratio * st.min_rr) {
-                    done = 4;
-                }
-                if (!done && rr <= st.thresh) done = 1;
-                if (!done && st.iters >= max_iters) done = 2;
-            }
-            const double rz_old = st.rz;
-            const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
-            const int act = (done == 0 ? 1 : 0) | (copy_best ? 2 : 0) | (done == 4 ? 4 : 0);
-            st.beta = beta;
-            st.act = act;
-            if (copy_best) st.use_best = 1;
-            if (done != 3) st.rz = rz;
-            st.done = done;
-            *stp = st;
-            if (g.pcg_host) g.pcg_host[prob] = st;
-            if (kUpdate) {
-                s_act[prob] = act;
-                s_beta[prob] = beta;
-            }
-        }
+    if (lead) {
+        PcgState st = *dp;
+        st.act = 0;
+        if ((act & kActStep) && !ok) st.done = 3;   // breakdown: x stays the last iterate
+        g.pcg[prob] = st;
+        // the host mirror only when the PCG stops (the host waits for every
+        // PCG to stop; a store to host memory delays the kernel's end by a
+        // bus round trip)
+        if (g.pcg_host && st.done) g.pcg_host[prob] = st;
     }
-    if (!kUpdate) return;
-    __syncthreads();
-    // p = z + beta p, best-iterate copy / restore
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int k = threadIdx.x + 1024 * u;
-        if (k >= n) continue;
-        const int act = s_act[pr[u]];
-        if (act & 1) p[k] = (T)((double)zv[u] + s_beta[pr[u]] * (double)pv[u]);
-        if (act & 2) best[k] = x[k];
-        if (act & 4) x[k] = best[k];
-    }
-}
-
-// PCG step, vectors (camera-aligned workgroups): p = z + beta p, and the
-// best-iterate copy / restore when the rejection ratio is enabled.
-template <typename T>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(DeviceGraph g) {
-    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
-    int cb, ce;
-    const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
-    const PcgState* st = g.pcg + prob;
-    const int tid = threadIdx.x;
-    if (tid >= 9 * (ce - cb)) return;
-    const int k = 9 * cb + tid;
-    T* __restrict__ x = (T*)g.v_x;
-    T* __restrict__ p = (T*)g.v_p;
-    const T* __restrict__ z = (const T*)g.v_z;
-    T* __restrict__ best = (T*)g.v_best;
-    // p and z are loaded before the state is known (one memory latency)
-    const double zk = (double)z[k], pk = (double)p[k];
-    const int act = st->act;
-    if (!act) return;
-    if (act & 1) p[k] = (T)(zk + st->beta * pk);
-    if (act & 2) best[k] = x[k];
-    if (act & 4) x[k] = best[k];
 }
 
 // ==========================================================================
@@ -1211,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
     __shared__ double red[4][9];
     const int chunk = blockIdx.x;
     const int cam = g.chunk_cam[chunk];
-    if (kMode == kMatvec && g.pcg[g.cam_prob[cam]].done) return;   // converged
+    if (kMode == kMatvec && !(g.pcg_dec[g.cam_prob[cam]].act & kActStep)) return;   // stopped
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
     double y[9];
 #pragma unroll
@@ -1437,60 +1423,49 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
     if (g.nc == 0) return hipSuccess;
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL(k_pcg_start<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_start_finish<double>, dim3(1), dim3(1024), 0, s, g, tol, relative);
+        hipLaunchKernelGGL(k_pcg_start_finish, dim3(1), dim3(1024), 0, s, g, tol, relative);
     } else {
         hipLaunchKernelGGL(k_pcg_start<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        hipLaunchKernelGGL(k_pcg_start_finish<float>, dim3(1), dim3(1024), 0, s, g, tol, relative);
+        hipLaunchKernelGGL(k_pcg_start_finish, dim3(1), dim3(1024), 0, s, g, tol, relative);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s) {
-    if (g.nc == 0) return hipSuccess;
+// The product of one PCG iteration (with its decision): S p, p formed from z
+// and the previous direction.
+hipError_t launch_matvec(const DeviceGraph& g0, hipStream_t s, int max_iters, double ratio) {
+    if (g0.nc == 0) return hipSuccess;
+    DeviceGraph g = g0;
+    g.pcg_max_iters = max_iters;
+    g.pcg_ratio = ratio;
     if (g.mode == kModeFP64) {
-        point_pass<double, double, double, kMatvec>(g, s, g.v_p, g.cam_partial);
+        point_pass<double, double, double, kMatvec>(g, s, g.v_z, g.cam_partial);
     } else if (g.mode == kModeFP32) {
-        point_pass<float, float, double, kMatvec>(g, s, g.v_p, g.cam_partial);
+        point_pass<float, float, double, kMatvec>(g, s, g.v_z, g.cam_partial);
     } else {
-        point_pass<float, bf16, double, kMatvec>(g, s, g.v_p, g.cam_partial);
+        point_pass<float, bf16, double, kMatvec>(g, s, g.v_z, g.cam_partial);
     }
     if (g.cam_pass) cam_pass<kMatvec>(g, s);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-// the PCG finisher also updates the vectors when the reduced systems are
-// small enough for one workgroup to do it faster than a separate launch
-static bool fused_update(const DeviceGraph& g) {
-    return g.n_probs <= kFusedUpdateProbs && 9 * (long long)g.nc <= kFusedUpdateComps;
-}
-
+// One PCG iteration: the product (which takes the step's decision), the q
+// reduction and the vector update.
 hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                            int max_iters, double ratio, hipEvent_t ev0, hipEvent_t ev1) {
     if (g.nc == 0) return hipSuccess;
     if (ev0) (void)hipEventRecord(ev0, s);
-    hipError_t e = launch_matvec(g, s);
+    hipError_t e = launch_matvec(g, s, max_iters, ratio);
     if (e != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        if (fused_update(g)) {
-            hipLaunchKernelGGL((k_pcg_finish<double, true>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
-        } else {
-            hipLaunchKernelGGL((k_pcg_finish<double, false>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
-            hipLaunchKernelGGL(k_pcg_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        }
     } else {
         hipLaunchKernelGGL((k_reduce<float, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
         hipLaunchKernelGGL(k_pcg_apply<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        if (fused_update(g)) {
-            hipLaunchKernelGGL((k_pcg_finish<float, true>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
-        } else {
-            hipLaunchKernelGGL((k_pcg_finish<float, false>), dim3(1), dim3(1024), 0, s, g, max_iters, ratio);
-            hipLaunchKernelGGL(k_pcg_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
-        }
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
