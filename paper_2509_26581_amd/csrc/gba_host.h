@@ -156,8 +156,9 @@ struct Batch {
     int h_cap = 0;
     TrialScalars* h_scal = nullptr;
     PcgState* h_pcg = nullptr;
-    // device addresses of the mapped h_scal / h_pcg: the trial and PCG finishers
-    // write these copies, so the host reads them after a synchronize
+    // device addresses of the mapped h_scal / h_pcg: the trial finisher and
+    // the PCG kernels (start, stop) write these copies, so the host reads
+    // them after a synchronize
     TrialScalars* d_scal_host = nullptr;
     PcgState* d_pcg_host = nullptr;
     double* h_lam = nullptr;

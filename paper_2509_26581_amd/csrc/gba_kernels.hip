@@ -10,6 +10,7 @@
 // [n_cams][9]; per-point blocks are [6][n_pts] / [3][n_pts].
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <type_traits>
 
 #include "gba_device.h"
@@ -1000,6 +1001,16 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     const int act = dp->act;
     const double rz_dec = dp->rz;
     if (!(act & kActState)) return;
+    // the lead thread loads the decision it stores as the state now, so that
+    // the store at the end waits for nothing
+    const bool lead = tid == 0 && (int)blockIdx.x == g.dc_cam.prob_blk[prob];
+    constexpr int kWords = (int)(sizeof(PcgState) / 8);   // copied as 8-byte words
+    static_assert(sizeof(PcgState) % 8 == 0, "PcgState is a whole number of 8-byte words");
+    uint2 dq[kWords];
+    if (lead) {
+#pragma unroll
+        for (int u = 0; u < kWords; ++u) dq[u] = ((const uint2*)dp)[u];
+    }
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ r = (T*)g.v_r;
     double pq = 0.0;
@@ -1020,7 +1031,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     // every workgroup of the problem sums the same partials in the same
     // order, so all of them take the same branch
     pq = block_sum(pq, red);
-    const bool lead = tid == 0 && (int)blockIdx.x == g.dc_cam.prob_blk[prob];
     if (act & (kActKeepBest | kActRestore)) {   // rejection ratio
         T* __restrict__ best = (T*)g.v_best;
         if (valid && (act & kActKeepBest)) best[k] = (T)xk;
@@ -1056,14 +1066,21 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
         }
     }
     if (lead) {
-        PcgState st = *dp;
-        st.act = 0;
-        if ((act & kActStep) && !ok) st.done = 3;   // breakdown: x stays the last iterate
-        g.pcg[prob] = st;
+        // the decision becomes the state (act cleared; done = 3 on a
+        // breakdown, x then stays the last iterate)
+        static_assert(offsetof(PcgState, done) == 44 && offsetof(PcgState, act) == 52,
+                      "field offsets of the state copy");
+        if ((act & kActStep) && !ok) dq[5].y = 3;   // done (bytes 44..47)
+        dq[6].y = 0;                                // act (bytes 52..55)
+#pragma unroll
+        for (int u = 0; u < kWords; ++u) ((uint2*)(g.pcg + prob))[u] = dq[u];
         // the host mirror only when the PCG stops (the host waits for every
         // PCG to stop; a store to host memory delays the kernel's end by a
         // bus round trip)
-        if (g.pcg_host && st.done) g.pcg_host[prob] = st;
+        if (g.pcg_host && dq[5].y != 0) {
+#pragma unroll
+            for (int u = 0; u < kWords; ++u) ((uint2*)(g.pcg_host + prob))[u] = dq[u];
+        }
     }
 }
 
