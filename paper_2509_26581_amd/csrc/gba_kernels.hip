@@ -263,11 +263,16 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
             }
         }
     } else {
-        for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
-            const int q0 = g.cm_run_off[run];
+        // edge-parallel over the chunk's edges too: a run of edges on one
+        // (camera, point) pair (equal consecutive points; the chunk starts and
+        // ends on run boundaries) is handled by its first edge, so the chain
+        // of dependent loads per edge is point index -> inverse point block
+        const int qb = g.cm_run_off[rb], qe = g.cm_run_off[re];
+        for (int q0 = qb + (int)threadIdx.x; q0 < qe; q0 += blockDim.x) {
             const int j = g.cm_pt[q0];
+            if (q0 > qb && g.cm_pt[q0 - 1] == j) continue;   // inside a run
+            const bool single = q0 + 1 == qe || g.cm_pt[q0 + 1] != j;
             AccT W[9][3];
-            const int q1 = g.cm_run_off[run + 1];
             AccT Hi[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) jp[r][a] = (AccT)jpd[r][a];
             }
-            if (q1 - q0 == 1) {
+            if (single) {
                 // one edge: W Hpp^-1 W^T = J_c^T A J_c with the 2x2
                 // A = J_p Hpp^-1 J_p^T (fewer operations than forming W)
                 AccT JH[2][3];
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                 for (int a = 0; a < 9; ++a)
 #pragma unroll
                     for (int b = 0; b < 3; ++b) W[a][b] = jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
-                for (int q = q0 + 1; q < q1; ++q) {
+                for (int q = q0 + 1; q < qe && g.cm_pt[q] == j; ++q) {
                     jac_load<JS>(g.jst_cm, q, jcd, jpd);
 #pragma unroll
                     for (int r = 0; r < 2; ++r) {
