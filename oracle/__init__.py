@@ -22,6 +22,7 @@ Modules:
   robust    squared / Huber kernels and IRLS weights
   lm        generic LM loop (step acceptance, Nielsen damping update)
   ba        bundle-adjustment normal equations + block Cholesky solve
+  pcg       preconditioned CG on the reduced camera system (Sec. IV-D stop rules)
   dense     dense generic least-squares problems (circle example, linear LS)
   align     similarity (Umeyama) alignment for gauge-free comparisons
 

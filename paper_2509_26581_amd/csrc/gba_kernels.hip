@@ -920,7 +920,9 @@ __device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds
     return (T)s;
 }
 
-// PCG start, vectors: x = 0, z = M^{-1} r, partial (r^T z, r^T r) per workgroup.
+// PCG start, vectors: x = 0 and the best iterate of the rejection ratio
+// x_best = x = 0 (the start is the first candidate), z = M^{-1} r, partial
+// (r^T z, r^T r) per workgroup.
 template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
@@ -941,6 +943,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
         const T zv = minv_row((const T*)g.minv, r_lds, i, a, tid - a);
         ((T*)g.v_z)[k] = zv;
         ((T*)g.v_x)[k] = 0;
+        ((T*)g.v_best)[k] = 0;
         rz = (double)rv * (double)zv;
         rr = (double)rv * (double)rv;
     }

@@ -10,7 +10,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import align, ba, camera, robust
+from oracle import align, ba, camera, pcg, robust
 from paper_2509_26581_amd import gba, synth
 
 pytestmark = pytest.mark.gpu
@@ -142,6 +142,47 @@ def test_identity_preconditioner_step():
     dco, dpo = prob.solve(prob.linearize((sc.cams0, sc.pts0)), 1e-1, 1e-6, 1e32)
     _close(dc, dco, 1e-6, "camera step")
     _close(dp, dpo, 1e-6, "point step")
+
+
+# ------------------------------------------------- PCG stopping rules --
+def _pcg_case(seed=34, lam=1e-2):
+    # a small reduced system whose PCG residual norm rises at step 6 by a
+    # factor 2.3 over the best so far (the other steps fall clearly)
+    sc = synth.make_scene("small", seed=seed, n_cams=6, n_pts=200)
+    prob = _oracle(sc)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    S, v, fc = pcg.reduced_system(prob, lin, lam, 1e-6, 1e32)
+    return sc, S, v, fc, pcg.block_jacobi(S)
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_truncated_pcg_matches_the_oracle_iterate(k):
+    # the iteration limit: the k-th PCG iterate (not the solution)
+    sc, S, v, fc, M = _pcg_case()
+    x, steps, why = pcg.pcg(S, v, M, tol=1e-30, max_iters=k)
+    assert why == pcg.DONE_MAX_ITERS and steps == k
+    g = _graph(sc, pcg_max_iters=k, pcg_tol=1e-30)
+    dc, _, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
+    assert iters == k
+    _close(dc[fc].ravel(), x, 1e-8, f"camera step after {k} PCG steps")
+
+
+def test_rejection_ratio_returns_the_best_iterate_as_the_oracle():
+    # ratio 1.5: the PCG stops at step 6 and returns the iterate of smallest
+    # residual (the best-iterate copy and restore of the PCG kernels)
+    sc, S, v, fc, M = _pcg_case()
+    x, steps, why = pcg.pcg(S, v, M, tol=1e-30, max_iters=50, ratio=1.5)
+    assert why == pcg.DONE_REJECTED and steps == 6
+    g = _graph(sc, pcg_max_iters=50, pcg_tol=1e-30, pcg_rejection_ratio=1.5)
+    dc, _, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
+    assert iters == steps
+    _close(dc[fc].ravel(), x, 1e-8, "camera step (best iterate)")
+    # a ratio the residuals never exceed: the plain limit applies
+    g2 = _graph(sc, pcg_max_iters=8, pcg_tol=1e-30, pcg_rejection_ratio=100.0)
+    dc2, _, iters2 = gba.gba_eval_step(g2.h, 1e-2, sc.n_cams, sc.n_pts)
+    x2, steps2, why2 = pcg.pcg(S, v, M, tol=1e-30, max_iters=8, ratio=100.0)
+    assert why2 == pcg.DONE_MAX_ITERS and iters2 == steps2 == 8
+    _close(dc2[fc].ravel(), x2, 1e-8, "camera step (limit with tracking)")
 
 
 # ------------------------------------------------------ LM trajectories --
