@@ -30,7 +30,7 @@ SPACE = {
     "tiles_per_block": [4, 8, 16, 32, 64],
     "edges_per_block": [256, 512, 1024, 2048],
     "pts_per_block": [256, 512, 1024],
-    "pcg_sync_every": [4, 8, 16],
+    "pcg_sync_every": [4, 8, 16, 32],
 }
 START = {"tiles_per_block": 16, "edges_per_block": 1024, "pts_per_block": 512, "pcg_sync_every": 8}
 
