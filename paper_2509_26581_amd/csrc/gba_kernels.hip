@@ -512,7 +512,8 @@ __device__ __forceinline__ VT dir_entry(VT z, VT pold, int act, double beta) {
 // whole points, camera-side sums privatised in LDS per workgroup and flushed
 // as one partial camera vector per workgroup (no global atomics):
 //   kRhs:     sum_e J_c^T J_p (Hpp^-1 bp_j)                       (reduced RHS)
-//   kMatvec:  sum_e J_c^T J_p Hpp^-1 sum_e' J_p^T J_c' p_i'       (Schur product)
+//   kMatvec:  sum_e J_c^T J_p Hpp^-1 sum_e' J_p^T J_c' v_i'       (Schur product;
+//             v = the PCG vector z, after the iteration's decision)
 //   kBacksub: dp_j = -Hpp^-1 (bp_j + sum_e J_p^T J_c dc_i), candidate points,
 //             model terms sum |J_e dx_e|^2, bp^T dp, |dp|^2
 // ==========================================================================
@@ -1214,7 +1215,8 @@ __global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
 // per chunk of one camera's runs:
 //   sum_e J_c^T (J_p z_j)   with z_j from the first pass (zbuf)
 // into chunk_partial[chunk][0..8]; k_reduce adds a camera's chunks.
-//   kRhs: z_j = Hpp_lambda^-1 bp_j;  kMatvec: z_j = Hpp_lambda^-1 sum J_p^T J_c p.
+//   kRhs: z_j = Hpp_lambda^-1 bp_j;  kMatvec: z_j = Hpp_lambda^-1 sum J_p^T J_c v
+//   (v the product's camera vector).
 // ==========================================================================
 template <typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
@@ -1457,8 +1459,8 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
     return hipSuccess;
 }
 
-// The product of one PCG iteration (with its decision): S p, p formed from z
-// and the previous direction.
+// The product of one PCG iteration (with its decision): the Schur product of
+// z; q = S p follows from it by linearity in the reduction.
 hipError_t launch_matvec(const DeviceGraph& g0, hipStream_t s, int max_iters, double ratio) {
     if (g0.nc == 0) return hipSuccess;
     DeviceGraph g = g0;
