@@ -258,9 +258,10 @@ gba_status gba_eval_step(gba_graph* g, double lambda, double* dcam, double* dpt,
                          int* pcg_iters);
 
 /* gba_time_matvec (measurement): linearise at the current parameters, form
- * the damped reduced camera system at `lambda` as gba_eval_step does, then
- * run `launches` Schur products S p (the PCG hot loop's dominant kernel) back
- * to back on the graph's stream between two HIP events; *avg_us receives the
+ * the damped reduced camera system at `lambda` as gba_eval_step does, run one
+ * PCG iteration, then run `launches` Schur products (the PCG hot loop's
+ * dominant kernel, with the iteration's stop decision it takes first) back to
+ * back on the graph's stream between two HIP events; *avg_us receives the
  * average duration of one product in microseconds.  The parameters are not
  * changed. */
 gba_status gba_time_matvec(gba_graph* g, double lambda, int launches, double* avg_us);
