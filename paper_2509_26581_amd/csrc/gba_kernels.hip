@@ -207,11 +207,21 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_d
 // ==========================================================================
 enum { kAssemble = 0, kPrecond = 1 };
 
+// y += J_c^T (J_p t) for one edge (the reduced RHS term of a run).
+template <typename A>
+__device__ __forceinline__ void rhs_term(const double (&jc)[2][9], const double (&jp)[2][3],
+                                         const A (&t)[3], A (&y)[9]) {
+    const A u0 = (A)jp[0][0] * t[0] + (A)jp[0][1] * t[1] + (A)jp[0][2] * t[2];
+    const A u1 = (A)jp[1][0] * t[0] + (A)jp[1][1] * t[1] + (A)jp[1][2] * t[2];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) y[k] += (A)jc[0][k] * u0 + (A)jc[1][k] * u1;
+}
+
 template <typename T, typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     constexpr int K = kMode == kAssemble ? 54 : 45;
-    __shared__ double red[4][K];
+    __shared__ double red[4][54];
     const int chunk = blockIdx.x;
     const int cam = g.chunk_cam[chunk];
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
@@ -223,6 +233,12 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     AccT acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = (AccT)0;
+    // kPrecond: the reduced RHS sums of the camera ride on the same pass over
+    // the runs (per thread in AccT over its few runs, FP64 across threads and
+    // chunks, as the block entries)
+    AccT y[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) y[k] = (AccT)0;
     const int ne = g.ne;
     if (kMode == kAssemble) {
         // edge-parallel over the chunk's edges (no per-run state here): the
@@ -268,9 +284,11 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
         // ends on run boundaries) is handled by its first edge, so the chain
         // of dependent loads per edge is point index -> inverse point block
         const int qb = g.cm_run_off[rb], qe = g.cm_run_off[re];
+        const T* __restrict__ bp = (const T*)g.bp;
         for (int q0 = qb + (int)threadIdx.x; q0 < qe; q0 += blockDim.x) {
             const int j = g.cm_pt[q0];
             if (q0 > qb && g.cm_pt[q0 - 1] == j) continue;   // inside a run
+            const T b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
             const bool single = q0 + 1 == qe || g.cm_pt[q0 + 1] != j;
             AccT W[9][3];
             AccT Hi[3][3];
@@ -280,6 +298,13 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                 for (int c = 0; c < 3; ++c) Hi[r][c] = (AccT)((const T*)g.hpp_inv)[kHinvStride * j + sym3(r, c)];
             double jcd[2][9], jpd[2][3];
             jac_load<JS>(g.jst_cm, q0, jcd, jpd);
+            // the reduced RHS term of the run: J_c^T J_p t with
+            // t = Hpp_lambda^-1 bp_j
+            AccT t[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                t[r] = Hi[r][0] * (AccT)b0 + Hi[r][1] * (AccT)b1 + Hi[r][2] * (AccT)b2;
+            rhs_term(jcd, jpd, t, y);
             AccT jc[2][9], jp[2][3];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -320,6 +345,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     for (int b = 0; b < 3; ++b) W[a][b] = jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
                 for (int q = q0 + 1; q < qe && g.cm_pt[q] == j; ++q) {
                     jac_load<JS>(g.jst_cm, q, jcd, jpd);
+                    rhs_term(jcd, jpd, t, y);
 #pragma unroll
                     for (int r = 0; r < 2; ++r) {
 #pragma unroll
@@ -347,15 +373,23 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
             }
         }
     }
-    // workgroup reduction of the K accumulators
+    // workgroup reduction of the accumulators (kPrecond: 45 block entries and
+    // 9 RHS sums)
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double v = wave_sum((double)acc[k]);
         if (lane_id() == 0) red[w][k] = v;
     }
+    if (kMode == kPrecond) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double v = wave_sum((double)y[k]);
+            if (lane_id() == 0) red[w][45 + k] = v;
+        }
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    for (int k = threadIdx.x; k < 54; k += blockDim.x) {
         const int nw = blockDim.x >> 6;
         double s = 0.0;
         for (int q = 0; q < nw; ++q) s += red[q][k];
@@ -387,6 +421,12 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
                 ((T*)g.bc)[i * 9 + (k - 45)] = (T)s;
         }
         return;
+    }
+    if (block_jacobi && k >= 45 && k < 54) {
+        // reduced RHS r = -bc + the camera's chunk sums (from the same pass)
+        double sr = 0.0;
+        for (int q = c0; q < c1; ++q) sr += g.chunk_partial[q * 54 + k];
+        ((T*)g.v_r)[i * 9 + (k - 45)] = (T)(-(double)((const T*)g.bc)[i * 9 + (k - 45)] + sr);
     }
     T* Minv = (T*)g.minv;
     const bool fixed = g.cam_fixed[i] != 0;
