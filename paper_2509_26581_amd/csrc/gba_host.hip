@@ -664,9 +664,9 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     HIP_OR(msg, hipMemcpyAsync(d.lam, b.h_lam, sizeof(double) * b.P, hipMemcpyHostToDevice, s));
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[0], s));
     HIP_OR(msg, launch_damp(d, s, o.min_diag, o.max_diag));
-    // the block-Jacobi pass forms the reduced RHS on its way
+    // the block-Jacobi pass forms the reduced RHS on its way (one-pass scheme)
     const int block_jacobi = o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0;
-    if (!block_jacobi) HIP_OR(msg, launch_rhs(d, s));
+    if (!precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
     HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi));
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[1], s));
     HIP_OR(msg, launch_pcg_init(d, s, o.pcg_tol, o.pcg_tol_relative));
@@ -781,9 +781,9 @@ gba_status batch_time_matvec(Batch& b, const gba_options& o, int launches, doubl
     hipStream_t s = b.stream;
     HIP_OR(msg, hipMemcpyAsync(d.lam, b.h_lam, sizeof(double) * b.P, hipMemcpyHostToDevice, s));
     HIP_OR(msg, launch_damp(d, s, o.min_diag, o.max_diag));
-    // the block-Jacobi pass forms the reduced RHS on its way
+    // the block-Jacobi pass forms the reduced RHS on its way (one-pass scheme)
     const int block_jacobi = o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0;
-    if (!block_jacobi) HIP_OR(msg, launch_rhs(d, s));
+    if (!precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
     HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi));
     // tolerance 0 and no iteration limit: the products below run for every
     // problem with work.  One iteration first, so that they take the decision

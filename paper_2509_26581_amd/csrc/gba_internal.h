@@ -239,6 +239,9 @@ hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double min_diag, dou
 hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                           int block_jacobi);
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s);
+// true: launch_precond also forms the reduced RHS (then launch_rhs is not
+// needed); false: call launch_rhs first
+bool precond_forms_rhs(const DeviceGraph& g, int block_jacobi);
 hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int relative);
 hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                            int max_iters, double reject_ratio, hipEvent_t ev_mv0,

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_d
 //              edges of J_c^T J_p, from jst_cm: the point-elimination term of
 //              the 9x9 diagonal block of the Schur complement.
 // ==========================================================================
-enum { kAssemble = 0, kPrecond = 1 };
+enum { kAssemble = 0, kPrecond = 1, kPrecondRhs = 2 };   // kPrecondRhs: kPrecond + reduced RHS
 
 // y += J_c^T (J_p t) for one edge (the reduced RHS term of a run).
 template <typename A>
@@ -229,11 +229,11 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     // kPrecond accumulates in the block type: FP32 in the mixed modes, where
     // a thread sums only its few runs before the FP64 workgroup and chunk
     // sums (the blocks are a preconditioner, computed at >= FP32)
-    using AccT = std::conditional_t<kMode == kPrecond, T, double>;
+    using AccT = std::conditional_t<kMode != kAssemble, T, double>;
     AccT acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = (AccT)0;
-    // kPrecond: the reduced RHS sums of the camera ride on the same pass over
+    // kPrecondRhs: the reduced RHS sums of the camera ride on the same pass over
     // the runs (per thread in AccT over its few runs, FP64 across threads and
     // chunks, as the block entries)
     AccT y[9];
@@ -288,7 +288,12 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
         for (int q0 = qb + (int)threadIdx.x; q0 < qe; q0 += blockDim.x) {
             const int j = g.cm_pt[q0];
             if (q0 > qb && g.cm_pt[q0 - 1] == j) continue;   // inside a run
-            const T b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
+            T b0 = 0, b1 = 0, b2 = 0;
+            if (kMode == kPrecondRhs) {
+                b0 = bp[j];
+                b1 = bp[g.np + j];
+                b2 = bp[2 * g.np + j];
+            }
             const bool single = q0 + 1 == qe || g.cm_pt[q0 + 1] != j;
             AccT W[9][3];
             AccT Hi[3][3];
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
             for (int r = 0; r < 3; ++r)
                 t[r] = Hi[r][0] * (AccT)b0 + Hi[r][1] * (AccT)b1 + Hi[r][2] * (AccT)b2;
-            rhs_term(jcd, jpd, t, y);
+            if (kMode == kPrecondRhs) rhs_term(jcd, jpd, t, y);
             AccT jc[2][9], jp[2][3];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -345,7 +350,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                     for (int b = 0; b < 3; ++b) W[a][b] = jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
                 for (int q = q0 + 1; q < qe && g.cm_pt[q] == j; ++q) {
                     jac_load<JS>(g.jst_cm, q, jcd, jpd);
-                    rhs_term(jcd, jpd, t, y);
+                    if (kMode == kPrecondRhs) rhs_term(jcd, jpd, t, y);
 #pragma unroll
                     for (int r = 0; r < 2; ++r) {
 #pragma unroll
@@ -373,15 +378,15 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
             }
         }
     }
-    // workgroup reduction of the accumulators (kPrecond: 45 block entries and
-    // 9 RHS sums)
+    // workgroup reduction of the accumulators (kPrecondRhs: 45 block entries
+    // and 9 RHS sums)
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double v = wave_sum((double)acc[k]);
         if (lane_id() == 0) red[w][k] = v;
     }
-    if (kMode == kPrecond) {
+    if (kMode == kPrecondRhs) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const double v = wave_sum((double)y[k]);
@@ -403,7 +408,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 // preconditioner stores I; fixed cameras store 0.
 template <typename T, int kMode>
 __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_diag, double max_diag,
-                                                     int block_jacobi) {
+                                                     int block_jacobi, int with_rhs) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ double Ms[54];
     const int i = blockIdx.x;
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
         }
         return;
     }
-    if (block_jacobi && k >= 45 && k < 54) {
+    if (kMode == kPrecond && with_rhs && k >= 45 && k < 54) {
         // reduced RHS r = -bc + the camera's chunk sums (from the same pass)
         double sr = 0.0;
         for (int q = c0; q < c1; ++q) sr += g.chunk_partial[q * 54 + k];
@@ -1377,9 +1382,9 @@ hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1407,23 +1412,41 @@ hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double min_diag, dou
     return hipSuccess;
 }
 
+// The block-Jacobi pass forms the reduced RHS too in the one-pass scheme;
+// with the two-pass scheme (large camera sets) the separate RHS passes are
+// cheaper than the extra registers the fused form costs there.
+bool precond_forms_rhs(const DeviceGraph& g, int block_jacobi) {
+    return block_jacobi != 0 && !g.cam_pass;
+}
+
 hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                           int block_jacobi) {
     if (g.nc == 0) return hipSuccess;
+    const int rhs = precond_forms_rhs(g, block_jacobi) ? 1 : 0;
     if (block_jacobi && g.n_chunks > 0) {
         // the pass reads jst_cm: its storage type must be the mode's
-        if (g.mode == kModeFP64)
-            hipLaunchKernelGGL((k_cam_accumulate<double, double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
-        else if (g.mode == kModeFP32)
-            hipLaunchKernelGGL((k_cam_accumulate<float, float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
-        else
-            hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        if (g.mode == kModeFP64) {
+            if (rhs)
+                hipLaunchKernelGGL((k_cam_accumulate<double, double, kPrecondRhs>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            else
+                hipLaunchKernelGGL((k_cam_accumulate<double, double, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        } else if (g.mode == kModeFP32) {
+            if (rhs)
+                hipLaunchKernelGGL((k_cam_accumulate<float, float, kPrecondRhs>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            else
+                hipLaunchKernelGGL((k_cam_accumulate<float, float, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        } else {
+            if (rhs)
+                hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kPrecondRhs>), dim3(g.n_chunks), dim3(256), 0, s, g);
+            else
+                hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kPrecond>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        }
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi);
+        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi);
+        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
