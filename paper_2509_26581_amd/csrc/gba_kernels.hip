@@ -204,8 +204,10 @@ __global__ __launch_bounds__(256) void k_damp_points(DeviceGraph g, double min_d
 //   kPrecond:  sum over runs of W Hpp_lambda^{-1} W^T, W = sum over the run's
 //              edges of J_c^T J_p, from jst_cm: the point-elimination term of
 //              the 9x9 diagonal block of the Schur complement.
+//   kPrecondRhs: kPrecond and the reduced RHS sums sum J_c^T J_p Hpp^-1 bp_j
+//              (chunk slots 45..53).
 // ==========================================================================
-enum { kAssemble = 0, kPrecond = 1, kPrecondRhs = 2 };   // kPrecondRhs: kPrecond + reduced RHS
+enum { kAssemble = 0, kPrecond = 1, kPrecondRhs = 2 };
 
 // y += J_c^T (J_p t) for one edge (the reduced RHS term of a run).
 template <typename A>
@@ -405,7 +407,8 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 // One workgroup per camera: sum the chunk partials of the camera.
 // kAssemble stores Hcc and bc.  kPrecond forms M_i = Hcc_lambda,i -
 // sum W Hpp^-1 W^T and stores M_i^{-1} (FP64 Cholesky); the identity
-// preconditioner stores I; fixed cameras store 0.
+// preconditioner stores I; fixed cameras store 0.  with_rhs (the pass ran as
+// kPrecondRhs): also the reduced RHS r_i = -bc_i + the chunks' RHS sums.
 template <typename T, int kMode>
 __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_diag, double max_diag,
                                                      int block_jacobi, int with_rhs) {
