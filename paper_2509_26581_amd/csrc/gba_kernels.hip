@@ -457,26 +457,67 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
         for (int q = c0; q < c1; ++q) s += g.chunk_partial[q * 54 + k];
         Ms[k] = h - s;
     }
+    // In-place Gauss-Jordan inversion of the SPD block over the workgroup:
+    // 81 entries, thread k owns k and k + 64; pivot q replaces A by
+    //   a_qq = 1/p, a_qj = a_qj/p, a_iq = -a_iq/p, a_ij -= a_iq a_qj / p
+    // (p = a_qq; all from the values before the step).  The pivots are the
+    // successive Schur complements, positive exactly when the block is
+    // positive definite (the Cholesky condition).
+    __shared__ double A[81];
+    __shared__ int s_bad;
+    const int e0 = k, e1 = k + 64;
+    if (e0 < 81) A[e0] = Ms[sym9(e0 / 9, e0 % 9)];
+    if (e1 < 81) A[e1] = Ms[sym9(e1 / 9, e1 % 9)];
+    if (k == 0) s_bad = 0;
     __syncthreads();
-    if (k != 0) return;
-    double M[9][9];
-    for (int r = 0; r < 9; ++r)
-        for (int c = r; c < 9; ++c) {
-            M[r][c] = Ms[sym9(r, c)];
-            M[c][r] = M[r][c];
+    for (int q = 0; q < 9; ++q) {
+        const double piv = A[q * 9 + q];
+        if (!(piv > 0.0) || !isfinite(piv)) {   // uniform: every thread reads the same pivot
+            if (k == 0) s_bad = 1;
+            break;
         }
-    if (!spd_inverse<9>(M)) {
+        const double ip = 1.0 / piv;
+        double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = h ? e1 : e0;
+            if (e >= 81) continue;
+            const int r = e / 9, c = e % 9;
+            double v;
+            if (r == q && c == q)
+                v = ip;
+            else if (r == q)
+                v = A[e] * ip;
+            else if (c == q)
+                v = -A[e] * ip;
+            else
+                v = A[e] - A[r * 9 + q] * A[q * 9 + c] * ip;
+            if (h) v1 = v; else v0 = v;
+        }
+        __syncthreads();
+        if (e0 < 81) A[e0] = v0;
+        if (e1 < 81) A[e1] = v1;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (s_bad) {
         // rounding left the block indefinite: fall back to the damped diagonal
-        for (int r = 0; r < 9; ++r)
-            for (int c = r; c < 9; ++c) {
-                double h = (double)Hcc[i * 45 + sym9(r, r)];
-                h += lambda * fmin(fmax(h, min_diag), max_diag);
-                Minv[i * 45 + sym9(r, c)] = (T)(r == c ? 1.0 / h : 0.0);
-            }
+        if (k < 45) {
+            int r = 0;
+            while (k >= sym9(r, 8) + 1) ++r;
+            const int c = k - sym9(r, r) + r;
+            double h = (double)Hcc[i * 45 + sym9(r, r)];
+            h += lambda * fmin(fmax(h, min_diag), max_diag);
+            Minv[i * 45 + k] = (T)(r == c ? 1.0 / h : 0.0);
+        }
         return;
     }
-    for (int r = 0; r < 9; ++r)
-        for (int c = r; c < 9; ++c) Minv[i * 45 + sym9(r, c)] = (T)M[r][c];
+    if (k < 45) {
+        int r = 0;
+        while (k >= sym9(r, 8) + 1) ++r;
+        const int c = k - sym9(r, r) + r;
+        Minv[i * 45 + k] = (T)(0.5 * (A[r * 9 + c] + A[c * 9 + r]));
+    }
 }
 
 // Sum of part[stride * q + off] over the workgroups q of a problem, by one
