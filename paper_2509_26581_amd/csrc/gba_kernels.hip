@@ -634,7 +634,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
         const PcgState d = pcg_decision(g, prob);
         if (threadIdx.x == 0) {
             s_act = d.act;
-            if (blockIdx.x == g.dc_pp.prob_blk[prob]) g.pcg_dec[prob] = d;
+            if ((int)blockIdx.x == g.dc_pp.prob_blk[prob]) g.pcg_dec[prob] = d;
         }
     }
     if (kMode != kBacksub && !cpass)
