@@ -20,7 +20,7 @@ stopping decisions can be compared with it:
     (x_0 included) returned (reading R11); a step with p^T S p <= 0 ends the
     iteration at the current iterate.
 
-Independent of the HIP path; pinned in tests/test_oracle_pins.py against
+Independent of the HIP path; pinned in tests/test_oracle_pcg_pins.py against
 np.linalg.solve, the Krylov-subspace minimisation property of CG and brute
 force enumeration of the stopping rule.
 """
