@@ -129,7 +129,26 @@ typedef struct gba_options {
                                   max(16, n_tiles / n_CU).  Read when the device
                                   graph is built; the server takes its sizes
                                   from gba_server_config instead.             */
-    int reserved[5];
+    int deterministic;         /* 1: every reduction runs in a fixed order, so
+                                  a solve repeats bit for bit (run twice, graph
+                                  replay or eager launches, alone or in a
+                                  served mix).  The camera-side sums of the
+                                  Schur products then take the camera-major
+                                  second pass (GBA_ACC_CAMERA_PASS); combined
+                                  with GBA_ACC_LDS it is INVALID_ARG.  0
+                                  (default): LDS partials combined by atomics,
+                                  results repeat to rounding.  Read when the
+                                  device graph is built.                      */
+    int jacobi_scaling;        /* 1: scale the camera columns of the Jacobian by
+                                  s_k = 1 / (1 + sqrt(H_kk)), H_kk the Hessian
+                                  diagonal (Sec. IV-D column rescaling).  PCG
+                                  on the scaled reduced system is PCG with the
+                                  preconditioner diag(s)^2, which is what the
+                                  identity preconditioner then applies; under
+                                  block Jacobi the scaling cancels exactly (the
+                                  blocks of the scaled system are the scaled
+                                  blocks), so it changes nothing there.  (0)  */
+    int reserved[3];
 } gba_options;
 
 #define GBA_ACC_AUTO 0

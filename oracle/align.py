@@ -58,7 +58,20 @@ def aligned_errors(cams, pts, ref_cams, ref_pts):
     num = np.sqrt(np.sum(rot_err ** 2) + np.sum((c2[:, 3:] - ref_cams[:, 3:]) ** 2) +
                   np.sum((p2 - ref_pts) ** 2))
     den = np.sqrt(np.sum(ref_cams ** 2) + np.sum(ref_pts ** 2))
+    # each parameter block against its own scale, so that the small
+    # distortion terms and the rotations are not measured against the focal
+    # lengths and the points
+    def rel(d, ref):
+        return float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300))
+
+    blocks = {"rot": rel(rot_err, ref_cams[:, 0:3]),
+              "t": rel(c2[:, 3:6] - ref_cams[:, 3:6], ref_cams[:, 3:6]),
+              "f": rel(c2[:, 6] - ref_cams[:, 6], ref_cams[:, 6]),
+              "k1": rel(c2[:, 7] - ref_cams[:, 7], ref_cams[:, 7]),
+              "k2": rel(c2[:, 8] - ref_cams[:, 8], ref_cams[:, 8]),
+              "X": rel(p2 - ref_pts, ref_pts)}
     return dict(rel=float(num / den), scale=s, max_rot=float(rot_err.max()),
                 pts_rel=float(np.linalg.norm(p2 - ref_pts) / np.linalg.norm(ref_pts)),
                 cams_rel=float(np.linalg.norm(c2[:, 3:] - ref_cams[:, 3:]) /
-                               np.linalg.norm(ref_cams[:, 3:])))
+                               np.linalg.norm(ref_cams[:, 3:])),
+                blocks=blocks, max_block=max(blocks.values()))

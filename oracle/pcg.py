@@ -109,3 +109,54 @@ def pcg(S, v, Minv, tol, relative=True, max_iters=100, ratio=np.inf):
         rz = rz_new
         p = z + beta * p
     return x, max_iters, DONE_MAX_ITERS
+
+
+def schur_pcg_step(problem, lin, lam, min_diag, max_diag, tol, relative=True,
+                   max_iters=100, ratio=np.inf, precond="block_jacobi"):
+    """The damped LM step computed as the GPU path does, written plainly and
+    densely: PCG on the reduced camera system (steps above), then the point
+    steps by back-substitution dp = Hpp_l^-1 (-bp - Hcp^T dc) (the Schur form
+    of Eq. 6).  Returns ((dcam, dpt), PCG steps)."""
+    S, v, fc = reduced_system(problem, lin, lam, min_diag, max_diag)
+    if precond == "block_jacobi":
+        M = block_jacobi(S)
+    else:
+        M = np.eye(len(v))
+    x, steps, _ = pcg(S, v, M, tol, relative, max_iters, ratio)
+    dc_diag, dp_diag = problem.damped_diagonal(lin, min_diag, max_diag)
+    fp = problem.free_pts
+    cam_pos = -np.ones(problem.n_cams, np.int64)
+    cam_pos[fc] = np.arange(len(fc))
+    dcam = np.zeros((problem.n_cams, 9))
+    dcam[fc] = x.reshape(-1, 9)
+    # t_j = -bp_j - sum over the point's camera pairs of Hcp^T dc
+    t = -lin.bp.copy()
+    for b in range(len(lin.pair_cam)):
+        i, j = lin.pair_cam[b], lin.pair_pt[b]
+        if cam_pos[i] >= 0:
+            t[j] -= lin.Hcp[b].T @ dcam[i]
+    dpt = np.zeros((problem.n_pts, 3))
+    for j in fp:
+        dpt[j] = np.linalg.solve(lin.Hpp[j] + lam * np.diag(dp_diag[j]), t[j])
+    return (dcam, dpt), steps
+
+
+class SchurPcgProblem:
+    """A BA problem whose LM steps are the truncated Schur + PCG steps of
+    schur_pcg_step (every other part of the LM problem interface is the
+    wrapped problem's)."""
+
+    def __init__(self, problem, tol, relative=True, max_iters=100, ratio=np.inf,
+                 precond="block_jacobi"):
+        self.p = problem
+        self.kw = dict(tol=tol, relative=relative, max_iters=max_iters, ratio=ratio,
+                       precond=precond)
+        self.steps = []
+
+    def __getattr__(self, name):
+        return getattr(self.p, name)
+
+    def solve(self, lin, lam, min_diag, max_diag):
+        dx, steps = schur_pcg_step(self.p, lin, lam, min_diag, max_diag, **self.kw)
+        self.steps.append(steps)
+        return dx

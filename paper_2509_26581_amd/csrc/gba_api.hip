@@ -19,6 +19,7 @@
 
 using gba::DeviceGraph;
 
+
 struct gba_graph {
     int precision = 0;
     int device = 0;
@@ -119,6 +120,46 @@ gba_status download_typed(gba_graph* g, const void* src, size_t n, std::vector<d
         to_double<double>(raw, dst.data(), n);
     else
         to_double<float>(raw, dst.data(), n);
+    return GBA_OK;
+}
+
+void zero_edge_outputs(size_t nall, double* r, double* jc, double* jp, double* w) {
+    if (r) std::memset(r, 0, sizeof(double) * 2 * nall);
+    if (jc) std::memset(jc, 0, sizeof(double) * 18 * nall);
+    if (jp) std::memset(jp, 0, sizeof(double) * 6 * nall);
+    if (w) std::memset(w, 0, sizeof(double) * nall);
+}
+
+// Device scratch of the edge evaluation: r, jc, jp, w for every inserted edge
+// (27 doubles; inactive ones stay 0) and the point-major -> insertion
+// permutation of the active ones.
+size_t edge_scratch_bytes(size_t nall, size_t ne) {
+    return sizeof(double) * 27 * nall + sizeof(int) * ne;
+}
+
+// Linearise with the unweighted per-edge outputs written into `buf` (device,
+// edge_scratch_bytes large) in the caller's layout, then copy each requested
+// output straight into the caller's host array.  Issues work on g->stream and
+// leaves it running (the caller synchronises).
+gba_status eval_edges_into(gba_graph* g, void* buf, double* r, double* jc, double* jp, double* w) {
+    const size_t ne = g->batch.dg.ne, nall = g->prob.e_cam.size();
+    double* d = (double*)buf;
+    double *dr = d, *djc = d + 2 * nall, *djp = d + 20 * nall, *dw = d + 26 * nall;
+    int* dpos = (int*)(d + 27 * nall);
+    HIP_TRY(g, gba::launch_fill_f64(d, 0.0, 27 * nall, g->stream));
+    HIP_TRY(g, hipMemcpyAsync(dpos, g->batch.pm_edge[0].data(), sizeof(int) * ne, hipMemcpyHostToDevice,
+                              g->stream));
+    gba::RawOut raw{r ? dr : nullptr, jc ? djc : nullptr, jp ? djp : nullptr, w ? dw : nullptr, dpos};
+    gba_status st = gba::batch_linearize(g->batch, &raw, nullptr, g->err);
+    if (st != GBA_OK) return st;
+    auto down = [&](double* host, const double* dev, size_t n) -> hipError_t {
+        if (!host || n == 0) return hipSuccess;
+        return hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, g->stream);
+    };
+    HIP_TRY(g, down(r, dr, 2 * nall));
+    HIP_TRY(g, down(jc, djc, 18 * nall));
+    HIP_TRY(g, down(jp, djp, 6 * nall));
+    HIP_TRY(g, down(w, dw, nall));
     return GBA_OK;
 }
 
@@ -336,14 +377,20 @@ gba_status gba_set_options(gba_graph* g, const gba_options* o) {
     if (!(o->initial_lambda > 0.0) || !(o->min_diag > 0.0) || !(o->max_diag >= o->min_diag) ||
         o->pcg_max_iters < 1 || !(o->pcg_tol >= 0.0) ||
         (o->precond != GBA_PRECOND_IDENTITY && o->precond != GBA_PRECOND_BLOCK_JACOBI) ||
-        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_CAMERA_PASS || o->tiles_per_block < 0)
+        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_CAMERA_PASS || o->tiles_per_block < 0 ||
+        (o->deterministic != 0 && o->deterministic != 1) || (o->jacobi_scaling != 0 && o->jacobi_scaling != 1))
         return fail(g, GBA_ERR_INVALID_ARG, "invalid option value");
-    if (o->accumulation != g->tune.accumulation || o->tiles_per_block != g->tune.tiles_per_block) {
-        // both are part of the device graph's plan
+    if (o->deterministic && o->accumulation == GBA_ACC_LDS)
+        return fail(g, GBA_ERR_INVALID_ARG,
+                    "deterministic sums use the camera-major pass; GBA_ACC_LDS combines LDS partials by atomics");
+    if (o->accumulation != g->tune.accumulation || o->tiles_per_block != g->tune.tiles_per_block ||
+        o->deterministic != g->tune.deterministic) {
+        // all three are part of the device graph's plan
         gba_status st = sync_params_to_host(g);
         if (st != GBA_OK) return st;
         g->tune.accumulation = o->accumulation;
         g->tune.tiles_per_block = o->tiles_per_block;
+        g->tune.deterministic = o->deterministic;
         g->dirty = true;
     }
     g->opts = *o;
@@ -466,39 +513,20 @@ gba_status gba_eval_edges(gba_graph* g, double* r, double* jc, double* jp, doubl
     HIP_TRY(g, hipSetDevice(g->device));
     gba_status st = ensure_built(g);
     if (st != GBA_OK) return st;
-    const DeviceGraph& d = g->batch.dg;
-    const size_t ne = d.ne, nall = g->prob.e_cam.size();
-    if (r) std::memset(r, 0, sizeof(double) * 2 * nall);
-    if (jc) std::memset(jc, 0, sizeof(double) * 18 * nall);
-    if (jp) std::memset(jp, 0, sizeof(double) * 6 * nall);
-    if (w) std::memset(w, 0, sizeof(double) * nall);
-    if (ne == 0) return GBA_OK;
-    double* buf = (double*)g->allocator.allocate(sizeof(double) * 27 * ne);
+    const size_t ne = g->batch.dg.ne, nall = g->prob.e_cam.size();
+    if (ne == 0) {
+        zero_edge_outputs(nall, r, jc, jp, w);
+        return GBA_OK;
+    }
+    // scratch: the outputs in the caller's layout and the edge permutation
+    const size_t bytes = edge_scratch_bytes(nall, ne);
+    void* buf = g->allocator.allocate(bytes);
     if (!buf) return fail(g, GBA_ERR_OOM, "scratch allocation failed");
-    gba::RawOut raw{buf, buf + 2 * ne, buf + 20 * ne, buf + 26 * ne};
-    std::vector<double> h(27 * ne);
-    st = gba::batch_linearize(g->batch, &raw, nullptr, g->err);
-    hipError_t e2 = st == GBA_OK ? hipMemcpyAsync(h.data(), buf, sizeof(double) * 27 * ne,
-                                                  hipMemcpyDeviceToHost, g->stream)
-                                 : hipSuccess;
+    st = eval_edges_into(g, buf, r, jc, jp, w);
     hipError_t e3 = hipStreamSynchronize(g->stream);
     g->allocator.release(buf);
     if (st != GBA_OK) return st;
-    if (e2 != hipSuccess || e3 != hipSuccess)
-        return fail(g, GBA_ERR_HIP, std::string("eval_edges: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
-    const std::vector<int>& pm = g->batch.pm_edge[0];
-    for (size_t q = 0; q < ne; ++q) {
-        const size_t e = (size_t)pm[q];
-        if (r) {
-            r[2 * e] = h[q];
-            r[2 * e + 1] = h[ne + q];
-        }
-        if (jc)
-            for (int k = 0; k < 18; ++k) jc[18 * e + k] = h[(2 + k) * ne + q];
-        if (jp)
-            for (int k = 0; k < 6; ++k) jp[6 * e + k] = h[(20 + k) * ne + q];
-        if (w) w[e] = h[26 * ne + q];
-    }
+    if (e3 != hipSuccess) return fail(g, GBA_ERR_HIP, std::string("eval_edges: ") + hipGetErrorString(e3));
     return GBA_OK;
 }
 

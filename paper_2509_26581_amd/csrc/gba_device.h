@@ -36,14 +36,17 @@ __device__ __forceinline__ bf16 store_as<bf16, float>(float x) { return to_bf16(
 template <typename T, typename S>
 __device__ __forceinline__ T load_as(S x) { return (T)to_float(x); }
 
-// Storage of a Jacobian entry computed in FP64, and the value the stored
-// entry represents (the linear system is built from what is stored).
-template <typename JS>
-__device__ __forceinline__ JS jac_store(double x) { return (JS)x; }
+// Storage of a Jacobian entry computed in the arithmetic type A, and the
+// value the stored entry represents (the linear system is built from what is
+// stored).
+template <typename JS, typename A>
+__device__ __forceinline__ JS jac_store(A x) { return (JS)x; }
 template <>
-__device__ __forceinline__ bf16 jac_store<bf16>(double x) { return to_bf16((float)x); }
-template <typename JS>
-__device__ __forceinline__ double jac_round(double x) { return (double)to_float(jac_store<JS>(x)); }
+__device__ __forceinline__ bf16 jac_store<bf16, double>(double x) { return to_bf16((float)x); }
+template <>
+__device__ __forceinline__ bf16 jac_store<bf16, float>(float x) { return to_bf16(x); }
+template <typename JS, typename A>
+__device__ __forceinline__ A jac_round(A x) { return (A)to_float(jac_store<JS, A>(x)); }
 
 // ------------------------------------------------ stored Jacobian layout
 // 24 entries per edge, in the order jc[0][0..8], jc[1][0..8], jp[0][0..2],
@@ -67,30 +70,44 @@ __host__ __device__ __forceinline__ size_t jac_chunk(int e, int c, int n) {
     return ((size_t)(e >> 6) * n + c) * 64 + (e & 63);
 }
 
+// entry s of a 16-byte chunk of storage type JS, in the arithmetic type A
+__device__ __forceinline__ double chunk_raw(const Chunk16& q, int s, double*) { return q.d[s]; }
+__device__ __forceinline__ float chunk_raw(const Chunk16& q, int s, float*) { return q.f[s]; }
+__device__ __forceinline__ float chunk_raw(const Chunk16& q, int s, bf16*) {
+    return __uint_as_float(((uint32_t)q.h[s]) << 16);
+}
+template <typename A, typename JS>
+__device__ __forceinline__ A chunk_get(const Chunk16& q, int s) {
+    return (A)chunk_raw(q, s, (JS*)nullptr);
+}
+// kept for the FP64 sums of stored entries
 __device__ __forceinline__ double chunk_get(const Chunk16& q, int s, double*) { return q.d[s]; }
 __device__ __forceinline__ double chunk_get(const Chunk16& q, int s, float*) { return (double)q.f[s]; }
 __device__ __forceinline__ double chunk_get(const Chunk16& q, int s, bf16*) {
     return (double)__uint_as_float(((uint32_t)q.h[s]) << 16);
 }
-__device__ __forceinline__ void chunk_put(Chunk16& q, int s, double x, double*) { q.d[s] = x; }
-__device__ __forceinline__ void chunk_put(Chunk16& q, int s, double x, float*) { q.f[s] = (float)x; }
-__device__ __forceinline__ void chunk_put(Chunk16& q, int s, double x, bf16*) {
+template <typename A>
+__device__ __forceinline__ void chunk_put(Chunk16& q, int s, A x, double*) { q.d[s] = (double)x; }
+template <typename A>
+__device__ __forceinline__ void chunk_put(Chunk16& q, int s, A x, float*) { q.f[s] = (float)x; }
+template <typename A>
+__device__ __forceinline__ void chunk_put(Chunk16& q, int s, A x, bf16*) {
     q.h[s] = to_bf16((float)x).v;
 }
 
-// the 24 stored entries of edge e (as FP64)
-template <typename JS>
-__device__ __forceinline__ void jac_load(const void* __restrict__ J, int e, double (&jc)[2][9],
-                                         double (&jp)[2][3]) {
+// the 24 stored entries of edge e, in the arithmetic type A
+template <typename JS, typename A>
+__device__ __forceinline__ void jac_load(const void* __restrict__ J, int e, A (&jc)[2][9],
+                                         A (&jp)[2][3]) {
     constexpr int kPer = JacPack<JS>::kPer, kCh = 24 / kPer;
     const uint4* __restrict__ src = (const uint4*)J;
-    double v[24];
+    A v[24];
 #pragma unroll
     for (int c = 0; c < kCh; ++c) {
         Chunk16 q;
         q.u = src[jac_chunk(e, c, kCh)];
 #pragma unroll
-        for (int s = 0; s < kPer; ++s) v[c * kPer + s] = chunk_get(q, s, (JS*)nullptr);
+        for (int s = 0; s < kPer; ++s) v[c * kPer + s] = chunk_get<A, JS>(q, s);
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -105,11 +122,11 @@ __device__ __forceinline__ void jac_load(const void* __restrict__ J, int e, doub
 }
 
 // store the 24 entries of edge e, rounded to JS as jac_store<JS> does
-template <typename JS>
-__device__ __forceinline__ void jac_save(void* __restrict__ J, int e, const double (&jc)[2][9],
-                                         const double (&jp)[2][3]) {
+template <typename JS, typename A>
+__device__ __forceinline__ void jac_save(void* __restrict__ J, int e, const A (&jc)[2][9],
+                                         const A (&jp)[2][3]) {
     constexpr int kPer = JacPack<JS>::kPer, kCh = 24 / kPer;
-    double v[24];
+    A v[24];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         v[a] = jc[0][a];
@@ -125,7 +142,7 @@ __device__ __forceinline__ void jac_save(void* __restrict__ J, int e, const doub
     for (int c = 0; c < kCh; ++c) {
         Chunk16 q;
 #pragma unroll
-        for (int s = 0; s < kPer; ++s) chunk_put(q, s, v[c * kPer + s], (JS*)nullptr);
+        for (int s = 0; s < kPer; ++s) chunk_put<A>(q, s, v[c * kPer + s], (JS*)nullptr);
         dst[jac_chunk(e, c, kCh)] = q.u;
     }
 }
@@ -195,7 +212,8 @@ __device__ __forceinline__ uint32_t pick32(uint32_t a, uint32_t b, uint32_t m) {
     return (a & ~m) | (b & m);   // m = 0: a, m = ~0: b (bitwise, no memory select)
 }
 
-__device__ __forceinline__ void gather9(const float* __restrict__ v, int i, double (&out)[9]) {
+template <typename A>
+__device__ __forceinline__ void gather9(const float* __restrict__ v, int i, A (&out)[9]) {
     const size_t w = 9 * (size_t)i;
     const uint4* b = (const uint4*)(v + (w & ~(size_t)3));
     const uint32_t m1 = (w & 1) ? ~0u : 0u, m2 = (w & 2) ? ~0u : 0u;
@@ -205,7 +223,7 @@ __device__ __forceinline__ void gather9(const float* __restrict__ v, int i, doub
     for (int k = 0; k < 9; ++k) {
         const uint32_t lo = pick32(q[k], q[k + 1], m1);
         const uint32_t hi = pick32(q[k + 2], q[k + 3], m1);
-        out[k] = (double)__uint_as_float(pick32(lo, hi, m2));
+        out[k] = (A)__uint_as_float(pick32(lo, hi, m2));
     }
 }
 

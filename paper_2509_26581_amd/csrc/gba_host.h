@@ -69,6 +69,7 @@ struct Tuning {
     int pts_per_block = 0;      // points per damping workgroup
     int pcg_sync_every = 8;     // PCG iterations launched between host checks
     int accumulation = GBA_ACC_AUTO;   // camera sums of the point passes
+    int deterministic = 0;      // fixed-order reductions only (camera-major second pass)
 };
 
 struct HostDecomp {
@@ -86,7 +87,9 @@ struct UnionPlan {
     std::vector<int> part_off;   // [max(1, pp.nblk())]
     long long part_total = 0;
     int max_cams = 0;
-    bool cam_pass = false;     // camera vector of some problem exceeds LDS: two passes
+    bool cam_pass = false;     // camera vector of some problem exceeds LDS (or fixed-order
+                               // sums were asked for): two passes
+    bool deterministic = false;
     std::vector<int> cam_prob, pt_prob;   // problem of each union camera / point
 };
 

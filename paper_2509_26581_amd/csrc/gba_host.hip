@@ -335,12 +335,19 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     u.tot.n_chunks = (int)sk;
     const size_t lds = 9 * (size_t)u.max_cams * sizeof(double);
     const bool fits = lds + 1024 <= dev.max_lds;
+    if (tune.accumulation == GBA_ACC_LDS && tune.deterministic) {
+        msg = "fixed-order sums need the camera-major pass, not LDS partials";
+        return GBA_ERR_INVALID_ARG;
+    }
     if (tune.accumulation == GBA_ACC_LDS && !fits) {
         msg = "the camera vector of one problem does not fit in LDS (" +
               std::to_string(u.max_cams) + " cameras)";
         return GBA_ERR_UNSUPPORTED;
     }
-    u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits;
+    // the LDS partials are combined by atomics in a varying order; the
+    // camera-major pass sums every camera in a fixed order
+    u.deterministic = tune.deterministic != 0;
+    u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits || u.deterministic;
     // automatic: one point-pass workgroup per CU (each flushes one LDS camera
     // partial; the flush grows with the workgroup count, and smaller
     // workgroups measured slower in both schemes)
@@ -478,6 +485,7 @@ void set_union_scalars(Batch& b, int precision, int loss, double delta) {
     d.jac_bytes = precision == GBA_FP64 ? 8 : (precision == GBA_MIXED_FP32 ? 4 : 2);
     d.block_pp = kPointPassBlock;
     d.cam_pass = u.cam_pass ? 1 : 0;
+    d.deterministic = u.deterministic ? 1 : 0;
     d.lds_pp = u.cam_pass ? 0 : (int)(9 * (size_t)u.max_cams * sizeof(double));
     d.dc_pp.nblk = u.pp.nblk();
     d.dc_red.nblk = u.red.nblk();
@@ -667,7 +675,7 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     // the block-Jacobi pass forms the reduced RHS on its way (one-pass scheme)
     const int block_jacobi = o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0;
     if (!precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
-    HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi));
+    HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi, o.jacobi_scaling));
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[1], s));
     HIP_OR(msg, launch_pcg_init(d, s, o.pcg_tol, o.pcg_tol_relative));
     const int chunk = std::max(1, std::min(kMaxPcgChunk, tune.pcg_sync_every));
@@ -784,7 +792,7 @@ gba_status batch_time_matvec(Batch& b, const gba_options& o, int launches, doubl
     // the block-Jacobi pass forms the reduced RHS on its way (one-pass scheme)
     const int block_jacobi = o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0;
     if (!precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
-    HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi));
+    HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi, o.jacobi_scaling));
     // tolerance 0 and no iteration limit: the products below run for every
     // problem with work.  One iteration first, so that they take the decision
     // of a later iteration, as in the PCG loop.

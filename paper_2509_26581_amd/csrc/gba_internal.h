@@ -23,6 +23,7 @@ constexpr int kCamsPerBlock = 28;     // cameras per PCG-vector workgroup (252 c
 constexpr int kPcgBlock = 256;        // threads of the PCG-vector workgroups
 constexpr int kRedComps = 64;         // components per partial-reduction workgroup
 constexpr int kMaxProblems = 4096;    // problems per device graph
+constexpr int kMaxDevices = 64;       // devices tracked for per-device kernel attributes
 #ifndef GBA_PP_BLOCK
 #define GBA_PP_BLOCK 1024
 #endif
@@ -185,9 +186,12 @@ struct DeviceGraph {
     int lds_pp;               // dynamic LDS bytes of the point passes (9 x max cameras of a problem)
     int pcg_max_iters;        // PCG stop rules, set by the PCG launchers
     double pcg_ratio;
-    int cam_pass;             // 1: a problem's camera vector exceeds LDS; the RHS and the
-                              // Schur product take two passes (point-major: z_j into zbuf;
-                              // camera-major over jst_cm: sums per chunk)
+    int cam_pass;             // 1: a problem's camera vector exceeds LDS (or fixed-order sums
+                              // were asked for); the RHS and the Schur product take two
+                              // passes (point-major: z_j into zbuf; camera-major over
+                              // jst_cm: sums per chunk)
+    int deterministic;        // 1: every sum in an order that depends only on the problem
+                              // (not on the batch it is packed with)
 };
 
 // The storage types a kernel is instantiated with must be those of the
@@ -203,12 +207,15 @@ __device__ __forceinline__ bool jac_type_ok(const DeviceGraph& g) {
 }
 
 // ---- launchers (gba_kernels.hip) --------------------------------------
-// debug outputs of gba_eval_edges, point-major, all may be null
+// outputs of gba_eval_edges in the caller's layout: edge q = pos[e] (the
+// insertion index of point-major edge e) at r[2q..], jc[18q..] (row-major
+// 2 x 9), jp[6q..] (2 x 3), w[q]; any of the four may be null
 struct RawOut {
-    double* r;   // [2][ne]
-    double* jc;  // [18][ne]
-    double* jp;  // [6][ne]
-    double* w;   // [ne]
+    double* r;
+    double* jc;
+    double* jp;
+    double* w;
+    const int* pos;   // [ne] point-major position -> insertion index
 };
 
 // Batch assembly on the device: copy (or fill) element ranges, adding a
@@ -229,6 +236,9 @@ struct PackChunk {
 };
 hipError_t launch_pack(const PackDesc* desc, const PackChunk* chunks, int n_chunks, hipStream_t s);
 
+// p[0..n) = v with a fill kernel (no memset node, so it may be captured)
+hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s);
+
 // zero_blocks: clear Hpp and bp first (points without edges are never written;
 // needed once per device-graph layout)
 hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw, bool zero_blocks);
@@ -236,8 +246,11 @@ hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_cost(const DeviceGraph& g, hipStream_t s, const double* cam, const double* pt);
 hipError_t launch_cost_finish(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag);
+// jacobi_scaling: with the identity preconditioner, apply diag(s)^2 with
+// s_k = 1 / (1 + sqrt(Hcc_kk)) (the column-scaled system); no effect under
+// block Jacobi
 hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
-                          int block_jacobi);
+                          int block_jacobi, int jacobi_scaling);
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s);
 // true: launch_precond also forms the reduced RHS (then launch_rhs is not
 // needed); false: call launch_rhs first

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <mutex>
 #include <type_traits>
 
 #include "gba_device.h"
@@ -62,22 +63,24 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
                 jac_save<JS>(g.jst, e, ev.jc, ev.jp);
                 rw[e] = (T)ev.r[0];
                 rw[ne + e] = (T)ev.r[1];
-                if (raw.r) {
-                    // unweighted values for verification
+                if (raw.pos) {
+                    // unweighted values for verification, at the edge's
+                    // insertion index in the caller's layout
                     EdgeEval<double> ed;
                     bal_eval<double, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ed);
-                    raw.r[e] = ed.r[0];
-                    raw.r[ne + e] = ed.r[1];
+                    const size_t q = (size_t)raw.pos[e];
                     const bool cf = g.cam_fixed[i] != 0, pf = g.pt_fixed[j] != 0;
-                    for (int k = 0; k < 9; ++k) {
-                        raw.jc[k * ne + e] = cf ? 0.0 : ed.jc[0][k];
-                        raw.jc[(9 + k) * ne + e] = cf ? 0.0 : ed.jc[1][k];
+                    if (raw.r) {
+                        raw.r[2 * q] = ed.r[0];
+                        raw.r[2 * q + 1] = ed.r[1];
                     }
-                    for (int k = 0; k < 3; ++k) {
-                        raw.jp[k * ne + e] = pf ? 0.0 : ed.jp[0][k];
-                        raw.jp[(3 + k) * ne + e] = pf ? 0.0 : ed.jp[1][k];
-                    }
-                    raw.w[e] = (double)w;
+                    if (raw.jc)
+                        for (int a = 0; a < 2; ++a)
+                            for (int k = 0; k < 9; ++k) raw.jc[18 * q + 9 * a + k] = cf ? 0.0 : ed.jc[a][k];
+                    if (raw.jp)
+                        for (int a = 0; a < 2; ++a)
+                            for (int k = 0; k < 3; ++k) raw.jp[6 * q + 3 * a + k] = pf ? 0.0 : ed.jp[a][k];
+                    if (raw.w) raw.w[q] = (double)w;
                 }
             }
             // point-side contributions of this edge: the Hessian block from the
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 // kPrecondRhs): also the reduced RHS r_i = -bc_i + the chunks' RHS sums.
 template <typename T, int kMode>
 __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_diag, double max_diag,
-                                                     int block_jacobi, int with_rhs) {
+                                                     int block_jacobi, int with_rhs, int jacobi_scaling) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ double Ms[54];
     const int i = blockIdx.x;
@@ -439,11 +442,18 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
     T* Minv = (T*)g.minv;
     const bool fixed = g.cam_fixed[i] != 0;
     if (fixed || !block_jacobi) {
+        // identity, or with column scaling s_k = 1 / (1 + sqrt(H_kk)) the
+        // preconditioner diag(s)^2 (PCG on the column-scaled system)
         if (k < 45) {
             int r = 0;
             while (k >= sym9(r, 8) + 1) ++r;
             const int c = k - sym9(r, r) + r;
-            Minv[i * 45 + k] = (T)((!fixed && r == c) ? 1.0 : 0.0);
+            double m = 1.0;
+            if (jacobi_scaling && r == c) {
+                const double sk = 1.0 / (1.0 + sqrt(fmax((double)Hcc[i * 45 + k], 0.0)));
+                m = sk * sk;
+            }
+            Minv[i * 45 + k] = (T)((!fixed && r == c) ? m : 0.0);
         }
         return;
     }
@@ -1223,7 +1233,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_cam_update(DeviceGraph g) {
 __global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
     __shared__ double part[16][8];
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int wpp = g.n_probs >= nw ? 1 : nw / g.n_probs;   // wavefronts per problem
+    // wavefronts per problem: with fixed-order sums one, so that a problem's
+    // sums do not depend on how many problems share the batch
+    const int wpp = (g.deterministic || g.n_probs >= nw) ? 1 : nw / g.n_probs;
     const int groups = nw / wpp, gw = w / wpp, sub = w % wpp;
     for (int base = 0; base < g.n_probs; base += groups) {
         const int prob = base + gw;
@@ -1268,7 +1280,7 @@ __global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
 __global__ __launch_bounds__(1024) void k_cost_finish(DeviceGraph g) {
     __shared__ double part[16];
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int wpp = g.n_probs >= nw ? 1 : nw / g.n_probs;
+    const int wpp = (g.deterministic || g.n_probs >= nw) ? 1 : nw / g.n_probs;
     const int groups = nw / wpp, gw = w / wpp, sub = w % wpp;
     for (int base = 0; base < g.n_probs; base += groups) {
         const int prob = base + gw;
@@ -1394,7 +1406,7 @@ __global__ void k_fill(T* p, T v, size_t n) {
     } while (0)
 
 hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw, bool zero_blocks) {
-    RawOut r = raw ? *raw : RawOut{nullptr, nullptr, nullptr, nullptr};
+    RawOut r = raw ? *raw : RawOut{nullptr, nullptr, nullptr, nullptr, nullptr};
     const int blocks = (g.n_tiles * kWave + 255) / 256;
     const int grid = blocks < 1 ? 1 : blocks;
     if (g.mode == kModeFP64) {
@@ -1426,9 +1438,9 @@ hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1464,7 +1476,7 @@ bool precond_forms_rhs(const DeviceGraph& g, int block_jacobi) {
 }
 
 hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
-                          int block_jacobi) {
+                          int block_jacobi, int jacobi_scaling) {
     if (g.nc == 0) return hipSuccess;
     const int rhs = precond_forms_rhs(g, block_jacobi) ? 1 : 0;
     if (block_jacobi && g.n_chunks > 0) {
@@ -1488,9 +1500,9 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, 
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs);
+        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs, jacobi_scaling);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs);
+        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs, jacobi_scaling);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1501,11 +1513,21 @@ static void point_pass(const DeviceGraph& g, hipStream_t s, const void* vin, voi
     // dynamic LDS: the FP64 camera partials of the product and the RHS, beyond
     // the 64 KiB default (gfx950 has 160 KiB per CU)
     const int lds = kMode == kBacksub ? 0 : g.lds_pp;
-    static int lds_set = -1;
-    if (lds > 0 && lds_set < lds) {
-        (void)hipFuncSetAttribute((const void*)k_point_pass<VT, JS, AT, kMode>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        lds_set = lds;
+    if (lds > 0) {
+        // the attribute only grows, per device; graph handles and the server
+        // thread may launch concurrently, so the check and the raise are one
+        // critical section
+        static std::mutex mu;
+        static int lds_set[kMaxDevices] = {};
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(mu);
+        int& cur = lds_set[dev >= 0 && dev < kMaxDevices ? dev : 0];
+        if (cur < lds) {
+            (void)hipFuncSetAttribute((const void*)k_point_pass<VT, JS, AT, kMode>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            cur = lds;
+        }
     }
     hipLaunchKernelGGL((k_point_pass<VT, JS, AT, kMode>), dim3(g.dc_pp.nblk), dim3(g.block_pp),
                        lds, s, g, (const void*)g.jst, (const VT*)vin, (AT*)out);
@@ -1630,6 +1652,15 @@ hipError_t launch_finish(const DeviceGraph& g, hipStream_t s) {
 hipError_t launch_pack(const PackDesc* desc, const PackChunk* chunks, int n_chunks, hipStream_t s) {
     if (n_chunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack, dim3(n_chunks), dim3(256), 0, s, desc, chunks);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t grid = (n + 255) / 256;
+    grid = grid > 4096 ? 4096 : grid;
+    hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)grid), dim3(256), 0, s, p, v, n);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -23,6 +23,7 @@
 #include "gba.h"
 #include "gba_host.h"
 #include "gba_internal.h"
+#include "gba_range.h"
 
 namespace gba {
 namespace {
@@ -34,56 +35,6 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-// First-fit from the bottom / last-fit from the top over [0, size).
-class RangeAlloc {
-  public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc_low(size_t n, size_t& off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            const size_t o = it->first, sz = it->second;
-            free_.erase(it);
-            if (sz > n) free_[o + n] = sz - n;
-            off = o;
-            return true;
-        }
-        return false;
-    }
-    bool alloc_high(size_t n, size_t& off) {
-        for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
-            if (it->second < n) continue;
-            const size_t o = it->first, sz = it->second;
-            free_.erase(o);
-            if (sz > n) free_[o] = sz - n;
-            off = o + sz - n;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n) {
-        if (!n) return;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<size_t, size_t> free_;
-};
 
 // Byte offsets of the arrays of one problem's device image (the same layout
 // is used for the pinned host copy that is uploaded).
@@ -269,13 +220,7 @@ bool gba_server::fits_locked(const Request* r, size_t& img_off) {
     c.push_back(&r->counts);
     const size_t ub = union_bytes_for(c);
     if (ub == std::numeric_limits<size_t>::max()) return false;
-    RangeAlloc sim = ra;
-    if (have_union) sim.release(union_off, union_bytes);
-    size_t io = 0, uo = 0;
-    if (!sim.alloc_low(r->lay.bytes, io)) return false;
-    if (!sim.alloc_high(ub, uo)) return false;
-    img_off = io;
-    return true;
+    return simulate_admission(ra, have_union, union_off, union_bytes, r->lay.bytes, ub, img_off);
 }
 
 gba_status gba_server::admit_locked(std::vector<Request*>& newly) {
@@ -663,7 +608,9 @@ gba_status gba_server_create(const gba_server_config* cfg, gba_alloc_fn alloc, g
     if (!(o.initial_lambda > 0.0) || !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag) ||
         o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) ||
         (o.precond != GBA_PRECOND_IDENTITY && o.precond != GBA_PRECOND_BLOCK_JACOBI) ||
-        o.accumulation < GBA_ACC_AUTO || o.accumulation > GBA_ACC_CAMERA_PASS)
+        o.accumulation < GBA_ACC_AUTO || o.accumulation > GBA_ACC_CAMERA_PASS ||
+        (o.deterministic != 0 && o.deterministic != 1) || (o.jacobi_scaling != 0 && o.jacobi_scaling != 1) ||
+        (o.deterministic && o.accumulation == GBA_ACC_LDS))
         return GBA_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return GBA_ERR_HIP;
@@ -695,6 +642,7 @@ gba_status gba_server_create(const gba_server_config* cfg, gba_alloc_fn alloc, g
     if (cfg->pts_per_block > 0) s->tune.pts_per_block = cfg->pts_per_block;
     if (cfg->pcg_sync_every > 0) s->tune.pcg_sync_every = cfg->pcg_sync_every;
     s->tune.accumulation = o.accumulation;
+    s->tune.deterministic = o.deterministic;
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->ev_admit, hipEventDisableTiming) != hipSuccess) {

@@ -41,7 +41,8 @@ class gba_options(ctypes.Structure):
                 ("pcg_tol", ctypes.c_double), ("pcg_tol_relative", ctypes.c_int),
                 ("pcg_rejection_ratio", ctypes.c_double), ("precond", ctypes.c_int),
                 ("timing", ctypes.c_int), ("accumulation", ctypes.c_int),
-                ("tiles_per_block", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("tiles_per_block", ctypes.c_int), ("deterministic", ctypes.c_int),
+                ("jacobi_scaling", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class gba_report(ctypes.Structure):

@@ -51,12 +51,44 @@ def _info(n, seed):
     return np.stack([a[:, 0], c, a[:, 1]], axis=1)
 
 
+# camera parameter blocks: rotation, translation, f, k1, k2
+CAM_BLOCKS = {"w": slice(0, 3), "t": slice(3, 6), "f": slice(6, 7), "k1": slice(7, 8),
+              "k2": slice(8, 9)}
+
+
 def _close(a, b, rtol, what):
+    """Max error of each parameter block relative to that block's own largest
+    reference entry: camera-shaped arrays (last axis 9, or 9 x 9 blocks) per
+    camera parameter block (pair of blocks), anything else as a whole, so
+    that k1, k2 and the rotation are not measured against the focal length."""
     a = np.asarray(a, float)
     b = np.asarray(b, float)
-    scale = max(np.abs(b).max(), 1e-300)
-    err = np.abs(a - b).max() / scale
-    assert err <= rtol, f"{what}: max error {err:.3e} (relative to {scale:.3e}) > {rtol}"
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if a.ndim >= 2 and a.shape[-2:] == (9, 9):
+        parts = {f"{r}/{c}": (Ellipsis, sr, sc) for r, sr in CAM_BLOCKS.items()
+                 for c, sc in CAM_BLOCKS.items()}
+    elif a.ndim >= 2 and a.shape[-1] == 9:
+        parts = {k: (Ellipsis, sl) for k, sl in CAM_BLOCKS.items()}
+    else:
+        parts = {"all": (Ellipsis,)}
+    for name, idx in parts.items():
+        aa, bb = a[idx], b[idx]
+        scale = np.abs(bb).max()
+        if scale == 0.0:
+            assert np.abs(aa).max() == 0.0, f"{what} [{name}]: nonzero where the reference is 0"
+            continue
+        err = np.abs(aa - bb).max() / scale
+        assert err <= rtol, f"{what} [{name}]: max error {err:.3e} (relative to {scale:.3e}) > {rtol}"
+
+
+def _aligned(cams, pts, ref_cams, ref_pts, tol, block_tol=None):
+    """Parameter error after the similarity alignment: the stacked relative
+    norm and each parameter block against its own scale."""
+    err = align.aligned_errors(cams, pts, ref_cams, ref_pts)
+    assert err["rel"] <= tol, err
+    bt = tol if block_tol is None else block_tol
+    assert err["max_block"] <= bt, err["blocks"]
+    return err
 
 
 # ------------------------------------------------------------ per edge --
@@ -168,7 +200,7 @@ def test_truncated_pcg_matches_the_oracle_iterate(k, precision, rtol):
     g = _graph(sc, precision=precision, pcg_max_iters=k, pcg_tol=1e-30)
     dc, _, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
     assert iters == k
-    _close(dc[fc].ravel(), x, rtol, f"camera step after {k} PCG steps")
+    _close(dc[fc], x.reshape(-1, 9), rtol, f"camera step after {k} PCG steps")
 
 
 def test_rejection_ratio_returns_the_best_iterate_as_the_oracle():
@@ -180,13 +212,13 @@ def test_rejection_ratio_returns_the_best_iterate_as_the_oracle():
     g = _graph(sc, pcg_max_iters=50, pcg_tol=1e-30, pcg_rejection_ratio=1.5)
     dc, _, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
     assert iters == steps
-    _close(dc[fc].ravel(), x, 1e-8, "camera step (best iterate)")
+    _close(dc[fc], x.reshape(-1, 9), 1e-8, "camera step (best iterate)")
     # a ratio the residuals never exceed: the plain limit applies
     g2 = _graph(sc, pcg_max_iters=8, pcg_tol=1e-30, pcg_rejection_ratio=100.0)
     dc2, _, iters2 = gba.gba_eval_step(g2.h, 1e-2, sc.n_cams, sc.n_pts)
     x2, steps2, why2 = pcg.pcg(S, v, M, tol=1e-30, max_iters=8, ratio=100.0)
     assert why2 == pcg.DONE_MAX_ITERS and iters2 == steps2 == 8
-    _close(dc2[fc].ravel(), x2, 1e-8, "camera step (limit with tracking)")
+    _close(dc2[fc], x2.reshape(-1, 9), 1e-8, "camera step (limit with tracking)")
 
 
 # ------------------------------------------------------ LM trajectories --
@@ -213,8 +245,7 @@ def test_lm_trajectory_small_workload(acc):
     _compare_trajectory(g.trials(), res.log)
     assert abs(rep.final_cost - res.cost) <= 1e-10 * res.cost
     assert abs(rep.initial_cost - res.initial_cost) <= 1e-12 * res.initial_cost
-    err = align.aligned_errors(g.cameras(), g.points(), res.x[0], res.x[1])
-    assert err["rel"] <= 1e-6, err
+    _aligned(g.cameras(), g.points(), res.x[0], res.x[1], 1e-6)
 
 
 def test_lm_trajectory_fixed_inactive_information_huber():
@@ -235,8 +266,9 @@ def test_lm_trajectory_fixed_inactive_information_huber():
     cams, pts = g.cameras(), g.points()
     np.testing.assert_array_equal(cams[cf], sc.cams0[cf])
     np.testing.assert_array_equal(pts[pf], sc.pts0[pf])
-    np.testing.assert_allclose(cams, res.x[0], rtol=0, atol=1e-6 * np.abs(res.x[0]).max())
-    np.testing.assert_allclose(pts, res.x[1], rtol=0, atol=1e-6 * np.abs(res.x[1]).max())
+    # two fixed cameras fix the gauge: parameters compared directly, per block
+    _close(cams, res.x[0], 1e-6, "cameras")
+    _close(pts, res.x[1], 1e-6, "points")
 
 
 @pytest.mark.parametrize("acc", ACC)
@@ -270,32 +302,161 @@ def test_mixed_track_lengths_ragged_tiles(acc):
     _close(dp, dpo, 1e-8, "point step")
 
 
-def test_pcg_graph_replay_matches_eager_launches():
+def _trial_tuple(t):
+    return (t["cost"], t["candidate_cost"], t["lam"], t["model_decrease"], t["step_norm"],
+            t["accepted"], t["pcg_iters"])
+
+
+@pytest.mark.parametrize("precision", [gba.GBA_FP64, gba.GBA_MIXED_FP32, gba.GBA_MIXED_BF16])
+def test_deterministic_graph_replay_equals_eager_launches_bitwise(precision):
     # the solver replays each chunk of PCG iterations as a captured HIP graph;
-    # with per-phase timing on it launches every kernel eagerly instead.
-    # Several solves in a row (reset in between) replay the same graphs.
-    # Once the decrease reaches the rounding level of F, accept / reject is
-    # decided by rounding noise (camera partials are combined by LDS atomics
-    # in a varying order), so the comparison stops there (_compare_trajectory).
+    # with per-phase timing on it launches every kernel eagerly instead.  With
+    # fixed-order sums the two, and repeated solves after a reset on one
+    # handle, agree bit for bit (tolerance 1e-10 relative on the PCG makes its
+    # stopping iteration sensitive to the last bit, so this also checks that
+    # no sum depends on launch timing)
     sc = synth.make_scene("small", seed=2, n_cams=12, n_pts=800)
-    ref = _graph(sc, pcg_max_iters=60, pcg_tol=1e-10, timing=1)
+    kw = dict(precision=precision, pcg_max_iters=60, pcg_tol=1e-10, deterministic=1)
+    ref = _graph(sc, timing=1, **kw)
     rep_ref = ref.solve(8)
-    want = ref.trials()
-    g = _graph(sc, pcg_max_iters=60, pcg_tol=1e-10)
+    want = [_trial_tuple(t) for t in ref.trials()]
+    cams_ref, pts_ref = ref.cameras(), ref.points()
+    g = _graph(sc, **kw)
     for _ in range(3):
         gba.gba_reset(g.h)
         rep = g.solve(8)
-        got = g.trials()
-        _compare_trajectory(got, want)
-        # The early trials, far above rounding, match step for step in cost,
-        # candidate cost and damping.  Their PCG iteration counts need not:
-        # with a 1e-10 relative tolerance the residual flattens near the
-        # threshold, and the rounding-level variation of the LDS camera sums
-        # moves the crossing (repeated eager solves of this problem stop
-        # after 42 to 50 iterations).  Both must stop on the tolerance.
-        assert got[0]["pcg_iters"] < 60 and want[0]["pcg_iters"] < 60
-        assert got[0]["accepted"] and want[0]["accepted"]
+        assert [_trial_tuple(t) for t in g.trials()] == want
+        assert rep.final_cost == rep_ref.final_cost
+        np.testing.assert_array_equal(g.cameras(), cams_ref)
+        np.testing.assert_array_equal(g.points(), pts_ref)
+
+
+def test_graph_replay_matches_eager_launches_at_a_converged_pcg():
+    # default (LDS atomic) sums: results repeat to rounding.  With the PCG run
+    # to the rounding level (tolerance 1e-14) each step is the exact Schur
+    # solution up to rounding, so replayed and eager trials agree to 1e-10 in
+    # cost and candidate cost, and accept the same steps.  (With a tolerance
+    # tau the step itself is only defined to O(tau): two runs may then stop
+    # the PCG at different iterations, and bitwise repetition needs the
+    # deterministic mode above.)
+    sc = synth.make_scene("small", seed=2, n_cams=12, n_pts=800)
+    ref = _graph(sc, pcg_max_iters=200, pcg_tol=1e-14, timing=1)
+    rep_ref = ref.solve(8)
+    want = ref.trials()
+    g = _graph(sc, pcg_max_iters=200, pcg_tol=1e-14)
+    for _ in range(2):
+        gba.gba_reset(g.h)
+        rep = g.solve(8)
+        _compare_trajectory(g.trials(), want)
         assert abs(rep.final_cost - rep_ref.final_cost) <= 1e-10 * rep_ref.final_cost
+
+
+@pytest.mark.parametrize("precision", [gba.GBA_FP64, gba.GBA_MIXED_FP32])
+def test_deterministic_mode_solves_the_same_problem(precision):
+    # the fixed-order mode (camera-major sums) reaches the oracle's result
+    # as the default mode does, and two handles repeat each other bitwise
+    sc = synth.make_scene("small", seed=0)
+    kw = dict(precision=precision, pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
+              deterministic=1)
+    a = _graph(sc, **kw)
+    b = _graph(sc, **kw)
+    ra, rb = a.solve(sc.trials), b.solve(sc.trials)
+    assert ra.final_cost == rb.final_cost
+    np.testing.assert_array_equal(a.cameras(), b.cameras())
+    res = ba.solve(_oracle(sc), sc.cams0, sc.pts0, sc.trials)
+    tol = 1e-10 if precision == gba.GBA_FP64 else 1e-4
+    assert abs(ra.final_cost - res.cost) <= tol * res.cost
+    with pytest.raises(gba.GbaError) as e:
+        gba.gba_set_options(a.h, gba.options(deterministic=1, accumulation=gba.GBA_ACC_LDS))
+    assert e.value.status == -1
+
+
+# ---------------------------------------------------------- stop rules --
+def test_stop_rule_cost_tol_and_step_tol_match_the_oracle():
+    # termination reason and trial count at tol > 0, on cases whose decision
+    # margins (checked on the oracle's log) are far above rounding
+    sc = synth.make_scene("small", seed=0)
+    prob = _oracle(sc)
+    for tol in (1e-3, 1e-5):
+        res = ba.solve(prob, sc.cams0, sc.pts0, 30, tol=tol)
+        assert res.termination in (2, 3), res.termination
+        for e in res.log:
+            if e["accepted"]:
+                rel = (e["cost"] - e["candidate_cost"]) / e["cost"]
+                assert abs(rel - tol) > 0.05 * tol, (rel, tol)
+        g = _graph(sc, pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol, deterministic=1)
+        rep = g.solve(30, tol)
+        assert rep.termination == res.termination and rep.trials == res.trials, (rep.as_dict(), tol)
+        assert abs(rep.final_cost - res.cost) <= 1e-10 * res.cost
+
+
+def test_stop_rule_lambda_overflow():
+    # from lambda0 = 1e31 the steps are ~1e-31 of the parameters: x + dx == x,
+    # F' == F, every trial is rejected and lambda 1e31 -> 2e31 -> 8e31 ->
+    # 6.4e32 ends the solve after three trials (as the oracle)
+    sc = synth.make_scene("small", seed=41, n_cams=4, n_pts=60)
+    res = ba.solve(_oracle(sc), sc.cams0, sc.pts0, 50, initial_lambda=1e31)
+    g = _graph(sc, initial_lambda=1e31)
+    rep = g.solve(50)
+    assert rep.termination == res.termination == 4
+    assert rep.trials == res.trials == 3 and rep.accepted == 0
+    assert [t["lam"] for t in g.trials()] == [1e31, 2e31, 8e31]
+    assert all(t["candidate_cost"] == t["cost"] for t in g.trials())
+    np.testing.assert_array_equal(g.cameras(), sc.cams0)
+
+
+def test_stop_rule_numerical_failure_on_a_non_finite_start():
+    # a point in the plane z = 0 of a camera at the origin: the projection
+    # divides by zero, the starting cost is not finite, no trial runs
+    sc = synth.make_scene("small", seed=42, n_cams=3, n_pts=20)
+    cams, pts = sc.cams0.copy(), sc.pts0.copy()
+    cams[0, :6] = 0.0
+    pts[int(sc.pt_idx[sc.cam_idx == 0][0])] = [1.0, 2.0, 0.0]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        res = ba.solve(_oracle(sc), cams, pts, 5)
+    g = _graph(sc, cams=cams, pts=pts)
+    rep = g.solve(5)
+    assert rep.termination == res.termination == 5 and rep.trials == 0
+    np.testing.assert_array_equal(g.cameras(), cams)
+
+
+@pytest.mark.parametrize("k,tol", [(1, 1e-6), (3, 1e-6), (25, 0.0)])
+def test_truncated_pcg_lm_trajectory_matches_the_oracle(k, tol):
+    # gba_solve with the PCG cut at k steps (or run to its limit with tol 0):
+    # every trial's step is the k-step Schur + PCG step, which the oracle
+    # computes densely; trajectories agree trial by trial
+    sc = synth.make_scene("small", seed=3, n_cams=8, n_pts=300)
+    oprob = pcg.SchurPcgProblem(_oracle(sc), tol=tol, max_iters=k)
+    res = ba.solve(oprob, sc.cams0, sc.pts0, 8)
+    g = _graph(sc, pcg_max_iters=k, pcg_tol=tol, deterministic=1)
+    rep = g.solve(8)
+    got = g.trials()
+    _compare_trajectory(got, res.log)
+    assert [t["pcg_iters"] for t in got][:3] == oprob.steps[:3]
+    assert abs(rep.final_cost - res.cost) <= 1e-9 * res.cost
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_jacobi_column_scaling_with_the_identity_preconditioner(k):
+    # column scaling s = 1 / (1 + sqrt(diag Hcc)) under the identity
+    # preconditioner is PCG with M^-1 = diag(s)^2 (pinned on the CPU against
+    # CG on the explicitly scaled system); under block Jacobi it changes
+    # nothing
+    sc, S, v, fc, _ = _pcg_case()
+    prob = _oracle(sc)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    s = 1.0 / (1.0 + np.sqrt(np.einsum("nii->ni", lin.Hcc[fc]).ravel()))
+    x, steps, _ = pcg.pcg(S, v, np.diag(s * s), tol=1e-30, max_iters=k)
+    g = _graph(sc, pcg_max_iters=k, pcg_tol=1e-30, precond=gba.GBA_PRECOND_IDENTITY,
+               jacobi_scaling=1)
+    dc, _, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
+    assert iters == steps == k
+    _close(dc[fc], x.reshape(-1, 9), 1e-8, f"scaled identity PCG after {k} steps")
+    a = _graph(sc, pcg_max_iters=k, pcg_tol=1e-30, deterministic=1)
+    b = _graph(sc, pcg_max_iters=k, pcg_tol=1e-30, deterministic=1, jacobi_scaling=1)
+    da, _, _ = gba.gba_eval_step(a.h, 1e-2, sc.n_cams, sc.n_pts)
+    db, _, _ = gba.gba_eval_step(b.h, 1e-2, sc.n_cams, sc.n_pts)
+    np.testing.assert_array_equal(da, db)
 
 
 # ------------------------------------------------------------ edge cases --
@@ -336,15 +497,18 @@ def test_errors_are_reported():
 
 
 def test_reset_restores_start_and_repeats_the_solve():
+    # with fixed-order sums the repeated solve is the same bit for bit
     sc = synth.make_scene("small", seed=29, n_cams=6, n_pts=200)
-    g = _graph(sc)
+    g = _graph(sc, deterministic=1)
     a = g.solve(6)
-    c1 = g.cameras()
+    c1, p1 = g.cameras(), g.points()
     gba.gba_reset(g.h)
     np.testing.assert_array_equal(g.cameras(), sc.cams0)
+    np.testing.assert_array_equal(g.points(), sc.pts0)
     b = g.solve(6)
-    assert abs(a.final_cost - b.final_cost) <= 1e-12 * a.final_cost
-    np.testing.assert_allclose(g.cameras(), c1, rtol=0, atol=1e-9)
+    assert a.final_cost == b.final_cost and a.trials == b.trials
+    np.testing.assert_array_equal(g.cameras(), c1)
+    np.testing.assert_array_equal(g.points(), p1)
 
 
 def test_torch_allocator_and_stream():
@@ -396,8 +560,8 @@ def test_bal1m_fp64_final_cost_and_solution(acc):
     assert rel <= 1e-8, (rep.final_cost, gold["final_cost"], rel)
     cams = g.cameras()
     pts = g.points()[gold["point_sample"]]
-    err = align.aligned_errors(cams, pts, np.array(gold["cams"]), np.array(gold["points"]))
-    assert err["rel"] <= 1e-6, err
+    err = _aligned(cams, pts, np.array(gold["cams"]), np.array(gold["points"]), 1e-6)
+    print("bal1m fp64 parameter errors by block:", err["blocks"])
 
 
 # ------------------------------------------------------ mixed precision --
@@ -428,8 +592,8 @@ def test_mixed_small_workload_final_cost(precision):
     rep = g.solve(sc.trials)
     res = ba.solve(_oracle(sc), sc.cams0, sc.pts0, sc.trials)
     assert abs(rep.final_cost - res.cost) <= 1e-4 * res.cost, (rep.final_cost, res.cost)
-    err = align.aligned_errors(g.cameras(), g.points(), res.x[0], res.x[1])
-    assert err["rel"] <= 1e-3, err
+    err = _aligned(g.cameras(), g.points(), res.x[0], res.x[1], 1e-3)
+    print(f"small workload precision {precision} errors by block:", err["blocks"])
     acc = [t["candidate_cost"] for t in g.trials() if t["accepted"]]
     assert all(b < a for a, b in zip(acc, acc[1:]))          # FP64 acceptance
 
@@ -447,8 +611,8 @@ def test_bal1m_mixed_final_cost_and_solution(precision, acc):
     rel = abs(rep.final_cost - gold["final_cost"]) / gold["final_cost"]
     assert rel <= 1e-4, (rep.final_cost, gold["final_cost"], rel)
     pts = g.points()[gold["point_sample"]]
-    err = align.aligned_errors(g.cameras(), pts, np.array(gold["cams"]), np.array(gold["points"]))
-    assert err["rel"] <= 1e-3, err
+    err = _aligned(g.cameras(), pts, np.array(gold["cams"]), np.array(gold["points"]), 1e-3)
+    print(f"bal1m precision {precision} final cost rel {rel:.3e}, errors by block:", err["blocks"])
 
 
 @pytest.mark.parametrize("acc", ACC)
@@ -470,8 +634,8 @@ def test_bal8m_proxy_bf16_against_oracle(acc):
     rel = abs(rep.final_cost - gold["final_cost"]) / gold["final_cost"]
     assert rel <= 1e-4, (rep.final_cost, gold["final_cost"], rel)
     pts = g.points()[gold["point_sample"]]
-    err = align.aligned_errors(g.cameras(), pts, np.array(gold["cams"]), np.array(gold["points"]))
-    assert err["rel"] <= 1e-3, err
+    err = _aligned(g.cameras(), pts, np.array(gold["cams"]), np.array(gold["points"]), 1e-3)
+    print(f"bal8m proxy bf16 final cost rel {rel:.3e}, errors by block:", err["blocks"])
 
 
 # ------------------------------------------------- 10k cameras, 8M obs --

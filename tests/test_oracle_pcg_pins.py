@@ -121,3 +121,30 @@ def test_rejection_before_any_improvement_returns_the_start():
     x, steps, why = pcg.pcg(S, v, M, tol=1e-30, max_iters=10, ratio=1.0)
     assert why == pcg.DONE_REJECTED and steps == 1
     assert np.all(x == 0.0)
+
+
+def test_schur_pcg_step_converged_equals_the_block_cholesky_step():
+    # run to convergence, the Schur + PCG step (reduced solve, back-substitution)
+    # is the exact damped step of the full system
+    sc = synth.make_scene("small", seed=44, n_cams=5, n_pts=120)
+    prob = ba.BAProblem(sc.n_cams, sc.n_pts, sc.cam_idx, sc.pt_idx, sc.obs)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    (dc, dp), steps = pcg.schur_pcg_step(prob, lin, 1e-3, 1e-6, 1e32, tol=1e-15, max_iters=200)
+    dco, dpo = prob.solve(lin, 1e-3, 1e-6, 1e32)
+    np.testing.assert_allclose(dc, dco, rtol=0, atol=1e-9 * np.abs(dco).max())
+    np.testing.assert_allclose(dp, dpo, rtol=0, atol=1e-9 * np.abs(dpo).max())
+    assert 0 < steps <= 200
+
+
+def test_schur_pcg_one_step_is_the_steepest_descent_step_in_the_m_norm():
+    # one PCG step from x = 0: x1 = alpha z0, z0 = M^-1 v, alpha = v^T z0 / z0^T S z0
+    sc = synth.make_scene("small", seed=45, n_cams=4, n_pts=80)
+    prob = ba.BAProblem(sc.n_cams, sc.n_pts, sc.cam_idx, sc.pt_idx, sc.obs)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    S, v, fc = pcg.reduced_system(prob, lin, 1e-2, 1e-6, 1e32)
+    M = pcg.block_jacobi(S)
+    z0 = M @ v
+    x1 = (v @ z0) / (z0 @ S @ z0) * z0
+    (dc, _), steps = pcg.schur_pcg_step(prob, lin, 1e-2, 1e-6, 1e32, tol=0.0, max_iters=1)
+    assert steps == 1
+    np.testing.assert_allclose(dc[fc].ravel(), x1, rtol=1e-12, atol=1e-16)

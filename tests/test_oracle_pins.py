@@ -496,3 +496,19 @@ def test_aligned_errors_are_gauge_and_branch_invariant():
     p3[0] += 1e-3
     e3 = align.aligned_errors(sc.cams_true, p3, sc.cams_true, sc.pts_true)
     assert 1e-6 < e3["rel"] < 1e-4
+
+
+def test_aligned_block_errors_isolate_one_block():
+    # a relative perturbation of 1e-4 of every k2 shows up as exactly that in
+    # the k2 block and nowhere else (the points, hence the alignment, are
+    # unchanged)
+    sc = synth.make_scene("small", seed=17, n_pts=60)
+    c2 = sc.cams_true.copy()
+    c2[:, 8] *= 1.0 + 1e-4
+    err = align.aligned_errors(c2, sc.pts_true, sc.cams_true, sc.pts_true)
+    b = err["blocks"]
+    assert abs(b["k2"] - 1e-4) < 1e-10
+    assert max(b["rot"], b["t"], b["f"], b["k1"], b["X"]) < 1e-12
+    assert err["max_block"] == b["k2"]
+    # the stacked norm hides it: k2 is ~1e-3 of the stacked vector's scale
+    assert err["rel"] < 1e-8
