@@ -263,6 +263,19 @@ gba_status gba_get_trials(gba_graph* g, int max_entries, gba_trial* out, int* n_
  * output pointer may be NULL. */
 gba_status gba_eval_edges(gba_graph* g, double* r, double* jc, double* jp, double* w);
 
+/* gba_eval_edges_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the outputs of gba_eval_edges, computed by the same kernels,
+ * without any device or host allocation.  The graph must already be on the
+ * device (gba_prepare, or a solve, after the last change): GBA_ERR_STATE
+ * otherwise.  At most GBA_NOALLOC_MAX_EDGES inserted edges: GBA_ERR_UNSUPPORTED
+ * otherwise.  The working memory is a fixed device array of the library
+ * (about 14 MB, one per GPU, held until the process ends) that every call on
+ * that GPU shares: calls that overlap on one GPU race on it.  Synchronous
+ * (returns after the outputs are in the caller's arrays). */
+#define GBA_NOALLOC_MAX_EDGES 65536
+gba_status gba_eval_edges_noalloc(gba_graph* g, double* r, double* jc, double* jp, double* w);
+
 /* gba_eval_normal_equations: the blocks of H = sum J^T w Omega J and
  * b = sum J^T w Omega r (Eq. 5) at the current parameters: hcc[n_cams x 81],
  * bc[n_cams x 9], hpp[n_pts x 9], bp[n_pts x 3] (row-major 9x9 / 3x3). */

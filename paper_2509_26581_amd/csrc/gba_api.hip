@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -19,6 +20,13 @@
 
 using gba::DeviceGraph;
 
+// Scratch of gba_eval_edges_noalloc: a fixed device array (one copy per GPU,
+// held until the process ends) for the per-edge outputs in the caller's
+// layout (27 doubles per inserted edge) and the edge permutation (one int per
+// active edge).  Host code never passes the array's name to a kernel or a
+// copy: it uses the device address resolved per device by noalloc_scratch().
+static __device__ __align__(256) double scratch[27 * (size_t)GBA_NOALLOC_MAX_EDGES +
+                                                (size_t)GBA_NOALLOC_MAX_EDGES / 2];
 
 struct gba_graph {
     int precision = 0;
@@ -123,6 +131,29 @@ gba_status download_typed(gba_graph* g, const void* src, size_t n, std::vector<d
     return GBA_OK;
 }
 
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[gba::kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), resolved
+// once per device with hipGetSymbolAddress; null (and a message) on failure.
+void* noalloc_scratch(int device, std::string& msg) {
+    if (device < 0 || device >= gba::kMaxDevices) {
+        msg = "device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+
 void zero_edge_outputs(size_t nall, double* r, double* jc, double* jp, double* w) {
     if (r) std::memset(r, 0, sizeof(double) * 2 * nall);
     if (jc) std::memset(jc, 0, sizeof(double) * 18 * nall);
@@ -204,6 +235,10 @@ gba_status gba_create(gba_precision precision, int device, gba_alloc_fn alloc, g
         g->dev.n_cu = prop.multiProcessorCount;
         g->dev.max_lds = prop.sharedMemPerBlock;
     }
+    // set-up of the allocation-free entry point's scratch on this device (a
+    // failure is reported by that entry point, not here)
+    std::string msg;
+    (void)noalloc_scratch(device, msg);
     *out = g;
     return GBA_OK;
 }
@@ -527,6 +562,28 @@ gba_status gba_eval_edges(gba_graph* g, double* r, double* jc, double* jp, doubl
     g->allocator.release(buf);
     if (st != GBA_OK) return st;
     if (e3 != hipSuccess) return fail(g, GBA_ERR_HIP, std::string("eval_edges: ") + hipGetErrorString(e3));
+    return GBA_OK;
+}
+
+gba_status gba_eval_edges_noalloc(gba_graph* g, double* r, double* jc, double* jp, double* w) {
+    if (!g) return GBA_ERR_INVALID_ARG;
+    HIP_TRY(g, hipSetDevice(g->device));
+    if (!g->built || g->dirty)
+        return fail(g, GBA_ERR_STATE, "the graph is not on the device: call gba_prepare first");
+    const size_t ne = g->batch.dg.ne, nall = g->prob.e_cam.size();
+    if (nall > (size_t)GBA_NOALLOC_MAX_EDGES)
+        return fail(g, GBA_ERR_UNSUPPORTED, "more than GBA_NOALLOC_MAX_EDGES (" +
+                                                std::to_string(GBA_NOALLOC_MAX_EDGES) + ") edges");
+    void* buf = noalloc_scratch(g->device, g->err);
+    if (!buf) return GBA_ERR_HIP;
+    if (ne == 0) {
+        zero_edge_outputs(nall, r, jc, jp, w);
+        return GBA_OK;
+    }
+    gba_status st = eval_edges_into(g, buf, r, jc, jp, w);
+    hipError_t e3 = hipStreamSynchronize(g->stream);
+    if (st != GBA_OK) return st;
+    if (e3 != hipSuccess) return fail(g, GBA_ERR_HIP, std::string("eval_edges_noalloc: ") + hipGetErrorString(e3));
     return GBA_OK;
 }
 

@@ -138,6 +138,7 @@ _SIGS = {
     "gba_get_trials": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(gba_trial),
                                       ctypes.POINTER(ctypes.c_int)]),
     "gba_eval_edges": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "gba_eval_edges_noalloc": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "gba_eval_normal_equations": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "gba_eval_step": (ctypes.c_int, [_P, ctypes.c_double, _D, _D, ctypes.POINTER(ctypes.c_int)]),
     "gba_time_matvec": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D]),
@@ -333,6 +334,18 @@ def gba_eval_edges(h, n_edges):
     w = np.empty(n_edges)
     _check(h, load().gba_eval_edges(h, _ptr(r), _ptr(jc), _ptr(jp), _ptr(w)))
     return r, jc, jp, w
+
+
+def gba_eval_edges_noalloc(h, n_edges):
+    r = np.empty((n_edges, 2))
+    jc = np.empty((n_edges, 2, 9))
+    jp = np.empty((n_edges, 2, 3))
+    w = np.empty(n_edges)
+    _check(h, load().gba_eval_edges_noalloc(h, _ptr(r), _ptr(jc), _ptr(jp), _ptr(w)))
+    return r, jc, jp, w
+
+
+GBA_NOALLOC_MAX_EDGES = 65536
 
 
 def gba_eval_normal_equations(h, n_cams, n_pts):
