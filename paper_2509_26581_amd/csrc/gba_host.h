@@ -87,6 +87,7 @@ struct UnionPlan {
     std::vector<int> part_off;   // [max(1, pp.nblk())]
     long long part_total = 0;
     int max_cams = 0;
+    int lds_pp = 0;            // dynamic LDS bytes of the point passes (one-pass scheme)
     bool cam_pass = false;     // camera vector of some problem exceeds LDS (or fixed-order
                                // sums were asked for): two passes
     bool deterministic = false;
@@ -98,8 +99,10 @@ struct DeviceInfo {
     size_t max_lds = 65536;
 };
 
+// precision: the LDS camera sums of the point passes are in the vector type
+// (FP64 or FP32), which decides whether a problem's camera vector fits
 gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning& tune,
-                      const DeviceInfo& dev, UnionPlan& u, std::string& msg);
+                      const DeviceInfo& dev, int precision, UnionPlan& u, std::string& msg);
 
 // Device workspace of a union: assigns the DeviceGraph pointers inside
 // [base, base + bytes) when base is non-null; returns the byte count.

@@ -290,7 +290,7 @@ struct Planner {
 }  // namespace
 
 gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning& tune,
-                      const DeviceInfo& dev, UnionPlan& u, std::string& msg) {
+                      const DeviceInfo& dev, int precision, UnionPlan& u, std::string& msg) {
     u = UnionPlan{};
     const int P = (int)probs.size();
     if (P < 1 || P > kMaxProblems) {
@@ -333,6 +333,8 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     u.tot.n_tiles = (int)st;
     u.tot.n_runs = (int)sr;
     u.tot.n_chunks = (int)sk;
+    // the LDS camera sums of the point passes are FP64 in every mode
+    (void)precision;
     const size_t lds = 9 * (size_t)u.max_cams * sizeof(double);
     const bool fits = lds + 1024 <= dev.max_lds;
     if (tune.accumulation == GBA_ACC_LDS && tune.deterministic) {
@@ -348,6 +350,7 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     // camera-major pass sums every camera in a fixed order
     u.deterministic = tune.deterministic != 0;
     u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits || u.deterministic;
+    u.lds_pp = u.cam_pass ? 0 : (int)lds;
     // automatic: one point-pass workgroup per CU (each flushes one LDS camera
     // partial; the flush grows with the workgroup count, and smaller
     // workgroups measured slower in both schemes)
@@ -441,13 +444,13 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.bc, tsz * 9 * NC);
     L.add(d.hpp_inv, tsz * kHinvStride * NP);
     L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
-    if (u.cam_pass) L.add(d.zbuf, sizeof(double) * 4 * NP);
+    if (u.cam_pass) L.add(d.zbuf, tsz * 4 * NP);
     L.add(d.minv, tsz * 45 * NC);
     L.add(d.v_x, tsz * 9 * NC + 64);   // slack: 16-byte gathers (gather9); back-substitution
     L.add(d.v_r, tsz * 9 * NC);
     L.add(d.v_z, tsz * 9 * NC + 64);   // the product gathers z
     L.add(d.v_p, tsz * 9 * NC);
-    L.add(d.v_q, sizeof(double) * 9 * NC);   // FP64 in every mode (formed by recurrence)
+    L.add(d.v_q, tsz * 9 * NC);
     L.add(d.v_best, tsz * 9 * NC);
     decomp(d.dc_pp, u.pp);
     decomp(d.dc_red, u.red);
@@ -486,7 +489,7 @@ void set_union_scalars(Batch& b, int precision, int loss, double delta) {
     d.block_pp = kPointPassBlock;
     d.cam_pass = u.cam_pass ? 1 : 0;
     d.deterministic = u.deterministic ? 1 : 0;
-    d.lds_pp = u.cam_pass ? 0 : (int)(9 * (size_t)u.max_cams * sizeof(double));
+    d.lds_pp = u.lds_pp;
     d.dc_pp.nblk = u.pp.nblk();
     d.dc_red.nblk = u.red.nblk();
     d.dc_cam.nblk = u.cam.nblk();
@@ -536,7 +539,7 @@ gba_status build_batch(const std::vector<const HostProblem*>& probs, int precisi
         if (st != GBA_OK) return st;
         counts[p] = &imgs[p].n;
     }
-    gba_status st = plan_union(counts, tune, dev, b.plan, msg);
+    gba_status st = plan_union(counts, tune, dev, precision, b.plan, msg);
     if (st != GBA_OK) return st;
     if ((st = b.ensure_mirrors(P, msg)) != GBA_OK) return st;
     const UnionPlan& u = b.plan;

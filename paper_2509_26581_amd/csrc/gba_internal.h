@@ -154,7 +154,7 @@ struct DeviceGraph {
     void* hpp_inv;            // [np][8] damped inverse (inverted in FP64, stored in the block
                               // type), 6 unique entries per row
     void* jst_cm;             // camera-major copy of jst, same layout
-    double* zbuf;             // [np][4] point vectors between the two passes
+    void* zbuf;               // [np][4] point vectors between the two passes (vector type)
     void* minv;               // [nc][45] preconditioner inverse blocks
 
     // Schur / PCG vectors, [nc][9]

@@ -24,12 +24,17 @@ namespace gba {
 // whitening (Eq. 7 kernel on s = r^T Omega r, IRLS weight), storage of the
 // weighted blocks, and point-side sums Hpp_j = sum J_p^T J_p, bp_j =
 // sum J_p^T r (Eq. 5) by segmented wavefront reductions over the point's
-// contiguous edges.  One wavefront per tile of whole points.  Arithmetic is
-// FP64 in every precision mode; T (blocks) and JS (Jacobian) are storage
-// types.  The linear system is built from the stored Jacobian, the gradient
-// b from the FP64 one, so the LM fixed point is that of the FP64 problem.
+// contiguous edges.  One wavefront per tile of whole points.  The camera
+// model is evaluated in FP64 in every precision mode and the Jacobian rounded
+// once to its storage type JS (T is the block type): an FP32 evaluation
+// leaves the gradient with components along the gauge directions, where the
+// reduced system has only the damping as curvature, and the PCG then needs
+// more iterations.  The linear system is built from the stored Jacobian, the
+// gradient b from the FP64 one, so the LM fixed point is that of the FP64
+// problem.  kRaw: also write the FP64 evaluation in the caller's layout (the
+// edge evaluation entry point), a separate instantiation.
 // ==========================================================================
-template <typename T, typename JS>
+template <typename T, typename JS, bool kRaw>
 __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
     if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     const int l = lane_id();
@@ -63,7 +68,7 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
                 jac_save<JS>(g.jst, e, ev.jc, ev.jp);
                 rw[e] = (T)ev.r[0];
                 rw[ne + e] = (T)ev.r[1];
-                if (raw.pos) {
+                if (kRaw) {
                     // unweighted values for verification, at the edge's
                     // insertion index in the caller's layout
                     EdgeEval<double> ed;
@@ -214,36 +219,41 @@ enum { kAssemble = 0, kPrecond = 1, kPrecondRhs = 2 };
 
 // y += J_c^T (J_p t) for one edge (the reduced RHS term of a run).
 template <typename A>
-__device__ __forceinline__ void rhs_term(const double (&jc)[2][9], const double (&jp)[2][3],
+__device__ __forceinline__ void rhs_term(const A (&jc)[2][9], const A (&jp)[2][3],
                                          const A (&t)[3], A (&y)[9]) {
-    const A u0 = (A)jp[0][0] * t[0] + (A)jp[0][1] * t[1] + (A)jp[0][2] * t[2];
-    const A u1 = (A)jp[1][0] * t[0] + (A)jp[1][1] * t[1] + (A)jp[1][2] * t[2];
+    const A u0 = jp[0][0] * t[0] + jp[0][1] * t[1] + jp[0][2] * t[2];
+    const A u1 = jp[1][0] * t[0] + jp[1][1] * t[1] + jp[1][2] * t[2];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) y[k] += (A)jc[0][k] * u0 + (A)jc[1][k] * u1;
+    for (int k = 0; k < 9; ++k) y[k] += jc[0][k] * u0 + jc[1][k] * u1;
 }
 
 template <typename T, typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
-    constexpr int K = kMode == kAssemble ? 54 : 45;
+    constexpr int K = 45;
     __shared__ double red[4][54];
     const int chunk = blockIdx.x;
     const int cam = g.chunk_cam[chunk];
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
     const bool cfix = g.cam_fixed[cam] != 0;
-    // kPrecond accumulates in the block type: FP32 in the mixed modes, where
-    // a thread sums only its few runs before the FP64 workgroup and chunk
-    // sums (the blocks are a preconditioner, computed at >= FP32)
-    using AccT = std::conditional_t<kMode != kAssemble, T, double>;
+    // block entries: the assembly evaluates the camera model in FP64 (see
+    // the linearisation) and sums in FP64; the preconditioner computes and
+    // accumulates its per-thread sums in the block type (FP32 in the mixed
+    // modes: the blocks are a preconditioner, kept >= FP32); wavefront,
+    // workgroup and chunk sums in FP64
+    using AccT = std::conditional_t<kMode == kAssemble, double, T>;
     AccT acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = (AccT)0;
     // kPrecondRhs: the reduced RHS sums of the camera ride on the same pass over
-    // the runs (per thread in AccT over its few runs, FP64 across threads and
-    // chunks, as the block entries)
+    // the runs (accumulated as the block entries)
     AccT y[9];
+    double gb[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) y[k] = (AccT)0;
+    for (int k = 0; k < 9; ++k) {
+        y[k] = (AccT)0;
+        gb[k] = 0.0;
+    }
     const int ne = g.ne;
     if (kMode == kAssemble) {
         // edge-parallel over the chunk's edges (no per-run state here): the
@@ -259,8 +269,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                 whiten<double, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
                 // gradient from the unrounded Jacobian, before it is rounded
 #pragma unroll
-                for (int a = 0; a < 9; ++a)
-                    acc[45 + a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
+                for (int a = 0; a < 9; ++a) gb[a] += ev.jc[0][a] * ev.r[0] + ev.jc[1][a] * ev.r[1];
                 double jc[2][9], jp[2][3];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
@@ -306,23 +315,15 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
             for (int r = 0; r < 3; ++r)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Hi[r][c] = (AccT)((const T*)g.hpp_inv)[kHinvStride * j + sym3(r, c)];
-            double jcd[2][9], jpd[2][3];
-            jac_load<JS>(g.jst_cm, q0, jcd, jpd);
+            AccT jc[2][9], jp[2][3];
+            jac_load<JS>(g.jst_cm, q0, jc, jp);
             // the reduced RHS term of the run: J_c^T J_p t with
             // t = Hpp_lambda^-1 bp_j
             AccT t[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
                 t[r] = Hi[r][0] * (AccT)b0 + Hi[r][1] * (AccT)b1 + Hi[r][2] * (AccT)b2;
-            if (kMode == kPrecondRhs) rhs_term(jcd, jpd, t, y);
-            AccT jc[2][9], jp[2][3];
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-#pragma unroll
-                for (int a = 0; a < 9; ++a) jc[r][a] = (AccT)jcd[r][a];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) jp[r][a] = (AccT)jpd[r][a];
-            }
+            if (kMode == kPrecondRhs) rhs_term(jc, jp, t, y);
             if (single) {
                 // one edge: W Hpp^-1 W^T = J_c^T A J_c with the 2x2
                 // A = J_p Hpp^-1 J_p^T (fewer operations than forming W)
@@ -354,15 +355,8 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 #pragma unroll
                     for (int b = 0; b < 3; ++b) W[a][b] = jc[0][a] * jp[0][b] + jc[1][a] * jp[1][b];
                 for (int q = q0 + 1; q < qe && g.cm_pt[q] == j; ++q) {
-                    jac_load<JS>(g.jst_cm, q, jcd, jpd);
-                    if (kMode == kPrecondRhs) rhs_term(jcd, jpd, t, y);
-#pragma unroll
-                    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-                        for (int a = 0; a < 9; ++a) jc[r][a] = (AccT)jcd[r][a];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) jp[r][a] = (AccT)jpd[r][a];
-                    }
+                    jac_load<JS>(g.jst_cm, q, jc, jp);
+                    if (kMode == kPrecondRhs) rhs_term(jc, jp, t, y);
 #pragma unroll
                     for (int a = 0; a < 9; ++a)
 #pragma unroll
@@ -388,13 +382,20 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double v = wave_sum((double)acc[k]);
-        if (lane_id() == 0) red[w][k] = v;
+        const AccT v = wave_sum(acc[k]);
+        if (lane_id() == 0) red[w][k] = (double)v;
     }
     if (kMode == kPrecondRhs) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const double v = wave_sum((double)y[k]);
+            if (lane_id() == 0) red[w][45 + k] = v;
+        }
+    }
+    if (kMode == kAssemble) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double v = wave_sum(gb[k]);
             if (lane_id() == 0) red[w][45 + k] = v;
         }
     }
@@ -602,8 +603,8 @@ __device__ __forceinline__ PcgState pcg_decision(const DeviceGraph& g, int prob)
 // One entry of the direction: z + beta p_old rounded to the vector type, or z
 // on the first step.
 template <typename VT>
-__device__ __forceinline__ VT dir_entry(VT z, VT pold, int act, double beta) {
-    return (act & kActRun) ? (VT)fma(beta, (double)pold, (double)z) : z;
+__device__ __forceinline__ VT dir_entry(VT z, VT pold, int act, VT beta) {
+    return (act & kActRun) ? fma(beta, pold, z) : z;
 }
 
 // ==========================================================================
@@ -622,11 +623,12 @@ template <typename VT, typename JS, typename AT, int kMode>
 __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const void* __restrict__ J,
                                                      const VT* __restrict__ vin, AT* __restrict__ out) {
     if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
-    // Arithmetic in FP64 whatever the storage type: the product chain
-    // J_c p -> J_p^T -> Hpp^-1 -> J_p -> J_c^T and the final cancellation
-    // against Hcc p amplify rounding, and FP64 costs nothing in this
-    // memory-bound pass.
-    using T = double;
+    // Arithmetic in the vector type (FP32 in the mixed modes); the camera sums
+    // in LDS are AT = FP64 in every mode (ds_add_f64: FP32 LDS atomics
+    // measured 2.4x slower for this pattern); the back-substitution's model
+    // terms are summed in FP64 (gain ratio).
+    using T = VT;
+    T* zbuf = (T*)g.zbuf;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     AT* acc_lds = (AT*)smem_raw;
     __shared__ double red[16];
@@ -714,9 +716,9 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                     zz[1] = h01 * v0 + h11 * v1 + h12 * v2;
                     zz[2] = h02 * v0 + h12 * v1 + h22 * v2;
                     if (kMode == kMatvec && cpass) {
-                        g.zbuf[4 * j] = zz[0];
-                        g.zbuf[4 * j + 1] = zz[1];
-                        g.zbuf[4 * j + 2] = zz[2];
+                        zbuf[4 * j] = zz[0];
+                        zbuf[4 * j + 1] = zz[1];
+                        zbuf[4 * j + 2] = zz[2];
                     }
                     if (kMode == kBacksub) {
                         zz[0] = -zz[0];
@@ -798,9 +800,9 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
                 z[2] = H[2] * tt[0] + H[4] * tt[1] + H[5] * tt[2];
                 if (kMode == kMatvec && cpass) {
                     if (l == 0) {
-                        g.zbuf[4 * j] = z[0];
-                        g.zbuf[4 * j + 1] = z[1];
-                        g.zbuf[4 * j + 2] = z[2];
+                        zbuf[4 * j] = z[0];
+                        zbuf[4 * j + 1] = z[1];
+                        zbuf[4 * j + 2] = z[2];
                     }
                     continue;   // uniform: the whole wave
                 }
@@ -888,17 +890,17 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
     constexpr int kCpl = 16 / (int)sizeof(T);
     constexpr int kCols = kRedComps / kCpl;
     constexpr int kGroups = 1024 / kCols;
-    __shared__ double red[kGroups][kRedComps];
+    __shared__ T red[kGroups][kRedComps];
     __shared__ double dred[16];
     int kb, ke;
     const int prob = decomp_block(g.dc_red, blockIdx.x, kb, ke);
     int act = 0;
-    double beta = 0.0;
+    T beta = 0;
     if (kMode == kMatvec) {
         const PcgState* dp = g.pcg_dec + prob;
         act = dp->act;
         if (!(act & kActStep)) return;   // this problem's PCG has stopped
-        beta = dp->beta;
+        beta = (T)dp->beta;
     }
     const int tid = threadIdx.x;
     const int k = kb + tid;                               // component (threads < kRedComps)
@@ -906,30 +908,32 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
     // the damped diagonal block row, z, p and q (or bc) of this component are
     // loaded before the partial sums, so their latency overlaps
     const int i = k / 9, r = k % 9;
-    double h[9], pv[9], lambda = 0.0, bk = 0.0, qold = 0.0;
+    // arithmetic in the vector type (FP32 in the mixed modes); the dot
+    // partials p^T q in FP64
+    T h[9], pv[9], lambda = 0, bk = 0, qold = 0;
     T pold = 0;
     if (own) {
         if (kMode == kRhs) {
-            bk = (double)((const T*)g.bc)[k];
+            bk = ((const T*)g.bc)[k];
         } else {
-            lambda = fabs(g.lam[prob]);   // negative: problem idle this trial
+            lambda = (T)fabs(g.lam[prob]);   // negative: problem idle this trial
             const T* Hcc = (const T*)g.hcc;
             const T* z = (const T*)g.v_z;
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-                h[c] = (double)Hcc[i * 45 + sym9(r, c)];
-                pv[c] = (double)z[9 * i + c];
+                h[c] = Hcc[i * 45 + sym9(r, c)];
+                pv[c] = z[9 * i + c];
             }
             pold = ((const T*)g.v_p)[k];
-            qold = ((const double*)g.v_q)[k];
+            qold = ((const T*)g.v_q)[k];
         }
     }
-    double tot = 0.0;
+    T tot = 0;
     if (g.cam_pass) {
         // two-pass scheme: the camera's chunk sums from k_cam_pass
         if (own)
             for (int c = g.cam_chunk_off[i]; c < g.cam_chunk_off[i + 1]; ++c)
-                tot += g.chunk_partial[54 * c + r];
+                tot += (T)g.chunk_partial[54 * c + r];
     } else {
         const int col = tid % kCols, grp = tid / kCols;
         const int c0 = kCpl * col;                        // first component of this lane
@@ -942,11 +946,11 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
         const size_t stride = (size_t)(9 * (g.prob_cam_off[prob + 1] - g.prob_cam_off[prob]) + 3) / 4 * 4;
         const T* base = (const T*)g.cam_partial + g.pp_part_off[q0] + kl;   // vector type
         const int nq = q1 - q0;
-        double a[4][kCpl];
+        T a[4][kCpl];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int u = 0; u < kCpl; ++u) a[v][u] = 0.0;
+            for (int u = 0; u < kCpl; ++u) a[v][u] = 0;
         if (kb + c0 < ke) {
             for (int q = grp; q < nq; q += 4 * kGroups) {
                 Chunk16 x[4];
@@ -957,14 +961,14 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
                 for (int v = 0; v < 4; ++v)
                     if (q + v * kGroups < nq)
 #pragma unroll
-                        for (int u = 0; u < kCpl; ++u) a[v][u] += chunk_get(x[v], u, (T*)nullptr);
+                        for (int u = 0; u < kCpl; ++u) a[v][u] += chunk_get<T, T>(x[v], u);
             }
         }
 #pragma unroll
         for (int u = 0; u < kCpl; ++u) red[grp][c0 + u] = (a[0][u] + a[1][u]) + (a[2][u] + a[3][u]);
         __syncthreads();
         if (own) {
-            double t0 = 0.0, t1 = 0.0;
+            T t0 = 0, t1 = 0;
             for (int q = 0; q < kGroups; q += 2) {
                 t0 += red[q][tid];
                 t1 += red[q + 1][tid];
@@ -977,23 +981,23 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
         if (kMode == kRhs) {
             ((T*)g.v_r)[k] = (T)(-bk + tot);
         } else {
-            double hp = 0.0;
+            T hp = 0;
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-                double hc = h[c];
-                if (c == r) hc += lambda * fmin(fmax(hc, min_diag), max_diag);
+                T hc = h[c];
+                if (c == r) hc += lambda * fmin(fmax(hc, (T)min_diag), (T)max_diag);
                 hp += hc * pv[c];
             }
-            // S z, then q = S p = S z + beta q_old (FP64) and p = z + beta p_old
-            const double sz = hp - tot;
-            const double q = (act & kActRun) ? fma(beta, qold, sz) : sz;
-            double zk = pv[0];
+            // S z, then q = S p = S z + beta q_old and p = z + beta p_old
+            const T sz = hp - tot;
+            const T q = (act & kActRun) ? fma(beta, qold, sz) : sz;
+            T zk = pv[0];
 #pragma unroll
             for (int c = 1; c < 9; ++c) zk = c == r ? pv[c] : zk;
-            const T pk = dir_entry<T>((T)zk, pold, act, beta);
-            ((double*)g.v_q)[k] = q;
+            const T pk = dir_entry<T>(zk, pold, act, beta);
+            ((T*)g.v_q)[k] = q;
             ((T*)g.v_p)[k] = pk;
-            dot = (double)pk * q;
+            dot = (double)pk * (double)q;
         }
     }
     if (kMode == kMatvec) {
@@ -1014,10 +1018,10 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
 template <typename T>
 __device__ __forceinline__ T minv_row(const T* __restrict__ Minv, const T* r_lds, int i, int a,
                                       int base) {
-    double s = 0.0;
+    T s = 0;
 #pragma unroll
-    for (int b = 0; b < 9; ++b) s += (double)Minv[i * 45 + sym9(a, b)] * (double)r_lds[base + b];
-    return (T)s;
+    for (int b = 0; b < 9; ++b) s += Minv[i * 45 + sym9(a, b)] * r_lds[base + b];
+    return s;
 }
 
 // PCG start, vectors: x = 0 and the best iterate of the rejection ratio
@@ -1102,7 +1106,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     const int tid = threadIdx.x;
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
-    // A PCG stopped before this iteration (the rest of a replayed chunk of
+    // T PCG stopped before this iteration (the rest of a replayed chunk of
     // iterations) exits after one load.  Otherwise every load of the step is
     // issued before the next wait (the dot, alpha).
     const PcgState* dp = g.pcg_dec + prob;
@@ -1124,14 +1128,15 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     double pq = 0.0;
     for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
         pq += g.pq_partial[b];
-    double xk = 0.0, pk = 0.0, qk = 0.0, rk = 0.0;
+    // vector arithmetic in the vector type; dots (and alpha) in FP64
+    T xk = 0, pk = 0, qk = 0, rk = 0;
     T m[9];
     const int i = k / 9, a = k % 9;
     if (valid) {
-        xk = (double)x[k];
-        pk = (double)((const T*)g.v_p)[k];
-        qk = ((const double*)g.v_q)[k];
-        rk = (double)r[k];
+        xk = x[k];
+        pk = ((const T*)g.v_p)[k];
+        qk = ((const T*)g.v_q)[k];
+        rk = r[k];
         const T* __restrict__ Minv = (const T*)g.minv;
 #pragma unroll
         for (int b = 0; b < 9; ++b) m[b] = Minv[i * 45 + sym9(a, b)];
@@ -1146,11 +1151,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     }
     const bool ok = pq > 0.0 && isfinite(pq);
     if ((act & kActStep) && ok) {
-        const double alpha = rz_dec / pq;
+        const T alpha = (T)(rz_dec / pq);
         T rv = 0;
         if (valid) {
-            x[k] = (T)(xk + alpha * pk);
-            rv = (T)(rk - alpha * qk);
+            x[k] = (T)fma(alpha, pk, xk);
+            rv = (T)fma(-alpha, qk, rk);
             r[k] = rv;
         }
         r_lds[tid] = rv;
@@ -1158,9 +1163,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
         double rz = 0.0, rr = 0.0;
         if (valid) {
             const int base = tid - a;
-            double sz = 0.0;
+            T sz = 0;
 #pragma unroll
-            for (int b = 0; b < 9; ++b) sz += (double)m[b] * (double)r_lds[base + b];
+            for (int b = 0; b < 9; ++b) sz += (T)m[b] * (T)r_lds[base + b];
             const T zv = (T)sz;
             ((T*)g.v_z)[k] = zv;
             rz = (double)rv * (double)zv;
@@ -1319,26 +1324,29 @@ __global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
 //   kRhs: z_j = Hpp_lambda^-1 bp_j;  kMatvec: z_j = Hpp_lambda^-1 sum J_p^T J_c v
 //   (v the product's camera vector).
 // ==========================================================================
-template <typename JS, int kMode>
+template <typename VT, typename JS, int kMode>
 __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
-    if (!jac_type_ok<JS>(g)) return;   // instantiated for another mode
-    __shared__ double red[4][9];
+    if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
+    // arithmetic and sums in the vector type (FP32 in the mixed modes)
+    using T = VT;
+    __shared__ T red[4][9];
     const int chunk = blockIdx.x;
     const int cam = g.chunk_cam[chunk];
     if (kMode == kMatvec && !(g.pcg_dec[g.cam_prob[cam]].act & kActStep)) return;   // stopped
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
-    double y[9];
+    const T* __restrict__ zbuf = (const T*)g.zbuf;
+    T y[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) y[k] = 0.0;
+    for (int k = 0; k < 9; ++k) y[k] = (T)0;
     for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
         const int q0 = g.cm_run_off[run], q1 = g.cm_run_off[run + 1];
         const int j = g.cm_pt[q0];
-        const double z0 = g.zbuf[4 * j], z1 = g.zbuf[4 * j + 1], z2 = g.zbuf[4 * j + 2];
+        const T z0 = zbuf[4 * j], z1 = zbuf[4 * j + 1], z2 = zbuf[4 * j + 2];
         for (int q = q0; q < q1; ++q) {
-            double jc[2][9], jp[2][3];
+            T jc[2][9], jp[2][3];
             jac_load<JS>(g.jst_cm, q, jc, jp);
-            const double u0 = jp[0][0] * z0 + jp[0][1] * z1 + jp[0][2] * z2;
-            const double u1 = jp[1][0] * z0 + jp[1][1] * z1 + jp[1][2] * z2;
+            const T u0 = jp[0][0] * z0 + jp[0][1] * z1 + jp[0][2] * z2;
+            const T u1 = jp[1][0] * z0 + jp[1][1] * z1 + jp[1][2] * z2;
 #pragma unroll
             for (int k = 0; k < 9; ++k) y[k] += jc[0][k] * u0 + jc[1][k] * u1;
         }
@@ -1346,15 +1354,15 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
     const int w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const double v = wave_sum(y[k]);
+        const T v = wave_sum(y[k]);
         if (lane_id() == 0) red[w][k] = v;
     }
     __syncthreads();
     if (threadIdx.x < 9) {
         const int nw = blockDim.x >> 6;
-        double s = 0.0;
+        T s = 0;
         for (int q = 0; q < nw; ++q) s += red[q][threadIdx.x];
-        g.chunk_partial[54 * chunk + threadIdx.x] = s;
+        g.chunk_partial[54 * chunk + threadIdx.x] = (double)s;
     }
 }
 
@@ -1362,13 +1370,15 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
+    using PT = T;
     const T* bp = (const T*)g.bp;
+    PT* zbuf = (PT*)g.zbuf;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.np; j += gridDim.x * blockDim.x) {
-        const double b0 = (double)bp[j], b1 = (double)bp[g.np + j], b2 = (double)bp[2 * g.np + j];
+        const PT b0 = bp[j], b1 = bp[g.np + j], b2 = bp[2 * g.np + j];
         const T* H = (const T*)g.hpp_inv + kHinvStride * j;
-        g.zbuf[4 * j] = H[0] * b0 + H[1] * b1 + H[2] * b2;
-        g.zbuf[4 * j + 1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
-        g.zbuf[4 * j + 2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
+        zbuf[4 * j] = H[0] * b0 + H[1] * b1 + H[2] * b2;
+        zbuf[4 * j + 1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
+        zbuf[4 * j + 2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
     }
 }
 
@@ -1412,15 +1422,24 @@ hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* r
     if (g.mode == kModeFP64) {
         if (zero_blocks) hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.hpp, 0.0, (size_t)6 * g.np);
         if (zero_blocks) hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.bp, 0.0, (size_t)3 * g.np);
-        hipLaunchKernelGGL((k_linearize<double, double>), dim3(grid), dim3(256), 0, s, g, r);
+        if (r.pos)
+            hipLaunchKernelGGL((k_linearize<double, double, true>), dim3(grid), dim3(256), 0, s, g, r);
+        else
+            hipLaunchKernelGGL((k_linearize<double, double, false>), dim3(grid), dim3(256), 0, s, g, r);
     } else if (g.mode == kModeFP32) {
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
-        hipLaunchKernelGGL((k_linearize<float, float>), dim3(grid), dim3(256), 0, s, g, r);
+        if (r.pos)
+            hipLaunchKernelGGL((k_linearize<float, float, true>), dim3(grid), dim3(256), 0, s, g, r);
+        else
+            hipLaunchKernelGGL((k_linearize<float, float, false>), dim3(grid), dim3(256), 0, s, g, r);
     } else {  // FP32 blocks, BF16 Jacobian
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
-        hipLaunchKernelGGL((k_linearize<float, bf16>), dim3(grid), dim3(256), 0, s, g, r);
+        if (r.pos)
+            hipLaunchKernelGGL((k_linearize<float, bf16, true>), dim3(grid), dim3(256), 0, s, g, r);
+        else
+            hipLaunchKernelGGL((k_linearize<float, bf16, false>), dim3(grid), dim3(256), 0, s, g, r);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
@@ -1538,11 +1557,11 @@ template <int kMode>
 static void cam_pass(const DeviceGraph& g, hipStream_t s) {
     if (g.n_chunks == 0) return;
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_pass<double, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_cam_pass<double, double, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
     else if (g.mode == kModeFP32)
-        hipLaunchKernelGGL((k_cam_pass<float, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_cam_pass<float, float, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
     else
-        hipLaunchKernelGGL((k_cam_pass<bf16, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_cam_pass<float, bf16, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
 }
 
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {

@@ -205,7 +205,7 @@ size_t gba_server::union_bytes_for(const std::vector<const ImageCounts*>& c) {
     UnionPlan u;
     std::string m;
     if (c.empty()) return 0;
-    if (plan_union(c, tune, dev, u, m) != GBA_OK) return std::numeric_limits<size_t>::max();
+    if (plan_union(c, tune, dev, cfg.precision, u, m) != GBA_OK) return std::numeric_limits<size_t>::max();
     return align256(layout_union(u, cfg.precision, nullptr, nullptr));
 }
 
@@ -352,7 +352,7 @@ gba_status gba_server::repack() {
     if (order.empty()) return GBA_OK;
     std::vector<const ImageCounts*> counts;
     for (Request* r : order) counts.push_back(&r->counts);
-    st = plan_union(counts, tune, dev, batch.plan, err);
+    st = plan_union(counts, tune, dev, cfg.precision, batch.plan, err);
     if (st != GBA_OK) return st;
     const UnionPlan& u = batch.plan;
     const size_t ub = align256(layout_union(u, cfg.precision, nullptr, nullptr));

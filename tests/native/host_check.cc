@@ -301,7 +301,7 @@ static void check_plans() {
             dev.max_lds = 160 * 1024;
             UnionPlan u;
             std::string msg;
-            CHECK(plan_union(counts, tune, dev, u, msg) == GBA_OK);
+            CHECK(plan_union(counts, tune, dev, GBA_FP64, u, msg) == GBA_OK);
             CHECK(u.cam_pass == (det == 1));
             check_decomp(u.pp, u.tile_off, false, tune.tiles_per_block);
             std::vector<int> comp(P + 1);
@@ -336,7 +336,7 @@ static void check_plans() {
         std::string msg;
         DeviceInfo dev;
         dev.max_lds = 160 * 1024;
-        CHECK(plan_union(counts, bad, dev, u, msg) == GBA_ERR_INVALID_ARG);
+        CHECK(plan_union(counts, bad, dev, GBA_FP64, u, msg) == GBA_ERR_INVALID_ARG);
     }
     // a non positive-definite information matrix is refused by the build
     std::mt19937_64 r2(5);

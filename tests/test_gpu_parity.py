@@ -187,19 +187,54 @@ def _pcg_case(seed=34, lam=1e-2):
     return sc, S, v, fc, pcg.block_jacobi(S)
 
 
-@pytest.mark.parametrize("precision,rtol", [(gba.GBA_FP64, 1e-8), (gba.GBA_MIXED_FP32, 2e-5)])
+def _block_rel_err(a, b):
+    """Largest error of a camera-shaped array per parameter block, relative to
+    that block's largest reference entry (the measure of _close)."""
+    a, b = np.asarray(a).reshape(-1, 9), np.asarray(b).reshape(-1, 9)
+    return max(np.abs(a[:, sl] - b[:, sl]).max() / np.abs(b[:, sl]).max()
+               for sl in CAM_BLOCKS.values())
+
+
+def _fp32_iterate_tolerance(sc, S, v, M, k, lam=1e-2, c=16.0, trials=4):
+    """Tolerance of a mixed-FP32 PCG iterate, from the arithmetic: the mixed
+    products form S z = Hcc_lambda z - sum W Hpp^-1 W^T z in FP32, so each
+    entry of S carries an error of about c u (|Hcc_lambda| + |the point
+    elimination term|) <= c u (|S| + 2 |blockdiag Hcc_lambda|), and v about
+    c u |v|.  The oracle's own k-th iterate on systems perturbed at random by
+    that much deviates by `dev`; the tolerance is 10 dev (at least 1e-7)."""
+    prob = _oracle(sc)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    dc_diag, _ = prob.damped_diagonal(lin, 1e-6, 1e32)
+    hd = np.zeros_like(S)
+    for n, i in enumerate(prob.free_cams):
+        hd[9 * n:9 * n + 9, 9 * n:9 * n + 9] = lin.Hcc[i] + lam * np.diag(dc_diag[i])
+    scale = c * U32 * (np.abs(S) + 2 * np.abs(hd))
+    x, _, _ = pcg.pcg(S, v, M, tol=1e-30, max_iters=k)
+    rng = np.random.default_rng(7)
+    dev = 0.0
+    for _ in range(trials):
+        E = rng.uniform(-1.0, 1.0, S.shape)
+        Sp = S + scale * 0.5 * (E + E.T)
+        vp = v * (1.0 + c * U32 * rng.uniform(-1.0, 1.0, v.shape))
+        xp, _, _ = pcg.pcg(Sp, vp, M, tol=1e-30, max_iters=k)
+        dev = max(dev, _block_rel_err(xp, x))
+    return max(10.0 * dev, 1e-7)
+
+
+@pytest.mark.parametrize("precision", [gba.GBA_FP64, gba.GBA_MIXED_FP32])
 @pytest.mark.parametrize("k", [1, 3, 7])
-def test_truncated_pcg_matches_the_oracle_iterate(k, precision, rtol):
-    # the iteration limit: the k-th PCG iterate (not the solution).  Mixed
-    # FP32 (FP32 Jacobian, blocks and vectors; q and the dots FP64) follows
-    # the FP64 iterates to the FP32 rounding of its system (~1e-7 relative
-    # per entry, grown by the short Krylov recurrence)
+def test_truncated_pcg_matches_the_oracle_iterate(k, precision):
+    # the iteration limit: the k-th PCG iterate (not the solution).  FP64 to
+    # 1e-8; mixed FP32 (FP32 arithmetic, FP64 dots) to the sensitivity of the
+    # k-th iterate to FP32 errors in its system
     sc, S, v, fc, M = _pcg_case()
     x, steps, why = pcg.pcg(S, v, M, tol=1e-30, max_iters=k)
     assert why == pcg.DONE_MAX_ITERS and steps == k
+    rtol = 1e-8 if precision == gba.GBA_FP64 else _fp32_iterate_tolerance(sc, S, v, M, k)
     g = _graph(sc, precision=precision, pcg_max_iters=k, pcg_tol=1e-30)
     dc, _, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
     assert iters == k
+    print(f"k={k} precision {precision}: error {_block_rel_err(dc[fc], x):.3e}, tolerance {rtol:.3e}")
     _close(dc[fc], x.reshape(-1, 9), rtol, f"camera step after {k} PCG steps")
 
 
@@ -568,21 +603,54 @@ def test_bal1m_fp64_final_cost_and_solution(acc):
 MIXED = [gba.GBA_MIXED_FP32, gba.GBA_MIXED_BF16]
 
 
+U32 = 2.0 ** -24   # FP32 unit roundoff
+
+
+def _mixed_block_bounds(sc, lin, jac_unit, c=4.0):
+    """Element-wise error bounds of the mixed modes' normal-equation blocks
+    against the FP64 oracle.  The mixed modes evaluate the camera model in
+    FP64 and round each Jacobian entry once to its storage type (relative
+    error jac_unit: 2^-24 FP32, 2^-8 BF16); the Hessian blocks are summed in
+    FP64 from the stored entries and stored in FP32, the gradient is summed in
+    FP64 from the unrounded Jacobian and stored in FP32.  Hence
+    |dH| <= (2 jac_unit + c u) sum |J|^T w |J| and |db| <= c u sum |J|^T w |r|
+    (c = 4 covers the FP64 sums and the final FP32 rounding)."""
+    w = lin.w[:, None, None]
+    aJc, aJp = np.abs(lin.Jc), np.abs(lin.Jp)
+    ar = np.abs(lin.r)[:, :, None]
+    hunit = 2 * jac_unit + c * U32
+
+    def ssum(idx, v, n):
+        out = np.zeros((n,) + v.shape[1:])
+        np.add.at(out, idx, v)
+        return out
+    Hcc = hunit * ssum(sc.cam_idx, np.matmul(aJc.transpose(0, 2, 1), w * aJc), sc.n_cams)
+    Hpp = hunit * ssum(sc.pt_idx, np.matmul(aJp.transpose(0, 2, 1), w * aJp), sc.n_pts)
+    bc = c * U32 * ssum(sc.cam_idx, np.matmul(aJc.transpose(0, 2, 1), w * ar)[:, :, 0], sc.n_cams)
+    bp = c * U32 * ssum(sc.pt_idx, np.matmul(aJp.transpose(0, 2, 1), w * ar)[:, :, 0], sc.n_pts)
+    return Hcc, Hpp, bc, bp
+
+
 @pytest.mark.parametrize("precision", MIXED)
 def test_mixed_normal_equation_blocks(precision):
     sc = synth.make_scene("small", seed=31, n_cams=9, n_pts=500, noise_px=2.0)
     g = _graph(sc, precision=precision, loss=robust.HUBER, delta=1.0)
     hcc, bc, hpp, bp = gba.gba_eval_normal_equations(g.h, 9, 500)
     lin = _oracle(sc, loss=robust.HUBER, delta=1.0).linearize((sc.cams0, sc.pts0))
-    # Hessian blocks are formed (in FP64) from the stored Jacobian, so their
-    # error follows the storage unit roundoff: FP32 2^-24, BF16 2^-9 per entry
-    # (products about twice that); the gradient comes from the FP64 Jacobian
-    # and is rounded once to FP32.
-    h_tol = 1e-6 if precision == gba.GBA_MIXED_FP32 else 8e-3
-    _close(hcc, lin.Hcc, h_tol, "Hcc")
-    _close(hpp, lin.Hpp, h_tol, "Hpp")
-    _close(bc, lin.bc, 1e-6, "bc")
-    _close(bp, lin.bp, 1e-6, "bp")
+    unit = U32 if precision == gba.GBA_MIXED_FP32 else 2.0 ** -8   # BF16: 8 significand bits
+    bounds = _mixed_block_bounds(sc, lin, unit)
+    for name, a, b, bnd in (("Hcc", hcc, lin.Hcc, bounds[0]), ("Hpp", hpp, lin.Hpp, bounds[1]),
+                            ("bc", bc, lin.bc, bounds[2]), ("bp", bp, lin.bp, bounds[3])):
+        err = np.abs(np.asarray(a) - b)
+        ratio = float((err / np.maximum(bnd, 1e-300)).max())
+        print(f"{name}: largest error / bound = {ratio:.3f}")
+        assert np.all(err <= bnd), (name, ratio)
+    if precision == gba.GBA_MIXED_FP32:
+        # and per parameter block against its own scale
+        _close(hcc, lin.Hcc, 1e-6, "Hcc")
+        _close(hpp, lin.Hpp, 1e-6, "Hpp")
+        _close(bc, lin.bc, 1e-6, "bc")
+        _close(bp, lin.bp, 1e-6, "bp")
 
 
 @pytest.mark.parametrize("precision", MIXED)
