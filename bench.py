@@ -32,10 +32,10 @@ METRIC = "LM iter/s + PCG HBM GB/s at 1M obs; p50/p99 latency for local-BA strea
 HBM_PEAK_GBS = 8000.0
 PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf16", 2)}
 # HBM bytes per matvec launch measured with rocprofv3 counters on the 1M-observation
-# workload (FETCH_SIZE x 2 + WRITE_SIZE, the factor 2 from a 256 MiB copy probe whose
-# FETCH_SIZE reads half its size); see profiles/.  None until measured for the
-# current kernel.
-MEASURED_TRAFFIC = {"fp32": None, "fp64": 235340246, "bf16": None}
+# workload (FETCH_SIZE x 2 + WRITE_SIZE; the factor 2 from the streaming read of a
+# 256 MiB buffer by gba_hbm_probe, whose FETCH_SIZE counts half of it); see
+# profiles/.  None until measured for the current kernel.
+MEASURED_TRAFFIC = {"fp32": 120250972, "fp64": 235340246, "bf16": 72177546}
 MATVEC_WARMUP, MATVEC_LAUNCHES = 20, 200
 
 
@@ -173,8 +173,11 @@ def main():
     ap.add_argument("--serve-budget-mb", type=int, default=4096)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="before the run, one device-to-device copy of this many MiB "
-                         "(calibrates HBM byte counters; not timed)")
+                    help="before the run, one fill (write) and one streaming read "
+                         "(gba_hbm_probe) of a buffer of this many MiB: calibrates HBM byte "
+                         "counters")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="fixed-order reductions (gba_options.deterministic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path",
@@ -191,13 +194,17 @@ def main():
         build()
     torch.cuda.set_device(0)
     if args.copy_probe_mb:
-        n = args.copy_probe_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+        nbytes = args.copy_probe_mb << 20
+        buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        buf.fill_(1.0)                                    # writes nbytes
+        sink = torch.empty(2048, dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        us = gba.gba_hbm_probe(0, buf.data_ptr(), nbytes, sink.data_ptr(), 1, stream)
         torch.cuda.synchronize()
-        print(f"[bench] copy probe: {args.copy_probe_mb} MiB device-to-device", flush=True)
-        del src, dst
+        print(f"[bench] byte-counter probe: fill of {args.copy_probe_mb} MiB, then one "
+              f"streaming read of {args.copy_probe_mb} MiB by k_hbm_probe "
+              f"({nbytes / us / 1e3:.0f} GB/s, {us:.1f} us)", flush=True)
+        del buf, sink
     prec_id, dtype_name, jac_bytes = PRECISIONS[args.precision]
     tune_db = os.path.join(ROOT, "paper_2509_26581_amd", "tune_db.txt")
     tune_db = tune_db if os.path.exists(tune_db) else None
@@ -218,7 +225,8 @@ def main():
     def make_graph(prec_id, timing):
         opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
                            timing=1 if timing else 0, accumulation=args.accumulation,
-                           tiles_per_block=args.tiles_per_block)
+                           tiles_per_block=args.tiles_per_block,
+                           deterministic=1 if args.deterministic else 0)
         return gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
                                      loss=sc.loss, delta=sc.delta, precision=prec_id,
                                      options=opts, use_torch=True)
@@ -306,7 +314,8 @@ def main():
                                f"PCG tol {sc.pcg_tol} max {sc.pcg_max_iters}",
                    "precision": args.precision, "seed": 0,
                    "accumulation": {0: "auto", 1: "lds", 2: "camera_pass"}[args.accumulation],
-                   "tiles_per_block": args.tiles_per_block or "auto"},
+                   "tiles_per_block": args.tiles_per_block or "auto",
+                   "deterministic": bool(args.deterministic)},
         "obs_per_s": round(sc.n_obs * lm_iters_s, 1),
         "pcg_iters_per_trial": round(sum(r.pcg_iters_total for r in reports) / max(total_trials, 1), 2),
         "final_cost": last.final_cost, "initial_cost": last.initial_cost,

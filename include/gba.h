@@ -298,6 +298,18 @@ gba_status gba_eval_step(gba_graph* g, double lambda, double* dcam, double* dpt,
  * changed. */
 gba_status gba_time_matvec(gba_graph* g, double lambda, int launches, double* avg_us);
 
+/* gba_hbm_probe (measurement): read the `bytes` (a positive multiple of 16)
+ * of device memory at `buf` once per launch with 16-byte loads, `launches`
+ * times back to back on `stream` (a hipStream_t, NULL: the null stream) of
+ * `device`, between two HIP events; each of the 2048 workgroups writes one
+ * 8-byte word to the device array `sink` (2048 words, caller-owned).  A
+ * launch reads exactly `bytes` and writes 16 KiB, which calibrates the HBM
+ * byte counters of a profiler; *avg_us receives the average duration of one
+ * launch.  INVALID_ARG for null pointers, a size that is not a positive
+ * multiple of 16, or launches < 1. */
+gba_status gba_hbm_probe(int device, const void* buf, size_t bytes, double* sink, int launches,
+                         void* stream, double* avg_us);
+
 const char* gba_last_error(const gba_graph* g);
 
 /* Release all device and host memory of the graph.  NULL is ignored. */

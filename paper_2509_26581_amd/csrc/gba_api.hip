@@ -668,6 +668,28 @@ gba_status gba_time_matvec(gba_graph* g, double lambda, int launches, double* av
     return GBA_OK;
 }
 
+gba_status gba_hbm_probe(int device, const void* buf, size_t bytes, double* sink, int launches,
+                         void* stream, double* avg_us) {
+    if (!buf || !sink || !avg_us || bytes == 0 || bytes % 16 != 0 || launches < 1)
+        return GBA_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return GBA_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return GBA_ERR_HIP;
+    hipError_t r = hipEventCreate(&e1);
+    if (r == hipSuccess) r = hipEventRecord(e0, s);
+    for (int k = 0; k < launches && r == hipSuccess; ++k) r = gba::launch_hbm_probe(buf, bytes / 16, sink, s);
+    if (r == hipSuccess) r = hipEventRecord(e1, s);
+    if (r == hipSuccess) r = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (r != hipSuccess) return GBA_ERR_HIP;
+    *avg_us = 1e3 * (double)ms / launches;
+    return GBA_OK;
+}
+
 const char* gba_last_error(const gba_graph* g) {
     if (!g) return "null graph handle";
     return g->err.c_str();

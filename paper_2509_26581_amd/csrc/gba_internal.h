@@ -265,5 +265,9 @@ hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s, int max_iters, dou
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_finish(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_commit(const DeviceGraph& g, hipStream_t s);
+// streaming read of n16 16-byte words (byte-counter calibration); one word
+// per workgroup into sink[kProbeBlocks]
+constexpr int kProbeBlocks = 2048;
+hipError_t launch_hbm_probe(const void* buf, size_t n16, double* sink, hipStream_t s);
 
 }  // namespace gba

@@ -1399,6 +1399,29 @@ __global__ __launch_bounds__(256) void k_pack(const PackDesc* __restrict__ desc,
     }
 }
 
+// Streaming read of n 16-byte words, four loads in flight per thread; the
+// XOR of the words keeps the loads live; one word per workgroup.
+__global__ __launch_bounds__(256) void k_hbm_probe(const uint4* __restrict__ buf, size_t n,
+                                                   double* __restrict__ sink) {
+    __shared__ uint32_t red[4];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    uint32_t x = 0;
+    for (; k + 3 * stride < n; k += 4 * stride) {
+        const uint4 a = buf[k], b = buf[k + stride], c = buf[k + 2 * stride], d = buf[k + 3 * stride];
+        x ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+    }
+    for (; k < n; k += stride) {
+        const uint4 a = buf[k];
+        x ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) x ^= (uint32_t)__shfl_xor((int)x, off, kWave);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = (double)(red[0] ^ red[1] ^ red[2] ^ red[3]);
+}
+
 template <typename T>
 __global__ void k_fill(T* p, T v, size_t n) {
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
@@ -1680,6 +1703,12 @@ hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s) {
     size_t grid = (n + 255) / 256;
     grid = grid > 4096 ? 4096 : grid;
     hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)grid), dim3(256), 0, s, p, v, n);
+    GBA_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_hbm_probe(const void* buf, size_t n16, double* sink, hipStream_t s) {
+    hipLaunchKernelGGL(k_hbm_probe, dim3(kProbeBlocks), dim3(256), 0, s, (const uint4*)buf, n16, sink);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -142,6 +142,7 @@ _SIGS = {
     "gba_eval_normal_equations": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "gba_eval_step": (ctypes.c_int, [_P, ctypes.c_double, _D, _D, ctypes.POINTER(ctypes.c_int)]),
     "gba_time_matvec": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D]),
+    "gba_hbm_probe": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_size_t, _P, ctypes.c_int, _P, _D]),
     "gba_last_error": (ctypes.c_char_p, [_P]),
     "gba_destroy": (None, [_P]),
     "gba_server_default_config": (None, [ctypes.POINTER(gba_server_config)]),
@@ -368,6 +369,18 @@ def gba_eval_step(h, lam, n_cams, n_pts):
 def gba_time_matvec(h, lam, launches):
     t = ctypes.c_double()
     _check(h, load().gba_time_matvec(h, float(lam), int(launches), ctypes.byref(t)))
+    return t.value
+
+
+def gba_hbm_probe(device, buf_ptr, nbytes, sink_ptr, launches, stream=None):
+    """Streaming read of nbytes at the device address buf_ptr, `launches`
+    times; returns the average microseconds per launch (marshalling only)."""
+    t = ctypes.c_double()
+    st = load().gba_hbm_probe(int(device), ctypes.c_void_p(buf_ptr), ctypes.c_size_t(nbytes),
+                              ctypes.c_void_p(sink_ptr), int(launches),
+                              ctypes.c_void_p(stream) if stream else None, ctypes.byref(t))
+    if st != 0:
+        raise GbaError(st, "gba_hbm_probe failed")
     return t.value
 
 
