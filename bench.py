@@ -37,6 +37,7 @@ PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf1
 # profiles/.  None until measured for the current kernel.
 MEASURED_TRAFFIC = {"fp32": 120250972, "fp64": 235340246, "bf16": 72177546}
 MATVEC_WARMUP, MATVEC_LAUNCHES = 20, 200
+SCHEDULES = {"auto": 0, "chunked": 1, "persistent": 2}
 
 
 def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes, block_bytes):
@@ -72,7 +73,7 @@ def cpu_baseline(sc):
             "trial_cost": res.log[0]["candidate_cost"]}
 
 
-def serving_measurement(gba, synth, n_req, precision, budget, slots, tune_db, seed=0):
+def serving_measurement(gba, synth, n_req, precision, budget, slots, tune_db, seed=0, schedule=0):
     """Local-BA stream on the server: (1) the same requests one at a time,
     (2) all submitted at once (saturated throughput), (3) a Poisson stream at
     0.8 x the saturated rate; latency = submission to result."""
@@ -86,7 +87,7 @@ def serving_measurement(gba, synth, n_req, precision, budget, slots, tune_db, se
 
     def server():
         return gba.Server(precision=precision, budget_bytes=budget, max_slots=slots,
-                          tune_db=tune_db)
+                          tune_db=tune_db, pcg_schedule=schedule)
 
     # (1) one at a time, on a prefix
     n_single = min(n_req, 64)
@@ -178,6 +179,8 @@ def main():
                          "counters")
     ap.add_argument("--deterministic", action="store_true",
                     help="fixed-order reductions (gba_options.deterministic)")
+    ap.add_argument("--pcg-schedule", default="auto", choices=["auto", "chunked", "persistent"],
+                    help="gba_options.pcg_schedule of the solve and the server")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path",
@@ -210,7 +213,8 @@ def main():
     tune_db = tune_db if os.path.exists(tune_db) else None
     if args.serve_only:
         out = serving_measurement(gba, synth, args.serve_requests, prec_id,
-                                  args.serve_budget_mb << 20, args.serve_slots, tune_db)
+                                  args.serve_budget_mb << 20, args.serve_slots, tune_db,
+                                  schedule=SCHEDULES[args.pcg_schedule])
         print(json.dumps({"serving": out}), flush=True)
         return
     t0 = time.perf_counter()
@@ -226,7 +230,8 @@ def main():
         opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
                            timing=1 if timing else 0, accumulation=args.accumulation,
                            tiles_per_block=args.tiles_per_block,
-                           deterministic=1 if args.deterministic else 0)
+                           deterministic=1 if args.deterministic else 0,
+                           pcg_schedule=SCHEDULES[args.pcg_schedule])
         return gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
                                      loss=sc.loss, delta=sc.delta, precision=prec_id,
                                      options=opts, use_torch=True)
@@ -315,7 +320,8 @@ def main():
                    "precision": args.precision, "seed": 0,
                    "accumulation": {0: "auto", 1: "lds", 2: "camera_pass"}[args.accumulation],
                    "tiles_per_block": args.tiles_per_block or "auto",
-                   "deterministic": bool(args.deterministic)},
+                   "deterministic": bool(args.deterministic),
+                   "pcg_schedule": args.pcg_schedule},
         "obs_per_s": round(sc.n_obs * lm_iters_s, 1),
         "pcg_iters_per_trial": round(sum(r.pcg_iters_total for r in reports) / max(total_trials, 1), 2),
         "final_cost": last.final_cost, "initial_cost": last.initial_cost,
@@ -328,7 +334,7 @@ def main():
     if not args.no_serve:
         line["serving"] = serving_measurement(gba, synth, args.serve_requests, prec_id,
                                               args.serve_budget_mb << 20, args.serve_slots,
-                                              tune_db)
+                                              tune_db, schedule=SCHEDULES[args.pcg_schedule])
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a one-trial sample ...", flush=True)
         line["cpu_baseline"] = cpu_baseline(sc)

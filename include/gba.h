@@ -148,8 +148,59 @@ typedef struct gba_options {
                                   block Jacobi the scaling cancels exactly (the
                                   blocks of the scaled system are the scaled
                                   blocks), so it changes nothing there.  (0)  */
-    int reserved[3];
+    int pcg_schedule;          /* how the PCG iterations of a damped step are
+                                  launched: GBA_PCG_CHUNKED = chunks of
+                                  iterations (three kernels each) replayed as
+                                  HIP graphs, the host checking the PCG state
+                                  between chunks; GBA_PCG_PERSISTENT = one
+                                  cooperative kernel runs every iteration of
+                                  every problem of the batch (product,
+                                  reduction and update as phases separated by
+                                  grid barriers), each problem stopping on its
+                                  own device-side decision, and the rest of the
+                                  trial follows without a host check;
+                                  GBA_PCG_AUTO (0) = persistent when the device
+                                  supports cooperative launches and a problem
+                                  has at most GBA_PERSISTENT_MAX_CAMS cameras,
+                                  chunked otherwise.  Per-phase timing
+                                  (`timing`) always launches chunks.          */
+    int jacobian;              /* GBA_JACOBIAN_ANALYTIC (0): closed-form edge
+                                  Jacobians (Sec. IV-B); GBA_JACOBIAN_AUTODIFF:
+                                  forward-mode automatic differentiation
+                                  (Sec. IV-C): the residual evaluated on dual
+                                  numbers, one seeded input per evaluation
+                                  giving one Jacobian column.  The solver's
+                                  linearisation evaluates an edge's 12 columns
+                                  in its lane; gba_eval_edges runs one lane per
+                                  (edge, column).  Same storage either way.
+                                  GBA_JACOBIAN_DYNAMIC (full solver only):
+                                  no stored Jacobian; every product and pass
+                                  that needs J recomputes it from the
+                                  parameters (Sec. IV-B dynamic Jacobians,
+                                  the minimum-memory form).                  */
+    int solver;                /* GBA_SOLVER_SCHUR (0): PCG on the reduced
+                                  camera system after eliminating the point
+                                  blocks; GBA_SOLVER_FULL: PCG on the whole
+                                  damped system H + lambda D (cameras and
+                                  points together) with block-Jacobi 9x9 and
+                                  3x3 diagonal blocks, the paper's own form
+                                  (Sec. IV-D).  FULL needs each problem's
+                                  camera vector in LDS (UNSUPPORTED above
+                                  ~2,200 cameras) and no fixed-order mode.
+                                  Read when the device graph is built.       */
 } gba_options;
+
+#define GBA_SOLVER_SCHUR 0
+#define GBA_SOLVER_FULL 1
+
+#define GBA_JACOBIAN_ANALYTIC 0
+#define GBA_JACOBIAN_AUTODIFF 1
+#define GBA_JACOBIAN_DYNAMIC 2
+
+#define GBA_PCG_AUTO 0
+#define GBA_PCG_CHUNKED 1
+#define GBA_PCG_PERSISTENT 2
+#define GBA_PERSISTENT_MAX_CAMS 256
 
 #define GBA_ACC_AUTO 0
 #define GBA_ACC_LDS 1

@@ -413,22 +413,34 @@ gba_status gba_set_options(gba_graph* g, const gba_options* o) {
         o->pcg_max_iters < 1 || !(o->pcg_tol >= 0.0) ||
         (o->precond != GBA_PRECOND_IDENTITY && o->precond != GBA_PRECOND_BLOCK_JACOBI) ||
         o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_CAMERA_PASS || o->tiles_per_block < 0 ||
-        (o->deterministic != 0 && o->deterministic != 1) || (o->jacobi_scaling != 0 && o->jacobi_scaling != 1))
+        (o->deterministic != 0 && o->deterministic != 1) || (o->jacobi_scaling != 0 && o->jacobi_scaling != 1) ||
+        o->pcg_schedule < GBA_PCG_AUTO || o->pcg_schedule > GBA_PCG_PERSISTENT ||
+        o->jacobian < GBA_JACOBIAN_ANALYTIC || o->jacobian > GBA_JACOBIAN_DYNAMIC ||
+        (o->solver != GBA_SOLVER_SCHUR && o->solver != GBA_SOLVER_FULL))
         return fail(g, GBA_ERR_INVALID_ARG, "invalid option value");
+    if (o->jacobian == GBA_JACOBIAN_DYNAMIC && o->solver != GBA_SOLVER_FULL)
+        return fail(g, GBA_ERR_INVALID_ARG, "dynamic Jacobians need the full-Hessian solver");
+    if (o->solver == GBA_SOLVER_FULL && (o->deterministic || o->accumulation == GBA_ACC_CAMERA_PASS))
+        return fail(g, GBA_ERR_INVALID_ARG,
+                    "the full-Hessian solver sums the camera rows in LDS (no fixed-order mode)");
     if (o->deterministic && o->accumulation == GBA_ACC_LDS)
         return fail(g, GBA_ERR_INVALID_ARG,
                     "deterministic sums use the camera-major pass; GBA_ACC_LDS combines LDS partials by atomics");
     if (o->accumulation != g->tune.accumulation || o->tiles_per_block != g->tune.tiles_per_block ||
-        o->deterministic != g->tune.deterministic) {
+        o->deterministic != g->tune.deterministic || o->solver != g->tune.solver ||
+        (o->jacobian == GBA_JACOBIAN_DYNAMIC) != (g->tune.dynamic != 0)) {
         // all three are part of the device graph's plan
         gba_status st = sync_params_to_host(g);
         if (st != GBA_OK) return st;
         g->tune.accumulation = o->accumulation;
         g->tune.tiles_per_block = o->tiles_per_block;
         g->tune.deterministic = o->deterministic;
+        g->tune.solver = o->solver;
+        g->tune.dynamic = o->jacobian == GBA_JACOBIAN_DYNAMIC ? 1 : 0;
         g->dirty = true;
     }
     g->opts = *o;
+    g->batch.jacobian = o->jacobian;
     return GBA_OK;
 }
 

@@ -70,6 +70,8 @@ struct Tuning {
     int pcg_sync_every = 8;     // PCG iterations launched between host checks
     int accumulation = GBA_ACC_AUTO;   // camera sums of the point passes
     int deterministic = 0;      // fixed-order reductions only (camera-major second pass)
+    int solver = 0;             // GBA_SOLVER_* (full: point vectors and partials are laid out)
+    int dynamic = 0;            // 1: dynamic Jacobians (no stored Jacobian copies)
 };
 
 struct HostDecomp {
@@ -91,6 +93,8 @@ struct UnionPlan {
     bool cam_pass = false;     // camera vector of some problem exceeds LDS (or fixed-order
                                // sums were asked for): two passes
     bool deterministic = false;
+    bool full = false;         // full-Hessian PCG
+    bool dynamic = false;      // no stored Jacobian
     std::vector<int> cam_prob, pt_prob;   // problem of each union camera / point
 };
 
@@ -156,6 +160,8 @@ struct Batch {
     // PCG iterations of the last damped step (the largest over the problems):
     // with graphs, the next step's first chunk is sized from it
     int last_pcg_iters = 0;
+    int persistent_ok = -1;         // launch_pcg_persistent usable for this layout (-1: not checked)
+    int jacobian = 0;               // GBA_JACOBIAN_* of the linearisation (options)
     // Hpp / bp of the current layout cleared once (points without edges keep 0)
     bool blocks_zeroed = false;
     // pinned host mirrors of the per-problem device arrays (capacity h_cap)

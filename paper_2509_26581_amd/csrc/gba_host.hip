@@ -349,6 +349,13 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
     // the LDS partials are combined by atomics in a varying order; the
     // camera-major pass sums every camera in a fixed order
     u.deterministic = tune.deterministic != 0;
+    u.full = tune.solver == GBA_SOLVER_FULL;
+    u.dynamic = u.full && tune.dynamic != 0;
+    if (u.full && (u.deterministic || tune.accumulation == GBA_ACC_CAMERA_PASS || !fits)) {
+        msg = "the full-Hessian PCG sums the camera side in LDS (at most " +
+              std::to_string((dev.max_lds - 1024) / 72) + " cameras per problem, no fixed-order mode)";
+        return GBA_ERR_UNSUPPORTED;
+    }
     u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits || u.deterministic;
     u.lds_pp = u.cam_pass ? 0 : (int)lds;
     // automatic: one point-pass workgroup per CU (each flushes one LDS camera
@@ -436,14 +443,16 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.pt_init, sizeof(double) * 3 * NP);
     L.add(d.dpt, sizeof(double) * 3 * NP);
     const size_t NE64 = (NE + 63) / 64 * 64;   // the stored Jacobian pads to whole 64-edge groups
-    L.add(d.jst, jsz * 24 * NE64);
+    if (!u.dynamic) L.add(d.jst, jsz * 24 * NE64);
+    else if (dptr) d.jst = nullptr;
     L.add(d.rw, tsz * 2 * NE);
     L.add(d.hpp, tsz * 6 * NP);
     L.add(d.bp, tsz * 3 * NP);
     L.add(d.hcc, tsz * 45 * NC);
     L.add(d.bc, tsz * 9 * NC);
     L.add(d.hpp_inv, tsz * kHinvStride * NP);
-    L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
+    if (!u.dynamic) L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
+    else if (dptr) d.jst_cm = nullptr;
     if (u.cam_pass) L.add(d.zbuf, tsz * 4 * NP);
     L.add(d.minv, tsz * 45 * NC);
     L.add(d.v_x, tsz * 9 * NC + 64);   // slack: 16-byte gathers (gather9); back-substitution
@@ -466,6 +475,16 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.red_partial, sizeof(double) * 4 * std::max(1, u.pp.nblk()));
     L.add(d.cost_partial, sizeof(double) * std::max(1, u.edges.nblk()));
     L.add(d.damp_partial, sizeof(double) * std::max(1, u.pts.nblk()));
+    L.add(d.gbar, 64);
+    if (u.full) {
+        for (void** v : {&d.w_x, &d.w_r, &d.w_z, &d.w_p, &d.w_q, &d.w_best})
+            L.add(*v, tsz * 3 * NP + 64);
+        L.add(d.pdot_partial, sizeof(double) * 2 * std::max(1, u.pts.nblk()));
+        L.add(d.ppq_partial, sizeof(double) * std::max(1, u.pp.nblk()));
+    } else if (dptr) {
+        d.w_x = d.w_r = d.w_z = d.w_p = d.w_q = d.w_best = nullptr;
+        d.pdot_partial = d.ppq_partial = nullptr;
+    }
     return L.off;
 }
 
@@ -489,6 +508,8 @@ void set_union_scalars(Batch& b, int precision, int loss, double delta) {
     d.block_pp = kPointPassBlock;
     d.cam_pass = u.cam_pass ? 1 : 0;
     d.deterministic = u.deterministic ? 1 : 0;
+    d.full = u.full ? 1 : 0;
+    d.dynamic = u.dynamic ? 1 : 0;
     d.lds_pp = u.lds_pp;
     d.dc_pp.nblk = u.pp.nblk();
     d.dc_red.nblk = u.red.nblk();
@@ -553,6 +574,7 @@ gba_status build_batch(const std::vector<const HostProblem*>& probs, int precisi
     b.arena_bytes = bytes;
     b.dg = DeviceGraph{};
     b.blocks_zeroed = false;
+    b.persistent_ok = -1;
     layout_union(u, precision, arena, &b.dg);
     set_union_scalars(b, precision, loss, delta);
     DeviceGraph& d = b.dg;
@@ -653,6 +675,7 @@ gba_status read_scal(Batch& b, std::string& msg) {
 
 gba_status batch_linearize(Batch& b, const RawOut* raw, Timers* tm, std::string& msg) {
     const bool timing = tm && tm->on;
+    b.dg.jacobian = b.jacobian;
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[0], b.stream));
     HIP_OR(msg, launch_linearize(b.dg, b.stream, raw, !b.blocks_zeroed));
     b.blocks_zeroed = true;
@@ -669,6 +692,8 @@ gba_status batch_linearize(Batch& b, const RawOut* raw, Timers* tm, std::string&
 
 gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune, Timers* tm,
                              std::string& msg) {
+    b.dg.min_diag = o.min_diag;   // the full system's products damp the point rows
+    b.dg.max_diag = o.max_diag;
     const DeviceGraph& d = b.dg;
     hipStream_t s = b.stream;
     const bool timing = tm && tm->on;
@@ -677,10 +702,43 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     HIP_OR(msg, launch_damp(d, s, o.min_diag, o.max_diag));
     // the block-Jacobi pass forms the reduced RHS on its way (one-pass scheme)
     const int block_jacobi = o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0;
-    if (!precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
+    // the full system needs no reduced RHS (its PCG starts from -b)
+    if (!d.full && !precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
     HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi, o.jacobi_scaling));
     if (timing) HIP_OR(msg, hipEventRecord(tm->ev[1], s));
     HIP_OR(msg, launch_pcg_init(d, s, o.pcg_tol, o.pcg_tol_relative));
+    // one cooperative launch for every PCG iteration (the trial then runs to
+    // its end without a host check), or chunks of launched iterations
+    bool persistent = false;
+    if (!timing && o.pcg_schedule != GBA_PCG_CHUNKED) {
+        if (b.persistent_ok < 0) b.persistent_ok = pcg_persistent_ok(d) ? 1 : 0;
+        if (o.pcg_schedule == GBA_PCG_PERSISTENT && !b.persistent_ok) {
+            msg = "the persistent PCG needs cooperative launches and a co-resident grid";
+            return GBA_ERR_UNSUPPORTED;
+        }
+        persistent = b.persistent_ok &&
+                     (o.pcg_schedule == GBA_PCG_PERSISTENT || b.plan.max_cams <= GBA_PERSISTENT_MAX_CAMS);
+    }
+    if (persistent) {
+        HIP_OR(msg, launch_pcg_persistent(d, s, o.min_diag, o.max_diag, o.pcg_max_iters,
+                                          o.pcg_rejection_ratio));
+        if (timing) HIP_OR(msg, hipEventRecord(tm->ev[2], s));
+        HIP_OR(msg, launch_backsub(d, s));
+        HIP_OR(msg, launch_cost(d, s, d.cam_c, d.pt_c));
+        HIP_OR(msg, launch_finish(d, s));
+        gba_status st = read_scal(b, msg);
+        if (st != GBA_OK) return st;
+        int iters = 0;
+        for (int p = 0; p < b.P; ++p) {
+            if (b.h_scal[p].barrier_err) {
+                msg = "persistent PCG: a grid barrier wait exceeded its bound";
+                return GBA_ERR_HIP;
+            }
+            iters = std::max(iters, b.h_scal[p].pcg_iters);
+        }
+        b.last_pcg_iters = iters;
+        return GBA_OK;
+    }
     const int chunk = std::max(1, std::min(kMaxPcgChunk, tune.pcg_sync_every));
     // A PCG of k steps takes k + 1 launched iterations: an iteration decides
     // at its start whether the previous step ended the PCG.  With graphs, the
@@ -788,13 +846,16 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
 
 gba_status batch_time_matvec(Batch& b, const gba_options& o, int launches, double* ms,
                              std::string& msg) {
+    b.dg.min_diag = o.min_diag;
+    b.dg.max_diag = o.max_diag;
     const DeviceGraph& d = b.dg;
     hipStream_t s = b.stream;
     HIP_OR(msg, hipMemcpyAsync(d.lam, b.h_lam, sizeof(double) * b.P, hipMemcpyHostToDevice, s));
     HIP_OR(msg, launch_damp(d, s, o.min_diag, o.max_diag));
     // the block-Jacobi pass forms the reduced RHS on its way (one-pass scheme)
     const int block_jacobi = o.precond == GBA_PRECOND_BLOCK_JACOBI ? 1 : 0;
-    if (!precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
+    // the full system needs no reduced RHS (its PCG starts from -b)
+    if (!d.full && !precond_forms_rhs(d, block_jacobi)) HIP_OR(msg, launch_rhs(d, s));
     HIP_OR(msg, launch_precond(d, s, o.min_diag, o.max_diag, block_jacobi, o.jacobi_scaling));
     // tolerance 0 and no iteration limit: the products below run for every
     // problem with work.  One iteration first, so that they take the decision

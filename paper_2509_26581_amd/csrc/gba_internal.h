@@ -49,6 +49,8 @@ struct TrialScalars {
     double x2;           // |x|^2 over free variables
     int pcg_iters;
     int pcg_reason;
+    int barrier_err;     // the persistent PCG's grid barrier gave up waiting (never expected)
+    int pad_;
 };
 
 // Per-problem PCG state.
@@ -192,6 +194,21 @@ struct DeviceGraph {
                               // jst_cm: sums per chunk)
     int deterministic;        // 1: every sum in an order that depends only on the problem
                               // (not on the batch it is packed with)
+    unsigned int* gbar;       // [4] grid barrier of the persistent PCG: arrivals, generation,
+                              // error flag, unused
+    int jacobian;             // GBA_JACOBIAN_*: closed form, forward-mode AD, dynamic (closed form)
+    // full-Hessian PCG (the solver form without point elimination)
+    int full;                 // 1: PCG on the whole damped system
+    int dynamic;              // 1: no stored Jacobian; products recompute it from the parameters
+    void* w_x;                // [np][3] point parts of the PCG vectors (vector type)
+    void* w_r;
+    void* w_z;
+    void* w_p;
+    void* w_q;
+    void* w_best;
+    double* pdot_partial;     // [2][dc_pts.nblk] point parts of r^T z, r^T r
+    double* ppq_partial;      // [dc_pp.nblk] point part of p^T q
+    double min_diag, max_diag;  // damping clamp (set by the full system's launchers)
 };
 
 // The storage types a kernel is instantiated with must be those of the
@@ -262,6 +279,15 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag,
 // the Schur product of a PCG iteration alone (its decision and the q
 // partials, no update)
 hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s, int max_iters, double reject_ratio);
+// Every PCG iteration of every problem in one cooperative launch (the
+// phases of launch_pcg_iter separated by grid barriers), after
+// launch_pcg_init.  hipErrorNotSupported when the device has no cooperative
+// launch or the grid would not be co-resident.
+constexpr int kPersistentBlock = 256;
+hipError_t launch_pcg_persistent(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
+                                 int max_iters, double reject_ratio);
+// whether launch_pcg_persistent can run this graph on the current device
+bool pcg_persistent_ok(const DeviceGraph& g);
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_finish(const DeviceGraph& g, hipStream_t s);
 hipError_t launch_commit(const DeviceGraph& g, hipStream_t s);

@@ -10,14 +10,48 @@
 // [n_cams][9]; per-point blocks are [6][n_pts] / [3][n_pts].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <mutex>
 #include <type_traits>
 
+#include "gba.h"
+#include "gba_autodiff.h"
 #include "gba_device.h"
 #include "gba_internal.h"
 
 namespace gba {
+
+// An edge's residual and Jacobian in FP64: closed form, or (kAD) forward-mode
+// automatic differentiation with the 12 columns evaluated one after another
+// in this lane (the fused passes need the whole edge in one lane).
+template <bool kAD>
+__device__ __forceinline__ void edge_eval(const double* __restrict__ cam, const double* __restrict__ X,
+                                          double ou, double ov, EdgeEval<double>& ev) {
+    if constexpr (kAD) {
+        // one dual evaluation live at a time (the loop is kept rolled); the
+        // column lands in its register slot through selects
+#pragma unroll 1
+        for (int k = 0; k < 12; ++k) {
+            double r[2], col[2];
+            bal_jacobian_column<double>(cam, X, ou, ov, k, r, col);
+#pragma unroll
+            for (int m = 0; m < 9; ++m) {
+                ev.jc[0][m] = m == k ? col[0] : ev.jc[0][m];
+                ev.jc[1][m] = m == k ? col[1] : ev.jc[1][m];
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                ev.jp[0][m] = 9 + m == k ? col[0] : ev.jp[0][m];
+                ev.jp[1][m] = 9 + m == k ? col[1] : ev.jp[1][m];
+            }
+            ev.r[0] = r[0];
+            ev.r[1] = r[1];
+        }
+    } else {
+        bal_eval<double, true>(cam, X, ou, ov, ev);
+    }
+}
 
 // ==========================================================================
 // Linearisation: per edge residual and closed-form Jacobian, robust
@@ -32,9 +66,10 @@ namespace gba {
 // more iterations.  The linear system is built from the stored Jacobian, the
 // gradient b from the FP64 one, so the LM fixed point is that of the FP64
 // problem.  kRaw: also write the FP64 evaluation in the caller's layout (the
-// edge evaluation entry point), a separate instantiation.
+// edge evaluation entry point), a separate instantiation.  kAD: the Jacobian
+// by forward-mode automatic differentiation.
 // ==========================================================================
-template <typename T, typename JS, bool kRaw>
+template <typename T, typename JS, bool kRaw, bool kAD>
 __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
     if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     const int l = lane_id();
@@ -60,12 +95,12 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
             const int j = g.e_pt[e];
             const int i = g.e_cam[e];
             EdgeEval<double> ev;
-            bal_eval<double, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
+            edge_eval<kAD>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[ne + e], ev);
             double s, rho, w;
             whiten<double, true>(ev, g.sinfo, ne, e, g.loss, g.delta, g.cam_fixed[i] != 0,
                             g.pt_fixed[j] != 0, s, rho, w);
             if (valid) {
-                jac_save<JS>(g.jst, e, ev.jc, ev.jp);
+                if (!g.dynamic) jac_save<JS>(g.jst, e, ev.jc, ev.jp);
                 rw[e] = (T)ev.r[0];
                 rw[ne + e] = (T)ev.r[1];
                 if (kRaw) {
@@ -161,6 +196,52 @@ __global__ __launch_bounds__(256) void k_cost(DeviceGraph g, const double* __res
 }
 
 // ==========================================================================
+// Forward-mode AD Jacobians in the caller's layout (the edge evaluation entry
+// point with GBA_JACOBIAN_AUTODIFF): one lane per (edge, column) pair; each
+// lane evaluates the residual once on dual numbers with its column's input
+// seeded and writes that column; the lane of column 0 also writes the
+// residual and the robust weight.
+// ==========================================================================
+__global__ __launch_bounds__(256) void k_jacobian_autodiff(DeviceGraph g, RawOut raw) {
+    const size_t total = 12 * (size_t)g.ne;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int e = (int)(t / 12), k = (int)(t % 12);
+        const int i = g.e_cam[e], j = g.e_pt[e];
+        double r[2], col[2];
+        bal_jacobian_column<double>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[g.ne + e], k, r, col);
+        const size_t q = (size_t)raw.pos[e];
+        if (k < 9) {
+            const bool cf = g.cam_fixed[i] != 0;
+            if (raw.jc) {
+                raw.jc[18 * q + k] = cf ? 0.0 : col[0];
+                raw.jc[18 * q + 9 + k] = cf ? 0.0 : col[1];
+            }
+        } else {
+            const bool pf = g.pt_fixed[j] != 0;
+            if (raw.jp) {
+                raw.jp[6 * q + (k - 9)] = pf ? 0.0 : col[0];
+                raw.jp[6 * q + 3 + (k - 9)] = pf ? 0.0 : col[1];
+            }
+        }
+        if (k == 0) {
+            if (raw.r) {
+                raw.r[2 * q] = r[0];
+                raw.r[2 * q + 1] = r[1];
+            }
+            if (raw.w) {
+                EdgeEval<double> ev;
+                ev.r[0] = r[0];
+                ev.r[1] = r[1];
+                double s, rho, w;
+                whiten<double, false>(ev, g.sinfo, g.ne, e, g.loss, g.delta, false, false, s, rho, w);
+                raw.w[q] = w;
+            }
+        }
+    }
+}
+
+// ==========================================================================
 // Point blocks: Hpp_lambda = Hpp + lambda diag(clamp(diag Hpp)) (Eq. 4-6 with
 // the clamped diagonal, lambda of the point's problem), inverted in FP64 by
 // Cholesky; fixed points get a zero inverse (no unknowns).  Also initialises the candidate points and
@@ -227,7 +308,7 @@ __device__ __forceinline__ void rhs_term(const A (&jc)[2][9], const A (&jp)[2][3
     for (int k = 0; k < 9; ++k) y[k] += jc[0][k] * u0 + jc[1][k] * u1;
 }
 
-template <typename T, typename JS, int kMode>
+template <typename T, typename JS, int kMode, bool kAD = false>
 __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
     if (!vec_type_ok<T>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     constexpr int K = 45;
@@ -264,7 +345,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
             const bool pfix = g.pt_fixed[j] != 0;
             {
                 EdgeEval<double> ev;
-                bal_eval<double, true>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
+                edge_eval<kAD>(g.cam + 9 * cam, g.pt + 3 * j, g.cm_obs[q], g.cm_obs[ne + q], ev);
                 double s, rho, w;
                 whiten<double, true>(ev, g.cm_sinfo, ne, q, g.loss, g.delta, cfix, pfix, s, rho, w);
                 // gradient from the unrounded Jacobian, before it is rounded
@@ -283,7 +364,7 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
                 }
                 // camera-major copy of the stored Jacobian (the preconditioner
                 // pass and the two-pass products read it)
-                jac_save<JS>(g.jst_cm, q, jc, jp);
+                if (!g.dynamic) jac_save<JS>(g.jst_cm, q, jc, jp);
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < 9; ++a)
@@ -415,7 +496,8 @@ __global__ __launch_bounds__(256) void k_cam_accumulate(DeviceGraph g) {
 // kPrecondRhs): also the reduced RHS r_i = -bc_i + the chunks' RHS sums.
 template <typename T, int kMode>
 __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_diag, double max_diag,
-                                                     int block_jacobi, int with_rhs, int jacobi_scaling) {
+                                                     int block_jacobi, int with_rhs, int jacobi_scaling,
+                                                     int full) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ double Ms[54];
     const int i = blockIdx.x;
@@ -464,8 +546,11 @@ __global__ __launch_bounds__(64) void k_cam_finalize(DeviceGraph g, double min_d
         const int c = k - sym9(r, r) + r;
         double h = (double)Hcc[i * 45 + k];
         if (r == c) h += lambda * fmin(fmax(h, min_diag), max_diag);
+        // the Schur form subtracts the point-elimination term; the full
+        // system's block is Hcc_lambda itself
         double s = 0.0;
-        for (int q = c0; q < c1; ++q) s += g.chunk_partial[q * 54 + k];
+        if (!full)
+            for (int q = c0; q < c1; ++q) s += g.chunk_partial[q * 54 + k];
         Ms[k] = h - s;
     }
     // In-place Gauss-Jordan inversion of the SPD block over the workgroup:
@@ -566,8 +651,13 @@ __device__ __forceinline__ double wave_sum_blocks(const double* part, int stride
 __device__ __forceinline__ PcgState pcg_decision(const DeviceGraph& g, int prob) {
     PcgState st = g.pcg[prob];
     const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
-    const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
-    const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+    double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
+    double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+    if (g.full) {   // the point parts of the full system's vectors
+        const int p0 = g.dc_pts.prob_blk[prob], p1 = g.dc_pts.prob_blk[prob + 1];
+        rz += wave_sum_blocks(g.pdot_partial, 2, 0, p0, p1);
+        rr += wave_sum_blocks(g.pdot_partial, 2, 1, p0, p1);
+    }
     if (st.done) {   // stopped earlier: nothing to do
         st.act = 0;
         return st;
@@ -619,9 +709,12 @@ __device__ __forceinline__ VT dir_entry(VT z, VT pold, int act, VT beta) {
 // ==========================================================================
 enum { kRhs = 0, kMatvec = 1, kBacksub = 2 };
 
+// One workgroup's share (decomposition block `bid`) of a point pass; the
+// kernels below run one block per workgroup, the persistent PCG kernel loops
+// over blocks.
 template <typename VT, typename JS, typename AT, int kMode>
-__global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const void* __restrict__ J,
-                                                     const VT* __restrict__ vin, AT* __restrict__ out) {
+__device__ __forceinline__ void pp_body(const DeviceGraph& g, const int bid, const void* __restrict__ J,
+                                        const VT* __restrict__ vin, AT* __restrict__ out) {
     if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     // Arithmetic in the vector type (FP32 in the mixed modes); the camera sums
     // in LDS are AT = FP64 in every mode (ds_add_f64: FP32 LDS atomics
@@ -634,7 +727,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
     __shared__ double red[16];
     __shared__ int s_act;
     int tb, te;
-    const int prob = decomp_block(g.dc_pp, blockIdx.x, tb, te);
+    const int prob = decomp_block(g.dc_pp, bid, tb, te);
     const int l = lane_id();
     const int c0 = g.prob_cam_off[prob];
     const int nc9 = 9 * (g.prob_cam_off[prob + 1] - c0);   // this problem's camera components
@@ -646,7 +739,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
         const PcgState d = pcg_decision(g, prob);
         if (threadIdx.x == 0) {
             s_act = d.act;
-            if ((int)blockIdx.x == g.dc_pp.prob_blk[prob]) g.pcg_dec[prob] = d;
+            if ((int)bid == g.dc_pp.prob_blk[prob]) g.pcg_dec[prob] = d;
         }
     }
     if (kMode != kBacksub && !cpass)
@@ -858,10 +951,10 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
         red_b = block_sum(red_b, red);
         red_s = block_sum(red_s, red);
         if (threadIdx.x == 0) {
-            g.red_partial[4 * blockIdx.x + 0] = red_m;
-            g.red_partial[4 * blockIdx.x + 1] = red_b;
-            g.red_partial[4 * blockIdx.x + 2] = red_s;
-            g.red_partial[4 * blockIdx.x + 3] = 0.0;
+            g.red_partial[4 * bid + 0] = red_m;
+            g.red_partial[4 * bid + 1] = red_b;
+            g.red_partial[4 * bid + 2] = red_s;
+            g.red_partial[4 * bid + 3] = 0.0;
         }
         return;
     }
@@ -870,8 +963,233 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
     // the flushed partial vector in the storage type of the PCG vectors: the
     // LDS sums are FP64, each partial is rounded once (FP32 in the mixed
     // modes halves the flush and the reduction's reads)
-    VT* dst = (VT*)out + g.pp_part_off[blockIdx.x];
+    VT* dst = (VT*)out + g.pp_part_off[bid];
     for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = (VT)acc_lds[k];
+}
+
+template <typename VT, typename JS, typename AT, int kMode>
+__global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, const void* __restrict__ J,
+                                                     const VT* __restrict__ vin, AT* __restrict__ out) {
+    pp_body<VT, JS, AT, kMode>(g, (int)blockIdx.x, J, vin, out);
+}
+
+// ==========================================================================
+// Full-Hessian PCG (the solver form without point elimination, Sec. IV-D):
+// the product H_lambda v over cameras and points together.  Per edge
+// u = J_c v_c + J_p v_p; the camera rows J_c^T u are privatised in LDS and
+// flushed per workgroup (k_reduce adds the damping), the point rows J_p^T u
+// are segmented wavefront sums over the point's edges, finished by the head
+// lane with the point's damping.  kMatvec multiplies z after the iteration's
+// decision and forms the point parts of q = H z + beta q_old and
+// p = z + beta p_old (and p^T q); kBacksub multiplies the step x and gives
+// the candidate points and the model terms.  kDyn: the Jacobian is
+// recomputed from the parameters in every pass (no stored copy), rounded to
+// the storage type so that it equals what would have been stored.
+// ==========================================================================
+template <typename T, typename JS, bool kDyn>
+__device__ __forceinline__ void edge_jacobian(const DeviceGraph& g, int e, int i, int j,
+                                              T (&jc)[2][9], T (&jp)[2][3]) {
+    if constexpr (kDyn) {
+        EdgeEval<double> ev;
+        bal_eval<double, true>(g.cam + 9 * i, g.pt + 3 * j, g.obs[e], g.obs[g.ne + e], ev);
+        double s, rho, w;
+        whiten<double, true>(ev, g.sinfo, g.ne, e, g.loss, g.delta, g.cam_fixed[i] != 0,
+                             g.pt_fixed[j] != 0, s, rho, w);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) jc[a][k] = (T)jac_round<JS>(ev.jc[a][k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) jp[a][k] = (T)jac_round<JS>(ev.jp[a][k]);
+        }
+    } else {
+        jac_load<JS>(g.jst, e, jc, jp);
+    }
+}
+
+template <typename VT, typename JS, bool kDyn, int kMode>
+__device__ __forceinline__ void full_pp_body(const DeviceGraph& g, const int bid) {
+    if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
+    using T = VT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* acc_lds = (double*)smem_raw;
+    __shared__ double red[16];
+    __shared__ int s_act;
+    __shared__ double s_beta;
+    int tb, te;
+    const int prob = decomp_block(g.dc_pp, bid, tb, te);
+    const int l = lane_id();
+    const int c0 = g.prob_cam_off[prob];
+    const int nc9 = 9 * (g.prob_cam_off[prob + 1] - c0);
+    // the vector multiplied: z of the PCG, or the step x
+    const T* vc = (const T*)(kMode == kMatvec ? g.v_z : g.v_x);
+    const T* vp = (const T*)(kMode == kMatvec ? g.w_z : g.w_x);
+    if (kMode == kMatvec) {
+        if (threadIdx.x < kWave) {
+            const PcgState d = pcg_decision(g, prob);
+            if (threadIdx.x == 0) {
+                s_act = d.act;
+                s_beta = d.beta;
+                if (bid == g.dc_pp.prob_blk[prob]) g.pcg_dec[prob] = d;
+            }
+        }
+        for (int k = threadIdx.x; k < nc9; k += blockDim.x) acc_lds[k] = 0;
+        __syncthreads();
+        if (!(s_act & kActStep)) return;   // this problem's PCG has stopped
+    }
+    const int act = kMode == kMatvec ? s_act : 0;
+    const T beta = kMode == kMatvec ? (T)s_beta : (T)0;
+    const T lambda = (T)fabs(g.lam[prob]);
+    const T* Hpp = (const T*)g.hpp;
+    const T* bp = (const T*)g.bp;
+    const T lo = (T)g.min_diag, hi = (T)g.max_diag;
+    const int nw = blockDim.x >> 6;
+    double red_q = 0.0, red_m = 0.0, red_b = 0.0, red_s = 0.0;
+    // the point rows of one point j (head lane): H_lambda v_p finished, then
+    // q, p and p^T q (kMatvec), or the candidate point (kBacksub)
+    auto point_rows = [&](int j, const T (&tt)[3], const T (&zp)[3]) {
+        if (kMode == kMatvec) {
+            T q[3], p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T d = fmin(fmax(Hpp[sym3(c, c) * g.np + j], lo), hi);
+                const T hz = tt[c] + lambda * d * zp[c];
+                q[c] = (act & kActRun) ? fma(beta, ((const T*)g.w_q)[3 * j + c], hz) : hz;
+                p[c] = dir_entry<T>(zp[c], ((const T*)g.w_p)[3 * j + c], act, beta);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ((T*)g.w_q)[3 * j + c] = q[c];
+                ((T*)g.w_p)[3 * j + c] = p[c];
+                red_q += (double)p[c] * (double)q[c];
+            }
+        } else {
+            const double d0 = zp[0], d1 = zp[1], d2 = zp[2];
+            g.dpt[3 * j] = d0;
+            g.dpt[3 * j + 1] = d1;
+            g.dpt[3 * j + 2] = d2;
+            g.pt_c[3 * j] = g.pt[3 * j] + d0;
+            g.pt_c[3 * j + 1] = g.pt[3 * j + 1] + d1;
+            g.pt_c[3 * j + 2] = g.pt[3 * j + 2] + d2;
+            red_b += (double)bp[j] * d0 + (double)bp[g.np + j] * d1 + (double)bp[2 * g.np + j] * d2;
+            red_s += d0 * d0 + d1 * d1 + d2 * d2;
+        }
+    };
+    for (int t = tb + (int)(threadIdx.x >> 6); t < te; t += nw) {
+        const int e0 = g.tile_off[t], e1 = g.tile_off[t + 1];
+        const int n = e1 - e0;
+        if (n <= kWave) {
+            const bool valid = l < n;
+            const int e = e0 + (valid ? l : 0);
+            const int j = g.e_pt[e];
+            const int i = g.e_cam[e];
+            const int jprev = __shfl_up(j, 1);
+            const bool st = !valid || l == 0 || jprev != j;
+            const uint64_t starts = __ballot(st);
+            int head, end;
+            segment_of(starts, l, head, end);
+            T jc[2][9], jp[2][3];
+            edge_jacobian<T, JS, kDyn>(g, e, i, j, jc, jp);
+            T zp[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) zp[k] = vp[3 * j + k];
+            T u0 = 0, u1 = 0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const T pk = vc[9 * i + k];
+                u0 += jc[0][k] * pk;
+                u1 += jc[1][k] * pk;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                u0 += jp[0][k] * zp[k];
+                u1 += jp[1][k] * zp[k];
+            }
+            if (kMode == kBacksub) {
+                if (valid) red_m += (double)u0 * (double)u0 + (double)u1 * (double)u1;
+                if (valid && head == l) {
+                    const T none[3] = {0, 0, 0};
+                    point_rows(j, none, zp);
+                }
+                continue;
+            }
+            T tt[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                tt[k] = valid ? jp[0][k] * u0 + jp[1][k] * u1 : (T)0;
+                tt[k] = segment_sum(tt[k], l, end);
+            }
+            if (valid && head == l) point_rows(j, tt, zp);
+            if (valid) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    atomicAdd(&acc_lds[9 * (i - c0) + k], (double)(jc[0][k] * u0 + jc[1][k] * u1));
+            }
+        } else {
+            // one point with more than 64 edges: chunks of a wavefront
+            const int j = g.e_pt[e0];
+            T zp[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) zp[k] = vp[3 * j + k];
+            T tt[3] = {0, 0, 0};
+            for (int ch = 0; ch < n; ch += kWave) {
+                if (ch + l < n) {
+                    const int e = e0 + ch + l;
+                    const int i = g.e_cam[e];
+                    T jc[2][9], jp[2][3];
+                    edge_jacobian<T, JS, kDyn>(g, e, i, j, jc, jp);
+                    T u0 = 0, u1 = 0;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        const T pk = vc[9 * i + k];
+                        u0 += jc[0][k] * pk;
+                        u1 += jc[1][k] * pk;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        u0 += jp[0][k] * zp[k];
+                        u1 += jp[1][k] * zp[k];
+                    }
+                    if (kMode == kBacksub) {
+                        red_m += (double)u0 * (double)u0 + (double)u1 * (double)u1;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) tt[k] += jp[0][k] * u0 + jp[1][k] * u1;
+#pragma unroll
+                        for (int k = 0; k < 9; ++k)
+                            atomicAdd(&acc_lds[9 * (i - c0) + k], (double)(jc[0][k] * u0 + jc[1][k] * u1));
+                    }
+                }
+            }
+            if (kMode == kMatvec) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) tt[k] = wave_sum(tt[k]);
+            }
+            if (l == 0) point_rows(j, tt, zp);
+        }
+    }
+    if (kMode == kBacksub) {
+        red_m = block_sum(red_m, red);
+        red_b = block_sum(red_b, red);
+        red_s = block_sum(red_s, red);
+        if (threadIdx.x == 0) {
+            g.red_partial[4 * bid + 0] = red_m;
+            g.red_partial[4 * bid + 1] = red_b;
+            g.red_partial[4 * bid + 2] = red_s;
+            g.red_partial[4 * bid + 3] = 0.0;
+        }
+        return;
+    }
+    red_q = block_sum(red_q, red);
+    if (threadIdx.x == 0) g.ppq_partial[bid] = red_q;
+    // block_sum ends with a barrier: the LDS camera rows are complete
+    VT* dst = (VT*)g.cam_partial + g.pp_part_off[bid];
+    for (int k = threadIdx.x; k < nc9; k += blockDim.x) dst[k] = (VT)acc_lds[k];
+}
+
+template <typename VT, typename JS, bool kDyn, int kMode>
+__global__ __launch_bounds__(kPointPassBlock) void k_full_point_pass(DeviceGraph g) {
+    full_pp_body<VT, JS, kDyn, kMode>(g, (int)blockIdx.x);
 }
 
 // ==========================================================================
@@ -881,19 +1199,20 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
 //            q = S p = S z + beta q (FP64); partial dots p^T q (FP64)
 // Workgroup: up to 64 components of one problem x 16 partial groups.
 // ==========================================================================
-template <typename T, int kMode>
-__global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag, double max_diag) {
+template <typename T, int kMode, int kBlock>
+__device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid, double min_diag,
+                                            double max_diag) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     // The partial vectors are read with one 16-byte load per lane: a row of
     // kRedComps components is kCols lanes, and kGroups rows are summed at once
     // (each partial vector starts on a 16-byte boundary, padded to 4 entries).
     constexpr int kCpl = 16 / (int)sizeof(T);
     constexpr int kCols = kRedComps / kCpl;
-    constexpr int kGroups = 1024 / kCols;
+    constexpr int kGroups = kBlock / kCols;
     __shared__ T red[kGroups][kRedComps];
     __shared__ double dred[16];
     int kb, ke;
-    const int prob = decomp_block(g.dc_red, blockIdx.x, kb, ke);
+    const int prob = decomp_block(g.dc_red, bid, kb, ke);
     int act = 0;
     T beta = 0;
     if (kMode == kMatvec) {
@@ -981,15 +1300,19 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
         if (kMode == kRhs) {
             ((T*)g.v_r)[k] = (T)(-bk + tot);
         } else {
-            T hp = 0;
+            T hp = 0, hd = 0;
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
                 T hc = h[c];
-                if (c == r) hc += lambda * fmin(fmax(hc, (T)min_diag), (T)max_diag);
-                hp += hc * pv[c];
+                const T dmp = c == r ? lambda * fmin(fmax(hc, (T)min_diag), (T)max_diag) : (T)0;
+                hd += dmp * pv[c];
+                hp += (hc + dmp) * pv[c];
             }
-            // S z, then q = S p = S z + beta q_old and p = z + beta p_old
-            const T sz = hp - tot;
+            // S z (Schur form: Hcc_lambda z minus the point elimination), or
+            // the full system's camera rows (the edge sums already hold
+            // J_c^T J z, so only the damping is added); then
+            // q = S p = S z + beta q_old and p = z + beta p_old
+            const T sz = g.full ? tot + hd : hp - tot;
             const T q = (act & kActRun) ? fma(beta, qold, sz) : sz;
             T zk = pv[0];
 #pragma unroll
@@ -1002,8 +1325,13 @@ __global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag,
     }
     if (kMode == kMatvec) {
         dot = block_sum(dot, dred);
-        if (threadIdx.x == 0) g.pq_partial[blockIdx.x] = dot;
+        if (threadIdx.x == 0) g.pq_partial[bid] = dot;
     }
+}
+
+template <typename T, int kMode>
+__global__ __launch_bounds__(1024) void k_reduce(DeviceGraph g, double min_diag, double max_diag) {
+    reduce_body<T, kMode, 1024>(g, (int)blockIdx.x, min_diag, max_diag);
 }
 
 // ==========================================================================
@@ -1038,7 +1366,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_start(DeviceGraph g) {
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
     const T* __restrict__ r = (const T*)g.v_r;
-    T rv = valid ? r[k] : (T)0;
+    // the reduced right-hand side, or the full system's -b_c
+    T rv = valid ? (g.full ? -((const T*)g.bc)[k] : r[k]) : (T)0;
+    if (valid && g.full) ((T*)g.v_r)[k] = rv;
     r_lds[tid] = rv;
     __syncthreads();
     double rz = 0.0, rr = 0.0;
@@ -1065,8 +1395,13 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int prob = w; prob < g.n_probs; prob += nw) {
         const int q0 = g.dc_cam.prob_blk[prob], q1 = g.dc_cam.prob_blk[prob + 1];
-        const double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
-        const double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+        double rz = wave_sum_blocks(g.dot_partial, 2, 0, q0, q1);
+        double rr = wave_sum_blocks(g.dot_partial, 2, 1, q0, q1);
+        if (g.full) {
+            const int p0 = g.dc_pts.prob_blk[prob], p1 = g.dc_pts.prob_blk[prob + 1];
+            rz += wave_sum_blocks(g.pdot_partial, 2, 0, p0, p1);
+            rr += wave_sum_blocks(g.pdot_partial, 2, 1, p0, p1);
+        }
         if (lane_id() == 0) {
             PcgState st;
             st.rz = rz;
@@ -1097,12 +1432,12 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
 // workgroup stores the state (the decision, or a breakdown when p^T q <= 0),
 // and its host mirror once the PCG stops; no other workgroup reads the state.
 template <typename T>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
+__device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ T r_lds[kPcgBlock];
     __shared__ double red[16];
     int cb, ce;
-    const int prob = decomp_block(g.dc_cam, blockIdx.x, cb, ce);
+    const int prob = decomp_block(g.dc_cam, bid, cb, ce);
     const int tid = threadIdx.x;
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
@@ -1115,7 +1450,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     if (!(act & kActState)) return;
     // the lead thread loads the decision it stores as the state now, so that
     // the store at the end waits for nothing
-    const bool lead = tid == 0 && (int)blockIdx.x == g.dc_cam.prob_blk[prob];
+    const bool lead = tid == 0 && (int)bid == g.dc_cam.prob_blk[prob];
     constexpr int kWords = (int)(sizeof(PcgState) / 8);   // copied as 8-byte words
     static_assert(sizeof(PcgState) % 8 == 0, "PcgState is a whole number of 8-byte words");
     uint2 dq[kWords];
@@ -1128,6 +1463,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     double pq = 0.0;
     for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
         pq += g.pq_partial[b];
+    if (g.full)   // the point part of p^T q, from the product's workgroups
+        for (int b = g.dc_pp.prob_blk[prob] + tid; b < g.dc_pp.prob_blk[prob + 1]; b += blockDim.x)
+            pq += g.ppq_partial[b];
     // vector arithmetic in the vector type; dots (and alpha) in FP64
     T xk = 0, pk = 0, qk = 0, rk = 0;
     T m[9];
@@ -1174,8 +1512,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
         rz = block_sum(rz, red);
         rr = block_sum(rr, red);
         if (tid == 0) {
-            g.dot_partial[2 * blockIdx.x] = rz;
-            g.dot_partial[2 * blockIdx.x + 1] = rr;
+            g.dot_partial[2 * bid] = rz;
+            g.dot_partial[2 * bid + 1] = rr;
         }
     }
     if (lead) {
@@ -1195,6 +1533,116 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
             for (int u = 0; u < kWords; ++u) ((uint2*)(g.pcg_host + prob))[u] = dq[u];
         }
     }
+}
+
+// The point part of the full system's PCG update (workgroup `bid` of the
+// point decomposition), as decided for its problem: x += alpha p,
+// r -= alpha q, z = Hpp_lambda^-1 r, partial (r^T z, r^T r) of the points;
+// the best-iterate copy / restore of the rejection ratio.  alpha from the
+// same sums, in the same order, as the camera part.
+template <typename T>
+__device__ __forceinline__ void apply_pts_body(const DeviceGraph& g, const int bid) {
+    __shared__ double red[16];
+    int pb, pe;
+    const int prob = decomp_block(g.dc_pts, bid, pb, pe);
+    const int tid = threadIdx.x;
+    const PcgState* dp = g.pcg_dec + prob;
+    const int act = dp->act;
+    const double rz_dec = dp->rz;
+    if (!(act & kActState)) return;
+    double pq = 0.0;
+    for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
+        pq += g.pq_partial[b];
+    for (int b = g.dc_pp.prob_blk[prob] + tid; b < g.dc_pp.prob_blk[prob + 1]; b += blockDim.x)
+        pq += g.ppq_partial[b];
+    pq = block_sum(pq, red);
+    T* __restrict__ x = (T*)g.w_x;
+    T* __restrict__ r = (T*)g.w_r;
+    T* __restrict__ best = (T*)g.w_best;
+    if (act & (kActKeepBest | kActRestore))
+        for (int k = 3 * pb + tid; k < 3 * pe; k += blockDim.x) {
+            if (act & kActKeepBest) best[k] = x[k];
+            if (act & kActRestore) x[k] = best[k];
+        }
+    const bool ok = pq > 0.0 && isfinite(pq);
+    if (!((act & kActStep) && ok)) return;
+    const T alpha = (T)(rz_dec / pq);
+    const T* __restrict__ p = (const T*)g.w_p;
+    const T* __restrict__ q = (const T*)g.w_q;
+    double rz = 0.0, rr = 0.0;
+    for (int j = pb + tid; j < pe; j += blockDim.x) {
+        const T* H = (const T*)g.hpp_inv + kHinvStride * j;
+        T rv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[3 * j + c] = fma(alpha, p[3 * j + c], x[3 * j + c]);
+            rv[c] = fma(-alpha, q[3 * j + c], r[3 * j + c]);
+            r[3 * j + c] = rv[c];
+        }
+        T zv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            zv[a] = H[sym3(a, 0)] * rv[0] + H[sym3(a, 1)] * rv[1] + H[sym3(a, 2)] * rv[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ((T*)g.w_z)[3 * j + c] = zv[c];
+            rz += (double)rv[c] * (double)zv[c];
+            rr += (double)rv[c] * (double)rv[c];
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (tid == 0) {
+        g.pdot_partial[2 * bid] = rz;
+        g.pdot_partial[2 * bid + 1] = rr;
+    }
+}
+
+// PCG start, the full system's point part: r = -b_p, z = Hpp_lambda^-1 r,
+// x = best = p = q = 0, partial (r^T z, r^T r) per point workgroup.
+template <typename T>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_start_pts(DeviceGraph g) {
+    if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
+    __shared__ double red[16];
+    int pb, pe;
+    decomp_block(g.dc_pts, blockIdx.x, pb, pe);
+    const T* bp = (const T*)g.bp;
+    double rz = 0.0, rr = 0.0;
+    for (int j = pb + (int)threadIdx.x; j < pe; j += blockDim.x) {
+        const T* H = (const T*)g.hpp_inv + kHinvStride * j;
+        T rv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rv[c] = -bp[c * g.np + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T zv = H[sym3(a, 0)] * rv[0] + H[sym3(a, 1)] * rv[1] + H[sym3(a, 2)] * rv[2];
+            ((T*)g.w_r)[3 * j + a] = rv[a];
+            ((T*)g.w_z)[3 * j + a] = zv;
+            ((T*)g.w_x)[3 * j + a] = 0;
+            ((T*)g.w_best)[3 * j + a] = 0;
+            ((T*)g.w_p)[3 * j + a] = 0;
+            ((T*)g.w_q)[3 * j + a] = 0;
+            rz += (double)rv[a] * (double)zv;
+            rr += (double)rv[a] * (double)rv[a];
+        }
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        g.pdot_partial[2 * blockIdx.x] = rz;
+        g.pdot_partial[2 * blockIdx.x + 1] = rr;
+    }
+}
+
+// The update of one PCG iteration: camera workgroups first, then (full
+// system) the point workgroups.
+template <typename T>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
+    const int b = (int)blockIdx.x;
+    if (b < g.dc_cam.nblk)
+        apply_body<T>(g, b);
+    else if (g.full && vec_type_ok<T>(g))
+        apply_pts_body<T>(g, b - g.dc_cam.nblk);
 }
 
 // ==========================================================================
@@ -1275,6 +1723,8 @@ __global__ __launch_bounds__(1024) void k_finish(DeviceGraph g) {
             ts->x2 = t[7] + t[4];
             ts->pcg_iters = g.pcg[prob].iters;
             ts->pcg_reason = g.pcg[prob].done;
+            ts->barrier_err = g.gbar ? (int)g.gbar[2] : 0;
+            ts->pad_ = 0;
             if (g.scal_host) g.scal_host[prob] = *ts;
         }
         __syncthreads();
@@ -1325,12 +1775,11 @@ __global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
 //   (v the product's camera vector).
 // ==========================================================================
 template <typename VT, typename JS, int kMode>
-__global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
+__device__ __forceinline__ void cam_pass_body(const DeviceGraph& g, const int chunk) {
     if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     // arithmetic and sums in the vector type (FP32 in the mixed modes)
     using T = VT;
     __shared__ T red[4][9];
-    const int chunk = blockIdx.x;
     const int cam = g.chunk_cam[chunk];
     if (kMode == kMatvec && !(g.pcg_dec[g.cam_prob[cam]].act & kActStep)) return;   // stopped
     const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
@@ -1366,6 +1815,11 @@ __global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
     }
 }
 
+template <typename VT, typename JS, int kMode>
+__global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
+    cam_pass_body<VT, JS, kMode>(g, (int)blockIdx.x);
+}
+
 // Two-pass scheme, RHS first pass: z_j = Hpp_lambda^-1 bp_j for every point.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
@@ -1379,6 +1833,104 @@ __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
         zbuf[4 * j] = H[0] * b0 + H[1] * b1 + H[2] * b2;
         zbuf[4 * j + 1] = H[1] * b0 + H[3] * b1 + H[4] * b2;
         zbuf[4 * j + 2] = H[2] * b0 + H[4] * b1 + H[5] * b2;
+    }
+}
+
+// ==========================================================================
+// Persistent PCG: one cooperative launch runs every iteration of every
+// problem of the batch.  An iteration is the three phases of the launched
+// form (the product with its decision, the partial reduction with q and p,
+// the update with the next dots; the camera-major pass of the two-pass
+// scheme as a fourth), each a loop over its decomposition blocks, separated
+// by grid barriers.  Each problem stops on its own decision as in the
+// launched form; the loop ends when every problem has stopped, after at most
+// max_iters + 1 iterations.
+// ==========================================================================
+constexpr unsigned int kBarrierSpin = 1u << 21;   // sleeps before a barrier gives up
+
+// Grid barrier over the co-resident workgroups of a cooperative launch:
+// bar[0] arrivals, bar[1] generation, bar[2] error.  The last arrival resets
+// the count and opens the next generation (release); the others wait for it
+// (acquire).  A wait longer than kBarrierSpin sleeps sets the error flag and
+// returns, and every later barrier returns at once, so the kernel ends
+// whatever happens (the host reports the flag).
+__device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int nblocks, unsigned int& gen) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int arrived =
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned int spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kBarrierSpin) {
+                    __hip_atomic_fetch_or(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+    }
+    ++gen;
+    __syncthreads();
+    __threadfence();
+}
+
+// kForm: 0 the Schur form, 1 the full system, 2 the full system with
+// dynamic Jacobians
+template <typename VT, typename JS, int kForm>
+__global__ __launch_bounds__(kPersistentBlock) void k_pcg_persistent(DeviceGraph g, double min_diag,
+                                                                    double max_diag, int max_launch) {
+    // every workgroup runs the same loop (uniform trip count), so each
+    // arrives at every barrier; the type check is uniform too
+    if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;
+    __shared__ int s_more;
+    unsigned int gen = 0;
+    const unsigned int nb = gridDim.x;
+    const bool cpass = g.cam_pass != 0;
+    for (int it = 0; it < max_launch; ++it) {
+        for (int b = blockIdx.x; b < g.dc_pp.nblk; b += gridDim.x) {
+            if constexpr (kForm == 0)
+                pp_body<VT, JS, double, kMatvec>(g, b, g.jst, (const VT*)g.v_z, (double*)g.cam_partial);
+            else
+                full_pp_body<VT, JS, kForm == 2, kMatvec>(g, b);
+            __syncthreads();   // the block's shared state is reused by the next one
+        }
+        if (cpass) {
+            grid_barrier(g.gbar, nb, gen);
+            for (int c = blockIdx.x; c < g.n_chunks; c += gridDim.x) {
+                cam_pass_body<VT, JS, kMatvec>(g, c);
+                __syncthreads();
+            }
+        }
+        grid_barrier(g.gbar, nb, gen);
+        for (int b = blockIdx.x; b < g.dc_red.nblk; b += gridDim.x) {
+            reduce_body<VT, kMatvec, kPersistentBlock>(g, b, min_diag, max_diag);
+            __syncthreads();
+        }
+        grid_barrier(g.gbar, nb, gen);
+        const int napply = g.dc_cam.nblk + (kForm != 0 ? g.dc_pts.nblk : 0);
+        for (int b = blockIdx.x; b < napply; b += gridDim.x) {
+            if (b < g.dc_cam.nblk)
+                apply_body<VT>(g, b);
+            else
+                apply_pts_body<VT>(g, b - g.dc_cam.nblk);
+            __syncthreads();
+        }
+        grid_barrier(g.gbar, nb, gen);
+        // every workgroup reads the same states after the barrier
+        if (threadIdx.x == 0) {
+            int more = 0;
+            for (int p = 0; p < g.n_probs && !more; ++p) more = g.pcg[p].done == 0;
+            if (g.gbar[2] != 0u) more = 0;
+            s_more = more;
+        }
+        __syncthreads();
+        if (!s_more) break;
     }
 }
 
@@ -1438,6 +1990,23 @@ __global__ void k_fill(T* p, T v, size_t n) {
         if (e_ != hipSuccess) return e_;   \
     } while (0)
 
+template <typename T, typename JS>
+static void linearize_kernels(const DeviceGraph& g, hipStream_t s, const RawOut& r, int grid) {
+    const bool ad = g.jacobian == GBA_JACOBIAN_AUTODIFF;
+    if (r.pos && !ad)
+        hipLaunchKernelGGL((k_linearize<T, JS, true, false>), dim3(grid), dim3(256), 0, s, g, r);
+    else if (ad)
+        hipLaunchKernelGGL((k_linearize<T, JS, false, true>), dim3(grid), dim3(256), 0, s, g, r);
+    else
+        hipLaunchKernelGGL((k_linearize<T, JS, false, false>), dim3(grid), dim3(256), 0, s, g, r);
+    if (r.pos && ad && g.ne > 0) {
+        // the caller's layout from the one-lane-per-column kernel
+        const size_t lanes = 12 * (size_t)g.ne;
+        const int ag = (int)std::min<size_t>((lanes + 255) / 256, 65535);
+        hipLaunchKernelGGL(k_jacobian_autodiff, dim3(ag), dim3(256), 0, s, g, r);
+    }
+}
+
 hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* raw, bool zero_blocks) {
     RawOut r = raw ? *raw : RawOut{nullptr, nullptr, nullptr, nullptr, nullptr};
     const int blocks = (g.n_tiles * kWave + 255) / 256;
@@ -1445,24 +2014,15 @@ hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* r
     if (g.mode == kModeFP64) {
         if (zero_blocks) hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.hpp, 0.0, (size_t)6 * g.np);
         if (zero_blocks) hipLaunchKernelGGL(k_fill<double>, dim3(256), dim3(256), 0, s, (double*)g.bp, 0.0, (size_t)3 * g.np);
-        if (r.pos)
-            hipLaunchKernelGGL((k_linearize<double, double, true>), dim3(grid), dim3(256), 0, s, g, r);
-        else
-            hipLaunchKernelGGL((k_linearize<double, double, false>), dim3(grid), dim3(256), 0, s, g, r);
+        linearize_kernels<double, double>(g, s, r, grid);
     } else if (g.mode == kModeFP32) {
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
-        if (r.pos)
-            hipLaunchKernelGGL((k_linearize<float, float, true>), dim3(grid), dim3(256), 0, s, g, r);
-        else
-            hipLaunchKernelGGL((k_linearize<float, float, false>), dim3(grid), dim3(256), 0, s, g, r);
+        linearize_kernels<float, float>(g, s, r, grid);
     } else {  // FP32 blocks, BF16 Jacobian
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.hpp, 0.f, (size_t)6 * g.np);
         if (zero_blocks) hipLaunchKernelGGL(k_fill<float>, dim3(256), dim3(256), 0, s, (float*)g.bp, 0.f, (size_t)3 * g.np);
-        if (r.pos)
-            hipLaunchKernelGGL((k_linearize<float, bf16, true>), dim3(grid), dim3(256), 0, s, g, r);
-        else
-            hipLaunchKernelGGL((k_linearize<float, bf16, false>), dim3(grid), dim3(256), 0, s, g, r);
+        linearize_kernels<float, bf16>(g, s, r, grid);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
@@ -1471,18 +2031,28 @@ hipError_t launch_linearize(const DeviceGraph& g, hipStream_t s, const RawOut* r
 hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;
     if (g.n_chunks > 0) {
-        if (g.mode == kModeFP64)
-            hipLaunchKernelGGL((k_cam_accumulate<double, double, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
-        else if (g.mode == kModeFP32)
-            hipLaunchKernelGGL((k_cam_accumulate<float, float, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
-        else
-            hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kAssemble>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        const dim3 grid(g.n_chunks), block(256);
+        if (g.jacobian == GBA_JACOBIAN_AUTODIFF) {
+            if (g.mode == kModeFP64)
+                hipLaunchKernelGGL((k_cam_accumulate<double, double, kAssemble, true>), grid, block, 0, s, g);
+            else if (g.mode == kModeFP32)
+                hipLaunchKernelGGL((k_cam_accumulate<float, float, kAssemble, true>), grid, block, 0, s, g);
+            else
+                hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kAssemble, true>), grid, block, 0, s, g);
+        } else {
+            if (g.mode == kModeFP64)
+                hipLaunchKernelGGL((k_cam_accumulate<double, double, kAssemble>), grid, block, 0, s, g);
+            else if (g.mode == kModeFP32)
+                hipLaunchKernelGGL((k_cam_accumulate<float, float, kAssemble>), grid, block, 0, s, g);
+            else
+                hipLaunchKernelGGL((k_cam_accumulate<float, bf16, kAssemble>), grid, block, 0, s, g);
+        }
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0, 0);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0);
+        hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0, 0);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1514,14 +2084,15 @@ hipError_t launch_damp(const DeviceGraph& g, hipStream_t s, double min_diag, dou
 // with the two-pass scheme (large camera sets) the separate RHS passes are
 // cheaper than the extra registers the fused form costs there.
 bool precond_forms_rhs(const DeviceGraph& g, int block_jacobi) {
-    return block_jacobi != 0 && !g.cam_pass;
+    return block_jacobi != 0 && !g.cam_pass && !g.full;
 }
 
 hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                           int block_jacobi, int jacobi_scaling) {
     if (g.nc == 0) return hipSuccess;
     const int rhs = precond_forms_rhs(g, block_jacobi) ? 1 : 0;
-    if (block_jacobi && g.n_chunks > 0) {
+    // the full system's camera blocks have no point-elimination term
+    if (block_jacobi && g.n_chunks > 0 && !g.full) {
         // the pass reads jst_cm: its storage type must be the mode's
         if (g.mode == kModeFP64) {
             if (rhs)
@@ -1542,11 +2113,51 @@ hipError_t launch_precond(const DeviceGraph& g, hipStream_t s, double min_diag, 
         GBA_CHECK_LAUNCH();
     }
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs, jacobi_scaling);
+        hipLaunchKernelGGL((k_cam_finalize<double, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs, jacobi_scaling, g.full);
     else
-        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs, jacobi_scaling);
+        hipLaunchKernelGGL((k_cam_finalize<float, kPrecond>), dim3(g.nc), dim3(64), 0, s, g, min_diag, max_diag, block_jacobi, rhs, jacobi_scaling, g.full);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+// Raise a kernel's dynamic LDS limit to `lds` bytes on the current device
+// (once per kernel and device; the attribute only grows).  Graph handles and
+// the server thread may launch concurrently, so the check and the raise are
+// one critical section.
+static void ensure_lds(const void* fn, int lds, int* set /* [kMaxDevices] */) {
+    static std::mutex mu;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    int& cur = set[dev >= 0 && dev < kMaxDevices ? dev : 0];
+    if (cur < lds) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        cur = lds;
+    }
+}
+
+template <typename VT, typename JS, bool kDyn, int kMode>
+static void full_point_pass(const DeviceGraph& g, hipStream_t s) {
+    if (g.dc_pp.nblk == 0) return;
+    const int lds = kMode == kBacksub ? 0 : g.lds_pp;
+    static int lds_set[kMaxDevices] = {};
+    if (lds > 0) ensure_lds((const void*)k_full_point_pass<VT, JS, kDyn, kMode>, lds, lds_set);
+    hipLaunchKernelGGL((k_full_point_pass<VT, JS, kDyn, kMode>), dim3(g.dc_pp.nblk), dim3(g.block_pp),
+                       lds, s, g);
+}
+
+template <int kMode>
+static void full_pass(const DeviceGraph& g, hipStream_t s) {
+    if (g.mode == kModeFP64) {
+        if (g.dynamic) full_point_pass<double, double, true, kMode>(g, s);
+        else full_point_pass<double, double, false, kMode>(g, s);
+    } else if (g.mode == kModeFP32) {
+        if (g.dynamic) full_point_pass<float, float, true, kMode>(g, s);
+        else full_point_pass<float, float, false, kMode>(g, s);
+    } else {
+        if (g.dynamic) full_point_pass<float, bf16, true, kMode>(g, s);
+        else full_point_pass<float, bf16, false, kMode>(g, s);
+    }
 }
 
 template <typename VT, typename JS, typename AT, int kMode>
@@ -1621,9 +2232,13 @@ hipError_t launch_pcg_init(const DeviceGraph& g, hipStream_t s, double tol, int 
     if (g.nc == 0) return hipSuccess;
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL(k_pcg_start<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        if (g.full && g.dc_pts.nblk > 0)
+            hipLaunchKernelGGL(k_pcg_start_pts<double>, dim3(g.dc_pts.nblk), dim3(kPcgBlock), 0, s, g);
         hipLaunchKernelGGL(k_pcg_start_finish, dim3(1), dim3(1024), 0, s, g, tol, relative);
     } else {
         hipLaunchKernelGGL(k_pcg_start<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        if (g.full && g.dc_pts.nblk > 0)
+            hipLaunchKernelGGL(k_pcg_start_pts<float>, dim3(g.dc_pts.nblk), dim3(kPcgBlock), 0, s, g);
         hipLaunchKernelGGL(k_pcg_start_finish, dim3(1), dim3(1024), 0, s, g, tol, relative);
     }
     GBA_CHECK_LAUNCH();
@@ -1637,6 +2252,11 @@ hipError_t launch_matvec(const DeviceGraph& g0, hipStream_t s, int max_iters, do
     DeviceGraph g = g0;
     g.pcg_max_iters = max_iters;
     g.pcg_ratio = ratio;
+    if (g.full) {
+        full_pass<kMatvec>(g, s);
+        GBA_CHECK_LAUNCH();
+        return hipSuccess;
+    }
     if (g.mode == kModeFP64) {
         point_pass<double, double, double, kMatvec>(g, s, g.v_z, g.cam_partial);
     } else if (g.mode == kModeFP32) {
@@ -1658,19 +2278,97 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag,
     hipError_t e = launch_matvec(g, s, max_iters, ratio);
     if (e != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
+    const int apply_blocks = g.dc_cam.nblk + (g.full ? g.dc_pts.nblk : 0);
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_apply<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_apply<double>, dim3(apply_blocks), dim3(kPcgBlock), 0, s, g);
     } else {
         hipLaunchKernelGGL((k_reduce<float, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_apply<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        hipLaunchKernelGGL(k_pcg_apply<float>, dim3(apply_blocks), dim3(kPcgBlock), 0, s, g);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
 
+template <typename VT, typename JS, int kForm>
+static hipError_t persistent_launch(const DeviceGraph& g, hipStream_t s, double min_diag,
+                                    double max_diag, int max_launch, bool check_only) {
+    const void* fn = (const void*)k_pcg_persistent<VT, JS, kForm>;
+    const int lds = g.cam_pass ? 0 : g.lds_pp;
+    int dev = 0, coop = 0, n_cu = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (e != hipSuccess) return e;
+    if (!coop || lds + 4096 > max_lds) return hipErrorNotSupported;
+    if (lds > 0) {
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistentBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorNotSupported;
+    if (check_only) return hipSuccess;
+    int want = std::max(std::max(g.dc_pp.nblk, g.dc_red.nblk),
+                        g.dc_cam.nblk + (g.full ? g.dc_pts.nblk : 0));
+    if (g.cam_pass) want = std::max(want, g.n_chunks);
+    const int grid = std::max(1, std::min(want, per_cu * n_cu));
+    // a fresh barrier: arrivals, generation and error flag cleared by a fill
+    // kernel (no memset node, so the launch may be captured)
+    hipLaunchKernelGGL(k_fill<unsigned int>, dim3(1), dim3(64), 0, s, g.gbar, 0u, (size_t)4);
+    GBA_CHECK_LAUNCH();
+    DeviceGraph ga = g;
+    void* args[] = {(void*)&ga, (void*)&min_diag, (void*)&max_diag, (void*)&max_launch};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPersistentBlock), args, (unsigned)lds, s);
+}
+
+template <bool kCheck, int kForm>
+static hipError_t persistent_form(const DeviceGraph& g, hipStream_t s, double min_diag,
+                                  double max_diag, int max_launch) {
+    if (g.mode == kModeFP64)
+        return persistent_launch<double, double, kForm>(g, s, min_diag, max_diag, max_launch, kCheck);
+    if (g.mode == kModeFP32)
+        return persistent_launch<float, float, kForm>(g, s, min_diag, max_diag, max_launch, kCheck);
+    return persistent_launch<float, bf16, kForm>(g, s, min_diag, max_diag, max_launch, kCheck);
+}
+
+template <bool kCheck>
+static hipError_t persistent_dispatch(const DeviceGraph& g, hipStream_t s, double min_diag,
+                                      double max_diag, int max_launch) {
+    if (!g.full) return persistent_form<kCheck, 0>(g, s, min_diag, max_diag, max_launch);
+    if (!g.dynamic) return persistent_form<kCheck, 1>(g, s, min_diag, max_diag, max_launch);
+    return persistent_form<kCheck, 2>(g, s, min_diag, max_diag, max_launch);
+}
+
+bool pcg_persistent_ok(const DeviceGraph& g) {
+    return persistent_dispatch<true>(g, nullptr, 0.0, 0.0, 1) == hipSuccess;
+}
+
+hipError_t launch_pcg_persistent(const DeviceGraph& g0, hipStream_t s, double min_diag, double max_diag,
+                                 int max_iters, double ratio) {
+    if (g0.nc == 0) return hipSuccess;
+    DeviceGraph g = g0;
+    g.pcg_max_iters = max_iters;
+    g.pcg_ratio = ratio;
+    // a PCG of k steps takes k + 1 iterations (the last finds the stop)
+    return persistent_dispatch<false>(g, s, min_diag, max_diag, max_iters + 1);
+}
+
 hipError_t launch_backsub(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;
+    if (g.full) {
+        // the point step is the PCG's point part: candidates and model terms
+        if (g.mode == kModeFP64)
+            hipLaunchKernelGGL(k_cam_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        else
+            hipLaunchKernelGGL(k_cam_update<float>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
+        full_pass<kBacksub>(g, s);
+        GBA_CHECK_LAUNCH();
+        return hipSuccess;
+    }
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL(k_cam_update<double>, dim3(g.dc_cam.nblk), dim3(kPcgBlock), 0, s, g);
         point_pass<double, double, double, kBacksub>(g, s, g.v_x, nullptr);

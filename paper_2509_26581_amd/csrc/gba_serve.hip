@@ -369,6 +369,8 @@ gba_status gba_server::repack() {
     if ((st = batch.ensure_mirrors(std::max<int>(cfg.max_slots, (int)order.size()), err)) != GBA_OK) return st;
     batch.dg = DeviceGraph{};
     batch.blocks_zeroed = false;
+    batch.persistent_ok = -1;
+    batch.jacobian = cfg.options.jacobian;
     layout_union(u, cfg.precision, (char*)arena + uo, &batch.dg);
     set_union_scalars(batch, cfg.precision, cfg.loss, cfg.delta);
     batch.arena = (char*)arena + uo;
@@ -610,7 +612,12 @@ gba_status gba_server_create(const gba_server_config* cfg, gba_alloc_fn alloc, g
         (o.precond != GBA_PRECOND_IDENTITY && o.precond != GBA_PRECOND_BLOCK_JACOBI) ||
         o.accumulation < GBA_ACC_AUTO || o.accumulation > GBA_ACC_CAMERA_PASS ||
         (o.deterministic != 0 && o.deterministic != 1) || (o.jacobi_scaling != 0 && o.jacobi_scaling != 1) ||
-        (o.deterministic && o.accumulation == GBA_ACC_LDS))
+        (o.deterministic && o.accumulation == GBA_ACC_LDS) ||
+        o.pcg_schedule < GBA_PCG_AUTO || o.pcg_schedule > GBA_PCG_PERSISTENT ||
+        o.jacobian < GBA_JACOBIAN_ANALYTIC || o.jacobian > GBA_JACOBIAN_DYNAMIC ||
+        (o.solver != GBA_SOLVER_SCHUR && o.solver != GBA_SOLVER_FULL) ||
+        (o.jacobian == GBA_JACOBIAN_DYNAMIC && o.solver != GBA_SOLVER_FULL) ||
+        (o.solver == GBA_SOLVER_FULL && (o.deterministic || o.accumulation == GBA_ACC_CAMERA_PASS)))
         return GBA_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return GBA_ERR_HIP;
@@ -643,6 +650,8 @@ gba_status gba_server_create(const gba_server_config* cfg, gba_alloc_fn alloc, g
     if (cfg->pcg_sync_every > 0) s->tune.pcg_sync_every = cfg->pcg_sync_every;
     s->tune.accumulation = o.accumulation;
     s->tune.deterministic = o.deterministic;
+    s->tune.solver = o.solver;
+    s->tune.dynamic = o.jacobian == GBA_JACOBIAN_DYNAMIC ? 1 : 0;
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s->ev_admit, hipEventDisableTiming) != hipSuccess) {

@@ -25,6 +25,10 @@ GBA_FP64, GBA_MIXED_FP32, GBA_MIXED_BF16 = 0, 1, 2
 GBA_LOSS_SQUARED, GBA_LOSS_HUBER = 0, 1
 GBA_PRECOND_IDENTITY, GBA_PRECOND_BLOCK_JACOBI = 0, 1
 GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_CAMERA_PASS = 0, 1, 2
+GBA_PCG_AUTO, GBA_PCG_CHUNKED, GBA_PCG_PERSISTENT = 0, 1, 2
+GBA_JACOBIAN_ANALYTIC, GBA_JACOBIAN_AUTODIFF, GBA_JACOBIAN_DYNAMIC = 0, 1, 2
+GBA_SOLVER_SCHUR, GBA_SOLVER_FULL = 0, 1
+GBA_PERSISTENT_MAX_CAMS = 256
 TERMINATION = {0: "NONE", 1: "MAX_ITERS", 2: "COST_TOL", 3: "STEP_TOL",
                4: "LAMBDA_OVERFLOW", 5: "NUMERICAL_FAILURE", 6: "NO_WORK"}
 
@@ -42,7 +46,8 @@ class gba_options(ctypes.Structure):
                 ("pcg_rejection_ratio", ctypes.c_double), ("precond", ctypes.c_int),
                 ("timing", ctypes.c_int), ("accumulation", ctypes.c_int),
                 ("tiles_per_block", ctypes.c_int), ("deterministic", ctypes.c_int),
-                ("jacobi_scaling", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("jacobi_scaling", ctypes.c_int), ("pcg_schedule", ctypes.c_int),
+                ("jacobian", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 class gba_report(ctypes.Structure):

@@ -1,0 +1,127 @@
+"""The full-Hessian PCG on the GPU (GBA_SOLVER_FULL, the paper's own solver
+form: PCG on the whole damped system, cameras and points together, with
+9x9 / 3x3 block-Jacobi preconditioning), with stored and with dynamic
+Jacobians (GBA_JACOBIAN_DYNAMIC: recomputed from the parameters in every
+product, no stored copy).  Checked against the oracle's dense full system
+(oracle/full.py): truncated iterates, the converged step, LM trajectories.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import align, ba, full, pcg
+from paper_2509_26581_amd import gba, synth
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FORMS = [("stored", gba.GBA_JACOBIAN_ANALYTIC), ("dynamic", gba.GBA_JACOBIAN_DYNAMIC)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gba.load()
+
+
+def _graph(sc, precision=gba.GBA_FP64, cam_fixed=None, **opt):
+    opt.setdefault("solver", gba.GBA_SOLVER_FULL)
+    return gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
+                                 loss=sc.loss, delta=sc.delta, precision=precision,
+                                 options=gba.options(**opt), cam_fixed=cam_fixed)
+
+
+def _oracle(sc, cam_fixed=None):
+    return ba.BAProblem(sc.n_cams, sc.n_pts, sc.cam_idx, sc.pt_idx, sc.obs, loss=sc.loss,
+                        delta=sc.delta, cam_fixed=cam_fixed)
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("form,jac", FORMS)
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_full_truncated_pcg_matches_the_oracle_iterate(k, form, jac):
+    sc = synth.make_scene("small", seed=34, n_cams=6, n_pts=200)
+    cf = np.zeros(6, bool)
+    cf[0] = True
+    prob = _oracle(sc, cam_fixed=cf)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    H, v, fc, fp = full.full_system(prob, lin, 1e-2, 1e-6, 1e32)
+    x, steps, why = pcg.pcg(H, v, full.block_jacobi_full(H, len(fc)), tol=1e-30, max_iters=k)
+    assert why == pcg.DONE_MAX_ITERS and steps == k
+    dco, dpo = full.split(x, prob, fc, fp)
+    g = _graph(sc, cam_fixed=cf, jacobian=jac, pcg_max_iters=k, pcg_tol=1e-30)
+    dc, dp, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
+    assert iters == k
+    assert _rel(dc, dco) <= 1e-8 and _rel(dp, dpo) <= 1e-8, (_rel(dc, dco), _rel(dp, dpo))
+
+
+@pytest.mark.parametrize("form,jac", FORMS)
+def test_full_converged_step_is_the_exact_step(form, jac):
+    sc = synth.make_scene("small", seed=34, n_cams=6, n_pts=200)
+    prob = _oracle(sc)
+    lin = prob.linearize((sc.cams0, sc.pts0))
+    dco, dpo = prob.solve(lin, 1e-2, 1e-6, 1e32)
+    g = _graph(sc, jacobian=jac, pcg_max_iters=3000, pcg_tol=1e-13)
+    dc, dp, iters = gba.gba_eval_step(g.h, 1e-2, sc.n_cams, sc.n_pts)
+    assert iters < 3000
+    assert _rel(dc, dco) <= 1e-7 and _rel(dp, dpo) <= 1e-7, (_rel(dc, dco), _rel(dp, dpo))
+
+
+@pytest.mark.parametrize("form,jac", FORMS)
+@pytest.mark.parametrize("schedule", [gba.GBA_PCG_CHUNKED, gba.GBA_PCG_PERSISTENT])
+def test_full_lm_trajectory_matches_the_oracle(form, jac, schedule):
+    # the PCG run to the rounding level: per-trial costs and decisions of the
+    # oracle's exact LM, and its final cost and solution
+    sc = synth.make_scene("small", seed=0)
+    g = _graph(sc, jacobian=jac, pcg_max_iters=4000, pcg_tol=1e-13, pcg_schedule=schedule)
+    rep = g.solve(sc.trials)
+    res = ba.solve(_oracle(sc), sc.cams0, sc.pts0, sc.trials)
+    for a, b in zip(g.trials(), res.log):
+        assert abs(a["cost"] - b["cost"]) <= 1e-9 * b["cost"], (a, b)
+        if abs(b["cost"] - b["candidate_cost"]) > 1e-8 * b["cost"]:
+            assert a["accepted"] == b["accepted"], (a, b)
+    assert abs(rep.final_cost - res.cost) <= 1e-9 * res.cost
+    err = align.aligned_errors(g.cameras(), g.points(), res.x[0], res.x[1])
+    assert err["rel"] <= 1e-6, err
+
+
+def test_dynamic_jacobians_store_no_jacobian():
+    sc = synth.make_scene("small", seed=3, n_cams=20, n_pts=3000)
+    a = _graph(sc, precision=gba.GBA_MIXED_FP32, jacobian=gba.GBA_JACOBIAN_ANALYTIC)
+    b = _graph(sc, precision=gba.GBA_MIXED_FP32, jacobian=gba.GBA_JACOBIAN_DYNAMIC)
+    ra, rb = a.solve(3), b.solve(3)
+    # two stored copies of 24 FP32 entries per edge (point- and camera-major)
+    saved = 2 * 24 * 4 * sc.n_obs
+    assert ra.workspace_bytes - rb.workspace_bytes >= saved, (ra.workspace_bytes, rb.workspace_bytes)
+    assert abs(ra.final_cost - rb.final_cost) <= 1e-6 * ra.final_cost
+
+
+@pytest.mark.parametrize("precision,form,jac", [(gba.GBA_MIXED_FP32, "stored", gba.GBA_JACOBIAN_ANALYTIC),
+                                                (gba.GBA_MIXED_FP32, "dynamic", gba.GBA_JACOBIAN_DYNAMIC)])
+def test_full_bal1m_final_cost(precision, form, jac):
+    gold = json.load(open(os.path.join(GOLD, "bal1m_seed0.json")))
+    sc = synth.make_scene("bal1m", seed=0)
+    g = _graph(sc, precision=precision, jacobian=jac, pcg_max_iters=sc.pcg_max_iters,
+               pcg_tol=sc.pcg_tol)
+    rep = g.solve(gold["trials"])
+    rel = abs(rep.final_cost - gold["final_cost"]) / gold["final_cost"]
+    print(f"bal1m full {form}: final cost rel {rel:.3e}, {rep.pcg_iters_total} PCG iterations")
+    assert rel <= 1e-4, rel
+
+
+def test_full_option_errors():
+    sc = synth.make_scene("small", seed=1, n_cams=4, n_pts=50)
+    g = _graph(sc, solver=gba.GBA_SOLVER_SCHUR)
+    for bad in (dict(jacobian=gba.GBA_JACOBIAN_DYNAMIC),                    # dynamic needs FULL
+                dict(solver=gba.GBA_SOLVER_FULL, deterministic=1),
+                dict(solver=2)):
+        with pytest.raises(gba.GbaError) as e:
+            gba.gba_set_options(g.h, gba.options(**bad))
+        assert e.value.status == -1
