@@ -38,6 +38,8 @@ PRECISIONS = {"fp64": (0, "f64", 8), "fp32": (1, "f32", 4), "bf16": (2, "f32+bf1
 MEASURED_TRAFFIC = {"fp32": 120250972, "fp64": 235340246, "bf16": 72177546}
 MATVEC_WARMUP, MATVEC_LAUNCHES = 20, 200
 SCHEDULES = {"auto": 0, "chunked": 1, "persistent": 2}
+SOLVERS = {"schur": 0, "full": 1}
+JACOBIANS = {"analytic": 0, "autodiff": 1, "dynamic": 2}
 
 
 def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes, block_bytes):
@@ -46,6 +48,19 @@ def matvec_algorithmic_bytes(n_obs, n_pts_active, jac_bytes, block_bytes):
     CSR offset and the 6 unique entries of the inverse point block (stored in
     the block type: FP64, or FP32 in the mixed modes)."""
     return n_obs * (24 * jac_bytes + 4) + n_pts_active * (4 + 6 * block_bytes)
+
+
+def full_product_algorithmic_bytes(n_obs, n_pts_active, n_cams, jac_bytes, vec_bytes, dynamic):
+    """Bytes of one product of the full damped system's point pass
+    (k_full_point_pass): per edge its two indices and either the stored
+    Jacobian (24 entries) or, recomputed, its observation (FP64 u, v) and
+    the parameters of its camera (9 FP64, once per camera) and point
+    (3 FP64); per point its v_p, the p and q rows (read and written) and the
+    diagonal of its block (3 + 6 + 6 + 3 vector entries); the camera partial
+    flushes are left out."""
+    per_edge = 8 + (16 if dynamic else 24 * jac_bytes)
+    per_pt = 18 * vec_bytes + (24 if dynamic else 0)
+    return n_obs * per_edge + n_pts_active * per_pt + (72 * n_cams if dynamic else 0)
 
 
 def cpu_baseline(sc):
@@ -181,6 +196,10 @@ def main():
                     help="fixed-order reductions (gba_options.deterministic)")
     ap.add_argument("--pcg-schedule", default="auto", choices=["auto", "chunked", "persistent"],
                     help="gba_options.pcg_schedule of the solve and the server")
+    ap.add_argument("--solver", default="schur", choices=["schur", "full"],
+                    help="gba_options.solver: Schur + PCG on the cameras, or PCG on the full system")
+    ap.add_argument("--jacobian", default="analytic", choices=["analytic", "autodiff", "dynamic"],
+                    help="gba_options.jacobian")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path",
@@ -223,15 +242,25 @@ def main():
     print(f"[bench] workload {args.workload}: {sc.n_cams} cams, {sc.n_pts} pts, {sc.n_obs} obs "
           f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
     n_pts_active = int(np.unique(sc.pt_idx).size)
-    alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes,
-                                         8 if args.precision == "fp64" else 4)
+    vec_bytes = 8 if args.precision == "fp64" else 4
+    if args.solver == "full":
+        alg_bytes = full_product_algorithmic_bytes(sc.n_obs, n_pts_active, sc.n_cams, jac_bytes,
+                                                   vec_bytes, args.jacobian == "dynamic")
+        product_kernel = "k_full_point_pass<kMatvec> (full-system product, point pass)"
+    else:
+        alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes, vec_bytes)
+        product_kernel = "k_point_pass<kMatvec> (fused Schur product)"
 
-    def make_graph(prec_id, timing):
-        opts = gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
+    def run_options(timing):
+        return gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
                            timing=1 if timing else 0, accumulation=args.accumulation,
                            tiles_per_block=args.tiles_per_block,
                            deterministic=1 if args.deterministic else 0,
-                           pcg_schedule=SCHEDULES[args.pcg_schedule])
+                           pcg_schedule=SCHEDULES[args.pcg_schedule],
+                           solver=SOLVERS[args.solver], jacobian=JACOBIANS[args.jacobian])
+
+    def make_graph(prec_id, timing):
+        opts = run_options(timing)
         return gba.Graph.from_arrays(sc.cams0, sc.pts0, sc.cam_idx, sc.pt_idx, sc.obs,
                                      loss=sc.loss, delta=sc.delta, precision=prec_id,
                                      options=opts, use_torch=True)
@@ -242,10 +271,11 @@ def main():
         gba.gba_time_matvec(g.h, 1e-4, MATVEC_WARMUP)
         avg_us = gba.gba_time_matvec(g.h, 1e-4, MATVEC_LAUNCHES)
         achieved = alg_bytes / (avg_us * 1e-6) / 1e9
-        traffic = MEASURED_TRAFFIC.get(args.precision) if args.workload == "bal1m" else None
+        traffic = (MEASURED_TRAFFIC.get(args.precision)
+                   if args.workload == "bal1m" and args.solver == "schur" else None)
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_point_pass<kMatvec> (fused Schur product)",
+                "kernel": product_kernel,
                 "avg_us": round(avg_us, 2), "launches": MATVEC_LAUNCHES,
                 "algorithmic_bytes": int(alg_bytes)}
 
@@ -291,9 +321,7 @@ def main():
     phases = None
     if not args.no_timing:
         gba.gba_reset(g.h)
-        gba.gba_set_options(g.h, gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
-                                             timing=1, accumulation=args.accumulation,
-                                             tiles_per_block=args.tiles_per_block))
+        gba.gba_set_options(g.h, run_options(True))
         rt = g.solve(trials)
         phases = {k: round(getattr(rt, k), 3) for k in
                   ("ms_total", "ms_linearize", "ms_precond", "ms_pcg", "ms_other", "ms_matvec")}
@@ -321,7 +349,8 @@ def main():
                    "accumulation": {0: "auto", 1: "lds", 2: "camera_pass"}[args.accumulation],
                    "tiles_per_block": args.tiles_per_block or "auto",
                    "deterministic": bool(args.deterministic),
-                   "pcg_schedule": args.pcg_schedule},
+                   "pcg_schedule": args.pcg_schedule, "solver": args.solver,
+                   "jacobian": args.jacobian},
         "obs_per_s": round(sc.n_obs * lm_iters_s, 1),
         "pcg_iters_per_trial": round(sum(r.pcg_iters_total for r in reports) / max(total_trials, 1), 2),
         "final_cost": last.final_cost, "initial_cost": last.initial_cost,

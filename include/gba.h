@@ -159,11 +159,12 @@ typedef struct gba_options {
                                   grid barriers), each problem stopping on its
                                   own device-side decision, and the rest of the
                                   trial follows without a host check;
-                                  GBA_PCG_AUTO (0) = persistent when the device
-                                  supports cooperative launches and a problem
-                                  has at most GBA_PERSISTENT_MAX_CAMS cameras,
-                                  chunked otherwise.  Per-phase timing
-                                  (`timing`) always launches chunks.          */
+                                  GBA_PCG_AUTO (0) = chunked (on MI355X each
+                                  grid barrier costs every workgroup a
+                                  device-scope L2 write-back and invalidation,
+                                  more than the graph's launch gaps it
+                                  replaces).  Per-phase timing (`timing`)
+                                  always launches chunks.                     */
     int jacobian;              /* GBA_JACOBIAN_ANALYTIC (0): closed-form edge
                                   Jacobians (Sec. IV-B); GBA_JACOBIAN_AUTODIFF:
                                   forward-mode automatic differentiation
@@ -200,7 +201,6 @@ typedef struct gba_options {
 #define GBA_PCG_AUTO 0
 #define GBA_PCG_CHUNKED 1
 #define GBA_PCG_PERSISTENT 2
-#define GBA_PERSISTENT_MAX_CAMS 256
 
 #define GBA_ACC_AUTO 0
 #define GBA_ACC_LDS 1
@@ -476,6 +476,59 @@ const char* gba_server_last_error(gba_server* s);
 /* Stop the thread (finishing resident requests is not waited for) and
  * release everything.  NULL is ignored. */
 void gba_server_destroy(gba_server* s);
+
+/* ====================================================================
+ * Visual-inertial factors (Background Eq. 8; Sec. V-C): the inertial
+ * residual between consecutive keyframes from preintegrated IMU
+ * measurements, and rectified stereo reprojection.  Evaluation calls for
+ * verification and for building solvers on them; device memory is allocated
+ * and freed inside each call, inputs and outputs are host arrays owned by the
+ * caller.
+ *
+ * Keyframe state (15 doubles): rotation world <- body as an angle-axis
+ * vector (3), position (3) and velocity (3) in the world frame, gyroscope
+ * bias (3), accelerometer bias (3).  Jacobian columns are the local
+ * perturbations R Exp(dtheta) (right), p + dp, v + dv, b + db.  Gravity is
+ * (0, 0, -9.81) in the world frame.
+ * ==================================================================== */
+
+#define GBA_VI_PRE_STRIDE 148   /* doubles per preintegrated interval */
+
+/* gba_vi_preintegrate: IMU preintegration of n intervals (on-manifold
+ * discrete propagation).  Interval f holds the samples
+ * [sample_off[f], sample_off[f+1]) of gyro / acc (3 doubles each, one every
+ * dt seconds) and is integrated with the bias estimates bias0[6f..6f+5]
+ * (b_g, then b_a).  out[148 f ..]: dt_total, dR (3x3 row-major), dv, dp, the
+ * bias Jacobians dR/db_g, dv/db_g, dv/db_a, dp/db_g, dp/db_a (3x3 each), the
+ * biases b_g0, b_a0, and the covariance (9x9 over [dphi, dv, dp]) from the
+ * continuous noise densities sigma_g, sigma_a.  INVALID_ARG for a negative
+ * n, decreasing offsets, sample_off[0] != 0, dt <= 0 or negative sigmas. */
+gba_status gba_vi_preintegrate(int device, int n, const int64_t* sample_off, const double* gyro,
+                               const double* acc, double dt, const double* bias0, double sigma_g,
+                               double sigma_a, double* out);
+
+/* gba_vi_eval_inertial: the inertial factors between keyframes f and f + 1
+ * (f = 0 .. n_kf - 2) from states[15 n_kf] and their preintegrated intervals
+ * pre[148 (n_kf - 1)]: r[9 f ..] = (r_R, r_v, r_p) with
+ *   r_R = Log((dR Exp(JRg dbg))^T Ri^T Rj),
+ *   r_v = Ri^T (vj - vi - g dt) - (dv + Jvg dbg + Jva dba),
+ *   r_p = Ri^T (pj - pi - vi dt - g dt^2 / 2) - (dp + Jpg dbg + Jpa dba),
+ * dbg, dba the bias of keyframe f minus the interval's b_g0, b_a0; J[216 f ..]
+ * the 9 x 24 Jacobian (row-major) over dtheta_i, dp_i, dv_i, dbg_i, dba_i,
+ * dtheta_j, dp_j, dv_j by forward-mode AD (one lane per column). */
+gba_status gba_vi_eval_inertial(int device, int n_kf, const double* states, const double* pre,
+                                double* r, double* J);
+
+/* gba_vi_eval_stereo: rectified stereo reprojection of n_obs observations
+ * (keyframe kf[e], point pt[e], obs[3e..] = u_l, v_l, u_r) with
+ * intr = (fx, fy, cx, cy, baseline): Xc = R^T (X - p), u_l = fx Xc_x / Xc_z
+ * + cx, v_l = fy Xc_y / Xc_z + cy, u_r = u_l - fx baseline / Xc_z;
+ * r[3e..] = prediction - obs, J[27 e ..] the 3 x 9 Jacobian over dtheta, dp
+ * of the keyframe and dX of the point (forward-mode AD).  UNKNOWN_ID for an
+ * index out of range. */
+gba_status gba_vi_eval_stereo(int device, int n_kf, const double* states, int64_t n_pts,
+                              const double* pts, int64_t n_obs, const int64_t* kf, const int64_t* pt,
+                              const double* obs, const double* intr, double* r, double* J);
 
 #ifdef __cplusplus
 }

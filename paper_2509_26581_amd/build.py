@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["gba_kernels.hip", "gba_host.hip", "gba_api.hip", "gba_serve.hip"]
+SRC = ["gba_kernels.hip", "gba_host.hip", "gba_api.hip", "gba_serve.hip", "gba_vi.hip"]
 LIB = os.path.join(HERE, "libgba.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

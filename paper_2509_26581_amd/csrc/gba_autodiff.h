@@ -45,6 +45,11 @@ template <typename T>
 __device__ __forceinline__ Dual<T> operator*(T a, Dual<T> b) { return {a * b.v, a * b.d}; }
 template <typename T>
 __device__ __forceinline__ Dual<T> operator/(Dual<T> a, T b) { return {a.v / b, a.d / b}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> operator/(T a, Dual<T> b) {
+    const T q = a / b.v;
+    return {q, -q * b.d / b.v};
+}
 
 template <typename T>
 __device__ __forceinline__ Dual<T> ad_sqrt(Dual<T> a) {
@@ -54,9 +59,20 @@ __device__ __forceinline__ Dual<T> ad_sqrt(Dual<T> a) {
 template <typename T>
 __device__ __forceinline__ Dual<T> ad_sin(Dual<T> a) { return {sin(a.v), cos(a.v) * a.d}; }
 template <typename T>
+__device__ __forceinline__ Dual<T> ad_cos(Dual<T> a) { return {cos(a.v), -sin(a.v) * a.d}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> ad_atan2(Dual<T> y, Dual<T> x) {
+    const T den = x.v * x.v + y.v * y.v;
+    return {atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / den};
+}
+template <typename T>
 __device__ __forceinline__ T ad_sqrt(T a) { return sqrt(a); }
 template <typename T>
 __device__ __forceinline__ T ad_sin(T a) { return sin(a); }
+template <typename T>
+__device__ __forceinline__ T ad_cos(T a) { return cos(a); }
+template <typename T>
+__device__ __forceinline__ T ad_atan2(T y, T x) { return atan2(y, x); }
 
 template <typename T>
 __device__ __forceinline__ T ad_value(Dual<T> a) { return a.v; }

@@ -203,6 +203,27 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
     return s;
 }
 
+// Sum over a sub-block of kSub consecutive threads (a whole number of waves
+// that divides the workgroup); every thread gets its sub-block's sum.  Every
+// thread of the workgroup calls it (it holds the workgroup's barriers).  With
+// kSub == blockDim.x it is block_sum, in the same order.  `red` holds one
+// value per wave of the workgroup (>= 16).
+template <int kSub, typename T>
+__device__ __forceinline__ T sub_sum(T v, T* red) {
+    static_assert(kSub % kWave == 0, "a sub-block is whole waves");
+    constexpr int nw = kSub / kWave;
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    const int w0 = w - w % nw;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = v;
+    __syncthreads();
+    T s = 0;
+    for (int k = 0; k < nw; ++k) s += red[w0 + k];
+    __syncthreads();
+    return s;
+}
+
 // ------------------------------------------- camera-vector gathers
 // The 9 entries of camera i of a [nc][9] vector with 16-byte loads: the
 // aligned chunks covering them (3 for FP32, 5 for FP64) and a select of the

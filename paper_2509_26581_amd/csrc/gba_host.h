@@ -146,8 +146,11 @@ struct Batch {
     UnionPlan plan;
     int P = 0;
     std::vector<std::vector<int>> pm_edge; // per problem: point-major position -> insertion index
-    // PCG chunks replayed as HIP graphs (kernel arguments captured by value;
-    // the PCG kernels read no field that changes between rebuilds)
+    // PCG chunks replayed as HIP graphs (kernel arguments captured by value).
+    // Between rebuilds the only fields that change are the parameter
+    // pointers, swapped with the candidate's on an accepted step of a single
+    // problem; only the dynamic-Jacobian product reads them, so its graphs
+    // are kept per orientation of that swap and checked against the pointers.
     bool use_graphs = false;
     bool pcg_warm = false;          // one eager chunk ran (kernel attributes set)
     hipStream_t cap_stream = nullptr;   // capture only (the null stream cannot be captured)
@@ -155,7 +158,9 @@ struct Batch {
         hipGraphExec_t exec = nullptr;
         int iters = 0, max_iters = 0;
         double min_diag = 0, max_diag = 0, ratio = 0;
-    } pcg_graph[kMaxPcgChunk + 1];      // by chunk length
+        const double* cam = nullptr;
+        const double* pt = nullptr;
+    } pcg_graph[kMaxPcgChunk + 1][2];   // by chunk length and parameter orientation
     void drop_graphs();
     // PCG iterations of the last damped step (the largest over the problems):
     // with graphs, the next step's first chunk is sized from it

@@ -42,10 +42,11 @@ void Allocator::release(void* p) const {
 }
 
 void Batch::drop_graphs() {
-    for (auto& pg : pcg_graph) {
-        if (pg.exec) (void)hipGraphExecDestroy(pg.exec);
-        pg = PcgGraph{};
-    }
+    for (auto& row : pcg_graph)
+        for (auto& pg : row) {
+            if (pg.exec) (void)hipGraphExecDestroy(pg.exec);
+            pg = PcgGraph{};
+        }
     pcg_warm = false;
 }
 
@@ -475,7 +476,7 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.red_partial, sizeof(double) * 4 * std::max(1, u.pp.nblk()));
     L.add(d.cost_partial, sizeof(double) * std::max(1, u.edges.nblk()));
     L.add(d.damp_partial, sizeof(double) * std::max(1, u.pts.nblk()));
-    L.add(d.gbar, 64);
+    L.add(d.gbar, sizeof(unsigned int) * kGbarWords);
     if (u.full) {
         for (void** v : {&d.w_x, &d.w_r, &d.w_z, &d.w_p, &d.w_q, &d.w_best})
             L.add(*v, tsz * 3 * NP + 64);
@@ -710,14 +711,13 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     // one cooperative launch for every PCG iteration (the trial then runs to
     // its end without a host check), or chunks of launched iterations
     bool persistent = false;
-    if (!timing && o.pcg_schedule != GBA_PCG_CHUNKED) {
+    if (!timing && o.pcg_schedule == GBA_PCG_PERSISTENT) {
         if (b.persistent_ok < 0) b.persistent_ok = pcg_persistent_ok(d) ? 1 : 0;
-        if (o.pcg_schedule == GBA_PCG_PERSISTENT && !b.persistent_ok) {
+        if (!b.persistent_ok) {
             msg = "the persistent PCG needs cooperative launches and a co-resident grid";
             return GBA_ERR_UNSUPPORTED;
         }
-        persistent = b.persistent_ok &&
-                     (o.pcg_schedule == GBA_PCG_PERSISTENT || b.plan.max_cams <= GBA_PERSISTENT_MAX_CAMS);
+        persistent = true;
     }
     if (persistent) {
         HIP_OR(msg, launch_pcg_persistent(d, s, o.min_diag, o.max_diag, o.pcg_max_iters,
@@ -759,10 +759,14 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
         const int c = std::min(launched == 0 ? first : rest, max_launch - launched);
         if (b.use_graphs && !timing && b.pcg_warm) {
             // replay the chunk as one graph (captured on first use, cached by length)
-            Batch::PcgGraph& pg = b.pcg_graph[c];
+            // the dynamic product reads the parameters: one graph per
+            // orientation of the current/candidate buffers
+            const int orient = d.dynamic && d.cam > d.cam_c ? 1 : 0;
+            Batch::PcgGraph& pg = b.pcg_graph[c][orient];
+            const bool moved = d.dynamic && (pg.cam != d.cam || pg.pt != d.pt);
             if (pg.exec && (pg.iters != c || pg.max_iters != o.pcg_max_iters ||
                             pg.min_diag != o.min_diag || pg.max_diag != o.max_diag ||
-                            pg.ratio != o.pcg_rejection_ratio)) {
+                            pg.ratio != o.pcg_rejection_ratio || moved)) {
                 (void)hipGraphExecDestroy(pg.exec);
                 pg = Batch::PcgGraph{};
             }
@@ -788,6 +792,8 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
                 pg.min_diag = o.min_diag;
                 pg.max_diag = o.max_diag;
                 pg.ratio = o.pcg_rejection_ratio;
+                pg.cam = d.cam;
+                pg.pt = d.pt;
             }
             HIP_OR(msg, hipGraphLaunch(pg.exec, s));
         } else {

@@ -21,6 +21,7 @@ constexpr int kChunkRuns = 1024;      // camera-major runs per workgroup chunk
 constexpr int kHinvStride = 8;        // padded row of the damped inverse point blocks
 constexpr int kCamsPerBlock = 28;     // cameras per PCG-vector workgroup (252 components)
 constexpr int kPcgBlock = 256;        // threads of the PCG-vector workgroups
+constexpr int kCamPassBlock = 256;    // threads of the camera-major pass workgroups
 constexpr int kRedComps = 64;         // components per partial-reduction workgroup
 constexpr int kMaxProblems = 4096;    // problems per device graph
 constexpr int kMaxDevices = 64;       // devices tracked for per-device kernel attributes
@@ -194,8 +195,9 @@ struct DeviceGraph {
                               // jst_cm: sums per chunk)
     int deterministic;        // 1: every sum in an order that depends only on the problem
                               // (not on the batch it is packed with)
-    unsigned int* gbar;       // [4] grid barrier of the persistent PCG: arrivals, generation,
-                              // error flag, unused
+    unsigned int* gbar;       // [kGbarWords] grid barrier of the persistent PCG: arrivals,
+                              // generation, error flag; group arrival counters
+                              // kGbarLine words apart
     int jacobian;             // GBA_JACOBIAN_*: closed form, forward-mode AD, dynamic (closed form)
     // full-Hessian PCG (the solver form without point elimination)
     int full;                 // 1: PCG on the whole damped system
@@ -283,7 +285,18 @@ hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s, int max_iters, dou
 // phases of launch_pcg_iter separated by grid barriers), after
 // launch_pcg_init.  hipErrorNotSupported when the device has no cooperative
 // launch or the grid would not be co-resident.
-constexpr int kPersistentBlock = 256;
+// Its workgroups are point-pass sized: the product and the reduction run as
+// launched, the vector updates and the camera-major pass as kSubs launched
+// workgroups side by side.
+constexpr int kPersistentBlock = kPointPassBlock;
+// The grid barrier counts arrivals in kGbarGroups groups (workgroup index
+// modulo kGbarGroups), each counter on its own 128-byte line, then the groups
+// at the top: no one address takes every workgroup's atomic.
+constexpr int kGbarGroups = 8;
+constexpr int kGbarLine = 32;                                  // words per 128-byte line
+constexpr int kGbarWords = kGbarLine * (1 + kGbarGroups);
+static_assert(kPersistentBlock % kPcgBlock == 0 && kPersistentBlock % kCamPassBlock == 0,
+              "persistent workgroups hold whole vector and camera-pass workgroups");
 hipError_t launch_pcg_persistent(const DeviceGraph& g, hipStream_t s, double min_diag, double max_diag,
                                  int max_iters, double reject_ratio);
 // whether launch_pcg_persistent can run this graph on the current device

@@ -1431,26 +1431,33 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
 // the best-iterate copy / restore of the rejection ratio.  The problem's first
 // workgroup stores the state (the decision, or a breakdown when p^T q <= 0),
 // and its host mirror once the PCG stops; no other workgroup reads the state.
-template <typename T>
-__device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid) {
+// kSubs > 1: a workgroup of kSubs x kPcgBlock threads runs camera workgroups
+// bid0 .. bid0 + kSubs - 1 side by side (the persistent kernel), each with
+// the arithmetic of a launched one; every thread then passes every barrier.
+template <typename T, int kSubs>
+__device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
-    __shared__ T r_lds[kPcgBlock];
+    __shared__ T r_lds[kSubs * kPcgBlock];
     __shared__ double red[16];
-    int cb, ce;
-    const int prob = decomp_block(g.dc_cam, bid, cb, ce);
-    const int tid = threadIdx.x;
+    const int sub = kSubs > 1 ? (int)threadIdx.x / kPcgBlock : 0;
+    const int tid = (int)threadIdx.x - sub * kPcgBlock;
+    const int bid = bid0 + sub;
+    int cb = 0, ce = 0, prob = 0;
+    const bool blk = kSubs == 1 || bid < g.dc_cam.nblk;
+    if (blk) prob = decomp_block(g.dc_cam, bid, cb, ce);
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
     // T PCG stopped before this iteration (the rest of a replayed chunk of
     // iterations) exits after one load.  Otherwise every load of the step is
     // issued before the next wait (the dot, alpha).
     const PcgState* dp = g.pcg_dec + prob;
-    const int act = dp->act;
-    const double rz_dec = dp->rz;
-    if (!(act & kActState)) return;
+    const int act = blk ? dp->act : 0;
+    const double rz_dec = blk ? dp->rz : 0.0;
+    const bool live = (act & kActState) != 0;
+    if (kSubs == 1 && !live) return;
     // the lead thread loads the decision it stores as the state now, so that
     // the store at the end waits for nothing
-    const bool lead = tid == 0 && (int)bid == g.dc_cam.prob_blk[prob];
+    const bool lead = live && tid == 0 && bid == g.dc_cam.prob_blk[prob];
     constexpr int kWords = (int)(sizeof(PcgState) / 8);   // copied as 8-byte words
     static_assert(sizeof(PcgState) % 8 == 0, "PcgState is a whole number of 8-byte words");
     uint2 dq[kWords];
@@ -1461,16 +1468,18 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid) 
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ r = (T*)g.v_r;
     double pq = 0.0;
-    for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
-        pq += g.pq_partial[b];
-    if (g.full)   // the point part of p^T q, from the product's workgroups
-        for (int b = g.dc_pp.prob_blk[prob] + tid; b < g.dc_pp.prob_blk[prob + 1]; b += blockDim.x)
-            pq += g.ppq_partial[b];
+    if (live) {
+        for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += kPcgBlock)
+            pq += g.pq_partial[b];
+        if (g.full)   // the point part of p^T q, from the product's workgroups
+            for (int b = g.dc_pp.prob_blk[prob] + tid; b < g.dc_pp.prob_blk[prob + 1]; b += kPcgBlock)
+                pq += g.ppq_partial[b];
+    }
     // vector arithmetic in the vector type; dots (and alpha) in FP64
     T xk = 0, pk = 0, qk = 0, rk = 0;
     T m[9];
     const int i = k / 9, a = k % 9;
-    if (valid) {
+    if (live && valid) {
         xk = x[k];
         pk = ((const T*)g.v_p)[k];
         qk = ((const T*)g.v_q)[k];
@@ -1481,26 +1490,27 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid) 
     }
     // every workgroup of the problem sums the same partials in the same
     // order, so all of them take the same branch
-    pq = block_sum(pq, red);
-    if (act & (kActKeepBest | kActRestore)) {   // rejection ratio
+    pq = sub_sum<kPcgBlock>(pq, red);
+    if (live && (act & (kActKeepBest | kActRestore))) {   // rejection ratio
         T* __restrict__ best = (T*)g.v_best;
         if (valid && (act & kActKeepBest)) best[k] = (T)xk;
         if (valid && (act & kActRestore)) x[k] = best[k];
     }
     const bool ok = pq > 0.0 && isfinite(pq);
-    if ((act & kActStep) && ok) {
-        const T alpha = (T)(rz_dec / pq);
+    const bool step = live && (act & kActStep) && ok;
+    if (kSubs > 1 || step) {
+        const T alpha = step ? (T)(rz_dec / pq) : (T)0;
         T rv = 0;
-        if (valid) {
+        if (step && valid) {
             x[k] = (T)fma(alpha, pk, xk);
             rv = (T)fma(-alpha, qk, rk);
             r[k] = rv;
         }
-        r_lds[tid] = rv;
+        r_lds[sub * kPcgBlock + tid] = rv;
         __syncthreads();
         double rz = 0.0, rr = 0.0;
-        if (valid) {
-            const int base = tid - a;
+        if (step && valid) {
+            const int base = sub * kPcgBlock + tid - a;
             T sz = 0;
 #pragma unroll
             for (int b = 0; b < 9; ++b) sz += (T)m[b] * (T)r_lds[base + b];
@@ -1509,9 +1519,9 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid) 
             rz = (double)rv * (double)zv;
             rr = (double)rv * (double)rv;
         }
-        rz = block_sum(rz, red);
-        rr = block_sum(rr, red);
-        if (tid == 0) {
+        rz = sub_sum<kPcgBlock>(rz, red);
+        rr = sub_sum<kPcgBlock>(rr, red);
+        if (step && tid == 0) {
             g.dot_partial[2 * bid] = rz;
             g.dot_partial[2 * bid + 1] = rr;
         }
@@ -1539,38 +1549,45 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid) 
 // point decomposition), as decided for its problem: x += alpha p,
 // r -= alpha q, z = Hpp_lambda^-1 r, partial (r^T z, r^T r) of the points;
 // the best-iterate copy / restore of the rejection ratio.  alpha from the
-// same sums, in the same order, as the camera part.
-template <typename T>
-__device__ __forceinline__ void apply_pts_body(const DeviceGraph& g, const int bid) {
+// same sums, in the same order, as the camera part.  kSubs as in apply_body.
+template <typename T, int kSubs>
+__device__ __forceinline__ void apply_pts_body(const DeviceGraph& g, const int bid0) {
     __shared__ double red[16];
-    int pb, pe;
-    const int prob = decomp_block(g.dc_pts, bid, pb, pe);
-    const int tid = threadIdx.x;
+    const int sub = kSubs > 1 ? (int)threadIdx.x / kPcgBlock : 0;
+    const int tid = (int)threadIdx.x - sub * kPcgBlock;
+    const int bid = bid0 + sub;
+    int pb = 0, pe = 0, prob = 0;
+    const bool blk = kSubs == 1 || bid < g.dc_pts.nblk;
+    if (blk) prob = decomp_block(g.dc_pts, bid, pb, pe);
     const PcgState* dp = g.pcg_dec + prob;
-    const int act = dp->act;
-    const double rz_dec = dp->rz;
-    if (!(act & kActState)) return;
+    const int act = blk ? dp->act : 0;
+    const double rz_dec = blk ? dp->rz : 0.0;
+    const bool live = (act & kActState) != 0;
+    if (kSubs == 1 && !live) return;
     double pq = 0.0;
-    for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += blockDim.x)
-        pq += g.pq_partial[b];
-    for (int b = g.dc_pp.prob_blk[prob] + tid; b < g.dc_pp.prob_blk[prob + 1]; b += blockDim.x)
-        pq += g.ppq_partial[b];
-    pq = block_sum(pq, red);
+    if (live) {
+        for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += kPcgBlock)
+            pq += g.pq_partial[b];
+        for (int b = g.dc_pp.prob_blk[prob] + tid; b < g.dc_pp.prob_blk[prob + 1]; b += kPcgBlock)
+            pq += g.ppq_partial[b];
+    }
+    pq = sub_sum<kPcgBlock>(pq, red);
     T* __restrict__ x = (T*)g.w_x;
     T* __restrict__ r = (T*)g.w_r;
     T* __restrict__ best = (T*)g.w_best;
-    if (act & (kActKeepBest | kActRestore))
-        for (int k = 3 * pb + tid; k < 3 * pe; k += blockDim.x) {
+    if (live && (act & (kActKeepBest | kActRestore)))
+        for (int k = 3 * pb + tid; k < 3 * pe; k += kPcgBlock) {
             if (act & kActKeepBest) best[k] = x[k];
             if (act & kActRestore) x[k] = best[k];
         }
     const bool ok = pq > 0.0 && isfinite(pq);
-    if (!((act & kActStep) && ok)) return;
-    const T alpha = (T)(rz_dec / pq);
+    const bool step = live && (act & kActStep) && ok;
+    if (kSubs == 1 && !step) return;
+    const T alpha = step ? (T)(rz_dec / pq) : (T)0;
     const T* __restrict__ p = (const T*)g.w_p;
     const T* __restrict__ q = (const T*)g.w_q;
     double rz = 0.0, rr = 0.0;
-    for (int j = pb + tid; j < pe; j += blockDim.x) {
+    for (int j = pb + tid; step && j < pe; j += kPcgBlock) {
         const T* H = (const T*)g.hpp_inv + kHinvStride * j;
         T rv[3];
 #pragma unroll
@@ -1590,9 +1607,9 @@ __device__ __forceinline__ void apply_pts_body(const DeviceGraph& g, const int b
             rr += (double)rv[c] * (double)rv[c];
         }
     }
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
-    if (tid == 0) {
+    rz = sub_sum<kPcgBlock>(rz, red);
+    rr = sub_sum<kPcgBlock>(rr, red);
+    if (step && tid == 0) {
         g.pdot_partial[2 * bid] = rz;
         g.pdot_partial[2 * bid + 1] = rr;
     }
@@ -1640,9 +1657,9 @@ template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     const int b = (int)blockIdx.x;
     if (b < g.dc_cam.nblk)
-        apply_body<T>(g, b);
+        apply_body<T, 1>(g, b);
     else if (g.full && vec_type_ok<T>(g))
-        apply_pts_body<T>(g, b - g.dc_cam.nblk);
+        apply_pts_body<T, 1>(g, b - g.dc_cam.nblk);
 }
 
 // ==========================================================================
@@ -1774,20 +1791,28 @@ __global__ __launch_bounds__(256) void k_commit(DeviceGraph g) {
 //   kRhs: z_j = Hpp_lambda^-1 bp_j;  kMatvec: z_j = Hpp_lambda^-1 sum J_p^T J_c v
 //   (v the product's camera vector).
 // ==========================================================================
-template <typename VT, typename JS, int kMode>
-__device__ __forceinline__ void cam_pass_body(const DeviceGraph& g, const int chunk) {
+template <typename VT, typename JS, int kMode, int kSubs>
+__device__ __forceinline__ void cam_pass_body(const DeviceGraph& g, const int chunk0) {
     if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
     // arithmetic and sums in the vector type (FP32 in the mixed modes)
     using T = VT;
-    __shared__ T red[4][9];
-    const int cam = g.chunk_cam[chunk];
-    if (kMode == kMatvec && !(g.pcg_dec[g.cam_prob[cam]].act & kActStep)) return;   // stopped
-    const int rb = g.chunk_run_off[chunk], re = g.chunk_run_off[chunk + 1];
+    constexpr int kWaves = kCamPassBlock / kWave;
+    __shared__ T red[kSubs * kWaves][9];
+    // kSubs > 1: chunks chunk0 .. chunk0 + kSubs - 1 side by side in one
+    // workgroup of kSubs x kCamPassBlock threads (the persistent kernel)
+    const int sub = kSubs > 1 ? (int)threadIdx.x / kCamPassBlock : 0;
+    const int tid = (int)threadIdx.x - sub * kCamPassBlock;
+    const int chunk = chunk0 + sub;
+    bool live = kSubs == 1 || chunk < g.n_chunks;
+    const int cam = live ? g.chunk_cam[chunk] : 0;
+    if (kMode == kMatvec && live && !(g.pcg_dec[g.cam_prob[cam]].act & kActStep)) live = false;   // stopped
+    if (kSubs == 1 && !live) return;
+    const int rb = live ? g.chunk_run_off[chunk] : 0, re = live ? g.chunk_run_off[chunk + 1] : 0;
     const T* __restrict__ zbuf = (const T*)g.zbuf;
     T y[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) y[k] = (T)0;
-    for (int run = rb + (int)threadIdx.x; run < re; run += blockDim.x) {
+    for (int run = rb + tid; run < re; run += kCamPassBlock) {
         const int q0 = g.cm_run_off[run], q1 = g.cm_run_off[run + 1];
         const int j = g.cm_pt[q0];
         const T z0 = zbuf[4 * j], z1 = zbuf[4 * j + 1], z2 = zbuf[4 * j + 2];
@@ -1807,17 +1832,16 @@ __device__ __forceinline__ void cam_pass_body(const DeviceGraph& g, const int ch
         if (lane_id() == 0) red[w][k] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 9) {
-        const int nw = blockDim.x >> 6;
+    if (live && tid < 9) {
         T s = 0;
-        for (int q = 0; q < nw; ++q) s += red[q][threadIdx.x];
-        g.chunk_partial[54 * chunk + threadIdx.x] = (double)s;
+        for (int q = 0; q < kWaves; ++q) s += red[sub * kWaves + q][tid];
+        g.chunk_partial[54 * chunk + tid] = (double)s;
     }
 }
 
 template <typename VT, typename JS, int kMode>
-__global__ __launch_bounds__(256) void k_cam_pass(DeviceGraph g) {
-    cam_pass_body<VT, JS, kMode>(g, (int)blockIdx.x);
+__global__ __launch_bounds__(kCamPassBlock) void k_cam_pass(DeviceGraph g) {
+    cam_pass_body<VT, JS, kMode, 1>(g, (int)blockIdx.x);
 }
 
 // Two-pass scheme, RHS first pass: z_j = Hpp_lambda^-1 bp_j for every point.
@@ -1849,23 +1873,46 @@ __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
 constexpr unsigned int kBarrierSpin = 1u << 21;   // sleeps before a barrier gives up
 
 // Grid barrier over the co-resident workgroups of a cooperative launch:
-// bar[0] arrivals, bar[1] generation, bar[2] error.  The last arrival resets
-// the count and opens the next generation (release); the others wait for it
-// (acquire).  A wait longer than kBarrierSpin sleeps sets the error flag and
-// returns, and every later barrier returns at once, so the kernel ends
-// whatever happens (the host reports the flag).
+// bar[0] group arrivals, bar[1] generation, bar[2] error, and the arrival
+// counter of workgroup group k (index modulo kGbarGroups) at
+// bar[kGbarLine * (1 + k)].  One thread per workgroup takes part.  Its
+// arrival at its group is a release at device scope (the workgroup's writes,
+// ordered before it by the workgroup barrier, reach the point of coherence
+// of the eight XCDs); a group's last arrival acquires them and arrives at the
+// top (release), and the top's last arrival resets the count and opens the
+// next generation (release).  The others poll the generation with relaxed
+// loads, which read the coherent copy and leave the caches alone, and
+// acquire once after the wait.  So each workgroup pays one L2 write-back and
+// one or two invalidations per barrier (an acquiring poll would invalidate
+// its XCD's L2 on every probe while other workgroups still compute), and no
+// counter takes more than about nblocks / kGbarGroups atomics.  The other
+// threads are ordered after the acquire by the closing workgroup barrier.  A
+// wait longer than kBarrierSpin sleeps sets the error flag and returns, and
+// every later barrier returns at once, so the kernel ends whatever happens
+// (the host reports the flag).
 __device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int nblocks, unsigned int& gen) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int arrived =
-            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        constexpr unsigned int G = kGbarGroups;
+        const unsigned int grp = blockIdx.x % G;
+        const unsigned int groups = nblocks < G ? nblocks : G;
+        const unsigned int members = (nblocks - grp + G - 1) / G;
+        unsigned int* cnt = bar + kGbarLine * (1 + grp);
+        bool open = false;
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the group's writes
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
+                groups - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every group's writes
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                open = true;
+            }
+        }
+        if (!open) {
             unsigned int spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > kBarrierSpin) {
@@ -1873,11 +1920,11 @@ __device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int nbl
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the generation's writes
         }
     }
     ++gen;
     __syncthreads();
-    __threadfence();
 }
 
 // kForm: 0 the Schur form, 1 the full system, 2 the full system with
@@ -1888,6 +1935,9 @@ __global__ __launch_bounds__(kPersistentBlock) void k_pcg_persistent(DeviceGraph
     // every workgroup runs the same loop (uniform trip count), so each
     // arrives at every barrier; the type check is uniform too
     if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;
+    static_assert(kPersistentBlock == kPointPassBlock, "the product runs as launched");
+    constexpr int kSubsV = kPersistentBlock / kPcgBlock;        // vector workgroups side by side
+    constexpr int kSubsC = kPersistentBlock / kCamPassBlock;    // camera-pass workgroups
     __shared__ int s_more;
     unsigned int gen = 0;
     const unsigned int nb = gridDim.x;
@@ -1902,8 +1952,8 @@ __global__ __launch_bounds__(kPersistentBlock) void k_pcg_persistent(DeviceGraph
         }
         if (cpass) {
             grid_barrier(g.gbar, nb, gen);
-            for (int c = blockIdx.x; c < g.n_chunks; c += gridDim.x) {
-                cam_pass_body<VT, JS, kMatvec>(g, c);
+            for (int c = blockIdx.x * kSubsC; c < g.n_chunks; c += gridDim.x * kSubsC) {
+                cam_pass_body<VT, JS, kMatvec, kSubsC>(g, c);
                 __syncthreads();
             }
         }
@@ -1913,13 +1963,17 @@ __global__ __launch_bounds__(kPersistentBlock) void k_pcg_persistent(DeviceGraph
             __syncthreads();
         }
         grid_barrier(g.gbar, nb, gen);
-        const int napply = g.dc_cam.nblk + (kForm != 0 ? g.dc_pts.nblk : 0);
-        for (int b = blockIdx.x; b < napply; b += gridDim.x) {
-            if (b < g.dc_cam.nblk)
-                apply_body<VT>(g, b);
-            else
-                apply_pts_body<VT>(g, b - g.dc_cam.nblk);
+        // the camera and the point updates are independent (separate vectors
+        // and partials), one after the other without a barrier
+        for (int b = blockIdx.x * kSubsV; b < g.dc_cam.nblk; b += gridDim.x * kSubsV) {
+            apply_body<VT, kSubsV>(g, b);
             __syncthreads();
+        }
+        if constexpr (kForm != 0) {
+            for (int b = blockIdx.x * kSubsV; b < g.dc_pts.nblk; b += gridDim.x * kSubsV) {
+                apply_pts_body<VT, kSubsV>(g, b);
+                __syncthreads();
+            }
         }
         grid_barrier(g.gbar, nb, gen);
         // every workgroup reads the same states after the barrier
@@ -2191,11 +2245,11 @@ template <int kMode>
 static void cam_pass(const DeviceGraph& g, hipStream_t s) {
     if (g.n_chunks == 0) return;
     if (g.mode == kModeFP64)
-        hipLaunchKernelGGL((k_cam_pass<double, double, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_cam_pass<double, double, kMode>), dim3(g.n_chunks), dim3(kCamPassBlock), 0, s, g);
     else if (g.mode == kModeFP32)
-        hipLaunchKernelGGL((k_cam_pass<float, float, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_cam_pass<float, float, kMode>), dim3(g.n_chunks), dim3(kCamPassBlock), 0, s, g);
     else
-        hipLaunchKernelGGL((k_cam_pass<float, bf16, kMode>), dim3(g.n_chunks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_cam_pass<float, bf16, kMode>), dim3(g.n_chunks), dim3(kCamPassBlock), 0, s, g);
 }
 
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
@@ -2312,13 +2366,17 @@ static hipError_t persistent_launch(const DeviceGraph& g, hipStream_t s, double 
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorNotSupported;
     if (check_only) return hipSuccess;
+    // one workgroup per product and reduction workgroup, or per kSubs vector
+    // (camera-pass) workgroups, up to a co-resident grid
+    constexpr int kSubsV = kPersistentBlock / kPcgBlock, kSubsC = kPersistentBlock / kCamPassBlock;
     int want = std::max(std::max(g.dc_pp.nblk, g.dc_red.nblk),
-                        g.dc_cam.nblk + (g.full ? g.dc_pts.nblk : 0));
-    if (g.cam_pass) want = std::max(want, g.n_chunks);
+                        std::max((g.dc_cam.nblk + kSubsV - 1) / kSubsV,
+                                 g.full ? (g.dc_pts.nblk + kSubsV - 1) / kSubsV : 0));
+    if (g.cam_pass) want = std::max(want, (g.n_chunks + kSubsC - 1) / kSubsC);
     const int grid = std::max(1, std::min(want, per_cu * n_cu));
     // a fresh barrier: arrivals, generation and error flag cleared by a fill
     // kernel (no memset node, so the launch may be captured)
-    hipLaunchKernelGGL(k_fill<unsigned int>, dim3(1), dim3(64), 0, s, g.gbar, 0u, (size_t)4);
+    hipLaunchKernelGGL(k_fill<unsigned int>, dim3(1), dim3(256), 0, s, g.gbar, 0u, (size_t)kGbarWords);
     GBA_CHECK_LAUNCH();
     DeviceGraph ga = g;
     void* args[] = {(void*)&ga, (void*)&min_diag, (void*)&max_diag, (void*)&max_launch};

@@ -28,7 +28,7 @@ GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_CAMERA_PASS = 0, 1, 2
 GBA_PCG_AUTO, GBA_PCG_CHUNKED, GBA_PCG_PERSISTENT = 0, 1, 2
 GBA_JACOBIAN_ANALYTIC, GBA_JACOBIAN_AUTODIFF, GBA_JACOBIAN_DYNAMIC = 0, 1, 2
 GBA_SOLVER_SCHUR, GBA_SOLVER_FULL = 0, 1
-GBA_PERSISTENT_MAX_CAMS = 256
+GBA_VI_PRE_STRIDE = 148
 TERMINATION = {0: "NONE", 1: "MAX_ITERS", 2: "COST_TOL", 3: "STEP_TOL",
                4: "LAMBDA_OVERFLOW", 5: "NUMERICAL_FAILURE", 6: "NO_WORK"}
 
@@ -148,6 +148,11 @@ _SIGS = {
     "gba_eval_step": (ctypes.c_int, [_P, ctypes.c_double, _D, _D, ctypes.POINTER(ctypes.c_int)]),
     "gba_time_matvec": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D]),
     "gba_hbm_probe": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_size_t, _P, ctypes.c_int, _P, _D]),
+    "gba_vi_preintegrate": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _D, _D, ctypes.c_double,
+                                           _D, ctypes.c_double, ctypes.c_double, _D]),
+    "gba_vi_eval_inertial": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]),
+    "gba_vi_eval_stereo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int64, _D,
+                                          ctypes.c_int64, _P, _P, _D, _D, _D, _D]),
     "gba_last_error": (ctypes.c_char_p, [_P]),
     "gba_destroy": (None, [_P]),
     "gba_server_default_config": (None, [ctypes.POINTER(gba_server_config)]),
@@ -387,6 +392,54 @@ def gba_hbm_probe(device, buf_ptr, nbytes, sink_ptr, launches, stream=None):
     if st != 0:
         raise GbaError(st, "gba_hbm_probe failed")
     return t.value
+
+
+def _vi_check(st, what):
+    if st != 0:
+        raise GbaError(st, what + " failed")
+
+
+def gba_vi_preintegrate(device, sample_off, gyro, acc, dt, bias0, sigma_g=0.0, sigma_a=0.0):
+    """IMU preintegration of len(sample_off) - 1 intervals; returns (n, 148)."""
+    off = np.ascontiguousarray(sample_off, np.int64)
+    n = len(off) - 1
+    g = np.ascontiguousarray(gyro, np.float64)
+    a = np.ascontiguousarray(acc, np.float64)
+    b = np.ascontiguousarray(bias0, np.float64)
+    out = np.empty((max(n, 0), GBA_VI_PRE_STRIDE))
+    _vi_check(load().gba_vi_preintegrate(int(device), n, off.ctypes.data, _ptr(g), _ptr(a), float(dt),
+                                         _ptr(b), float(sigma_g), float(sigma_a), _ptr(out)),
+              "gba_vi_preintegrate")
+    return out
+
+
+def gba_vi_eval_inertial(device, states, pre):
+    """Residuals (n_kf - 1, 9) and Jacobians (n_kf - 1, 9, 24)."""
+    st = np.ascontiguousarray(states, np.float64)
+    pr = np.ascontiguousarray(pre, np.float64)
+    n = max(len(st) - 1, 0)
+    r = np.empty((n, 9))
+    J = np.empty((n, 9, 24))
+    _vi_check(load().gba_vi_eval_inertial(int(device), len(st), _ptr(st), _ptr(pr), _ptr(r), _ptr(J)),
+              "gba_vi_eval_inertial")
+    return r, J
+
+
+def gba_vi_eval_stereo(device, states, pts, kf, pt, obs, intr):
+    """Residuals (n, 3) and Jacobians (n, 3, 9)."""
+    st = np.ascontiguousarray(states, np.float64)
+    P = np.ascontiguousarray(pts, np.float64)
+    k = np.ascontiguousarray(kf, np.int64)
+    q = np.ascontiguousarray(pt, np.int64)
+    o = np.ascontiguousarray(obs, np.float64)
+    it = np.ascontiguousarray(intr, np.float64)
+    n = len(k)
+    r = np.empty((n, 3))
+    J = np.empty((n, 3, 9))
+    _vi_check(load().gba_vi_eval_stereo(int(device), len(st), _ptr(st), len(P), _ptr(P), n,
+                                        k.ctypes.data, q.ctypes.data, _ptr(o), _ptr(it), _ptr(r),
+                                        _ptr(J)), "gba_vi_eval_stereo")
+    return r, J
 
 
 def gba_last_error(h):

@@ -78,16 +78,21 @@ def test_full_converged_step_is_the_exact_step(form, jac):
 @pytest.mark.parametrize("schedule", [gba.GBA_PCG_CHUNKED, gba.GBA_PCG_PERSISTENT])
 def test_full_lm_trajectory_matches_the_oracle(form, jac, schedule):
     # the PCG run to the rounding level: per-trial costs and decisions of the
-    # oracle's exact LM, and its final cost and solution
+    # oracle's exact LM while the decrease is above rounding (after that both
+    # sides decide on rounding noise).  The dynamic form recomputes the
+    # Jacobian at the current parameters in every product, also in replayed
+    # PCG graphs after an accepted step has swapped the parameter buffers (a
+    # product at the previous parameters shows here as a cost off by ~1e-8)
     sc = synth.make_scene("small", seed=0)
     g = _graph(sc, jacobian=jac, pcg_max_iters=4000, pcg_tol=1e-13, pcg_schedule=schedule)
     rep = g.solve(sc.trials)
     res = ba.solve(_oracle(sc), sc.cams0, sc.pts0, sc.trials)
     for a, b in zip(g.trials(), res.log):
         assert abs(a["cost"] - b["cost"]) <= 1e-9 * b["cost"], (a, b)
-        if abs(b["cost"] - b["candidate_cost"]) > 1e-8 * b["cost"]:
-            assert a["accepted"] == b["accepted"], (a, b)
-    assert abs(rep.final_cost - res.cost) <= 1e-9 * res.cost
+        if abs(b["cost"] - b["candidate_cost"]) <= 1e-9 * b["cost"]:
+            break
+        assert a["accepted"] == b["accepted"], (a, b)
+    assert abs(rep.final_cost - res.cost) <= 1e-7 * res.cost
     err = align.aligned_errors(g.cameras(), g.points(), res.x[0], res.x[1])
     assert err["rel"] <= 1e-6, err
 
@@ -114,6 +119,15 @@ def test_full_bal1m_final_cost(precision, form, jac):
     rel = abs(rep.final_cost - gold["final_cost"]) / gold["final_cost"]
     print(f"bal1m full {form}: final cost rel {rel:.3e}, {rep.pcg_iters_total} PCG iterations")
     assert rel <= 1e-4, rel
+    if form == "dynamic":
+        # the same products as the stored Jacobian's (rounded to the same
+        # storage type): the same PCG work to within rounding-level decisions
+        gs = _graph(sc, precision=precision, jacobian=gba.GBA_JACOBIAN_ANALYTIC,
+                    pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol)
+        rs = gs.solve(gold["trials"])
+        assert abs(rep.pcg_iters_total - rs.pcg_iters_total) <= 0.02 * rs.pcg_iters_total, \
+            (rep.pcg_iters_total, rs.pcg_iters_total)
+        assert abs(rep.final_cost - rs.final_cost) <= 1e-7 * rs.final_cost
 
 
 def test_full_option_errors():
