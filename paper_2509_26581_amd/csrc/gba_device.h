@@ -169,17 +169,67 @@ __device__ __forceinline__ T shfl64(T v, int src) {
     return __shfl(v, src, kWave);
 }
 
-// Inclusive suffix sum inside contiguous segments: after the call the head
-// lane of each segment holds the segment total.
-template <typename T>
-__device__ __forceinline__ T segment_sum(T v, int l, int end) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        T o = shfl_down64(v, off);
-        if (l + off <= end) v += o;
-    }
-    return v;
+// Segmented inclusive prefix sums across a wavefront by DPP lane moves, with
+// no LDS traffic (a ds_bpermute shuffle goes through the LDS crossbar and
+// waits for it): Hillis-Steele steps of 1, 2, 4 and 8 lanes inside each row
+// of 16, then the broadcasts of lane 15 into rows 1 and 3 and of lane 31
+// into rows 2 and 3.  `start` marks the first lane of a segment.  After
+// sum(v) the last lane of each segment holds the segment's total (the order
+// of the additions depends only on the segmentation).  The closing flags of
+// the six steps are computed once per segmentation and shared by its sums.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_move(int v) {
+    // lanes outside the row mask, or without a source lane, read 0
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
 }
+
+struct SegScan {
+    bool closed[6];   // before step s the lane's prefix already starts a segment
+
+    __device__ __forceinline__ explicit SegScan(bool start) {
+        int f = start ? 1 : 0;
+        closed[0] = f != 0;
+        f |= dpp_move<0x111, 0xF>(f);   // row_shr:1
+        closed[1] = f != 0;
+        f |= dpp_move<0x112, 0xF>(f);   // row_shr:2
+        closed[2] = f != 0;
+        f |= dpp_move<0x114, 0xF>(f);   // row_shr:4
+        closed[3] = f != 0;
+        f |= dpp_move<0x118, 0xF>(f);   // row_shr:8
+        closed[4] = f != 0;
+        f |= dpp_move<0x142, 0xA>(f);   // row_bcast:15
+        closed[5] = f != 0;
+    }
+
+    template <int kCtrl, int kRowMask>
+    __device__ __forceinline__ static float move(float v) {
+        return __int_as_float(dpp_move<kCtrl, kRowMask>(__float_as_int(v)));
+    }
+    template <int kCtrl, int kRowMask>
+    __device__ __forceinline__ static double move(double v) {
+        const int lo = dpp_move<kCtrl, kRowMask>(__double2loint(v));
+        const int hi = dpp_move<kCtrl, kRowMask>(__double2hiint(v));
+        return __hiloint2double(hi, lo);
+    }
+
+    template <typename T>
+    __device__ __forceinline__ T sum(T v) const {
+        T m;
+        m = move<0x111, 0xF>(v);
+        v = closed[0] ? v : v + m;
+        m = move<0x112, 0xF>(v);
+        v = closed[1] ? v : v + m;
+        m = move<0x114, 0xF>(v);
+        v = closed[2] ? v : v + m;
+        m = move<0x118, 0xF>(v);
+        v = closed[3] ? v : v + m;
+        m = move<0x142, 0xA>(v);
+        v = closed[4] ? v : v + m;
+        m = move<0x143, 0xC>(v);
+        v = closed[5] ? v : v + m;
+        return v;
+    }
+};
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -145,9 +145,10 @@ __global__ __launch_bounds__(256) void k_linearize(DeviceGraph g, RawOut raw) {
                 const bool st = !valid || idx == 0 || g.e_pt[e - 1] != j;
                 starts = __ballot(st);
                 segment_of(starts, l, head, end);
+                const SegScan seg(st);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) acc[k] = segment_sum(valid ? h[k] : 0.0, l, end);
-                if (valid && head == l) {
+                for (int k = 0; k < 9; ++k) acc[k] = seg.sum(valid ? h[k] : 0.0);
+                if (valid && end == l) {   // the segment's last lane holds its sums
 #pragma unroll
                     for (int k = 0; k < 6; ++k) Hpp[k * g.np + j] = (T)acc[k];
 #pragma unroll
@@ -775,7 +776,7 @@ __device__ __forceinline__ void pp_body(const DeviceGraph& g, const int bid, con
                 z[2] = h02 * b0 + h12 * b1 + h22 * b2;
             } else {
                 // the point block is loaded by every lane of the point at the
-                // start (the head lane applies it), next to the camera gather
+                // start (its last lane applies it), next to the camera gather
                 const VT* H = (const VT*)g.hpp_inv + kHinvStride * j;
                 const T h00 = H[0], h01 = H[1], h02 = H[2], h11 = H[3], h12 = H[4], h22 = H[5];
                 if constexpr (sizeof(VT) == 8) {
@@ -791,14 +792,12 @@ __device__ __forceinline__ void pp_body(const DeviceGraph& g, const int bid, con
                     a1 += jc[1][k] * pc[k];
                 }
                 T tt[3];
+                const SegScan seg(st);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    tt[k] = valid ? jp[0][k] * a0 + jp[1][k] * a1 : (T)0;
-                    tt[k] = segment_sum(tt[k], l, end);
-                }
-                // head lane applies the point block
+                for (int k = 0; k < 3; ++k) tt[k] = seg.sum(valid ? jp[0][k] * a0 + jp[1][k] * a1 : (T)0);
+                // the point's last lane (which holds the sums) applies the point block
                 T zz[3] = {0, 0, 0};
-                if (valid && head == l) {
+                if (valid && end == l) {
                     T v0 = tt[0], v1 = tt[1], v2 = tt[2];
                     if (kMode == kBacksub) {
                         v0 += bp[j];
@@ -831,7 +830,7 @@ __device__ __forceinline__ void pp_body(const DeviceGraph& g, const int bid, con
                 }
                 if (kMode == kMatvec && cpass) continue;   // uniform: the whole wave
 #pragma unroll
-                for (int k = 0; k < 3; ++k) z[k] = shfl64(zz[k], head);
+                for (int k = 0; k < 3; ++k) z[k] = shfl64(zz[k], end);
             }
             if (kMode == kBacksub) {
                 if (valid) {
@@ -978,7 +977,7 @@ __global__ __launch_bounds__(kPointPassBlock) void k_point_pass(DeviceGraph g, c
 // the product H_lambda v over cameras and points together.  Per edge
 // u = J_c v_c + J_p v_p; the camera rows J_c^T u are privatised in LDS and
 // flushed per workgroup (k_reduce adds the damping), the point rows J_p^T u
-// are segmented wavefront sums over the point's edges, finished by the head
+// are segmented wavefront sums over the point's edges, finished by the last
 // lane with the point's damping.  kMatvec multiplies z after the iteration's
 // decision and forms the point parts of q = H z + beta q_old and
 // p = z + beta p_old (and p^T q); kBacksub multiplies the step x and gives
@@ -1045,7 +1044,7 @@ __device__ __forceinline__ void full_pp_body(const DeviceGraph& g, const int bid
     const T lo = (T)g.min_diag, hi = (T)g.max_diag;
     const int nw = blockDim.x >> 6;
     double red_q = 0.0, red_m = 0.0, red_b = 0.0, red_s = 0.0;
-    // the point rows of one point j (head lane): H_lambda v_p finished, then
+    // the point rows of one point j (one lane of it): H_lambda v_p finished, then
     // q, p and p^T q (kMatvec), or the candidate point (kBacksub)
     auto point_rows = [&](int j, const T (&tt)[3], const T (&zp)[3]) {
         if (kMode == kMatvec) {
@@ -1114,12 +1113,10 @@ __device__ __forceinline__ void full_pp_body(const DeviceGraph& g, const int bid
                 continue;
             }
             T tt[3];
+            const SegScan seg(st);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                tt[k] = valid ? jp[0][k] * u0 + jp[1][k] * u1 : (T)0;
-                tt[k] = segment_sum(tt[k], l, end);
-            }
-            if (valid && head == l) point_rows(j, tt, zp);
+            for (int k = 0; k < 3; ++k) tt[k] = seg.sum(valid ? jp[0][k] * u0 + jp[1][k] * u1 : (T)0);
+            if (valid && end == l) point_rows(j, tt, zp);   // the last lane holds the sums
             if (valid) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k)
