@@ -735,7 +735,25 @@ __device__ __forceinline__ void pp_body(const DeviceGraph& g, const int bid, con
     // two-pass scheme: this pass only produces z_j (camera sums in k_cam_pass)
     const bool cpass = g.cam_pass != 0;
     // the product: this PCG iteration's decision, by the first wavefront
-    // while the others clear the partials
+    // while the others clear the partials and request their first tile (edge
+    // range, indices, Jacobian), whose loads so overlap the decision's two
+    // dependent reads (about a microsecond at bal1m).  Only FP32 Jacobians
+    // are requested ahead (FP64: 48 registers; BF16 measured slower with).
+    constexpr bool kPreJ = std::is_same<JS, float>::value;
+    const int w = threadIdx.x >> 6;
+    const bool pre = kMode == kMatvec && w > 0 && tb + w < te;   // uniform per wavefront
+    int f_e0 = 0, f_e1 = 0, f_j = 0, f_i = 0;
+    T f_jc[2][9], f_jp[2][3];
+    if (pre) {
+        f_e0 = g.tile_off[tb + w];
+        f_e1 = g.tile_off[tb + w + 1];
+        if (f_e1 - f_e0 <= kWave) {
+            const int e = f_e0 + (l < f_e1 - f_e0 ? l : 0);
+            f_j = g.e_pt[e];
+            f_i = g.e_cam[e];
+            if constexpr (kPreJ) jac_load<JS>(J, e, f_jc, f_jp);
+        }
+    }
     if (kMode == kMatvec && threadIdx.x < kWave) {
         const PcgState d = pcg_decision(g, prob);
         if (threadIdx.x == 0) {
@@ -750,21 +768,33 @@ __device__ __forceinline__ void pp_body(const DeviceGraph& g, const int bid, con
     const int nw = blockDim.x >> 6;
     const VT* bp = (const VT*)g.bp;
     double red_m = 0.0, red_b = 0.0, red_s = 0.0;
-    for (int t = tb + (int)(threadIdx.x >> 6); t < te; t += nw) {
-        const int e0 = g.tile_off[t], e1 = g.tile_off[t + 1];
+    for (int t = tb + w; t < te; t += nw) {
+        const bool first = pre && t == tb + w;
+        const int e0 = first ? f_e0 : g.tile_off[t];
+        const int e1 = first ? f_e1 : g.tile_off[t + 1];
         const int n = e1 - e0;
         if (n <= kWave) {
             const bool valid = l < n;
             const int e = e0 + (valid ? l : 0);
-            const int j = g.e_pt[e];
-            const int i = g.e_cam[e];
+            const int j = first ? f_j : g.e_pt[e];
+            const int i = first ? f_i : g.e_cam[e];
             const int jprev = __shfl_up(j, 1);   // the previous edge of the tile
             const bool st = !valid || l == 0 || jprev != j;
             const uint64_t starts = __ballot(st);
             int head, end;
             segment_of(starts, l, head, end);
             T jc[2][9], jp[2][3];
-            jac_load<JS>(J, e, jc, jp);
+            if (kPreJ && first) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) jc[a][k] = f_jc[a][k];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) jp[a][k] = f_jp[a][k];
+                }
+            } else {
+                jac_load<JS>(J, e, jc, jp);
+            }
             T z[3];
             T pc[9];
             if (kMode == kRhs) {
