@@ -231,11 +231,28 @@ struct SegScan {
     }
 };
 
+// Sum over the 64 lanes of a wavefront (every lane active), returned to
+// every lane: the inclusive-scan steps of SegScan without segments (DPP lane
+// moves, no LDS round trips), then lane 63's total read into a scalar
+// register.  The order of the additions is fixed.
+__device__ __forceinline__ float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += SegScan::move<0x111, 0xF>(v);
+    v += SegScan::move<0x112, 0xF>(v);
+    v += SegScan::move<0x114, 0xF>(v);
+    v += SegScan::move<0x118, 0xF>(v);
+    v += SegScan::move<0x142, 0xA>(v);
+    v += SegScan::move<0x143, 0xC>(v);
+    return lane63(v);
 }
 
 // Block-wide sum; every thread gets the result.  `red` holds >= 16 values.
