@@ -1240,12 +1240,14 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
     __shared__ double dred[16];
     int kb, ke;
     const int prob = decomp_block(g.dc_red, bid, kb, ke);
+    // the decision is read here but tested after every load of the
+    // workgroup has been issued (the test would otherwise hold them behind
+    // its load); a stopped problem's workgroup only wastes those reads
     int act = 0;
     T beta = 0;
     if (kMode == kMatvec) {
         const PcgState* dp = g.pcg_dec + prob;
         act = dp->act;
-        if (!(act & kActStep)) return;   // this problem's PCG has stopped
         beta = (T)dp->beta;
     }
     const int tid = threadIdx.x;
@@ -1310,18 +1312,35 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
                         for (int u = 0; u < kCpl; ++u) a[v][u] += chunk_get<T, T>(x[v], u);
             }
         }
+        if (kMode == kMatvec && !(act & kActStep)) return;   // this problem's PCG has stopped
 #pragma unroll
         for (int u = 0; u < kCpl; ++u) red[grp][c0 + u] = (a[0][u] + a[1][u]) + (a[2][u] + a[3][u]);
         __syncthreads();
+        // the kGroups rows in two stages over the whole workgroup: kParts
+        // partial rows of kGroups / kParts, then their sum by the owners
+        constexpr int kParts = kBlock / kRedComps;
+        static_assert(kGroups % kParts == 0 && kParts <= kGroups, "row split of the partial sums");
+        constexpr int kRows = kGroups / kParts;
+        {
+            const int c = tid % kRedComps, part = tid / kRedComps;
+            T t = 0;
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) t += red[part * kRows + q][c];
+            __syncthreads();
+            red[part][c] = t;
+        }
+        __syncthreads();
         if (own) {
             T t0 = 0, t1 = 0;
-            for (int q = 0; q < kGroups; q += 2) {
+#pragma unroll
+            for (int q = 0; q < kParts; q += 2) {
                 t0 += red[q][tid];
                 t1 += red[q + 1][tid];
             }
             tot = t0 + t1;
         }
     }
+    if (kMode == kMatvec && !(act & kActStep)) return;   // (the two-pass scheme's test)
     double dot = 0.0;
     if (own) {
         if (kMode == kRhs) {
@@ -1477,25 +1496,25 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0)
     // T PCG stopped before this iteration (the rest of a replayed chunk of
     // iterations) exits after one load.  Otherwise every load of the step is
     // issued before the next wait (the dot, alpha).
+    // the decision is read with the rest and tested once every load is
+    // issued (a stopped problem's workgroup only wastes those reads)
     const PcgState* dp = g.pcg_dec + prob;
     const int act = blk ? dp->act : 0;
     const double rz_dec = blk ? dp->rz : 0.0;
-    const bool live = (act & kActState) != 0;
-    if (kSubs == 1 && !live) return;
     // the lead thread loads the decision it stores as the state now, so that
     // the store at the end waits for nothing
-    const bool lead = live && tid == 0 && bid == g.dc_cam.prob_blk[prob];
+    const bool lead0 = blk && tid == 0 && bid == g.dc_cam.prob_blk[prob];
     constexpr int kWords = (int)(sizeof(PcgState) / 8);   // copied as 8-byte words
     static_assert(sizeof(PcgState) % 8 == 0, "PcgState is a whole number of 8-byte words");
     uint2 dq[kWords];
-    if (lead) {
+    if (lead0) {
 #pragma unroll
         for (int u = 0; u < kWords; ++u) dq[u] = ((const uint2*)dp)[u];
     }
     T* __restrict__ x = (T*)g.v_x;
     T* __restrict__ r = (T*)g.v_r;
     double pq = 0.0;
-    if (live) {
+    if (blk) {
         for (int b = g.dc_red.prob_blk[prob] + tid; b < g.dc_red.prob_blk[prob + 1]; b += kPcgBlock)
             pq += g.pq_partial[b];
         if (g.full)   // the point part of p^T q, from the product's workgroups
@@ -1506,7 +1525,7 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0)
     T xk = 0, pk = 0, qk = 0, rk = 0;
     T m[9];
     const int i = k / 9, a = k % 9;
-    if (live && valid) {
+    if (valid) {
         xk = x[k];
         pk = ((const T*)g.v_p)[k];
         qk = ((const T*)g.v_q)[k];
@@ -1515,6 +1534,9 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0)
 #pragma unroll
         for (int b = 0; b < 9; ++b) m[b] = Minv[i * 45 + sym9(a, b)];
     }
+    const bool live = (act & kActState) != 0;
+    if (kSubs == 1 && !live) return;
+    const bool lead = lead0 && live;
     // every workgroup of the problem sums the same partials in the same
     // order, so all of them take the same branch
     pq = sub_sum<kPcgBlock>(pq, red);
