@@ -285,18 +285,23 @@ gba_status gba_set_options(gba_graph* g, const gba_options* opts);
 gba_status gba_prepare(gba_graph* g);
 
 /* Run up to max_iters LM trials from the current parameters (tol as in
- * gba_termination).  Synchronous: returns after the results are on device and
- * the report is filled (report may be NULL).  Returns GBA_OK whenever the
- * solver ran, including on early termination. */
+ * gba_termination): the Levenberg-Marquardt iteration of the Background
+ * section (the damped normal equations of Eq. normal-equations, solved by PCG
+ * as in the mixed-precision solver section; the step kept when the cost
+ * falls).  Synchronous: returns after the results are on device and the
+ * report is filled (report may be NULL).  Returns GBA_OK whenever the solver
+ * ran, including on early termination. */
 gba_status gba_solve(gba_graph* g, int max_iters, double tol, gba_report* report);
 
 /* Restore the parameters given at insertion time (device-side copy). */
 gba_status gba_reset(gba_graph* g);
 
-/* Current cost F = 1/2 sum rho(s_e) over active edges (FP64). */
+/* Current cost F = 1/2 sum rho(s_e) over active edges (FP64): the total
+ * error of Eq. total-error with the robust kernel applied per edge. */
 gba_status gba_get_cost(gba_graph* g, double* cost);
 
-/* Current parameters, insertion order: out[n_cams x 9] / out[n_pts x 3]. */
+/* Current parameters (the vertices x of Eq. total-error), insertion order:
+ * out[n_cams x 9] / out[n_pts x 3]; out is host memory the caller owns. */
 gba_status gba_get_cameras(gba_graph* g, double* out);
 gba_status gba_get_points(gba_graph* g, double* out);
 
