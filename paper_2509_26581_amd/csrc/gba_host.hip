@@ -477,6 +477,7 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     L.add(d.cost_partial, sizeof(double) * std::max(1, u.edges.nblk()));
     L.add(d.damp_partial, sizeof(double) * std::max(1, u.pts.nblk()));
     L.add(d.gbar, sizeof(unsigned int) * kGbarWords);
+    L.add(d.red_count, sizeof(unsigned int) * u.P);
     if (u.full) {
         for (void** v : {&d.w_x, &d.w_r, &d.w_z, &d.w_p, &d.w_q, &d.w_best})
             L.add(*v, tsz * 3 * NP + 64);
@@ -512,6 +513,7 @@ void set_union_scalars(Batch& b, int precision, int loss, double delta) {
     d.full = u.full ? 1 : 0;
     d.dynamic = u.dynamic ? 1 : 0;
     d.lds_pp = u.lds_pp;
+    d.fuse_apply = !u.full && u.max_cams <= kFuseApplyCams ? 1 : 0;
     d.dc_pp.nblk = u.pp.nblk();
     d.dc_red.nblk = u.red.nblk();
     d.dc_cam.nblk = u.cam.nblk();

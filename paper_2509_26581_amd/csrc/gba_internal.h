@@ -195,6 +195,12 @@ struct DeviceGraph {
                               // jst_cm: sums per chunk)
     int deterministic;        // 1: every sum in an order that depends only on the problem
                               // (not on the batch it is packed with)
+    // Small problems: the last reduction workgroup of a problem to finish
+    // runs that problem's PCG update (no update launch); red_count[P] counts
+    // the finished reduction workgroups per problem (cleared at each PCG start
+    // and by the last arrival)
+    int fuse_apply;
+    unsigned int* red_count;
     unsigned int* gbar;       // [kGbarWords] grid barrier of the persistent PCG: arrivals,
                               // generation, error flag; group arrival counters
                               // kGbarLine words apart
@@ -289,6 +295,10 @@ hipError_t launch_matvec(const DeviceGraph& g, hipStream_t s, int max_iters, dou
 // launched, the vector updates and the camera-major pass as kSubs launched
 // workgroups side by side.
 constexpr int kPersistentBlock = kPointPassBlock;
+// the fused update runs when every problem has at most this many cameras (at
+// most four camera-aligned update workgroups, one pass of the reduction's
+// 1024 threads)
+constexpr int kFuseApplyCams = 4 * (kPcgBlock / 9);
 // The grid barrier counts arrivals in kGbarGroups groups (workgroup index
 // modulo kGbarGroups), each counter on its own 128-byte line, then the groups
 // at the top: no one address takes every workgroup's atomic.

@@ -1226,6 +1226,44 @@ __global__ __launch_bounds__(kPointPassBlock) void k_full_point_pass(DeviceGraph
 //            q = S p = S z + beta q (FP64); partial dots p^T q (FP64)
 // Workgroup: up to 64 components of one problem x 16 partial groups.
 // ==========================================================================
+template <typename T, int kSubs>
+__device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0, const int bid_end);
+
+// Every vector-memory access of this wavefront has completed: its stores are
+// in the L2 (s_waitcnt vmcnt(0); the workgroup barrier does not wait for them).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// The fused update: each reduction workgroup of a problem arrives after its
+// q, p and p^T q partial are written; the problem's last arrival acquires
+// them all and runs the problem's update as kBlock / kPcgBlock camera-aligned
+// update workgroups side by side (the arithmetic of the update kernel).  The
+// arrival is a device-scope release by one thread after every wavefront's
+// stores have reached the L2.
+template <typename T, int kBlock>
+__device__ __forceinline__ void fused_update(const DeviceGraph& g, const int prob) {
+    __shared__ int s_last;
+    wait_vmem();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int n = (unsigned int)(g.dc_red.prob_blk[prob + 1] - g.dc_red.prob_blk[prob]);
+        const unsigned int old =
+            __hip_atomic_fetch_add(g.red_count + prob, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = old == n - 1;
+        if (s_last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every arrival's writes
+            g.red_count[prob] = 0;                               // ready for the next iteration
+        }
+    }
+    __syncthreads();
+    if (!s_last) return;
+    constexpr int kSubs = kBlock / kPcgBlock;
+    const int b1 = g.dc_cam.prob_blk[prob + 1];
+    for (int b = g.dc_cam.prob_blk[prob]; b < b1; b += kSubs) {
+        apply_body<T, kSubs>(g, b, b1);
+        __syncthreads();
+    }
+}
+
 template <typename T, int kMode, int kBlock>
 __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid, double min_diag,
                                             double max_diag) {
@@ -1242,7 +1280,9 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
     const int prob = decomp_block(g.dc_red, bid, kb, ke);
     // the decision is read here but tested after every load of the
     // workgroup has been issued (the test would otherwise hold them behind
-    // its load); a stopped problem's workgroup only wastes those reads
+    // its load); a stopped problem's workgroup only wastes those reads.  A
+    // problem whose PCG stopped at this iteration's decision still passes
+    // the fused update (which stores the state).
     int act = 0;
     T beta = 0;
     if (kMode == kMatvec) {
@@ -1250,6 +1290,7 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
         act = dp->act;
         beta = (T)dp->beta;
     }
+    const bool fuse = kMode == kMatvec && g.fuse_apply;
     const int tid = threadIdx.x;
     const int k = kb + tid;                               // component (threads < kRedComps)
     const bool own = tid < kRedComps && k < ke;
@@ -1312,7 +1353,10 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
                         for (int u = 0; u < kCpl; ++u) a[v][u] += chunk_get<T, T>(x[v], u);
             }
         }
-        if (kMode == kMatvec && !(act & kActStep)) return;   // this problem's PCG has stopped
+        if (kMode == kMatvec && !(act & kActStep)) {   // this problem's PCG has stopped
+            if (fuse && (act & kActState)) fused_update<T, kBlock>(g, prob);
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < kCpl; ++u) red[grp][c0 + u] = (a[0][u] + a[1][u]) + (a[2][u] + a[3][u]);
         __syncthreads();
@@ -1340,7 +1384,10 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
             tot = t0 + t1;
         }
     }
-    if (kMode == kMatvec && !(act & kActStep)) return;   // (the two-pass scheme's test)
+    if (kMode == kMatvec && !(act & kActStep)) {   // (the two-pass scheme's test)
+        if (fuse && (act & kActState)) fused_update<T, kBlock>(g, prob);
+        return;
+    }
     double dot = 0.0;
     if (own) {
         if (kMode == kRhs) {
@@ -1372,6 +1419,7 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
     if (kMode == kMatvec) {
         dot = block_sum(dot, dred);
         if (threadIdx.x == 0) g.pq_partial[bid] = dot;
+        if (fuse) fused_update<T, kBlock>(g, prob);
     }
 }
 
@@ -1463,6 +1511,7 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
             st.pad_ = 0;
             st.done = g.lam[prob] < 0.0 ? 5 : ((rr <= st.thresh || !(rz > 0.0)) ? 1 : 0);
             g.pcg[prob] = st;
+            if (g.red_count) g.red_count[prob] = 0;
             // a problem without point-pass workgroups never takes a decision:
             // its slot says stopped (such a problem has r = 0 and stops here)
             g.pcg_dec[prob] = st;
@@ -1481,7 +1530,7 @@ __global__ __launch_bounds__(1024) void k_pcg_start_finish(DeviceGraph g, double
 // bid0 .. bid0 + kSubs - 1 side by side (the persistent kernel), each with
 // the arithmetic of a launched one; every thread then passes every barrier.
 template <typename T, int kSubs>
-__device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0) {
+__device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0, const int bid_end) {
     if (!vec_type_ok<T>(g)) return;   // instantiated for another mode
     __shared__ T r_lds[kSubs * kPcgBlock];
     __shared__ double red[16];
@@ -1489,7 +1538,7 @@ __device__ __forceinline__ void apply_body(const DeviceGraph& g, const int bid0)
     const int tid = (int)threadIdx.x - sub * kPcgBlock;
     const int bid = bid0 + sub;
     int cb = 0, ce = 0, prob = 0;
-    const bool blk = kSubs == 1 || bid < g.dc_cam.nblk;
+    const bool blk = kSubs == 1 || bid < bid_end;
     if (blk) prob = decomp_block(g.dc_cam, bid, cb, ce);
     const int k = 9 * cb + tid;
     const bool valid = tid < 9 * (ce - cb);
@@ -1706,7 +1755,7 @@ template <typename T>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_apply(DeviceGraph g) {
     const int b = (int)blockIdx.x;
     if (b < g.dc_cam.nblk)
-        apply_body<T, 1>(g, b);
+        apply_body<T, 1>(g, b, g.dc_cam.nblk);
     else if (g.full && vec_type_ok<T>(g))
         apply_pts_body<T, 1>(g, b - g.dc_cam.nblk);
 }
@@ -1926,8 +1975,8 @@ constexpr unsigned int kBarrierSpin = 1u << 21;   // sleeps before a barrier giv
 // counter of workgroup group k (index modulo kGbarGroups) at
 // bar[kGbarLine * (1 + k)].  One thread per workgroup takes part.  Its
 // arrival at its group is a release at device scope (the workgroup's writes,
-// ordered before it by the workgroup barrier, reach the point of coherence
-// of the eight XCDs); a group's last arrival acquires them and arrives at the
+// in the L2 once every wavefront has waited for its stores, reach the point
+// of coherence of the eight XCDs); a group's last arrival acquires them and arrives at the
 // top (release), and the top's last arrival resets the count and opens the
 // next generation (release).  The others poll the generation with relaxed
 // loads, which read the coherent copy and leave the caches alone, and
@@ -1940,6 +1989,7 @@ constexpr unsigned int kBarrierSpin = 1u << 21;   // sleeps before a barrier giv
 // every later barrier returns at once, so the kernel ends whatever happens
 // (the host reports the flag).
 __device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int nblocks, unsigned int& gen) {
+    wait_vmem();   // every wavefront's stores are in the L2 before the release
     __syncthreads();
     if (threadIdx.x == 0) {
         constexpr unsigned int G = kGbarGroups;
@@ -2015,7 +2065,7 @@ __global__ __launch_bounds__(kPersistentBlock) void k_pcg_persistent(DeviceGraph
         // the camera and the point updates are independent (separate vectors
         // and partials), one after the other without a barrier
         for (int b = blockIdx.x * kSubsV; b < g.dc_cam.nblk; b += gridDim.x * kSubsV) {
-            apply_body<VT, kSubsV>(g, b);
+            apply_body<VT, kSubsV>(g, b, g.dc_cam.nblk);
             __syncthreads();
         }
         if constexpr (kForm != 0) {
@@ -2382,12 +2432,15 @@ hipError_t launch_pcg_iter(const DeviceGraph& g, hipStream_t s, double min_diag,
     if (e != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
     const int apply_blocks = g.dc_cam.nblk + (g.full ? g.dc_pts.nblk : 0);
+    // small problems: the reduction's last workgroup per problem runs the update
     if (g.mode == kModeFP64) {
         hipLaunchKernelGGL((k_reduce<double, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_apply<double>, dim3(apply_blocks), dim3(kPcgBlock), 0, s, g);
+        if (!g.fuse_apply)
+            hipLaunchKernelGGL(k_pcg_apply<double>, dim3(apply_blocks), dim3(kPcgBlock), 0, s, g);
     } else {
         hipLaunchKernelGGL((k_reduce<float, kMatvec>), dim3(g.dc_red.nblk), dim3(1024), 0, s, g, min_diag, max_diag);
-        hipLaunchKernelGGL(k_pcg_apply<float>, dim3(apply_blocks), dim3(kPcgBlock), 0, s, g);
+        if (!g.fuse_apply)
+            hipLaunchKernelGGL(k_pcg_apply<float>, dim3(apply_blocks), dim3(kPcgBlock), 0, s, g);
     }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
@@ -2428,6 +2481,7 @@ static hipError_t persistent_launch(const DeviceGraph& g, hipStream_t s, double 
     hipLaunchKernelGGL(k_fill<unsigned int>, dim3(1), dim3(256), 0, s, g.gbar, 0u, (size_t)kGbarWords);
     GBA_CHECK_LAUNCH();
     DeviceGraph ga = g;
+    ga.fuse_apply = 0;   // the update is a phase of its own here
     void* args[] = {(void*)&ga, (void*)&min_diag, (void*)&max_diag, (void*)&max_launch};
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPersistentBlock), args, (unsigned)lds, s);
 }
