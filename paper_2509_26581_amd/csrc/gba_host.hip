@@ -743,13 +743,14 @@ gba_status batch_damped_step(Batch& b, const gba_options& o, const Tuning& tune,
     }
     const int chunk = std::max(1, std::min(kMaxPcgChunk, tune.pcg_sync_every));
     // A PCG of k steps takes k + 1 launched iterations: an iteration decides
-    // at its start whether the previous step ended the PCG.  With graphs, the
-    // first chunk is the previous step's launch count (successive LM trials
-    // need similar counts; an idle iteration costs a few microseconds, a
-    // further host check about thirty) and the rest are chunks of two.
-    // Without a previous count: chunks of pcg_sync_every.
+    // at its start whether the previous step ended the PCG.  The first chunk
+    // is the previous step's launch count (successive LM trials need similar
+    // counts; an idle iteration costs a few microseconds, a further host
+    // check about thirty), replayed as a graph or launched directly, and the
+    // rest are chunks of two.  Without a previous count: chunks of
+    // pcg_sync_every.
     int first = chunk, rest = chunk;
-    if (b.use_graphs && b.last_pcg_iters > 0) {
+    if (b.last_pcg_iters > 0) {
         first = std::min(kMaxPcgChunk, b.last_pcg_iters + 1);
         rest = std::min(chunk, 2);
     }
