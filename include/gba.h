@@ -535,6 +535,61 @@ gba_status gba_vi_eval_stereo(int device, int n_kf, const double* states, int64_
                               const double* pts, int64_t n_obs, const int64_t* kf, const int64_t* pt,
                               const double* obs, const double* intr, double* r, double* J);
 
+/* A visual-inertial bundle-adjustment problem (Background Eq. 8; Sec. V-C):
+ * keyframe states (angle-axis of R world <- body, p, v, b_g, b_a; 15 doubles
+ * each, updated in place), map points (3 doubles each, updated in place),
+ * stereo observations (keyframe kf[e], point pt[e], u_l, v_l, u_r) with the
+ * rectified pair intr = (fx, fy, cx, cy, baseline), and the preintegrated
+ * interval of each consecutive keyframe pair (gba_vi_preintegrate's output,
+ * GBA_VI_PRE_STRIDE doubles per interval).  The cost is
+ *   F = 1/2 sum_stereo rho(|r|^2 / sigma_px^2)          (Huber with threshold
+ *       huber_delta2 on the squared norm; 0: squared loss)
+ *     + 1/2 sum_inertial r^T cov^-1 r                    (gba_vi_eval_inertial)
+ *     + 1/2 sum_bias r^T Omega_b r,  r = b_{f+1} - b_f,
+ *       Omega_b = diag(I3 / (sigma_gw^2 dt), I3 / (sigma_aw^2 dt)).
+ * The first keyframe is held fixed (the gauge). */
+typedef struct gba_vi_problem {
+    int32_t n_kf;              /* keyframes, >= 2                            */
+    int32_t reserved0;
+    int64_t n_pts;
+    int64_t n_obs;
+    double* states;            /* [15 n_kf] in/out                           */
+    double* pts;               /* [3 n_pts] in/out                           */
+    const int64_t* kf;         /* [n_obs]                                    */
+    const int64_t* pt;         /* [n_obs]                                    */
+    const double* obs;         /* [3 n_obs]                                  */
+    const double* intr;        /* [5]                                        */
+    const double* pre;         /* [GBA_VI_PRE_STRIDE (n_kf - 1)]             */
+    double sigma_px;           /* > 0                                        */
+    double huber_delta2;       /* >= 0                                       */
+    double sigma_gw;           /* gyroscope bias random-walk density, > 0    */
+    double sigma_aw;           /* accelerometer bias random-walk density     */
+} gba_vi_problem;
+
+typedef struct gba_vi_options {
+    int pcg_max_iters;         /* PCG iterations per trial (100)             */
+    int reserved0;
+    double pcg_tol;            /* stop at |r| <= pcg_tol |r0| (1e-8)         */
+    double initial_lambda;     /* 1e-4                                       */
+    double min_diag, max_diag; /* clip of the damping diagonal (1e-6, 1e32)  */
+} gba_vi_options;
+
+void gba_vi_default_options(gba_vi_options* out);
+
+/* gba_vi_solve: up to max_iters Levenberg-Marquardt trials on a
+ * visual-inertial problem, with the acceptance, damping and stop rules of
+ * gba_solve (tol as in gba_termination), in the paper's solver form for it:
+ * PCG on the whole damped system over keyframe states and points (no point
+ * elimination), block-Jacobi preconditioned (15 x 15 keyframe blocks, 3 x 3
+ * point blocks), FP64 throughout.  Host arrays in and out (copied to and from
+ * device memory the call allocates and frees); report and the first max_log
+ * trials in log (n_log: their count) may be NULL / 0.  INVALID_ARG for
+ * missing arrays, n_kf < 2 or non-positive noise parameters, UNKNOWN_ID for
+ * an index out of range, OOM when device memory runs out. */
+gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, double tol,
+                        const gba_vi_options* opts, gba_report* report, gba_trial* log,
+                        int max_log, int* n_log);
+
 #ifdef __cplusplus
 }
 #endif

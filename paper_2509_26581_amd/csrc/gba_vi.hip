@@ -9,6 +9,9 @@
 // perturbation R Exp(dtheta) and additive p, v, b.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -374,6 +377,565 @@ __global__ __launch_bounds__(256) void k_stereo_eval(long long n, const double* 
         for (int k = 0; k < 3; ++k) r_out[3 * (size_t)e + k] = r[k].v;
 }
 
+// block-wide sum of a double over a 256-thread workgroup (lane 0 of the
+// first wavefront holds the result)
+__device__ __forceinline__ double block_sum_vi(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;
+}
+
+// ==========================================================================
+// The visual-inertial LM solve (Background Eq. 8; Sec. V-C) in the paper's
+// solver form for it: PCG on the whole damped system over keyframe states and
+// points (no point elimination), block-Jacobi preconditioned (15 x 15
+// keyframe blocks, 3 x 3 point blocks), FP64.  Unknowns per keyframe: dtheta,
+// dp, dv, dbg, dba (the rotation updated on the right); per point: dX.  The
+// first keyframe is held fixed (its columns are zero).  Terms:
+//   stereo   1/2 rho(|r|^2 / sigma^2), Huber on the squared norm, IRLS
+//            whitening sqrt(w) / sigma;
+//   inertial 1/2 r^T Omega r, Omega the inverse preintegrated covariance;
+//   bias     1/2 r^T Omega_b r, r = b_j - b_i, Omega_b from the random-walk
+//            densities and the interval length.
+// Products H v are sums over the terms of J^T Omega J v with the vertex
+// outputs added atomically; the stored Jacobians are the terms' whitened
+// (stereo) or raw (inertial, with Omega applied in the product) blocks.
+// ==========================================================================
+constexpr int kSt = 21;   // device keyframe state: R (row-major), p, v, bg, ba
+
+struct VIDev {
+    int K;                 // keyframes
+    long long N, M;        // points, stereo observations
+    double* st;            // [K kSt] current
+    double* st_c;          // [K kSt] candidate
+    double* X;             // [3 N]
+    double* X_c;
+    const int* kf;         // [M]
+    const int* pt;
+    const double* obs;     // [3 M]
+    const double* pre;     // [kPreStride (K - 1)]
+    double* info;          // [81 (K - 1)] Omega of the inertial terms
+    double* js;            // [27 M] whitened stereo Jacobians (dtheta, dp | dX)
+    double* rs;            // [3 M]
+    double* ji;            // [216 (K - 1)] inertial Jacobians
+    double* ri;            // [9 (K - 1)]
+    double* b;             // [n] gradient J^T Omega r
+    double* hk;            // [225 K] keyframe diagonal blocks
+    double* hp;            // [9 N] point diagonal blocks
+    double* dg;            // [n] clipped diagonal (damping)
+    double* mk;            // [225 K] Cholesky factors of the damped keyframe blocks
+    double* mp;            // [9 N] inverses of the damped point blocks
+    double* scal;          // [8] reductions
+    double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
+    long long n() const { return 15LL * K + 3 * N; }
+};
+
+__device__ __forceinline__ void atomic_add(double* a, double v) { unsafeAtomicAdd(a, v); }
+
+__global__ void k_vi_states_in(int K, const double* __restrict__ s15, double* __restrict__ s21) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const double w[3] = {s15[15 * k], s15[15 * k + 1], s15[15 * k + 2]};
+    double R[3][3];
+    so3_exp(w, R);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) s21[kSt * k + 3 * r + c] = R[r][c];
+    for (int j = 0; j < 12; ++j) s21[kSt * k + 9 + j] = s15[15 * k + 3 + j];
+}
+
+__global__ void k_vi_states_out(int K, const double* __restrict__ s21, double* __restrict__ s15) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double R[3][3], w[3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) R[r][c] = s21[kSt * k + 3 * r + c];
+    so3_log(R, w);
+    for (int j = 0; j < 3; ++j) s15[15 * k + j] = w[j];
+    for (int j = 0; j < 12; ++j) s15[15 * k + 3 + j] = s21[kSt * k + 9 + j];
+}
+
+// Omega = cov^-1 per interval by Cholesky (cov = L L^T): Omega = L^-T L^-1.
+__global__ void k_vi_info(int n, const double* __restrict__ pre, double* __restrict__ info) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n) return;
+    const double* C = pre + (size_t)kPreStride * f + kCov;
+    double L[9][9] = {};
+    for (int j = 0; j < 9; ++j) {
+        double d = C[9 * j + j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < 9; ++i) {
+            double t = C[9 * i + j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    double Li[9][9] = {};   // L^-1 (lower)
+    for (int c = 0; c < 9; ++c) {
+        for (int r = c; r < 9; ++r) {
+            double t = r == c ? 1.0 : 0.0;
+            for (int k = c; k < r; ++k) t -= L[r][k] * Li[k][c];
+            Li[r][c] = t / L[r][r];
+        }
+    }
+    double* O = info + 81 * (size_t)f;
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            double t = 0.0;
+            for (int k = (r > c ? r : c); k < 9; ++k) t += Li[k][r] * Li[k][c];
+            O[9 * r + c] = t;
+        }
+}
+
+// Stereo projection of observation e at (R, p) and X: Xc, the prediction and
+// (with kJac) the 3 x 9 Jacobian over dtheta, dp, dX.
+template <bool kJac>
+__device__ __forceinline__ void vi_stereo(const VIDev& d, const double* __restrict__ s,
+                                          const double* __restrict__ X, long long e, double (&r)[3],
+                                          double (&J)[3][9]) {
+    double q[3], Xc[3];
+    for (int k = 0; k < 3; ++k) q[k] = X[k] - s[9 + k];
+    for (int k = 0; k < 3; ++k) Xc[k] = s[k] * q[0] + s[3 + k] * q[1] + s[6 + k] * q[2];
+    const double iz = 1.0 / Xc[2];
+    const double ul = d.fx * Xc[0] * iz + d.cx;
+    r[0] = ul - d.obs[3 * e];
+    r[1] = d.fy * Xc[1] * iz + d.cy - d.obs[3 * e + 1];
+    r[2] = ul - d.fx * d.base * iz - d.obs[3 * e + 2];
+    if (!kJac) return;
+    double P[3][3] = {{d.fx * iz, 0.0, -d.fx * Xc[0] * iz * iz},
+                      {0.0, d.fy * iz, -d.fy * Xc[1] * iz * iz},
+                      {d.fx * iz, 0.0, -d.fx * (Xc[0] - d.base) * iz * iz}};
+    const double Kx[3][3] = {{0.0, -Xc[2], Xc[1]}, {Xc[2], 0.0, -Xc[0]}, {-Xc[1], Xc[0], 0.0}};
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) {
+            J[a][c] = P[a][0] * Kx[0][c] + P[a][1] * Kx[1][c] + P[a][2] * Kx[2][c];
+            // P R^T: (R^T)[k][c] = R[c][k]
+            const double PRt = P[a][0] * s[3 * c] + P[a][1] * s[3 * c + 1] + P[a][2] * s[3 * c + 2];
+            J[a][3 + c] = -PRt;
+            J[a][6 + c] = PRt;
+        }
+}
+
+__device__ __forceinline__ void vi_huber(double s, double delta2, double& rho, double& w) {
+    if (delta2 > 0.0 && s > delta2) {
+        const double q = sqrt(s);
+        rho = 2.0 * sqrt(delta2) * q - delta2;
+        w = sqrt(delta2) / q;
+    } else {
+        rho = s;
+        w = 1.0;
+    }
+}
+
+// linearisation of the stereo terms: whitened J and r stored; gradient and
+// diagonal blocks accumulated
+__global__ void k_vi_lin_stereo(VIDev d) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= d.M) return;
+    const int k = d.kf[e], j = d.pt[e];
+    double r[3], J[3][9];
+    vi_stereo<true>(d, d.st + (size_t)kSt * k, d.X + 3 * (size_t)j, e, r, J);
+    const double s = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * d.inv_sigma * d.inv_sigma;
+    double rho, w;
+    vi_huber(s, d.delta2, rho, w);
+    const double sc = sqrt(w) * d.inv_sigma;
+    for (int a = 0; a < 3; ++a) {
+        r[a] *= sc;
+        for (int c = 0; c < 9; ++c) J[a][c] = (k == 0 && c < 6) ? 0.0 : J[a][c] * sc;
+    }
+    for (int a = 0; a < 3; ++a) {
+        d.rs[3 * e + a] = r[a];
+        for (int c = 0; c < 9; ++c) d.js[27 * e + 9 * a + c] = J[a][c];
+    }
+    double* bk = d.b + 15 * (size_t)k;
+    double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
+    for (int c = 0; c < 9; ++c) {
+        const double g = J[0][c] * r[0] + J[1][c] * r[1] + J[2][c] * r[2];
+        atomic_add(c < 6 ? bk + c : bp + (c - 6), g);
+    }
+    if (k != 0)
+        for (int a = 0; a < 6; ++a)
+            for (int c = 0; c < 6; ++c)
+                atomic_add(d.hk + 225 * (size_t)k + 15 * a + c,
+                           J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            atomic_add(d.hp + 9 * (size_t)j + 3 * a + c,
+                       J[0][6 + a] * J[0][6 + c] + J[1][6 + a] * J[1][6 + c] + J[2][6 + a] * J[2][6 + c]);
+}
+
+// inertial Jacobians by forward-mode AD, one lane per (term, column), at the
+// device states (rotation matrices); columns of a fixed first keyframe zero
+__global__ __launch_bounds__(256) void k_vi_lin_inertial(VIDev d) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int n = d.K - 1;
+    if (t >= 24LL * n) return;
+    const int f = (int)(t / 24), col = (int)(t % 24);
+    using S = Dual<double>;
+    const double* si = d.st + (size_t)kSt * f;
+    const double* sj = d.st + (size_t)kSt * (f + 1);
+    double Ri0[3][3], Rj0[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            Ri0[r][c] = si[3 * r + c];
+            Rj0[r][c] = sj[3 * r + c];
+        }
+    S z[24];
+    for (int k = 0; k < 24; ++k) z[k] = {0.0, k == col ? 1.0 : 0.0};
+    S di[3] = {z[0], z[1], z[2]}, dj[3] = {z[15], z[16], z[17]};
+    S Ri[3][3], Rj[3][3];
+    perturb_rot(Ri0, di, Ri);
+    perturb_rot(Rj0, dj, Rj);
+    S pi[3], vi_[3], bg[3], ba[3], pj[3], vj[3];
+    for (int k = 0; k < 3; ++k) {
+        pi[k] = si[9 + k] + z[3 + k];
+        vi_[k] = si[12 + k] + z[6 + k];
+        bg[k] = si[15 + k] + z[9 + k];
+        ba[k] = si[18 + k] + z[12 + k];
+        pj[k] = sj[9 + k] + z[18 + k];
+        vj[k] = sj[12 + k] + z[21 + k];
+    }
+    S r[9];
+    inertial_residual(Ri, pi, vi_, bg, ba, Rj, pj, vj, d.pre + (size_t)kPreStride * f, r);
+    const bool zero = f == 0 && col < 15;
+    for (int k = 0; k < 9; ++k) d.ji[(size_t)216 * f + 24 * k + col] = zero ? 0.0 : r[k].d;
+    if (col == 0)
+        for (int k = 0; k < 9; ++k) d.ri[9 * (size_t)f + k] = r[k].v;
+}
+
+// inertial and bias terms: gradient and diagonal blocks (one lane per term)
+__global__ void k_vi_acc_inertial(VIDev d) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.K - 1) return;
+    const double* J = d.ji + (size_t)216 * f;
+    const double* O = d.info + 81 * (size_t)f;
+    const double* r = d.ri + 9 * (size_t)f;
+    double Or[9];
+    for (int a = 0; a < 9; ++a) {
+        double t = 0.0;
+        for (int c = 0; c < 9; ++c) t += O[9 * a + c] * r[c];
+        Or[a] = t;
+    }
+    double* bi = d.b + 15 * (size_t)f;
+    double* bj = d.b + 15 * (size_t)(f + 1);
+    for (int c = 0; c < 24; ++c) {
+        double g = 0.0;
+        for (int a = 0; a < 9; ++a) g += J[24 * a + c] * Or[a];
+        atomic_add(c < 15 ? bi + c : bj + (c - 15), g);
+    }
+    // J^T Omega J on the two diagonal blocks (OJ = Omega J, 9 x 24)
+    double* hi = d.hk + 225 * (size_t)f;
+    double* hj = d.hk + 225 * (size_t)(f + 1);
+    for (int c2 = 0; c2 < 24; ++c2) {
+        double OJ[9];
+        for (int a = 0; a < 9; ++a) {
+            double t = 0.0;
+            for (int k = 0; k < 9; ++k) t += O[9 * a + k] * J[24 * k + c2];
+            OJ[a] = t;
+        }
+        for (int c1 = 0; c1 < 24; ++c1) {
+            const bool same = (c1 < 15) == (c2 < 15);
+            if (!same) continue;
+            double t = 0.0;
+            for (int a = 0; a < 9; ++a) t += J[24 * a + c1] * OJ[a];
+            if (c1 < 15)
+                atomic_add(hi + 15 * c1 + c2, t);
+            else
+                atomic_add(hj + 15 * (c1 - 15) + (c2 - 15), t);
+        }
+    }
+    // bias random walk: r = b_j - b_i (6), Omega_b = diag(wg I3, wa I3) / dt
+    const double dt = d.pre[(size_t)kPreStride * f + kDt];
+    const double* si = d.st + (size_t)kSt * f;
+    const double* sj = d.st + (size_t)kSt * (f + 1);
+    for (int k = 0; k < 6; ++k) {
+        const double w = (k < 3 ? d.wg : d.wa) / dt;
+        const double rb = sj[15 + k] - si[15 + k];
+        atomic_add(bj + 9 + k, w * rb);
+        atomic_add(hj + 15 * (9 + k) + 9 + k, w);
+        if (f != 0) {
+            atomic_add(bi + 9 + k, -w * rb);
+            atomic_add(hi + 15 * (9 + k) + 9 + k, w);
+        }
+    }
+}
+
+// cost at (st, X): 1/2 sum rho over stereo, 1/2 r^T Omega r over inertial,
+// 1/2 r^T Omega_b r over bias; into scal[slot]
+__global__ void k_vi_cost(VIDev d, const double* __restrict__ st, const double* __restrict__ X,
+                          int slot) {
+    __shared__ double red[16];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double c = 0.0;
+    if (t < d.M) {
+        double r[3], J[3][9];
+        vi_stereo<false>(d, st + (size_t)kSt * d.kf[t], X + 3 * (size_t)d.pt[t], t, r, J);
+        double rho, w;
+        vi_huber((r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * d.inv_sigma * d.inv_sigma, d.delta2, rho, w);
+        c = 0.5 * rho;
+    } else if (t < d.M + d.K - 1) {
+        const int f = (int)(t - d.M);
+        const double* si = st + (size_t)kSt * f;
+        const double* sj = st + (size_t)kSt * (f + 1);
+        double Ri[3][3], Rj[3][3], pi[3], vi_[3], bg[3], ba[3], pj[3], vj[3];
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) {
+                Ri[a][b] = si[3 * a + b];
+                Rj[a][b] = sj[3 * a + b];
+            }
+            pi[a] = si[9 + a];
+            vi_[a] = si[12 + a];
+            bg[a] = si[15 + a];
+            ba[a] = si[18 + a];
+            pj[a] = sj[9 + a];
+            vj[a] = sj[12 + a];
+        }
+        double r[9];
+        inertial_residual(Ri, pi, vi_, bg, ba, Rj, pj, vj, d.pre + (size_t)kPreStride * f, r);
+        const double* O = d.info + 81 * (size_t)f;
+        for (int a = 0; a < 9; ++a)
+            for (int b = 0; b < 9; ++b) c += 0.5 * r[a] * O[9 * a + b] * r[b];
+        const double dt = d.pre[(size_t)kPreStride * f + kDt];
+        for (int k = 0; k < 6; ++k) {
+            const double rb = sj[15 + k] - si[15 + k];
+            c += 0.5 * ((k < 3 ? d.wg : d.wa) / dt) * rb * rb;
+        }
+    }
+    c = block_sum_vi(c, red);
+    if (threadIdx.x == 0) atomic_add(d.scal + slot, c);
+}
+
+// damped block-Jacobi preconditioner: D = clip(diag H); keyframe blocks
+// H + lambda diag(D) factored (Cholesky, in place into mk), point blocks
+// inverted; one lane per block
+__global__ void k_vi_precond(VIDev d, double lam, double lo, double hi) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < d.K) {
+        const int k = (int)t;
+        const double* H = d.hk + 225 * (size_t)k;
+        double* L = d.mk + 225 * (size_t)k;
+        for (int i = 0; i < 15; ++i) {
+            const double dd = fmin(fmax(H[16 * i], lo), hi);
+            d.dg[15 * (size_t)k + i] = dd;
+        }
+        for (int i = 0; i < 225; ++i) L[i] = H[i];
+        for (int i = 0; i < 15; ++i) L[16 * i] += lam * d.dg[15 * (size_t)k + i];
+        for (int j = 0; j < 15; ++j) {
+            double s = L[16 * j];
+            for (int q = 0; q < j; ++q) s -= L[15 * j + q] * L[15 * j + q];
+            const double ljj = sqrt(fmax(s, 1e-300));
+            L[16 * j] = ljj;
+            for (int i = j + 1; i < 15; ++i) {
+                double u = L[15 * i + j];
+                for (int q = 0; q < j; ++q) u -= L[15 * i + q] * L[15 * j + q];
+                L[15 * i + j] = u / ljj;
+            }
+        }
+    } else if (t < d.K + d.N) {
+        const long long j = t - d.K;
+        const double* H = d.hp + 9 * j;
+        double A[3][3];
+        for (int a = 0; a < 3; ++a) {
+            const double dd = fmin(fmax(H[4 * a], lo), hi);
+            d.dg[15 * (size_t)d.K + 3 * j + a] = dd;
+            for (int c = 0; c < 3; ++c) A[a][c] = H[3 * a + c] + (a == c ? lam * dd : 0.0);
+        }
+        const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+        const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+        const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+        const double id = 1.0 / det;
+        double* M = d.mp + 9 * j;
+        M[0] = c00 * id;
+        M[1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+        M[2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+        M[3] = c01 * id;
+        M[4] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+        M[5] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+        M[6] = c02 * id;
+        M[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+        M[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    }
+}
+
+// z = M^-1 r
+__global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __restrict__ z) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < d.K) {
+        const size_t o = 15 * (size_t)t;
+        const double* L = d.mk + 225 * (size_t)t;
+        double y[15];
+        for (int i = 0; i < 15; ++i) {
+            double u = r[o + i];
+            for (int q = 0; q < i; ++q) u -= L[15 * i + q] * y[q];
+            y[i] = u / L[16 * i];
+        }
+        for (int i = 14; i >= 0; --i) {
+            double u = y[i];
+            for (int q = i + 1; q < 15; ++q) u -= L[15 * q + i] * y[q];
+            y[i] = u / L[16 * i];
+        }
+        for (int i = 0; i < 15; ++i) z[o + i] = y[i];
+    } else if (t < d.K + d.N) {
+        const long long j = t - d.K;
+        const size_t o = 15 * (size_t)d.K + 3 * j;
+        const double* M = d.mp + 9 * j;
+        const double a = r[o], b = r[o + 1], c = r[o + 2];
+        for (int i = 0; i < 3; ++i) z[o + i] = M[3 * i] * a + M[3 * i + 1] * b + M[3 * i + 2] * c;
+    }
+}
+
+// q += (stereo part of H) v
+__global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* __restrict__ q) {
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= d.M) return;
+    const size_t ok = 15 * (size_t)d.kf[e], op = 15 * (size_t)d.K + 3 * (size_t)d.pt[e];
+    double in[9];
+    for (int c = 0; c < 6; ++c) in[c] = v[ok + c];
+    for (int c = 0; c < 3; ++c) in[6 + c] = v[op + c];
+    const double* J = d.js + 27 * (size_t)e;
+    double u[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = 0.0;
+        for (int c = 0; c < 9; ++c) t += J[9 * a + c] * in[c];
+        u[a] = t;
+    }
+    for (int c = 0; c < 9; ++c) {
+        const double y = J[c] * u[0] + J[9 + c] * u[1] + J[18 + c] * u[2];
+        atomic_add(q + (c < 6 ? ok + c : op + (c - 6)), y);
+    }
+}
+
+// q += (inertial and bias parts of H) v
+__global__ void k_vi_prod_inertial(VIDev d, const double* __restrict__ v, double* __restrict__ q) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= d.K - 1) return;
+    const size_t oi = 15 * (size_t)f, oj = 15 * (size_t)(f + 1);
+    const double* J = d.ji + (size_t)216 * f;
+    const double* O = d.info + 81 * (size_t)f;
+    double u[9];
+    for (int a = 0; a < 9; ++a) {
+        double t = 0.0;
+        for (int c = 0; c < 15; ++c) t += J[24 * a + c] * v[oi + c];
+        for (int c = 0; c < 9; ++c) t += J[24 * a + 15 + c] * v[oj + c];
+        u[a] = t;
+    }
+    double w[9];
+    for (int a = 0; a < 9; ++a) {
+        double t = 0.0;
+        for (int c = 0; c < 9; ++c) t += O[9 * a + c] * u[c];
+        w[a] = t;
+    }
+    for (int c = 0; c < 24; ++c) {
+        double y = 0.0;
+        for (int a = 0; a < 9; ++a) y += J[24 * a + c] * w[a];
+        atomic_add(q + (c < 15 ? oi + c : oj + (c - 15)), y);
+    }
+    const double dt = d.pre[(size_t)kPreStride * f + kDt];
+    for (int k = 0; k < 6; ++k) {
+        const double wb = (k < 3 ? d.wg : d.wa) / dt;
+        const double vi_k = f != 0 ? v[oi + 9 + k] : 0.0;
+        const double yb = wb * (v[oj + 9 + k] - vi_k);
+        atomic_add(q + oj + 9 + k, yb);
+        if (f != 0) atomic_add(q + oi + 9 + k, -yb);
+    }
+}
+
+// q = lambda diag(D) v (the first term of the product; the others add)
+__global__ void k_vi_prod_damp(long long n, double lam, const double* __restrict__ dg,
+                               const double* __restrict__ v, double* __restrict__ q) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) q[i] = lam * dg[i] * v[i];
+}
+
+__global__ void k_vi_dot(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                         double* __restrict__ out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        s += a[i] * b[i];
+    s = block_sum_vi(s, red);
+    if (threadIdx.x == 0) atomic_add(out, s);
+}
+
+// x += alpha p, r -= alpha q
+__global__ void k_vi_axpy2(long long n, double alpha, const double* __restrict__ p,
+                           const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) {
+        x[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+    }
+}
+
+// p = z + beta p
+__global__ void k_vi_xpby(long long n, double beta, const double* __restrict__ z, double* __restrict__ p) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_vi_neg(long long n, const double* __restrict__ b, double* __restrict__ r,
+                         double* __restrict__ x) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) {
+        r[i] = -b[i];
+        x[i] = 0.0;
+    }
+}
+
+__global__ void k_vi_fill(long long n, double* __restrict__ a) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0;
+}
+
+// candidate: R Exp(dtheta), p + dp, v + dv, b + db; X + dX
+__global__ void k_vi_step(VIDev d, const double* __restrict__ dx) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < d.K) {
+        const double* s = d.st + (size_t)kSt * t;
+        double* c = d.st_c + (size_t)kSt * t;
+        const double* u = dx + 15 * (size_t)t;
+        const double w[3] = {u[0], u[1], u[2]};
+        double E[3][3];
+        so3_exp(w, E);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                c[3 * a + b] = s[3 * a] * E[0][b] + s[3 * a + 1] * E[1][b] + s[3 * a + 2] * E[2][b];
+        for (int k = 0; k < 12; ++k) c[9 + k] = s[9 + k] + u[3 + k];
+    } else if (t < d.K + d.N) {
+        const long long j = t - d.K;
+        for (int k = 0; k < 3; ++k) d.X_c[3 * j + k] = d.X[3 * j + k] + dx[15 * (size_t)d.K + 3 * j + k];
+    }
+}
+
+// |x|^2 over the free parameters: |Log R|^2 and the other state entries of
+// keyframes 1.., and the points
+__global__ void k_vi_xnorm(VIDev d, const double* __restrict__ st, const double* __restrict__ X, int slot) {
+    __shared__ double red[16];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (t >= 1 && t < d.K) {
+        const double* q = st + (size_t)kSt * t;
+        double R[3][3], w[3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) R[a][b] = q[3 * a + b];
+        so3_log(R, w);
+        for (int k = 0; k < 3; ++k) s += w[k] * w[k];
+        for (int k = 9; k < kSt; ++k) s += q[k] * q[k];
+    } else if (t >= d.K && t < d.K + d.N) {
+        const long long j = t - d.K;
+        for (int k = 0; k < 3; ++k) s += X[3 * j + k] * X[3 * j + k];
+    }
+    s = block_sum_vi(s, red);
+    if (threadIdx.x == 0) atomic_add(d.scal + slot, s);
+}
+
 }  // namespace vi
 }  // namespace gba
 
@@ -472,6 +1034,229 @@ gba_status gba_vi_eval_stereo(int device, int n_kf, const double* states, int64_
     if (hipMemcpy(r, dr, sizeof(double) * 3 * n_obs, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(J, dj, sizeof(double) * 27 * n_obs, hipMemcpyDeviceToHost) != hipSuccess)
         return GBA_ERR_HIP;
+    return GBA_OK;
+}
+
+void gba_vi_default_options(gba_vi_options* o) {
+    if (!o) return;
+    o->pcg_max_iters = 100;
+    o->reserved0 = 0;
+    o->pcg_tol = 1e-8;
+    o->initial_lambda = 1e-4;
+    o->min_diag = 1e-6;
+    o->max_diag = 1e32;
+}
+
+gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, double tol,
+                        const gba_vi_options* opts, gba_report* report, gba_trial* log, int max_log,
+                        int* n_log) {
+    using namespace gba::vi;
+    const auto t_start = std::chrono::steady_clock::now();
+    if (n_log) *n_log = 0;
+    if (!prob || max_iters < 0 || !(tol >= 0.0) || (max_log > 0 && !log)) return GBA_ERR_INVALID_ARG;
+    const gba_vi_problem& P = *prob;
+    if (P.n_kf < 2 || P.n_pts < 0 || P.n_obs < 0 || !P.states || !P.intr || !P.pre ||
+        (P.n_pts > 0 && !P.pts) || (P.n_obs > 0 && (!P.kf || !P.pt || !P.obs)) ||
+        !(P.sigma_px > 0.0) || !(P.huber_delta2 >= 0.0) || !(P.sigma_gw > 0.0) || !(P.sigma_aw > 0.0))
+        return GBA_ERR_INVALID_ARG;
+    if (P.n_obs > INT32_MAX / 27 || P.n_pts > INT32_MAX || P.n_kf > INT32_MAX / 225)
+        return GBA_ERR_UNSUPPORTED;
+    gba_vi_options o;
+    gba_vi_default_options(&o);
+    if (opts) o = *opts;
+    if (o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) || !(o.initial_lambda > 0.0) ||
+        !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag))
+        return GBA_ERR_INVALID_ARG;
+    std::vector<int> hkf((size_t)P.n_obs), hpt((size_t)P.n_obs);
+    for (int64_t e = 0; e < P.n_obs; ++e) {
+        if (P.kf[e] < 0 || P.kf[e] >= P.n_kf || P.pt[e] < 0 || P.pt[e] >= P.n_pts) return GBA_ERR_UNKNOWN_ID;
+        hkf[(size_t)e] = (int)P.kf[e];
+        hpt[(size_t)e] = (int)P.pt[e];
+    }
+    if (hipSetDevice(device) != hipSuccess) return GBA_ERR_HIP;
+    const int K = P.n_kf;
+    const long long N = P.n_pts, M = P.n_obs, n = 15LL * K + 3 * N;
+    DevBufs B;
+    VIDev d{};
+    d.K = K;
+    d.N = N;
+    d.M = M;
+    double *s15 = nullptr, *pre = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr,
+           *q = nullptr;
+    int *dkf = nullptr, *dpt = nullptr;
+    double* obs = nullptr;
+    if (!B.up(&s15, P.states, 15 * (size_t)K) || !B.up(&d.st, (const double*)nullptr, kSt * (size_t)K) ||
+        !B.up(&d.st_c, (const double*)nullptr, kSt * (size_t)K) ||
+        !B.up(&d.X, P.pts, 3 * (size_t)N + 1) || !B.up(&d.X_c, (const double*)nullptr, 3 * (size_t)N + 1) ||
+        !B.up(&dkf, hkf.data(), (size_t)M + 1) || !B.up(&dpt, hpt.data(), (size_t)M + 1) ||
+        !B.up(&obs, P.obs, 3 * (size_t)M + 1) ||
+        !B.up(&pre, P.pre, (size_t)kPreStride * (K - 1)) ||
+        !B.up(&d.info, (const double*)nullptr, 81 * (size_t)(K - 1)) ||
+        !B.up(&d.js, (const double*)nullptr, 27 * (size_t)M + 1) ||
+        !B.up(&d.rs, (const double*)nullptr, 3 * (size_t)M + 1) ||
+        !B.up(&d.ji, (const double*)nullptr, 216 * (size_t)(K - 1)) ||
+        !B.up(&d.ri, (const double*)nullptr, 9 * (size_t)(K - 1)) ||
+        !B.up(&d.b, (const double*)nullptr, (size_t)n) || !B.up(&d.hk, (const double*)nullptr, 225 * (size_t)K) ||
+        !B.up(&d.hp, (const double*)nullptr, 9 * (size_t)N + 1) || !B.up(&d.dg, (const double*)nullptr, (size_t)n) ||
+        !B.up(&d.mk, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
+        !B.up(&d.scal, (const double*)nullptr, 8) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
+        !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
+        !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n))
+        return GBA_ERR_OOM;
+    d.kf = dkf;
+    d.pt = dpt;
+    d.obs = obs;
+    d.pre = pre;
+    d.fx = P.intr[0];
+    d.fy = P.intr[1];
+    d.cx = P.intr[2];
+    d.cy = P.intr[3];
+    d.base = P.intr[4];
+    d.inv_sigma = 1.0 / P.sigma_px;
+    d.delta2 = P.huber_delta2;
+    d.wg = 1.0 / (P.sigma_gw * P.sigma_gw);
+    d.wa = 1.0 / (P.sigma_aw * P.sigma_aw);
+    auto grid = [](long long cnt) { return dim3((unsigned)std::max(1LL, (cnt + 255) / 256)); };
+    const dim3 blk(256);
+    hipError_t err = hipSuccess;
+    auto chk = [&]() {
+        if (err == hipSuccess) err = hipGetLastError();
+        return err == hipSuccess;
+    };
+    hipLaunchKernelGGL(k_vi_states_in, grid(K), blk, 0, nullptr, K, s15, d.st);
+    hipLaunchKernelGGL(k_vi_info, grid(K - 1), blk, 0, nullptr, K - 1, pre, d.info);
+    if (!chk()) return GBA_ERR_HIP;
+    double hs[8];
+    auto read_scal = [&]() {
+        if (err == hipSuccess) err = hipMemcpy(hs, d.scal, sizeof(hs), hipMemcpyDeviceToHost);
+        return err == hipSuccess;
+    };
+    auto zero_scal = [&]() { hipLaunchKernelGGL(k_vi_fill, dim3(1), dim3(64), 0, nullptr, 8LL, d.scal); };
+    // cost of (st, X) into slot 0, and |x|^2 into slot 1 when asked
+    auto cost_of = [&](const double* st, const double* X, bool xnorm, double& F, double& xn) {
+        zero_scal();
+        hipLaunchKernelGGL(k_vi_cost, grid(M + K - 1), blk, 0, nullptr, d, st, X, 0);
+        if (xnorm) hipLaunchKernelGGL(k_vi_xnorm, grid(K + N), blk, 0, nullptr, d, st, X, 1);
+        if (!chk() || !read_scal()) return false;
+        F = hs[0];
+        xn = std::sqrt(hs[1]);
+        return true;
+    };
+    auto linearize = [&]() {
+        hipLaunchKernelGGL(k_vi_fill, grid(n), blk, 0, nullptr, n, d.b);
+        hipLaunchKernelGGL(k_vi_fill, grid(225LL * K), blk, 0, nullptr, 225LL * K, d.hk);
+        hipLaunchKernelGGL(k_vi_fill, grid(9 * N + 1), blk, 0, nullptr, 9 * N + 1, d.hp);
+        if (M > 0) hipLaunchKernelGGL(k_vi_lin_stereo, grid(M), blk, 0, nullptr, d);
+        hipLaunchKernelGGL(k_vi_lin_inertial, grid(24LL * (K - 1)), blk, 0, nullptr, d);
+        hipLaunchKernelGGL(k_vi_acc_inertial, grid(K - 1), blk, 0, nullptr, d);
+        return chk();
+    };
+    // q = (H + lam diag(D)) v
+    auto product = [&](const double* v, double* out, double lam) {
+        hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out);
+        if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out);
+        hipLaunchKernelGGL(k_vi_prod_inertial, grid(K - 1), blk, 0, nullptr, d, v, out);
+    };
+    auto dot = [&](const double* a, const double* b2, double& out) {
+        zero_scal();
+        const long long nb = std::min<long long>(1024, (n + 255) / 256);
+        hipLaunchKernelGGL(k_vi_dot, dim3((unsigned)nb), blk, 0, nullptr, n, a, b2, d.scal);
+        if (!chk() || !read_scal()) return false;
+        out = hs[0];
+        return true;
+    };
+    // PCG from 0 on (H + lam D) x = -b to |r| <= pcg_tol |r0|
+    auto pcg = [&](double lam, int& iters) {
+        iters = 0;
+        hipLaunchKernelGGL(k_vi_precond, grid(K + N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag);
+        hipLaunchKernelGGL(k_vi_neg, grid(n), blk, 0, nullptr, n, d.b, r, x);
+        hipLaunchKernelGGL(k_vi_apply_m, grid(K + N), blk, 0, nullptr, d, r, z);
+        hipLaunchKernelGGL(k_vi_xpby, grid(n), blk, 0, nullptr, n, 0.0, z, pv);
+        double rz = 0.0, rr0 = 0.0;
+        if (!dot(r, z, rz) || !dot(r, r, rr0)) return false;
+        const double thresh = o.pcg_tol * o.pcg_tol * rr0;
+        if (!(rr0 > thresh) || !(rz > 0.0)) return true;
+        for (int it = 0; it < o.pcg_max_iters; ++it) {
+            product(pv, q, lam);
+            double pq = 0.0;
+            if (!dot(pv, q, pq)) return false;
+            if (!(pq > 0.0)) break;
+            const double alpha = rz / pq;
+            hipLaunchKernelGGL(k_vi_axpy2, grid(n), blk, 0, nullptr, n, alpha, pv, q, x, r);
+            iters = it + 1;
+            double rr = 0.0;
+            if (!dot(r, r, rr)) return false;
+            if (rr <= thresh) break;
+            hipLaunchKernelGGL(k_vi_apply_m, grid(K + N), blk, 0, nullptr, d, r, z);
+            double rz_new = 0.0;
+            if (!dot(r, z, rz_new)) return false;
+            hipLaunchKernelGGL(k_vi_xpby, grid(n), blk, 0, nullptr, n, rz_new / rz, z, pv);
+            rz = rz_new;
+        }
+        return chk();
+    };
+    gba_report rep{};
+    double F = 0.0, xn = 0.0;
+    if (!cost_of(d.st, d.X, false, F, xn)) return GBA_ERR_HIP;
+    rep.initial_cost = F;
+    rep.termination = GBA_TERM_MAX_ITERS;
+    int nl = 0;
+    double lam = o.initial_lambda, nu = 2.0;
+    if (!std::isfinite(F)) {
+        rep.termination = GBA_TERM_NUMERICAL_FAILURE;
+    } else if (max_iters > 0) {
+        if (!linearize()) return GBA_ERR_HIP;
+        for (int it = 0; it < max_iters; ++it) {
+            int iters = 0;
+            if (!pcg(lam, iters)) return GBA_ERR_HIP;
+            rep.pcg_iters_total += iters;
+            // model decrease -(b.dx + 1/2 dx^T H dx) with the undamped H
+            product(x, q, 0.0);
+            double bdx = 0.0, dHd = 0.0, dd = 0.0;
+            if (!chk() || !dot(d.b, x, bdx) || !dot(x, q, dHd) || !dot(x, x, dd)) return GBA_ERR_HIP;
+            const double L = -(bdx + 0.5 * dHd);
+            hipLaunchKernelGGL(k_vi_step, grid(K + N), blk, 0, nullptr, d, x);
+            double Fn = 0.0, xnorm = 0.0, dummy = 0.0;
+            if (!cost_of(d.st_c, d.X_c, false, Fn, dummy) || !cost_of(d.st, d.X, true, dummy, xnorm))
+                return GBA_ERR_HIP;
+            const double dnorm = std::sqrt(dd);
+            const bool accepted = L > 0.0 && Fn < F;
+            const double gain = L != 0.0 ? (F - Fn) / L : NAN;
+            if (nl < max_log) log[nl++] = gba_trial{F, Fn, lam, L, dnorm, accepted ? 1 : 0, iters};
+            rep.trials += 1;
+            int stop = 0;
+            if (accepted) {
+                rep.accepted += 1;
+                const double rel = (F - Fn) / F;
+                std::swap(d.st, d.st_c);
+                std::swap(d.X, d.X_c);
+                F = Fn;
+                lam *= std::max(1.0 / 3.0, 1.0 - std::pow(2.0 * gain - 1.0, 3));
+                nu = 2.0;
+                if (rel < tol) stop = GBA_TERM_COST_TOL;
+            } else {
+                lam *= nu;
+                nu *= 2.0;
+            }
+            if (!stop && dnorm <= tol * (xnorm + tol)) stop = GBA_TERM_STEP_TOL;
+            if (!stop && lam > 1e32) stop = GBA_TERM_LAMBDA_OVERFLOW;
+            if (stop) {
+                rep.termination = stop;
+                break;
+            }
+            if (accepted && !linearize()) return GBA_ERR_HIP;
+        }
+    }
+    rep.final_cost = F;
+    rep.final_lambda = lam;
+    hipLaunchKernelGGL(k_vi_states_out, grid(K), blk, 0, nullptr, K, d.st, s15);
+    if (!chk()) return GBA_ERR_HIP;
+    if (hipMemcpy(P.states, s15, sizeof(double) * 15 * K, hipMemcpyDeviceToHost) != hipSuccess ||
+        (N > 0 && hipMemcpy(P.pts, d.X, sizeof(double) * 3 * N, hipMemcpyDeviceToHost) != hipSuccess))
+        return GBA_ERR_HIP;
+    rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (report) *report = rep;
+    if (n_log) *n_log = nl;
     return GBA_OK;
 }
 

@@ -121,6 +121,22 @@ _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 
+class gba_vi_problem(ctypes.Structure):
+    _fields_ = [("n_kf", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n_pts", ctypes.c_int64), ("n_obs", ctypes.c_int64),
+                ("states", ctypes.c_void_p), ("pts", ctypes.c_void_p), ("kf", ctypes.c_void_p),
+                ("pt", ctypes.c_void_p), ("obs", ctypes.c_void_p), ("intr", ctypes.c_void_p),
+                ("pre", ctypes.c_void_p), ("sigma_px", ctypes.c_double),
+                ("huber_delta2", ctypes.c_double), ("sigma_gw", ctypes.c_double),
+                ("sigma_aw", ctypes.c_double)]
+
+
+class gba_vi_options(ctypes.Structure):
+    _fields_ = [("pcg_max_iters", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("pcg_tol", ctypes.c_double), ("initial_lambda", ctypes.c_double),
+                ("min_diag", ctypes.c_double), ("max_diag", ctypes.c_double)]
+
+
 _SIGS = {
     "gba_default_options": (None, [ctypes.POINTER(gba_options)]),
     "gba_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ALLOC_FN, FREE_FN, _P,
@@ -153,6 +169,11 @@ _SIGS = {
     "gba_vi_eval_inertial": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]),
     "gba_vi_eval_stereo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _D, ctypes.c_int64, _D,
                                           ctypes.c_int64, _P, _P, _D, _D, _D, _D]),
+    "gba_vi_default_options": (None, [ctypes.POINTER(gba_vi_options)]),
+    "gba_vi_solve": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(gba_vi_problem), ctypes.c_int,
+                                    ctypes.c_double, ctypes.POINTER(gba_vi_options),
+                                    ctypes.POINTER(gba_report), _P, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)]),
     "gba_last_error": (ctypes.c_char_p, [_P]),
     "gba_destroy": (None, [_P]),
     "gba_server_default_config": (None, [ctypes.POINTER(gba_server_config)]),
@@ -440,6 +461,44 @@ def gba_vi_eval_stereo(device, states, pts, kf, pt, obs, intr):
                                         k.ctypes.data, q.ctypes.data, _ptr(o), _ptr(it), _ptr(r),
                                         _ptr(J)), "gba_vi_eval_stereo")
     return r, J
+
+
+def vi_options(**kw):
+    o = gba_vi_options()
+    load().gba_vi_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def gba_vi_solve(device, states, pts, kf, pt, obs, intr, pre, max_iters, tol=0.0,
+                 sigma_px=1.0, huber_delta2=0.0, sigma_gw=1e-4, sigma_aw=1e-3, options=None,
+                 max_log=1000):
+    """Visual-inertial LM solve (marshalling only).  Returns (states (K, 15),
+    points (N, 3), report dict, trial log)."""
+    st = np.array(states, np.float64, order="C", copy=True)
+    P = np.array(pts, np.float64, order="C", copy=True).reshape(-1, 3)
+    k = np.ascontiguousarray(kf, np.int64)
+    q = np.ascontiguousarray(pt, np.int64)
+    o = np.ascontiguousarray(obs, np.float64)
+    it = np.ascontiguousarray(intr, np.float64)
+    pr = np.ascontiguousarray(pre, np.float64)
+    prob = gba_vi_problem(n_kf=len(st), n_pts=len(P), n_obs=len(k), states=st.ctypes.data,
+                          pts=P.ctypes.data, kf=k.ctypes.data, pt=q.ctypes.data,
+                          obs=o.ctypes.data, intr=it.ctypes.data, pre=pr.ctypes.data,
+                          sigma_px=sigma_px, huber_delta2=huber_delta2, sigma_gw=sigma_gw,
+                          sigma_aw=sigma_aw)
+    rep = gba_report()
+    buf = (gba_trial * max(1, max_log))()
+    n = ctypes.c_int()
+    _vi_check(load().gba_vi_solve(int(device), ctypes.byref(prob), int(max_iters), float(tol),
+                                  ctypes.byref(options) if options is not None else None,
+                                  ctypes.byref(rep), ctypes.cast(buf, _P), int(max_log),
+                                  ctypes.byref(n)), "gba_vi_solve")
+    log = [dict(cost=t.cost, candidate_cost=t.candidate_cost, lam=t.lambda_,
+                model_decrease=t.model_decrease, step_norm=t.step_norm,
+                accepted=bool(t.accepted), pcg_iters=t.pcg_iters) for t in buf[:n.value]]
+    return st, P, rep.as_dict(), log
 
 
 def gba_last_error(h):
