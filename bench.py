@@ -165,6 +165,57 @@ def serving_measurement(gba, synth, n_req, precision, budget, slots, tune_db, se
     return out
 
 
+def vi_measurement(gba, args):
+    """The visual-inertial configuration: a smooth trajectory with a 200 Hz
+    IMU, 2,000 keyframes 0.25 s apart, 300k points seen within three
+    keyframes of their anchor in a rectified stereo pair (about 2M
+    observations), Huber on the stereo terms (delta^2 = 7.815, the chi^2_3
+    95% point); the IMU preintegrated on the GPU, then LM with full-system
+    PCG (gba_vi_solve, FP64)."""
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+
+    from paper_2509_26581_amd import synth_vi
+    t0 = time.perf_counter()
+    sc = synth_vi.make_vi_scene(seed=0, n_kf=args.vi_kf, n_pts=args.vi_pts, window=3)
+    K = sc.n_kf
+    rng = np.random.default_rng(1)
+    rot = Rotation.from_matrix(sc.R_true)
+    dth = rng.normal(0, 0.01, (K, 3))
+    dth[0] = 0.0
+    R0 = (rot * Rotation.from_rotvec(dth)).as_rotvec()
+    dp = rng.normal(0, 0.05, (K, 3))
+    dv = rng.normal(0, 0.05, (K, 3))
+    dp[0] = dv[0] = 0.0
+    states = np.concatenate([R0, sc.p_true + dp, sc.v_true + dv, sc.bg_true, sc.ba_true], axis=1)
+    pts0 = sc.pts + rng.normal(0, 0.05, sc.pts.shape)
+    print(f"[bench] vi: {K} keyframes, {len(sc.pts)} points, {len(sc.st_kf)} stereo observations "
+          f"(generated in {time.perf_counter() - t0:.1f} s)", flush=True)
+    m = sc.gyro.shape[1]
+    off = np.arange(K, dtype=np.int64) * m
+    bias0 = np.concatenate([sc.bg_true[:-1], sc.ba_true[:-1]], axis=1)
+    t0 = time.perf_counter()
+    pre = gba.gba_vi_preintegrate(0, off, sc.gyro.reshape(-1, 3), sc.acc.reshape(-1, 3),
+                                  sc.imu_dt, bias0, 1.7e-4, 2e-3)
+    pre_s = time.perf_counter() - t0
+    opts = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6)
+    kw = dict(sigma_px=1.0, huber_delta2=7.815, sigma_gw=2e-5, sigma_aw=3e-3, options=opts)
+    trials = args.trials or 10
+    gba.gba_vi_solve(0, states, pts0, sc.st_kf, sc.st_pt, sc.st_obs, sc.intr, pre, 1, **kw)  # warm-up
+    t0 = time.perf_counter()
+    _, _, rep, log = gba.gba_vi_solve(0, states, pts0, sc.st_kf, sc.st_pt, sc.st_obs, sc.intr,
+                                      pre, trials, **kw)
+    el = time.perf_counter() - t0
+    return {"vi": {"workload": f"{K} keyframes (0.25 s apart, 200 Hz IMU), {len(sc.pts)} points, "
+                               f"{len(sc.st_kf)} stereo observations, Huber delta^2 7.815, "
+                               f"{trials} LM trials, PCG tol 1e-6 max 100",
+                   "lm_iter_per_s": round(rep["trials"] / el, 3), "ms_per_trial": round(el / rep["trials"] * 1e3, 2),
+                   "pcg_iters_per_trial": round(rep["pcg_iters_total"] / max(rep["trials"], 1), 2),
+                   "initial_cost": rep["initial_cost"], "final_cost": rep["final_cost"],
+                   "accepted": rep["accepted"], "trials": rep["trials"],
+                   "preintegration_s": round(pre_s, 4), "dtype": "f64"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +251,11 @@ def main():
                     help="gba_options.solver: Schur + PCG on the cameras, or PCG on the full system")
     ap.add_argument("--jacobian", default="analytic", choices=["analytic", "autodiff", "dynamic"],
                     help="gba_options.jacobian")
+    ap.add_argument("--vi", action="store_true",
+                    help="the visual-inertial configuration instead (2,000 keyframes, 300k points, "
+                         "~2M stereo observations; gba_vi_solve, FP64)")
+    ap.add_argument("--vi-kf", type=int, default=2000)
+    ap.add_argument("--vi-pts", type=int, default=300_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path",
@@ -227,6 +283,9 @@ def main():
               f"streaming read of {args.copy_probe_mb} MiB by k_hbm_probe "
               f"({nbytes / us / 1e3:.0f} GB/s, {us:.1f} us)", flush=True)
         del buf, sink
+    if args.vi:
+        print(json.dumps(vi_measurement(gba, args)), flush=True)
+        return
     prec_id, dtype_name, jac_bytes = PRECISIONS[args.precision]
     tune_db = os.path.join(ROOT, "paper_2509_26581_amd", "tune_db.txt")
     tune_db = tune_db if os.path.exists(tune_db) else None
