@@ -17,6 +17,7 @@
 
 #include "gba.h"
 #include "gba_autodiff.h"
+#include "gba_device.h"
 
 namespace gba {
 namespace vi {
@@ -533,11 +534,20 @@ __device__ __forceinline__ void vi_huber(double s, double delta2, double& rho, d
 }
 
 // linearisation of the stereo terms: whitened J and r stored; gradient and
-// diagonal blocks accumulated
+// diagonal blocks accumulated.  The observations are in keyframe order, so a
+// keyframe's terms are summed across the wavefront (SegScan) and added once
+// per segment; the point terms are added per observation.
 __global__ void k_vi_lin_stereo(VIDev d) {
-    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (e >= d.M) return;
+    const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = e0 < d.M;
+    const long long e = valid ? e0 : d.M - 1;
     const int k = d.kf[e], j = d.pt[e];
+    const int l = (int)(threadIdx.x & 63);
+    const int kprev = __shfl_up(k, 1, 64);
+    const bool start = !valid || l == 0 || kprev != k;
+    const SegScan seg(start);
+    int head, end;
+    segment_of(__ballot(start), l, head, end);
     double r[3], J[3][9];
     vi_stereo<true>(d, d.st + (size_t)kSt * k, d.X + 3 * (size_t)j, e, r, J);
     const double s = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * d.inv_sigma * d.inv_sigma;
@@ -548,25 +558,38 @@ __global__ void k_vi_lin_stereo(VIDev d) {
         r[a] *= sc;
         for (int c = 0; c < 9; ++c) J[a][c] = (k == 0 && c < 6) ? 0.0 : J[a][c] * sc;
     }
-    for (int a = 0; a < 3; ++a) {
-        d.rs[3 * e + a] = r[a];
-        for (int c = 0; c < 9; ++c) d.js[27 * e + 9 * a + c] = J[a][c];
-    }
+    if (!valid)
+        for (int a = 0; a < 3; ++a) {
+            r[a] = 0.0;
+            for (int c = 0; c < 9; ++c) J[a][c] = 0.0;
+        }
+    if (valid)
+        for (int a = 0; a < 3; ++a) {
+            d.rs[3 * e + a] = r[a];
+            for (int c = 0; c < 9; ++c) d.js[27 * e + 9 * a + c] = J[a][c];
+        }
+    const bool last = valid && l == end;
     double* bk = d.b + 15 * (size_t)k;
     double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
     for (int c = 0; c < 9; ++c) {
         const double g = J[0][c] * r[0] + J[1][c] * r[1] + J[2][c] * r[2];
-        atomic_add(c < 6 ? bk + c : bp + (c - 6), g);
+        if (c < 6) {
+            const double sg = seg.sum(g);
+            if (last) atomic_add(bk + c, sg);
+        } else if (valid) {
+            atomic_add(bp + (c - 6), g);
+        }
     }
-    if (k != 0)
-        for (int a = 0; a < 6; ++a)
-            for (int c = 0; c < 6; ++c)
-                atomic_add(d.hk + 225 * (size_t)k + 15 * a + c,
-                           J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
-    for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c)
-            atomic_add(d.hp + 9 * (size_t)j + 3 * a + c,
-                       J[0][6 + a] * J[0][6 + c] + J[1][6 + a] * J[1][6 + c] + J[2][6 + a] * J[2][6 + c]);
+    for (int a = 0; a < 6; ++a)
+        for (int c = 0; c < 6; ++c) {
+            const double h = seg.sum(J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
+            if (last && k != 0) atomic_add(d.hk + 225 * (size_t)k + 15 * a + c, h);
+        }
+    if (valid)
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                atomic_add(d.hp + 9 * (size_t)j + 3 * a + c,
+                           J[0][6 + a] * J[0][6 + c] + J[1][6 + a] * J[1][6 + c] + J[2][6 + a] * J[2][6 + c]);
 }
 
 // inertial Jacobians by forward-mode AD, one lane per (term, column), at the
@@ -792,9 +815,17 @@ __global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __re
 
 // q += (stereo part of H) v
 __global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* __restrict__ q) {
-    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (e >= d.M) return;
-    const size_t ok = 15 * (size_t)d.kf[e], op = 15 * (size_t)d.K + 3 * (size_t)d.pt[e];
+    const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = e0 < d.M;
+    const long long e = valid ? e0 : d.M - 1;
+    const int k = d.kf[e];
+    const int l = (int)(threadIdx.x & 63);
+    const int kprev = __shfl_up(k, 1, 64);
+    const bool start = !valid || l == 0 || kprev != k;
+    const SegScan seg(start);
+    int head, end;
+    segment_of(__ballot(start), l, head, end);
+    const size_t ok = 15 * (size_t)k, op = 15 * (size_t)d.K + 3 * (size_t)d.pt[e];
     double in[9];
     for (int c = 0; c < 6; ++c) in[c] = v[ok + c];
     for (int c = 0; c < 3; ++c) in[6 + c] = v[op + c];
@@ -803,11 +834,16 @@ __global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* 
     for (int a = 0; a < 3; ++a) {
         double t = 0.0;
         for (int c = 0; c < 9; ++c) t += J[9 * a + c] * in[c];
-        u[a] = t;
+        u[a] = valid ? t : 0.0;
     }
     for (int c = 0; c < 9; ++c) {
         const double y = J[c] * u[0] + J[9 + c] * u[1] + J[18 + c] * u[2];
-        atomic_add(q + (c < 6 ? ok + c : op + (c - 6)), y);
+        if (c < 6) {
+            const double sy = seg.sum(y);   // the keyframe's sum over its run of the wavefront
+            if (valid && l == end) atomic_add(q + ok + c, sy);
+        } else if (valid) {
+            atomic_add(q + op + (c - 6), y);
+        }
     }
 }
 
@@ -1067,11 +1103,24 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     if (o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) || !(o.initial_lambda > 0.0) ||
         !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag))
         return GBA_ERR_INVALID_ARG;
-    std::vector<int> hkf((size_t)P.n_obs), hpt((size_t)P.n_obs);
-    for (int64_t e = 0; e < P.n_obs; ++e) {
-        if (P.kf[e] < 0 || P.kf[e] >= P.n_kf || P.pt[e] < 0 || P.pt[e] >= P.n_pts) return GBA_ERR_UNKNOWN_ID;
-        hkf[(size_t)e] = (int)P.kf[e];
-        hpt[(size_t)e] = (int)P.pt[e];
+    // observations in keyframe order (a stable counting sort), so that the
+    // keyframe terms of a wavefront sum across it before their atomic add
+    std::vector<int> hkf((size_t)P.n_obs + 1, 0), hpt((size_t)P.n_obs + 1, 0);   // + 1: uploaded with a pad
+    std::vector<double> hobs(3 * (size_t)P.n_obs + 1, 0.0);
+    {
+        std::vector<int64_t> cnt((size_t)P.n_kf + 1, 0);
+        for (int64_t e = 0; e < P.n_obs; ++e) {
+            if (P.kf[e] < 0 || P.kf[e] >= P.n_kf || P.pt[e] < 0 || P.pt[e] >= P.n_pts)
+                return GBA_ERR_UNKNOWN_ID;
+            ++cnt[(size_t)P.kf[e] + 1];
+        }
+        for (int k = 0; k < P.n_kf; ++k) cnt[(size_t)k + 1] += cnt[(size_t)k];
+        for (int64_t e = 0; e < P.n_obs; ++e) {
+            const size_t q = (size_t)cnt[(size_t)P.kf[e]]++;
+            hkf[q] = (int)P.kf[e];
+            hpt[q] = (int)P.pt[e];
+            for (int c = 0; c < 3; ++c) hobs[3 * q + c] = P.obs[3 * e + c];
+        }
     }
     if (hipSetDevice(device) != hipSuccess) return GBA_ERR_HIP;
     const int K = P.n_kf;
@@ -1087,9 +1136,9 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     double* obs = nullptr;
     if (!B.up(&s15, P.states, 15 * (size_t)K) || !B.up(&d.st, (const double*)nullptr, kSt * (size_t)K) ||
         !B.up(&d.st_c, (const double*)nullptr, kSt * (size_t)K) ||
-        !B.up(&d.X, P.pts, 3 * (size_t)N + 1) || !B.up(&d.X_c, (const double*)nullptr, 3 * (size_t)N + 1) ||
+        !B.up(&d.X, P.pts, 3 * (size_t)N) || !B.up(&d.X_c, (const double*)nullptr, 3 * (size_t)N + 1) ||
         !B.up(&dkf, hkf.data(), (size_t)M + 1) || !B.up(&dpt, hpt.data(), (size_t)M + 1) ||
-        !B.up(&obs, P.obs, 3 * (size_t)M + 1) ||
+        !B.up(&obs, hobs.data(), 3 * (size_t)M + 1) ||
         !B.up(&pre, P.pre, (size_t)kPreStride * (K - 1)) ||
         !B.up(&d.info, (const double*)nullptr, 81 * (size_t)(K - 1)) ||
         !B.up(&d.js, (const double*)nullptr, 27 * (size_t)M + 1) ||
