@@ -430,6 +430,7 @@ struct VIDev {
     double* hp;            // [9 N] point diagonal blocks
     double* dg;            // [n] clipped diagonal (damping)
     double* mk;            // [225 K] Cholesky factors of the damped keyframe blocks
+    double* mki;           // [225 K] their inverses (the preconditioner applied)
     double* mp;            // [9 N] inverses of the damped point blocks
     double* scal;          // [8] reductions
     double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
@@ -759,6 +760,22 @@ __global__ void k_vi_precond(VIDev d, double lam, double lo, double hi) {
                 L[15 * i + j] = u / ljj;
             }
         }
+        // the inverse, column by column: L L^T x = e_c
+        double* Mi = d.mki + 225 * (size_t)k;
+        for (int c = 0; c < 15; ++c) {
+            double y[15];
+            for (int i = 0; i < 15; ++i) {
+                double u = i == c ? 1.0 : 0.0;
+                for (int q2 = 0; q2 < i; ++q2) u -= L[15 * i + q2] * y[q2];
+                y[i] = u / L[16 * i];
+            }
+            for (int i = 14; i >= 0; --i) {
+                double u = y[i];
+                for (int q2 = i + 1; q2 < 15; ++q2) u -= L[15 * q2 + i] * y[q2];
+                y[i] = u / L[16 * i];
+            }
+            for (int i = 0; i < 15; ++i) Mi[15 * i + c] = y[i];
+        }
     } else if (t < d.K + d.N) {
         const long long j = t - d.K;
         const double* H = d.hp + 9 * j;
@@ -786,26 +803,20 @@ __global__ void k_vi_precond(VIDev d, double lam, double lo, double hi) {
     }
 }
 
-// z = M^-1 r
+// z = M^-1 r: one lane per keyframe row (the block inverse's row times the
+// keyframe's residual), one per point
 __global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __restrict__ z) {
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t < d.K) {
-        const size_t o = 15 * (size_t)t;
-        const double* L = d.mk + 225 * (size_t)t;
-        double y[15];
-        for (int i = 0; i < 15; ++i) {
-            double u = r[o + i];
-            for (int q = 0; q < i; ++q) u -= L[15 * i + q] * y[q];
-            y[i] = u / L[16 * i];
-        }
-        for (int i = 14; i >= 0; --i) {
-            double u = y[i];
-            for (int q = i + 1; q < 15; ++q) u -= L[15 * q + i] * y[q];
-            y[i] = u / L[16 * i];
-        }
-        for (int i = 0; i < 15; ++i) z[o + i] = y[i];
-    } else if (t < d.K + d.N) {
-        const long long j = t - d.K;
+    if (t < 15LL * d.K) {
+        const long long k = t / 15;
+        const int row = (int)(t % 15);
+        const double* Mi = d.mki + 225 * (size_t)k + 15 * row;
+        const double* rk = r + 15 * (size_t)k;
+        double u = 0.0;
+        for (int c = 0; c < 15; ++c) u += Mi[c] * rk[c];
+        z[t] = u;
+    } else if (t < 15LL * d.K + d.N) {
+        const long long j = t - 15LL * d.K;
         const size_t o = 15 * (size_t)d.K + 3 * j;
         const double* M = d.mp + 9 * j;
         const double a = r[o], b = r[o + 1], c = r[o + 2];
@@ -847,38 +858,37 @@ __global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* 
     }
 }
 
-// q += (inertial and bias parts of H) v
-__global__ void k_vi_prod_inertial(VIDev d, const double* __restrict__ v, double* __restrict__ q) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= d.K - 1) return;
+// q += (inertial and bias parts of H) v: one wavefront per term; lane c < 24
+// holds column c (keyframe i's 15 entries, then keyframe j's first 9)
+__global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double* __restrict__ v,
+                                                          double* __restrict__ q) {
+    const int f = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6);
+    const int l = (int)(threadIdx.x & 63);
+    if (f >= d.K - 1) return;   // whole wavefronts
     const size_t oi = 15 * (size_t)f, oj = 15 * (size_t)(f + 1);
     const double* J = d.ji + (size_t)216 * f;
     const double* O = d.info + 81 * (size_t)f;
+    const bool col = l < 24;
+    const double vc = col ? v[l < 15 ? oi + l : oj + (l - 15)] : 0.0;
+    double jc[9];
+    for (int a = 0; a < 9; ++a) jc[a] = col ? J[24 * a + l] : 0.0;
+    // u = J v (sums over the 24 columns), w = Omega u, y_c = sum_a J[a][c] w[a]
     double u[9];
+    for (int a = 0; a < 9; ++a) u[a] = wave_sum(jc[a] * vc);
+    double y = 0.0;
     for (int a = 0; a < 9; ++a) {
-        double t = 0.0;
-        for (int c = 0; c < 15; ++c) t += J[24 * a + c] * v[oi + c];
-        for (int c = 0; c < 9; ++c) t += J[24 * a + 15 + c] * v[oj + c];
-        u[a] = t;
+        double w = 0.0;
+        for (int b = 0; b < 9; ++b) w += O[9 * a + b] * u[b];
+        y += jc[a] * w;
     }
-    double w[9];
-    for (int a = 0; a < 9; ++a) {
-        double t = 0.0;
-        for (int c = 0; c < 9; ++c) t += O[9 * a + c] * u[c];
-        w[a] = t;
-    }
-    for (int c = 0; c < 24; ++c) {
-        double y = 0.0;
-        for (int a = 0; a < 9; ++a) y += J[24 * a + c] * w[a];
-        atomic_add(q + (c < 15 ? oi + c : oj + (c - 15)), y);
-    }
-    const double dt = d.pre[(size_t)kPreStride * f + kDt];
-    for (int k = 0; k < 6; ++k) {
-        const double wb = (k < 3 ? d.wg : d.wa) / dt;
-        const double vi_k = f != 0 ? v[oi + 9 + k] : 0.0;
-        const double yb = wb * (v[oj + 9 + k] - vi_k);
-        atomic_add(q + oj + 9 + k, yb);
-        if (f != 0) atomic_add(q + oi + 9 + k, -yb);
+    if (col) atomic_add(q + (l < 15 ? oi + l : oj + (l - 15)), y);
+    if (l < 6) {
+        const double dt = d.pre[(size_t)kPreStride * f + kDt];
+        const double wb = (l < 3 ? d.wg : d.wa) / dt;
+        const double vi_k = f != 0 ? v[oi + 9 + l] : 0.0;
+        const double yb = wb * (v[oj + 9 + l] - vi_k);
+        atomic_add(q + oj + 9 + l, yb);
+        if (f != 0) atomic_add(q + oi + 9 + l, -yb);
     }
 }
 
@@ -1147,7 +1157,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&d.ri, (const double*)nullptr, 9 * (size_t)(K - 1)) ||
         !B.up(&d.b, (const double*)nullptr, (size_t)n) || !B.up(&d.hk, (const double*)nullptr, 225 * (size_t)K) ||
         !B.up(&d.hp, (const double*)nullptr, 9 * (size_t)N + 1) || !B.up(&d.dg, (const double*)nullptr, (size_t)n) ||
-        !B.up(&d.mk, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
+        !B.up(&d.mk, (const double*)nullptr, 225 * (size_t)K) ||
+        !B.up(&d.mki, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
         !B.up(&d.scal, (const double*)nullptr, 8) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
         !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
         !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n))
@@ -1204,7 +1215,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     auto product = [&](const double* v, double* out, double lam) {
         hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out);
         if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out);
-        hipLaunchKernelGGL(k_vi_prod_inertial, grid(K - 1), blk, 0, nullptr, d, v, out);
+        hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out);
     };
     auto dot = [&](const double* a, const double* b2, double& out) {
         zero_scal();
@@ -1219,7 +1230,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         iters = 0;
         hipLaunchKernelGGL(k_vi_precond, grid(K + N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag);
         hipLaunchKernelGGL(k_vi_neg, grid(n), blk, 0, nullptr, n, d.b, r, x);
-        hipLaunchKernelGGL(k_vi_apply_m, grid(K + N), blk, 0, nullptr, d, r, z);
+        hipLaunchKernelGGL(k_vi_apply_m, grid(15LL * K + N), blk, 0, nullptr, d, r, z);
         hipLaunchKernelGGL(k_vi_xpby, grid(n), blk, 0, nullptr, n, 0.0, z, pv);
         double rz = 0.0, rr0 = 0.0;
         if (!dot(r, z, rz) || !dot(r, r, rr0)) return false;
@@ -1236,7 +1247,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             double rr = 0.0;
             if (!dot(r, r, rr)) return false;
             if (rr <= thresh) break;
-            hipLaunchKernelGGL(k_vi_apply_m, grid(K + N), blk, 0, nullptr, d, r, z);
+            hipLaunchKernelGGL(k_vi_apply_m, grid(15LL * K + N), blk, 0, nullptr, d, r, z);
             double rz_new = 0.0;
             if (!dot(r, z, rz_new)) return false;
             hipLaunchKernelGGL(k_vi_xpby, grid(n), blk, 0, nullptr, n, rz_new / rz, z, pv);
