@@ -26,6 +26,15 @@ Readings (listed in the design notes):
     the normal equations of the whole system (no point elimination), as in
     the paper's full-system PCG.
 
+The Schur form of the same step (schur_pcg_step) eliminates the points
+(Eq. 5-6 applied to the keyframe / point partition): with the damped
+blocks A (keyframes), B (keyframe-point) and C (points, block diagonal),
+    S = A - B C^-1 B^T,   v = -b_k + B C^-1 b_p,
+PCG on S x_k = v from 0 with the exact 15 x 15 diagonal blocks of S as
+the block-Jacobi preconditioner and the stop rules of oracle.pcg.pcg, then
+x_p = C^-1 (-b_p - B^T x_k).  S carries the keyframe-keyframe blocks of
+the inertial terms and of the points two keyframes share.
+
 The stereo Jacobian is the closed form of the projection chain
 (dXc/dtheta = [Xc]x, dXc/dp = -R^T, dXc/dX = R^T); it is pinned against the
 dual numbers of oracle.imu.  The inertial Jacobian comes from those dual
@@ -34,6 +43,7 @@ numbers.
 import numpy as np
 
 from . import imu
+from . import pcg as _pcg
 
 
 class VIState:
@@ -207,6 +217,33 @@ class VIProblem:
         dx = np.zeros(len(f))
         dx[f] = np.linalg.solve(H + lam * np.diag(d), -lin["b"][f])
         return dx
+
+    def reduced_system(self, lin, lam, min_diag, max_diag):
+        """(S, v, A, B, C, b_k, b_p) of the damped step over the free
+        variables, densely: keyframes 1.. first (15 each), then the points."""
+        f = lin["free"]
+        H = lin["H"][np.ix_(f, f)]
+        Hd = H + lam * np.diag(np.clip(np.diag(H), min_diag, max_diag))
+        b = lin["b"][f]
+        nk = 15 * (self.K - 1)
+        A, B, C = Hd[:nk, :nk], Hd[:nk, nk:], Hd[nk:, nk:]
+        bk, bp = b[:nk], b[nk:]
+        CiBt = np.linalg.solve(C, B.T)               # C^-1 B^T
+        S = A - B @ CiBt
+        v = -bk + CiBt.T @ bp
+        return 0.5 * (S + S.T), v, A, B, C, bk, bp
+
+    def schur_pcg_step(self, lin, lam, min_diag, max_diag, tol, max_iters):
+        """The damped step by PCG on the keyframe Schur complement (relative
+        tolerance, no rejection test), then point back-substitution.
+        Returns (dx over all variables, PCG steps)."""
+        S, v, A, B, C, bk, bp = self.reduced_system(lin, lam, min_diag, max_diag)
+        M = _pcg.block_jacobi(S, 15)
+        xk, steps, _ = _pcg.pcg(S, v, M, tol, True, max_iters)
+        xp = np.linalg.solve(C, -bp - B.T @ xk)
+        dx = np.zeros(len(lin["free"]))
+        dx[lin["free"]] = np.concatenate([xk, xp])
+        return dx, steps
 
     def model_decrease(self, lin, dx):
         Jd = lin["J"] @ dx

@@ -102,3 +102,75 @@ def test_lm_descends_to_the_noise_level():
     # 20 m with an 11 cm baseline), so the points are judged by the median
     assert np.max(np.abs(res.x.p - sc.p_true)) < 0.02
     assert np.median(np.linalg.norm(res.x.X - sc.pts, axis=1)) < 0.05
+
+
+def _schur_setup(seed=10, lam=1e-3):
+    sc = _scene(seed=seed, n_kf=6, n_pts=60)
+    prob = _problem(sc)
+    x = _perturbed(sc, seed=seed + 1)
+    return prob, prob.linearize(x), lam
+
+
+def test_schur_step_converged_equals_the_full_solve():
+    prob, lin, lam = _schur_setup()
+    dx_full = prob.solve(lin, lam, 1e-6, 1e32)
+    dx, steps = prob.schur_pcg_step(lin, lam, 1e-6, 1e32, 0.0, 400)
+    assert steps > 0
+    np.testing.assert_allclose(dx, dx_full, rtol=0, atol=1e-9 * np.max(np.abs(dx_full)))
+
+
+def test_schur_back_substitution_solves_the_point_rows_exactly():
+    # a truncated keyframe step: the point rows of the damped full system
+    # still hold exactly, whatever x_k is
+    prob, lin, lam = _schur_setup(seed=11)
+    dx, _ = prob.schur_pcg_step(lin, lam, 1e-6, 1e32, 0.0, 2)
+    f = lin["free"]
+    H = lin["H"][np.ix_(f, f)]
+    Hd = H + lam * np.diag(np.clip(np.diag(H), 1e-6, 1e32))
+    nk = 15 * (prob.K - 1)
+    res = Hd @ dx[f] + lin["b"][f]
+    assert np.max(np.abs(res[nk:])) <= 1e-9 * np.max(np.abs(lin["b"][f]))
+    assert np.max(np.abs(res[:nk])) > 1e-6 * np.max(np.abs(lin["b"][f]))   # truncated
+
+
+def test_schur_iterates_minimise_the_energy_over_the_preconditioned_krylov_space():
+    # CG's k-th iterate is the Galerkin solution on span{z0, (M S) z0, ...,
+    # (M S)^(k-1) z0}, z0 = M v, M the inverse diagonal blocks of S
+    prob, lin, lam = _schur_setup(seed=12)
+    S, v, A, B, C, bk, bp = prob.reduced_system(lin, lam, 1e-6, 1e32)
+    Minv = np.zeros_like(S)
+    for a in range(0, len(v), 15):
+        Minv[a:a + 15, a:a + 15] = np.linalg.inv(S[a:a + 15, a:a + 15])
+    nk = len(v)
+    for k in (1, 2, 4):
+        dx, steps = prob.schur_pcg_step(lin, lam, 1e-6, 1e32, 0.0, k)
+        assert steps == k
+        xk = dx[lin["free"]][:nk]
+        V = [Minv @ v]
+        for _ in range(k - 1):
+            V.append(Minv @ (S @ V[-1]))
+        Q, _ = np.linalg.qr(np.stack(V, axis=1))
+        y = np.linalg.solve(Q.T @ S @ Q, Q.T @ v)
+        np.testing.assert_allclose(xk, Q @ y, rtol=0, atol=1e-8 * np.max(np.abs(Q @ y)))
+
+
+def test_schur_diagonal_blocks_are_the_per_observation_sums():
+    # each (keyframe, point) pair is observed once in these scenes, so the
+    # diagonal block of S at keyframe k is its damped block minus, over its
+    # observations e of point j, W_e C_j^-1 W_e^T with W_e = J_k^T J_p
+    prob, lin, lam = _schur_setup(seed=13)
+    S, v, A, B, C, bk, bp = prob.reduced_system(lin, lam, 1e-6, 1e32)
+    J = lin["J"]
+    K = prob.K
+    assert len(set(zip(prob.kf.tolist(), prob.pt.tolist()))) == len(prob.kf)
+    for k in range(1, K):
+        blk = A[15 * (k - 1):15 * k, 15 * (k - 1):15 * k].copy()
+        for e in np.flatnonzero(prob.kf == k):
+            j = prob.pt[e]
+            Jk = J[3 * e:3 * e + 3, 15 * k:15 * k + 15]
+            Jp = J[3 * e:3 * e + 3, 15 * K + 3 * j:15 * K + 3 * j + 3]
+            Cj = C[3 * j:3 * j + 3, 3 * j:3 * j + 3]
+            W = Jk.T @ Jp
+            blk -= W @ np.linalg.solve(Cj, W.T)
+        np.testing.assert_allclose(S[15 * (k - 1):15 * k, 15 * (k - 1):15 * k], blk,
+                                   rtol=0, atol=1e-9 * np.max(np.abs(blk)))
