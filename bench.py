@@ -170,8 +170,8 @@ def vi_measurement(gba, args):
     IMU, 2,000 keyframes 0.25 s apart, 300k points seen within three
     keyframes of their anchor in a rectified stereo pair (about 2M
     observations), Huber on the stereo terms (delta^2 = 7.815, the chi^2_3
-    95% point); the IMU preintegrated on the GPU, then LM with full-system
-    PCG (gba_vi_solve, FP64)."""
+    95% point); the IMU preintegrated on the GPU, then LM with PCG on the
+    keyframe Schur complement or on the whole system (gba_vi_solve, FP64)."""
     import numpy as np
     from scipy.spatial.transform import Rotation
 
@@ -198,7 +198,8 @@ def vi_measurement(gba, args):
     pre = gba.gba_vi_preintegrate(0, off, sc.gyro.reshape(-1, 3), sc.acc.reshape(-1, 3),
                                   sc.imu_dt, bias0, 1.7e-4, 2e-3)
     pre_s = time.perf_counter() - t0
-    opts = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6)
+    solver = gba.GBA_SOLVER_SCHUR if args.vi_solver == "schur" else gba.GBA_SOLVER_FULL
+    opts = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6, solver=solver)
     kw = dict(sigma_px=1.0, huber_delta2=7.815, sigma_gw=2e-5, sigma_aw=3e-3, options=opts)
     trials = args.trials or 10
     gba.gba_vi_solve(0, states, pts0, sc.st_kf, sc.st_pt, sc.st_obs, sc.intr, pre, 1, **kw)  # warm-up
@@ -209,6 +210,7 @@ def vi_measurement(gba, args):
     return {"vi": {"workload": f"{K} keyframes (0.25 s apart, 200 Hz IMU), {len(sc.pts)} points, "
                                f"{len(sc.st_kf)} stereo observations, Huber delta^2 7.815, "
                                f"{trials} LM trials, PCG tol 1e-6 max 100",
+                   "solver": args.vi_solver,
                    "lm_iter_per_s": round(rep["trials"] / el, 3), "ms_per_trial": round(el / rep["trials"] * 1e3, 2),
                    "pcg_iters_per_trial": round(rep["pcg_iters_total"] / max(rep["trials"], 1), 2),
                    "initial_cost": rep["initial_cost"], "final_cost": rep["final_cost"],
@@ -256,6 +258,9 @@ def main():
                          "~2M stereo observations; gba_vi_solve, FP64)")
     ap.add_argument("--vi-kf", type=int, default=2000)
     ap.add_argument("--vi-pts", type=int, default=300_000)
+    ap.add_argument("--vi-solver", default="schur", choices=["schur", "full"],
+                    help="visual-inertial step: PCG on the keyframe Schur complement, or on the "
+                         "whole system")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path",

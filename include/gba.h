@@ -568,7 +568,9 @@ typedef struct gba_vi_problem {
 
 typedef struct gba_vi_options {
     int pcg_max_iters;         /* PCG iterations per trial (100)             */
-    int reserved0;
+    int solver;                /* GBA_SOLVER_SCHUR (default): the points
+                                  eliminated, PCG on the keyframe system S;
+                                  GBA_SOLVER_FULL: PCG on the whole system  */
     double pcg_tol;            /* stop at |r| <= pcg_tol |r0| (1e-8)         */
     double initial_lambda;     /* 1e-4                                       */
     double min_diag, max_diag; /* clip of the damping diagonal (1e-6, 1e32)  */
@@ -577,11 +579,18 @@ typedef struct gba_vi_options {
 void gba_vi_default_options(gba_vi_options* out);
 
 /* gba_vi_solve: up to max_iters Levenberg-Marquardt trials on a
- * visual-inertial problem, with the acceptance, damping and stop rules of
- * gba_solve (tol as in gba_termination), in the paper's solver form for it:
- * PCG on the whole damped system over keyframe states and points (no point
- * elimination), block-Jacobi preconditioned (15 x 15 keyframe blocks, 3 x 3
- * point blocks), FP64 throughout.  Host arrays in and out (copied to and from
+ * visual-inertial problem (Background Eq. 8; Sec. V-C), with the acceptance,
+ * damping and stop rules of gba_solve (tol as in gba_termination), FP64
+ * throughout, in one of two forms of the damped step:
+ *   GBA_SOLVER_SCHUR: the point blocks eliminated (Eq. 5-6 on the keyframe /
+ *     point partition), PCG on the keyframe system S (keyframe-keyframe
+ *     blocks from the inertial terms and from the points two keyframes
+ *     share) preconditioned by S's 15 x 15 diagonal blocks (exact when a
+ *     keyframe observes each point at most once), then the point steps by
+ *     back-substitution; the PCG tolerance applies to S's residual;
+ *   GBA_SOLVER_FULL: the paper's form for it, PCG on the whole damped system
+ *     over keyframe states and points, block-Jacobi preconditioned (15 x 15
+ *     keyframe blocks, 3 x 3 point blocks).  Host arrays in and out (copied to and from
  * device memory the call allocates and frees); report and the first max_log
  * trials in log (n_log: their count) may be NULL / 0.  INVALID_ARG for
  * missing arrays, n_kf < 2 or non-positive noise parameters, UNKNOWN_ID for

@@ -433,9 +433,22 @@ struct VIDev {
     double* mki;           // [225 K] their inverses (the preconditioner applied)
     double* mp;            // [9 N] inverses of the damped point blocks
     double* scal;          // [8] reductions
+    // Schur form (null in the full form): W_e = J_k^T J_p (6 x 3) per
+    // observation, in keyframe order (wk) and in point order (wp), each in
+    // tiles of 64 observations with entry c of lane l at (18 tile + c) 64 + l
+    double* wk;
+    double* wp;
+    const int* qkf;        // [M] keyframe of the i-th observation in point order
+    const int* qpt;        // [M] its point
+    const int* pos;        // [M] point-order position of keyframe-order observation e
+    double* sm;            // [36 K] sum over a keyframe's observations of W C^-1 W^T
     double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
     long long n() const { return 15LL * K + 3 * N; }
 };
+
+__device__ __forceinline__ size_t w_at(long long e, int c) {
+    return ((size_t)(e >> 6) * 18 + c) * 64 + (size_t)(e & 63);
+}
 
 __device__ __forceinline__ void atomic_add(double* a, double v) { unsafeAtomicAdd(a, v); }
 
@@ -569,6 +582,15 @@ __global__ void k_vi_lin_stereo(VIDev d) {
             d.rs[3 * e + a] = r[a];
             for (int c = 0; c < 9; ++c) d.js[27 * e + 9 * a + c] = J[a][c];
         }
+    if (valid && d.wk) {
+        const long long ep = d.pos[e];
+        for (int a = 0; a < 6; ++a)
+            for (int c = 0; c < 3; ++c) {
+                const double w = J[0][a] * J[0][6 + c] + J[1][a] * J[1][6 + c] + J[2][a] * J[2][6 + c];
+                d.wk[w_at(e, 3 * a + c)] = w;
+                d.wp[w_at(ep, 3 * a + c)] = w;
+            }
+    }
     const bool last = valid && l == end;
     double* bk = d.b + 15 * (size_t)k;
     double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
@@ -737,9 +759,12 @@ __global__ void k_vi_cost(VIDev d, const double* __restrict__ st, const double* 
 // damped block-Jacobi preconditioner: D = clip(diag H); keyframe blocks
 // H + lambda diag(D) factored (Cholesky, in place into mk), point blocks
 // inverted; one lane per block
-__global__ void k_vi_precond(VIDev d, double lam, double lo, double hi) {
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t < d.K) {
+// parts: 1 the point blocks, 2 the keyframe blocks, 3 both.  In the Schur
+// form the keyframe blocks are those of S: the pose block less sm.
+__global__ void k_vi_precond(VIDev d, double lam, double lo, double hi, int parts) {
+    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (!(parts & 2)) t += d.K;
+    if (t < d.K && (parts & 2)) {
         const int k = (int)t;
         const double* H = d.hk + 225 * (size_t)k;
         double* L = d.mk + 225 * (size_t)k;
@@ -749,6 +774,9 @@ __global__ void k_vi_precond(VIDev d, double lam, double lo, double hi) {
         }
         for (int i = 0; i < 225; ++i) L[i] = H[i];
         for (int i = 0; i < 15; ++i) L[16 * i] += lam * d.dg[15 * (size_t)k + i];
+        if (d.sm)
+            for (int a = 0; a < 6; ++a)
+                for (int c = 0; c < 6; ++c) L[15 * a + c] -= d.sm[36 * (size_t)k + 6 * a + c];
         for (int j = 0; j < 15; ++j) {
             double s = L[16 * j];
             for (int q = 0; q < j; ++q) s -= L[15 * j + q] * L[15 * j + q];
@@ -776,7 +804,7 @@ __global__ void k_vi_precond(VIDev d, double lam, double lo, double hi) {
             }
             for (int i = 0; i < 15; ++i) Mi[15 * i + c] = y[i];
         }
-    } else if (t < d.K + d.N) {
+    } else if (t >= d.K && t < d.K + d.N && (parts & 1)) {
         const long long j = t - d.K;
         const double* H = d.hp + 9 * j;
         double A[3][3];
@@ -889,6 +917,171 @@ __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double*
         const double yb = wb * (v[oj + 9 + l] - vi_k);
         atomic_add(q + oj + 9 + l, yb);
         if (f != 0) atomic_add(q + oi + 9 + l, -yb);
+    }
+}
+
+// ---- Schur form: the points eliminated (Eq. 5-6 on the keyframe / point
+// partition).  With the damped blocks A (keyframes), B (keyframe-point,
+// B_kj = W_e for the observation e of point j in keyframe k) and C (points):
+//   S p = A p - B C^-1 B^T p,  v = -b_k + B C^-1 b_p,
+//   x_p = C^-1 (-b_p - B^T x_k).
+// A p is the keyframe diagonal blocks (hk + lambda D) plus the inertial and
+// bias cross terms between consecutive keyframes.
+
+// z_j = sign C_j^-1 (sum_{e of j} W_e^T v_k(e) + add_j): observations in
+// point order, a point's sum across its run of the wavefront; a point whose
+// observations all sit in one wavefront is stored, one split across
+// wavefronts is added in parts (z is zero beforehand), add_j once
+__global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const double* __restrict__ add,
+                               double sign, double* __restrict__ z) {
+    const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = i0 < d.M;
+    const long long i = valid ? i0 : d.M - 1;
+    const int j = d.qpt[i], k = d.qkf[i];
+    const int l = (int)(threadIdx.x & 63);
+    const int jprev = __shfl_up(j, 1, 64);
+    const bool start = !valid || l == 0 || jprev != j;
+    const SegScan seg(start);
+    int head, end;
+    segment_of(__ballot(start), l, head, end);
+    // the point's first and last observations in the whole order
+    const bool first = i == 0 || d.qpt[i - 1] != j;
+    const bool last = i == d.M - 1 || d.qpt[i + 1] != j;
+    const bool whole_head = __shfl(first ? 1 : 0, head, 64) != 0;
+    const double* vk = v + 15 * (size_t)k;
+    double t[3];
+    for (int c = 0; c < 3; ++c) {
+        double u = 0.0;
+        for (int a = 0; a < 6; ++a) u += d.wp[w_at(i, 3 * a + c)] * vk[a];
+        t[c] = seg.sum(valid ? u : 0.0);
+    }
+    if (!valid || l != end) return;
+    if (add && whole_head)
+        for (int c = 0; c < 3; ++c) t[c] += add[3 * (size_t)j + c];
+    const double* Mi = d.mp + 9 * (size_t)j;
+    double o[3];
+    for (int a = 0; a < 3; ++a) o[a] = sign * (Mi[3 * a] * t[0] + Mi[3 * a + 1] * t[1] + Mi[3 * a + 2] * t[2]);
+    if (whole_head && last) {
+        for (int a = 0; a < 3; ++a) z[3 * (size_t)j + a] = o[a];
+    } else {
+        for (int a = 0; a < 3; ++a) atomic_add(z + 3 * (size_t)j + a, o[a]);
+    }
+}
+
+// out_j = sign C_j^-1 in_j, one lane per point
+__global__ void k_vi_pt_apply(VIDev d, const double* __restrict__ in, double sign, double* __restrict__ out) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= d.N) return;
+    const double* Mi = d.mp + 9 * j;
+    const double a = in[3 * j], b = in[3 * j + 1], c = in[3 * j + 2];
+    for (int r = 0; r < 3; ++r) out[3 * j + r] = sign * (Mi[3 * r] * a + Mi[3 * r + 1] * b + Mi[3 * r + 2] * c);
+}
+
+// q_k -= sum_{e of k} W_e z_j(e): observations in keyframe order, the
+// keyframe's sum across its run of the wavefront, one atomic add per run
+__global__ void k_vi_schur_kf(VIDev d, const double* __restrict__ z, double* __restrict__ q) {
+    const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = e0 < d.M;
+    const long long e = valid ? e0 : d.M - 1;
+    const int k = d.kf[e], j = d.pt[e];
+    const int l = (int)(threadIdx.x & 63);
+    const int kprev = __shfl_up(k, 1, 64);
+    const bool start = !valid || l == 0 || kprev != k;
+    const SegScan seg(start);
+    int head, end;
+    segment_of(__ballot(start), l, head, end);
+    const double zj[3] = {z[3 * (size_t)j], z[3 * (size_t)j + 1], z[3 * (size_t)j + 2]};
+    double y[6];
+    for (int a = 0; a < 6; ++a) {
+        double u = 0.0;
+        for (int c = 0; c < 3; ++c) u += d.wk[w_at(e, 3 * a + c)] * zj[c];
+        y[a] = seg.sum(valid ? u : 0.0);
+    }
+    if (valid && l == end && k != 0)
+        for (int a = 0; a < 6; ++a) atomic_add(q + 15 * (size_t)k + a, -y[a]);
+}
+
+// sm_k = sum_{e of k} W_e C_j^-1 W_e^T (the pose block's Schur term for the
+// preconditioner: the diagonal block of S when each keyframe sees a point at
+// most once), summed across the keyframe's run of the wavefront
+__global__ void k_vi_schur_blocks(VIDev d) {
+    const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = e0 < d.M;
+    const long long e = valid ? e0 : d.M - 1;
+    const int k = d.kf[e], j = d.pt[e];
+    const int l = (int)(threadIdx.x & 63);
+    const int kprev = __shfl_up(k, 1, 64);
+    const bool start = !valid || l == 0 || kprev != k;
+    const SegScan seg(start);
+    int head, end;
+    segment_of(__ballot(start), l, head, end);
+    const double* Mi = d.mp + 9 * (size_t)j;
+    double W[6][3], G[6][3];
+    for (int a = 0; a < 6; ++a)
+        for (int c = 0; c < 3; ++c) W[a][c] = valid ? d.wk[w_at(e, 3 * a + c)] : 0.0;
+    for (int a = 0; a < 6; ++a)
+        for (int c = 0; c < 3; ++c) G[a][c] = W[a][0] * Mi[c] + W[a][1] * Mi[3 + c] + W[a][2] * Mi[6 + c];
+    const bool out = valid && l == end && k != 0;
+    double* S = d.sm + 36 * (size_t)k;
+    for (int a = 0; a < 6; ++a)
+        for (int c = a; c < 6; ++c) {
+            const double h = seg.sum(G[a][0] * W[c][0] + G[a][1] * W[c][1] + G[a][2] * W[c][2]);
+            if (out) {
+                atomic_add(S + 6 * a + c, h);
+                if (c != a) atomic_add(S + 6 * c + a, h);
+            }
+        }
+}
+
+// q_k = (hk_k + lambda diag(D_k)) v_k: one lane per keyframe row
+__global__ void k_vi_schur_diag(VIDev d, double lam, const double* __restrict__ v, double* __restrict__ q) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= 15LL * d.K) return;
+    const long long k = t / 15;
+    const int row = (int)(t % 15);
+    const double* H = d.hk + 225 * (size_t)k + 15 * row;
+    const double* vk = v + 15 * (size_t)k;
+    double u = lam * d.dg[t] * vk[row];
+    for (int c = 0; c < 15; ++c) u += H[c] * vk[c];
+    q[t] = u;
+}
+
+// q += the inertial and bias cross blocks between keyframes i = f and
+// j = f + 1 applied to v: one wavefront per term, lane c < 15 holds column c
+// of J_i, lanes 15..23 the columns of J_j; y_i = J_i^T Omega J_j v_j and
+// y_j = J_j^T Omega J_i v_i
+__global__ __launch_bounds__(256) void k_vi_schur_inertial(VIDev d, const double* __restrict__ v,
+                                                           double* __restrict__ q) {
+    const int f = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6);
+    const int l = (int)(threadIdx.x & 63);
+    if (f >= d.K - 1) return;   // whole wavefronts
+    const size_t oi = 15 * (size_t)f, oj = 15 * (size_t)(f + 1);
+    const double* J = d.ji + (size_t)216 * f;
+    const double* O = d.info + 81 * (size_t)f;
+    const bool ci = l < 15, cj = l >= 15 && l < 24;
+    const double vc = ci ? v[oi + l] : (cj ? v[oj + (l - 15)] : 0.0);
+    double jc[9];
+    for (int a = 0; a < 9; ++a) jc[a] = (ci || cj) ? J[24 * a + l] : 0.0;
+    double ui[9], uj[9];
+    for (int a = 0; a < 9; ++a) {
+        ui[a] = wave_sum(ci ? jc[a] * vc : 0.0);
+        uj[a] = wave_sum(cj ? jc[a] * vc : 0.0);
+    }
+    double y = 0.0;
+    for (int a = 0; a < 9; ++a) {
+        double w = 0.0;
+        for (int b = 0; b < 9; ++b) w += O[9 * a + b] * (ci ? uj[b] : ui[b]);
+        y += jc[a] * w;
+    }
+    if (ci && f != 0) atomic_add(q + oi + l, y);
+    if (cj) atomic_add(q + oj + (l - 15), y);
+    if (l < 6) {
+        const double dt = d.pre[(size_t)kPreStride * f + kDt];
+        const double wb = (l < 3 ? d.wg : d.wa) / dt;
+        if (f != 0) {
+            atomic_add(q + oj + 9 + l, -wb * v[oi + 9 + l]);
+            atomic_add(q + oi + 9 + l, -wb * v[oj + 9 + l]);
+        }
     }
 }
 
@@ -1086,7 +1279,7 @@ gba_status gba_vi_eval_stereo(int device, int n_kf, const double* states, int64_
 void gba_vi_default_options(gba_vi_options* o) {
     if (!o) return;
     o->pcg_max_iters = 100;
-    o->reserved0 = 0;
+    o->solver = GBA_SOLVER_SCHUR;
     o->pcg_tol = 1e-8;
     o->initial_lambda = 1e-4;
     o->min_diag = 1e-6;
@@ -1111,6 +1304,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     gba_vi_default_options(&o);
     if (opts) o = *opts;
     if (o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) || !(o.initial_lambda > 0.0) ||
+        (o.solver != GBA_SOLVER_SCHUR && o.solver != GBA_SOLVER_FULL) ||
         !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag))
         return GBA_ERR_INVALID_ARG;
     // observations in keyframe order (a stable counting sort), so that the
@@ -1130,6 +1324,24 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             hkf[q] = (int)P.kf[e];
             hpt[q] = (int)P.pt[e];
             for (int c = 0; c < 3; ++c) hobs[3 * q + c] = P.obs[3 * e + c];
+        }
+    }
+    const bool schur = o.solver == GBA_SOLVER_SCHUR;
+    // Schur form: the same observations in point order (a stable counting
+    // sort of the keyframe order), for the point sums of the products
+    std::vector<int> hqkf, hqpt, hpos;
+    if (schur) {
+        hqkf.assign((size_t)P.n_obs + 1, 0);
+        hqpt.assign((size_t)P.n_obs + 1, 0);
+        hpos.assign((size_t)P.n_obs + 1, 0);
+        std::vector<int64_t> cnt((size_t)P.n_pts + 1, 0);
+        for (int64_t e = 0; e < P.n_obs; ++e) ++cnt[(size_t)hpt[e] + 1];
+        for (int64_t j = 0; j < P.n_pts; ++j) cnt[(size_t)j + 1] += cnt[(size_t)j];
+        for (int64_t e = 0; e < P.n_obs; ++e) {
+            const size_t q = (size_t)cnt[(size_t)hpt[e]]++;
+            hqkf[q] = hkf[e];
+            hqpt[q] = hpt[e];
+            hpos[e] = (int)q;
         }
     }
     if (hipSetDevice(device) != hipSuccess) return GBA_ERR_HIP;
@@ -1163,6 +1375,19 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
         !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n))
         return GBA_ERR_OOM;
+    double* zb = nullptr;   // Schur form: the point vector of a product
+    if (schur) {
+        const size_t wn = 18 * 64 * (size_t)((M + 63) / 64) + 1;
+        int *qkf = nullptr, *qpt = nullptr, *pos = nullptr;
+        if (!B.up(&d.wk, (const double*)nullptr, wn) || !B.up(&d.wp, (const double*)nullptr, wn) ||
+            !B.up(&qkf, hqkf.data(), (size_t)M + 1) || !B.up(&qpt, hqpt.data(), (size_t)M + 1) ||
+            !B.up(&pos, hpos.data(), (size_t)M + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
+            !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1))
+            return GBA_ERR_OOM;
+        d.qkf = qkf;
+        d.qpt = qpt;
+        d.pos = pos;
+    }
     d.kf = dkf;
     d.pt = dpt;
     d.obs = obs;
@@ -1211,47 +1436,79 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_acc_inertial, grid(K - 1), blk, 0, nullptr, d);
         return chk();
     };
-    // q = (H + lam diag(D)) v
+    // q = (H + lam diag(D)) v, the whole system
     auto product = [&](const double* v, double* out, double lam) {
         hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out);
         if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out);
         hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out);
     };
-    auto dot = [&](const double* a, const double* b2, double& out) {
+    // q = S v over the keyframes (the point vector through zb)
+    auto schur_product = [&](const double* v, double* out, double lam) {
+        hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, zb);
+        if (M > 0) hipLaunchKernelGGL(k_vi_schur_pts, grid(M), blk, 0, nullptr, d, v, nullptr, 1.0, zb);
+        hipLaunchKernelGGL(k_vi_schur_diag, grid(15LL * K), blk, 0, nullptr, d, lam, v, out);
+        hipLaunchKernelGGL(k_vi_schur_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out);
+        if (M > 0) hipLaunchKernelGGL(k_vi_schur_kf, grid(M), blk, 0, nullptr, d, zb, out);
+    };
+    auto dot = [&](long long len, const double* a, const double* b2, double& out) {
         zero_scal();
-        const long long nb = std::min<long long>(1024, (n + 255) / 256);
-        hipLaunchKernelGGL(k_vi_dot, dim3((unsigned)nb), blk, 0, nullptr, n, a, b2, d.scal);
+        const long long nb = std::min<long long>(1024, (len + 255) / 256);
+        hipLaunchKernelGGL(k_vi_dot, dim3((unsigned)nb), blk, 0, nullptr, len, a, b2, d.scal);
         if (!chk() || !read_scal()) return false;
         out = hs[0];
         return true;
     };
-    // PCG from 0 on (H + lam D) x = -b to |r| <= pcg_tol |r0|
+    // PCG from 0 to |r| <= pcg_tol |r0|: on (H + lam D) x = -b (full form),
+    // or on S x_k = v followed by the point back-substitution (Schur form)
+    const long long nn = schur ? 15LL * K : n;          // PCG unknowns
+    const long long nm = schur ? 15LL * K : 15LL * K + N;   // preconditioner lanes
     auto pcg = [&](double lam, int& iters) {
         iters = 0;
-        hipLaunchKernelGGL(k_vi_precond, grid(K + N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag);
-        hipLaunchKernelGGL(k_vi_neg, grid(n), blk, 0, nullptr, n, d.b, r, x);
-        hipLaunchKernelGGL(k_vi_apply_m, grid(15LL * K + N), blk, 0, nullptr, d, r, z);
-        hipLaunchKernelGGL(k_vi_xpby, grid(n), blk, 0, nullptr, n, 0.0, z, pv);
+        if (schur) {
+            hipLaunchKernelGGL(k_vi_precond, grid(N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 1);
+            hipLaunchKernelGGL(k_vi_fill, grid(36LL * K), blk, 0, nullptr, 36LL * K, d.sm);
+            if (M > 0) hipLaunchKernelGGL(k_vi_schur_blocks, grid(M), blk, 0, nullptr, d);
+            hipLaunchKernelGGL(k_vi_precond, grid(K), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 2);
+            // r = -b_k + B C^-1 b_p
+            hipLaunchKernelGGL(k_vi_pt_apply, grid(N), blk, 0, nullptr, d, d.b + 15 * (size_t)K, -1.0, zb);
+            hipLaunchKernelGGL(k_vi_neg, grid(nn), blk, 0, nullptr, nn, d.b, r, x);
+            if (M > 0) hipLaunchKernelGGL(k_vi_schur_kf, grid(M), blk, 0, nullptr, d, zb, r);
+        } else {
+            hipLaunchKernelGGL(k_vi_precond, grid(K + N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 3);
+            hipLaunchKernelGGL(k_vi_neg, grid(n), blk, 0, nullptr, n, d.b, r, x);
+        }
+        hipLaunchKernelGGL(k_vi_apply_m, grid(nm), blk, 0, nullptr, d, r, z);
+        hipLaunchKernelGGL(k_vi_xpby, grid(nn), blk, 0, nullptr, nn, 0.0, z, pv);
         double rz = 0.0, rr0 = 0.0;
-        if (!dot(r, z, rz) || !dot(r, r, rr0)) return false;
+        if (!dot(nn, r, z, rz) || !dot(nn, r, r, rr0)) return false;
         const double thresh = o.pcg_tol * o.pcg_tol * rr0;
-        if (!(rr0 > thresh) || !(rz > 0.0)) return true;
-        for (int it = 0; it < o.pcg_max_iters; ++it) {
-            product(pv, q, lam);
-            double pq = 0.0;
-            if (!dot(pv, q, pq)) return false;
-            if (!(pq > 0.0)) break;
-            const double alpha = rz / pq;
-            hipLaunchKernelGGL(k_vi_axpy2, grid(n), blk, 0, nullptr, n, alpha, pv, q, x, r);
-            iters = it + 1;
-            double rr = 0.0;
-            if (!dot(r, r, rr)) return false;
-            if (rr <= thresh) break;
-            hipLaunchKernelGGL(k_vi_apply_m, grid(15LL * K + N), blk, 0, nullptr, d, r, z);
-            double rz_new = 0.0;
-            if (!dot(r, z, rz_new)) return false;
-            hipLaunchKernelGGL(k_vi_xpby, grid(n), blk, 0, nullptr, n, rz_new / rz, z, pv);
-            rz = rz_new;
+        if (rr0 > thresh && rz > 0.0) {
+            for (int it = 0; it < o.pcg_max_iters; ++it) {
+                if (schur) schur_product(pv, q, lam);
+                else product(pv, q, lam);
+                double pq = 0.0;
+                if (!dot(nn, pv, q, pq)) return false;
+                if (!(pq > 0.0)) break;
+                const double alpha = rz / pq;
+                hipLaunchKernelGGL(k_vi_axpy2, grid(nn), blk, 0, nullptr, nn, alpha, pv, q, x, r);
+                iters = it + 1;
+                double rr = 0.0;
+                if (!dot(nn, r, r, rr)) return false;
+                if (rr <= thresh) break;
+                hipLaunchKernelGGL(k_vi_apply_m, grid(nm), blk, 0, nullptr, d, r, z);
+                double rz_new = 0.0;
+                if (!dot(nn, r, z, rz_new)) return false;
+                hipLaunchKernelGGL(k_vi_xpby, grid(nn), blk, 0, nullptr, nn, rz_new / rz, z, pv);
+                rz = rz_new;
+            }
+        }
+        if (schur) {
+            // x_p = -C^-1 (b_p + B^T x_k)
+            double* xp = x + 15 * (size_t)K;
+            hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, xp);
+            if (M > 0)
+                hipLaunchKernelGGL(k_vi_schur_pts, grid(M), blk, 0, nullptr, d, x, d.b + 15 * (size_t)K,
+                                   -1.0, xp);
         }
         return chk();
     };
@@ -1273,7 +1530,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             // model decrease -(b.dx + 1/2 dx^T H dx) with the undamped H
             product(x, q, 0.0);
             double bdx = 0.0, dHd = 0.0, dd = 0.0;
-            if (!chk() || !dot(d.b, x, bdx) || !dot(x, q, dHd) || !dot(x, x, dd)) return GBA_ERR_HIP;
+            if (!chk() || !dot(n, d.b, x, bdx) || !dot(n, x, q, dHd) || !dot(n, x, x, dd)) return GBA_ERR_HIP;
             const double L = -(bdx + 0.5 * dHd);
             hipLaunchKernelGGL(k_vi_step, grid(K + N), blk, 0, nullptr, d, x);
             double Fn = 0.0, xnorm = 0.0, dummy = 0.0;

@@ -132,7 +132,7 @@ class gba_vi_problem(ctypes.Structure):
 
 
 class gba_vi_options(ctypes.Structure):
-    _fields_ = [("pcg_max_iters", ctypes.c_int), ("reserved0", ctypes.c_int),
+    _fields_ = [("pcg_max_iters", ctypes.c_int), ("solver", ctypes.c_int),
                 ("pcg_tol", ctypes.c_double), ("initial_lambda", ctypes.c_double),
                 ("min_diag", ctypes.c_double), ("max_diag", ctypes.c_double)]
 

@@ -1,8 +1,11 @@
-"""The visual-inertial LM solve on the GPU (gba_vi_solve: PCG on the whole
-damped system over keyframe states and points) against the oracle's LM with
-exact dense solves (oracle/vi.py): per-trial costs, damping and decisions,
-the final cost and the final states and points.  The GPU path preintegrates
-its own IMU intervals (gba_vi_preintegrate); the oracle uses its own."""
+"""The visual-inertial LM solve on the GPU (gba_vi_solve, in both forms of
+the damped step: PCG on the keyframe Schur complement with point
+back-substitution, and PCG on the whole damped system over keyframe states
+and points) against the oracle's LM with exact dense solves (oracle/vi.py):
+per-trial costs, damping and decisions, the final cost and the final states
+and points; and the truncated Schur-form steps against the oracle's Schur
+PCG.  The GPU path preintegrates its own IMU intervals
+(gba_vi_preintegrate); the oracle uses its own."""
 import numpy as np
 import pytest
 
@@ -53,11 +56,13 @@ def _gpu(sc, states, x0, pre_g, trials, delta2, **opt):
                             options=o)
 
 
+@pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
 @pytest.mark.parametrize("delta2", [0.0, 7.815])
-def test_vi_lm_trajectory_matches_the_oracle(delta2):
+def test_vi_lm_trajectory_matches_the_oracle(delta2, solver):
     sc, prob, x0, states, pre_g = _setup(seed=8, n_kf=8, n_pts=100, delta2=delta2)
     res = lm.levenberg_marquardt(prob, x0, 8)
-    st, X, rep, log = _gpu(sc, states, x0, pre_g, 8, delta2, pcg_tol=1e-12, pcg_max_iters=4000)
+    st, X, rep, log = _gpu(sc, states, x0, pre_g, 8, delta2, pcg_tol=1e-12, pcg_max_iters=4000,
+                           solver=solver)
     assert len(log) == len(res.log)
     assert abs(rep["initial_cost"] - res.initial_cost) <= 1e-9 * res.initial_cost
     for a, b in zip(log, res.log):
@@ -81,10 +86,33 @@ def test_vi_lm_trajectory_matches_the_oracle(delta2):
     np.testing.assert_allclose(st[0, 0:3], states[0, 0:3], rtol=0, atol=1e-14)
 
 
-def test_vi_truncated_pcg_still_descends():
-    # the paper's form with a loose PCG: every accepted trial lowers the cost
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_vi_truncated_schur_step_matches_the_oracle(k):
+    # k PCG steps on S from the first linearisation: the candidate cost, the
+    # model decrease and the step norm of the GPU's step against the oracle's
+    # Schur PCG step (same preconditioner, same stop rules)
+    # (with one more point that no keyframe observes: its step is zero)
+    sc, prob, x0, states, pre_g = _setup(seed=5, n_kf=9, n_pts=120, delta2=7.815)
+    x0 = vi.VIState(x0.R, x0.p, x0.v, x0.bg, x0.ba, np.vstack([x0.X, [[0.5, -0.2, 7.0]]]))
+    st, X, rep, log = _gpu(sc, states, x0, pre_g, 1, 7.815, pcg_tol=0.0, pcg_max_iters=k,
+                           solver=gba.GBA_SOLVER_SCHUR)
+    lin = prob.linearize(x0)
+    dx, steps = prob.schur_pcg_step(lin, 1e-4, 1e-6, 1e32, 0.0, k)
+    assert log[0]["pcg_iters"] == steps == k
+    F1 = prob.cost(prob.step(x0, dx))
+    L = prob.model_decrease(lin, dx)
+    t = log[0]
+    assert abs(t["candidate_cost"] - F1) <= 1e-9 * F1, (t, F1)
+    assert abs(t["model_decrease"] - L) <= 1e-8 * abs(L), (t, L)
+    assert abs(t["step_norm"] - np.linalg.norm(dx)) <= 1e-8 * np.linalg.norm(dx)
+
+
+@pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
+def test_vi_truncated_pcg_still_descends(solver):
+    # a loose PCG: every accepted trial lowers the cost
     sc, prob, x0, states, pre_g = _setup(seed=3, n_kf=10, n_pts=150, delta2=7.815)
-    st, X, rep, log = _gpu(sc, states, x0, pre_g, 10, 7.815, pcg_tol=1e-3, pcg_max_iters=30)
+    st, X, rep, log = _gpu(sc, states, x0, pre_g, 10, 7.815, pcg_tol=1e-3, pcg_max_iters=30,
+                           solver=solver)
     costs = [t["cost"] for t in log] + [rep["final_cost"]]
     assert all(b <= a for a, b in zip(costs, costs[1:]))
     assert rep["final_cost"] < 0.2 * rep["initial_cost"]
@@ -106,3 +134,6 @@ def test_vi_solve_errors():
         gba.gba_vi_solve(0, states, x0.X, sc.st_kf, sc.st_pt, sc.st_obs, sc.intr, pre_g, 3,
                          sigma_px=0.0)
     assert e.value.status == -1
+    with pytest.raises(gba.GbaError) as e:
+        _gpu(sc, states, x0, pre_g, 3, 0.0, solver=7)
+    assert e.value.status == -1                      # unknown solver form
