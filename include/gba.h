@@ -574,6 +574,12 @@ typedef struct gba_vi_options {
     double pcg_tol;            /* stop at |r| <= pcg_tol |r0| (1e-8)         */
     double initial_lambda;     /* 1e-4                                       */
     double min_diag, max_diag; /* clip of the damping diagonal (1e-6, 1e32)  */
+    int precision;             /* GBA_FP64 (default), or GBA_MIXED_FP32 (the
+                                  Schur form only): the per-observation
+                                  blocks W = J_k^T J_p that the PCG products
+                                  stream stored in FP32, all arithmetic and
+                                  every other array FP64                     */
+    int reserved1;
 } gba_vi_options;
 
 void gba_vi_default_options(gba_vi_options* out);
@@ -581,7 +587,7 @@ void gba_vi_default_options(gba_vi_options* out);
 /* gba_vi_solve: up to max_iters Levenberg-Marquardt trials on a
  * visual-inertial problem (Background Eq. 8; Sec. V-C), with the acceptance,
  * damping and stop rules of gba_solve (tol as in gba_termination), FP64
- * throughout, in one of two forms of the damped step:
+ * arithmetic (precision below), in one of two forms of the damped step:
  *   GBA_SOLVER_SCHUR: the point blocks eliminated (Eq. 5-6 on the keyframe /
  *     point partition), PCG on the keyframe system S (keyframe-keyframe
  *     blocks from the inertial terms and from the points two keyframes
@@ -591,9 +597,13 @@ void gba_vi_default_options(gba_vi_options* out);
  *   GBA_SOLVER_FULL: the paper's form for it, PCG on the whole damped system
  *     over keyframe states and points, block-Jacobi preconditioned (15 x 15
  *     keyframe blocks, 3 x 3 point blocks).  Host arrays in and out (copied to and from
- * device memory the call allocates and frees); report and the first max_log
+ * device memory the call allocates and frees; report.ms_other is that set-up
+ * (orderings, allocation, uploads), report.ms_total - ms_other the LM
+ * trials and the download, workspace_bytes the device bytes); report and the
+ * first max_log
  * trials in log (n_log: their count) may be NULL / 0.  INVALID_ARG for
- * missing arrays, n_kf < 2 or non-positive noise parameters, UNKNOWN_ID for
+ * missing arrays, n_kf < 2, non-positive noise parameters, an unknown solver
+ * form or precision, or GBA_MIXED_FP32 with GBA_SOLVER_FULL, UNKNOWN_ID for
  * an index out of range, OOM when device memory runs out. */
 gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, double tol,
                         const gba_vi_options* opts, gba_report* report, gba_trial* log,

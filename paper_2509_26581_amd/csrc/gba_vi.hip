@@ -436,15 +436,28 @@ struct VIDev {
     // Schur form (null in the full form): W_e = J_k^T J_p (6 x 3) per
     // observation, in keyframe order (wk) and in point order (wp), each in
     // tiles of 64 observations with entry c of lane l at (18 tile + c) 64 + l
-    double* wk;
-    double* wp;
+    void* wk;              // double, or float when w32
+    void* wp;
+    int w32;
     const int* qkf;        // [M] keyframe of the i-th observation in point order
     const int* qpt;        // [M] its point
     const int* pos;        // [M] point-order position of keyframe-order observation e
     double* sm;            // [36 K] sum over a keyframe's observations of W C^-1 W^T
+    double* icx;           // [135 (K - 1)] inertial cross blocks J_i^T Omega J_j (15 x 9)
     double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
     long long n() const { return 15LL * K + 3 * N; }
 };
+
+// PCG scalars on the device: three slots of dot accumulators {p.q, r.r,
+// r.z}, used round robin (step s accumulates into slot s % 3, takes the
+// previous r.z from slot (s + 2) % 3 and clears slot (s + 1) % 3 for the
+// next step, so no kernel reads a value another workgroup of it resets),
+// then the stop threshold, the stop flag and the step count
+enum { kAccPq = 0, kAccRr, kAccRz, kAccN };
+constexpr int kSlots = 3;
+enum { kThr = kSlots * kAccN, kDone, kSteps, kPcgScalars };
+
+__device__ __forceinline__ bool pcg_done(const double* ps) { return ps && ps[kDone] != 0.0; }
 
 __device__ __forceinline__ size_t w_at(long long e, int c) {
     return ((size_t)(e >> 6) * 18 + c) * 64 + (size_t)(e & 63);
@@ -587,8 +600,13 @@ __global__ void k_vi_lin_stereo(VIDev d) {
         for (int a = 0; a < 6; ++a)
             for (int c = 0; c < 3; ++c) {
                 const double w = J[0][a] * J[0][6 + c] + J[1][a] * J[1][6 + c] + J[2][a] * J[2][6 + c];
-                d.wk[w_at(e, 3 * a + c)] = w;
-                d.wp[w_at(ep, 3 * a + c)] = w;
+                if (d.w32) {
+                    ((float*)d.wk)[w_at(e, 3 * a + c)] = (float)w;
+                    ((float*)d.wp)[w_at(ep, 3 * a + c)] = (float)w;
+                } else {
+                    ((double*)d.wk)[w_at(e, 3 * a + c)] = w;
+                    ((double*)d.wp)[w_at(ep, 3 * a + c)] = w;
+                }
             }
     }
     const bool last = valid && l == end;
@@ -833,7 +851,9 @@ __global__ void k_vi_precond(VIDev d, double lam, double lo, double hi, int part
 
 // z = M^-1 r: one lane per keyframe row (the block inverse's row times the
 // keyframe's residual), one per point
-__global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __restrict__ z) {
+__global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __restrict__ z,
+                             const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t < 15LL * d.K) {
         const long long k = t / 15;
@@ -853,7 +873,9 @@ __global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __re
 }
 
 // q += (stereo part of H) v
-__global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* __restrict__ q) {
+__global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* __restrict__ q,
+                                 const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool valid = e0 < d.M;
     const long long e = valid ? e0 : d.M - 1;
@@ -889,7 +911,9 @@ __global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* 
 // q += (inertial and bias parts of H) v: one wavefront per term; lane c < 24
 // holds column c (keyframe i's 15 entries, then keyframe j's first 9)
 __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double* __restrict__ v,
-                                                          double* __restrict__ q) {
+                                                          double* __restrict__ q,
+                                                          const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const int f = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6);
     const int l = (int)(threadIdx.x & 63);
     if (f >= d.K - 1) return;   // whole wavefronts
@@ -932,8 +956,10 @@ __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double*
 // point order, a point's sum across its run of the wavefront; a point whose
 // observations all sit in one wavefront is stored, one split across
 // wavefronts is added in parts (z is zero beforehand), add_j once
+template <typename WT>
 __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const double* __restrict__ add,
-                               double sign, double* __restrict__ z) {
+                               double sign, double* __restrict__ z, const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool valid = i0 < d.M;
     const long long i = valid ? i0 : d.M - 1;
@@ -952,7 +978,7 @@ __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const doub
     double t[3];
     for (int c = 0; c < 3; ++c) {
         double u = 0.0;
-        for (int a = 0; a < 6; ++a) u += d.wp[w_at(i, 3 * a + c)] * vk[a];
+        for (int a = 0; a < 6; ++a) u += (double)((const WT*)d.wp)[w_at(i, 3 * a + c)] * vk[a];
         t[c] = seg.sum(valid ? u : 0.0);
     }
     if (!valid || l != end) return;
@@ -979,7 +1005,10 @@ __global__ void k_vi_pt_apply(VIDev d, const double* __restrict__ in, double sig
 
 // q_k -= sum_{e of k} W_e z_j(e): observations in keyframe order, the
 // keyframe's sum across its run of the wavefront, one atomic add per run
-__global__ void k_vi_schur_kf(VIDev d, const double* __restrict__ z, double* __restrict__ q) {
+template <typename WT>
+__global__ void k_vi_schur_kf(VIDev d, const double* __restrict__ z, double* __restrict__ q,
+                              const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool valid = e0 < d.M;
     const long long e = valid ? e0 : d.M - 1;
@@ -994,7 +1023,7 @@ __global__ void k_vi_schur_kf(VIDev d, const double* __restrict__ z, double* __r
     double y[6];
     for (int a = 0; a < 6; ++a) {
         double u = 0.0;
-        for (int c = 0; c < 3; ++c) u += d.wk[w_at(e, 3 * a + c)] * zj[c];
+        for (int c = 0; c < 3; ++c) u += (double)((const WT*)d.wk)[w_at(e, 3 * a + c)] * zj[c];
         y[a] = seg.sum(valid ? u : 0.0);
     }
     if (valid && l == end && k != 0)
@@ -1004,6 +1033,7 @@ __global__ void k_vi_schur_kf(VIDev d, const double* __restrict__ z, double* __r
 // sm_k = sum_{e of k} W_e C_j^-1 W_e^T (the pose block's Schur term for the
 // preconditioner: the diagonal block of S when each keyframe sees a point at
 // most once), summed across the keyframe's run of the wavefront
+template <typename WT>
 __global__ void k_vi_schur_blocks(VIDev d) {
     const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool valid = e0 < d.M;
@@ -1018,7 +1048,7 @@ __global__ void k_vi_schur_blocks(VIDev d) {
     const double* Mi = d.mp + 9 * (size_t)j;
     double W[6][3], G[6][3];
     for (int a = 0; a < 6; ++a)
-        for (int c = 0; c < 3; ++c) W[a][c] = valid ? d.wk[w_at(e, 3 * a + c)] : 0.0;
+        for (int c = 0; c < 3; ++c) W[a][c] = valid ? (double)((const WT*)d.wk)[w_at(e, 3 * a + c)] : 0.0;
     for (int a = 0; a < 6; ++a)
         for (int c = 0; c < 3; ++c) G[a][c] = W[a][0] * Mi[c] + W[a][1] * Mi[3 + c] + W[a][2] * Mi[6 + c];
     const bool out = valid && l == end && k != 0;
@@ -1033,8 +1063,31 @@ __global__ void k_vi_schur_blocks(VIDev d) {
         }
 }
 
-// q_k = (hk_k + lambda diag(D_k)) v_k: one lane per keyframe row
-__global__ void k_vi_schur_diag(VIDev d, double lam, const double* __restrict__ v, double* __restrict__ q) {
+// the inertial cross blocks of the damped system, once per linearisation:
+// icx_f = J_i^T Omega J_j over keyframe i's 15 columns and keyframe j's first
+// 9 (one lane per entry)
+__global__ void k_vi_cross(VIDev d) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= 135LL * (d.K - 1)) return;
+    const long long f = t / 135;
+    const int a = (int)(t % 135) / 9, c = (int)(t % 9);
+    const double* J = d.ji + (size_t)216 * f;
+    const double* O = d.info + 81 * (size_t)f;
+    double u = 0.0;
+    for (int m = 0; m < 9; ++m) {
+        double w = 0.0;
+        for (int k = 0; k < 9; ++k) w += O[9 * m + k] * J[24 * k + 15 + c];
+        u += J[24 * m + a] * w;
+    }
+    d.icx[t] = u;
+}
+
+// q_k = A_k v: (hk_k + lambda diag(D_k)) v_k plus the cross blocks to
+// keyframes k - 1 and k + 1 (inertial, and the bias random walk's -Omega_b);
+// one lane per keyframe row, no atomics
+__global__ void k_vi_schur_ap(VIDev d, double lam, const double* __restrict__ v, double* __restrict__ q,
+                              const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (t >= 15LL * d.K) return;
     const long long k = t / 15;
@@ -1043,57 +1096,160 @@ __global__ void k_vi_schur_diag(VIDev d, double lam, const double* __restrict__ 
     const double* vk = v + 15 * (size_t)k;
     double u = lam * d.dg[t] * vk[row];
     for (int c = 0; c < 15; ++c) u += H[c] * vk[c];
-    q[t] = u;
-}
-
-// q += the inertial and bias cross blocks between keyframes i = f and
-// j = f + 1 applied to v: one wavefront per term, lane c < 15 holds column c
-// of J_i, lanes 15..23 the columns of J_j; y_i = J_i^T Omega J_j v_j and
-// y_j = J_j^T Omega J_i v_i
-__global__ __launch_bounds__(256) void k_vi_schur_inertial(VIDev d, const double* __restrict__ v,
-                                                           double* __restrict__ q) {
-    const int f = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6);
-    const int l = (int)(threadIdx.x & 63);
-    if (f >= d.K - 1) return;   // whole wavefronts
-    const size_t oi = 15 * (size_t)f, oj = 15 * (size_t)(f + 1);
-    const double* J = d.ji + (size_t)216 * f;
-    const double* O = d.info + 81 * (size_t)f;
-    const bool ci = l < 15, cj = l >= 15 && l < 24;
-    const double vc = ci ? v[oi + l] : (cj ? v[oj + (l - 15)] : 0.0);
-    double jc[9];
-    for (int a = 0; a < 9; ++a) jc[a] = (ci || cj) ? J[24 * a + l] : 0.0;
-    double ui[9], uj[9];
-    for (int a = 0; a < 9; ++a) {
-        ui[a] = wave_sum(ci ? jc[a] * vc : 0.0);
-        uj[a] = wave_sum(cj ? jc[a] * vc : 0.0);
-    }
-    double y = 0.0;
-    for (int a = 0; a < 9; ++a) {
-        double w = 0.0;
-        for (int b = 0; b < 9; ++b) w += O[9 * a + b] * (ci ? uj[b] : ui[b]);
-        y += jc[a] * w;
-    }
-    if (ci && f != 0) atomic_add(q + oi + l, y);
-    if (cj) atomic_add(q + oj + (l - 15), y);
-    if (l < 6) {
-        const double dt = d.pre[(size_t)kPreStride * f + kDt];
-        const double wb = (l < 3 ? d.wg : d.wa) / dt;
-        if (f != 0) {
-            atomic_add(q + oj + 9 + l, -wb * v[oi + 9 + l]);
-            atomic_add(q + oi + 9 + l, -wb * v[oj + 9 + l]);
+    if (k + 1 < d.K) {   // keyframe k as i of the term k: row of icx_k
+        const double* C = d.icx + 135 * (size_t)k + 9 * row;
+        const double* vj = v + 15 * (size_t)(k + 1);
+        for (int c = 0; c < 9; ++c) u += C[c] * vj[c];
+        if (row >= 9 && k != 0) {
+            const double dt = d.pre[(size_t)kPreStride * k + kDt];
+            u -= ((row < 12 ? d.wg : d.wa) / dt) * vj[row];
         }
     }
+    if (k > 0) {         // keyframe k as j of the term k - 1: column of icx_{k-1}
+        const double* vi = v + 15 * (size_t)(k - 1);
+        if (row < 9) {
+            const double* C = d.icx + 135 * (size_t)(k - 1) + row;
+            for (int c = 0; c < 15; ++c) u += C[9 * c] * vi[c];
+        } else if (k - 1 != 0) {
+            const double dt = d.pre[(size_t)kPreStride * (k - 1) + kDt];
+            u -= ((row < 12 ? d.wg : d.wa) / dt) * vi[row];
+        }
+    }
+    q[t] = u;
 }
 
 // q = lambda diag(D) v (the first term of the product; the others add)
 __global__ void k_vi_prod_damp(long long n, double lam, const double* __restrict__ dg,
-                               const double* __restrict__ v, double* __restrict__ q) {
+                               const double* __restrict__ v, double* __restrict__ q,
+                               const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i < n) q[i] = lam * dg[i] * v[i];
 }
 
+// r.r and r.z into the accumulators acc (the start of the PCG)
+__global__ void k_vi_dot2(long long n, const double* __restrict__ r, const double* __restrict__ z,
+                          double* __restrict__ acc) {
+    __shared__ double red[16];
+    double a = 0.0, b = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        a += r[i] * r[i];
+        b += r[i] * z[i];
+    }
+    a = block_sum_vi(a, red);
+    __syncthreads();
+    b = block_sum_vi(b, red);
+    if (threadIdx.x == 0) {
+        atomic_add(acc + kAccRr, a);
+        atomic_add(acc + kAccRz, b);
+    }
+}
+
+// the start: threshold tol^2 r0.r0 (r0.r0 and r0.z0 in the last slot);
+// nothing to do when r0 is already below it or r0.z0 <= 0
+__global__ void k_vi_pcg_init(double* __restrict__ ps, double tol) {
+    const double* a = ps + kAccN * (kSlots - 1);
+    const double thr = tol * tol * a[kAccRr];
+    ps[kThr] = thr;
+    ps[kDone] = (a[kAccRr] > thr && a[kAccRz] > 0.0) ? 0.0 : 1.0;
+    ps[kSteps] = 0.0;
+}
+
+// step `slot`: alpha = r.z / p.q (a step with p.q <= 0 ends the iteration at
+// the current iterate), x += alpha p, r -= alpha q, z = M^-1 r and the new
+// r.r, r.z.  Keyframe rows: 16 lanes per keyframe (15 used), the residual
+// block through LDS for the 15 x 15 inverse; point rows (the whole-system
+// form): one lane per point after the keyframe workgroups.
+__global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, double* __restrict__ ps,
+                                                      int slot, const double* __restrict__ p,
+                                                      const double* __restrict__ q, double* __restrict__ x,
+                                                      double* __restrict__ r, double* __restrict__ z) {
+    __shared__ double rs[256];
+    __shared__ double red[16];
+    if (ps[kDone] != 0.0) return;
+    double* acc = ps + kAccN * slot;
+    const double pq = acc[kAccPq];
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ps[kDone] = 1.0;
+        return;
+    }
+    const double alpha = ps[kAccN * ((slot + kSlots - 1) % kSlots) + kAccRz] / pq;
+    const long long kf_blocks = (d.K + 15) / 16;
+    double rr = 0.0, rz = 0.0;
+    if (blockIdx.x < kf_blocks) {
+        const long long k = blockIdx.x * 16LL + (threadIdx.x >> 4);
+        const int row = (int)(threadIdx.x & 15);
+        const bool act = k < d.K && row < 15;
+        const size_t i = 15 * (size_t)k + row;
+        double rn = 0.0;
+        if (act) {
+            x[i] += alpha * p[i];
+            rn = r[i] - alpha * q[i];
+            r[i] = rn;
+        }
+        rs[threadIdx.x] = rn;
+        __syncthreads();
+        if (act) {
+            const double* Mi = d.mki + 225 * (size_t)k + 15 * row;
+            const double* rk = rs + (threadIdx.x & ~15u);
+            double u = 0.0;
+            for (int c = 0; c < 15; ++c) u += Mi[c] * rk[c];
+            z[i] = u;
+            rr = rn * rn;
+            rz = rn * u;
+        }
+    } else {
+        const long long j = (blockIdx.x - kf_blocks) * 256LL + threadIdx.x;
+        if (j < npt) {
+            const size_t o = 15 * (size_t)d.K + 3 * j;
+            double rn[3];
+            for (int a = 0; a < 3; ++a) {
+                x[o + a] += alpha * p[o + a];
+                rn[a] = r[o + a] - alpha * q[o + a];
+                r[o + a] = rn[a];
+            }
+            const double* M = d.mp + 9 * j;
+            for (int a = 0; a < 3; ++a) {
+                const double u = M[3 * a] * rn[0] + M[3 * a + 1] * rn[1] + M[3 * a + 2] * rn[2];
+                z[o + a] = u;
+                rr += rn[a] * rn[a];
+                rz += rn[a] * u;
+            }
+        }
+    }
+    rr = block_sum_vi(rr, red);
+    __syncthreads();
+    rz = block_sum_vi(rz, red);
+    if (threadIdx.x == 0) {
+        atomic_add(acc + kAccRr, rr);
+        atomic_add(acc + kAccRz, rz);
+        if (blockIdx.x == 0) ps[kSteps] += 1.0;
+    }
+}
+
+// step `slot`, continued: stop once r.r <= the threshold, else p = z + beta p
+// with beta = r.z / previous r.z; zb (the next product's point vector) is
+// cleared and the next slot's accumulators too
+__global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, const double* __restrict__ z,
+                             double* __restrict__ p, double* __restrict__ zb, long long nzb) {
+    if (ps[kDone] != 0.0) return;
+    const double* acc = ps + kAccN * slot;
+    if (acc[kAccRr] <= ps[kThr]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ps[kDone] = 1.0;
+        return;
+    }
+    const double beta = acc[kAccRz] / ps[kAccN * ((slot + kSlots - 1) % kSlots) + kAccRz];
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += st)
+        p[i] = z[i] + beta * p[i];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nzb; i += st) zb[i] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x < kAccN) ps[kAccN * ((slot + 1) % kSlots) + threadIdx.x] = 0.0;
+}
+
 __global__ void k_vi_dot(long long n, const double* __restrict__ a, const double* __restrict__ b,
-                         double* __restrict__ out) {
+                         double* __restrict__ out, const double* __restrict__ ps = nullptr) {
+    if (pcg_done(ps)) return;
     __shared__ double red[16];
     double s = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -1103,20 +1259,10 @@ __global__ void k_vi_dot(long long n, const double* __restrict__ a, const double
     if (threadIdx.x == 0) atomic_add(out, s);
 }
 
-// x += alpha p, r -= alpha q
-__global__ void k_vi_axpy2(long long n, double alpha, const double* __restrict__ p,
-                           const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r) {
+// p = z (the first direction)
+__global__ void k_vi_copy(long long n, const double* __restrict__ z, double* __restrict__ p) {
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) {
-        x[i] += alpha * p[i];
-        r[i] -= alpha * q[i];
-    }
-}
-
-// p = z + beta p
-__global__ void k_vi_xpby(long long n, double beta, const double* __restrict__ z, double* __restrict__ p) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) p[i] = z[i] + beta * p[i];
+    if (i < n) p[i] = z[i];
 }
 
 __global__ void k_vi_neg(long long n, const double* __restrict__ b, double* __restrict__ r,
@@ -1128,7 +1274,8 @@ __global__ void k_vi_neg(long long n, const double* __restrict__ b, double* __re
     }
 }
 
-__global__ void k_vi_fill(long long n, double* __restrict__ a) {
+__global__ void k_vi_fill(long long n, double* __restrict__ a, const double* __restrict__ ps = nullptr) {
+    if (pcg_done(ps)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0.0;
 }
@@ -1184,6 +1331,7 @@ namespace {
 // Device buffers of one call, released on every return path.
 struct DevBufs {
     std::vector<void*> p;
+    size_t bytes = 0;
     ~DevBufs() {
         for (void* q : p) (void)hipFree(q);
     }
@@ -1192,6 +1340,7 @@ struct DevBufs {
         void* q = nullptr;
         if (hipMalloc(&q, n * sizeof(T) + 16) != hipSuccess) return false;
         p.push_back(q);
+        bytes += n * sizeof(T) + 16;
         *dst = (T*)q;
         return !src || hipMemcpy(q, src, n * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
     }
@@ -1280,6 +1429,8 @@ void gba_vi_default_options(gba_vi_options* o) {
     if (!o) return;
     o->pcg_max_iters = 100;
     o->solver = GBA_SOLVER_SCHUR;
+    o->precision = GBA_FP64;
+    o->reserved1 = 0;
     o->pcg_tol = 1e-8;
     o->initial_lambda = 1e-4;
     o->min_diag = 1e-6;
@@ -1305,6 +1456,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     if (opts) o = *opts;
     if (o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) || !(o.initial_lambda > 0.0) ||
         (o.solver != GBA_SOLVER_SCHUR && o.solver != GBA_SOLVER_FULL) ||
+        (o.precision != GBA_FP64 && o.precision != GBA_MIXED_FP32) ||
+        (o.precision == GBA_MIXED_FP32 && o.solver != GBA_SOLVER_SCHUR) ||
         !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag))
         return GBA_ERR_INVALID_ARG;
     // observations in keyframe order (a stable counting sort), so that the
@@ -1371,15 +1524,19 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&d.hp, (const double*)nullptr, 9 * (size_t)N + 1) || !B.up(&d.dg, (const double*)nullptr, (size_t)n) ||
         !B.up(&d.mk, (const double*)nullptr, 225 * (size_t)K) ||
         !B.up(&d.mki, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
-        !B.up(&d.scal, (const double*)nullptr, 8) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
+        !B.up(&d.scal, (const double*)nullptr, 8 + kPcgScalars) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
         !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
         !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n))
         return GBA_ERR_OOM;
     double* zb = nullptr;   // Schur form: the point vector of a product
     if (schur) {
-        const size_t wn = 18 * 64 * (size_t)((M + 63) / 64) + 1;
+        // W in FP32 takes half the doubles of FP64 (rounded up)
+        d.w32 = o.precision == GBA_MIXED_FP32 ? 1 : 0;
+        const size_t wn = (18 * 64 * (size_t)((M + 63) / 64) + 2) / (d.w32 ? 2 : 1);
         int *qkf = nullptr, *qpt = nullptr, *pos = nullptr;
-        if (!B.up(&d.wk, (const double*)nullptr, wn) || !B.up(&d.wp, (const double*)nullptr, wn) ||
+        double *wk = nullptr, *wp = nullptr;
+        if (!B.up(&wk, (const double*)nullptr, wn) || !B.up(&wp, (const double*)nullptr, wn) ||
+            !B.up(&d.icx, (const double*)nullptr, 135 * (size_t)(K - 1)) ||
             !B.up(&qkf, hqkf.data(), (size_t)M + 1) || !B.up(&qpt, hqpt.data(), (size_t)M + 1) ||
             !B.up(&pos, hpos.data(), (size_t)M + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
             !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1))
@@ -1387,6 +1544,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         d.qkf = qkf;
         d.qpt = qpt;
         d.pos = pos;
+        d.wk = wk;
+        d.wp = wp;
     }
     d.kf = dkf;
     d.pt = dpt;
@@ -1411,12 +1570,16 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     hipLaunchKernelGGL(k_vi_states_in, grid(K), blk, 0, nullptr, K, s15, d.st);
     hipLaunchKernelGGL(k_vi_info, grid(K - 1), blk, 0, nullptr, K - 1, pre, d.info);
     if (!chk()) return GBA_ERR_HIP;
-    double hs[8];
+    double hs[8 + kPcgScalars];
     auto read_scal = [&]() {
         if (err == hipSuccess) err = hipMemcpy(hs, d.scal, sizeof(hs), hipMemcpyDeviceToHost);
         return err == hipSuccess;
     };
-    auto zero_scal = [&]() { hipLaunchKernelGGL(k_vi_fill, dim3(1), dim3(64), 0, nullptr, 8LL, d.scal); };
+    const long long n_scal = 8 + kPcgScalars;
+    double* ps = d.scal + 8;   // PCG scalars
+    auto zero_scal = [&]() {
+        hipLaunchKernelGGL(k_vi_fill, dim3(1), dim3(64), 0, nullptr, n_scal, d.scal, (const double*)nullptr);
+    };
     // cost of (st, X) into slot 0, and |x|^2 into slot 1 when asked
     auto cost_of = [&](const double* st, const double* X, bool xnorm, double& F, double& xn) {
         zero_scal();
@@ -1428,32 +1591,40 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         return true;
     };
     auto linearize = [&]() {
-        hipLaunchKernelGGL(k_vi_fill, grid(n), blk, 0, nullptr, n, d.b);
-        hipLaunchKernelGGL(k_vi_fill, grid(225LL * K), blk, 0, nullptr, 225LL * K, d.hk);
-        hipLaunchKernelGGL(k_vi_fill, grid(9 * N + 1), blk, 0, nullptr, 9 * N + 1, d.hp);
+        const double* none = nullptr;
+        hipLaunchKernelGGL(k_vi_fill, grid(n), blk, 0, nullptr, n, d.b, none);
+        hipLaunchKernelGGL(k_vi_fill, grid(225LL * K), blk, 0, nullptr, 225LL * K, d.hk, none);
+        hipLaunchKernelGGL(k_vi_fill, grid(9 * N + 1), blk, 0, nullptr, 9 * N + 1, d.hp, none);
         if (M > 0) hipLaunchKernelGGL(k_vi_lin_stereo, grid(M), blk, 0, nullptr, d);
         hipLaunchKernelGGL(k_vi_lin_inertial, grid(24LL * (K - 1)), blk, 0, nullptr, d);
         hipLaunchKernelGGL(k_vi_acc_inertial, grid(K - 1), blk, 0, nullptr, d);
+        if (schur) hipLaunchKernelGGL(k_vi_cross, grid(135LL * (K - 1)), blk, 0, nullptr, d);
         return chk();
     };
-    // q = (H + lam diag(D)) v, the whole system
-    auto product = [&](const double* v, double* out, double lam) {
-        hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out);
-        if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out);
-        hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out);
+    auto schur_kf = [&](const double* zz, double* out, const double* g) {
+        if (M == 0) return;
+        if (d.w32) hipLaunchKernelGGL(k_vi_schur_kf<float>, grid(M), blk, 0, nullptr, d, zz, out, g);
+        else hipLaunchKernelGGL(k_vi_schur_kf<double>, grid(M), blk, 0, nullptr, d, zz, out, g);
     };
-    // q = S v over the keyframes (the point vector through zb)
-    auto schur_product = [&](const double* v, double* out, double lam) {
-        hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, zb);
-        if (M > 0) hipLaunchKernelGGL(k_vi_schur_pts, grid(M), blk, 0, nullptr, d, v, nullptr, 1.0, zb);
-        hipLaunchKernelGGL(k_vi_schur_diag, grid(15LL * K), blk, 0, nullptr, d, lam, v, out);
-        hipLaunchKernelGGL(k_vi_schur_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out);
-        if (M > 0) hipLaunchKernelGGL(k_vi_schur_kf, grid(M), blk, 0, nullptr, d, zb, out);
+    // q = (H + lam diag(D)) v, the whole system (nothing once g's stop flag is set)
+    auto product = [&](const double* v, double* out, double lam, const double* g) {
+        hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out, g);
+        if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out, g);
+        hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out, g);
     };
+    // q = S v over the keyframes (the point vector through zb, clear on entry)
+    auto schur_product = [&](const double* v, double* out, double lam, const double* g) {
+        if (M > 0) {
+            if (d.w32) hipLaunchKernelGGL(k_vi_schur_pts<float>, grid(M), blk, 0, nullptr, d, v, (const double*)nullptr, 1.0, zb, g);
+            else hipLaunchKernelGGL(k_vi_schur_pts<double>, grid(M), blk, 0, nullptr, d, v, (const double*)nullptr, 1.0, zb, g);
+        }
+        hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, lam, v, out, g);
+        schur_kf(zb, out, g);
+    };
+    auto dot_blocks = [](long long len) { return dim3((unsigned)std::min<long long>(1024, (len + 255) / 256)); };
     auto dot = [&](long long len, const double* a, const double* b2, double& out) {
         zero_scal();
-        const long long nb = std::min<long long>(1024, (len + 255) / 256);
-        hipLaunchKernelGGL(k_vi_dot, dim3((unsigned)nb), blk, 0, nullptr, len, a, b2, d.scal);
+        hipLaunchKernelGGL(k_vi_dot, dot_blocks(len), blk, 0, nullptr, len, a, b2, d.scal, (const double*)nullptr);
         if (!chk() || !read_scal()) return false;
         out = hs[0];
         return true;
@@ -1462,57 +1633,74 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     // or on S x_k = v followed by the point back-substitution (Schur form)
     const long long nn = schur ? 15LL * K : n;          // PCG unknowns
     const long long nm = schur ? 15LL * K : 15LL * K + N;   // preconditioner lanes
+    // the PCG runs from its device scalars: its kernels are queued without
+    // host round trips, and the stop flag is read every kPcgSync steps
+    constexpr int kPcgSync = 8;
     auto pcg = [&](double lam, int& iters) {
         iters = 0;
+        const double* none = nullptr;
         if (schur) {
             hipLaunchKernelGGL(k_vi_precond, grid(N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 1);
-            hipLaunchKernelGGL(k_vi_fill, grid(36LL * K), blk, 0, nullptr, 36LL * K, d.sm);
-            if (M > 0) hipLaunchKernelGGL(k_vi_schur_blocks, grid(M), blk, 0, nullptr, d);
+            hipLaunchKernelGGL(k_vi_fill, grid(36LL * K), blk, 0, nullptr, 36LL * K, d.sm, none);
+            if (M > 0) {
+                if (d.w32) hipLaunchKernelGGL(k_vi_schur_blocks<float>, grid(M), blk, 0, nullptr, d);
+                else hipLaunchKernelGGL(k_vi_schur_blocks<double>, grid(M), blk, 0, nullptr, d);
+            }
             hipLaunchKernelGGL(k_vi_precond, grid(K), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 2);
             // r = -b_k + B C^-1 b_p
-            hipLaunchKernelGGL(k_vi_pt_apply, grid(N), blk, 0, nullptr, d, d.b + 15 * (size_t)K, -1.0, zb);
+            hipLaunchKernelGGL(k_vi_pt_apply, grid(N), blk, 0, nullptr, d, (const double*)(d.b + 15 * (size_t)K),
+                               -1.0, zb);
             hipLaunchKernelGGL(k_vi_neg, grid(nn), blk, 0, nullptr, nn, d.b, r, x);
-            if (M > 0) hipLaunchKernelGGL(k_vi_schur_kf, grid(M), blk, 0, nullptr, d, zb, r);
+            schur_kf(zb, r, none);
+            hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, zb, none);
         } else {
             hipLaunchKernelGGL(k_vi_precond, grid(K + N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 3);
             hipLaunchKernelGGL(k_vi_neg, grid(n), blk, 0, nullptr, n, d.b, r, x);
         }
-        hipLaunchKernelGGL(k_vi_apply_m, grid(nm), blk, 0, nullptr, d, r, z);
-        hipLaunchKernelGGL(k_vi_xpby, grid(nn), blk, 0, nullptr, nn, 0.0, z, pv);
-        double rz = 0.0, rr0 = 0.0;
-        if (!dot(nn, r, z, rz) || !dot(nn, r, r, rr0)) return false;
-        const double thresh = o.pcg_tol * o.pcg_tol * rr0;
-        if (rr0 > thresh && rz > 0.0) {
-            for (int it = 0; it < o.pcg_max_iters; ++it) {
-                if (schur) schur_product(pv, q, lam);
-                else product(pv, q, lam);
-                double pq = 0.0;
-                if (!dot(nn, pv, q, pq)) return false;
-                if (!(pq > 0.0)) break;
-                const double alpha = rz / pq;
-                hipLaunchKernelGGL(k_vi_axpy2, grid(nn), blk, 0, nullptr, nn, alpha, pv, q, x, r);
-                iters = it + 1;
-                double rr = 0.0;
-                if (!dot(nn, r, r, rr)) return false;
-                if (rr <= thresh) break;
-                hipLaunchKernelGGL(k_vi_apply_m, grid(nm), blk, 0, nullptr, d, r, z);
-                double rz_new = 0.0;
-                if (!dot(nn, r, z, rz_new)) return false;
-                hipLaunchKernelGGL(k_vi_xpby, grid(nn), blk, 0, nullptr, nn, rz_new / rz, z, pv);
-                rz = rz_new;
+        zero_scal();
+        hipLaunchKernelGGL(k_vi_apply_m, grid(nm), blk, 0, nullptr, d, r, z, none);
+        hipLaunchKernelGGL(k_vi_copy, grid(nn), blk, 0, nullptr, nn, (const double*)z, pv);
+        hipLaunchKernelGGL(k_vi_dot2, dot_blocks(nn), blk, 0, nullptr, nn, r, z, ps + kAccN * (kSlots - 1));
+        hipLaunchKernelGGL(k_vi_pcg_init, dim3(1), dim3(1), 0, nullptr, ps, o.pcg_tol);
+        const long long npt = schur ? 0 : N;
+        const dim3 upd((unsigned)((K + 15) / 16 + (npt + 255) / 256));
+        const long long nzb = schur ? 3 * N : 0;
+        const dim3 dirg((unsigned)std::max(1LL, std::min<long long>(1024, (std::max(nn, nzb) + 255) / 256)));
+        for (int it = 0; it < o.pcg_max_iters; ++it) {
+            const int slot = it % kSlots;
+            if (schur) schur_product(pv, q, lam, ps);
+            else product(pv, q, lam, ps);
+            hipLaunchKernelGGL(k_vi_dot, dot_blocks(nn), blk, 0, nullptr, nn, (const double*)pv, (const double*)q,
+                               ps + kAccN * slot + kAccPq, (const double*)ps);
+            hipLaunchKernelGGL(k_vi_pcg_update, upd, blk, 0, nullptr, d, npt, ps, slot, (const double*)pv,
+                               (const double*)q, x, r, z);
+            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv, zb, nzb);
+            if ((it + 1) % kPcgSync == 0 && it + 1 < o.pcg_max_iters) {
+                if (!chk() || !read_scal()) return false;
+                if (hs[8 + kDone] != 0.0) break;
             }
         }
         if (schur) {
             // x_p = -C^-1 (b_p + B^T x_k)
             double* xp = x + 15 * (size_t)K;
-            hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, xp);
-            if (M > 0)
-                hipLaunchKernelGGL(k_vi_schur_pts, grid(M), blk, 0, nullptr, d, x, d.b + 15 * (size_t)K,
-                                   -1.0, xp);
+            hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, xp, none);
+            if (M > 0) {
+                if (d.w32)
+                    hipLaunchKernelGGL(k_vi_schur_pts<float>, grid(M), blk, 0, nullptr, d, (const double*)x,
+                                       (const double*)(d.b + 15 * (size_t)K), -1.0, xp, none);
+                else
+                    hipLaunchKernelGGL(k_vi_schur_pts<double>, grid(M), blk, 0, nullptr, d, (const double*)x,
+                                       (const double*)(d.b + 15 * (size_t)K), -1.0, xp, none);
+            }
         }
-        return chk();
+        if (!chk() || !read_scal()) return false;
+        iters = (int)hs[8 + kSteps];
+        return true;
     };
     gba_report rep{};
+    if (hipDeviceSynchronize() != hipSuccess) return GBA_ERR_HIP;
+    rep.ms_other = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    rep.workspace_bytes = B.bytes;
     double F = 0.0, xn = 0.0;
     if (!cost_of(d.st, d.X, false, F, xn)) return GBA_ERR_HIP;
     rep.initial_cost = F;
@@ -1528,7 +1716,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             if (!pcg(lam, iters)) return GBA_ERR_HIP;
             rep.pcg_iters_total += iters;
             // model decrease -(b.dx + 1/2 dx^T H dx) with the undamped H
-            product(x, q, 0.0);
+            product(x, q, 0.0, nullptr);
             double bdx = 0.0, dHd = 0.0, dd = 0.0;
             if (!chk() || !dot(n, d.b, x, bdx) || !dot(n, x, q, dHd) || !dot(n, x, x, dd)) return GBA_ERR_HIP;
             const double L = -(bdx + 0.5 * dHd);

@@ -107,6 +107,35 @@ def test_vi_truncated_schur_step_matches_the_oracle(k):
     assert abs(t["step_norm"] - np.linalg.norm(dx)) <= 1e-8 * np.linalg.norm(dx)
 
 
+def test_vi_mixed_fp32_within_the_mixed_bounds():
+    # W = J_k^T J_p stored in FP32 (Schur form): final cost within 1e-4 and
+    # the solution within 1e-3 relative of the oracle's FP64 LM (the mixed
+    # bounds), and the first trial's step close to the FP64 path's
+    delta2 = 7.815
+    sc, prob, x0, states, pre_g = _setup(seed=8, n_kf=8, n_pts=100, delta2=delta2)
+    res = lm.levenberg_marquardt(prob, x0, 8)
+    st, X, rep, log = _gpu(sc, states, x0, pre_g, 8, delta2, pcg_tol=1e-12, pcg_max_iters=4000,
+                           precision=gba.GBA_MIXED_FP32)
+    st64, X64, rep64, log64 = _gpu(sc, states, x0, pre_g, 8, delta2, pcg_tol=1e-12,
+                                   pcg_max_iters=4000)
+    assert abs(rep["final_cost"] - res.cost) <= 1e-4 * res.cost
+    b = np.concatenate([res.x.p.ravel(), res.x.v.ravel(), res.x.bg.ravel(), res.x.ba.ravel(),
+                        res.x.X.ravel()])
+    a = np.concatenate([st[:, 3:6].ravel(), st[:, 6:9].ravel(), st[:, 9:12].ravel(),
+                        st[:, 12:15].ravel(), X.ravel()])
+    assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b)
+    t, t64 = log[0], log64[0]
+    # the FP32 storage moves the step at FP32's rounding level (and so is in use)
+    dstep = abs(t["step_norm"] - t64["step_norm"]) / t64["step_norm"]
+    assert 1e-12 < dstep < 1e-4, dstep
+    assert abs(t["model_decrease"] - t64["model_decrease"]) <= 1e-5 * abs(t64["model_decrease"])
+    assert abs(t["candidate_cost"] - t64["candidate_cost"]) <= 1e-5 * t64["candidate_cost"]
+    print("mixed fp32: final cost rel", abs(rep["final_cost"] - res.cost) / res.cost,
+          "solution rel", np.linalg.norm(a - b) / np.linalg.norm(b),
+          "first-trial step norm rel", dstep, "model decrease rel",
+          abs(t["model_decrease"] - t64["model_decrease"]) / abs(t64["model_decrease"]))
+
+
 @pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
 def test_vi_truncated_pcg_still_descends(solver):
     # a loose PCG: every accepted trial lowers the cost
@@ -137,3 +166,10 @@ def test_vi_solve_errors():
     with pytest.raises(gba.GbaError) as e:
         _gpu(sc, states, x0, pre_g, 3, 0.0, solver=7)
     assert e.value.status == -1                      # unknown solver form
+    with pytest.raises(gba.GbaError) as e:
+        _gpu(sc, states, x0, pre_g, 3, 0.0, solver=gba.GBA_SOLVER_FULL,
+             precision=gba.GBA_MIXED_FP32)
+    assert e.value.status == -1                      # FP32 W only in the Schur form
+    with pytest.raises(gba.GbaError) as e:
+        _gpu(sc, states, x0, pre_g, 3, 0.0, precision=gba.GBA_MIXED_BF16)
+    assert e.value.status == -1
