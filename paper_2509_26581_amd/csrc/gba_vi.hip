@@ -429,10 +429,9 @@ struct VIDev {
     double* hk;            // [225 K] keyframe diagonal blocks
     double* hp;            // [9 N] point diagonal blocks
     double* dg;            // [n] clipped diagonal (damping)
-    double* mk;            // [225 K] Cholesky factors of the damped keyframe blocks
     double* mki;           // [225 K] their inverses (the preconditioner applied)
     double* mp;            // [9 N] inverses of the damped point blocks
-    double* scal;          // [8] reductions
+    double* scal;          // [8 + kPcgScalars] reductions
     // Schur form (null in the full form): W_e = J_k^T J_p (6 x 3) per
     // observation, in keyframe order (wk) and in point order (wp), each in
     // tiles of 64 observations with entry c of lane l at (18 tile + c) 64 + l
@@ -441,7 +440,7 @@ struct VIDev {
     int w32;
     const int* qkf;        // [M] keyframe of the i-th observation in point order
     const int* qpt;        // [M] its point
-    const int* pos;        // [M] point-order position of keyframe-order observation e
+    const double* qobs;    // [3 M] the observed pixels in point order
     double* sm;            // [36 K] sum over a keyframe's observations of W C^-1 W^T
     double* icx;           // [135 (K - 1)] inertial cross blocks J_i^T Omega J_j (15 x 9)
     double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
@@ -459,8 +458,46 @@ enum { kThr = kSlots * kAccN, kDone, kSteps, kPcgScalars };
 
 __device__ __forceinline__ bool pcg_done(const double* ps) { return ps && ps[kDone] != 0.0; }
 
+// W tiles: 64 observations x 18 entries, in 16-byte groups so that a lane
+// loads its entries as float4 / double2 and one load instruction of a
+// wavefront reads 1 KiB contiguous: group g (V = 16 / sizeof(WT) entries,
+// the last one of FP32 two wide) of lane l at tile + 64 V g + width l
+template <typename WT>
 __device__ __forceinline__ size_t w_at(long long e, int c) {
-    return ((size_t)(e >> 6) * 18 + c) * 64 + (size_t)(e & 63);
+    constexpr int V = 16 / (int)sizeof(WT);
+    const int g = c / V;
+    const int width = (18 - g * V) < V ? (18 - g * V) : V;
+    return (size_t)(e >> 6) * (18 * 64) + (size_t)g * V * 64 + (size_t)(e & 63) * width + (c - g * V);
+}
+
+template <typename WT>
+__device__ __forceinline__ void load_w(const void* w, long long e, double (&out)[18]);
+
+template <>
+__device__ __forceinline__ void load_w<float>(const void* w, long long e, double (&out)[18]) {
+    const float* t = (const float*)w + (size_t)(e >> 6) * (18 * 64);
+    const int l = (int)(e & 63);
+    for (int g = 0; g < 4; ++g) {
+        const float4 v = ((const float4*)t)[g * 64 + l];
+        out[4 * g] = v.x;
+        out[4 * g + 1] = v.y;
+        out[4 * g + 2] = v.z;
+        out[4 * g + 3] = v.w;
+    }
+    const float2 v = ((const float2*)(t + 1024))[l];
+    out[16] = v.x;
+    out[17] = v.y;
+}
+
+template <>
+__device__ __forceinline__ void load_w<double>(const void* w, long long e, double (&out)[18]) {
+    const double* t = (const double*)w + (size_t)(e >> 6) * (18 * 64);
+    const int l = (int)(e & 63);
+    for (int g = 0; g < 9; ++g) {
+        const double2 v = ((const double2*)t)[g * 64 + l];
+        out[2 * g] = v.x;
+        out[2 * g + 1] = v.y;
+    }
 }
 
 __device__ __forceinline__ void atomic_add(double* a, double v) { unsafeAtomicAdd(a, v); }
@@ -560,10 +597,29 @@ __device__ __forceinline__ void vi_huber(double s, double delta2, double& rho, d
     }
 }
 
-// linearisation of the stereo terms: whitened J and r stored; gradient and
-// diagonal blocks accumulated.  The observations are in keyframe order, so a
-// keyframe's terms are summed across the wavefront (SegScan) and added once
-// per segment; the point terms are added per observation.
+// whitened residual and Jacobian of observation (k, j) with the observed
+// pixels ob (zero when !valid; the first keyframe's columns zero)
+__device__ __forceinline__ void vi_stereo_whitened(const VIDev& d, const double* __restrict__ ob, int k, int j,
+                                                   bool valid, double (&r)[3], double (&J)[3][9]) {
+    VIDev dd = d;
+    dd.obs = ob;
+    vi_stereo<true>(dd, d.st + (size_t)kSt * k, d.X + 3 * (size_t)j, 0, r, J);
+    const double s = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * d.inv_sigma * d.inv_sigma;
+    double rho, w;
+    vi_huber(s, d.delta2, rho, w);
+    const double sc = valid ? sqrt(w) * d.inv_sigma : 0.0;
+    for (int a = 0; a < 3; ++a) {
+        r[a] *= sc;
+        for (int c = 0; c < 9; ++c) J[a][c] = (k == 0 && c < 6) ? 0.0 : J[a][c] * sc;
+    }
+}
+
+// linearisation of the stereo terms in keyframe order: the keyframe's
+// gradient and 6 x 6 block terms summed across its run of the wavefront
+// (SegScan) and added once per run.  Whole-system form: whitened J and r
+// stored, point terms added per observation.  Schur form: W = J_k^T J_p
+// stored (keyframe-order tiles); the point terms come from the point-order
+// pass below.
 __global__ void k_vi_lin_stereo(VIDev d) {
     const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool valid = e0 < d.M;
@@ -576,39 +632,19 @@ __global__ void k_vi_lin_stereo(VIDev d) {
     int head, end;
     segment_of(__ballot(start), l, head, end);
     double r[3], J[3][9];
-    vi_stereo<true>(d, d.st + (size_t)kSt * k, d.X + 3 * (size_t)j, e, r, J);
-    const double s = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * d.inv_sigma * d.inv_sigma;
-    double rho, w;
-    vi_huber(s, d.delta2, rho, w);
-    const double sc = sqrt(w) * d.inv_sigma;
-    for (int a = 0; a < 3; ++a) {
-        r[a] *= sc;
-        for (int c = 0; c < 9; ++c) J[a][c] = (k == 0 && c < 6) ? 0.0 : J[a][c] * sc;
-    }
-    if (!valid)
-        for (int a = 0; a < 3; ++a) {
-            r[a] = 0.0;
-            for (int c = 0; c < 9; ++c) J[a][c] = 0.0;
-        }
-    if (valid)
+    vi_stereo_whitened(d, d.obs + 3 * e, k, j, valid, r, J);
+    if (valid && !d.wk)
         for (int a = 0; a < 3; ++a) {
             d.rs[3 * e + a] = r[a];
             for (int c = 0; c < 9; ++c) d.js[27 * e + 9 * a + c] = J[a][c];
         }
-    if (valid && d.wk) {
-        const long long ep = d.pos[e];
+    if (valid && d.wk)
         for (int a = 0; a < 6; ++a)
             for (int c = 0; c < 3; ++c) {
                 const double w = J[0][a] * J[0][6 + c] + J[1][a] * J[1][6 + c] + J[2][a] * J[2][6 + c];
-                if (d.w32) {
-                    ((float*)d.wk)[w_at(e, 3 * a + c)] = (float)w;
-                    ((float*)d.wp)[w_at(ep, 3 * a + c)] = (float)w;
-                } else {
-                    ((double*)d.wk)[w_at(e, 3 * a + c)] = w;
-                    ((double*)d.wp)[w_at(ep, 3 * a + c)] = w;
-                }
+                if (d.w32) ((float*)d.wk)[w_at<float>(e, 3 * a + c)] = (float)w;
+                else ((double*)d.wk)[w_at<double>(e, 3 * a + c)] = w;
             }
-    }
     const bool last = valid && l == end;
     double* bk = d.b + 15 * (size_t)k;
     double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
@@ -617,7 +653,7 @@ __global__ void k_vi_lin_stereo(VIDev d) {
         if (c < 6) {
             const double sg = seg.sum(g);
             if (last) atomic_add(bk + c, sg);
-        } else if (valid) {
+        } else if (valid && !d.wk) {
             atomic_add(bp + (c - 6), g);
         }
     }
@@ -626,11 +662,58 @@ __global__ void k_vi_lin_stereo(VIDev d) {
             const double h = seg.sum(J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
             if (last && k != 0) atomic_add(d.hk + 225 * (size_t)k + 15 * a + c, h);
         }
-    if (valid)
+    if (valid && !d.wk)
         for (int a = 0; a < 3; ++a)
             for (int c = 0; c < 3; ++c)
                 atomic_add(d.hp + 9 * (size_t)j + 3 * a + c,
                            J[0][6 + a] * J[0][6 + c] + J[1][6 + a] * J[1][6 + c] + J[2][6 + a] * J[2][6 + c]);
+}
+
+// the same terms in point order (Schur form): W stored in point-order tiles,
+// the point's gradient b_p and block H_pp summed across its run of the
+// wavefront; a point whose observations all sit in one wavefront is stored,
+// one split across wavefronts is added in parts (b and hp are zero before)
+template <typename WT>
+__global__ void k_vi_lin_stereo_pts(VIDev d) {
+    const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool valid = i0 < d.M;
+    const long long i = valid ? i0 : d.M - 1;
+    const int j = d.qpt[i], k = d.qkf[i];
+    const int l = (int)(threadIdx.x & 63);
+    const int jprev = __shfl_up(j, 1, 64);
+    const bool start = !valid || l == 0 || jprev != j;
+    const SegScan seg(start);
+    int head, end;
+    segment_of(__ballot(start), l, head, end);
+    const bool first = i == 0 || d.qpt[i - 1] != j;
+    const bool lastp = i == d.M - 1 || d.qpt[i + 1] != j;
+    const bool whole = (__shfl(first ? 1 : 0, head, 64) != 0) && lastp;
+    double r[3], J[3][9];
+    vi_stereo_whitened(d, d.qobs + 3 * i, k, j, valid, r, J);
+    if (valid)
+        for (int a = 0; a < 6; ++a)
+            for (int c = 0; c < 3; ++c)
+                ((WT*)d.wp)[w_at<WT>(i, 3 * a + c)] =
+                    (WT)(J[0][a] * J[0][6 + c] + J[1][a] * J[1][6 + c] + J[2][a] * J[2][6 + c]);
+    const bool out = valid && l == end;
+    double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
+    for (int c = 0; c < 3; ++c) {
+        const double g = seg.sum(J[0][6 + c] * r[0] + J[1][6 + c] * r[1] + J[2][6 + c] * r[2]);
+        if (out) {
+            if (whole) bp[c] = g;
+            else atomic_add(bp + c, g);
+        }
+    }
+    double* hp = d.hp + 9 * (size_t)j;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) {
+            const double h = seg.sum(J[0][6 + a] * J[0][6 + c] + J[1][6 + a] * J[1][6 + c] +
+                                     J[2][6 + a] * J[2][6 + c]);
+            if (out) {
+                if (whole) hp[3 * a + c] = h;
+                else atomic_add(hp + 3 * a + c, h);
+            }
+        }
 }
 
 // inertial Jacobians by forward-mode AD, one lane per (term, column), at the
@@ -672,52 +755,47 @@ __global__ __launch_bounds__(256) void k_vi_lin_inertial(VIDev d) {
         for (int k = 0; k < 9; ++k) d.ri[9 * (size_t)f + k] = r[k].v;
 }
 
-// inertial and bias terms: gradient and diagonal blocks (one lane per term)
-__global__ void k_vi_acc_inertial(VIDev d) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= d.K - 1) return;
+// inertial and bias terms: gradient and diagonal blocks, one wavefront per
+// term, lane c < 24 for column c (keyframe i's 15, then keyframe j's first 9)
+__global__ __launch_bounds__(256) void k_vi_acc_inertial(VIDev d) {
+    const int f = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6);
+    const int l = (int)(threadIdx.x & 63);
+    if (f >= d.K - 1) return;   // whole wavefronts
     const double* J = d.ji + (size_t)216 * f;
     const double* O = d.info + 81 * (size_t)f;
     const double* r = d.ri + 9 * (size_t)f;
-    double Or[9];
-    for (int a = 0; a < 9; ++a) {
-        double t = 0.0;
-        for (int c = 0; c < 9; ++c) t += O[9 * a + c] * r[c];
-        Or[a] = t;
-    }
     double* bi = d.b + 15 * (size_t)f;
     double* bj = d.b + 15 * (size_t)(f + 1);
-    for (int c = 0; c < 24; ++c) {
-        double g = 0.0;
-        for (int a = 0; a < 9; ++a) g += J[24 * a + c] * Or[a];
-        atomic_add(c < 15 ? bi + c : bj + (c - 15), g);
-    }
-    // J^T Omega J on the two diagonal blocks (OJ = Omega J, 9 x 24)
     double* hi = d.hk + 225 * (size_t)f;
     double* hj = d.hk + 225 * (size_t)(f + 1);
-    for (int c2 = 0; c2 < 24; ++c2) {
-        double OJ[9];
+    if (l < 24) {
+        double Or[9], OJ[9];   // Omega r, and column l of Omega J
         for (int a = 0; a < 9; ++a) {
-            double t = 0.0;
-            for (int k = 0; k < 9; ++k) t += O[9 * a + k] * J[24 * k + c2];
-            OJ[a] = t;
+            double t = 0.0, u = 0.0;
+            for (int c = 0; c < 9; ++c) {
+                t += O[9 * a + c] * r[c];
+                u += O[9 * a + c] * J[24 * c + l];
+            }
+            Or[a] = t;
+            OJ[a] = u;
         }
-        for (int c1 = 0; c1 < 24; ++c1) {
-            const bool same = (c1 < 15) == (c2 < 15);
-            if (!same) continue;
+        double g = 0.0;
+        for (int a = 0; a < 9; ++a) g += J[24 * a + l] * Or[a];
+        atomic_add(l < 15 ? bi + l : bj + (l - 15), g);
+        // column l of J^T Omega J within its keyframe's block
+        const int c0 = l < 15 ? 0 : 15, c1 = l < 15 ? 15 : 24;
+        for (int c = c0; c < c1; ++c) {
             double t = 0.0;
-            for (int a = 0; a < 9; ++a) t += J[24 * a + c1] * OJ[a];
-            if (c1 < 15)
-                atomic_add(hi + 15 * c1 + c2, t);
-            else
-                atomic_add(hj + 15 * (c1 - 15) + (c2 - 15), t);
+            for (int a = 0; a < 9; ++a) t += J[24 * a + c] * OJ[a];
+            if (l < 15) atomic_add(hi + 15 * c + l, t);
+            else atomic_add(hj + 15 * (c - 15) + (l - 15), t);
         }
-    }
-    // bias random walk: r = b_j - b_i (6), Omega_b = diag(wg I3, wa I3) / dt
-    const double dt = d.pre[(size_t)kPreStride * f + kDt];
-    const double* si = d.st + (size_t)kSt * f;
-    const double* sj = d.st + (size_t)kSt * (f + 1);
-    for (int k = 0; k < 6; ++k) {
+    } else if (l < 30) {
+        // bias random walk: r = b_j - b_i (6), Omega_b = diag(wg I3, wa I3) / dt
+        const int k = l - 24;
+        const double dt = d.pre[(size_t)kPreStride * f + kDt];
+        const double* si = d.st + (size_t)kSt * f;
+        const double* sj = d.st + (size_t)kSt * (f + 1);
         const double w = (k < 3 ? d.wg : d.wa) / dt;
         const double rb = sj[15 + k] - si[15 + k];
         atomic_add(bj + 9 + k, w * rb);
@@ -774,56 +852,13 @@ __global__ void k_vi_cost(VIDev d, const double* __restrict__ st, const double* 
     if (threadIdx.x == 0) atomic_add(d.scal + slot, c);
 }
 
-// damped block-Jacobi preconditioner: D = clip(diag H); keyframe blocks
-// H + lambda diag(D) factored (Cholesky, in place into mk), point blocks
-// inverted; one lane per block
-// parts: 1 the point blocks, 2 the keyframe blocks, 3 both.  In the Schur
-// form the keyframe blocks are those of S: the pose block less sm.
-__global__ void k_vi_precond(VIDev d, double lam, double lo, double hi, int parts) {
-    long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (!(parts & 2)) t += d.K;
-    if (t < d.K && (parts & 2)) {
-        const int k = (int)t;
-        const double* H = d.hk + 225 * (size_t)k;
-        double* L = d.mk + 225 * (size_t)k;
-        for (int i = 0; i < 15; ++i) {
-            const double dd = fmin(fmax(H[16 * i], lo), hi);
-            d.dg[15 * (size_t)k + i] = dd;
-        }
-        for (int i = 0; i < 225; ++i) L[i] = H[i];
-        for (int i = 0; i < 15; ++i) L[16 * i] += lam * d.dg[15 * (size_t)k + i];
-        if (d.sm)
-            for (int a = 0; a < 6; ++a)
-                for (int c = 0; c < 6; ++c) L[15 * a + c] -= d.sm[36 * (size_t)k + 6 * a + c];
-        for (int j = 0; j < 15; ++j) {
-            double s = L[16 * j];
-            for (int q = 0; q < j; ++q) s -= L[15 * j + q] * L[15 * j + q];
-            const double ljj = sqrt(fmax(s, 1e-300));
-            L[16 * j] = ljj;
-            for (int i = j + 1; i < 15; ++i) {
-                double u = L[15 * i + j];
-                for (int q = 0; q < j; ++q) u -= L[15 * i + q] * L[15 * j + q];
-                L[15 * i + j] = u / ljj;
-            }
-        }
-        // the inverse, column by column: L L^T x = e_c
-        double* Mi = d.mki + 225 * (size_t)k;
-        for (int c = 0; c < 15; ++c) {
-            double y[15];
-            for (int i = 0; i < 15; ++i) {
-                double u = i == c ? 1.0 : 0.0;
-                for (int q2 = 0; q2 < i; ++q2) u -= L[15 * i + q2] * y[q2];
-                y[i] = u / L[16 * i];
-            }
-            for (int i = 14; i >= 0; --i) {
-                double u = y[i];
-                for (int q2 = i + 1; q2 < 15; ++q2) u -= L[15 * q2 + i] * y[q2];
-                y[i] = u / L[16 * i];
-            }
-            for (int i = 0; i < 15; ++i) Mi[15 * i + c] = y[i];
-        }
-    } else if (t >= d.K && t < d.K + d.N && (parts & 1)) {
-        const long long j = t - d.K;
+// the point blocks of the preconditioner (and, in the Schur form, C^-1):
+// D = clip(diag H_pp), the damped 3 x 3 block inverted by cofactors; one
+// lane per point
+__global__ void k_vi_precond_pts(VIDev d, double lam, double lo, double hi) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t < d.N) {
+        const long long j = t;
         const double* H = d.hp + 9 * j;
         double A[3][3];
         for (int a = 0; a < 3; ++a) {
@@ -846,6 +881,61 @@ __global__ void k_vi_precond(VIDev d, double lam, double lo, double hi, int part
         M[6] = c02 * id;
         M[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
         M[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    }
+}
+
+// the keyframe blocks of the preconditioner, one wavefront per keyframe:
+// D = clip(diag H), A = H + lambda diag(D) (less sm in the Schur form),
+// factored A = L L^T in LDS (right-looking, the trailing update spread over
+// the lanes), then A^-1 column by column (lane c < 15 solves L L^T x = e_c)
+__global__ __launch_bounds__(256) void k_vi_precond_kf(VIDev d, double lam, double lo, double hi) {
+    __shared__ double La[4][225];
+    const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    const long long k = blockIdx.x * 4LL + w;
+    if (k >= d.K) return;   // whole wavefronts; no workgroup barrier below
+    double* A = La[w];
+    const double* H = d.hk + 225 * (size_t)k;
+    for (int e = l; e < 225; e += 64) {
+        const int a = e / 15, c = e % 15;
+        double v = H[e];
+        if (a == c) {
+            const double dd = fmin(fmax(v, lo), hi);
+            d.dg[15 * (size_t)k + a] = dd;
+            v += lam * dd;
+        }
+        if (d.sm && a < 6 && c < 6) v -= d.sm[36 * (size_t)k + 6 * a + c];
+        A[e] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int j = 0; j < 15; ++j) {
+        const double ljj = sqrt(fmax(A[16 * j], 1e-300));
+        if (l > j && l < 15) A[15 * l + j] /= ljj;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (l == 0) A[16 * j] = ljj;
+        // trailing update of the lower triangle: (a, c), j < c <= a < 15
+        for (int e = l; e < 225; e += 64) {
+            const int a = e / 15, c = e % 15;
+            if (c > j && c <= a) A[e] -= A[15 * a + j] * A[15 * c + j];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    if (l < 15) {
+        double y[15];
+        for (int i = 0; i < 15; ++i) {
+            double u = i == l ? 1.0 : 0.0;
+            for (int q = 0; q < i; ++q) u -= A[15 * i + q] * y[q];
+            y[i] = u / A[16 * i];
+        }
+        for (int i = 14; i >= 0; --i) {
+            double u = y[i];
+            for (int q = i + 1; q < 15; ++q) u -= A[15 * q + i] * y[q];
+            y[i] = u / A[16 * i];
+        }
+        double* Mi = d.mki + 225 * (size_t)k;
+        for (int i = 0; i < 15; ++i) Mi[15 * i + l] = y[i];
     }
 }
 
@@ -975,10 +1065,12 @@ __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const doub
     const bool last = i == d.M - 1 || d.qpt[i + 1] != j;
     const bool whole_head = __shfl(first ? 1 : 0, head, 64) != 0;
     const double* vk = v + 15 * (size_t)k;
+    double W[18];
+    load_w<WT>(d.wp, i, W);
     double t[3];
     for (int c = 0; c < 3; ++c) {
         double u = 0.0;
-        for (int a = 0; a < 6; ++a) u += (double)((const WT*)d.wp)[w_at(i, 3 * a + c)] * vk[a];
+        for (int a = 0; a < 6; ++a) u += W[3 * a + c] * vk[a];
         t[c] = seg.sum(valid ? u : 0.0);
     }
     if (!valid || l != end) return;
@@ -1003,6 +1095,21 @@ __global__ void k_vi_pt_apply(VIDev d, const double* __restrict__ in, double sig
     for (int r = 0; r < 3; ++r) out[3 * j + r] = sign * (Mi[3 * r] * a + Mi[3 * r + 1] * b + Mi[3 * r + 2] * c);
 }
 
+// sum over the points of x_j^T H_pp,j x_j (the undamped point blocks) into *out
+__global__ void k_vi_pt_quad(VIDev d, const double* __restrict__ x, double* __restrict__ out) {
+    __shared__ double red[16];
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (j < d.N) {
+        const double* H = d.hp + 9 * j;
+        const double a = x[3 * j], b = x[3 * j + 1], c = x[3 * j + 2];
+        s = a * (H[0] * a + H[1] * b + H[2] * c) + b * (H[3] * a + H[4] * b + H[5] * c) +
+            c * (H[6] * a + H[7] * b + H[8] * c);
+    }
+    s = block_sum_vi(s, red);
+    if (threadIdx.x == 0) atomic_add(out, s);
+}
+
 // q_k -= sum_{e of k} W_e z_j(e): observations in keyframe order, the
 // keyframe's sum across its run of the wavefront, one atomic add per run
 template <typename WT>
@@ -1020,10 +1127,12 @@ __global__ void k_vi_schur_kf(VIDev d, const double* __restrict__ z, double* __r
     int head, end;
     segment_of(__ballot(start), l, head, end);
     const double zj[3] = {z[3 * (size_t)j], z[3 * (size_t)j + 1], z[3 * (size_t)j + 2]};
+    double W[18];
+    load_w<WT>(d.wk, e, W);
     double y[6];
     for (int a = 0; a < 6; ++a) {
         double u = 0.0;
-        for (int c = 0; c < 3; ++c) u += (double)((const WT*)d.wk)[w_at(e, 3 * a + c)] * zj[c];
+        for (int c = 0; c < 3; ++c) u += W[3 * a + c] * zj[c];
         y[a] = seg.sum(valid ? u : 0.0);
     }
     if (valid && l == end && k != 0)
@@ -1046,9 +1155,10 @@ __global__ void k_vi_schur_blocks(VIDev d) {
     int head, end;
     segment_of(__ballot(start), l, head, end);
     const double* Mi = d.mp + 9 * (size_t)j;
-    double W[6][3], G[6][3];
+    double W[6][3], G[6][3], Wf[18];
+    load_w<WT>(d.wk, e, Wf);
     for (int a = 0; a < 6; ++a)
-        for (int c = 0; c < 3; ++c) W[a][c] = valid ? (double)((const WT*)d.wk)[w_at(e, 3 * a + c)] : 0.0;
+        for (int c = 0; c < 3; ++c) W[a][c] = valid ? Wf[3 * a + c] : 0.0;
     for (int a = 0; a < 6; ++a)
         for (int c = 0; c < 3; ++c) G[a][c] = W[a][0] * Mi[c] + W[a][1] * Mi[3 + c] + W[a][2] * Mi[6 + c];
     const bool out = valid && l == end && k != 0;
@@ -1479,14 +1589,36 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             for (int c = 0; c < 3; ++c) hobs[3 * q + c] = P.obs[3 * e + c];
         }
     }
+    // points renumbered by the first keyframe that observes them (stable;
+    // unobserved points last), so that a keyframe's observations and a run
+    // of consecutive points touch nearby points and keyframes: the point
+    // and keyframe gathers of the products stay within a narrow window
+    std::vector<int> pt_new((size_t)P.n_pts), pt_old((size_t)P.n_pts);
+    {
+        std::vector<int> first((size_t)P.n_pts, P.n_kf);
+        for (int64_t e = 0; e < P.n_obs; ++e) first[hpt[e]] = std::min(first[hpt[e]], hkf[e]);
+        std::vector<int64_t> cnt((size_t)P.n_kf + 2, 0);
+        for (int64_t j = 0; j < P.n_pts; ++j) ++cnt[(size_t)first[j] + 1];
+        for (int k = 0; k <= P.n_kf; ++k) cnt[(size_t)k + 1] += cnt[(size_t)k];
+        for (int64_t j = 0; j < P.n_pts; ++j) {
+            const int q = (int)cnt[(size_t)first[j]]++;
+            pt_new[j] = q;
+            pt_old[q] = (int)j;
+        }
+        for (int64_t e = 0; e < P.n_obs; ++e) hpt[e] = pt_new[hpt[e]];
+    }
+    std::vector<double> hX(3 * (size_t)P.n_pts + 1, 0.0);
+    for (int64_t q = 0; q < P.n_pts; ++q)
+        for (int c = 0; c < 3; ++c) hX[3 * q + c] = P.pts[3 * (size_t)pt_old[q] + c];
     const bool schur = o.solver == GBA_SOLVER_SCHUR;
     // Schur form: the same observations in point order (a stable counting
     // sort of the keyframe order), for the point sums of the products
-    std::vector<int> hqkf, hqpt, hpos;
+    std::vector<int> hqkf, hqpt;
+    std::vector<double> hqobs;
     if (schur) {
         hqkf.assign((size_t)P.n_obs + 1, 0);
         hqpt.assign((size_t)P.n_obs + 1, 0);
-        hpos.assign((size_t)P.n_obs + 1, 0);
+        hqobs.assign(3 * (size_t)P.n_obs + 1, 0.0);
         std::vector<int64_t> cnt((size_t)P.n_pts + 1, 0);
         for (int64_t e = 0; e < P.n_obs; ++e) ++cnt[(size_t)hpt[e] + 1];
         for (int64_t j = 0; j < P.n_pts; ++j) cnt[(size_t)j + 1] += cnt[(size_t)j];
@@ -1494,7 +1626,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             const size_t q = (size_t)cnt[(size_t)hpt[e]]++;
             hqkf[q] = hkf[e];
             hqpt[q] = hpt[e];
-            hpos[e] = (int)q;
+            for (int c = 0; c < 3; ++c) hqobs[3 * q + c] = hobs[3 * e + c];
         }
     }
     if (hipSetDevice(device) != hipSuccess) return GBA_ERR_HIP;
@@ -1511,18 +1643,17 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     double* obs = nullptr;
     if (!B.up(&s15, P.states, 15 * (size_t)K) || !B.up(&d.st, (const double*)nullptr, kSt * (size_t)K) ||
         !B.up(&d.st_c, (const double*)nullptr, kSt * (size_t)K) ||
-        !B.up(&d.X, P.pts, 3 * (size_t)N) || !B.up(&d.X_c, (const double*)nullptr, 3 * (size_t)N + 1) ||
+        !B.up(&d.X, (const double*)hX.data(), 3 * (size_t)N) || !B.up(&d.X_c, (const double*)nullptr, 3 * (size_t)N + 1) ||
         !B.up(&dkf, hkf.data(), (size_t)M + 1) || !B.up(&dpt, hpt.data(), (size_t)M + 1) ||
         !B.up(&obs, hobs.data(), 3 * (size_t)M + 1) ||
         !B.up(&pre, P.pre, (size_t)kPreStride * (K - 1)) ||
         !B.up(&d.info, (const double*)nullptr, 81 * (size_t)(K - 1)) ||
-        !B.up(&d.js, (const double*)nullptr, 27 * (size_t)M + 1) ||
-        !B.up(&d.rs, (const double*)nullptr, 3 * (size_t)M + 1) ||
+        !B.up(&d.js, (const double*)nullptr, schur ? 1 : 27 * (size_t)M + 1) ||   // whole-system form only
+        !B.up(&d.rs, (const double*)nullptr, schur ? 1 : 3 * (size_t)M + 1) ||
         !B.up(&d.ji, (const double*)nullptr, 216 * (size_t)(K - 1)) ||
         !B.up(&d.ri, (const double*)nullptr, 9 * (size_t)(K - 1)) ||
         !B.up(&d.b, (const double*)nullptr, (size_t)n) || !B.up(&d.hk, (const double*)nullptr, 225 * (size_t)K) ||
         !B.up(&d.hp, (const double*)nullptr, 9 * (size_t)N + 1) || !B.up(&d.dg, (const double*)nullptr, (size_t)n) ||
-        !B.up(&d.mk, (const double*)nullptr, 225 * (size_t)K) ||
         !B.up(&d.mki, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
         !B.up(&d.scal, (const double*)nullptr, 8 + kPcgScalars) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
         !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
@@ -1533,17 +1664,18 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         // W in FP32 takes half the doubles of FP64 (rounded up)
         d.w32 = o.precision == GBA_MIXED_FP32 ? 1 : 0;
         const size_t wn = (18 * 64 * (size_t)((M + 63) / 64) + 2) / (d.w32 ? 2 : 1);
-        int *qkf = nullptr, *qpt = nullptr, *pos = nullptr;
+        int *qkf = nullptr, *qpt = nullptr;
+        double* qobs = nullptr;
         double *wk = nullptr, *wp = nullptr;
         if (!B.up(&wk, (const double*)nullptr, wn) || !B.up(&wp, (const double*)nullptr, wn) ||
             !B.up(&d.icx, (const double*)nullptr, 135 * (size_t)(K - 1)) ||
             !B.up(&qkf, hqkf.data(), (size_t)M + 1) || !B.up(&qpt, hqpt.data(), (size_t)M + 1) ||
-            !B.up(&pos, hpos.data(), (size_t)M + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
+            !B.up(&qobs, hqobs.data(), 3 * (size_t)M + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
             !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1))
             return GBA_ERR_OOM;
         d.qkf = qkf;
         d.qpt = qpt;
-        d.pos = pos;
+        d.qobs = qobs;
         d.wk = wk;
         d.wp = wp;
     }
@@ -1596,8 +1728,12 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_fill, grid(225LL * K), blk, 0, nullptr, 225LL * K, d.hk, none);
         hipLaunchKernelGGL(k_vi_fill, grid(9 * N + 1), blk, 0, nullptr, 9 * N + 1, d.hp, none);
         if (M > 0) hipLaunchKernelGGL(k_vi_lin_stereo, grid(M), blk, 0, nullptr, d);
+        if (M > 0 && schur) {
+            if (d.w32) hipLaunchKernelGGL(k_vi_lin_stereo_pts<float>, grid(M), blk, 0, nullptr, d);
+            else hipLaunchKernelGGL(k_vi_lin_stereo_pts<double>, grid(M), blk, 0, nullptr, d);
+        }
         hipLaunchKernelGGL(k_vi_lin_inertial, grid(24LL * (K - 1)), blk, 0, nullptr, d);
-        hipLaunchKernelGGL(k_vi_acc_inertial, grid(K - 1), blk, 0, nullptr, d);
+        hipLaunchKernelGGL(k_vi_acc_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d);
         if (schur) hipLaunchKernelGGL(k_vi_cross, grid(135LL * (K - 1)), blk, 0, nullptr, d);
         return chk();
     };
@@ -1640,13 +1776,14 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         iters = 0;
         const double* none = nullptr;
         if (schur) {
-            hipLaunchKernelGGL(k_vi_precond, grid(N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 1);
+            hipLaunchKernelGGL(k_vi_precond_pts, grid(N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag);
             hipLaunchKernelGGL(k_vi_fill, grid(36LL * K), blk, 0, nullptr, 36LL * K, d.sm, none);
             if (M > 0) {
                 if (d.w32) hipLaunchKernelGGL(k_vi_schur_blocks<float>, grid(M), blk, 0, nullptr, d);
                 else hipLaunchKernelGGL(k_vi_schur_blocks<double>, grid(M), blk, 0, nullptr, d);
             }
-            hipLaunchKernelGGL(k_vi_precond, grid(K), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 2);
+            hipLaunchKernelGGL(k_vi_precond_kf, dim3((unsigned)((K + 3) / 4)), blk, 0, nullptr, d, lam, o.min_diag,
+                               o.max_diag);
             // r = -b_k + B C^-1 b_p
             hipLaunchKernelGGL(k_vi_pt_apply, grid(N), blk, 0, nullptr, d, (const double*)(d.b + 15 * (size_t)K),
                                -1.0, zb);
@@ -1654,7 +1791,9 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             schur_kf(zb, r, none);
             hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, zb, none);
         } else {
-            hipLaunchKernelGGL(k_vi_precond, grid(K + N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag, 3);
+            hipLaunchKernelGGL(k_vi_precond_pts, grid(N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag);
+            hipLaunchKernelGGL(k_vi_precond_kf, dim3((unsigned)((K + 3) / 4)), blk, 0, nullptr, d, lam, o.min_diag,
+                               o.max_diag);
             hipLaunchKernelGGL(k_vi_neg, grid(n), blk, 0, nullptr, n, d.b, r, x);
         }
         zero_scal();
@@ -1715,10 +1854,28 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             int iters = 0;
             if (!pcg(lam, iters)) return GBA_ERR_HIP;
             rep.pcg_iters_total += iters;
-            // model decrease -(b.dx + 1/2 dx^T H dx) with the undamped H
-            product(x, q, 0.0, nullptr);
+            // model decrease -(b.dx + 1/2 dx^T H dx) with the undamped H; in
+            // the Schur form dx^T H dx = dx_k^T A dx_k + 2 dx_k^T B dx_p
+            // + sum_j dx_j^T H_pp,j dx_j from the blocks
             double bdx = 0.0, dHd = 0.0, dd = 0.0;
-            if (!chk() || !dot(n, d.b, x, bdx) || !dot(n, x, q, dHd) || !dot(n, x, x, dd)) return GBA_ERR_HIP;
+            if (schur) {
+                const double* xp = x + 15 * (size_t)K;
+                hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, 0.0, (const double*)x, q,
+                                   (const double*)nullptr);
+                hipLaunchKernelGGL(k_vi_fill, grid(15LL * K), blk, 0, nullptr, 15LL * K, z, (const double*)nullptr);
+                schur_kf(xp, z, nullptr);   // z = -B dx_p
+                double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                zero_scal();
+                hipLaunchKernelGGL(k_vi_pt_quad, grid(N), blk, 0, nullptr, d, xp, d.scal);
+                if (!chk() || !read_scal()) return GBA_ERR_HIP;
+                t3 = hs[0];
+                if (!dot(15LL * K, x, q, t1) || !dot(15LL * K, x, z, t2)) return GBA_ERR_HIP;
+                dHd = t1 - 2.0 * t2 + t3;
+            } else {
+                product(x, q, 0.0, nullptr);
+                if (!chk() || !dot(n, x, q, dHd)) return GBA_ERR_HIP;
+            }
+            if (!dot(n, d.b, x, bdx) || !dot(n, x, x, dd)) return GBA_ERR_HIP;
             const double L = -(bdx + 0.5 * dHd);
             hipLaunchKernelGGL(k_vi_step, grid(K + N), blk, 0, nullptr, d, x);
             double Fn = 0.0, xnorm = 0.0, dummy = 0.0;
@@ -1757,8 +1914,10 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     hipLaunchKernelGGL(k_vi_states_out, grid(K), blk, 0, nullptr, K, d.st, s15);
     if (!chk()) return GBA_ERR_HIP;
     if (hipMemcpy(P.states, s15, sizeof(double) * 15 * K, hipMemcpyDeviceToHost) != hipSuccess ||
-        (N > 0 && hipMemcpy(P.pts, d.X, sizeof(double) * 3 * N, hipMemcpyDeviceToHost) != hipSuccess))
+        (N > 0 && hipMemcpy(hX.data(), d.X, sizeof(double) * 3 * N, hipMemcpyDeviceToHost) != hipSuccess))
         return GBA_ERR_HIP;
+    for (int64_t q = 0; q < N; ++q)
+        for (int c = 0; c < 3; ++c) P.pts[3 * (size_t)pt_old[q] + c] = hX[3 * q + c];
     rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (report) *report = rep;
     if (n_log) *n_log = nl;
