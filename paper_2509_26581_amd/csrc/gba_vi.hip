@@ -438,21 +438,28 @@ struct VIDev {
     void* wk;              // double, or float when w32
     void* wp;
     int w32;
-    const int* qkf;        // [M] keyframe of the i-th observation in point order
-    const int* qpt;        // [M] its point
-    const double* qobs;    // [3 M] the observed pixels in point order
+    const int* qkf;        // [Mp] keyframe of the i-th observation in padded point order
+    const int* qpt;        // [Mp] its point, -1 in a pad slot
+    const double* qobs;    // [3 Mp] the observed pixels in point order
+    long long Mp;          // padded point-order length (a multiple of 64)
+    const int* longp;      // [nlong] the points with more than 64 observations
+    int nlong;
+    double* tb;            // [3 N] their partial sums (zero between passes)
     double* sm;            // [36 K] sum over a keyframe's observations of W C^-1 W^T
     double* icx;           // [135 (K - 1)] inertial cross blocks J_i^T Omega J_j (15 x 9)
     double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
     long long n() const { return 15LL * K + 3 * N; }
 };
 
-// PCG scalars on the device: three slots of dot accumulators {p.q, r.r,
-// r.z}, used round robin (step s accumulates into slot s % 3, takes the
+// PCG scalars on the device: three slots of dot accumulators {p.q parts,
+// r.r, r.z}, used round robin (step s accumulates into slot s % 3, takes the
 // previous r.z from slot (s + 2) % 3 and clears slot (s + 1) % 3 for the
 // next step, so no kernel reads a value another workgroup of it resets),
 // then the stop threshold, the stop flag and the step count
-enum { kAccPq = 0, kAccRr, kAccRz, kAccN };
+// p.q is summed in kPqParts parts (a workgroup adds to part blockIdx %
+// kPqParts: thousands of workgroups adding to one address serialise)
+constexpr int kPqParts = 256;
+enum { kAccPq = 0, kAccRr = kPqParts, kAccRz, kAccN };
 constexpr int kSlots = 3;
 enum { kThr = kSlots * kAccN, kDone, kSteps, kPcgScalars };
 
@@ -676,17 +683,18 @@ __global__ void k_vi_lin_stereo(VIDev d) {
 template <typename WT>
 __global__ void k_vi_lin_stereo_pts(VIDev d) {
     const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const bool valid = i0 < d.M;
-    const long long i = valid ? i0 : d.M - 1;
-    const int j = d.qpt[i], k = d.qkf[i];
+    const long long i = i0 < d.Mp ? i0 : d.Mp - 1;
+    const int jq = d.qpt[i];
+    const bool valid = i0 < d.Mp && jq >= 0;
+    const int j = valid ? jq : 0, k = valid ? d.qkf[i] : 0;
     const int l = (int)(threadIdx.x & 63);
-    const int jprev = __shfl_up(j, 1, 64);
-    const bool start = !valid || l == 0 || jprev != j;
+    const int jprev = __shfl_up(jq, 1, 64);
+    const bool start = !valid || l == 0 || jprev != jq;
     const SegScan seg(start);
     int head, end;
     segment_of(__ballot(start), l, head, end);
-    const bool first = i == 0 || d.qpt[i - 1] != j;
-    const bool lastp = i == d.M - 1 || d.qpt[i + 1] != j;
+    const bool first = i == 0 || d.qpt[i - 1] != jq;
+    const bool lastp = i == d.Mp - 1 || d.qpt[i + 1] != jq;
     const bool whole = (__shfl(first ? 1 : 0, head, 64) != 0) && lastp;
     double r[3], J[3][9];
     vi_stereo_whitened(d, d.qobs + 3 * i, k, j, valid, r, J);
@@ -1043,17 +1051,23 @@ __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double*
 // bias cross terms between consecutive keyframes.
 
 // z_j = sign C_j^-1 (sum_{e of j} W_e^T v_k(e) + add_j): observations in
-// point order, a point's sum across its run of the wavefront; a point whose
-// observations all sit in one wavefront is stored, one split across
-// wavefronts is added in parts (z is zero beforehand), add_j once
+// padded point order (a point's observations within one wavefront unless it
+// has more than 64; pad slots have point -1), a point's sum across its run of
+// the wavefront.  A whole run stores z_j and, with acc, adds -t_j . z_j to
+// acc (the point part of p . S p = p . A p - sum_j t_j . C_j^-1 t_j); a run
+// of a point split across wavefronts adds its part of t_j to tb for
+// k_vi_long_pts
 template <typename WT>
 __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const double* __restrict__ add,
-                               double sign, double* __restrict__ z, const double* __restrict__ ps) {
+                               double sign, double* __restrict__ z, const double* __restrict__ ps,
+                               double* __restrict__ acc) {
     if (pcg_done(ps)) return;
+    __shared__ double red[16];
     const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const bool valid = i0 < d.M;
-    const long long i = valid ? i0 : d.M - 1;
-    const int j = d.qpt[i], k = d.qkf[i];
+    const long long i = i0 < d.Mp ? i0 : d.Mp - 1;
+    const int j = d.qpt[i];
+    const bool valid = i0 < d.Mp && j >= 0;
+    const int jj = valid ? j : 0, k = valid ? d.qkf[i] : 0;
     const int l = (int)(threadIdx.x & 63);
     const int jprev = __shfl_up(j, 1, 64);
     const bool start = !valid || l == 0 || jprev != j;
@@ -1062,8 +1076,11 @@ __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const doub
     segment_of(__ballot(start), l, head, end);
     // the point's first and last observations in the whole order
     const bool first = i == 0 || d.qpt[i - 1] != j;
-    const bool last = i == d.M - 1 || d.qpt[i + 1] != j;
-    const bool whole_head = __shfl(first ? 1 : 0, head, 64) != 0;
+    const bool last = i == d.Mp - 1 || d.qpt[i + 1] != j;
+    const bool whole = (__shfl(first ? 1 : 0, head, 64) != 0) && last;
+    const double* Mi = d.mp + 9 * (size_t)jj;
+    double M[9];
+    for (int c = 0; c < 9; ++c) M[c] = Mi[c];
     const double* vk = v + 15 * (size_t)k;
     double W[18];
     load_w<WT>(d.wp, i, W);
@@ -1073,16 +1090,52 @@ __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const doub
         for (int a = 0; a < 6; ++a) u += W[3 * a + c] * vk[a];
         t[c] = seg.sum(valid ? u : 0.0);
     }
-    if (!valid || l != end) return;
-    if (add && whole_head)
-        for (int c = 0; c < 3; ++c) t[c] += add[3 * (size_t)j + c];
-    const double* Mi = d.mp + 9 * (size_t)j;
-    double o[3];
-    for (int a = 0; a < 3; ++a) o[a] = sign * (Mi[3 * a] * t[0] + Mi[3 * a + 1] * t[1] + Mi[3 * a + 2] * t[2]);
-    if (whole_head && last) {
-        for (int a = 0; a < 3; ++a) z[3 * (size_t)j + a] = o[a];
-    } else {
-        for (int a = 0; a < 3; ++a) atomic_add(z + 3 * (size_t)j + a, o[a]);
+    double tz = 0.0;
+    if (valid && l == end) {
+        if (whole) {
+            if (add)
+                for (int c = 0; c < 3; ++c) t[c] += add[3 * (size_t)j + c];
+            for (int a = 0; a < 3; ++a) {
+                const double o = sign * (M[3 * a] * t[0] + M[3 * a + 1] * t[1] + M[3 * a + 2] * t[2]);
+                z[3 * (size_t)j + a] = o;
+                tz += t[a] * o;
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) atomic_add(d.tb + 3 * (size_t)j + a, t[a]);
+        }
+    }
+    if (acc) {
+        tz = block_sum_vi(tz, red);
+        if (threadIdx.x == 0) atomic_add(acc + blockIdx.x % kPqParts, -tz);
+    }
+}
+
+// the points split across wavefronts (more than 64 observations): z_j =
+// sign C_j^-1 (t_j + add_j) from the parts in tb, -t_j . z_j into acc, tb
+// cleared for the next pass; one lane per such point
+__global__ void k_vi_long_pts(VIDev d, const double* __restrict__ add, double sign, double* __restrict__ z,
+                              const double* __restrict__ ps, double* __restrict__ acc) {
+    if (pcg_done(ps)) return;
+    __shared__ double red[16];
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    double tz = 0.0;
+    if (q < d.nlong) {
+        const int j = d.longp[q];
+        double t[3];
+        for (int c = 0; c < 3; ++c) {
+            t[c] = d.tb[3 * (size_t)j + c] + (add ? add[3 * (size_t)j + c] : 0.0);
+            d.tb[3 * (size_t)j + c] = 0.0;
+        }
+        const double* Mi = d.mp + 9 * (size_t)j;
+        for (int a = 0; a < 3; ++a) {
+            const double o = sign * (Mi[3 * a] * t[0] + Mi[3 * a + 1] * t[1] + Mi[3 * a + 2] * t[2]);
+            z[3 * (size_t)j + a] = o;
+            tz += t[a] * o;
+        }
+    }
+    if (acc) {
+        tz = block_sum_vi(tz, red);
+        if (threadIdx.x == 0) atomic_add(acc + blockIdx.x % kPqParts, -tz);
     }
 }
 
@@ -1196,10 +1249,12 @@ __global__ void k_vi_cross(VIDev d) {
 // keyframes k - 1 and k + 1 (inertial, and the bias random walk's -Omega_b);
 // one lane per keyframe row, no atomics
 __global__ void k_vi_schur_ap(VIDev d, double lam, const double* __restrict__ v, double* __restrict__ q,
-                              const double* __restrict__ ps) {
+                              const double* __restrict__ ps, double* __restrict__ acc) {
     if (pcg_done(ps)) return;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (t >= 15LL * d.K) return;
+    __shared__ double red[16];
+    const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool act = t0 < 15LL * d.K;
+    const long long t = act ? t0 : 0;
     const long long k = t / 15;
     const int row = (int)(t % 15);
     const double* H = d.hk + 225 * (size_t)k + 15 * row;
@@ -1225,7 +1280,11 @@ __global__ void k_vi_schur_ap(VIDev d, double lam, const double* __restrict__ v,
             u -= ((row < 12 ? d.wg : d.wa) / dt) * vi[row];
         }
     }
-    q[t] = u;
+    if (act) q[t] = u;
+    if (acc) {   // with acc: v . A v (the keyframe part of p . S p)
+        const double s = block_sum_vi(act ? vk[row] * u : 0.0, red);
+        if (threadIdx.x == 0) atomic_add(acc + blockIdx.x % kPqParts, s);
+    }
 }
 
 // q = lambda diag(D) v (the first term of the product; the others add)
@@ -1279,7 +1338,13 @@ __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, d
     __shared__ double red[16];
     if (ps[kDone] != 0.0) return;
     double* acc = ps + kAccN * slot;
-    const double pq = acc[kAccPq];
+    __shared__ double pq_s;
+    {
+        const double part = block_sum_vi(threadIdx.x < kPqParts ? acc[kAccPq + threadIdx.x] : 0.0, red);
+        if (threadIdx.x == 0) pq_s = part;
+        __syncthreads();
+    }
+    const double pq = pq_s;
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) ps[kDone] = 1.0;
         return;
@@ -1339,10 +1404,9 @@ __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, d
 }
 
 // step `slot`, continued: stop once r.r <= the threshold, else p = z + beta p
-// with beta = r.z / previous r.z; zb (the next product's point vector) is
-// cleared and the next slot's accumulators too
+// with beta = r.z / previous r.z; the next slot's accumulators are cleared
 __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, const double* __restrict__ z,
-                             double* __restrict__ p, double* __restrict__ zb, long long nzb) {
+                             double* __restrict__ p) {
     if (ps[kDone] != 0.0) return;
     const double* acc = ps + kAccN * slot;
     if (acc[kAccRr] <= ps[kThr]) {
@@ -1353,8 +1417,8 @@ __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, con
     const long long st = (long long)gridDim.x * blockDim.x;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += st)
         p[i] = z[i] + beta * p[i];
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nzb; i += st) zb[i] = 0.0;
-    if (blockIdx.x == 0 && threadIdx.x < kAccN) ps[kAccN * ((slot + 1) % kSlots) + threadIdx.x] = 0.0;
+    if (blockIdx.x == 0)
+        for (int e = threadIdx.x; e < kAccN; e += blockDim.x) ps[kAccN * ((slot + 1) % kSlots) + e] = 0.0;
 }
 
 __global__ void k_vi_dot(long long n, const double* __restrict__ a, const double* __restrict__ b,
@@ -1611,19 +1675,30 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     for (int64_t q = 0; q < P.n_pts; ++q)
         for (int c = 0; c < 3; ++c) hX[3 * q + c] = P.pts[3 * (size_t)pt_old[q] + c];
     const bool schur = o.solver == GBA_SOLVER_SCHUR;
-    // Schur form: the same observations in point order (a stable counting
-    // sort of the keyframe order), for the point sums of the products
-    std::vector<int> hqkf, hqpt;
+    // Schur form: the same observations in point order (stable in the
+    // keyframe order), padded so that a point's observations sit in one
+    // wavefront (64 slots) unless it has more than 64 of them
+    std::vector<int> hqkf, hqpt, hlong;
     std::vector<double> hqobs;
+    long long Mp = 0;
     if (schur) {
-        hqkf.assign((size_t)P.n_obs + 1, 0);
-        hqpt.assign((size_t)P.n_obs + 1, 0);
-        hqobs.assign(3 * (size_t)P.n_obs + 1, 0.0);
-        std::vector<int64_t> cnt((size_t)P.n_pts + 1, 0);
-        for (int64_t e = 0; e < P.n_obs; ++e) ++cnt[(size_t)hpt[e] + 1];
-        for (int64_t j = 0; j < P.n_pts; ++j) cnt[(size_t)j + 1] += cnt[(size_t)j];
+        std::vector<int64_t> cnt((size_t)P.n_pts, 0), at((size_t)P.n_pts, 0);
+        for (int64_t e = 0; e < P.n_obs; ++e) ++cnt[(size_t)hpt[e]];
+        for (int64_t j = 0; j < P.n_pts; ++j) {
+            const int64_t c = cnt[(size_t)j];
+            if (c == 0) continue;
+            if (c > 64) hlong.push_back((int)j);
+            else if (Mp % 64 + c > 64) Mp = (Mp + 63) / 64 * 64;
+            at[(size_t)j] = Mp;
+            Mp += c;
+        }
+        Mp = (Mp + 63) / 64 * 64;
+        if (Mp > INT32_MAX / 18) return GBA_ERR_UNSUPPORTED;
+        hqkf.assign((size_t)Mp + 1, 0);
+        hqpt.assign((size_t)Mp + 1, -1);
+        hqobs.assign(3 * (size_t)Mp + 1, 0.0);
         for (int64_t e = 0; e < P.n_obs; ++e) {
-            const size_t q = (size_t)cnt[(size_t)hpt[e]]++;
+            const size_t q = (size_t)at[(size_t)hpt[e]]++;
             hqkf[q] = hkf[e];
             hqpt[q] = hpt[e];
             for (int c = 0; c < 3; ++c) hqobs[3 * q + c] = hobs[3 * e + c];
@@ -1664,20 +1739,27 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         // W in FP32 takes half the doubles of FP64 (rounded up)
         d.w32 = o.precision == GBA_MIXED_FP32 ? 1 : 0;
         const size_t wn = (18 * 64 * (size_t)((M + 63) / 64) + 2) / (d.w32 ? 2 : 1);
-        int *qkf = nullptr, *qpt = nullptr;
+        const size_t wpn = (18 * 64 * (size_t)(Mp / 64) + 2) / (d.w32 ? 2 : 1);
+        int *qkf = nullptr, *qpt = nullptr, *lp = nullptr;
         double* qobs = nullptr;
         double *wk = nullptr, *wp = nullptr;
-        if (!B.up(&wk, (const double*)nullptr, wn) || !B.up(&wp, (const double*)nullptr, wn) ||
+        if (!B.up(&wk, (const double*)nullptr, wn) || !B.up(&wp, (const double*)nullptr, wpn) ||
             !B.up(&d.icx, (const double*)nullptr, 135 * (size_t)(K - 1)) ||
-            !B.up(&qkf, hqkf.data(), (size_t)M + 1) || !B.up(&qpt, hqpt.data(), (size_t)M + 1) ||
-            !B.up(&qobs, hqobs.data(), 3 * (size_t)M + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
-            !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1))
+            !B.up(&qkf, hqkf.data(), (size_t)Mp + 1) || !B.up(&qpt, hqpt.data(), (size_t)Mp + 1) ||
+            !B.up(&qobs, hqobs.data(), 3 * (size_t)Mp + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
+            !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1) ||
+            !B.up(&lp, hlong.empty() ? (const int*)nullptr : hlong.data(), hlong.size() + 1) ||
+            !B.up(&d.tb, (const double*)nullptr, 3 * (size_t)N + 1))
             return GBA_ERR_OOM;
+        if (hipMemset(d.tb, 0, sizeof(double) * (3 * (size_t)N + 1)) != hipSuccess) return GBA_ERR_HIP;
         d.qkf = qkf;
         d.qpt = qpt;
         d.qobs = qobs;
         d.wk = wk;
         d.wp = wp;
+        d.Mp = Mp;
+        d.longp = lp;
+        d.nlong = (int)hlong.size();
     }
     d.kf = dkf;
     d.pt = dpt;
@@ -1710,7 +1792,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     const long long n_scal = 8 + kPcgScalars;
     double* ps = d.scal + 8;   // PCG scalars
     auto zero_scal = [&]() {
-        hipLaunchKernelGGL(k_vi_fill, dim3(1), dim3(64), 0, nullptr, n_scal, d.scal, (const double*)nullptr);
+        hipLaunchKernelGGL(k_vi_fill, grid(n_scal), blk, 0, nullptr, n_scal, d.scal, (const double*)nullptr);
     };
     // cost of (st, X) into slot 0, and |x|^2 into slot 1 when asked
     auto cost_of = [&](const double* st, const double* X, bool xnorm, double& F, double& xn) {
@@ -1729,8 +1811,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_fill, grid(9 * N + 1), blk, 0, nullptr, 9 * N + 1, d.hp, none);
         if (M > 0) hipLaunchKernelGGL(k_vi_lin_stereo, grid(M), blk, 0, nullptr, d);
         if (M > 0 && schur) {
-            if (d.w32) hipLaunchKernelGGL(k_vi_lin_stereo_pts<float>, grid(M), blk, 0, nullptr, d);
-            else hipLaunchKernelGGL(k_vi_lin_stereo_pts<double>, grid(M), blk, 0, nullptr, d);
+            if (d.w32) hipLaunchKernelGGL(k_vi_lin_stereo_pts<float>, grid(Mp), blk, 0, nullptr, d);
+            else hipLaunchKernelGGL(k_vi_lin_stereo_pts<double>, grid(Mp), blk, 0, nullptr, d);
         }
         hipLaunchKernelGGL(k_vi_lin_inertial, grid(24LL * (K - 1)), blk, 0, nullptr, d);
         hipLaunchKernelGGL(k_vi_acc_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d);
@@ -1748,13 +1830,19 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out, g);
         hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out, g);
     };
-    // q = S v over the keyframes (the point vector through zb, clear on entry)
-    auto schur_product = [&](const double* v, double* out, double lam, const double* g) {
-        if (M > 0) {
-            if (d.w32) hipLaunchKernelGGL(k_vi_schur_pts<float>, grid(M), blk, 0, nullptr, d, v, (const double*)nullptr, 1.0, zb, g);
-            else hipLaunchKernelGGL(k_vi_schur_pts<double>, grid(M), blk, 0, nullptr, d, v, (const double*)nullptr, 1.0, zb, g);
-        }
-        hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, lam, v, out, g);
+    // z = sign C^-1 (B^T v + add) over the points (acc: -t . z added)
+    auto schur_pts = [&](const double* v, const double* add, double sign, double* out, const double* g,
+                         double* acc) {
+        if (M == 0) return;
+        if (d.w32) hipLaunchKernelGGL(k_vi_schur_pts<float>, grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g, acc);
+        else hipLaunchKernelGGL(k_vi_schur_pts<double>, grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g, acc);
+        if (d.nlong > 0)
+            hipLaunchKernelGGL(k_vi_long_pts, grid(d.nlong), blk, 0, nullptr, d, add, sign, out, g, acc);
+    };
+    // q = S v over the keyframes (the point vector through zb); acc: v . S v
+    auto schur_product = [&](const double* v, double* out, double lam, const double* g, double* acc) {
+        schur_pts(v, nullptr, 1.0, zb, g, acc);
+        hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, lam, v, out, g, acc);
         schur_kf(zb, out, g);
     };
     auto dot_blocks = [](long long len) { return dim3((unsigned)std::min<long long>(1024, (len + 255) / 256)); };
@@ -1789,7 +1877,6 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
                                -1.0, zb);
             hipLaunchKernelGGL(k_vi_neg, grid(nn), blk, 0, nullptr, nn, d.b, r, x);
             schur_kf(zb, r, none);
-            hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, zb, none);
         } else {
             hipLaunchKernelGGL(k_vi_precond_pts, grid(N), blk, 0, nullptr, d, lam, o.min_diag, o.max_diag);
             hipLaunchKernelGGL(k_vi_precond_kf, dim3((unsigned)((K + 3) / 4)), blk, 0, nullptr, d, lam, o.min_diag,
@@ -1803,17 +1890,19 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_pcg_init, dim3(1), dim3(1), 0, nullptr, ps, o.pcg_tol);
         const long long npt = schur ? 0 : N;
         const dim3 upd((unsigned)((K + 15) / 16 + (npt + 255) / 256));
-        const long long nzb = schur ? 3 * N : 0;
-        const dim3 dirg((unsigned)std::max(1LL, std::min<long long>(1024, (std::max(nn, nzb) + 255) / 256)));
+        const dim3 dirg((unsigned)std::max(1LL, std::min<long long>(1024, (nn + 255) / 256)));
         for (int it = 0; it < o.pcg_max_iters; ++it) {
             const int slot = it % kSlots;
-            if (schur) schur_product(pv, q, lam, ps);
-            else product(pv, q, lam, ps);
-            hipLaunchKernelGGL(k_vi_dot, dot_blocks(nn), blk, 0, nullptr, nn, (const double*)pv, (const double*)q,
-                               ps + kAccN * slot + kAccPq, (const double*)ps);
+            if (schur) {
+                schur_product(pv, q, lam, ps, ps + kAccN * slot + kAccPq);   // p . q summed inside
+            } else {
+                product(pv, q, lam, ps);
+                hipLaunchKernelGGL(k_vi_dot, dot_blocks(nn), blk, 0, nullptr, nn, (const double*)pv,
+                                   (const double*)q, ps + kAccN * slot + kAccPq, (const double*)ps);
+            }
             hipLaunchKernelGGL(k_vi_pcg_update, upd, blk, 0, nullptr, d, npt, ps, slot, (const double*)pv,
                                (const double*)q, x, r, z);
-            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv, zb, nzb);
+            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv);
             if ((it + 1) % kPcgSync == 0 && it + 1 < o.pcg_max_iters) {
                 if (!chk() || !read_scal()) return false;
                 if (hs[8 + kDone] != 0.0) break;
@@ -1823,14 +1912,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             // x_p = -C^-1 (b_p + B^T x_k)
             double* xp = x + 15 * (size_t)K;
             hipLaunchKernelGGL(k_vi_fill, grid(3 * N), blk, 0, nullptr, 3 * N, xp, none);
-            if (M > 0) {
-                if (d.w32)
-                    hipLaunchKernelGGL(k_vi_schur_pts<float>, grid(M), blk, 0, nullptr, d, (const double*)x,
-                                       (const double*)(d.b + 15 * (size_t)K), -1.0, xp, none);
-                else
-                    hipLaunchKernelGGL(k_vi_schur_pts<double>, grid(M), blk, 0, nullptr, d, (const double*)x,
-                                       (const double*)(d.b + 15 * (size_t)K), -1.0, xp, none);
-            }
+            schur_pts(x, d.b + 15 * (size_t)K, -1.0, xp, none, nullptr);
         }
         if (!chk() || !read_scal()) return false;
         iters = (int)hs[8 + kSteps];
@@ -1861,7 +1943,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             if (schur) {
                 const double* xp = x + 15 * (size_t)K;
                 hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, 0.0, (const double*)x, q,
-                                   (const double*)nullptr);
+                                   (const double*)nullptr, (double*)nullptr);
                 hipLaunchKernelGGL(k_vi_fill, grid(15LL * K), blk, 0, nullptr, 15LL * K, z, (const double*)nullptr);
                 schur_kf(xp, z, nullptr);   // z = -B dx_p
                 double t1 = 0.0, t2 = 0.0, t3 = 0.0;
