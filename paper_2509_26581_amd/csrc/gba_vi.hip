@@ -392,20 +392,20 @@ __device__ __forceinline__ double block_sum_vi(double v, double* red) {
 }
 
 // ==========================================================================
-// The visual-inertial LM solve (Background Eq. 8; Sec. V-C) in the paper's
-// solver form for it: PCG on the whole damped system over keyframe states and
-// points (no point elimination), block-Jacobi preconditioned (15 x 15
-// keyframe blocks, 3 x 3 point blocks), FP64.  Unknowns per keyframe: dtheta,
-// dp, dv, dbg, dba (the rotation updated on the right); per point: dX.  The
-// first keyframe is held fixed (its columns are zero).  Terms:
+// The visual-inertial LM solve (Background Eq. 8; Sec. V-C), FP64
+// arithmetic, in two forms of the damped step: the points eliminated (Eq.
+// 5-6 on the keyframe / point partition) and PCG on the keyframe Schur
+// complement, or the paper's form for its VI runs, PCG on the whole damped
+// system over keyframe states and points; block-Jacobi preconditioned
+// (15 x 15 keyframe blocks; 3 x 3 point blocks in the whole-system form).
+// Unknowns per keyframe: dtheta, dp, dv, dbg, dba (the rotation updated on
+// the right); per point: dX.  The first keyframe is held fixed (its columns
+// are zero).  Terms:
 //   stereo   1/2 rho(|r|^2 / sigma^2), Huber on the squared norm, IRLS
 //            whitening sqrt(w) / sigma;
 //   inertial 1/2 r^T Omega r, Omega the inverse preintegrated covariance;
 //   bias     1/2 r^T Omega_b r, r = b_j - b_i, Omega_b from the random-walk
 //            densities and the interval length.
-// Products H v are sums over the terms of J^T Omega J v with the vertex
-// outputs added atomically; the stored Jacobians are the terms' whitened
-// (stereo) or raw (inertial, with Omega applied in the product) blocks.
 // ==========================================================================
 constexpr int kSt = 21;   // device keyframe state: R (row-major), p, v, bg, ba
 
