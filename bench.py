@@ -9,6 +9,11 @@ One step = one 20-trial solve from the perturbed start (device-side reset of
 the parameters, then gba_solve).  Inputs are resident on the device before the
 timed region.
 
+Visual-inertial (in the same JSON line, "vi"; alone with --vi): 2,000
+keyframes with a 200 Hz IMU, 300k points, ~2.07M stereo observations, Huber,
+LM with PCG on the keyframe Schur complement (W in FP32, FP64 arithmetic);
+LM iter/s over the trials, the call's set-up reported apart.
+
 Serving (in the same JSON line, "serving"): 512 local-BA requests (5-40
 keyframes, 500-20k points, tracks 2-10 inside a local window, first two
 keyframes fixed, 10 trials each, mixed FP32): one at a time, all at once
@@ -16,7 +21,7 @@ keyframes fixed, 10 trials each, mixed FP32): one at a time, all at once
 (p50/p99 latency from submission to result).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
-                  [--workload bal1m|bal8m|small] [--no-cpu-baseline] [--no-serve]
+                  [--workload bal1m|bal8m|small] [--no-cpu-baseline] [--no-serve] [--no-vi]
                   [--serve-only] [--accumulation 0|1|2] [--tiles-per-block N]
 """
 import argparse
@@ -243,6 +248,8 @@ def main():
     ap.add_argument("--tiles-per-block", type=int, default=0,
                     help="point tiles per point-pass workgroup (0: automatic)")
     ap.add_argument("--no-serve", action="store_true", help="skip the local-BA stream")
+    ap.add_argument("--no-vi", action="store_true",
+                    help="skip the visual-inertial configuration (reported as \"vi\")")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the back-to-back Schur-product timing (for kernel traces)")
     ap.add_argument("--serve-only", action="store_true")
@@ -434,6 +441,9 @@ def main():
         "roofline": roofline,
         "fp64_comparison": compare,
     }
+    line["vi"] = None
+    if not args.no_vi and args.workload == "bal1m":
+        line["vi"] = vi_measurement(gba, args)["vi"]
     line["serving"] = None
     if not args.no_serve:
         line["serving"] = serving_measurement(gba, synth, args.serve_requests, prec_id,
