@@ -206,7 +206,8 @@ def vi_measurement(gba, args):
     solver = gba.GBA_SOLVER_SCHUR if args.vi_solver == "schur" else gba.GBA_SOLVER_FULL
     prec = gba.GBA_MIXED_FP32 if (args.vi_precision == "fp32" and args.vi_solver == "schur") \
         else gba.GBA_FP64
-    opts = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6, solver=solver, precision=prec)
+    opts = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6, solver=solver, precision=prec,
+                          pcg_rejection_ratio=args.vi_ratio)
     kw = dict(sigma_px=1.0, huber_delta2=7.815, sigma_gw=2e-5, sigma_aw=3e-3, options=opts)
     trials = args.trials or 10
     gba.gba_vi_solve(0, states, pts0, sc.st_kf, sc.st_pt, sc.st_obs, sc.intr, pre, 1, **kw)  # warm-up
@@ -216,7 +217,8 @@ def vi_measurement(gba, args):
     el = time.perf_counter() - t0
     return {"vi": {"workload": f"{K} keyframes (0.25 s apart, 200 Hz IMU), {len(sc.pts)} points, "
                                f"{len(sc.st_kf)} stereo observations, Huber delta^2 7.815, "
-                               f"{trials} LM trials, PCG tol 1e-6 max 100",
+                               f"{trials} LM trials, PCG tol 1e-6 max 100"
+                               + (f" rejection ratio {args.vi_ratio:g}" if args.vi_ratio > 0 else ""),
                    "solver": args.vi_solver,
                    "w_storage": "f32" if prec == gba.GBA_MIXED_FP32 else "f64",
                    # the set-up of the call (orderings, allocation, uploads) is reported
@@ -276,6 +278,8 @@ def main():
     ap.add_argument("--vi-precision", default="fp32", choices=["fp32", "fp64"],
                     help="visual-inertial Schur form: the per-observation blocks W in FP32 "
                          "(FP64 arithmetic), or everything FP64")
+    ap.add_argument("--vi-ratio", type=float, default=0.0,
+                    help="visual-inertial PCG rejection ratio (0: none)")
     ap.add_argument("--vi-solver", default="schur", choices=["schur", "full"],
                     help="visual-inertial step: PCG on the keyframe Schur complement, or on the "
                          "whole system")

@@ -580,6 +580,10 @@ typedef struct gba_vi_options {
                                   stream stored in FP32, all arithmetic and
                                   every other array FP64                     */
     int reserved1;
+    double pcg_rejection_ratio;/* stop PCG and keep the best iterate when
+                                  |r_k| > ratio * min_m<=k |r_m| (the
+                                  paper's VI runs use 10); <= 0 or Inf
+                                  disables (default: disabled)               */
 } gba_vi_options;
 
 void gba_vi_default_options(gba_vi_options* out);

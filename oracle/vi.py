@@ -233,13 +233,14 @@ class VIProblem:
         v = -bk + CiBt.T @ bp
         return 0.5 * (S + S.T), v, A, B, C, bk, bp
 
-    def schur_pcg_step(self, lin, lam, min_diag, max_diag, tol, max_iters):
+    def schur_pcg_step(self, lin, lam, min_diag, max_diag, tol, max_iters, ratio=np.inf):
         """The damped step by PCG on the keyframe Schur complement (relative
-        tolerance, no rejection test), then point back-substitution.
-        Returns (dx over all variables, PCG steps)."""
+        tolerance, the rejection test of oracle.pcg.pcg with ratio), then
+        point back-substitution.  Returns (dx over all variables, PCG
+        steps); the PCG's stop reason is kept in self.last_reason."""
         S, v, A, B, C, bk, bp = self.reduced_system(lin, lam, min_diag, max_diag)
         M = _pcg.block_jacobi(S, 15)
-        xk, steps, _ = _pcg.pcg(S, v, M, tol, True, max_iters)
+        xk, steps, self.last_reason = _pcg.pcg(S, v, M, tol, True, max_iters, ratio)
         xp = np.linalg.solve(C, -bp - B.T @ xk)
         dx = np.zeros(len(lin["free"]))
         dx[lin["free"]] = np.concatenate([xk, xp])

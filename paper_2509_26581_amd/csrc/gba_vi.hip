@@ -459,9 +459,11 @@ struct VIDev {
 // p.q is summed in kPqParts parts (a workgroup adds to part blockIdx %
 // kPqParts: thousands of workgroups adding to one address serialise)
 constexpr int kPqParts = 256;
-enum { kAccPq = 0, kAccRr = kPqParts, kAccRz, kAccN };
+// per slot also: the least r.r so far (the rejection test), a breakdown flag
+// set by the update kernel and the stop decision of the direction kernel
+enum { kAccPq = 0, kAccRr = kPqParts, kAccRz, kAccMin, kAccBreak, kAccStop, kAccN };
 constexpr int kSlots = 3;
-enum { kThr = kSlots * kAccN, kDone, kSteps, kPcgScalars };
+enum { kThr = kSlots * kAccN, kDone, kSteps, kRatio2, kPcgScalars };
 
 __device__ __forceinline__ bool pcg_done(const double* ps) { return ps && ps[kDone] != 0.0; }
 
@@ -1316,13 +1318,17 @@ __global__ void k_vi_dot2(long long n, const double* __restrict__ r, const doubl
 }
 
 // the start: threshold tol^2 r0.r0 (r0.r0 and r0.z0 in the last slot);
-// nothing to do when r0 is already below it or r0.z0 <= 0
-__global__ void k_vi_pcg_init(double* __restrict__ ps, double tol) {
-    const double* a = ps + kAccN * (kSlots - 1);
+// nothing to do when r0 is already below it or r0.z0 <= 0.  ratio2: the
+// squared rejection ratio (0: no rejection test)
+__global__ void k_vi_pcg_init(double* __restrict__ ps, double tol, double ratio2) {
+    double* a = ps + kAccN * (kSlots - 1);
     const double thr = tol * tol * a[kAccRr];
     ps[kThr] = thr;
     ps[kDone] = (a[kAccRr] > thr && a[kAccRz] > 0.0) ? 0.0 : 1.0;
     ps[kSteps] = 0.0;
+    ps[kRatio2] = ratio2;
+    a[kAccMin] = a[kAccRr];
+    a[kAccStop] = ps[kDone];
 }
 
 // step `slot`: alpha = r.z / p.q (a step with p.q <= 0 ends the iteration at
@@ -1345,8 +1351,8 @@ __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, d
         __syncthreads();
     }
     const double pq = pq_s;
-    if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) ps[kDone] = 1.0;
+    if (!(pq > 0.0)) {   // breakdown: decided by every workgroup alike
+        if (blockIdx.x == 0 && threadIdx.x == 0) acc[kAccBreak] = 1.0;
         return;
     }
     const double alpha = ps[kAccN * ((slot + kSlots - 1) % kSlots) + kAccRz] / pq;
@@ -1403,22 +1409,58 @@ __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, d
     }
 }
 
-// step `slot`, continued: stop once r.r <= the threshold, else p = z + beta p
-// with beta = r.z / previous r.z; the next slot's accumulators are cleared
+// step `slot`, continued, with the decisions of the PCG rules: a breakdown
+// ends at the current iterate; with the rejection test, a new least r.r
+// saves x in xb, and r.r > ratio^2 times the least ends the iteration with
+// xb restored; r.r <= the threshold ends it; otherwise p = z + beta p with
+// beta = r.z / previous r.z.  Every workgroup takes the same decisions from
+// this slot's and the previous slot's values (which no workgroup of this
+// kernel writes); workgroup 0 records them (this slot's least r.r and stop
+// flag, the stop flag the later kernels read) and clears the next slot.
 __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, const double* __restrict__ z,
-                             double* __restrict__ p) {
-    if (ps[kDone] != 0.0) return;
-    const double* acc = ps + kAccN * slot;
-    if (acc[kAccRr] <= ps[kThr]) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) ps[kDone] = 1.0;
-        return;
-    }
-    const double beta = acc[kAccRz] / ps[kAccN * ((slot + kSlots - 1) % kSlots) + kAccRz];
+                             double* __restrict__ p, double* __restrict__ x, double* __restrict__ xb) {
+    double* acc = ps + kAccN * slot;
+    const double* prev = ps + kAccN * ((slot + kSlots - 1) % kSlots);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     const long long st = (long long)gridDim.x * blockDim.x;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += st)
-        p[i] = z[i] + beta * p[i];
+    const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (blockIdx.x == 0)
         for (int e = threadIdx.x; e < kAccN; e += blockDim.x) ps[kAccN * ((slot + 1) % kSlots) + e] = 0.0;
+    if (prev[kAccStop] != 0.0 || acc[kAccBreak] != 0.0) {
+        if (lead) {
+            acc[kAccStop] = 1.0;
+            acc[kAccMin] = prev[kAccMin];
+            ps[kDone] = 1.0;
+        }
+        return;
+    }
+    const double rr = acc[kAccRr], least = prev[kAccMin], ratio2 = ps[kRatio2];
+    double nmin = least;
+    if (ratio2 > 0.0) {
+        if (rr < least) {
+            nmin = rr;
+            for (long long i = i0; i < n; i += st) xb[i] = x[i];
+        } else if (rr > ratio2 * least) {
+            for (long long i = i0; i < n; i += st) x[i] = xb[i];
+            if (lead) {
+                acc[kAccStop] = 1.0;
+                acc[kAccMin] = least;
+                ps[kDone] = 1.0;
+            }
+            return;
+        }
+    }
+    if (rr <= ps[kThr]) {
+        if (lead) {
+            acc[kAccStop] = 1.0;
+            acc[kAccMin] = nmin;
+            ps[kDone] = 1.0;
+        }
+        return;
+    }
+    const double beta = acc[kAccRz] / prev[kAccRz];
+    for (long long i = i0; i < n; i += st) p[i] = z[i] + beta * p[i];
+    if (lead) acc[kAccMin] = nmin;
 }
 
 __global__ void k_vi_dot(long long n, const double* __restrict__ a, const double* __restrict__ b,
@@ -1605,6 +1647,7 @@ void gba_vi_default_options(gba_vi_options* o) {
     o->solver = GBA_SOLVER_SCHUR;
     o->precision = GBA_FP64;
     o->reserved1 = 0;
+    o->pcg_rejection_ratio = 0.0;
     o->pcg_tol = 1e-8;
     o->initial_lambda = 1e-4;
     o->min_diag = 1e-6;
@@ -1713,7 +1756,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     d.N = N;
     d.M = M;
     double *s15 = nullptr, *pre = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr,
-           *q = nullptr;
+           *q = nullptr, *xb = nullptr;
     int *dkf = nullptr, *dpt = nullptr;
     double* obs = nullptr;
     if (!B.up(&s15, P.states, 15 * (size_t)K) || !B.up(&d.st, (const double*)nullptr, kSt * (size_t)K) ||
@@ -1732,7 +1775,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&d.mki, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
         !B.up(&d.scal, (const double*)nullptr, 8 + kPcgScalars) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
         !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
-        !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n))
+        !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n) ||
+        !B.up(&xb, (const double*)nullptr, (size_t)n))
         return GBA_ERR_OOM;
     double* zb = nullptr;   // Schur form: the point vector of a product
     if (schur) {
@@ -1887,7 +1931,10 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_apply_m, grid(nm), blk, 0, nullptr, d, r, z, none);
         hipLaunchKernelGGL(k_vi_copy, grid(nn), blk, 0, nullptr, nn, (const double*)z, pv);
         hipLaunchKernelGGL(k_vi_dot2, dot_blocks(nn), blk, 0, nullptr, nn, r, z, ps + kAccN * (kSlots - 1));
-        hipLaunchKernelGGL(k_vi_pcg_init, dim3(1), dim3(1), 0, nullptr, ps, o.pcg_tol);
+        const double ratio2 = (o.pcg_rejection_ratio > 0.0 && std::isfinite(o.pcg_rejection_ratio))
+                                  ? o.pcg_rejection_ratio * o.pcg_rejection_ratio : 0.0;
+        hipLaunchKernelGGL(k_vi_fill, grid(nn), blk, 0, nullptr, nn, xb, none);   // the best iterate: x0 = 0
+        hipLaunchKernelGGL(k_vi_pcg_init, dim3(1), dim3(1), 0, nullptr, ps, o.pcg_tol, ratio2);
         const long long npt = schur ? 0 : N;
         const dim3 upd((unsigned)((K + 15) / 16 + (npt + 255) / 256));
         const dim3 dirg((unsigned)std::max(1LL, std::min<long long>(1024, (nn + 255) / 256)));
@@ -1902,7 +1949,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             }
             hipLaunchKernelGGL(k_vi_pcg_update, upd, blk, 0, nullptr, d, npt, ps, slot, (const double*)pv,
                                (const double*)q, x, r, z);
-            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv);
+            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv, x, xb);
             if ((it + 1) % kPcgSync == 0 && it + 1 < o.pcg_max_iters) {
                 if (!chk() || !read_scal()) return false;
                 if (hs[8 + kDone] != 0.0) break;

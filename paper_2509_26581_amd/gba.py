@@ -135,7 +135,8 @@ class gba_vi_options(ctypes.Structure):
     _fields_ = [("pcg_max_iters", ctypes.c_int), ("solver", ctypes.c_int),
                 ("pcg_tol", ctypes.c_double), ("initial_lambda", ctypes.c_double),
                 ("min_diag", ctypes.c_double), ("max_diag", ctypes.c_double),
-                ("precision", ctypes.c_int), ("reserved1", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("reserved1", ctypes.c_int),
+                ("pcg_rejection_ratio", ctypes.c_double)]
 
 
 _SIGS = {

@@ -107,6 +107,32 @@ def test_vi_truncated_schur_step_matches_the_oracle(k):
     assert abs(t["step_norm"] - np.linalg.norm(dx)) <= 1e-8 * np.linalg.norm(dx)
 
 
+@pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
+def test_vi_rejection_ratio(solver):
+    # a ratio just above 1 ends the PCG at the first rise of |r| and returns
+    # the best iterate; in the Schur form the step matches the oracle's Schur
+    # PCG with the same ratio, in both forms an infinite or zero ratio is the
+    # plain PCG
+    from oracle import pcg as opcg
+    sc, prob, x0, states, pre_g = _setup(seed=5, n_kf=9, n_pts=120, delta2=7.815)
+    kw = dict(pcg_tol=0.0, pcg_max_iters=60, solver=solver)
+    _, _, _, plain = _gpu(sc, states, x0, pre_g, 1, 7.815, **kw)
+    _, _, _, off = _gpu(sc, states, x0, pre_g, 1, 7.815, pcg_rejection_ratio=float("inf"), **kw)
+    assert off[0]["pcg_iters"] == plain[0]["pcg_iters"] == 60
+    # (atomic sums: two runs agree to rounding, not bit for bit)
+    assert abs(off[0]["step_norm"] - plain[0]["step_norm"]) <= 1e-10 * plain[0]["step_norm"]
+    _, _, _, rej = _gpu(sc, states, x0, pre_g, 1, 7.815, pcg_rejection_ratio=1.001, **kw)
+    assert rej[0]["pcg_iters"] < 60
+    if solver == gba.GBA_SOLVER_SCHUR:
+        lin = prob.linearize(x0)
+        dx, steps = prob.schur_pcg_step(lin, 1e-4, 1e-6, 1e32, 0.0, 60, ratio=1.001)
+        assert prob.last_reason == opcg.DONE_REJECTED
+        assert rej[0]["pcg_iters"] == steps
+        L = prob.model_decrease(lin, dx)
+        assert abs(rej[0]["model_decrease"] - L) <= 1e-8 * abs(L)
+        assert abs(rej[0]["step_norm"] - np.linalg.norm(dx)) <= 1e-8 * np.linalg.norm(dx)
+
+
 @pytest.mark.parametrize("precision", [gba.GBA_FP64, gba.GBA_MIXED_FP32])
 def test_vi_long_tracks_match_the_oracle(precision):
     # 70 keyframes that all see the same 40 points: every point has more
