@@ -445,6 +445,8 @@ struct VIDev {
     const int* longp;      // [nlong] the points with more than 64 observations
     int nlong;
     double* tb;            // [3 N] their partial sums (zero between passes)
+    const int* lslot;      // [nlslot] the point-order slots of their observations
+    long long nlslot;
     double* sm;            // [36 K] sum over a keyframe's observations of W C^-1 W^T
     double* icx;           // [135 (K - 1)] inertial cross blocks J_i^T Omega J_j (15 x 9)
     double fx, fy, cx, cy, base, inv_sigma, delta2, wg, wa;   // wg, wa: 1 / sigma_w^2
@@ -1059,12 +1061,27 @@ __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double*
 // acc (the point part of p . S p = p . A p - sum_j t_j . C_j^-1 t_j); a run
 // of a point split across wavefronts adds its part of t_j to tb for
 // k_vi_long_pts
-template <typename WT>
-__global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const double* __restrict__ add,
-                               double sign, double* __restrict__ z, const double* __restrict__ ps,
-                               double* __restrict__ acc) {
+//
+// kFuse (the PCG product, sign 1, no add): the keyframe side too, q_k -=
+// sum_{e of k} W_e z_j(e), in the same pass: z_j goes from the run's last
+// lane to the run, each observation's W_e z_j is added to the workgroup's
+// LDS partials of the keyframes kbase .. kbase + kKfWin - 1 (kbase the least
+// keyframe the workgroup sees; points are numbered by first observing
+// keyframe, so a workgroup's keyframes lie close together; one further out
+// is added to q directly), and the partials go to q with one atomic add
+// each.  Split points take this step in k_vi_long_kf.
+constexpr int kKfWin = 64;
+constexpr int kFuseBlock = 512;
+
+template <typename WT, bool kFuse>
+__global__ __launch_bounds__(1024) void k_vi_schur_pts(VIDev d, const double* __restrict__ v,
+                                                      const double* __restrict__ add, double sign,
+                                                      double* __restrict__ z, const double* __restrict__ ps,
+                                                      double* __restrict__ acc, double* __restrict__ q) {
     if (pcg_done(ps)) return;
     __shared__ double red[16];
+    __shared__ double part[kFuse ? kKfWin * 6 : 1];
+    __shared__ int kmin_w[16];
     const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const long long i = i0 < d.Mp ? i0 : d.Mp - 1;
     const int j = d.qpt[i];
@@ -1079,6 +1096,7 @@ __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const doub
     // the point's first and last observations in the whole order
     const bool first = i == 0 || d.qpt[i - 1] != j;
     const bool last = i == d.Mp - 1 || d.qpt[i + 1] != j;
+    // (the run is the point's every observation; meaningful at the run's last lane)
     const bool whole = (__shfl(first ? 1 : 0, head, 64) != 0) && last;
     const double* Mi = d.mp + 9 * (size_t)jj;
     double M[9];
@@ -1092,24 +1110,71 @@ __global__ void k_vi_schur_pts(VIDev d, const double* __restrict__ v, const doub
         for (int a = 0; a < 6; ++a) u += W[3 * a + c] * vk[a];
         t[c] = seg.sum(valid ? u : 0.0);
     }
-    double tz = 0.0;
+    double tz = 0.0, o[3] = {0.0, 0.0, 0.0};
     if (valid && l == end) {
         if (whole) {
             if (add)
                 for (int c = 0; c < 3; ++c) t[c] += add[3 * (size_t)j + c];
             for (int a = 0; a < 3; ++a) {
-                const double o = sign * (M[3 * a] * t[0] + M[3 * a + 1] * t[1] + M[3 * a + 2] * t[2]);
-                z[3 * (size_t)j + a] = o;
-                tz += t[a] * o;
+                o[a] = sign * (M[3 * a] * t[0] + M[3 * a + 1] * t[1] + M[3 * a + 2] * t[2]);
+                z[3 * (size_t)j + a] = o[a];
+                tz += t[a] * o[a];
             }
         } else {
             for (int a = 0; a < 3; ++a) atomic_add(d.tb + 3 * (size_t)j + a, t[a]);
+        }
+    }
+    if (kFuse) {
+        // the least keyframe of the workgroup's observations
+        int km = valid ? k : 0x7fffffff;
+        for (int off = 32; off > 0; off >>= 1) km = min(km, __shfl_xor(km, off, 64));
+        if (l == 0) kmin_w[threadIdx.x >> 6] = km;
+        for (int e = threadIdx.x; e < kKfWin * 6; e += blockDim.x) part[e] = 0.0;
+        __syncthreads();
+        int kbase = 0x7fffffff;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) kbase = min(kbase, kmin_w[w]);
+        // z_j and the run's wholeness from its last lane (`whole` holds
+        // there only)
+        double zj[3];
+        for (int a = 0; a < 3; ++a) zj[a] = __shfl(o[a], end, 64);
+        const bool run_whole = __shfl(whole ? 1 : 0, end, 64) != 0;
+        if (valid && run_whole) {
+            const int kk = k - kbase;
+            for (int a = 0; a < 6; ++a) {
+                const double y = W[3 * a] * zj[0] + W[3 * a + 1] * zj[1] + W[3 * a + 2] * zj[2];
+                if (kk < kKfWin) atomicAdd(part + 6 * kk + a, -y);
+                else if (k != 0) atomic_add(q + 15 * (size_t)k + a, -y);
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; kbase != 0x7fffffff && e < kKfWin * 6; e += blockDim.x) {
+            const int kf = kbase + e / 6;
+            const double val = part[e];
+            if (val != 0.0 && kf < d.K && kf != 0) atomic_add(q + 15 * (size_t)kf + e % 6, val);
         }
     }
     if (acc) {
         tz = block_sum_vi(tz, red);
         if (threadIdx.x == 0) atomic_add(acc + blockIdx.x % kPqParts, -tz);
     }
+}
+
+// the keyframe side of the product for the observations of split points:
+// q_k -= W_e z_j, one lane per such observation (their slots in lslot)
+template <typename WT>
+__global__ void k_vi_long_kf(VIDev d, const double* __restrict__ z, double* __restrict__ q,
+                             const double* __restrict__ ps) {
+    if (pcg_done(ps)) return;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= d.nlslot) return;
+    const long long i = d.lslot[t];
+    const int j = d.qpt[i], k = d.qkf[i];
+    if (k == 0) return;
+    double W[18];
+    load_w<WT>(d.wp, i, W);
+    const double zj[3] = {z[3 * (size_t)j], z[3 * (size_t)j + 1], z[3 * (size_t)j + 2]};
+    for (int a = 0; a < 6; ++a)
+        atomic_add(q + 15 * (size_t)k + a, -(W[3 * a] * zj[0] + W[3 * a + 1] * zj[1] + W[3 * a + 2] * zj[2]));
 }
 
 // the points split across wavefronts (more than 64 observations): z_j =
@@ -1721,7 +1786,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     // Schur form: the same observations in point order (stable in the
     // keyframe order), padded so that a point's observations sit in one
     // wavefront (64 slots) unless it has more than 64 of them
-    std::vector<int> hqkf, hqpt, hlong;
+    std::vector<int> hqkf, hqpt, hlong, hlslot;
     std::vector<double> hqobs;
     long long Mp = 0;
     if (schur) {
@@ -1746,6 +1811,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             hqpt[q] = hpt[e];
             for (int c = 0; c < 3; ++c) hqobs[3 * q + c] = hobs[3 * e + c];
         }
+        for (const int j : hlong)
+            for (int64_t q = at[(size_t)j] - cnt[(size_t)j]; q < at[(size_t)j]; ++q) hlslot.push_back((int)q);
     }
     if (hipSetDevice(device) != hipSuccess) return GBA_ERR_HIP;
     const int K = P.n_kf;
@@ -1784,7 +1851,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         d.w32 = o.precision == GBA_MIXED_FP32 ? 1 : 0;
         const size_t wn = (18 * 64 * (size_t)((M + 63) / 64) + 2) / (d.w32 ? 2 : 1);
         const size_t wpn = (18 * 64 * (size_t)(Mp / 64) + 2) / (d.w32 ? 2 : 1);
-        int *qkf = nullptr, *qpt = nullptr, *lp = nullptr;
+        int *qkf = nullptr, *qpt = nullptr, *lp = nullptr, *ls = nullptr;
         double* qobs = nullptr;
         double *wk = nullptr, *wp = nullptr;
         if (!B.up(&wk, (const double*)nullptr, wn) || !B.up(&wp, (const double*)nullptr, wpn) ||
@@ -1793,6 +1860,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             !B.up(&qobs, hqobs.data(), 3 * (size_t)Mp + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
             !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1) ||
             !B.up(&lp, hlong.empty() ? (const int*)nullptr : hlong.data(), hlong.size() + 1) ||
+            !B.up(&ls, hlslot.empty() ? (const int*)nullptr : hlslot.data(), hlslot.size() + 1) ||
             !B.up(&d.tb, (const double*)nullptr, 3 * (size_t)N + 1))
             return GBA_ERR_OOM;
         if (hipMemset(d.tb, 0, sizeof(double) * (3 * (size_t)N + 1)) != hipSuccess) return GBA_ERR_HIP;
@@ -1804,6 +1872,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         d.Mp = Mp;
         d.longp = lp;
         d.nlong = (int)hlong.size();
+        d.lslot = ls;
+        d.nlslot = (long long)hlslot.size();
     }
     d.kf = dkf;
     d.pt = dpt;
@@ -1878,16 +1948,35 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     auto schur_pts = [&](const double* v, const double* add, double sign, double* out, const double* g,
                          double* acc) {
         if (M == 0) return;
-        if (d.w32) hipLaunchKernelGGL(k_vi_schur_pts<float>, grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g, acc);
-        else hipLaunchKernelGGL(k_vi_schur_pts<double>, grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g, acc);
+        double* none_q = nullptr;
+        if (d.w32)
+            hipLaunchKernelGGL((k_vi_schur_pts<float, false>), grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g,
+                               acc, none_q);
+        else
+            hipLaunchKernelGGL((k_vi_schur_pts<double, false>), grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g,
+                               acc, none_q);
         if (d.nlong > 0)
             hipLaunchKernelGGL(k_vi_long_pts, grid(d.nlong), blk, 0, nullptr, d, add, sign, out, g, acc);
     };
-    // q = S v over the keyframes (the point vector through zb); acc: v . S v
+    // q = S v over the keyframes in one pass over the point-order W (the
+    // point vector through zb): A v first, then the fused point pass adds
+    // -B C^-1 B^T v; acc: v . S v
+    const dim3 fuse_grid((unsigned)std::max(1LL, (Mp + kFuseBlock - 1) / kFuseBlock));
     auto schur_product = [&](const double* v, double* out, double lam, const double* g, double* acc) {
-        schur_pts(v, nullptr, 1.0, zb, g, acc);
         hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, lam, v, out, g, acc);
-        schur_kf(zb, out, g);
+        if (M == 0) return;
+        const double* no_add = nullptr;
+        if (d.w32)
+            hipLaunchKernelGGL((k_vi_schur_pts<float, true>), fuse_grid, dim3(kFuseBlock), 0, nullptr, d, v, no_add,
+                               1.0, zb, g, acc, out);
+        else
+            hipLaunchKernelGGL((k_vi_schur_pts<double, true>), fuse_grid, dim3(kFuseBlock), 0, nullptr, d, v, no_add,
+                               1.0, zb, g, acc, out);
+        if (d.nlong > 0) {
+            hipLaunchKernelGGL(k_vi_long_pts, grid(d.nlong), blk, 0, nullptr, d, no_add, 1.0, zb, g, acc);
+            if (d.w32) hipLaunchKernelGGL(k_vi_long_kf<float>, grid(d.nlslot), blk, 0, nullptr, d, (const double*)zb, out, g);
+            else hipLaunchKernelGGL(k_vi_long_kf<double>, grid(d.nlslot), blk, 0, nullptr, d, (const double*)zb, out, g);
+        }
     };
     auto dot_blocks = [](long long len) { return dim3((unsigned)std::min<long long>(1024, (len + 255) / 256)); };
     auto dot = [&](long long len, const double* a, const double* b2, double& out) {
