@@ -1054,6 +1054,37 @@ __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double*
 // A p is the keyframe diagonal blocks (hk + lambda D) plus the inertial and
 // bias cross terms between consecutive keyframes.
 
+// row t of A v: the keyframe diagonal block (damped) and the cross blocks to
+// keyframes k - 1 and k + 1 (inertial, and the bias random walk's -Omega_b)
+__device__ __forceinline__ double vi_ap_row(const VIDev& d, double lam, const double* __restrict__ v, long long t) {
+    const long long k = t / 15;
+    const int row = (int)(t % 15);
+    const double* H = d.hk + 225 * (size_t)k + 15 * row;
+    const double* vk = v + 15 * (size_t)k;
+    double u = lam * d.dg[t] * vk[row];
+    for (int c = 0; c < 15; ++c) u += H[c] * vk[c];
+    if (k + 1 < d.K) {   // keyframe k as i of the term k: row of icx_k
+        const double* C = d.icx + 135 * (size_t)k + 9 * row;
+        const double* vj = v + 15 * (size_t)(k + 1);
+        for (int c = 0; c < 9; ++c) u += C[c] * vj[c];
+        if (row >= 9 && k != 0) {
+            const double dt = d.pre[(size_t)kPreStride * k + kDt];
+            u -= ((row < 12 ? d.wg : d.wa) / dt) * vj[row];
+        }
+    }
+    if (k > 0) {         // keyframe k as j of the term k - 1: column of icx_{k-1}
+        const double* vi = v + 15 * (size_t)(k - 1);
+        if (row < 9) {
+            const double* C = d.icx + 135 * (size_t)(k - 1) + row;
+            for (int c = 0; c < 15; ++c) u += C[9 * c] * vi[c];
+        } else if (k - 1 != 0) {
+            const double dt = d.pre[(size_t)kPreStride * (k - 1) + kDt];
+            u -= ((row < 12 ? d.wg : d.wa) / dt) * vi[row];
+        }
+    }
+    return u;
+}
+
 // z_j = sign C_j^-1 (sum_{e of j} W_e^T v_k(e) + add_j): observations in
 // padded point order (a point's observations within one wavefront unless it
 // has more than 64; pad slots have point -1), a point's sum across its run of
@@ -1073,15 +1104,33 @@ __global__ __launch_bounds__(256) void k_vi_prod_inertial(VIDev d, const double*
 constexpr int kKfWin = 64;
 constexpr int kFuseBlock = 512;
 
+//
+// With kFuse the workgroups after the point ones add q += A v (one lane per
+// keyframe row, vi_ap_row; q is zero beforehand) and v . A v: the whole
+// product S v in one launch.
 template <typename WT, bool kFuse>
 __global__ __launch_bounds__(1024) void k_vi_schur_pts(VIDev d, const double* __restrict__ v,
                                                       const double* __restrict__ add, double sign,
                                                       double* __restrict__ z, const double* __restrict__ ps,
-                                                      double* __restrict__ acc, double* __restrict__ q) {
+                                                      double* __restrict__ acc, double* __restrict__ q,
+                                                      double lam) {
     if (pcg_done(ps)) return;
     __shared__ double red[16];
     __shared__ double part[kFuse ? kKfWin * 6 : 1];
     __shared__ int kmin_w[16];
+    if (kFuse) {
+        const long long pt_blocks = (d.Mp + blockDim.x - 1) / blockDim.x;
+        if (blockIdx.x >= pt_blocks) {   // the keyframe rows (uniform per workgroup)
+            const long long t0 = (blockIdx.x - pt_blocks) * (long long)blockDim.x + threadIdx.x;
+            const bool act = t0 < 15LL * d.K;
+            const long long t = act ? t0 : 0;
+            const double u = vi_ap_row(d, lam, v, t);
+            if (act) atomic_add(q + t, u);
+            const double sa = block_sum_vi(act ? v[t] * u : 0.0, red);
+            if (threadIdx.x == 0) atomic_add(acc + blockIdx.x % kPqParts, sa);
+            return;
+        }
+    }
     const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const long long i = i0 < d.Mp ? i0 : d.Mp - 1;
     const int j = d.qpt[i];
@@ -1322,34 +1371,10 @@ __global__ void k_vi_schur_ap(VIDev d, double lam, const double* __restrict__ v,
     const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool act = t0 < 15LL * d.K;
     const long long t = act ? t0 : 0;
-    const long long k = t / 15;
-    const int row = (int)(t % 15);
-    const double* H = d.hk + 225 * (size_t)k + 15 * row;
-    const double* vk = v + 15 * (size_t)k;
-    double u = lam * d.dg[t] * vk[row];
-    for (int c = 0; c < 15; ++c) u += H[c] * vk[c];
-    if (k + 1 < d.K) {   // keyframe k as i of the term k: row of icx_k
-        const double* C = d.icx + 135 * (size_t)k + 9 * row;
-        const double* vj = v + 15 * (size_t)(k + 1);
-        for (int c = 0; c < 9; ++c) u += C[c] * vj[c];
-        if (row >= 9 && k != 0) {
-            const double dt = d.pre[(size_t)kPreStride * k + kDt];
-            u -= ((row < 12 ? d.wg : d.wa) / dt) * vj[row];
-        }
-    }
-    if (k > 0) {         // keyframe k as j of the term k - 1: column of icx_{k-1}
-        const double* vi = v + 15 * (size_t)(k - 1);
-        if (row < 9) {
-            const double* C = d.icx + 135 * (size_t)(k - 1) + row;
-            for (int c = 0; c < 15; ++c) u += C[9 * c] * vi[c];
-        } else if (k - 1 != 0) {
-            const double dt = d.pre[(size_t)kPreStride * (k - 1) + kDt];
-            u -= ((row < 12 ? d.wg : d.wa) / dt) * vi[row];
-        }
-    }
+    const double u = vi_ap_row(d, lam, v, t);
     if (act) q[t] = u;
     if (acc) {   // with acc: v . A v (the keyframe part of p . S p)
-        const double s = block_sum_vi(act ? vk[row] * u : 0.0, red);
+        const double s = block_sum_vi(act ? v[t] * u : 0.0, red);
         if (threadIdx.x == 0) atomic_add(acc + blockIdx.x % kPqParts, s);
     }
 }
@@ -1481,9 +1506,11 @@ __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, d
 // beta = r.z / previous r.z.  Every workgroup takes the same decisions from
 // this slot's and the previous slot's values (which no workgroup of this
 // kernel writes); workgroup 0 records them (this slot's least r.r and stop
-// flag, the stop flag the later kernels read) and clears the next slot.
+// flag, the stop flag the later kernels read) and clears the next slot; qz
+// (when given) is cleared for the next product.
 __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, const double* __restrict__ z,
-                             double* __restrict__ p, double* __restrict__ x, double* __restrict__ xb) {
+                             double* __restrict__ p, double* __restrict__ x, double* __restrict__ xb,
+                             double* __restrict__ qz) {
     double* acc = ps + kAccN * slot;
     const double* prev = ps + kAccN * ((slot + kSlots - 1) % kSlots);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -1524,7 +1551,10 @@ __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, con
         return;
     }
     const double beta = acc[kAccRz] / prev[kAccRz];
-    for (long long i = i0; i < n; i += st) p[i] = z[i] + beta * p[i];
+    for (long long i = i0; i < n; i += st) {
+        p[i] = z[i] + beta * p[i];
+        if (qz) qz[i] = 0.0;   // the next product adds into q
+    }
     if (lead) acc[kAccMin] = nmin;
 }
 
@@ -1909,10 +1939,13 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_fill, grid(n_scal), blk, 0, nullptr, n_scal, d.scal, (const double*)nullptr);
     };
     // cost of (st, X) into slot 0, and |x|^2 into slot 1 when asked
-    auto cost_of = [&](const double* st, const double* X, bool xnorm, double& F, double& xn) {
+    // cost of (st, X) into slot 0 and, with nst, |x| of (nst, nX) into slot
+    // 1, one readback
+    auto cost_of = [&](const double* st, const double* X, const double* nst, const double* nX, double& F,
+                       double& xn) {
         zero_scal();
         hipLaunchKernelGGL(k_vi_cost, grid(M + K - 1), blk, 0, nullptr, d, st, X, 0);
-        if (xnorm) hipLaunchKernelGGL(k_vi_xnorm, grid(K + N), blk, 0, nullptr, d, st, X, 1);
+        if (nst) hipLaunchKernelGGL(k_vi_xnorm, grid(K + N), blk, 0, nullptr, d, nst, nX, 1);
         if (!chk() || !read_scal()) return false;
         F = hs[0];
         xn = std::sqrt(hs[1]);
@@ -1951,27 +1984,26 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         double* none_q = nullptr;
         if (d.w32)
             hipLaunchKernelGGL((k_vi_schur_pts<float, false>), grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g,
-                               acc, none_q);
+                               acc, none_q, 0.0);
         else
             hipLaunchKernelGGL((k_vi_schur_pts<double, false>), grid(Mp), blk, 0, nullptr, d, v, add, sign, out, g,
-                               acc, none_q);
+                               acc, none_q, 0.0);
         if (d.nlong > 0)
             hipLaunchKernelGGL(k_vi_long_pts, grid(d.nlong), blk, 0, nullptr, d, add, sign, out, g, acc);
     };
     // q = S v over the keyframes in one pass over the point-order W (the
     // point vector through zb): A v first, then the fused point pass adds
     // -B C^-1 B^T v; acc: v . S v
-    const dim3 fuse_grid((unsigned)std::max(1LL, (Mp + kFuseBlock - 1) / kFuseBlock));
+    // (out is zero on entry: cleared before the PCG and by each direction step)
+    const dim3 fuse_grid((unsigned)((Mp + kFuseBlock - 1) / kFuseBlock + (15LL * K + kFuseBlock - 1) / kFuseBlock));
     auto schur_product = [&](const double* v, double* out, double lam, const double* g, double* acc) {
-        hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, lam, v, out, g, acc);
-        if (M == 0) return;
         const double* no_add = nullptr;
         if (d.w32)
             hipLaunchKernelGGL((k_vi_schur_pts<float, true>), fuse_grid, dim3(kFuseBlock), 0, nullptr, d, v, no_add,
-                               1.0, zb, g, acc, out);
+                               1.0, zb, g, acc, out, lam);
         else
             hipLaunchKernelGGL((k_vi_schur_pts<double, true>), fuse_grid, dim3(kFuseBlock), 0, nullptr, d, v, no_add,
-                               1.0, zb, g, acc, out);
+                               1.0, zb, g, acc, out, lam);
         if (d.nlong > 0) {
             hipLaunchKernelGGL(k_vi_long_pts, grid(d.nlong), blk, 0, nullptr, d, no_add, 1.0, zb, g, acc);
             if (d.w32) hipLaunchKernelGGL(k_vi_long_kf<float>, grid(d.nlslot), blk, 0, nullptr, d, (const double*)zb, out, g);
@@ -2023,6 +2055,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         const double ratio2 = (o.pcg_rejection_ratio > 0.0 && std::isfinite(o.pcg_rejection_ratio))
                                   ? o.pcg_rejection_ratio * o.pcg_rejection_ratio : 0.0;
         hipLaunchKernelGGL(k_vi_fill, grid(nn), blk, 0, nullptr, nn, xb, none);   // the best iterate: x0 = 0
+        if (schur) hipLaunchKernelGGL(k_vi_fill, grid(nn), blk, 0, nullptr, nn, q, none);   // the products add into q
         hipLaunchKernelGGL(k_vi_pcg_init, dim3(1), dim3(1), 0, nullptr, ps, o.pcg_tol, ratio2);
         const long long npt = schur ? 0 : N;
         const dim3 upd((unsigned)((K + 15) / 16 + (npt + 255) / 256));
@@ -2038,7 +2071,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             }
             hipLaunchKernelGGL(k_vi_pcg_update, upd, blk, 0, nullptr, d, npt, ps, slot, (const double*)pv,
                                (const double*)q, x, r, z);
-            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv, x, xb);
+            hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv, x, xb,
+                               schur ? q : nullptr);
             if ((it + 1) % kPcgSync == 0 && it + 1 < o.pcg_max_iters) {
                 if (!chk() || !read_scal()) return false;
                 if (hs[8 + kDone] != 0.0) break;
@@ -2059,7 +2093,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     rep.ms_other = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     rep.workspace_bytes = B.bytes;
     double F = 0.0, xn = 0.0;
-    if (!cost_of(d.st, d.X, false, F, xn)) return GBA_ERR_HIP;
+    if (!cost_of(d.st, d.X, nullptr, nullptr, F, xn)) return GBA_ERR_HIP;
     rep.initial_cost = F;
     rep.termination = GBA_TERM_MAX_ITERS;
     int nl = 0;
@@ -2096,8 +2130,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             if (!dot(n, d.b, x, bdx) || !dot(n, x, x, dd)) return GBA_ERR_HIP;
             const double L = -(bdx + 0.5 * dHd);
             hipLaunchKernelGGL(k_vi_step, grid(K + N), blk, 0, nullptr, d, x);
-            double Fn = 0.0, xnorm = 0.0, dummy = 0.0;
-            if (!cost_of(d.st_c, d.X_c, false, Fn, dummy) || !cost_of(d.st, d.X, true, dummy, xnorm))
+            double Fn = 0.0, xnorm = 0.0;
+            if (!cost_of(d.st_c, d.X_c, d.st, d.X, Fn, xnorm))   // candidate cost, current |x|
                 return GBA_ERR_HIP;
             const double dnorm = std::sqrt(dd);
             const bool accepted = L > 0.0 && Fn < F;
