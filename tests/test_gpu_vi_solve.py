@@ -225,3 +225,54 @@ def test_vi_solve_errors():
     with pytest.raises(gba.GbaError) as e:
         _gpu(sc, states, x0, pre_g, 3, 0.0, precision=gba.GBA_MIXED_BF16)
     assert e.value.status == -1
+
+
+def test_vi_full_size_configuration():
+    """The measured configuration (2,000 keyframes 0.25 s apart with a 200 Hz
+    IMU, 300k points seen within three keyframes of their anchor, ~2.07M
+    stereo observations, Huber, W in FP32, Schur form, PCG tol 1e-6 max 100),
+    as bench.py runs it.  The oracle cannot solve it densely, so it checks
+    what holds at any size: the reported initial and final costs equal the
+    oracle's cost (its own preintegration) at the start and at the returned
+    states and points, accepted costs decrease, the solve makes progress and
+    the first keyframe stays fixed."""
+    from scipy.spatial.transform import Rotation
+    sc = synth_vi.make_vi_scene(seed=0, n_kf=2000, n_pts=300000, window=3)
+    K = sc.n_kf
+    rng = np.random.default_rng(1)
+    dth = rng.normal(0, 0.01, (K, 3))
+    dth[0] = 0.0
+    R0 = (Rotation.from_matrix(sc.R_true) * Rotation.from_rotvec(dth)).as_rotvec()
+    dp = rng.normal(0, 0.05, (K, 3))
+    dv = rng.normal(0, 0.05, (K, 3))
+    dp[0] = dv[0] = 0.0
+    states = np.concatenate([R0, sc.p_true + dp, sc.v_true + dv, sc.bg_true, sc.ba_true], axis=1)
+    pts0 = sc.pts + rng.normal(0, 0.05, sc.pts.shape)
+    m = sc.gyro.shape[1]
+    off = np.arange(K, dtype=np.int64) * m
+    bias0 = np.concatenate([sc.bg_true[:-1], sc.ba_true[:-1]], axis=1)
+    pre_g = gba.gba_vi_preintegrate(0, off, sc.gyro.reshape(-1, 3), sc.acc.reshape(-1, 3), sc.imu_dt,
+                                    bias0, SIG_G, SIG_A)
+    o = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6, precision=gba.GBA_MIXED_FP32)
+    st, X, rep, log = gba.gba_vi_solve(0, states, pts0, sc.st_kf, sc.st_pt, sc.st_obs, sc.intr, pre_g, 5,
+                                       sigma_px=1.0, huber_delta2=7.815, sigma_gw=SIG_GW, sigma_aw=SIG_AW,
+                                       options=o)
+    pre_o = [imu.preintegrate(sc.gyro[f], sc.acc[f], sc.imu_dt, sc.bg_true[f], sc.ba_true[f], SIG_G, SIG_A)
+             for f in range(K - 1)]
+    prob = vi.VIProblem(sc.st_kf, sc.st_pt, sc.st_obs, sc.intr, pre_o, sigma_px=1.0, delta2=7.815,
+                        sigma_gw=SIG_GW, sigma_aw=SIG_AW)
+
+    def state(s15, P):
+        R = Rotation.from_rotvec(s15[:, 0:3]).as_matrix()
+        return vi.VIState(R, s15[:, 3:6], s15[:, 6:9], s15[:, 9:12], s15[:, 12:15], P)
+
+    F0 = prob.cost(state(states, pts0))
+    assert abs(rep["initial_cost"] - F0) <= 1e-9 * F0
+    F = prob.cost(state(st, X))
+    assert abs(rep["final_cost"] - F) <= 1e-9 * F
+    acc = [t["candidate_cost"] for t in log if t["accepted"]]
+    assert len(acc) >= 3 and all(b < a for a, b in zip(acc, acc[1:]))
+    assert rep["final_cost"] < 0.01 * rep["initial_cost"]
+    assert rep["pcg_iters_total"] <= 100 * rep["trials"]
+    np.testing.assert_array_equal(st[0, 3:], states[0, 3:])
+    np.testing.assert_allclose(st[0, 0:3], states[0, 0:3], rtol=0, atol=1e-14)
