@@ -421,20 +421,21 @@ struct VIDev {
     const double* obs;     // [3 M]
     const double* pre;     // [kPreStride (K - 1)]
     double* info;          // [81 (K - 1)] Omega of the inertial terms
-    double* js;            // [27 M] whitened stereo Jacobians (dtheta, dp | dX)
-    double* rs;            // [3 M]
+    double* js;            // [27 M] whitened stereo Jacobians (dtheta, dp | dX); whole-system form
+    double* rs;            // [3 M] whitened stereo residuals; whole-system form
     double* ji;            // [216 (K - 1)] inertial Jacobians
     double* ri;            // [9 (K - 1)]
     double* b;             // [n] gradient J^T Omega r
     double* hk;            // [225 K] keyframe diagonal blocks
     double* hp;            // [9 N] point diagonal blocks
     double* dg;            // [n] clipped diagonal (damping)
-    double* mki;           // [225 K] their inverses (the preconditioner applied)
+    double* mki;           // [225 K] inverses of the damped keyframe blocks (of S in the Schur form)
     double* mp;            // [9 N] inverses of the damped point blocks
     double* scal;          // [8 + kPcgScalars] reductions
-    // Schur form (null in the full form): W_e = J_k^T J_p (6 x 3) per
-    // observation, in keyframe order (wk) and in point order (wp), each in
-    // tiles of 64 observations with entry c of lane l at (18 tile + c) 64 + l
+    // Schur form (null in the whole-system form): W_e = J_k^T J_p (6 x 3)
+    // per observation, in keyframe order (wk) and in padded point order
+    // (wp), each in tiles of 64 observations x 18 entries in 16-byte lane
+    // groups (w_at)
     void* wk;              // double, or float when w32
     void* wp;
     int w32;
@@ -454,10 +455,11 @@ struct VIDev {
 };
 
 // PCG scalars on the device: three slots of dot accumulators {p.q parts,
-// r.r, r.z}, used round robin (step s accumulates into slot s % 3, takes the
-// previous r.z from slot (s + 2) % 3 and clears slot (s + 1) % 3 for the
-// next step, so no kernel reads a value another workgroup of it resets),
-// then the stop threshold, the stop flag and the step count
+// r.r, r.z, ...}, used round robin (step s accumulates into slot s % 3,
+// takes the previous step's values from slot (s + 2) % 3 and clears slot
+// (s + 1) % 3 for the next step, so no kernel reads a value another
+// workgroup of it resets), then the stop threshold, the stop flag, the step
+// count and the squared rejection ratio
 // p.q is summed in kPqParts parts (a workgroup adds to part blockIdx %
 // kPqParts: thousands of workgroups adding to one address serialise)
 constexpr int kPqParts = 256;
@@ -1100,14 +1102,12 @@ __device__ __forceinline__ double vi_ap_row(const VIDev& d, double lam, const do
 // keyframe the workgroup sees; points are numbered by first observing
 // keyframe, so a workgroup's keyframes lie close together; one further out
 // is added to q directly), and the partials go to q with one atomic add
-// each.  Split points take this step in k_vi_long_kf.
+// each.  Split points take this step in k_vi_long_kf.  The workgroups after
+// the point ones add q += A v (one lane per keyframe row, vi_ap_row; q is
+// zero beforehand) and v . A v: the whole product S v in one launch.
 constexpr int kKfWin = 64;
 constexpr int kFuseBlock = 512;
 
-//
-// With kFuse the workgroups after the point ones add q += A v (one lane per
-// keyframe row, vi_ap_row; q is zero beforehand) and v . A v: the whole
-// product S v in one launch.
 template <typename WT, bool kFuse>
 __global__ __launch_bounds__(1024) void k_vi_schur_pts(VIDev d, const double* __restrict__ v,
                                                       const double* __restrict__ add, double sign,
