@@ -2023,8 +2023,11 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     const long long nn = schur ? 15LL * K : n;          // PCG unknowns
     const long long nm = schur ? 15LL * K : 15LL * K + N;   // preconditioner lanes
     // the PCG runs from its device scalars: its kernels are queued without
-    // host round trips, and the stop flag is read every kPcgSync steps
+    // host round trips, and the stop flag is read every kPcgSync steps (a
+    // read drains the queue); the first read comes kPcgSync steps before the
+    // previous solve's count, as the next solve usually takes about as many
     constexpr int kPcgSync = 8;
+    int prev_iters = 0;
     auto pcg = [&](double lam, int& iters) {
         iters = 0;
         const double* none = nullptr;
@@ -2073,7 +2076,8 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
                                (const double*)q, x, r, z);
             hipLaunchKernelGGL(k_vi_pcg_dir, dirg, blk, 0, nullptr, nn, ps, slot, (const double*)z, pv, x, xb,
                                schur ? q : nullptr);
-            if ((it + 1) % kPcgSync == 0 && it + 1 < o.pcg_max_iters) {
+            const int first_read = std::max(kPcgSync, prev_iters - kPcgSync);
+            if (it + 1 >= first_read && (it + 1 - first_read) % kPcgSync == 0 && it + 1 < o.pcg_max_iters) {
                 if (!chk() || !read_scal()) return false;
                 if (hs[8 + kDone] != 0.0) break;
             }
@@ -2086,6 +2090,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         }
         if (!chk() || !read_scal()) return false;
         iters = (int)hs[8 + kSteps];
+        prev_iters = iters;
         return true;
     };
     gba_report rep{};
