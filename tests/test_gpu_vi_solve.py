@@ -159,6 +159,44 @@ def test_vi_long_tracks_match_the_oracle(precision):
         assert abs(log3[0]["step_norm"] - np.linalg.norm(dx)) <= 1e-8 * np.linalg.norm(dx)
 
 
+@pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
+def test_vi_inertial_only_matches_the_oracle(solver):
+    # no points and no stereo observations: the inertial and bias terms
+    # alone (the empty-observation paths of every kernel)
+    sc = synth_vi.make_vi_scene(seed=6, n_kf=7, n_pts=50)
+    K = sc.n_kf
+    pre_o = [imu.preintegrate(sc.gyro[f], sc.acc[f], sc.imu_dt, sc.bg_true[f], sc.ba_true[f],
+                              SIG_G, SIG_A) for f in range(K - 1)]
+    e = np.zeros(0, np.int64)
+    prob = vi.VIProblem(e, e, np.zeros((0, 3)), sc.intr, pre_o, sigma_px=1.0, delta2=0.0,
+                        sigma_gw=SIG_GW, sigma_aw=SIG_AW)
+    rng = np.random.default_rng(1)
+    R0 = np.stack([sc.R_true[k] @ imu.so3_exp(rng.normal(0, 0.01, 3) if k else np.zeros(3))
+                   for k in range(K)])
+    dp = rng.normal(0, 0.05, (K, 3))
+    dp[0] = 0.0
+    x0 = vi.VIState(R0, sc.p_true + dp, sc.v_true.copy(), sc.bg_true.copy(), sc.ba_true.copy(),
+                    np.zeros((0, 3)))
+    res = lm.levenberg_marquardt(prob, x0, 4)
+    m = sc.gyro.shape[1]
+    pre_g = gba.gba_vi_preintegrate(0, np.arange(K, dtype=np.int64) * m, sc.gyro.reshape(-1, 3),
+                                    sc.acc.reshape(-1, 3), sc.imu_dt,
+                                    np.concatenate([sc.bg_true[:-1], sc.ba_true[:-1]], axis=1),
+                                    SIG_G, SIG_A)
+    states = np.concatenate([np.array([imu.so3_log(R) for R in R0]), x0.p, x0.v, x0.bg, x0.ba], axis=1)
+    st, X, rep, log = gba.gba_vi_solve(0, states, np.zeros((0, 3)), e, e, np.zeros((0, 3)), sc.intr,
+                                       pre_g, 4, sigma_px=1.0, sigma_gw=SIG_GW, sigma_aw=SIG_AW,
+                                       options=gba.vi_options(pcg_tol=1e-12, pcg_max_iters=4000,
+                                                              solver=solver))
+    assert X.shape == (0, 3) and len(log) == len(res.log)
+    assert abs(rep["initial_cost"] - res.initial_cost) <= 1e-9 * res.initial_cost
+    for a, b in zip(log, res.log):
+        assert abs(a["cost"] - b["cost"]) <= 1e-8 * b["cost"] + 1e-9, (a, b)
+        assert a["accepted"] == b["accepted"]
+    np.testing.assert_allclose(st[:, 3:6], res.x.p, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(st[:, 6:9], res.x.v, rtol=0, atol=1e-7)
+
+
 def test_vi_mixed_fp32_within_the_mixed_bounds():
     # W = J_k^T J_p stored in FP32 (Schur form): final cost within 1e-4 and
     # the solution within 1e-3 relative of the oracle's FP64 LM (the mixed
