@@ -2011,13 +2011,6 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         }
     };
     auto dot_blocks = [](long long len) { return dim3((unsigned)std::min<long long>(1024, (len + 255) / 256)); };
-    auto dot = [&](long long len, const double* a, const double* b2, double& out) {
-        zero_scal();
-        hipLaunchKernelGGL(k_vi_dot, dot_blocks(len), blk, 0, nullptr, len, a, b2, d.scal, (const double*)nullptr);
-        if (!chk() || !read_scal()) return false;
-        out = hs[0];
-        return true;
-    };
     // PCG from 0 to |r| <= pcg_tol |r0|: on (H + lam D) x = -b (full form),
     // or on S x_k = v followed by the point back-substitution (Schur form)
     const long long nn = schur ? 15LL * K : n;          // PCG unknowns
@@ -2114,25 +2107,34 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             // model decrease -(b.dx + 1/2 dx^T H dx) with the undamped H; in
             // the Schur form dx^T H dx = dx_k^T A dx_k + 2 dx_k^T B dx_p
             // + sum_j dx_j^T H_pp,j dx_j from the blocks
+            // (the sums into scal slots 0..4, one readback)
             double bdx = 0.0, dHd = 0.0, dd = 0.0;
+            const double* cnone = nullptr;
+            zero_scal();
             if (schur) {
                 const double* xp = x + 15 * (size_t)K;
                 hipLaunchKernelGGL(k_vi_schur_ap, grid(15LL * K), blk, 0, nullptr, d, 0.0, (const double*)x, q,
-                                   (const double*)nullptr, (double*)nullptr);
-                hipLaunchKernelGGL(k_vi_fill, grid(15LL * K), blk, 0, nullptr, 15LL * K, z, (const double*)nullptr);
+                                   cnone, (double*)nullptr);
+                hipLaunchKernelGGL(k_vi_fill, grid(15LL * K), blk, 0, nullptr, 15LL * K, z, cnone);
                 schur_kf(xp, z, nullptr);   // z = -B dx_p
-                double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-                zero_scal();
-                hipLaunchKernelGGL(k_vi_pt_quad, grid(N), blk, 0, nullptr, d, xp, d.scal);
-                if (!chk() || !read_scal()) return GBA_ERR_HIP;
-                t3 = hs[0];
-                if (!dot(15LL * K, x, q, t1) || !dot(15LL * K, x, z, t2)) return GBA_ERR_HIP;
-                dHd = t1 - 2.0 * t2 + t3;
+                hipLaunchKernelGGL(k_vi_pt_quad, grid(N), blk, 0, nullptr, d, xp, d.scal + 2);
+                hipLaunchKernelGGL(k_vi_dot, dot_blocks(15LL * K), blk, 0, nullptr, 15LL * K, (const double*)x,
+                                   (const double*)q, d.scal + 0, cnone);
+                hipLaunchKernelGGL(k_vi_dot, dot_blocks(15LL * K), blk, 0, nullptr, 15LL * K, (const double*)x,
+                                   (const double*)z, d.scal + 1, cnone);
             } else {
                 product(x, q, 0.0, nullptr);
-                if (!chk() || !dot(n, x, q, dHd)) return GBA_ERR_HIP;
+                hipLaunchKernelGGL(k_vi_dot, dot_blocks(n), blk, 0, nullptr, n, (const double*)x, (const double*)q,
+                                   d.scal + 0, cnone);
             }
-            if (!dot(n, d.b, x, bdx) || !dot(n, x, x, dd)) return GBA_ERR_HIP;
+            hipLaunchKernelGGL(k_vi_dot, dot_blocks(n), blk, 0, nullptr, n, (const double*)d.b, (const double*)x,
+                               d.scal + 3, cnone);
+            hipLaunchKernelGGL(k_vi_dot, dot_blocks(n), blk, 0, nullptr, n, (const double*)x, (const double*)x,
+                               d.scal + 4, cnone);
+            if (!chk() || !read_scal()) return GBA_ERR_HIP;
+            dHd = schur ? hs[0] - 2.0 * hs[1] + hs[2] : hs[0];
+            bdx = hs[3];
+            dd = hs[4];
             const double L = -(bdx + 0.5 * dHd);
             hipLaunchKernelGGL(k_vi_step, grid(K + N), blk, 0, nullptr, d, x);
             double Fn = 0.0, xnorm = 0.0;
