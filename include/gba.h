@@ -122,8 +122,15 @@ typedef struct gba_options {
                                   camera-major over a camera-major copy of
                                   the stored Jacobian); GBA_ACC_LDS /
                                   GBA_ACC_CAMERA_PASS force one (LDS fails with
-                                  UNSUPPORTED when it does not fit).  Read when
-                                  the device graph is built.                  */
+                                  UNSUPPORTED when it does not fit).  In the
+                                  two-pass form of a single problem with more
+                                  than 1,024 cameras (no fixed order), the PCG
+                                  product's camera pass runs over camera
+                                  blocks of 1,024 (edges in point order inside
+                                  a block, LDS partials per block, its own
+                                  Jacobian copy); GBA_ACC_CAMERA_BLOCKS forces
+                                  that form at any size.  Read when the device
+                                  graph is built.                             */
     int tiles_per_block;       /* point tiles (whole points, <= 64 edges) per
                                   workgroup of the point passes; 0 (default):
                                   max(16, n_tiles / n_CU).  Read when the device
@@ -205,6 +212,7 @@ typedef struct gba_options {
 #define GBA_ACC_AUTO 0
 #define GBA_ACC_LDS 1
 #define GBA_ACC_CAMERA_PASS 2
+#define GBA_ACC_CAMERA_BLOCKS 3
 
 /* Summary of one gba_solve call. */
 typedef struct gba_report {

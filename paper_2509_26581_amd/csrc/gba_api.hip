@@ -412,7 +412,7 @@ gba_status gba_set_options(gba_graph* g, const gba_options* o) {
     if (!(o->initial_lambda > 0.0) || !(o->min_diag > 0.0) || !(o->max_diag >= o->min_diag) ||
         o->pcg_max_iters < 1 || !(o->pcg_tol >= 0.0) ||
         (o->precond != GBA_PRECOND_IDENTITY && o->precond != GBA_PRECOND_BLOCK_JACOBI) ||
-        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_CAMERA_PASS || o->tiles_per_block < 0 ||
+        o->accumulation < GBA_ACC_AUTO || o->accumulation > GBA_ACC_CAMERA_BLOCKS || o->tiles_per_block < 0 ||
         (o->deterministic != 0 && o->deterministic != 1) || (o->jacobi_scaling != 0 && o->jacobi_scaling != 1) ||
         o->pcg_schedule < GBA_PCG_AUTO || o->pcg_schedule > GBA_PCG_PERSISTENT ||
         o->jacobian < GBA_JACOBIAN_ANALYTIC || o->jacobian > GBA_JACOBIAN_DYNAMIC ||
@@ -420,7 +420,8 @@ gba_status gba_set_options(gba_graph* g, const gba_options* o) {
         return fail(g, GBA_ERR_INVALID_ARG, "invalid option value");
     if (o->jacobian == GBA_JACOBIAN_DYNAMIC && o->solver != GBA_SOLVER_FULL)
         return fail(g, GBA_ERR_INVALID_ARG, "dynamic Jacobians need the full-Hessian solver");
-    if (o->solver == GBA_SOLVER_FULL && (o->deterministic || o->accumulation == GBA_ACC_CAMERA_PASS))
+    if (o->solver == GBA_SOLVER_FULL && (o->deterministic || o->accumulation == GBA_ACC_CAMERA_PASS ||
+                                         o->accumulation == GBA_ACC_CAMERA_BLOCKS))
         return fail(g, GBA_ERR_INVALID_ARG,
                     "the full-Hessian solver sums the camera rows in LDS (no fixed-order mode)");
     if (o->deterministic && o->accumulation == GBA_ACC_LDS)

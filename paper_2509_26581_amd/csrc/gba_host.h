@@ -95,6 +95,9 @@ struct UnionPlan {
     bool deterministic = false;
     bool full = false;         // full-Hessian PCG
     bool dynamic = false;      // no stored Jacobian
+    bool cam_blocks = false;   // the camera-blocked product pass (one problem)
+    int bo_nblk = 0, bo_chunk_cap = 0;   // its blocks, and a bound on its chunks
+    int bo_target = 1;         // edges per chunk aimed at
     std::vector<int> cam_prob, pt_prob;   // problem of each union camera / point
 };
 

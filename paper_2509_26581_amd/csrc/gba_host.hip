@@ -357,8 +357,19 @@ gba_status plan_union(const std::vector<const ImageCounts*>& probs, const Tuning
               std::to_string((dev.max_lds - 1024) / 72) + " cameras per problem, no fixed-order mode)";
         return GBA_ERR_UNSUPPORTED;
     }
-    u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || !fits || u.deterministic;
+    u.cam_pass = tune.accumulation == GBA_ACC_CAMERA_PASS || tune.accumulation == GBA_ACC_CAMERA_BLOCKS ||
+                 !fits || u.deterministic;
     u.lds_pp = u.cam_pass ? 0 : (int)lds;
+    // the camera-blocked product pass: one problem, stored Jacobians, sums
+    // by LDS atomics (so not in the fixed-order mode)
+    u.cam_blocks = u.cam_pass && P == 1 && !u.deterministic && !u.full && u.tot.ne > 0 &&
+                   (tune.accumulation == GBA_ACC_CAMERA_BLOCKS ||
+                    (tune.accumulation == GBA_ACC_AUTO && u.tot.nc > kCamBlock));
+    if (u.cam_blocks) {
+        u.bo_nblk = (u.tot.nc + kCamBlock - 1) / kCamBlock;
+        u.bo_target = std::max(4096, (u.tot.ne + dev.n_cu - 1) / std::max(1, dev.n_cu));
+        u.bo_chunk_cap = u.bo_nblk + u.tot.ne / u.bo_target + 1;
+    }
     // automatic: one point-pass workgroup per CU (each flushes one LDS camera
     // partial; the flush grows with the workgroup count, and smaller
     // workgroups measured slower in both schemes)
@@ -455,6 +466,20 @@ size_t layout_union(const UnionPlan& u, int precision, void* base, DeviceGraph* 
     if (!u.dynamic) L.add(d.jst_cm, jsz * 24 * NE64);   // camera-major copy (preconditioner, two-pass products)
     else if (dptr) d.jst_cm = nullptr;
     if (u.cam_pass) L.add(d.zbuf, tsz * 4 * NP);
+    if (u.cam_blocks) {
+        const size_t cap = (size_t)u.bo_chunk_cap;
+        L.add(d.bo_off, sizeof(int) * (cap + 1));
+        L.add(d.bo_blk, sizeof(int) * cap);
+        L.add(d.bo_blk_chunk, sizeof(int) * (u.bo_nblk + 1));
+        L.add(d.bo_perm, sizeof(int) * NE);
+        L.add(d.bo_pt, sizeof(int) * NE);
+        L.add(d.bo_cam, sizeof(int) * NE);
+        L.add(d.jst_bo, jsz * 24 * NE64);
+        L.add(d.bo_partial, tsz * cap * kCamBlock * 9);
+    } else if (dptr) {
+        d.bo_off = d.bo_blk = d.bo_blk_chunk = d.bo_perm = d.bo_pt = d.bo_cam = nullptr;
+        d.jst_bo = d.bo_partial = nullptr;
+    }
     L.add(d.minv, tsz * 45 * NC);
     L.add(d.v_x, tsz * 9 * NC + 64);   // slack: 16-byte gathers (gather9); back-substitution
     L.add(d.v_r, tsz * 9 * NC);
@@ -642,6 +667,54 @@ gba_status build_batch(const std::vector<const HostProblem*>& probs, int precisi
     HIP_OR(msg, up(d.tile_off, tile_off.data(), sizeof(int) * tile_off.size()));
     HIP_OR(msg, up(d.e_cam, e_cam.data(), sizeof(int) * NE));
     HIP_OR(msg, up(d.e_pt, e_pt.data(), sizeof(int) * NE));
+    // the camera-blocked order: the point-major edges bucketed by camera
+    // block (so point order inside a block), each block cut into chunks of
+    // about bo_target edges
+    std::vector<int> bo_off, bo_blk, bo_blk_chunk, bo_perm, bo_pt, bo_cam;
+    d.bo_chunks = 0;
+    d.bo_nblk = 0;
+    if (u.cam_blocks) {
+        const int nb = u.bo_nblk;
+        std::vector<int> bstart(nb + 1, 0);
+        for (size_t e = 0; e < NE; ++e) ++bstart[e_cam[e] / kCamBlock + 1];
+        for (int b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
+        bo_perm.resize(NE);
+        bo_pt.resize(NE);
+        bo_cam.resize(NE);
+        {
+            std::vector<int> at(bstart.begin(), bstart.end() - 1);
+            for (size_t e = 0; e < NE; ++e) {
+                const int q = at[e_cam[e] / kCamBlock]++;
+                bo_perm[q] = (int)e;
+                bo_pt[q] = e_pt[e];
+                bo_cam[q] = e_cam[e];
+            }
+        }
+        bo_blk_chunk.assign(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+            bo_blk_chunk[b] = (int)bo_blk.size();
+            const long long n_b = bstart[b + 1] - bstart[b];
+            const long long k = std::max(1LL, (n_b + u.bo_target - 1) / u.bo_target);
+            for (long long c = 0; c < k && n_b > 0; ++c) {
+                bo_off.push_back(bstart[b] + (int)(n_b * c / k));
+                bo_blk.push_back(b);
+            }
+        }
+        bo_blk_chunk[nb] = (int)bo_blk.size();
+        bo_off.push_back((int)NE);
+        if ((int)bo_blk.size() > u.bo_chunk_cap) {
+            msg = "camera-blocked chunk count above its bound";
+            return GBA_ERR_STATE;
+        }
+        d.bo_chunks = (int)bo_blk.size();
+        d.bo_nblk = nb;
+        HIP_OR(msg, up(d.bo_off, bo_off.data(), sizeof(int) * bo_off.size()));
+        HIP_OR(msg, up(d.bo_blk, bo_blk.data(), sizeof(int) * bo_blk.size()));
+        HIP_OR(msg, up(d.bo_blk_chunk, bo_blk_chunk.data(), sizeof(int) * bo_blk_chunk.size()));
+        HIP_OR(msg, up(d.bo_perm, bo_perm.data(), sizeof(int) * NE));
+        HIP_OR(msg, up(d.bo_pt, bo_pt.data(), sizeof(int) * NE));
+        HIP_OR(msg, up(d.bo_cam, bo_cam.data(), sizeof(int) * NE));
+    }
     HIP_OR(msg, up(d.obs, obs.data(), sizeof(double) * 2 * NE));
     if (u.tot.info) {
         HIP_OR(msg, up(d.sinfo, sinfo.data(), sizeof(double) * 3 * NE));

@@ -22,6 +22,8 @@ constexpr int kHinvStride = 8;        // padded row of the damped inverse point 
 constexpr int kCamsPerBlock = 28;     // cameras per PCG-vector workgroup (252 components)
 constexpr int kPcgBlock = 256;        // threads of the PCG-vector workgroups
 constexpr int kCamPassBlock = 256;    // threads of the camera-major pass workgroups
+constexpr int kCamBlock = 1024;       // cameras per block of the camera-blocked product pass
+constexpr int kCamBlockThreads = 1024;   // threads of its workgroups
 constexpr int kRedComps = 64;         // components per partial-reduction workgroup
 constexpr int kMaxProblems = 4096;    // problems per device graph
 constexpr int kMaxDevices = 64;       // devices tracked for per-device kernel attributes
@@ -110,6 +112,22 @@ struct DeviceGraph {
     int jac_bytes;       // bytes per stored Jacobian entry
 
     // topology
+    // camera-blocked order of the PCG product's camera pass (two-pass form,
+    // one problem; bo_chunks == 0: off): edges grouped by block of kCamBlock
+    // cameras, in point order inside a block, cut into chunks (one workgroup
+    // each, within one block); the chunk's LDS sums of J_c^T J_p z_j per
+    // camera of the block go to bo_partial[chunk][kCamBlock][9] (vector type)
+    int bo_chunks;
+    int bo_nblk;
+    const int* bo_off;        // [bo_chunks + 1] edge ranges (block order)
+    const int* bo_blk;        // [bo_chunks] block of each chunk
+    const int* bo_blk_chunk;  // [bo_nblk + 1] chunks of each block
+    const int* bo_perm;       // [ne] point-major edge of each block-order edge
+    const int* bo_pt;         // [ne]
+    const int* bo_cam;        // [ne]
+    void* jst_bo;             // the stored Jacobian in block order
+    void* bo_partial;
+
     const int* tile_off;      // [n_tiles + 1] edge offsets
     const int* e_cam;         // [ne]
     const int* e_pt;          // [ne]

@@ -1318,7 +1318,23 @@ __device__ __forceinline__ void reduce_body(const DeviceGraph& g, const int bid,
         }
     }
     T tot = 0;
-    if (g.cam_pass) {
+    if (g.cam_pass && kMode == kMatvec && g.bo_chunks > 0) {
+        // camera-blocked product pass: the chunk sums of the camera's block
+        if (own) {
+            // eight independent sums keep eight loads in flight per lane
+            const int b = i / kCamBlock, il = i - b * kCamBlock;
+            const T* part = (const T*)g.bo_partial + 9 * il + r;
+            const int c1 = g.bo_blk_chunk[b + 1];
+            int c = g.bo_blk_chunk[b];
+            T t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (; c + 8 <= c1; c += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t[u] += part[(size_t)(c + u) * (kCamBlock * 9)];
+            }
+            for (int u = 0; c < c1; ++c, ++u) t[u] += part[(size_t)c * (kCamBlock * 9)];
+            tot = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+        }
+    } else if (g.cam_pass) {
         // two-pass scheme: the camera's chunk sums from k_cam_pass
         if (own)
             for (int c = g.cam_chunk_off[i]; c < g.cam_chunk_off[i + 1]; ++c)
@@ -1959,6 +1975,58 @@ __global__ __launch_bounds__(256) void k_rhs_z(DeviceGraph g) {
 }
 
 // ==========================================================================
+// Camera-blocked camera pass of the Schur product (two-pass form, one
+// problem): the camera pass with its edges grouped by block of kCamBlock
+// cameras and in point order inside a block, so a workgroup reads z_j of
+// nearby points in ascending order instead of one random point per edge.
+// One workgroup per chunk (within one block) sums J_c^T J_p z_j per camera of
+// the block in LDS (FP64) and writes the block's partial vector (vector type);
+// k_reduce adds the block's chunks.  The Jacobian is a copy in block order
+// (k_copy_jac_bo, after each linearisation).
+// ==========================================================================
+template <typename JS>
+__global__ __launch_bounds__(256) void k_copy_jac_bo(DeviceGraph g) {
+    if (!jac_type_ok<JS>(g)) return;   // instantiated for another mode
+    using A = typename std::conditional<std::is_same<JS, double>::value, double, float>::type;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.ne;
+         e += (long long)gridDim.x * blockDim.x) {
+        A jc[2][9], jp[2][3];
+        jac_load<JS>(g.jst, g.bo_perm[e], jc, jp);
+        jac_save<JS>(g.jst_bo, (int)e, jc, jp);
+    }
+}
+
+template <typename VT, typename JS>
+__global__ __launch_bounds__(kCamBlockThreads) void k_cam_block_pass(DeviceGraph g) {
+    if (!vec_type_ok<VT>(g) || !jac_type_ok<JS>(g)) return;   // instantiated for another mode
+    using T = VT;
+    // the sums in LDS are FP64 in every mode (FP32 LDS atomics are slower)
+    extern __shared__ __align__(16) unsigned char bo_lds[];
+    double* y = (double*)bo_lds;
+    if (!(g.pcg_dec[0].act & kActStep)) return;   // the PCG has stopped (uniform)
+    const int ch = blockIdx.x;
+    const int b = g.bo_blk[ch], cb0 = b * kCamBlock;
+    const int e0 = g.bo_off[ch], e1 = g.bo_off[ch + 1];
+    for (int k = threadIdx.x; k < kCamBlock * 9; k += blockDim.x) y[k] = 0.0;
+    __syncthreads();
+    const T* __restrict__ zbuf = (const T*)g.zbuf;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
+        const int j = g.bo_pt[e], il = g.bo_cam[e] - cb0;
+        const T z0 = zbuf[4 * j], z1 = zbuf[4 * j + 1], z2 = zbuf[4 * j + 2];
+        T jc[2][9], jp[2][3];
+        jac_load<JS>(g.jst_bo, e, jc, jp);
+        const T u0 = jp[0][0] * z0 + jp[0][1] * z1 + jp[0][2] * z2;
+        const T u1 = jp[1][0] * z0 + jp[1][1] * z1 + jp[1][2] * z2;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) atomicAdd(&y[9 * il + k], (double)(jc[0][k] * u0 + jc[1][k] * u1));
+    }
+    __syncthreads();
+    const int ncb = min(kCamBlock, g.nc - cb0) * 9;
+    T* dst = (T*)g.bo_partial + (size_t)ch * (kCamBlock * 9);
+    for (int k = threadIdx.x; k < ncb; k += blockDim.x) dst[k] = (T)y[k];
+}
+
+// ==========================================================================
 // Persistent PCG: one cooperative launch runs every iteration of every
 // problem of the batch.  An iteration is the three phases of the launched
 // form (the product with its decision, the partial reduction with q and p,
@@ -2206,6 +2274,12 @@ hipError_t launch_assemble(const DeviceGraph& g, hipStream_t s) {
         hipLaunchKernelGGL((k_cam_finalize<double, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0, 0);
     else
         hipLaunchKernelGGL((k_cam_finalize<float, kAssemble>), dim3(g.nc), dim3(64), 0, s, g, 0.0, 0.0, 0, 0, 0, 0);
+    if (g.bo_chunks > 0) {   // the Jacobian copy of the camera-blocked product pass
+        const int grid = (int)std::min<long long>(4096, ((long long)g.ne + 255) / 256);
+        if (g.mode == kModeFP64) hipLaunchKernelGGL(k_copy_jac_bo<double>, dim3(grid), dim3(256), 0, s, g);
+        else if (g.mode == kModeFP32) hipLaunchKernelGGL(k_copy_jac_bo<float>, dim3(grid), dim3(256), 0, s, g);
+        else hipLaunchKernelGGL(k_copy_jac_bo<bf16>, dim3(grid), dim3(256), 0, s, g);
+    }
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -2351,6 +2425,20 @@ static void cam_pass(const DeviceGraph& g, hipStream_t s) {
         hipLaunchKernelGGL((k_cam_pass<float, bf16, kMode>), dim3(g.n_chunks), dim3(kCamPassBlock), 0, s, g);
 }
 
+template <typename VT, typename JS>
+static void cam_block_pass_t(const DeviceGraph& g, hipStream_t s) {
+    const int lds = kCamBlock * 9 * (int)sizeof(double);
+    static int lds_set[kMaxDevices] = {};
+    ensure_lds((const void*)k_cam_block_pass<VT, JS>, lds, lds_set);
+    hipLaunchKernelGGL((k_cam_block_pass<VT, JS>), dim3(g.bo_chunks), dim3(kCamBlockThreads), lds, s, g);
+}
+
+static void cam_block_pass(const DeviceGraph& g, hipStream_t s) {
+    if (g.mode == kModeFP64) cam_block_pass_t<double, double>(g, s);
+    else if (g.mode == kModeFP32) cam_block_pass_t<float, float>(g, s);
+    else cam_block_pass_t<float, bf16>(g, s);
+}
+
 hipError_t launch_rhs(const DeviceGraph& g, hipStream_t s) {
     if (g.nc == 0) return hipSuccess;   // no cameras, hence no edges
     if (g.cam_pass) {
@@ -2417,7 +2505,8 @@ hipError_t launch_matvec(const DeviceGraph& g0, hipStream_t s, int max_iters, do
     } else {
         point_pass<float, bf16, double, kMatvec>(g, s, g.v_z, g.cam_partial);
     }
-    if (g.cam_pass) cam_pass<kMatvec>(g, s);
+    if (g.cam_pass && g.bo_chunks > 0) cam_block_pass(g, s);
+    else if (g.cam_pass) cam_pass<kMatvec>(g, s);
     GBA_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -2499,6 +2588,7 @@ static hipError_t persistent_form(const DeviceGraph& g, hipStream_t s, double mi
 template <bool kCheck>
 static hipError_t persistent_dispatch(const DeviceGraph& g, hipStream_t s, double min_diag,
                                       double max_diag, int max_launch) {
+    if (g.bo_chunks > 0) return hipErrorNotSupported;   // the camera-blocked pass is launched only
     if (!g.full) return persistent_form<kCheck, 0>(g, s, min_diag, max_diag, max_launch);
     if (!g.dynamic) return persistent_form<kCheck, 1>(g, s, min_diag, max_diag, max_launch);
     return persistent_form<kCheck, 2>(g, s, min_diag, max_diag, max_launch);

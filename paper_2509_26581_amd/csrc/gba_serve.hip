@@ -372,6 +372,8 @@ gba_status gba_server::repack() {
     batch.persistent_ok = -1;
     batch.jacobian = cfg.options.jacobian;
     layout_union(u, cfg.precision, (char*)arena + uo, &batch.dg);
+    batch.dg.bo_chunks = 0;   // the packed batch takes the camera-major pass
+    batch.dg.bo_nblk = 0;
     set_union_scalars(batch, cfg.precision, cfg.loss, cfg.delta);
     batch.arena = (char*)arena + uo;
     batch.arena_bytes = ub;

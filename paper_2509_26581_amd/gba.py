@@ -24,7 +24,7 @@ GBA_PENDING = 1
 GBA_FP64, GBA_MIXED_FP32, GBA_MIXED_BF16 = 0, 1, 2
 GBA_LOSS_SQUARED, GBA_LOSS_HUBER = 0, 1
 GBA_PRECOND_IDENTITY, GBA_PRECOND_BLOCK_JACOBI = 0, 1
-GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_CAMERA_PASS = 0, 1, 2
+GBA_ACC_AUTO, GBA_ACC_LDS, GBA_ACC_CAMERA_PASS, GBA_ACC_CAMERA_BLOCKS = 0, 1, 2, 3
 GBA_PCG_AUTO, GBA_PCG_CHUNKED, GBA_PCG_PERSISTENT = 0, 1, 2
 GBA_JACOBIAN_ANALYTIC, GBA_JACOBIAN_AUTODIFF, GBA_JACOBIAN_DYNAMIC = 0, 1, 2
 GBA_SOLVER_SCHUR, GBA_SOLVER_FULL = 0, 1

@@ -149,7 +149,9 @@ def test_normal_equation_blocks():
 
 
 # -------------------------------------------------------- damped step --
-ACC = [gba.GBA_ACC_AUTO, gba.GBA_ACC_CAMERA_PASS]   # one pass (LDS) / two passes
+# one pass (LDS) / two passes / two passes, the product's camera pass over
+# camera blocks
+ACC = [gba.GBA_ACC_AUTO, gba.GBA_ACC_CAMERA_PASS, gba.GBA_ACC_CAMERA_BLOCKS]
 
 
 @pytest.mark.parametrize("acc", ACC)
@@ -668,7 +670,8 @@ def test_mixed_small_workload_final_cost(precision):
 
 @pytest.mark.parametrize("precision,acc", [(gba.GBA_MIXED_FP32, gba.GBA_ACC_AUTO),
                                            (gba.GBA_MIXED_BF16, gba.GBA_ACC_AUTO),
-                                           (gba.GBA_MIXED_BF16, gba.GBA_ACC_CAMERA_PASS)])
+                                           (gba.GBA_MIXED_BF16, gba.GBA_ACC_CAMERA_PASS),
+                                           (gba.GBA_MIXED_BF16, gba.GBA_ACC_CAMERA_BLOCKS)])
 def test_bal1m_mixed_final_cost_and_solution(precision, acc):
     gold = _bal1m_golden()
     sc = synth.make_scene("bal1m", seed=0)
