@@ -2588,7 +2588,6 @@ static hipError_t persistent_form(const DeviceGraph& g, hipStream_t s, double mi
 template <bool kCheck>
 static hipError_t persistent_dispatch(const DeviceGraph& g, hipStream_t s, double min_diag,
                                       double max_diag, int max_launch) {
-    if (g.bo_chunks > 0) return hipErrorNotSupported;   // the camera-blocked pass is launched only
     if (!g.full) return persistent_form<kCheck, 0>(g, s, min_diag, max_diag, max_launch);
     if (!g.dynamic) return persistent_form<kCheck, 1>(g, s, min_diag, max_diag, max_launch);
     return persistent_form<kCheck, 2>(g, s, min_diag, max_diag, max_launch);
@@ -2602,6 +2601,7 @@ hipError_t launch_pcg_persistent(const DeviceGraph& g0, hipStream_t s, double mi
                                  int max_iters, double ratio) {
     if (g0.nc == 0) return hipSuccess;
     DeviceGraph g = g0;
+    g.bo_chunks = 0;   // the persistent kernel takes the camera-major pass (its structures are always built)
     g.pcg_max_iters = max_iters;
     g.pcg_ratio = ratio;
     // a PCG of k steps takes k + 1 iterations (the last finds the stop)

@@ -60,12 +60,15 @@ def test_persistent_equals_chunked_launches_bitwise(precision):
     assert rc.final_cost == ra.final_cost
 
 
-def test_persistent_lm_trajectory_matches_the_oracle():
+@pytest.mark.parametrize("acc", [gba.GBA_ACC_AUTO, gba.GBA_ACC_CAMERA_BLOCKS])
+def test_persistent_lm_trajectory_matches_the_oracle(acc):
     # default (LDS) sums, exact PCG: per-trial costs, damping and decisions
-    # as the oracle's exact block-Cholesky LM
+    # as the oracle's exact block-Cholesky LM; also on a graph built for the
+    # camera-blocked pass, which the persistent kernel runs as the
+    # camera-major pass
     sc = synth.make_scene("small", seed=0)
     g = _graph(sc, pcg_max_iters=sc.pcg_max_iters, pcg_tol=1e-14,
-               pcg_schedule=gba.GBA_PCG_PERSISTENT)
+               pcg_schedule=gba.GBA_PCG_PERSISTENT, accumulation=acc)
     rep = g.solve(sc.trials)
     prob = ba.BAProblem(sc.n_cams, sc.n_pts, sc.cam_idx, sc.pt_idx, sc.obs,
                         loss=sc.loss, delta=sc.delta)
