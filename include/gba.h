@@ -128,9 +128,11 @@ typedef struct gba_options {
                                   product's camera pass runs over camera
                                   blocks of 1,024 (edges in point order inside
                                   a block, LDS partials per block, its own
-                                  Jacobian copy); GBA_ACC_CAMERA_BLOCKS forces
-                                  that form at any size.  Read when the device
-                                  graph is built.                             */
+                                  Jacobian copy; the persistent PCG schedule
+                                  takes the camera-major pass instead);
+                                  GBA_ACC_CAMERA_BLOCKS forces that form at
+                                  any size.  Read when the device graph is
+                                  built.                                      */
     int tiles_per_block;       /* point tiles (whole points, <= 64 edges) per
                                   workgroup of the point passes; 0 (default):
                                   max(16, n_tiles / n_CU).  Read when the device
