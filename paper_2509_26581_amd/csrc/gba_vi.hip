@@ -421,8 +421,8 @@ struct VIDev {
     const double* obs;     // [3 M]
     const double* pre;     // [kPreStride (K - 1)]
     double* info;          // [81 (K - 1)] Omega of the inertial terms
-    double* js;            // [27 M] whitened stereo Jacobians (dtheta, dp | dX); whole-system form
-    double* rs;            // [3 M] whitened stereo residuals; whole-system form
+    double* jsp;           // whole-system form: whitened stereo J (dtheta, dp | dX), padded
+                           // point-order tiles (js_at); null in the Schur form
     double* ji;            // [216 (K - 1)] inertial Jacobians
     double* ri;            // [9 (K - 1)]
     double* b;             // [n] gradient J^T Omega r
@@ -470,6 +470,11 @@ constexpr int kSlots = 3;
 enum { kThr = kSlots * kAccN, kDone, kSteps, kRatio2, kPcgScalars };
 
 __device__ __forceinline__ bool pcg_done(const double* ps) { return ps && ps[kDone] != 0.0; }
+
+// the keyframe window of the LDS partials of the point-order products, and
+// their workgroup size
+constexpr int kKfWin = 64;
+constexpr int kFuseBlock = 512;
 
 // W tiles: 64 observations x 18 entries, in 16-byte groups so that a lane
 // loads its entries as float4 / double2 and one load instruction of a
@@ -629,9 +634,8 @@ __device__ __forceinline__ void vi_stereo_whitened(const VIDev& d, const double*
 
 // linearisation of the stereo terms in keyframe order: the keyframe's
 // gradient and 6 x 6 block terms summed across its run of the wavefront
-// (SegScan) and added once per run.  Whole-system form: whitened J and r
-// stored, point terms added per observation.  Schur form: W = J_k^T J_p
-// stored (keyframe-order tiles); the point terms come from the point-order
+// (SegScan) and added once per run; in the Schur form W = J_k^T J_p is
+// stored (keyframe-order tiles).  The point terms come from the point-order
 // pass below.
 __global__ void k_vi_lin_stereo(VIDev d) {
     const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -646,11 +650,6 @@ __global__ void k_vi_lin_stereo(VIDev d) {
     segment_of(__ballot(start), l, head, end);
     double r[3], J[3][9];
     vi_stereo_whitened(d, d.obs + 3 * e, k, j, valid, r, J);
-    if (valid && !d.wk)
-        for (int a = 0; a < 3; ++a) {
-            d.rs[3 * e + a] = r[a];
-            for (int c = 0; c < 9; ++c) d.js[27 * e + 9 * a + c] = J[a][c];
-        }
     if (valid && d.wk)
         for (int a = 0; a < 6; ++a)
             for (int c = 0; c < 3; ++c) {
@@ -660,29 +659,25 @@ __global__ void k_vi_lin_stereo(VIDev d) {
             }
     const bool last = valid && l == end;
     double* bk = d.b + 15 * (size_t)k;
-    double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
-    for (int c = 0; c < 9; ++c) {
-        const double g = J[0][c] * r[0] + J[1][c] * r[1] + J[2][c] * r[2];
-        if (c < 6) {
-            const double sg = seg.sum(g);
-            if (last) atomic_add(bk + c, sg);
-        } else if (valid && !d.wk) {
-            atomic_add(bp + (c - 6), g);
-        }
+    for (int c = 0; c < 6; ++c) {
+        const double sg = seg.sum(J[0][c] * r[0] + J[1][c] * r[1] + J[2][c] * r[2]);
+        if (last) atomic_add(bk + c, sg);
     }
     for (int a = 0; a < 6; ++a)
         for (int c = 0; c < 6; ++c) {
             const double h = seg.sum(J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
             if (last && k != 0) atomic_add(d.hk + 225 * (size_t)k + 15 * a + c, h);
         }
-    if (valid && !d.wk)
-        for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c)
-                atomic_add(d.hp + 9 * (size_t)j + 3 * a + c,
-                           J[0][6 + a] * J[0][6 + c] + J[1][6 + a] * J[1][6 + c] + J[2][6 + a] * J[2][6 + c]);
 }
 
-// the same terms in point order (Schur form): W stored in point-order tiles,
+// whitened J (3 x 9) of the whole-system form in padded point-order tiles:
+// entry c of slot i at (27 tile + c) 64 + lane
+__device__ __forceinline__ size_t js_at(long long i, int c) {
+    return ((size_t)(i >> 6) * 27 + c) * 64 + (size_t)(i & 63);
+}
+
+// the same terms in point order: W (Schur form) or the whitened J
+// (whole-system form) stored in point-order tiles,
 // the point's gradient b_p and block H_pp summed across its run of the
 // wavefront; a point whose observations all sit in one wavefront is stored,
 // one split across wavefronts is added in parts (b and hp are zero before)
@@ -704,11 +699,14 @@ __global__ void k_vi_lin_stereo_pts(VIDev d) {
     const bool whole = (__shfl(first ? 1 : 0, head, 64) != 0) && lastp;
     double r[3], J[3][9];
     vi_stereo_whitened(d, d.qobs + 3 * i, k, j, valid, r, J);
-    if (valid)
+    if (valid && d.wp)
         for (int a = 0; a < 6; ++a)
             for (int c = 0; c < 3; ++c)
                 ((WT*)d.wp)[w_at<WT>(i, 3 * a + c)] =
                     (WT)(J[0][a] * J[0][6 + c] + J[1][a] * J[1][6 + c] + J[2][a] * J[2][6 + c]);
+    if (valid && d.jsp)
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 9; ++c) d.jsp[js_at(i, 9 * a + c)] = J[a][c];
     const bool out = valid && l == end;
     double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
     for (int c = 0; c < 3; ++c) {
@@ -976,39 +974,71 @@ __global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __re
     }
 }
 
-// q += (stereo part of H) v
-__global__ void k_vi_prod_stereo(VIDev d, const double* __restrict__ v, double* __restrict__ q,
-                                 const double* __restrict__ ps) {
+// q += (stereo part of H) v, whole-system form: one pass over the padded
+// point-order J.  Per observation u = J_k v_k + J_p v_j; the point rows
+// J_p^T u are summed across the point's run of the wavefront (added by its
+// last lane: whole runs own the point's rows, parts of a point split across
+// wavefronts add atomically), the keyframe rows J_k^T u go to the
+// workgroup's LDS partials of its keyframe window (as in k_vi_schur_pts) and
+// to q with one atomic add per entry.  q holds lambda D v on entry.
+__global__ __launch_bounds__(512) void k_vi_prod_stereo(VIDev d, const double* __restrict__ v,
+                                                       double* __restrict__ q, const double* __restrict__ ps) {
     if (pcg_done(ps)) return;
-    const long long e0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const bool valid = e0 < d.M;
-    const long long e = valid ? e0 : d.M - 1;
-    const int k = d.kf[e];
+    __shared__ double part[kKfWin * 6];
+    __shared__ int kmin_w[16];
+    const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long i = i0 < d.Mp ? i0 : d.Mp - 1;
+    const int jq = d.qpt[i];
+    const bool valid = i0 < d.Mp && jq >= 0;
+    const int j = valid ? jq : 0, k = valid ? d.qkf[i] : 0;
     const int l = (int)(threadIdx.x & 63);
-    const int kprev = __shfl_up(k, 1, 64);
-    const bool start = !valid || l == 0 || kprev != k;
+    const int jprev = __shfl_up(jq, 1, 64);
+    const bool start = !valid || l == 0 || jprev != jq;
     const SegScan seg(start);
     int head, end;
     segment_of(__ballot(start), l, head, end);
-    const size_t ok = 15 * (size_t)k, op = 15 * (size_t)d.K + 3 * (size_t)d.pt[e];
+    const bool first = i == 0 || d.qpt[i - 1] != jq;
+    const bool lastp = i == d.Mp - 1 || d.qpt[i + 1] != jq;
+    const bool whole = (__shfl(first ? 1 : 0, head, 64) != 0) && lastp;   // at the run's last lane
+    const size_t ok = 15 * (size_t)k, op = 15 * (size_t)d.K + 3 * (size_t)j;
     double in[9];
     for (int c = 0; c < 6; ++c) in[c] = v[ok + c];
     for (int c = 0; c < 3; ++c) in[6 + c] = v[op + c];
-    const double* J = d.js + 27 * (size_t)e;
+    double J[27];
+    for (int c = 0; c < 27; ++c) J[c] = d.jsp[js_at(i, c)];
     double u[3];
     for (int a = 0; a < 3; ++a) {
         double t = 0.0;
         for (int c = 0; c < 9; ++c) t += J[9 * a + c] * in[c];
         u[a] = valid ? t : 0.0;
     }
-    for (int c = 0; c < 9; ++c) {
-        const double y = J[c] * u[0] + J[9 + c] * u[1] + J[18 + c] * u[2];
-        if (c < 6) {
-            const double sy = seg.sum(y);   // the keyframe's sum over its run of the wavefront
-            if (valid && l == end) atomic_add(q + ok + c, sy);
-        } else if (valid) {
-            atomic_add(q + op + (c - 6), y);
+    for (int c = 0; c < 3; ++c) {
+        const double sy = seg.sum(J[6 + c] * u[0] + J[15 + c] * u[1] + J[24 + c] * u[2]);
+        if (valid && l == end) {
+            if (whole) q[op + c] += sy;
+            else atomic_add(q + op + c, sy);
         }
+    }
+    int km = valid ? k : 0x7fffffff;
+    for (int off = 32; off > 0; off >>= 1) km = min(km, __shfl_xor(km, off, 64));
+    if (l == 0) kmin_w[threadIdx.x >> 6] = km;
+    for (int e = threadIdx.x; e < kKfWin * 6; e += blockDim.x) part[e] = 0.0;
+    __syncthreads();
+    int kbase = 0x7fffffff;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) kbase = min(kbase, kmin_w[w]);
+    if (valid && k != 0) {
+        const int kk = k - kbase;
+        for (int c = 0; c < 6; ++c) {
+            const double y = J[c] * u[0] + J[9 + c] * u[1] + J[18 + c] * u[2];
+            if (kk < kKfWin) atomicAdd(part + 6 * kk + c, y);
+            else atomic_add(q + ok + c, y);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; kbase != 0x7fffffff && e < kKfWin * 6; e += blockDim.x) {
+        const int kf = kbase + e / 6;
+        const double val = part[e];
+        if (val != 0.0 && kf < d.K && kf != 0) atomic_add(q + 15 * (size_t)kf + e % 6, val);
     }
 }
 
@@ -1105,8 +1135,6 @@ __device__ __forceinline__ double vi_ap_row(const VIDev& d, double lam, const do
 // each.  Split points take this step in k_vi_long_kf.  The workgroups after
 // the point ones add q += A v (one lane per keyframe row, vi_ap_row; q is
 // zero beforehand) and v . A v: the whole product S v in one launch.
-constexpr int kKfWin = 64;
-constexpr int kFuseBlock = 512;
 
 template <typename WT, bool kFuse>
 __global__ __launch_bounds__(1024) void k_vi_schur_pts(VIDev d, const double* __restrict__ v,
@@ -1813,13 +1841,13 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     for (int64_t q = 0; q < P.n_pts; ++q)
         for (int c = 0; c < 3; ++c) hX[3 * q + c] = P.pts[3 * (size_t)pt_old[q] + c];
     const bool schur = o.solver == GBA_SOLVER_SCHUR;
-    // Schur form: the same observations in point order (stable in the
-    // keyframe order), padded so that a point's observations sit in one
-    // wavefront (64 slots) unless it has more than 64 of them
+    // the same observations in point order (stable in the keyframe order),
+    // padded so that a point's observations sit in one wavefront (64 slots)
+    // unless it has more than 64 of them
     std::vector<int> hqkf, hqpt, hlong, hlslot;
     std::vector<double> hqobs;
     long long Mp = 0;
-    if (schur) {
+    {
         std::vector<int64_t> cnt((size_t)P.n_pts, 0), at((size_t)P.n_pts, 0);
         for (int64_t e = 0; e < P.n_obs; ++e) ++cnt[(size_t)hpt[e]];
         for (int64_t j = 0; j < P.n_pts; ++j) {
@@ -1863,8 +1891,6 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&obs, hobs.data(), 3 * (size_t)M + 1) ||
         !B.up(&pre, P.pre, (size_t)kPreStride * (K - 1)) ||
         !B.up(&d.info, (const double*)nullptr, 81 * (size_t)(K - 1)) ||
-        !B.up(&d.js, (const double*)nullptr, schur ? 1 : 27 * (size_t)M + 1) ||   // whole-system form only
-        !B.up(&d.rs, (const double*)nullptr, schur ? 1 : 3 * (size_t)M + 1) ||
         !B.up(&d.ji, (const double*)nullptr, 216 * (size_t)(K - 1)) ||
         !B.up(&d.ri, (const double*)nullptr, 9 * (size_t)(K - 1)) ||
         !B.up(&d.b, (const double*)nullptr, (size_t)n) || !B.up(&d.hk, (const double*)nullptr, 225 * (size_t)K) ||
@@ -1875,31 +1901,37 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n) ||
         !B.up(&xb, (const double*)nullptr, (size_t)n))
         return GBA_ERR_OOM;
+    {   // the padded point order (both forms)
+        int *qkf = nullptr, *qpt = nullptr;
+        double* qobs = nullptr;
+        if (!B.up(&qkf, hqkf.data(), (size_t)Mp + 1) || !B.up(&qpt, hqpt.data(), (size_t)Mp + 1) ||
+            !B.up(&qobs, hqobs.data(), 3 * (size_t)Mp + 1))
+            return GBA_ERR_OOM;
+        d.qkf = qkf;
+        d.qpt = qpt;
+        d.qobs = qobs;
+        d.Mp = Mp;
+    }
+    if (!schur && !B.up(&d.jsp, (const double*)nullptr, 27 * 64 * (size_t)(Mp / 64) + 1)) return GBA_ERR_OOM;
     double* zb = nullptr;   // Schur form: the point vector of a product
     if (schur) {
         // W in FP32 takes half the doubles of FP64 (rounded up)
         d.w32 = o.precision == GBA_MIXED_FP32 ? 1 : 0;
         const size_t wn = (18 * 64 * (size_t)((M + 63) / 64) + 2) / (d.w32 ? 2 : 1);
         const size_t wpn = (18 * 64 * (size_t)(Mp / 64) + 2) / (d.w32 ? 2 : 1);
-        int *qkf = nullptr, *qpt = nullptr, *lp = nullptr, *ls = nullptr;
-        double* qobs = nullptr;
+        int *lp = nullptr, *ls = nullptr;
         double *wk = nullptr, *wp = nullptr;
         if (!B.up(&wk, (const double*)nullptr, wn) || !B.up(&wp, (const double*)nullptr, wpn) ||
             !B.up(&d.icx, (const double*)nullptr, 135 * (size_t)(K - 1)) ||
-            !B.up(&qkf, hqkf.data(), (size_t)Mp + 1) || !B.up(&qpt, hqpt.data(), (size_t)Mp + 1) ||
-            !B.up(&qobs, hqobs.data(), 3 * (size_t)Mp + 1) || !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
+            !B.up(&d.sm, (const double*)nullptr, 36 * (size_t)K) ||
             !B.up(&zb, (const double*)nullptr, 3 * (size_t)N + 1) ||
             !B.up(&lp, hlong.empty() ? (const int*)nullptr : hlong.data(), hlong.size() + 1) ||
             !B.up(&ls, hlslot.empty() ? (const int*)nullptr : hlslot.data(), hlslot.size() + 1) ||
             !B.up(&d.tb, (const double*)nullptr, 3 * (size_t)N + 1))
             return GBA_ERR_OOM;
         if (hipMemset(d.tb, 0, sizeof(double) * (3 * (size_t)N + 1)) != hipSuccess) return GBA_ERR_HIP;
-        d.qkf = qkf;
-        d.qpt = qpt;
-        d.qobs = qobs;
         d.wk = wk;
         d.wp = wp;
-        d.Mp = Mp;
         d.longp = lp;
         d.nlong = (int)hlong.size();
         d.lslot = ls;
@@ -1957,7 +1989,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         hipLaunchKernelGGL(k_vi_fill, grid(225LL * K), blk, 0, nullptr, 225LL * K, d.hk, none);
         hipLaunchKernelGGL(k_vi_fill, grid(9 * N + 1), blk, 0, nullptr, 9 * N + 1, d.hp, none);
         if (M > 0) hipLaunchKernelGGL(k_vi_lin_stereo, grid(M), blk, 0, nullptr, d);
-        if (M > 0 && schur) {
+        if (M > 0) {
             if (d.w32) hipLaunchKernelGGL(k_vi_lin_stereo_pts<float>, grid(Mp), blk, 0, nullptr, d);
             else hipLaunchKernelGGL(k_vi_lin_stereo_pts<double>, grid(Mp), blk, 0, nullptr, d);
         }
@@ -1974,7 +2006,9 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     // q = (H + lam diag(D)) v, the whole system (nothing once g's stop flag is set)
     auto product = [&](const double* v, double* out, double lam, const double* g) {
         hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out, g);
-        if (M > 0) hipLaunchKernelGGL(k_vi_prod_stereo, grid(M), blk, 0, nullptr, d, v, out, g);
+        if (M > 0)
+            hipLaunchKernelGGL(k_vi_prod_stereo, dim3((unsigned)((Mp + kFuseBlock - 1) / kFuseBlock)),
+                               dim3(kFuseBlock), 0, nullptr, d, v, out, g);
         hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out, g);
     };
     // z = sign C^-1 (B^T v + add) over the points (acc: -t . z added)

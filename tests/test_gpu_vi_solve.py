@@ -133,8 +133,10 @@ def test_vi_rejection_ratio(solver):
         assert abs(rej[0]["step_norm"] - np.linalg.norm(dx)) <= 1e-8 * np.linalg.norm(dx)
 
 
-@pytest.mark.parametrize("precision", [gba.GBA_FP64, gba.GBA_MIXED_FP32])
-def test_vi_long_tracks_match_the_oracle(precision):
+@pytest.mark.parametrize("precision,solver", [(gba.GBA_FP64, gba.GBA_SOLVER_SCHUR),
+                                              (gba.GBA_MIXED_FP32, gba.GBA_SOLVER_SCHUR),
+                                              (gba.GBA_FP64, gba.GBA_SOLVER_FULL)])
+def test_vi_long_tracks_match_the_oracle(precision, solver):
     # 70 keyframes that all see the same 40 points: every point has more
     # than 64 observations, so its sums span wavefronts (the split-point
     # paths of the Schur form); trajectory and one truncated step against
@@ -143,14 +145,14 @@ def test_vi_long_tracks_match_the_oracle(precision):
     assert np.bincount(sc.st_pt).max() > 64
     res = lm.levenberg_marquardt(prob, x0, 3)
     st, X, rep, log = _gpu(sc, states, x0, pre_g, 3, 7.815, pcg_tol=1e-12, pcg_max_iters=4000,
-                           precision=precision)
+                           precision=precision, solver=solver)
     tol = 1e-8 if precision == gba.GBA_FP64 else 1e-6
     for a, b in zip(log, res.log):
         assert abs(a["cost"] - b["cost"]) <= tol * b["cost"], (a, b)
         assert a["accepted"] == b["accepted"]
     assert abs(rep["final_cost"] - res.cost) <= tol * res.cost
     np.testing.assert_allclose(X, res.x.X, rtol=0, atol=1e-4 * np.max(np.abs(res.x.X)))
-    if precision == gba.GBA_FP64:
+    if precision == gba.GBA_FP64 and solver == gba.GBA_SOLVER_SCHUR:
         st3, X3, rep3, log3 = _gpu(sc, states, x0, pre_g, 1, 7.815, pcg_tol=0.0, pcg_max_iters=3)
         lin = prob.linearize(x0)
         dx, steps = prob.schur_pcg_step(lin, 1e-4, 1e-6, 1e32, 0.0, 3)
