@@ -204,8 +204,7 @@ def vi_measurement(gba, args):
                                   sc.imu_dt, bias0, 1.7e-4, 2e-3)
     pre_s = time.perf_counter() - t0
     solver = gba.GBA_SOLVER_SCHUR if args.vi_solver == "schur" else gba.GBA_SOLVER_FULL
-    prec = gba.GBA_MIXED_FP32 if (args.vi_precision == "fp32" and args.vi_solver == "schur") \
-        else gba.GBA_FP64
+    prec = gba.GBA_MIXED_FP32 if args.vi_precision == "fp32" else gba.GBA_FP64
     opts = gba.vi_options(pcg_max_iters=100, pcg_tol=1e-6, solver=solver, precision=prec,
                           pcg_rejection_ratio=args.vi_ratio)
     kw = dict(sigma_px=1.0, huber_delta2=7.815, sigma_gw=2e-5, sigma_aw=3e-3, options=opts)
@@ -220,7 +219,7 @@ def vi_measurement(gba, args):
                                f"{trials} LM trials, PCG tol 1e-6 max 100"
                                + (f" rejection ratio {args.vi_ratio:g}" if args.vi_ratio > 0 else ""),
                    "solver": args.vi_solver,
-                   "w_storage": "f32" if prec == gba.GBA_MIXED_FP32 else "f64",
+                   "stream_storage": "f32" if prec == gba.GBA_MIXED_FP32 else "f64",
                    # the set-up of the call (orderings, allocation, uploads) is reported
                    # apart, as the graph build of the BA solve is
                    "lm_iter_per_s": round(rep["trials"] / ((rep["ms_total"] - rep["ms_other"]) * 1e-3), 3),
@@ -276,8 +275,8 @@ def main():
     ap.add_argument("--vi-kf", type=int, default=2000)
     ap.add_argument("--vi-pts", type=int, default=300_000)
     ap.add_argument("--vi-precision", default="fp32", choices=["fp32", "fp64"],
-                    help="visual-inertial Schur form: the per-observation blocks W in FP32 "
-                         "(FP64 arithmetic), or everything FP64")
+                    help="visual-inertial solve: the per-observation array its PCG products "
+                         "stream in FP32 (FP64 arithmetic), or everything FP64")
     ap.add_argument("--vi-ratio", type=float, default=0.0,
                     help="visual-inertial PCG rejection ratio (0: none)")
     ap.add_argument("--vi-solver", default="schur", choices=["schur", "full"],

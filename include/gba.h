@@ -584,10 +584,11 @@ typedef struct gba_vi_options {
     double pcg_tol;            /* stop at |r| <= pcg_tol |r0| (1e-8)         */
     double initial_lambda;     /* 1e-4                                       */
     double min_diag, max_diag; /* clip of the damping diagonal (1e-6, 1e32)  */
-    int precision;             /* GBA_FP64 (default), or GBA_MIXED_FP32 (the
-                                  Schur form only): the per-observation
-                                  blocks W = J_k^T J_p that the PCG products
-                                  stream stored in FP32, all arithmetic and
+    int precision;             /* GBA_FP64 (default), or GBA_MIXED_FP32: the
+                                  per-observation array the PCG products
+                                  stream (W = J_k^T J_p in the Schur form, the
+                                  whitened 3 x 9 stereo J in the whole-system
+                                  form) stored in FP32, all arithmetic and
                                   every other array FP64                     */
     int reserved1;
     double pcg_rejection_ratio;/* stop PCG and keep the best iterate when
@@ -617,7 +618,7 @@ void gba_vi_default_options(gba_vi_options* out);
  * first max_log
  * trials in log (n_log: their count) may be NULL / 0.  INVALID_ARG for
  * missing arrays, n_kf < 2, non-positive noise parameters, an unknown solver
- * form or precision, or GBA_MIXED_FP32 with GBA_SOLVER_FULL, UNKNOWN_ID for
+ * form or precision, UNKNOWN_ID for
  * an index out of range, OOM when device memory runs out. */
 gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, double tol,
                         const gba_vi_options* opts, gba_report* report, gba_trial* log,

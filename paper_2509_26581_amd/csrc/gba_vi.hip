@@ -421,8 +421,9 @@ struct VIDev {
     const double* obs;     // [3 M]
     const double* pre;     // [kPreStride (K - 1)]
     double* info;          // [81 (K - 1)] Omega of the inertial terms
-    double* jsp;           // whole-system form: whitened stereo J (dtheta, dp | dX), padded
-                           // point-order tiles (js_at); null in the Schur form
+    void* jsp;             // whole-system form: whitened stereo J (dtheta, dp | dX), padded
+                           // point-order tiles (js_at), double or float when w32; null in
+                           // the Schur form
     double* ji;            // [216 (K - 1)] inertial Jacobians
     double* ri;            // [9 (K - 1)]
     double* b;             // [n] gradient J^T Omega r
@@ -706,7 +707,7 @@ __global__ void k_vi_lin_stereo_pts(VIDev d) {
                     (WT)(J[0][a] * J[0][6 + c] + J[1][a] * J[1][6 + c] + J[2][a] * J[2][6 + c]);
     if (valid && d.jsp)
         for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 9; ++c) d.jsp[js_at(i, 9 * a + c)] = J[a][c];
+            for (int c = 0; c < 9; ++c) ((WT*)d.jsp)[js_at(i, 9 * a + c)] = (WT)J[a][c];
     const bool out = valid && l == end;
     double* bp = d.b + 15 * (size_t)d.K + 3 * (size_t)j;
     for (int c = 0; c < 3; ++c) {
@@ -981,6 +982,7 @@ __global__ void k_vi_apply_m(VIDev d, const double* __restrict__ r, double* __re
 // wavefronts add atomically), the keyframe rows J_k^T u go to the
 // workgroup's LDS partials of its keyframe window (as in k_vi_schur_pts) and
 // to q with one atomic add per entry.  q holds lambda D v on entry.
+template <typename JT>
 __global__ __launch_bounds__(512) void k_vi_prod_stereo(VIDev d, const double* __restrict__ v,
                                                        double* __restrict__ q, const double* __restrict__ ps) {
     if (pcg_done(ps)) return;
@@ -1005,7 +1007,7 @@ __global__ __launch_bounds__(512) void k_vi_prod_stereo(VIDev d, const double* _
     for (int c = 0; c < 6; ++c) in[c] = v[ok + c];
     for (int c = 0; c < 3; ++c) in[6 + c] = v[op + c];
     double J[27];
-    for (int c = 0; c < 27; ++c) J[c] = d.jsp[js_at(i, c)];
+    for (int c = 0; c < 27; ++c) J[c] = (double)((const JT*)d.jsp)[js_at(i, c)];
     double u[3];
     for (int a = 0; a < 3; ++a) {
         double t = 0.0;
@@ -1797,7 +1799,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     if (o.pcg_max_iters < 1 || !(o.pcg_tol >= 0.0) || !(o.initial_lambda > 0.0) ||
         (o.solver != GBA_SOLVER_SCHUR && o.solver != GBA_SOLVER_FULL) ||
         (o.precision != GBA_FP64 && o.precision != GBA_MIXED_FP32) ||
-        (o.precision == GBA_MIXED_FP32 && o.solver != GBA_SOLVER_SCHUR) ||
+
         !(o.min_diag > 0.0) || !(o.max_diag >= o.min_diag))
         return GBA_ERR_INVALID_ARG;
     // observations in keyframe order (a stable counting sort), so that the
@@ -1912,7 +1914,12 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         d.qobs = qobs;
         d.Mp = Mp;
     }
-    if (!schur && !B.up(&d.jsp, (const double*)nullptr, 27 * 64 * (size_t)(Mp / 64) + 1)) return GBA_ERR_OOM;
+    if (!schur) {   // the point-order J (FP32: half the doubles, rounded up)
+        d.w32 = o.precision == GBA_MIXED_FP32 ? 1 : 0;
+        double* jp = nullptr;
+        if (!B.up(&jp, (const double*)nullptr, (27 * 64 * (size_t)(Mp / 64) + 2) / (d.w32 ? 2 : 1))) return GBA_ERR_OOM;
+        d.jsp = jp;
+    }
     double* zb = nullptr;   // Schur form: the point vector of a product
     if (schur) {
         // W in FP32 takes half the doubles of FP64 (rounded up)
@@ -2006,9 +2013,11 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
     // q = (H + lam diag(D)) v, the whole system (nothing once g's stop flag is set)
     auto product = [&](const double* v, double* out, double lam, const double* g) {
         hipLaunchKernelGGL(k_vi_prod_damp, grid(n), blk, 0, nullptr, n, lam, d.dg, v, out, g);
-        if (M > 0)
-            hipLaunchKernelGGL(k_vi_prod_stereo, dim3((unsigned)((Mp + kFuseBlock - 1) / kFuseBlock)),
-                               dim3(kFuseBlock), 0, nullptr, d, v, out, g);
+        if (M > 0) {
+            const dim3 pg((unsigned)((Mp + kFuseBlock - 1) / kFuseBlock));
+            if (d.w32) hipLaunchKernelGGL(k_vi_prod_stereo<float>, pg, dim3(kFuseBlock), 0, nullptr, d, v, out, g);
+            else hipLaunchKernelGGL(k_vi_prod_stereo<double>, pg, dim3(kFuseBlock), 0, nullptr, d, v, out, g);
+        }
         hipLaunchKernelGGL(k_vi_prod_inertial, grid(64LL * (K - 1)), blk, 0, nullptr, d, v, out, g);
     };
     // z = sign C^-1 (B^T v + add) over the points (acc: -t . z added)

@@ -199,7 +199,8 @@ def test_vi_inertial_only_matches_the_oracle(solver):
     np.testing.assert_allclose(st[:, 6:9], res.x.v, rtol=0, atol=1e-7)
 
 
-def test_vi_mixed_fp32_within_the_mixed_bounds():
+@pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
+def test_vi_mixed_fp32_within_the_mixed_bounds(solver):
     # W = J_k^T J_p stored in FP32 (Schur form): final cost within 1e-4 and
     # the solution within 1e-3 relative of the oracle's FP64 LM (the mixed
     # bounds), and the first trial's step close to the FP64 path's
@@ -207,9 +208,9 @@ def test_vi_mixed_fp32_within_the_mixed_bounds():
     sc, prob, x0, states, pre_g = _setup(seed=8, n_kf=8, n_pts=100, delta2=delta2)
     res = lm.levenberg_marquardt(prob, x0, 8)
     st, X, rep, log = _gpu(sc, states, x0, pre_g, 8, delta2, pcg_tol=1e-12, pcg_max_iters=4000,
-                           precision=gba.GBA_MIXED_FP32)
+                           precision=gba.GBA_MIXED_FP32, solver=solver)
     st64, X64, rep64, log64 = _gpu(sc, states, x0, pre_g, 8, delta2, pcg_tol=1e-12,
-                                   pcg_max_iters=4000)
+                                   pcg_max_iters=4000, solver=solver)
     assert abs(rep["final_cost"] - res.cost) <= 1e-4 * res.cost
     b = np.concatenate([res.x.p.ravel(), res.x.v.ravel(), res.x.bg.ravel(), res.x.ba.ravel(),
                         res.x.X.ravel()])
@@ -258,10 +259,6 @@ def test_vi_solve_errors():
     with pytest.raises(gba.GbaError) as e:
         _gpu(sc, states, x0, pre_g, 3, 0.0, solver=7)
     assert e.value.status == -1                      # unknown solver form
-    with pytest.raises(gba.GbaError) as e:
-        _gpu(sc, states, x0, pre_g, 3, 0.0, solver=gba.GBA_SOLVER_FULL,
-             precision=gba.GBA_MIXED_FP32)
-    assert e.value.status == -1                      # FP32 W only in the Schur form
     with pytest.raises(gba.GbaError) as e:
         _gpu(sc, states, x0, pre_g, 3, 0.0, precision=gba.GBA_MIXED_BF16)
     assert e.value.status == -1
