@@ -14,6 +14,10 @@ keyframes with a 200 Hz IMU, 300k points, ~2.07M stereo observations, Huber,
 LM with PCG on the keyframe Schur complement (W in FP32, FP64 arithmetic);
 LM iter/s over the trials, the call's set-up reported apart.
 
+At scale (in the same JSON line, "bal8m"): 10,000 cameras, 1M points, ~8M
+observations, BF16 Jacobian copy, 15 LM trials per solve, run by this script
+in a child process (--no-bal8m skips it).
+
 Serving (in the same JSON line, "serving"): 512 local-BA requests (5-40
 keyframes, 500-20k points, tracks 2-10 inside a local window, first two
 keyframes fixed, 10 trials each, mixed FP32): one at a time, all at once
@@ -22,6 +26,7 @@ keyframes fixed, 10 trials each, mixed FP32): one at a time, all at once
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
                   [--workload bal1m|bal8m|small] [--no-cpu-baseline] [--no-serve] [--no-vi]
+                  [--no-bal8m]
                   [--serve-only] [--accumulation 0|1|2] [--tiles-per-block N]
 """
 import argparse
@@ -232,6 +237,27 @@ def vi_measurement(gba, args):
                    "preintegration_s": round(pre_s, 4), "dtype": "f64"}}
 
 
+def bal8m_measurement():
+    """The at-scale configuration (10,000 cameras, 1M points, ~8M
+    observations, BF16 Jacobian copy, 15 LM trials per solve) run by this
+    script in a child process; its LM iter/s, PCG iterations and product
+    roofline, or the child's failure."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "bal8m", "--precision", "bf16",
+           "--no-serve", "--no-vi", "--no-bal8m", "--no-cpu-baseline", "--no-compare",
+           "--steps", "2", "--warmup", "1"]
+    print("[bench] bal8m in a child process ...", flush=True)
+    try:
+        out = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        rec = json.loads(out.stdout.strip().splitlines()[-1])
+    except Exception as exc:   # reported in the line, not raised
+        return {"error": repr(exc)[:200]}
+    return {"workload": rec["config"]["workload"], "precision": "bf16",
+            "lm_iter_per_s": rec["value"], "ms_per_step": rec["ms_per_step"],
+            "pcg_iters_per_trial": rec["pcg_iters_per_trial"], "final_cost": rec["final_cost"],
+            "roofline": rec["roofline"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +275,8 @@ def main():
     ap.add_argument("--tiles-per-block", type=int, default=0,
                     help="point tiles per point-pass workgroup (0: automatic)")
     ap.add_argument("--no-serve", action="store_true", help="skip the local-BA stream")
+    ap.add_argument("--no-bal8m", action="store_true",
+                    help="skip the 10k-camera configuration (reported as \"bal8m\")")
     ap.add_argument("--no-vi", action="store_true",
                     help="skip the visual-inertial configuration (reported as \"vi\")")
     ap.add_argument("--matvec-only", action="store_true",
@@ -334,7 +362,15 @@ def main():
         product_kernel = "k_full_point_pass<kMatvec> (full-system product, point pass)"
     else:
         alg_bytes = matvec_algorithmic_bytes(sc.n_obs, n_pts_active, jac_bytes, vec_bytes)
-        product_kernel = "k_point_pass<kMatvec> (fused Schur product)"
+        # one problem's camera vector in LDS (FP64, 160 KB per CU) or two passes
+        two_pass = 9 * 8 * sc.n_cams + 1024 > 160 * 1024 or args.accumulation in (2, 3) \
+            or args.deterministic
+        blocked = two_pass and not args.deterministic and args.accumulation != 2 and \
+            (args.accumulation == 3 or sc.n_cams > 1024) and SCHEDULES[args.pcg_schedule] != 2
+        product_kernel = ("k_point_pass<kMatvec> + k_cam_block_pass (two-pass Schur product)"
+                          if blocked else
+                          "k_point_pass<kMatvec> + k_cam_pass<kMatvec> (two-pass Schur product)"
+                          if two_pass else "k_point_pass<kMatvec> (fused Schur product)")
 
     def run_options(timing):
         return gba.options(pcg_max_iters=sc.pcg_max_iters, pcg_tol=sc.pcg_tol,
@@ -447,6 +483,9 @@ def main():
     line["vi"] = None
     if not args.no_vi and args.workload == "bal1m":
         line["vi"] = vi_measurement(gba, args)["vi"]
+    line["bal8m"] = None
+    if not args.no_bal8m and args.workload == "bal1m":
+        line["bal8m"] = bal8m_measurement()
     line["serving"] = None
     if not args.no_serve:
         line["serving"] = serving_measurement(gba, synth, args.serve_requests, prec_id,
