@@ -86,6 +86,46 @@ def test_vi_lm_trajectory_matches_the_oracle(delta2, solver):
     np.testing.assert_allclose(st[0, 0:3], states[0, 0:3], rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("solver", [gba.GBA_SOLVER_SCHUR, gba.GBA_SOLVER_FULL])
+def test_vi_two_keyframes_and_unobserved_points(solver):
+    # the smallest window (one free keyframe behind the fixed first) with
+    # points that no keyframe observes placed between observed points in the
+    # caller's order: their rows of the damped system hold only the damping
+    # and a zero gradient, so they come back exactly as given, at their own
+    # places; everything else follows the oracle
+    sc, prob, x0, states, pre_g = _setup(seed=12, n_kf=2, n_pts=60, delta2=7.815)
+    N, extra = x0.X.shape[0], 7
+    rng = np.random.default_rng(13)
+    pos = np.sort(rng.choice(N + extra, extra, replace=False))
+    keep = np.setdiff1d(np.arange(N + extra), pos)   # old point j is now keep[j]
+    X0 = np.empty((N + extra, 3))
+    X0[keep] = x0.X
+    X0[pos] = rng.normal(0.0, 3.0, (extra, 3))
+    pt = keep[sc.st_pt]
+    prob2 = vi.VIProblem(sc.st_kf, pt, sc.st_obs, sc.intr, prob.pre, sigma_px=1.0, delta2=7.815,
+                         sigma_gw=SIG_GW, sigma_aw=SIG_AW)
+    xs = vi.VIState(x0.R, x0.p, x0.v, x0.bg, x0.ba, X0)
+    res = lm.levenberg_marquardt(prob2, xs, 5)
+    st, X, rep, log = gba.gba_vi_solve(0, states, X0, sc.st_kf, pt, sc.st_obs, sc.intr, pre_g, 5,
+                                       sigma_px=1.0, huber_delta2=7.815, sigma_gw=SIG_GW,
+                                       sigma_aw=SIG_AW,
+                                       options=gba.vi_options(pcg_tol=1e-12, pcg_max_iters=4000,
+                                                              solver=solver))
+    assert len(log) == len(res.log)
+    assert abs(rep["initial_cost"] - res.initial_cost) <= 1e-9 * res.initial_cost
+    for a, b in zip(log, res.log):
+        assert abs(a["cost"] - b["cost"]) <= 1e-8 * b["cost"], (a, b)
+        if abs(b["cost"] - b["candidate_cost"]) <= 1e-8 * b["cost"]:
+            break
+        assert a["accepted"] == b["accepted"], (a, b)
+    assert abs(rep["final_cost"] - res.cost) <= 1e-8 * res.cost
+    np.testing.assert_array_equal(X[pos], X0[pos])
+    np.testing.assert_array_equal(res.x.X[pos], X0[pos])
+    np.testing.assert_allclose(X[keep], res.x.X[keep], rtol=0, atol=1e-6 * np.max(np.abs(res.x.X)))
+    np.testing.assert_allclose(st[:, 3:6], res.x.p, rtol=0, atol=1e-7)
+    np.testing.assert_array_equal(st[0, 3:], states[0, 3:])
+
+
 @pytest.mark.parametrize("k", [1, 3, 7])
 def test_vi_truncated_schur_step_matches_the_oracle(k):
     # k PCG steps on S from the first linearisation: the candidate cost, the
