@@ -466,7 +466,8 @@ struct VIDev {
 constexpr int kPqParts = 256;
 // per slot also: the least r.r so far (the rejection test), a breakdown flag
 // set by the update kernel and the stop decision of the direction kernel
-enum { kAccPq = 0, kAccRr = kPqParts, kAccRz, kAccMin, kAccBreak, kAccStop, kAccN };
+enum { kAccPq = 0, kAccRr = kPqParts, kAccRz, kAccMin, kAccBreak, kAccStop, kAccRrP,
+       kAccRzP = kAccRrP + kPqParts, kAccN = kAccRzP + kPqParts };
 constexpr int kSlots = 3;
 enum { kThr = kSlots * kAccN, kDone, kSteps, kRatio2, kPcgScalars };
 
@@ -1455,7 +1456,8 @@ __global__ void k_vi_pcg_init(double* __restrict__ ps, double tol, double ratio2
 // the current iterate), x += alpha p, r -= alpha q, z = M^-1 r and the new
 // r.r, r.z.  Keyframe rows: 16 lanes per keyframe (15 used), the residual
 // block through LDS for the 15 x 15 inverse; point rows (the whole-system
-// form): one lane per point after the keyframe workgroups.
+// form): three lanes per point in the workgroups after the keyframe ones.
+constexpr int kUpdPts = 85;   // points per 256-lane workgroup of the update
 __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, double* __restrict__ ps,
                                                       int slot, const double* __restrict__ p,
                                                       const double* __restrict__ q, double* __restrict__ x,
@@ -1501,30 +1503,36 @@ __global__ __launch_bounds__(256) void k_vi_pcg_update(VIDev d, long long npt, d
             rz = rn * u;
         }
     } else {
-        const long long j = (blockIdx.x - kf_blocks) * 256LL + threadIdx.x;
-        if (j < npt) {
-            const size_t o = 15 * (size_t)d.K + 3 * j;
-            double rn[3];
-            for (int a = 0; a < 3; ++a) {
-                x[o + a] += alpha * p[o + a];
-                rn[a] = r[o + a] - alpha * q[o + a];
-                r[o + a] = rn[a];
-            }
-            const double* M = d.mp + 9 * j;
-            for (int a = 0; a < 3; ++a) {
-                const double u = M[3 * a] * rn[0] + M[3 * a + 1] * rn[1] + M[3 * a + 2] * rn[2];
-                z[o + a] = u;
-                rr += rn[a] * rn[a];
-                rz += rn[a] * u;
-            }
+        // point rows: three lanes per point (kUpdPts points per workgroup),
+        // so consecutive lanes take consecutive rows; the point's residual
+        // through LDS for its 3 x 3 inverse
+        const int pl = (int)threadIdx.x / 3, a = (int)threadIdx.x - 3 * pl;
+        const long long j = (blockIdx.x - kf_blocks) * (long long)kUpdPts + pl;
+        const bool act = pl < kUpdPts && j < npt;
+        const size_t i = 15 * (size_t)d.K + 3 * (size_t)j + a;
+        double rn = 0.0;
+        if (act) {
+            x[i] += alpha * p[i];
+            rn = r[i] - alpha * q[i];
+            r[i] = rn;
+        }
+        rs[threadIdx.x] = rn;
+        __syncthreads();
+        if (act) {
+            const double* M = d.mp + 9 * (size_t)j + 3 * a;
+            const double* rk = rs + 3 * pl;
+            const double u = M[0] * rk[0] + M[1] * rk[1] + M[2] * rk[2];
+            z[i] = u;
+            rr = rn * rn;
+            rz = rn * u;
         }
     }
     rr = block_sum_vi(rr, red);
     __syncthreads();
     rz = block_sum_vi(rz, red);
     if (threadIdx.x == 0) {
-        atomic_add(acc + kAccRr, rr);
-        atomic_add(acc + kAccRz, rz);
+        atomic_add(acc + kAccRrP + blockIdx.x % kPqParts, rr);   // summed by k_vi_pcg_dir
+        atomic_add(acc + kAccRzP + blockIdx.x % kPqParts, rz);
         if (blockIdx.x == 0) ps[kSteps] += 1.0;
     }
 }
@@ -1546,6 +1554,24 @@ __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, con
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     const long long st = (long long)gridDim.x * blockDim.x;
     const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    // this step's r.r and r.z from their parts (the same sums, in the same
+    // order, in every workgroup); workgroup 0 keeps them in the slot
+    __shared__ double red[16];
+    __shared__ double sums[2];
+    {
+        const double a = block_sum_vi(threadIdx.x < kPqParts ? acc[kAccRrP + threadIdx.x] : 0.0, red);
+        __syncthreads();
+        const double b = block_sum_vi(threadIdx.x < kPqParts ? acc[kAccRzP + threadIdx.x] : 0.0, red);
+        if (threadIdx.x == 0) {
+            sums[0] = a;
+            sums[1] = b;
+        }
+        __syncthreads();
+    }
+    if (lead) {
+        acc[kAccRr] = sums[0];
+        acc[kAccRz] = sums[1];
+    }
     if (blockIdx.x == 0)
         for (int e = threadIdx.x; e < kAccN; e += blockDim.x) ps[kAccN * ((slot + 1) % kSlots) + e] = 0.0;
     if (prev[kAccStop] != 0.0 || acc[kAccBreak] != 0.0) {
@@ -1556,7 +1582,7 @@ __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, con
         }
         return;
     }
-    const double rr = acc[kAccRr], least = prev[kAccMin], ratio2 = ps[kRatio2];
+    const double rr = sums[0], least = prev[kAccMin], ratio2 = ps[kRatio2];
     double nmin = least;
     if (ratio2 > 0.0) {
         if (rr < least) {
@@ -1580,7 +1606,7 @@ __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, con
         }
         return;
     }
-    const double beta = acc[kAccRz] / prev[kAccRz];
+    const double beta = sums[1] / prev[kAccRz];
     for (long long i = i0; i < n; i += st) {
         p[i] = z[i] + beta * p[i];
         if (qz) qz[i] = 0.0;   // the next product adds into q
@@ -1588,8 +1614,10 @@ __global__ void k_vi_pcg_dir(long long n, double* __restrict__ ps, int slot, con
     if (lead) acc[kAccMin] = nmin;
 }
 
+// out[blockIdx % parts] += the workgroup's part of a . b (parts > 1 spreads
+// the additions over addresses that the reader sums)
 __global__ void k_vi_dot(long long n, const double* __restrict__ a, const double* __restrict__ b,
-                         double* __restrict__ out, const double* __restrict__ ps = nullptr) {
+                         double* __restrict__ out, const double* __restrict__ ps = nullptr, int parts = 1) {
     if (pcg_done(ps)) return;
     __shared__ double red[16];
     double s = 0.0;
@@ -1597,7 +1625,7 @@ __global__ void k_vi_dot(long long n, const double* __restrict__ a, const double
          i += (long long)gridDim.x * blockDim.x)
         s += a[i] * b[i];
     s = block_sum_vi(s, red);
-    if (threadIdx.x == 0) atomic_add(out, s);
+    if (threadIdx.x == 0) atomic_add(out + blockIdx.x % parts, s);
 }
 
 // p = z (the first direction)
@@ -2097,7 +2125,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         if (schur) hipLaunchKernelGGL(k_vi_fill, grid(nn), blk, 0, nullptr, nn, q, none);   // the products add into q
         hipLaunchKernelGGL(k_vi_pcg_init, dim3(1), dim3(1), 0, nullptr, ps, o.pcg_tol, ratio2);
         const long long npt = schur ? 0 : N;
-        const dim3 upd((unsigned)((K + 15) / 16 + (npt + 255) / 256));
+        const dim3 upd((unsigned)((K + 15) / 16 + (npt + kUpdPts - 1) / kUpdPts));
         const dim3 dirg((unsigned)std::max(1LL, std::min<long long>(1024, (nn + 255) / 256)));
         for (int it = 0; it < o.pcg_max_iters; ++it) {
             const int slot = it % kSlots;
@@ -2106,7 +2134,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
             } else {
                 product(pv, q, lam, ps);
                 hipLaunchKernelGGL(k_vi_dot, dot_blocks(nn), blk, 0, nullptr, nn, (const double*)pv,
-                                   (const double*)q, ps + kAccN * slot + kAccPq, (const double*)ps);
+                                   (const double*)q, ps + kAccN * slot + kAccPq, (const double*)ps, kPqParts);
             }
             hipLaunchKernelGGL(k_vi_pcg_update, upd, blk, 0, nullptr, d, npt, ps, slot, (const double*)pv,
                                (const double*)q, x, r, z);
