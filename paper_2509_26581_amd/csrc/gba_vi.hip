@@ -470,6 +470,11 @@ enum { kAccPq = 0, kAccRr = kPqParts, kAccRz, kAccMin, kAccBreak, kAccStop, kAcc
        kAccRzP = kAccRrP + kPqParts, kAccN = kAccRzP + kPqParts };
 constexpr int kSlots = 3;
 enum { kThr = kSlots * kAccN, kDone, kSteps, kRatio2, kPcgScalars };
+// the cost, |x| and model-decrease sums: kRedSlots sums of kPqParts parts
+// each, after the PCG scalars (scal = 8 unused, the PCG scalars, the parts)
+constexpr int kRedSlots = 8;
+constexpr long long kRedOff = 8 + kPcgScalars;
+constexpr long long kScalN = kRedOff + (long long)kRedSlots * kPqParts;
 
 __device__ __forceinline__ bool pcg_done(const double* ps) { return ps && ps[kDone] != 0.0; }
 
@@ -822,7 +827,7 @@ __global__ __launch_bounds__(256) void k_vi_acc_inertial(VIDev d) {
 }
 
 // cost at (st, X): 1/2 sum rho over stereo, 1/2 r^T Omega r over inertial,
-// 1/2 r^T Omega_b r over bias; into scal[slot]
+// 1/2 r^T Omega_b r over bias; into the parts of reduction slot `slot`
 __global__ void k_vi_cost(VIDev d, const double* __restrict__ st, const double* __restrict__ X,
                           int slot) {
     __shared__ double red[16];
@@ -863,7 +868,7 @@ __global__ void k_vi_cost(VIDev d, const double* __restrict__ st, const double* 
         }
     }
     c = block_sum_vi(c, red);
-    if (threadIdx.x == 0) atomic_add(d.scal + slot, c);
+    if (threadIdx.x == 0) atomic_add(d.scal + kRedOff + slot * kPqParts + blockIdx.x % kPqParts, c);
 }
 
 // the point blocks of the preconditioner (and, in the Schur form, C^-1):
@@ -1307,7 +1312,7 @@ __global__ void k_vi_pt_quad(VIDev d, const double* __restrict__ x, double* __re
             c * (H[6] * a + H[7] * b + H[8] * c);
     }
     s = block_sum_vi(s, red);
-    if (threadIdx.x == 0) atomic_add(out, s);
+    if (threadIdx.x == 0) atomic_add(out + blockIdx.x % kPqParts, s);   // out: kPqParts parts
 }
 
 // q_k -= sum_{e of k} W_e z_j(e): observations in keyframe order, the
@@ -1688,7 +1693,7 @@ __global__ void k_vi_xnorm(VIDev d, const double* __restrict__ st, const double*
         for (int k = 0; k < 3; ++k) s += X[3 * j + k] * X[3 * j + k];
     }
     s = block_sum_vi(s, red);
-    if (threadIdx.x == 0) atomic_add(d.scal + slot, s);
+    if (threadIdx.x == 0) atomic_add(d.scal + kRedOff + slot * kPqParts + blockIdx.x % kPqParts, s);
 }
 
 }  // namespace vi
@@ -1926,7 +1931,7 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         !B.up(&d.b, (const double*)nullptr, (size_t)n) || !B.up(&d.hk, (const double*)nullptr, 225 * (size_t)K) ||
         !B.up(&d.hp, (const double*)nullptr, 9 * (size_t)N + 1) || !B.up(&d.dg, (const double*)nullptr, (size_t)n) ||
         !B.up(&d.mki, (const double*)nullptr, 225 * (size_t)K) || !B.up(&d.mp, (const double*)nullptr, 9 * (size_t)N + 1) ||
-        !B.up(&d.scal, (const double*)nullptr, 8 + kPcgScalars) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
+        !B.up(&d.scal, (const double*)nullptr, (size_t)kScalN) || !B.up(&x, (const double*)nullptr, (size_t)n) ||
         !B.up(&r, (const double*)nullptr, (size_t)n) || !B.up(&z, (const double*)nullptr, (size_t)n) ||
         !B.up(&pv, (const double*)nullptr, (size_t)n) || !B.up(&q, (const double*)nullptr, (size_t)n) ||
         !B.up(&xb, (const double*)nullptr, (size_t)n))
@@ -2000,7 +2005,20 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         if (err == hipSuccess) err = hipMemcpy(hs, d.scal, sizeof(hs), hipMemcpyDeviceToHost);
         return err == hipSuccess;
     };
-    const long long n_scal = 8 + kPcgScalars;
+    // the reduction slots' parts (each slot's parts summed in index order)
+    std::vector<double> hr((size_t)kRedSlots * kPqParts);
+    auto read_red = [&]() {
+        if (err == hipSuccess)
+            err = hipMemcpy(hr.data(), d.scal + kRedOff, hr.size() * sizeof(double), hipMemcpyDeviceToHost);
+        return err == hipSuccess;
+    };
+    auto red_sum = [&](int slot) {
+        double t = 0.0;
+        for (int i = 0; i < kPqParts; ++i) t += hr[(size_t)slot * kPqParts + i];
+        return t;
+    };
+    auto red_parts = [&](int slot) { return d.scal + kRedOff + (long long)slot * kPqParts; };
+    const long long n_scal = kScalN;
     double* ps = d.scal + 8;   // PCG scalars
     auto zero_scal = [&]() {
         hipLaunchKernelGGL(k_vi_fill, grid(n_scal), blk, 0, nullptr, n_scal, d.scal, (const double*)nullptr);
@@ -2013,9 +2031,9 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
         zero_scal();
         hipLaunchKernelGGL(k_vi_cost, grid(M + K - 1), blk, 0, nullptr, d, st, X, 0);
         if (nst) hipLaunchKernelGGL(k_vi_xnorm, grid(K + N), blk, 0, nullptr, d, nst, nX, 1);
-        if (!chk() || !read_scal()) return false;
-        F = hs[0];
-        xn = std::sqrt(hs[1]);
+        if (!chk() || !read_red()) return false;
+        F = red_sum(0);
+        xn = std::sqrt(red_sum(1));
         return true;
     };
     auto linearize = [&]() {
@@ -2188,24 +2206,24 @@ gba_status gba_vi_solve(int device, const gba_vi_problem* prob, int max_iters, d
                                    cnone, (double*)nullptr);
                 hipLaunchKernelGGL(k_vi_fill, grid(15LL * K), blk, 0, nullptr, 15LL * K, z, cnone);
                 schur_kf(xp, z, nullptr);   // z = -B dx_p
-                hipLaunchKernelGGL(k_vi_pt_quad, grid(N), blk, 0, nullptr, d, xp, d.scal + 2);
+                hipLaunchKernelGGL(k_vi_pt_quad, grid(N), blk, 0, nullptr, d, xp, red_parts(2));
                 hipLaunchKernelGGL(k_vi_dot, dot_blocks(15LL * K), blk, 0, nullptr, 15LL * K, (const double*)x,
-                                   (const double*)q, d.scal + 0, cnone);
+                                   (const double*)q, red_parts(0), cnone, kPqParts);
                 hipLaunchKernelGGL(k_vi_dot, dot_blocks(15LL * K), blk, 0, nullptr, 15LL * K, (const double*)x,
-                                   (const double*)z, d.scal + 1, cnone);
+                                   (const double*)z, red_parts(1), cnone, kPqParts);
             } else {
                 product(x, q, 0.0, nullptr);
                 hipLaunchKernelGGL(k_vi_dot, dot_blocks(n), blk, 0, nullptr, n, (const double*)x, (const double*)q,
-                                   d.scal + 0, cnone);
+                                   red_parts(0), cnone, kPqParts);
             }
             hipLaunchKernelGGL(k_vi_dot, dot_blocks(n), blk, 0, nullptr, n, (const double*)d.b, (const double*)x,
-                               d.scal + 3, cnone);
+                               red_parts(3), cnone, kPqParts);
             hipLaunchKernelGGL(k_vi_dot, dot_blocks(n), blk, 0, nullptr, n, (const double*)x, (const double*)x,
-                               d.scal + 4, cnone);
-            if (!chk() || !read_scal()) return GBA_ERR_HIP;
-            dHd = schur ? hs[0] - 2.0 * hs[1] + hs[2] : hs[0];
-            bdx = hs[3];
-            dd = hs[4];
+                               red_parts(4), cnone, kPqParts);
+            if (!chk() || !read_red()) return GBA_ERR_HIP;
+            dHd = schur ? red_sum(0) - 2.0 * red_sum(1) + red_sum(2) : red_sum(0);
+            bdx = red_sum(3);
+            dd = red_sum(4);
             const double L = -(bdx + 0.5 * dHd);
             hipLaunchKernelGGL(k_vi_step, grid(K + N), blk, 0, nullptr, d, x);
             double Fn = 0.0, xnorm = 0.0;
